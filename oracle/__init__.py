@@ -1,0 +1,274 @@
+"""FP64 CPU oracle of the TL-SPH multi-time-step hot path -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never loads it, and the
+two share no source.  ``liboracle.so`` is the plain FP64 oracle;
+``liboracle_cs.so`` is the same source compiled with complex ``real``, used as a
+complex-step derivative oracle (Im(f(x + i e)) / e = f'(x) to rounding).
+
+Arrays are numpy, structure-of-arrays ``[component, n]`` in the cell-sorted
+order that the build returns (``perm[s]`` = input id of sorted particle s).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sph_oracle.c")
+_LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_cs.so")}
+
+LE, NH, J2 = 0, 1, 2
+LOAD, DIFFUSION = 0, 1
+FIXED, CDIR, GRIP = 1, 2, 4
+
+
+def build(force: bool = True) -> None:
+    """Compile both oracle variants with gcc (no FMA contraction)."""
+    for cplx, out in _LIBS.items():
+        if not force and os.path.exists(out) and os.path.getmtime(out) > os.path.getmtime(_SRC):
+            continue
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-o", out, _SRC, "-lm"]
+        if cplx:
+            cmd.insert(1, "-DORC_COMPLEX")
+        subprocess.run(cmd, check=True)
+
+
+_cache: dict = {}
+
+
+def _lib(cplx: bool):
+    if cplx in _cache:
+        return _cache[cplx]
+    path = _LIBS[cplx]
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = C.CDLL(path)
+    vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    lib.orc_kernel_W.restype = dbl
+    lib.orc_kernel_W.argtypes = [i32, dbl, dbl]
+    lib.orc_kernel_dW_over_r.restype = dbl
+    lib.orc_kernel_dW_over_r.argtypes = [i32, dbl, dbl]
+    lib.orc_create.restype = vp
+    lib.orc_create.argtypes = [i32, i64, vp, vp, dbl, C.POINTER(C.c_int)]
+    lib.orc_destroy.argtypes = [vp]
+    lib.orc_sizes.argtypes = [vp, vp]
+    lib.orc_grid.argtypes = [vp, vp, vp]
+    lib.orc_get_build.argtypes = [vp] * 9
+    lib.orc_get_schedule.argtypes = [vp] * 8
+    lib.orc_constitutive.restype = i32
+    lib.orc_constitutive.argtypes = [vp, vp, vp, _real_t(cplx), vp]
+    lib.orc_deformation_gradient.argtypes = [vp, vp, vp]
+    lib.orc_stress.restype = i32
+    lib.orc_stress.argtypes = [vp] * 7
+    lib.orc_momentum.argtypes = [vp] * 4
+    lib.orc_solid_step.restype = i32
+    lib.orc_solid_step.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_damping_sweep.argtypes = [vp, dbl, dbl, dbl, vp, vp]
+    lib.orc_drift_ke.restype = _real_t(cplx)
+    lib.orc_drift_ke.argtypes = [vp, dbl, dbl, vp, vp, vp]
+    lib.orc_load_step.argtypes = [vp, dbl, vp, vp, vp]
+    lib.orc_diffusion_step.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, vp, vp, vp, vp]
+    lib.orc_advance.restype = i32
+    lib.orc_advance.argtypes = [vp] * 15
+    _cache[cplx] = lib
+    return lib
+
+
+class _Cplx(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+def _real_t(cplx):
+    return _Cplx if cplx else C.c_double
+
+
+def _to_real(x, cplx):
+    if cplx:
+        z = complex(x)
+        return _Cplx(z.real, z.imag)
+    return float(x)
+
+
+def _material_t(cplx):
+    R = _real_t(cplx)
+
+    class Material(C.Structure):
+        _fields_ = [("model", C.c_int32), ("pad_", C.c_int32), ("E", R), ("nu", C.c_double),
+                    ("rho0", C.c_double), ("sigma0", R), ("sigma_inf", R), ("delta", R), ("H", R),
+                    ("C_swell", R), ("c0", C.c_double)]
+    return Material
+
+
+def _cfg_t(cplx):
+    R = _real_t(cplx)
+
+    class Cfg(C.Structure):
+        _fields_ = [("n_slow", C.c_int32), ("slow_kind", C.c_int32), ("dt_slow", C.c_double),
+                    ("dt_s", C.c_double), ("eta", C.c_double), ("k_max", C.c_int64),
+                    ("fixed_inner", C.c_int64), ("ke_tol", C.c_double), ("D", R), ("c_bc", C.c_double)]
+    return Cfg
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle:
+    """One particle set: build (grid, sort, neighbours, B0, schedule) + steps."""
+
+    def __init__(self, dim, X_id, V_id, h, complex_step=False):
+        self.cplx = bool(complex_step)
+        self.lib = _lib(self.cplx)
+        self.dtype = np.complex128 if self.cplx else np.float64
+        X_id = np.ascontiguousarray(X_id, dtype=np.float64)
+        V_id = np.ascontiguousarray(V_id, dtype=np.float64)
+        assert X_id.shape[0] == dim and V_id.shape == (X_id.shape[1],)
+        self.dim, self.n, self.h = dim, X_id.shape[1], float(h)
+        err = C.c_int(0)
+        self._h = self.lib.orc_create(dim, self.n, _ptr(X_id), _ptr(V_id), float(h), C.byref(err))
+        if not self._h:
+            raise RuntimeError(f"orc_create failed with code {err.value}")
+        sz = np.zeros(10, np.int64)
+        self.lib.orc_sizes(self._h, _ptr(sz))
+        (self.n, self.n_pairs, self.n_upairs, self.n_cells, nc0, nc1, nc2, self.n_anchors,
+         self.max_level, self.max_deg) = [int(x) for x in sz]
+        self.ncell = (nc0, nc1, nc2)
+        org = np.zeros(3)
+        inv = C.c_double(0)
+        self.lib.orc_grid(self._h, _ptr(org), C.byref(inv))
+        self.origin, self.inv_rc = org, inv.value
+        n, d = self.n, dim
+        self.key = np.zeros(n, np.uint32)
+        self.perm = np.zeros(n, np.uint32)
+        self.cell_start = np.zeros(self.n_cells + 1, np.uint32)
+        self.nbr_off = np.zeros(n + 1, np.int64)
+        self.nbr_idx = np.zeros(max(self.n_pairs, 1), np.uint32)
+        self.X = np.zeros((d, n))
+        self.V = np.zeros(n)
+        self.B0 = np.zeros((d * d, n))
+        self.lib.orc_get_build(self._h, _ptr(self.key), _ptr(self.perm), _ptr(self.cell_start),
+                               _ptr(self.nbr_off), _ptr(self.nbr_idx), _ptr(self.X), _ptr(self.V),
+                               _ptr(self.B0))
+        self.nbr_idx = self.nbr_idx[: self.n_pairs]
+        npu = max(self.n_upairs, 1)
+        self.sched_a = np.zeros(npu, np.uint32)
+        self.sched_b = np.zeros(npu, np.uint32)
+        self.sched_level = np.zeros(npu, np.uint32)
+        self.anchor_key = np.zeros(max(self.n_anchors, 1), np.uint32)
+        self.anchor_off = np.zeros(self.n_anchors + 1, np.int64)
+        self.anchor_nlev = np.zeros(max(self.n_anchors, 1), np.uint32)
+        self.color_off = np.zeros(9, np.int64)
+        self.lib.orc_get_schedule(self._h, _ptr(self.sched_a), _ptr(self.sched_b),
+                                  _ptr(self.sched_level), _ptr(self.anchor_key),
+                                  _ptr(self.anchor_off), _ptr(self.anchor_nlev), _ptr(self.color_off))
+        self.sched_a = self.sched_a[: self.n_upairs]
+        self.sched_b = self.sched_b[: self.n_upairs]
+        self.sched_level = self.sched_level[: self.n_upairs]
+        self.anchor_key = self.anchor_key[: self.n_anchors]
+        self.anchor_nlev = self.anchor_nlev[: self.n_anchors]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self.lib.orc_destroy(h)
+            self._h = None
+
+    # -- helpers --------------------------------------------------------
+    def arr(self, *shape):
+        return np.zeros(shape, self.dtype)
+
+    def _a(self, x):
+        if x is None:
+            return None
+        assert x.dtype == self.dtype and x.flags.c_contiguous, (x.dtype, self.dtype)
+        return x
+
+    def material(self, model, E, nu, rho0, sigma0=0.0, sigma_inf=0.0, delta=0.0, H=0.0,
+                 C_swell=0.0, c0=0.0):
+        M = _material_t(self.cplx)
+        r = lambda x: _to_real(x, self.cplx)  # noqa: E731
+        return M(int(model), 0, r(E), float(nu), float(rho0), r(sigma0), r(sigma_inf), r(delta),
+                 r(H), r(C_swell), float(c0))
+
+    def cfg(self, n_slow, slow_kind, dt_slow, dt_s=0.0, eta=0.0, k_max=0, fixed_inner=0, ke_tol=0.0,
+            D=0.0, c_bc=0.0):
+        Cf = _cfg_t(self.cplx)
+        return Cf(int(n_slow), int(slow_kind), float(dt_slow), float(dt_s), float(eta), int(k_max),
+                  int(fixed_inner), float(ke_tol), _to_real(D, self.cplx), float(c_bc))
+
+    @staticmethod
+    def _from_real(x):
+        return complex(x.re, x.im) if isinstance(x, _Cplx) else x
+
+    # -- kernel ---------------------------------------------------------
+    def W(self, r):
+        return self.lib.orc_kernel_W(self.dim, self.h, float(r))
+
+    def dW_over_r(self, r):
+        return self.lib.orc_kernel_dW_over_r(self.dim, self.h, float(r))
+
+    # -- steps ----------------------------------------------------------
+    def constitutive(self, mat, F, plastic7=None, p=0.0):
+        F = np.ascontiguousarray(F, dtype=self.dtype).reshape(9)
+        pl = (np.array([1, 1, 1, 0, 0, 0, 0], self.dtype) if plastic7 is None
+              else np.ascontiguousarray(plastic7, dtype=self.dtype).copy())
+        P = np.zeros(9, self.dtype)
+        rc = self.lib.orc_constitutive(C.byref(mat), _ptr(F), _ptr(pl), _to_real(p, self.cplx), _ptr(P))
+        return rc, P.reshape(3, 3), pl
+
+    def deformation_gradient(self, u):
+        F9 = self.arr(9, self.n)
+        self.lib.orc_deformation_gradient(self._h, _ptr(self._a(u)), _ptr(F9))
+        return F9
+
+    def stress(self, mat, F9, plastic=None, p=None):
+        P9 = self.arr(9, self.n)
+        PB = self.arr(self.dim * self.dim, self.n)
+        rc = self.lib.orc_stress(self._h, C.byref(mat), _ptr(self._a(F9)), _ptr(self._a(plastic)),
+                                 _ptr(self._a(p)), _ptr(P9), _ptr(PB))
+        return rc, P9, PB
+
+    def momentum(self, mat, PB):
+        acc = self.arr(self.dim, self.n)
+        self.lib.orc_momentum(self._h, C.byref(mat), _ptr(self._a(PB)), _ptr(acc))
+        return acc
+
+    def solid_step(self, mat, dt, u, v, plastic=None, p=None, flags=None):
+        PB = self.arr(self.dim * self.dim, self.n)
+        acc = self.arr(self.dim, self.n)
+        rc = self.lib.orc_solid_step(self._h, C.byref(mat), float(dt), _ptr(self._a(u)), _ptr(self._a(v)),
+                                     _ptr(self._a(plastic)), _ptr(self._a(p)), _ptr(flags), _ptr(PB), _ptr(acc))
+        return rc, PB, acc
+
+    def damping_sweep(self, rho0, eta, dt, v, flags=None):
+        self.lib.orc_damping_sweep(self._h, float(rho0), float(eta), float(dt), _ptr(self._a(v)), _ptr(flags))
+
+    def drift_ke(self, rho0, dt, u, v, flags=None):
+        ke = self.lib.orc_drift_ke(self._h, float(rho0), float(dt), _ptr(self._a(u)), _ptr(self._a(v)),
+                                   _ptr(flags))
+        return self._from_real(ke)
+
+    def load_step(self, dt_l, u, vgrip, flags):
+        self.lib.orc_load_step(self._h, float(dt_l), _ptr(self._a(u)), _ptr(self._a(vgrip)), _ptr(flags))
+
+    def diffusion_step(self, D, dt_d, c_bc, C_swell, c0, c, q, p, flags=None):
+        self.lib.orc_diffusion_step(self._h, _to_real(D, self.cplx), float(dt_d), float(c_bc),
+                                    _to_real(C_swell, self.cplx), float(c0), _ptr(self._a(c)),
+                                    _ptr(self._a(q)), _ptr(self._a(p)), _ptr(flags))
+
+    def advance(self, mat, cfg, u, v, plastic=None, c=None, q=None, p=None, vgrip=None, flags=None,
+                k_sched=None):
+        k_out = np.zeros(cfg.n_slow, np.int64)
+        ke_out = np.zeros(cfg.n_slow)
+        conv = np.zeros(cfg.n_slow, np.int32)
+        if k_sched is not None:
+            k_sched = np.ascontiguousarray(k_sched, dtype=np.int64)
+        rc = self.lib.orc_advance(self._h, C.byref(mat), C.byref(cfg), _ptr(self._a(u)), _ptr(self._a(v)),
+                                  _ptr(self._a(plastic)), _ptr(self._a(c)), _ptr(self._a(q)), _ptr(self._a(p)),
+                                  _ptr(self._a(vgrip)), _ptr(flags), _ptr(k_sched), _ptr(k_out), _ptr(ke_out),
+                                  _ptr(conv))
+        return rc, k_out, ke_out, conv

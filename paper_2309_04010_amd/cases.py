@@ -1,0 +1,209 @@
+"""Seeded synthetic inputs: particle lattices, boundary flags and parameters.
+
+This module only *generates inputs* (positions, volumes, flags, prescribed
+grip velocities, material and schedule parameters).  It holds none of the
+method's arithmetic: kernel sums, moduli conversions inside the method, time
+step formulas and every SPH operator live on each side separately (the GPU
+library and the CPU oracle).  Both sides draw their inputs from here.
+
+Geometry follows the paper's test shapes (a bar stretched by grips at its
+ends, a thin strip or plate swelling by water diffusion, Sec. 5), at the sizes
+and parameter values of the five benchmark workloads:
+
+  bar2d     2D bar 40 x 8, linear elastic, grips at both ends, loading.
+  strip2d   2D strip 200 x 10, neo-Hookean + swelling, diffusion from the top.
+  neck3d    3D bar 100 x 20 x 20, J2 nonlinear hardening, symmetric pull.
+  plate3d   3D plate 500 x 500 x 4, neo-Hookean + swelling, diffusion patch.
+  strips2d  64 strips of log-uniform sizes (batched parameter sweep).
+
+Positions are X = ((i + 1/2) dp, (j + 1/2) dp, (k + 1/2) dp) with particle id
+i + nx (j + ny k); jitter, when asked for, is U(-a dp, a dp) drawn with
+numpy.default_rng(seed) as an (n, dim) array in id order (x, then y, then z).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FIXED, CDIR, GRIP = 1, 2, 4
+LE, NH, J2 = 0, 1, 2
+LOAD, DIFFUSION = 0, 1
+
+
+def lattice(shape, dp, jitter=0.0, seed=None):
+    """Reference positions [dim, n] (float64) of a cartesian particle lattice."""
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    idx = np.indices(shape[::-1]).reshape(dim, -1)[::-1]  # idx[0] fastest
+    X = (idx.astype(np.float64) + 0.5) * dp
+    if jitter:
+        rng = np.random.default_rng(seed)
+        X = X + rng.uniform(-jitter * dp, jitter * dp, size=(X.shape[1], dim)).T
+    return np.ascontiguousarray(X), idx
+
+
+@dataclass
+class Case:
+    name: str
+    dim: int
+    shape: tuple
+    dp: float
+    X: np.ndarray                 # [dim, n] input order
+    V: np.ndarray                 # [n]
+    h: float
+    flags: np.ndarray             # [n] uint8
+    vgrip: np.ndarray | None      # [dim, n] prescribed grip velocity (loading)
+    c_init: np.ndarray | None     # [n] initial saturation
+    material: dict
+    run: dict                     # multirate schedule parameters
+    observable: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return self.X.shape[1]
+
+
+def _sizes_ok(shape):
+    for s in shape:
+        if s < 1:
+            raise ValueError("lattice extent must be positive")
+
+
+def bar2d(nx=40, ny=8, dp=0.25e-3, grip_layers=3, pull=1.0e-3, dt_l=1.0e-3, n_slow=100,
+          eta=1.0e4, ke_rel=1.0e-8, affine=False):
+    """2D bar stretched in x.  Left `grip_layers` columns clamped; right ones
+    moved at `pull` m/s.  With `affine`, both grips follow the homogeneous
+    plane-strain uniaxial field u_x = e X, u_y = -nu/(1-nu) e Y (the elastic
+    analytic solution), so the converged interior is that affine field."""
+    _sizes_ok((nx, ny))
+    X, idx = lattice((nx, ny), dp)
+    n = X.shape[1]
+    V = np.full(n, dp * dp)
+    E, nu, rho = 210.0e9, 0.3, 7850.0
+    flags = np.zeros(n, np.uint8)
+    vgrip = np.zeros((2, n))
+    left = idx[0] < grip_layers
+    right = idx[0] >= nx - grip_layers
+    flags[left | right] = FIXED
+    L = nx * dp
+    if affine:
+        # strain rate of the homogeneous field (whole bar length L between the
+        # grip mid-planes is irrelevant: the field is affine everywhere)
+        erate = pull / L
+        grips = left | right
+        flags[grips] |= GRIP
+        xc = X[0] - 0.5 * L
+        yc = X[1] - 0.5 * ny * dp
+        vgrip[0, grips] = erate * xc[grips]
+        vgrip[1, grips] = -nu / (1.0 - nu) * erate * yc[grips]
+    else:
+        flags[right] |= GRIP
+        vgrip[0, right] = pull
+    # reference energy 1/2 F delta with the plane-strain bar stiffness
+    W = ny * dp
+    L_free = (nx - 2 * grip_layers) * dp
+    delta_total = pull * dt_l * n_slow
+    F_ref = E / (1.0 - nu * nu) * W * delta_total / L_free
+    E_ref = 0.5 * F_ref * delta_total
+    return Case("bar2d", 2, (nx, ny), dp, X, V, 1.3 * dp, flags, vgrip, None,
+                dict(model=LE, E=E, nu=nu, rho0=rho),
+                dict(n_slow=n_slow, slow_kind=LOAD, dt_slow=dt_l, eta=eta, ke_tol=ke_rel * E_ref,
+                     k_max=0, fixed_inner=0, D=0.0, c_bc=0.0),
+                dict(E_ref=E_ref, erate=pull / L))
+
+
+def strip2d(nx=200, ny=10, dp=12.5e-6, clamp_layers=3, E=100.0e6, nu=0.4, D=1.0e-10,
+            n_slow=100, eta=1.0e3, k_max=100000, fixed_inner=0, ke_frac=5.0e-4):
+    """2D strip, water entering through the top row (Dirichlet c = a = 0.4),
+    swelling through p = C (c - c0); both ends clamped."""
+    _sizes_ok((nx, ny))
+    X, idx = lattice((nx, ny), dp)
+    n = X.shape[1]
+    V = np.full(n, dp * dp)
+    rho, C_swell, a_por = 2000.0, 3.0e6, 0.4
+    flags = np.zeros(n, np.uint8)
+    flags[(idx[0] < clamp_layers) | (idx[0] >= nx - clamp_layers)] |= FIXED
+    flags[idx[1] == ny - 1] |= CDIR
+    c_init = np.zeros(n)
+    # density kinetic energy sum(1/2 m v^2) / sum(V) <= frac * C * a
+    ke_tol = ke_frac * C_swell * a_por * V.sum()
+    mid = (idx[0] == nx // 2) & (idx[1] == ny - 1)
+    return Case("strip2d", 2, (nx, ny), dp, X, V, 1.3 * dp, flags, None, c_init,
+                dict(model=NH, E=E, nu=nu, rho0=rho, C_swell=C_swell, c0=0.0),
+                dict(n_slow=n_slow, slow_kind=DIFFUSION, dt_slow=0.0, eta=eta, ke_tol=ke_tol,
+                     k_max=k_max, fixed_inner=fixed_inner, D=D, c_bc=a_por),
+                dict(J_index=np.nonzero(mid)[0], J_component=1))
+
+
+def neck3d(nx=100, ny=20, nz=20, dp=0.53334e-3, grip_layers=3, total_stretch=7.0e-3,
+           n_slow=100, dt_l=1.0, fixed_inner=1000, eta=1.0e4, jitter=0.01, seed=3):
+    """3D bar with J2 plasticity, pulled symmetrically at both ends."""
+    _sizes_ok((nx, ny, nz))
+    X, idx = lattice((nx, ny, nz), dp, jitter=jitter, seed=seed)
+    n = X.shape[1]
+    V = np.full(n, dp ** 3)
+    mu, K = 80.1938e9, 164.21e9       # shear and bulk moduli of the necking table
+    E = 9.0 * K * mu / (3.0 * K + mu)
+    nu = (3.0 * K - 2.0 * mu) / (2.0 * (3.0 * K + mu))
+    flags = np.zeros(n, np.uint8)
+    vgrip = np.zeros((3, n))
+    left = idx[0] < grip_layers
+    right = idx[0] >= nx - grip_layers
+    flags[left | right] = FIXED | GRIP
+    vpull = 0.5 * total_stretch / (n_slow * dt_l)
+    vgrip[0, left] = -vpull
+    vgrip[0, right] = vpull
+    return Case("neck3d", 3, (nx, ny, nz), dp, X, V, 1.3 * dp, flags, vgrip, None,
+                dict(model=J2, E=E, nu=nu, rho0=7850.0, sigma0=200.0e6, sigma_inf=400.0e6,
+                     delta=16.0, H=0.0),
+                dict(n_slow=n_slow, slow_kind=LOAD, dt_slow=dt_l, eta=eta, ke_tol=0.0, k_max=0,
+                     fixed_inner=fixed_inner, D=0.0, c_bc=0.0))
+
+
+def plate3d(nx=500, ny=500, nz=4, dp=31.25e-6, clamp_layers=3, patch=0.3, wet_layers=2,
+            E=100.0e6, nu=0.4, D=1.0e-10, C_swell=3.0e6, n_slow=50, fixed_inner=1000,
+            eta=1.0e4):
+    """3D thin plate, clamped on its four side faces, wetted on the top layers
+    of a central patch; observable = mean u_z of the centre columns."""
+    _sizes_ok((nx, ny, nz))
+    X, idx = lattice((nx, ny, nz), dp)
+    n = X.shape[1]
+    V = np.full(n, dp ** 3)
+    flags = np.zeros(n, np.uint8)
+    side = ((idx[0] < clamp_layers) | (idx[0] >= nx - clamp_layers) |
+            (idx[1] < clamp_layers) | (idx[1] >= ny - clamp_layers))
+    flags[side] |= FIXED
+    px0 = int(round(nx * (1 - patch) / 2)); px1 = nx - px0
+    py0 = int(round(ny * (1 - patch) / 2)); py1 = ny - py0
+    wet = ((idx[0] >= px0) & (idx[0] < px1) & (idx[1] >= py0) & (idx[1] < py1) &
+           (idx[2] >= nz - wet_layers))
+    flags[wet] |= CDIR
+    c_init = np.zeros(n)
+    ci, cj = (nx - 1) // 2, (ny - 1) // 2
+    centre = np.isin(idx[0], [ci, ci + 1]) & np.isin(idx[1], [cj, cj + 1])
+    return Case("plate3d", 3, (nx, ny, nz), dp, X, V, 1.3 * dp, flags, None, c_init,
+                dict(model=NH, E=E, nu=nu, rho0=2000.0, C_swell=C_swell, c0=0.0),
+                dict(n_slow=n_slow, slow_kind=DIFFUSION, dt_slow=0.0, eta=eta, ke_tol=0.0,
+                     k_max=0, fixed_inner=fixed_inner, D=D, c_bc=0.4),
+                dict(J_index=np.nonzero(centre)[0], J_component=2))
+
+
+def strips_sweep(n_strips=64, seed=5, dp=12.5e-6, n_min=1000, n_max=50000, rows=10,
+                 n_slow=10, fixed_inner=200):
+    """Batched sweep: strips of log-uniform size with E ~ U(50, 200) MPa and
+    D ~ LogU(1e-11, 1e-9); draws in this order: sizes, E, D."""
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(np.exp(rng.uniform(np.log(n_min), np.log(n_max), n_strips))).astype(int)
+    Es = rng.uniform(50.0e6, 200.0e6, n_strips)
+    Ds = np.exp(rng.uniform(np.log(1e-11), np.log(1e-9), n_strips))
+    out = []
+    for N, E, D in zip(sizes, Es, Ds):
+        ncol = max(int(round(N / rows)), 8)
+        out.append(strip2d(nx=ncol, ny=rows, dp=dp, E=float(E), D=float(D), n_slow=n_slow,
+                           fixed_inner=fixed_inner, eta=1.0e3))
+    return out
+
+
+def by_name(name, **kw):
+    return {"bar2d": bar2d, "strip2d": strip2d, "neck3d": neck3d, "plate3d": plate3d}[name](**kw)
