@@ -1,0 +1,238 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) library for the fast process of
+ * total-Lagrangian SPH solid dynamic relaxation inside an explicit
+ * multi-time-step scheme (Tang, Wu, Wang, Haidn, Hu, arXiv 2309.04010), with
+ * the slow-process SPH diffusion update beside it.
+ *
+ * Conventions
+ *  - Every function returns int: SPH_OK (0), a negative SPH_E_* error, or the
+ *    positive warning SPH_W_NOT_CONVERGED.  No exception crosses the ABI.
+ *    sph_last_error() returns a thread-local description of the last error.
+ *  - All array arguments are DEVICE pointers unless marked "host".  Arrays are
+ *    structure-of-arrays [component][n], contiguous, in the cell-sorted
+ *    particle order fixed by sph_build_neighbors (perm[s] = input index of
+ *    sorted particle s).  Matrices per particle are row-major d x d.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream unless stated otherwise.
+ *  - Precision: sph_state.prec selects the element type (float or double) of
+ *    v, PB, plastic, c, q, p, acc and vgrip.  Displacements u, the kinetic
+ *    energy and all reductions are always double.
+ *  - Ownership: the neighbour handle owns its device memory (allocated once,
+ *    at build time).  State arrays belong to the caller.  Stepping functions
+ *    allocate nothing.  Two calls that use the same handle must not overlap
+ *    in time (they share the handle's small control block).
+ *  - Device-side faults (non-finite kinetic energy, return-mapping Newton
+ *    failure, singular correction matrix) are latched in the handle's status
+ *    word and reported by the next synchronising call (sph_status,
+ *    sph_advance_multirate, sph_build_neighbors) as SPH_E_NUMERIC.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_OK 0
+#define SPH_E_ARG (-1)         /* invalid argument (null pointer, bad size) */
+#define SPH_E_CAPACITY (-2)    /* a structural limit of the build was exceeded */
+#define SPH_E_DEVICE (-3)      /* HIP runtime error */
+#define SPH_E_NUMERIC (-4)     /* NaN/Inf, singular B0, Newton failure */
+#define SPH_E_UNSUPPORTED (-5) /* unsupported dimension / model / precision */
+#define SPH_W_NOT_CONVERGED 1  /* an inner loop hit its step cap */
+
+#define SPH_F32 0
+#define SPH_F64 1
+
+#define SPH_MODEL_LE 0 /* small-strain linear elastic (plane strain in 2D) */
+#define SPH_MODEL_NH 1 /* neo-Hookean, App. A.2 eq. (kirchoff_stress_equation) */
+#define SPH_MODEL_J2 2 /* J2 return mapping, App. A.4 Algorithm 1 */
+
+#define SPH_SLOW_LOAD 0      /* slow step = prescribed grip displacement increment */
+#define SPH_SLOW_DIFFUSION 1 /* slow step = SPH diffusion of the saturation */
+
+/* per-particle flag bits (uint8) */
+#define SPH_FLAG_FIXED 1u /* velocity held (zero) in the inner loop; infinite mass in damping */
+#define SPH_FLAG_CDIR 2u  /* saturation reset to c_bc after every diffusion step */
+#define SPH_FLAG_GRIP 4u  /* u += dt_slow * vgrip at every loading step */
+
+/* status bits latched on the device */
+#define SPH_STATUS_NONFINITE 1
+#define SPH_STATUS_NEWTON 2
+#define SPH_STATUS_SINGULAR_B0 4
+
+typedef struct sph_nbr sph_nbr; /* opaque: fixed neighbourhood + schedule */
+
+/* Read-only view of a built neighbourhood (device pointers owned by the
+ * handle; valid until sph_nbr_destroy). */
+typedef struct {
+  int32_t dim;
+  int32_t n_colors;        /* 2^dim cell-parity colours of the damping sweep */
+  int64_t n;               /* particles */
+  int64_t n_pairs;         /* directed neighbour pairs (CSR length) */
+  int64_t n_upairs;        /* undirected pairs = n_pairs / 2 */
+  int64_t n_cells;         /* cells of edge 2h */
+  int64_t ncell[3];        /* cells per axis (1 for unused axes) */
+  int64_t n_anchors;       /* cells that anchor at least one pair */
+  int64_t max_deg;         /* largest neighbour count */
+  int64_t max_level;       /* largest number of levels of one anchor */
+  int64_t color_off[9];    /* host: anchors of colour k are [color_off[k], color_off[k+1]) */
+  double origin[3];        /* componentwise minimum of the reference positions */
+  double h;                /* smoothing length; support radius 2h */
+  double inv_rc;           /* 1/(2h), as used for the cell keys */
+  const uint32_t* key;     /* [n] cell key of each sorted particle */
+  const uint32_t* perm;    /* [n] sorted position -> input index */
+  const uint32_t* cell_start; /* [n_cells+1] first sorted particle of each cell */
+  const int64_t* nbr_off;  /* [n+1] CSR offsets */
+  const uint32_t* nbr_idx; /* [n_pairs] neighbours, ascending sorted position */
+  const double* X;         /* [dim][n] sorted reference positions */
+  const double* V;         /* [n] sorted reference volumes */
+  const double* B0;        /* [dim*dim][n] correction matrices (FP64) */
+  const uint32_t* sched_a; /* [n_upairs] damping pairs in canonical order: smaller index */
+  const uint32_t* sched_b; /* [n_upairs] larger index */
+  const uint32_t* sched_level; /* [n_upairs] level of the pair within its anchor */
+  const uint32_t* anchor_key;  /* [n_anchors] anchor cells, by (colour, key) */
+  const int64_t* anchor_off;   /* [n_anchors+1] pair range of each anchor */
+  const uint32_t* anchor_nlev; /* [n_anchors] levels per anchor */
+} sph_nbr_info;
+
+typedef struct {
+  int32_t model; /* SPH_MODEL_* */
+  int32_t pad_;
+  double E;      /* Young's modulus; mu = E/(2(1+nu)), K = E/(3(1-2nu)) (eq. relation-modulus) */
+  double nu;     /* Poisson ratio */
+  double rho0;   /* reference density (TL momentum uses rho0, eq. mechanical-mom) */
+  double sigma0, sigma_inf, delta, H; /* hardening k(a) = s0 + (sinf-s0)(1-exp(-delta a)) + H a (App. A.3) */
+  double C_swell; /* fluid-pressure coefficient: p = C (c - c0), eq. (fluid_pressure) */
+  double c0;      /* initial saturation */
+} sph_material;
+
+typedef struct {
+  int32_t prec;  /* SPH_F32 or SPH_F64: element type of the void* arrays below */
+  int32_t pad_;
+  double* u;     /* [dim][n] displacement, always FP64 */
+  void* v;       /* [dim][n] velocity */
+  void* PB;      /* [dim*dim][n] P B0 (written by the stress stage, read by momentum) */
+  void* plastic; /* [7][n] J2 state: Cbar_p^-1 (xx,yy,zz,xy,yz,xz) and alpha; NULL unless J2 */
+  void* c;       /* [n] saturation (diffusion) or NULL */
+  void* q;       /* [dim][n] flux scratch of the diffusion step or NULL */
+  void* p;       /* [n] fluid pressure used by the stress stage, or NULL (no swelling) */
+  void* acc;     /* [dim][n] optional output: acceleration before the kick, or NULL */
+  void* vgrip;   /* [dim][n] prescribed grip velocity for loading steps, or NULL */
+  const uint8_t* flags; /* [n] SPH_FLAG_* bits, or NULL (all free) */
+} sph_state;
+
+typedef struct {
+  int32_t n_slow;      /* outer (slow) steps */
+  int32_t slow_kind;   /* SPH_SLOW_LOAD / SPH_SLOW_DIFFUSION */
+  double dt_slow;      /* loading step; diffusion: <= 0 selects 0.5 h^2 / D (Sec. 4.1) */
+  double dt_s;         /* inner step; <= 0 selects 0.6 h / sqrt(K/rho0) (eq. dts-advection at rest) */
+  double eta;          /* damping viscosity (eq. damping-sph) */
+  int64_t k_max;       /* inner cap; <= 0 selects k0 = floor(dt_slow/dt_s) + 1 (Sec. 4.2) */
+  int64_t fixed_inner; /* > 0: exactly this many inner steps, no kinetic-energy exit */
+  double ke_tol;       /* absolute kinetic-energy threshold of the early exit */
+  double D;            /* diffusion coefficient */
+  double c_bc;         /* Dirichlet saturation */
+  int32_t chunk;       /* inner steps launched between host polls (<= 0: 64) */
+  int32_t use_graph;   /* 1: replay each chunk as a captured hipGraph */
+  const int64_t* k_sched; /* host, optional [n_slow]: frozen inner counts */
+} sph_multirate_cfg;
+
+typedef struct {
+  int64_t* k;          /* host [n_slow] (or NULL): inner steps taken per slow step */
+  double* ke;          /* host [n_slow] (or NULL): kinetic energy after the last inner step */
+  int32_t* converged;  /* host [n_slow] (or NULL): 1 if ke <= ke_tol at the end */
+  double dt_s;         /* out: inner step used */
+  double dt_slow;      /* out: slow step used */
+  int64_t k_max;       /* out: inner cap used */
+  int64_t total_inner; /* out: sum of k */
+} sph_report;
+
+/* ------------------------------------------------------------------------
+ * Fixed neighbourhood (Sec. 3.1: in the total-Lagrangian form the neighbour
+ * set and the correction matrix B0 of eq. (sph-correctmatrix) are built once
+ * in the initial configuration).
+ *   X [dim][n], V [n]: device FP64 reference positions and volumes, input order.
+ *   h: smoothing length; neighbours are b != a with |X_a - X_b|^2 < (2h)^2
+ *      (FP64, no fused multiply-add), found in cells of edge 2h with origin at
+ *      the componentwise minimum of X.  Particles are stably sorted by cell
+ *      key (x fastest); lists are in ascending sorted position.
+ *   Damping schedule: each unordered pair is anchored at the componentwise
+ *   minimum of its two cells and coloured by the parity of that anchor
+ *   (2^dim colours, so anchors of one colour touch disjoint 2^dim-cell blocks);
+ *   within an anchor, pairs in ascending (a, b) take the smallest level not
+ *   used by an earlier pair sharing a particle.
+ *   Synchronous.  On success *out receives a new handle.
+ *   Errors: SPH_E_ARG, SPH_E_UNSUPPORTED (dim not 2/3), SPH_E_CAPACITY (more
+ *   than 2^32-16 cells, 2^31 pairs, or an anchor block too dense for the level
+ *   builder), SPH_E_NUMERIC (singular correction matrix), SPH_E_DEVICE. */
+int sph_build_neighbors(int dim, int64_t n, const double* X, const double* V, double h,
+                        void* stream, sph_nbr** out);
+int sph_nbr_destroy(sph_nbr* nbr);
+int sph_nbr_query(const sph_nbr* nbr, sph_nbr_info* info);
+
+/* ------------------------------------------------------------------------
+ * One solid stage of an inner step (Sec. 3.1): deformation gradient from u
+ *   F_a = I + (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a
+ * (eq. deformationtensor-displacement with the corrected gradient; the exact
+ * time integral of eq. rate_F), the first Piola-Kirchhoff stress of the
+ * material model with the fluid-pressure term P -= J p F^-T (App. B.2),
+ * PB = P B0, the pair-averaged momentum sum of eq. (sph-mechanical-mom)
+ *   a_a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab,
+ * and the kick v += dt_s a for particles without SPH_FLAG_FIXED.
+ * J2 state in `plastic` is committed.  Asynchronous. */
+int sph_solid_relax_step(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                         double dt_s, void* stream);
+
+/* Implicit pairwise-splitting sweep of the viscous damping term (Sec. 4.3,
+ * eq. damping-sph): for every pair in canonical order (colour, anchor, level)
+ *   beta = 2 eta V_a V_b (dW/dr / r) dt_s,
+ *   delta = beta (v_a - v_b) / (m_a m_b - beta (m_a + m_b)),
+ *   v_a += m_b delta, v_b -= m_a delta,
+ * with a fixed particle acting as infinite mass.  Pairs of one level of one
+ * anchor are disjoint and anchors of one colour touch disjoint particles, so
+ * the parallel sweep equals the sequential canonical order.  Asynchronous. */
+int sph_damping_sweep(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                      double eta, double dt_s, void* stream);
+
+/* Drift and kinetic energy (Sec. 4.2): u += dt_s v for free particles, then
+ * E_k = sum 1/2 rho0 V |v|^2 reduced in a fixed order (deterministic) into
+ * the device double *ke_out (may be NULL).  Asynchronous. */
+int sph_drift_ke(const sph_nbr* nbr, const sph_material* mat, const sph_state* st, double dt_s,
+                 double* ke_out, void* stream);
+
+/* Loading slow step: u += dt_l * vgrip for SPH_FLAG_GRIP particles.  Async. */
+int sph_load_step(const sph_nbr* nbr, const sph_state* st, double dt_l, void* stream);
+
+/* Diffusion slow step (Fick's law, eqs. grad_q and fluid_mass_der, SPH form
+ * of Sec. 3.2 read as linear in the saturation c with constant D):
+ *   q_a = -D B0_a sum_b V_b (c_b - c_a) grad_a W_ab,
+ *   c_a += dt_d (- sum_b V_b (B0_a q_a + B0_b q_b) . grad_a W_ab),
+ * then c = c_bc on SPH_FLAG_CDIR particles and p = C_swell (c - c0)
+ * (eq. fluid_pressure) when st->p is not NULL.  Needs st->c and st->q.  Async. */
+int sph_diffusion_step(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                       double D, double dt_d, double c_bc, void* stream);
+
+/* Multi-time-step driver (Sec. 4.2): for l = 1..n_slow, one slow step (load
+ * or diffusion), then inner steps {solid stage, damping sweep, drift + E_k}
+ * until E_k <= ke_tol, or k = k_max (warning), or exactly fixed_inner /
+ * k_sched[l] steps.  The stop test runs on the device; the host polls once per
+ * chunk of inner steps.  Synchronous; fills the host report.  Returns SPH_OK,
+ * SPH_W_NOT_CONVERGED, or an error. */
+int sph_advance_multirate(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                          const sph_multirate_cfg* cfg, sph_report* report, void* stream);
+
+/* Synchronise `stream` and return (and clear) the latched status bits in
+ * *status_bits (may be NULL): SPH_OK, or SPH_E_NUMERIC if any bit was set. */
+int sph_status(const sph_nbr* nbr, void* stream, int32_t* status_bits);
+
+/* Thread-local description of the last error ("" if none). */
+const char* sph_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H */

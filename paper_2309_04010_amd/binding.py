@@ -1,0 +1,331 @@
+"""Thin ctypes binding of libsph.so (include/sph.h), same names as the C ABI.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libsph.so.  PyTorch supplies device memory (tensors) and the stream
+(torch's current stream).  If the library is missing, or no GPU is visible,
+calls raise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph.so")
+
+SPH_OK, SPH_E_ARG, SPH_E_CAPACITY, SPH_E_DEVICE, SPH_E_NUMERIC, SPH_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+SPH_W_NOT_CONVERGED = 1
+SPH_F32, SPH_F64 = 0, 1
+SPH_MODEL_LE, SPH_MODEL_NH, SPH_MODEL_J2 = 0, 1, 2
+SPH_SLOW_LOAD, SPH_SLOW_DIFFUSION = 0, 1
+SPH_FLAG_FIXED, SPH_FLAG_CDIR, SPH_FLAG_GRIP = 1, 2, 4
+
+EXPORTED = [
+    "sph_build_neighbors", "sph_nbr_destroy", "sph_nbr_query", "sph_solid_relax_step",
+    "sph_damping_sweep", "sph_drift_ke", "sph_load_step", "sph_diffusion_step",
+    "sph_advance_multirate", "sph_status", "sph_last_error",
+]
+
+
+class SphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sph error {code}: {msg}")
+        self.code = code
+
+
+vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+
+
+class NbrInfo(C.Structure):
+    _fields_ = [("dim", i32), ("n_colors", i32), ("n", i64), ("n_pairs", i64), ("n_upairs", i64),
+                ("n_cells", i64), ("ncell", i64 * 3), ("n_anchors", i64), ("max_deg", i64),
+                ("max_level", i64), ("color_off", i64 * 9), ("origin", dbl * 3), ("h", dbl),
+                ("inv_rc", dbl), ("key", vp), ("perm", vp), ("cell_start", vp), ("nbr_off", vp),
+                ("nbr_idx", vp), ("X", vp), ("V", vp), ("B0", vp), ("sched_a", vp), ("sched_b", vp),
+                ("sched_level", vp), ("anchor_key", vp), ("anchor_off", vp), ("anchor_nlev", vp)]
+
+
+class Material(C.Structure):
+    _fields_ = [("model", i32), ("pad_", i32), ("E", dbl), ("nu", dbl), ("rho0", dbl),
+                ("sigma0", dbl), ("sigma_inf", dbl), ("delta", dbl), ("H", dbl),
+                ("C_swell", dbl), ("c0", dbl)]
+
+
+class State(C.Structure):
+    _fields_ = [("prec", i32), ("pad_", i32), ("u", vp), ("v", vp), ("PB", vp), ("plastic", vp),
+                ("c", vp), ("q", vp), ("p", vp), ("acc", vp), ("vgrip", vp), ("flags", vp)]
+
+
+class MultirateCfg(C.Structure):
+    _fields_ = [("n_slow", i32), ("slow_kind", i32), ("dt_slow", dbl), ("dt_s", dbl), ("eta", dbl),
+                ("k_max", i64), ("fixed_inner", i64), ("ke_tol", dbl), ("D", dbl), ("c_bc", dbl),
+                ("chunk", i32), ("use_graph", i32), ("k_sched", vp)]
+
+
+class Report(C.Structure):
+    _fields_ = [("k", vp), ("ke", vp), ("converged", vp), ("dt_s", dbl), ("dt_slow", dbl),
+                ("k_max", i64), ("total_inner", i64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsph.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SphError(SPH_E_DEVICE, f"{LIB_PATH} is missing: run paper_2309_04010_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    L.sph_build_neighbors.argtypes = [C.c_int, i64, vp, vp, dbl, vp, C.POINTER(vp)]
+    L.sph_nbr_destroy.argtypes = [vp]
+    L.sph_nbr_query.argtypes = [vp, C.POINTER(NbrInfo)]
+    L.sph_solid_relax_step.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp]
+    L.sph_damping_sweep.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, vp]
+    L.sph_drift_ke.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp, vp]
+    L.sph_load_step.argtypes = [vp, C.POINTER(State), dbl, vp]
+    L.sph_diffusion_step.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, dbl, vp]
+    L.sph_advance_multirate.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
+                                        C.POINTER(MultirateCfg), C.POINTER(Report), vp]
+    L.sph_status.argtypes = [vp, vp, C.POINTER(i32)]
+    L.sph_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        getattr(L, name).restype = C.c_int if name != "sph_last_error" else C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc, allow_warning=False):
+    if rc == SPH_OK or (allow_warning and rc == SPH_W_NOT_CONVERGED):
+        return rc
+    raise SphError(rc, lib().sph_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape, name):
+    import torch
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise SphError(SPH_E_ARG, f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise SphError(SPH_E_ARG, f"{name}: want {dtype} {tuple(shape)} contiguous, got "
+                                  f"{t.dtype} {tuple(t.shape)}")
+    del torch
+
+
+# --- device -> host copies of handle-owned arrays (plumbing) ----------------
+_hip = None
+
+
+def _hip_lib():
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [vp, vp, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    return _hip
+
+
+def copy_out(ptr, count, dtype):
+    out = np.empty(int(count), dtype=dtype)
+    if count:
+        rc = _hip_lib().hipMemcpy(out.ctypes.data_as(vp), C.c_void_p(ptr), out.nbytes, 2)
+        if rc != 0:
+            raise SphError(SPH_E_DEVICE, f"hipMemcpy failed ({rc})")
+    return out
+
+
+class Neighbors:
+    """Owner of an sph_nbr handle (fixed TL neighbourhood + damping schedule)."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+        self.info = NbrInfo()
+        _check(lib().sph_nbr_query(self._h, C.byref(self.info)))
+        self.dim = self.info.dim
+        self.n = self.info.n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().sph_nbr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def host(self, name):
+        """Copy one handle-owned array to a numpy array (for checks)."""
+        i = self.info
+        d, n = i.dim, i.n
+        spec = {
+            "key": (i.key, n, np.uint32), "perm": (i.perm, n, np.uint32),
+            "cell_start": (i.cell_start, i.n_cells + 1, np.uint32),
+            "nbr_off": (i.nbr_off, n + 1, np.int64), "nbr_idx": (i.nbr_idx, i.n_pairs, np.uint32),
+            "X": (i.X, d * n, np.float64), "V": (i.V, n, np.float64),
+            "B0": (i.B0, d * d * n, np.float64),
+            "sched_a": (i.sched_a, i.n_upairs, np.uint32), "sched_b": (i.sched_b, i.n_upairs, np.uint32),
+            "sched_level": (i.sched_level, i.n_upairs, np.uint32),
+            "anchor_key": (i.anchor_key, i.n_anchors, np.uint32),
+            "anchor_off": (i.anchor_off, i.n_anchors + 1, np.int64),
+            "anchor_nlev": (i.anchor_nlev, i.n_anchors, np.uint32),
+        }[name]
+        arr = copy_out(*spec)
+        if name == "X":
+            arr = arr.reshape(d, n)
+        elif name == "B0":
+            arr = arr.reshape(d * d, n)
+        return arr
+
+
+def sph_build_neighbors(X, V, h, stream=None):
+    """X: cuda float64 [dim, n]; V: cuda float64 [n] (input order)."""
+    import torch
+    dim, n = X.shape
+    _need(X, torch.float64, (dim, n), "X")
+    _need(V, torch.float64, (n,), "V")
+    out = C.c_void_p()
+    _check(lib().sph_build_neighbors(int(dim), int(n), _dptr(X), _dptr(V), float(h), _stream(stream),
+                                     C.byref(out)))
+    return Neighbors(out, (X, V))
+
+
+def material(model, E, nu, rho0, sigma0=0.0, sigma_inf=0.0, delta=0.0, H=0.0, C_swell=0.0, c0=0.0):
+    return Material(int(model), 0, float(E), float(nu), float(rho0), float(sigma0), float(sigma_inf),
+                    float(delta), float(H), float(C_swell), float(c0))
+
+
+@dataclass
+class SphState:
+    """Caller-owned device state (torch tensors), cell-sorted order."""
+    prec: int
+    u: object
+    v: object
+    PB: object
+    plastic: object = None
+    c: object = None
+    q: object = None
+    p: object = None
+    acc: object = None
+    vgrip: object = None
+    flags: object = None
+    _c: State = field(default=None, repr=False)
+
+    def validate(self, nbr):
+        import torch
+        d, n = nbr.dim, nbr.n
+        T = torch.float32 if self.prec == SPH_F32 else torch.float64
+        _need(self.u, torch.float64, (d, n), "u")
+        _need(self.v, T, (d, n), "v")
+        _need(self.PB, T, (d * d, n), "PB")
+        _need(self.plastic, T, (7, n), "plastic")
+        _need(self.c, T, (n,), "c")
+        _need(self.q, T, (d, n), "q")
+        _need(self.p, T, (n,), "p")
+        _need(self.acc, T, (d, n), "acc")
+        _need(self.vgrip, T, (d, n), "vgrip")
+        _need(self.flags, torch.uint8, (n,), "flags")
+
+    def cstruct(self, nbr):
+        self.validate(nbr)
+        return State(int(self.prec), 0, _dptr(self.u), _dptr(self.v), _dptr(self.PB), _dptr(self.plastic),
+                     _dptr(self.c), _dptr(self.q), _dptr(self.p), _dptr(self.acc), _dptr(self.vgrip),
+                     _dptr(self.flags))
+
+
+def new_state(nbr, prec, with_plastic=False, with_diffusion=False, with_acc=False, device="cuda"):
+    import torch
+    d, n = nbr.dim, nbr.n
+    T = torch.float32 if prec == SPH_F32 else torch.float64
+    z = lambda *s, dt=T: torch.zeros(s, dtype=dt, device=device)  # noqa: E731
+    st = SphState(prec, z(d, n, dt=torch.float64), z(d, n), z(d * d, n))
+    if with_plastic:
+        pl = z(7, n)
+        pl[0:3] = 1.0
+        st.plastic = pl
+    if with_diffusion:
+        st.c, st.q, st.p = z(n), z(d, n), z(n)
+    if with_acc:
+        st.acc = z(d, n)
+    return st
+
+
+def sph_solid_relax_step(nbr, mat, st, dt_s, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_solid_relax_step(nbr.handle, C.byref(mat), C.byref(cs), float(dt_s), _stream(stream)))
+
+
+def sph_damping_sweep(nbr, mat, st, eta, dt_s, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_damping_sweep(nbr.handle, C.byref(mat), C.byref(cs), float(eta), float(dt_s),
+                                   _stream(stream)))
+
+
+def sph_drift_ke(nbr, mat, st, dt_s, ke_out=None, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_drift_ke(nbr.handle, C.byref(mat), C.byref(cs), float(dt_s), _dptr(ke_out),
+                              _stream(stream)))
+
+
+def sph_load_step(nbr, st, dt_l, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_load_step(nbr.handle, C.byref(cs), float(dt_l), _stream(stream)))
+
+
+def sph_diffusion_step(nbr, mat, st, D, dt_d, c_bc, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_diffusion_step(nbr.handle, C.byref(mat), C.byref(cs), float(D), float(dt_d),
+                                    float(c_bc), _stream(stream)))
+
+
+def sph_status(nbr, stream=None):
+    bits = i32(0)
+    rc = lib().sph_status(nbr.handle, _stream(stream), C.byref(bits))
+    return rc, bits.value
+
+
+def multirate_cfg(n_slow, slow_kind, dt_slow=0.0, dt_s=0.0, eta=0.0, k_max=0, fixed_inner=0,
+                  ke_tol=0.0, D=0.0, c_bc=0.0, chunk=64, use_graph=0, k_sched=None):
+    cfg = MultirateCfg(int(n_slow), int(slow_kind), float(dt_slow), float(dt_s), float(eta), int(k_max),
+                       int(fixed_inner), float(ke_tol), float(D), float(c_bc), int(chunk), int(use_graph),
+                       None)
+    if k_sched is not None:
+        ks = np.ascontiguousarray(k_sched, dtype=np.int64)
+        cfg._ks = ks
+        cfg.k_sched = ks.ctypes.data_as(vp)
+    return cfg
+
+
+def sph_advance_multirate(nbr, mat, st, cfg, stream=None):
+    """Returns (rc, k[n_slow], ke[n_slow], converged[n_slow], report)."""
+    cs = st.cstruct(nbr)
+    ns = cfg.n_slow
+    k = np.zeros(max(ns, 1), np.int64)
+    ke = np.zeros(max(ns, 1))
+    conv = np.zeros(max(ns, 1), np.int32)
+    rep = Report(k.ctypes.data_as(vp), ke.ctypes.data_as(vp), conv.ctypes.data_as(vp), 0.0, 0.0, 0, 0)
+    rc = _check(lib().sph_advance_multirate(nbr.handle, C.byref(mat), C.byref(cs), C.byref(cfg),
+                                            C.byref(rep), _stream(stream)), allow_warning=True)
+    return rc, k[:ns], ke[:ns], conv[:ns], rep

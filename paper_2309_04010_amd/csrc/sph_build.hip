@@ -1,0 +1,818 @@
+// sph_build.hip -- fixed total-Lagrangian neighbourhood on gfx950.
+//
+// Sec. 3.1 of the paper: in the TL form the neighbour set and the correction
+// matrix B0 (eq. sph-correctmatrix) are built once, in the initial
+// configuration.  Pipeline (all on the device, one host sync per size query):
+//   bounds -> cell keys -> stable LSD radix sort (8-bit digits, bit-exact)
+//   -> cell ranges -> neighbour count / scan / fill (FP64, no FMA in the
+//   distance test) -> B0 -> damping schedule (anchors by cell parity, first-fit
+//   levels inside each anchor).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "sph_common.h"
+
+namespace sph {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int64 (setup only)
+constexpr int kScanT = 256;
+constexpr int kScanItems = 8;
+constexpr int64_t kScanTile = kScanT * kScanItems;
+
+__global__ __launch_bounds__(kScanT) void k_scan_local(const int64_t* in, int64_t* out,
+                                                       int64_t* bsum, int64_t n) {
+  __shared__ int64_t wsum[kScanT / 64];
+  const int64_t base = blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t incl = s;
+  for (int off = 1; off < 64; off <<= 1) {
+    int64_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int w = 0; w < kScanT / 64; ++w) {
+      int64_t t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  int64_t ex = incl - s + wsum[wid];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (threadIdx.x == kScanT - 1) bsum[blockIdx.x] = ex;
+}
+
+__global__ void k_scan_add(int64_t* out, const int64_t* boff, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] += boff[i / kScanTile];
+}
+
+// out[i] = sum_{j<i} in[j]; *total (device, may be null) = sum of all
+static int scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* total,
+                          hipStream_t s) {
+  if (n <= 0) {
+    if (total) SPH_HIP(hipMemsetAsync(total, 0, sizeof(int64_t), s));
+    return SPH_OK;
+  }
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  int64_t* bsum = nullptr;
+  SPH_HIP(hipMalloc(&bsum, (nb + 1) * sizeof(int64_t)));
+  k_scan_local<<<(unsigned)nb, kScanT, 0, s>>>(in, out, bsum, n);
+  SPH_LAUNCH_CHECK();
+  int rc = SPH_OK;
+  if (nb > 1) {
+    rc = scan_exclusive(bsum, bsum, nb, total, s);
+    if (rc == SPH_OK) {
+      k_scan_add<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, bsum, n);
+      if (hipGetLastError() != hipSuccess) rc = SPH_E_DEVICE;
+    }
+  } else if (total) {
+    if (hipMemcpyAsync(total, bsum, sizeof(int64_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      rc = SPH_E_DEVICE;
+  }
+  hipStreamSynchronize(s);
+  hipFree(bsum);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// bounds: componentwise min and max of X (one block, fixed-order tree)
+__global__ __launch_bounds__(1024) void k_bounds(const double* X, int64_t n, int dim,
+                                                 double* out /*[2*dim]*/) {
+  __shared__ double slo[1024], shi[1024];
+  for (int k = 0; k < dim; ++k) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      double x = X[k * n + i];
+      lo = fmin(lo, x);
+      hi = fmax(hi, x);
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + w]);
+        shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      out[2 * k] = slo[0];
+      out[2 * k + 1] = shi[0];
+    }
+    __syncthreads();
+  }
+}
+
+struct Grid {
+  int dim;
+  int64_t nc0, nc1, nc2;
+  double o0, o1, o2;
+  double inv_rc;
+};
+
+__device__ __forceinline__ void key_coords(uint32_t key, const Grid& g, int64_t c[3]) {
+  int64_t k = key;
+  c[0] = k % g.nc0;
+  k /= g.nc0;
+  c[1] = k % g.nc1;
+  c[2] = k / g.nc1;
+}
+
+__global__ void k_cellkey(const double* X, int64_t n, Grid g, uint32_t* key, uint32_t* val) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t c0 = (int64_t)floor((X[i] - g.o0) * g.inv_rc);
+  int64_t c1 = g.dim > 1 ? (int64_t)floor((X[n + i] - g.o1) * g.inv_rc) : 0;
+  int64_t c2 = g.dim > 2 ? (int64_t)floor((X[2 * n + i] - g.o2) * g.inv_rc) : 0;
+  key[i] = (uint32_t)(c0 + g.nc0 * (c1 + g.nc1 * c2));
+  val[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (key, value), 8-bit digits
+constexpr int kRsT = 256;
+constexpr int kRsRounds = 4;
+constexpr int64_t kRsTile = kRsT * kRsRounds;
+
+__global__ __launch_bounds__(kRsT) void k_rs_hist(const uint32_t* keys, int64_t n, int shift,
+                                                  int64_t* hist, int64_t nblk) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int r = 0; r < kRsRounds; ++r) {
+    int64_t i = blockIdx.x * kRsTile + r * kRsT + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsT) void k_rs_scatter(const uint32_t* kin, const uint32_t* vin,
+                                                     uint32_t* kout, uint32_t* vout, int64_t n,
+                                                     int shift, const int64_t* offs,
+                                                     int64_t nblk) {
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcnt[kRsT / 64][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  running[threadIdx.x] = 0;
+  for (int r = 0; r < kRsRounds; ++r) {
+    int64_t i = blockIdx.x * kRsTile + r * kRsT + threadIdx.x;
+    bool valid = i < n;
+    uint32_t key = valid ? kin[i] : 0u;
+    uint32_t d = (key >> shift) & 255u;
+    for (int w = 0; w < kRsT / 64; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t eq = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      int bit = (d >> b) & 1u;
+      uint64_t bal = __ballot(bit);
+      eq &= bit ? bal : ~bal;
+    }
+    uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    uint32_t rank = (uint32_t)__popcll(eq & lt);
+    if (valid && rank == 0) wcnt[wid][d] = (uint32_t)__popcll(eq);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = 0;
+      for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
+      int64_t pos = offs[(int64_t)d * nblk + blockIdx.x] + running[d] + pre + rank;
+      kout[pos] = key;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kRsT / 64; ++w) add += wcnt[w][threadIdx.x];
+    running[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+static int radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* kalt, uint32_t* valt, int64_t n,
+                      uint32_t max_key, hipStream_t s) {
+  int bits = 0;
+  while (bits < 32 && (max_key >> bits) != 0u) ++bits;
+  int passes = std::max(1, (bits + 7) / 8);
+  int64_t nblk = (n + kRsTile - 1) / kRsTile;
+  int64_t* hist = nullptr;
+  SPH_HIP(hipMalloc(&hist, 256 * nblk * sizeof(int64_t)));
+  uint32_t *ki = keys, *vi = vals, *ko = kalt, *vo = valt;
+  int rc = SPH_OK;
+  for (int p = 0; p < passes && rc == SPH_OK; ++p) {
+    k_rs_hist<<<(unsigned)nblk, kRsT, 0, s>>>(ki, n, 8 * p, hist, nblk);
+    if (hipGetLastError() != hipSuccess) { rc = SPH_E_DEVICE; break; }
+    rc = scan_exclusive(hist, hist, 256 * nblk, nullptr, s);
+    if (rc) break;
+    k_rs_scatter<<<(unsigned)nblk, kRsT, 0, s>>>(ki, vi, ko, vo, n, 8 * p, hist, nblk);
+    if (hipGetLastError() != hipSuccess) { rc = SPH_E_DEVICE; break; }
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  if (rc == SPH_OK && ki != keys) {
+    if (hipMemcpyAsync(keys, ki, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(vals, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      rc = SPH_E_DEVICE;
+  }
+  hipStreamSynchronize(s);
+  hipFree(hist);
+  if (rc) set_error("radix sort failed");
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_gather_sorted(const double* X, const double* V, const uint32_t* perm,
+                                int64_t n, int dim, double* Xs, double* Vs, float* Vf) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  uint32_t id = perm[s];
+  for (int k = 0; k < dim; ++k) Xs[k * n + s] = X[k * n + id];
+  Vs[s] = V[id];
+  Vf[s] = (float)V[id];
+}
+
+// cell_start[c] = first sorted position with key >= c, c in [0, ncells]
+__global__ void k_cell_start(const uint32_t* key, int64_t n, int64_t ncells, uint32_t* cs) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c > ncells) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  cs[c] = (uint32_t)lo;
+}
+
+// neighbour test: r^2 in FP64 with no contraction, in a fixed operation order
+template <bool FILL>
+__global__ void k_nbr(const double* X, const uint32_t* key, const uint32_t* cs, int64_t n, Grid g,
+                      double rc2, int64_t* deg, const int64_t* off, uint32_t* idx,
+                      unsigned long long* maxdeg) {
+#pragma clang fp contract(off)
+  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  int64_t c[3];
+  key_coords(key[a], g, c);
+  double xa = X[a], ya = g.dim > 1 ? X[n + a] : 0.0, za = g.dim > 2 ? X[2 * n + a] : 0.0;
+  int64_t cnt = 0;
+  int64_t base = FILL ? off[a] : 0;
+  int zlo = g.dim > 2 ? -1 : 0, zhi = g.dim > 2 ? 1 : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    int64_t z = c[2] + dz;
+    if (z < 0 || z >= g.nc2) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int64_t y = c[1] + dy;
+      if (y < 0 || y >= g.nc1) continue;
+      int64_t x0 = c[0] > 0 ? c[0] - 1 : 0;
+      int64_t x1 = c[0] + 1 < g.nc0 ? c[0] + 1 : g.nc0 - 1;
+      int64_t k0 = x0 + g.nc0 * (y + g.nc1 * z);
+      int64_t k1 = x1 + g.nc0 * (y + g.nc1 * z);
+      for (int64_t b = cs[k0]; b < cs[k1 + 1]; ++b) {
+        if (b == a) continue;
+        double dx = X[b] - xa;
+        double r2 = dx * dx;
+        if (g.dim > 1) {
+          double dy_ = X[n + b] - ya;
+          r2 = r2 + dy_ * dy_;
+        }
+        if (g.dim > 2) {
+          double dz_ = X[2 * n + b] - za;
+          r2 = r2 + dz_ * dz_;
+        }
+        if (r2 < rc2) {
+          if (FILL) idx[base + cnt] = (uint32_t)b;
+          ++cnt;
+        }
+      }
+    }
+  }
+  if (!FILL) {
+    deg[a] = cnt;
+    atomicMax(maxdeg, (unsigned long long)cnt);
+  }
+}
+
+// B0_a = (sum_b V_b (X_b - X_a) (x) grad_a W_ab)^-1, eq. (sph-correctmatrix)
+__global__ void k_B0(const double* X, const double* V, const int64_t* off, const uint32_t* idx,
+                     int64_t n, int dim, double inv_h, double c5, double* B0, float* B0f,
+                     int32_t* status) {
+  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double xa[3] = {X[a], dim > 1 ? X[n + a] : 0.0, dim > 2 ? X[2 * n + a] : 0.0};
+  for (int64_t j = off[a]; j < off[a + 1]; ++j) {
+    int64_t b = idx[j];
+    double d[3] = {0, 0, 0};
+    double r2 = 0;
+    for (int k = 0; k < dim; ++k) {
+      d[k] = xa[k] - X[k * n + b];
+      r2 += d[k] * d[k];
+    }
+    double w = dw_over_r(r2, inv_h, c5);
+    for (int i = 0; i < dim; ++i)
+      for (int k = 0; k < dim; ++k) M[i * 3 + k] += V[b] * (-d[i]) * (w * d[k]);
+  }
+  double Mi[9], det, fro = 0;
+  for (int i = 0; i < dim; ++i)
+    for (int k = 0; k < dim; ++k) fro += M[i * 3 + k] * M[i * 3 + k];
+  fro = sqrt(fro);
+  if (dim == 2) {
+    det = M[0] * M[4] - M[1] * M[3];
+    Mi[0] = M[4] / det;
+    Mi[1] = -M[1] / det;
+    Mi[3] = -M[3] / det;
+    Mi[4] = M[0] / det;
+  } else {
+    double c00 = M[4] * M[8] - M[5] * M[7];
+    double c01 = M[5] * M[6] - M[3] * M[8];
+    double c02 = M[3] * M[7] - M[4] * M[6];
+    det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    Mi[0] = c00 / det;
+    Mi[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+    Mi[2] = (M[1] * M[5] - M[2] * M[4]) / det;
+    Mi[3] = c01 / det;
+    Mi[4] = (M[0] * M[8] - M[2] * M[6]) / det;
+    Mi[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+    Mi[6] = c02 / det;
+    Mi[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+    Mi[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+  }
+  double lim = 1e-12 * (dim == 2 ? fro * fro : fro * fro * fro);
+  if (!(fabs(det) >= lim) || !isfinite(det)) atomicOr(status, SPH_STATUS_SINGULAR_B0);
+  for (int i = 0; i < dim; ++i)
+    for (int k = 0; k < dim; ++k) {
+      B0[(i * dim + k) * n + a] = Mi[i * 3 + k];
+      B0f[(i * dim + k) * n + a] = (float)Mi[i * 3 + k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// damping schedule
+struct Block {
+  int nr;
+  int64_t beg[4], end[4];
+};
+
+__device__ __forceinline__ Block anchor_block(uint32_t akey, const Grid& g, const uint32_t* cs) {
+  int64_t A[3];
+  key_coords(akey, g, A);
+  Block blk;
+  blk.nr = 0;
+  int zmax = g.dim > 2 ? 1 : 0;
+  for (int dz = 0; dz <= zmax; ++dz) {
+    int64_t z = A[2] + dz;
+    if (z >= g.nc2) continue;
+    for (int dy = 0; dy <= 1; ++dy) {
+      int64_t y = A[1] + dy;
+      if (y >= g.nc1) continue;
+      int64_t k0 = A[0] + g.nc0 * (y + g.nc1 * z);
+      int64_t k1 = k0 + (A[0] + 1 < g.nc0 ? 2 : 1);
+      blk.beg[blk.nr] = cs[k0];
+      blk.end[blk.nr] = cs[k1];
+      ++blk.nr;
+    }
+  }
+  return blk;
+}
+
+__device__ __forceinline__ bool anchored_at(uint32_t ks, uint32_t kt, const int64_t A[3],
+                                            const Grid& g) {
+  int64_t cs_[3], ct[3];
+  key_coords(ks, g, cs_);
+  key_coords(kt, g, ct);
+  for (int k = 0; k < 3; ++k)
+    if ((cs_[k] < ct[k] ? cs_[k] : ct[k]) != A[k]) return false;
+  return true;
+}
+
+// per cell: number of pairs anchored there, and the block's particle count
+__global__ void k_sched_count(const uint32_t* key, const uint32_t* cs, const int64_t* off,
+                              const uint32_t* idx, Grid g, int64_t ncells, int64_t* cnt,
+                              unsigned long long* bmax) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int64_t A[3];
+  key_coords((uint32_t)c, g, A);
+  Block blk = anchor_block((uint32_t)c, g, cs);
+  int64_t m = 0, bc = 0;
+  for (int r = 0; r < blk.nr; ++r) {
+    bc += blk.end[r] - blk.beg[r];
+    for (int64_t s = blk.beg[r]; s < blk.end[r]; ++s)
+      for (int64_t j = off[s]; j < off[s + 1]; ++j) {
+        uint32_t t = idx[j];
+        if ((int64_t)t <= s) continue;
+        if (anchored_at(key[s], key[t], A, g)) ++m;
+      }
+  }
+  cnt[c] = m;
+  atomicMax(bmax, (unsigned long long)bc);
+}
+
+__global__ void k_color_flags(const int64_t* cnt, Grid g, int64_t ncells, int color,
+                              int64_t* flag) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int64_t A[3];
+  key_coords((uint32_t)c, g, A);
+  int col = (int)((A[0] & 1) | ((A[1] & 1) << 1) | ((A[2] & 1) << 2));
+  flag[c] = (cnt[c] > 0 && col == color) ? 1 : 0;
+}
+
+__global__ void k_color_emit(const int64_t* cnt, const int64_t* flag, const int64_t* pos,
+                             int64_t ncells, int64_t base, uint32_t* akey, int64_t* acnt) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncells || !flag[c]) return;
+  akey[base + pos[c]] = (uint32_t)c;
+  acnt[base + pos[c]] = cnt[c];
+}
+
+// one thread per anchor: enumerate its pairs in ascending (a, b), assign
+// first-fit levels, write them level-major
+__global__ void k_sched_fill(const uint32_t* key, const uint32_t* cs, const int64_t* off,
+                             const uint32_t* idx, Grid g, const uint32_t* akey,
+                             const int64_t* aoff, int64_t a0, int64_t a1, int words, int64_t bmax,
+                             unsigned long long* scratch, uint32_t* ta, uint32_t* tb, uint32_t* tl,
+                             uint32_t* pa, uint32_t* pb, uint32_t* pl, uint32_t* anlev,
+                             unsigned long long* maxlev, int32_t* err) {
+  int64_t ai = a0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (ai >= a1) return;
+  unsigned long long* used = scratch + (ai - a0) * bmax * words;
+  for (int64_t i = 0; i < bmax * words; ++i) used[i] = 0ull;
+  uint32_t ak = akey[ai];
+  int64_t A[3];
+  key_coords(ak, g, A);
+  Block blk = anchor_block(ak, g, cs);
+  int64_t lbase[4];
+  int64_t acc = 0;
+  for (int r = 0; r < blk.nr; ++r) {
+    lbase[r] = acc;
+    acc += blk.end[r] - blk.beg[r];
+  }
+  int64_t o = aoff[ai];
+  int64_t m = 0;
+  uint32_t nl = 0;
+  const int maxbits = words * 64;
+  for (int r = 0; r < blk.nr; ++r)
+    for (int64_t s = blk.beg[r]; s < blk.end[r]; ++s)
+      for (int64_t j = off[s]; j < off[s + 1]; ++j) {
+        uint32_t t = idx[j];
+        if ((int64_t)t <= s) continue;
+        if (!anchored_at(key[s], key[t], A, g)) continue;
+        int64_t ls = lbase[r] + (s - blk.beg[r]);
+        int64_t lt = -1;
+        for (int q = 0; q < blk.nr; ++q)
+          if ((int64_t)t >= blk.beg[q] && (int64_t)t < blk.end[q]) lt = lbase[q] + ((int64_t)t - blk.beg[q]);
+        if (lt < 0) {
+          atomicOr(err, 1);
+          return;
+        }
+        unsigned long long* Ua = used + ls * words;
+        unsigned long long* Ub = used + lt * words;
+        int lev = 0;
+        while (lev < maxbits && (((Ua[lev >> 6] | Ub[lev >> 6]) >> (lev & 63)) & 1ull)) ++lev;
+        if (lev >= maxbits) {
+          atomicOr(err, 2);
+          return;
+        }
+        Ua[lev >> 6] |= 1ull << (lev & 63);
+        Ub[lev >> 6] |= 1ull << (lev & 63);
+        ta[o + m] = (uint32_t)s;
+        tb[o + m] = t;
+        tl[o + m] = (uint32_t)lev;
+        if ((uint32_t)lev + 1 > nl) nl = (uint32_t)lev + 1;
+        ++m;
+      }
+  int64_t w = o;
+  for (uint32_t lev = 0; lev < nl; ++lev)
+    for (int64_t i = o; i < o + m; ++i)
+      if (tl[i] == lev) {
+        pa[w] = ta[i];
+        pb[w] = tb[i];
+        pl[w] = lev;
+        ++w;
+      }
+  anlev[ai] = nl;
+  atomicMax(maxlev, (unsigned long long)nl);
+}
+
+// ---------------------------------------------------------------------------
+static void free_nbr(sph_nbr* h) {
+  if (!h) return;
+  void* ptrs[] = {h->key, h->perm, h->cell_start, h->nbr_off, h->nbr_idx, h->X,   h->V,
+                  h->B0,  h->Vf,   h->B0f,        h->sa,      h->sb,      h->slev, h->akey,
+                  h->aoff, h->anlev, h->ctrl,     h->ke_partial};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  if (h->ctrl_host) hipHostFree(h->ctrl_host);
+  delete h;
+}
+
+template <typename T>
+static int dalloc(T** p, int64_t count) {
+  *p = nullptr;
+  SPH_HIP(hipMalloc((void**)p, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+  return SPH_OK;
+}
+
+static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+static int build(int dim, int64_t n, const double* X, const double* V, double h, hipStream_t s,
+                 sph_nbr* nb) {
+  nb->dim = dim;
+  nb->n = n;
+  nb->h = h;
+  const double rc = 2.0 * h;
+  const double rc2 = rc * rc;
+  nb->inv_rc = 1.0 / rc;
+  const double pi = 3.14159265358979323846;
+  double alpha = dim == 2 ? 7.0 / (4.0 * pi * h * h) : 21.0 / (16.0 * pi * h * h * h);
+  nb->c5 = -5.0 * alpha / (h * h);
+  nb->inv_h = 1.0 / h;
+  SPH_HIP(hipGetDevice(&nb->device));
+
+  // bounds
+  double* dbounds = nullptr;
+  SPH_HIP(hipMalloc(&dbounds, 6 * sizeof(double)));
+  k_bounds<<<1, 1024, 0, s>>>(X, n, dim, dbounds);
+  SPH_LAUNCH_CHECK();
+  double hb[6] = {0, 0, 0, 0, 0, 0};
+  SPH_HIP(hipMemcpyAsync(hb, dbounds, 2 * dim * sizeof(double), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  hipFree(dbounds);
+  for (int k = 0; k < dim; ++k) {
+    if (!std::isfinite(hb[2 * k]) || !std::isfinite(hb[2 * k + 1])) {
+      set_error("non-finite reference positions");
+      return SPH_E_ARG;
+    }
+    nb->origin[k] = hb[2 * k];
+    nb->nc[k] = (int64_t)floor((hb[2 * k + 1] - hb[2 * k]) * nb->inv_rc) + 1;
+  }
+  nb->n_cells = nb->nc[0] * nb->nc[1] * nb->nc[2];
+  if (nb->n_cells > 0xFFFFFFF0LL || n > 0xFFFFFFF0LL) {
+    set_error("too many cells (%lld) or particles", (long long)nb->n_cells);
+    return SPH_E_CAPACITY;
+  }
+  Grid g{dim, nb->nc[0], nb->nc[1], nb->nc[2], nb->origin[0], nb->origin[1], nb->origin[2],
+         nb->inv_rc};
+
+  // keys and stable sort
+  uint32_t *kalt = nullptr, *valt = nullptr;
+  int rc_ = SPH_OK;
+  if ((rc_ = dalloc(&nb->key, n)) || (rc_ = dalloc(&nb->perm, n)) || (rc_ = dalloc(&kalt, n)) ||
+      (rc_ = dalloc(&valt, n)))
+    return rc_;
+  k_cellkey<<<nblocks(n, 256), 256, 0, s>>>(X, n, g, nb->key, nb->perm);
+  SPH_LAUNCH_CHECK();
+  rc_ = radix_sort(nb->key, nb->perm, kalt, valt, n, (uint32_t)(nb->n_cells - 1), s);
+  hipFree(kalt);
+  hipFree(valt);
+  if (rc_) return rc_;
+
+  if ((rc_ = dalloc(&nb->X, dim * n)) || (rc_ = dalloc(&nb->V, n)) || (rc_ = dalloc(&nb->Vf, n)) ||
+      (rc_ = dalloc(&nb->cell_start, nb->n_cells + 1)))
+    return rc_;
+  k_gather_sorted<<<nblocks(n, 256), 256, 0, s>>>(X, V, nb->perm, n, dim, nb->X, nb->V, nb->Vf);
+  SPH_LAUNCH_CHECK();
+  k_cell_start<<<nblocks(nb->n_cells + 1, 256), 256, 0, s>>>(nb->key, n, nb->n_cells,
+                                                              nb->cell_start);
+  SPH_LAUNCH_CHECK();
+
+  // neighbours
+  int64_t* deg = nullptr;
+  unsigned long long* dmax = nullptr;
+  if ((rc_ = dalloc(&deg, n + 1)) || (rc_ = dalloc(&nb->nbr_off, n + 1)) || (rc_ = dalloc(&dmax, 4)))
+    return rc_;
+  SPH_HIP(hipMemsetAsync(dmax, 0, 4 * sizeof(unsigned long long), s));
+  k_nbr<false><<<nblocks(n, 128), 128, 0, s>>>(nb->X, nb->key, nb->cell_start, n, g, rc2, deg,
+                                               nullptr, nullptr, dmax);
+  SPH_LAUNCH_CHECK();
+  rc_ = scan_exclusive(deg, nb->nbr_off, n, nb->nbr_off + n, s);
+  hipFree(deg);
+  if (rc_) return rc_;
+  int64_t P = 0;
+  unsigned long long maxdeg = 0;
+  SPH_HIP(hipMemcpyAsync(&P, nb->nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipMemcpyAsync(&maxdeg, dmax, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  nb->n_pairs = P;
+  nb->n_upairs = P / 2;
+  nb->max_deg = (int64_t)maxdeg;
+  if ((rc_ = dalloc(&nb->nbr_idx, P))) return rc_;
+  k_nbr<true><<<nblocks(n, 128), 128, 0, s>>>(nb->X, nb->key, nb->cell_start, n, g, rc2, nullptr,
+                                              nb->nbr_off, nb->nbr_idx, nullptr);
+  SPH_LAUNCH_CHECK();
+
+  // correction matrices
+  int32_t* dstat = nullptr;
+  if ((rc_ = dalloc(&nb->B0, dim * dim * n)) || (rc_ = dalloc(&nb->B0f, dim * dim * n)) ||
+      (rc_ = dalloc(&dstat, 2)))
+    return rc_;
+  SPH_HIP(hipMemsetAsync(dstat, 0, 2 * sizeof(int32_t), s));
+  k_B0<<<nblocks(n, 128), 128, 0, s>>>(nb->X, nb->V, nb->nbr_off, nb->nbr_idx, n, dim, nb->inv_h,
+                                       nb->c5, nb->B0, nb->B0f, dstat);
+  SPH_LAUNCH_CHECK();
+  int32_t hstat = 0;
+  SPH_HIP(hipMemcpyAsync(&hstat, dstat, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  if (hstat) {
+    hipFree(dstat);
+    hipFree(dmax);
+    set_error("singular correction matrix (particle without a full-rank neighbourhood)");
+    return SPH_E_NUMERIC;
+  }
+
+  // damping schedule
+  const int64_t nc = nb->n_cells;
+  int64_t *cnt = nullptr, *flag = nullptr, *pos = nullptr, *acnt = nullptr;
+  if ((rc_ = dalloc(&cnt, nc)) || (rc_ = dalloc(&flag, nc)) || (rc_ = dalloc(&pos, nc + 1)) ||
+      (rc_ = dalloc(&nb->akey, nc)) || (rc_ = dalloc(&acnt, nc + 1)))
+    return rc_;
+  SPH_HIP(hipMemsetAsync(dmax, 0, 4 * sizeof(unsigned long long), s));
+  k_sched_count<<<nblocks(nc, 128), 128, 0, s>>>(nb->key, nb->cell_start, nb->nbr_off,
+                                                 nb->nbr_idx, g, nc, cnt, dmax);
+  SPH_LAUNCH_CHECK();
+  int64_t ncol = 1LL << dim;
+  int64_t base = 0;
+  for (int col = 0; col < ncol; ++col) {
+    nb->color_off[col] = base;
+    k_color_flags<<<nblocks(nc, 256), 256, 0, s>>>(cnt, g, nc, col, flag);
+    SPH_LAUNCH_CHECK();
+    if ((rc_ = scan_exclusive(flag, pos, nc, pos + nc, s))) return rc_;
+    k_color_emit<<<nblocks(nc, 256), 256, 0, s>>>(cnt, flag, pos, nc, base, nb->akey, acnt);
+    SPH_LAUNCH_CHECK();
+    int64_t tot = 0;
+    SPH_HIP(hipMemcpyAsync(&tot, pos + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    base += tot;
+  }
+  for (int col = (int)ncol; col < 9; ++col) nb->color_off[col] = base;
+  nb->n_anchors = base;
+  unsigned long long hbmax = 0;
+  SPH_HIP(hipMemcpyAsync(&hbmax, dmax, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  if ((rc_ = dalloc(&nb->aoff, base + 1))) return rc_;
+  if ((rc_ = scan_exclusive(acnt, nb->aoff, base, nb->aoff + base, s))) return rc_;
+  int64_t npu = 0;
+  SPH_HIP(hipMemcpyAsync(&npu, nb->aoff + base, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  hipFree(cnt);
+  hipFree(flag);
+  hipFree(pos);
+  hipFree(acnt);
+  if (npu != nb->n_upairs) {
+    set_error("schedule pair count %lld != %lld", (long long)npu, (long long)nb->n_upairs);
+    return SPH_E_DEVICE;
+  }
+  uint32_t *ta = nullptr, *tb = nullptr, *tl = nullptr;
+  if ((rc_ = dalloc(&nb->sa, npu)) || (rc_ = dalloc(&nb->sb, npu)) || (rc_ = dalloc(&nb->slev, npu)) ||
+      (rc_ = dalloc(&nb->anlev, base)) || (rc_ = dalloc(&ta, npu)) || (rc_ = dalloc(&tb, npu)) ||
+      (rc_ = dalloc(&tl, npu)))
+    return rc_;
+  const int words = (int)((2 * nb->max_deg) / 64 + 1);
+  const int64_t bmax = std::max<int64_t>((int64_t)hbmax, 1);
+  const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(16384, (int64_t)(512ll << 20) /
+                                                                          (bmax * words * 8)));
+  unsigned long long* scratch = nullptr;
+  if ((rc_ = dalloc(&scratch, batch * bmax * words))) return rc_;
+  SPH_HIP(hipMemsetAsync(dmax, 0, 4 * sizeof(unsigned long long), s));
+  for (int64_t a0 = 0; a0 < base; a0 += batch) {
+    int64_t a1 = std::min(base, a0 + batch);
+    k_sched_fill<<<nblocks(a1 - a0, 64), 64, 0, s>>>(
+        nb->key, nb->cell_start, nb->nbr_off, nb->nbr_idx, g, nb->akey, nb->aoff, a0, a1, words,
+        bmax, scratch, ta, tb, tl, nb->sa, nb->sb, nb->slev, nb->anlev, dmax, dstat + 1);
+    SPH_LAUNCH_CHECK();
+  }
+  unsigned long long hmaxlev = 0;
+  int32_t herr = 0;
+  SPH_HIP(hipMemcpyAsync(&hmaxlev, dmax, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipMemcpyAsync(&herr, dstat + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  hipFree(scratch);
+  hipFree(ta);
+  hipFree(tb);
+  hipFree(tl);
+  hipFree(dmax);
+  hipFree(dstat);
+  if (herr) {
+    set_error("schedule builder failed (code %d)", herr);
+    return SPH_E_CAPACITY;
+  }
+  nb->max_level = (int64_t)hmaxlev;
+
+  // inner-loop control block
+  SPH_HIP(hipMalloc(&nb->ctrl, sizeof(Ctrl)));
+  SPH_HIP(hipMemsetAsync(nb->ctrl, 0, sizeof(Ctrl), s));
+  SPH_HIP(hipHostMalloc((void**)&nb->ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
+  SPH_HIP(hipMalloc(&nb->ke_partial, kKeMaxBlocks * sizeof(double)));
+  SPH_HIP(hipStreamSynchronize(s));
+  return SPH_OK;
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" int sph_build_neighbors(int dim, int64_t n, const double* X, const double* V, double h,
+                                   void* stream, sph_nbr** out) {
+  clear_error();
+  if (!out) {
+    set_error("out is NULL");
+    return SPH_E_ARG;
+  }
+  *out = nullptr;
+  if (dim != 2 && dim != 3) {
+    set_error("dim must be 2 or 3");
+    return SPH_E_UNSUPPORTED;
+  }
+  if (n < 1 || !X || !V || !(h > 0.0) || !std::isfinite(h)) {
+    set_error("bad arguments (n=%lld, h=%g)", (long long)n, h);
+    return SPH_E_ARG;
+  }
+  sph_nbr* nb = new sph_nbr();
+  int rc = build(dim, n, X, V, h, (hipStream_t)stream, nb);
+  if (rc != SPH_OK) {
+    hipStreamSynchronize((hipStream_t)stream);
+    free_nbr(nb);
+    return rc;
+  }
+  *out = nb;
+  return SPH_OK;
+}
+
+extern "C" int sph_nbr_destroy(sph_nbr* nb) {
+  if (!nb) return SPH_OK;
+  hipDeviceSynchronize();
+  free_nbr(nb);
+  return SPH_OK;
+}
+
+extern "C" int sph_nbr_query(const sph_nbr* nb, sph_nbr_info* info) {
+  if (!nb || !info) {
+    set_error("null argument");
+    return SPH_E_ARG;
+  }
+  std::memset(info, 0, sizeof(*info));
+  info->dim = nb->dim;
+  info->n_colors = 1 << nb->dim;
+  info->n = nb->n;
+  info->n_pairs = nb->n_pairs;
+  info->n_upairs = nb->n_upairs;
+  info->n_cells = nb->n_cells;
+  for (int k = 0; k < 3; ++k) {
+    info->ncell[k] = nb->nc[k];
+    info->origin[k] = nb->origin[k];
+  }
+  info->n_anchors = nb->n_anchors;
+  info->max_deg = nb->max_deg;
+  info->max_level = nb->max_level;
+  for (int k = 0; k < 9; ++k) info->color_off[k] = nb->color_off[k];
+  info->h = nb->h;
+  info->inv_rc = nb->inv_rc;
+  info->key = nb->key;
+  info->perm = nb->perm;
+  info->cell_start = nb->cell_start;
+  info->nbr_off = nb->nbr_off;
+  info->nbr_idx = nb->nbr_idx;
+  info->X = nb->X;
+  info->V = nb->V;
+  info->B0 = nb->B0;
+  info->sched_a = nb->sa;
+  info->sched_b = nb->sb;
+  info->sched_level = nb->slev;
+  info->anchor_key = nb->akey;
+  info->anchor_off = nb->aoff;
+  info->anchor_nlev = nb->anlev;
+  return SPH_OK;
+}
+
+extern "C" const char* sph_last_error(void) { return sph::g_err.c_str(); }

@@ -1,0 +1,244 @@
+// sph_driver.hip -- C ABI of the stepping functions and the multi-time-step
+// driver (Sec. 4.2 of the paper): outer loop over slow steps (loading or
+// diffusion), inner loop of damped solid relaxation steps until the kinetic
+// energy falls to the threshold.  The stop test runs on the device (the
+// drift/E_k kernel sets a flag that every later inner kernel checks), so the
+// host only polls once per chunk of inner steps; a chunk can be replayed as a
+// captured hipGraph to remove per-kernel launch cost on small problems.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "sph_common.h"
+
+using namespace sph;
+
+namespace {
+
+int inner_steps(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
+                double eta, int count, hipStream_t s) {
+  for (int i = 0; i < count; ++i) {
+    int rc = solid_stage(nb, m, st, dt, s, true);
+    if (rc) return rc;
+    rc = damping_sweep(nb, m, st, eta, dt, s, true);
+    if (rc) return rc;
+    rc = drift_ke(nb, m, st, dt, nullptr, s, true);
+    if (rc) return rc;
+  }
+  return SPH_OK;
+}
+
+struct GraphChunk {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GraphChunk() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  }
+};
+
+}  // namespace
+
+extern "C" int sph_solid_relax_step(const sph_nbr* nb, const sph_material* mat,
+                                    const sph_state* st, double dt_s, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!mat) {
+    set_error("material is NULL");
+    return SPH_E_ARG;
+  }
+  return solid_stage(nb, mat, st, dt_s, (hipStream_t)stream, false);
+}
+
+extern "C" int sph_damping_sweep(const sph_nbr* nb, const sph_material* mat, const sph_state* st,
+                                 double eta, double dt_s, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!mat) {
+    set_error("material is NULL");
+    return SPH_E_ARG;
+  }
+  return damping_sweep(nb, mat, st, eta, dt_s, (hipStream_t)stream, false);
+}
+
+extern "C" int sph_drift_ke(const sph_nbr* nb, const sph_material* mat, const sph_state* st,
+                            double dt_s, double* ke_out, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!mat) {
+    set_error("material is NULL");
+    return SPH_E_ARG;
+  }
+  return drift_ke(nb, mat, st, dt_s, ke_out, (hipStream_t)stream, false);
+}
+
+extern "C" int sph_load_step(const sph_nbr* nb, const sph_state* st, double dt_l, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, false);
+  if (rc) return rc;
+  return load_step(nb, st, dt_l, (hipStream_t)stream);
+}
+
+extern "C" int sph_diffusion_step(const sph_nbr* nb, const sph_material* mat, const sph_state* st,
+                                  double D, double dt_d, double c_bc, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, false);
+  if (rc) return rc;
+  if (!mat) {
+    set_error("material is NULL");
+    return SPH_E_ARG;
+  }
+  return diffusion_step(nb, mat, st, D, dt_d, c_bc, (hipStream_t)stream);
+}
+
+extern "C" int sph_status(const sph_nbr* nb, void* stream, int32_t* bits) {
+  clear_error();
+  if (!nb) {
+    set_error("null handle");
+    return SPH_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  SPH_HIP(hipMemcpyAsync(nb->ctrl_host, nb->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  int32_t st = nb->ctrl_host->status;
+  if (bits) *bits = st;
+  if (st) {
+    int32_t zero = 0;
+    SPH_HIP(hipMemcpy((char*)nb->ctrl + offsetof(Ctrl, status), &zero, sizeof(int32_t),
+                      hipMemcpyHostToDevice));
+    set_error("device status bits 0x%x", st);
+    return SPH_E_NUMERIC;
+  }
+  return SPH_OK;
+}
+
+extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
+                                     const sph_state* st, const sph_multirate_cfg* cfg,
+                                     sph_report* rep, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!m || !cfg) {
+    set_error("material or cfg is NULL");
+    return SPH_E_ARG;
+  }
+  if (cfg->n_slow < 0 || (cfg->slow_kind != SPH_SLOW_LOAD && cfg->slow_kind != SPH_SLOW_DIFFUSION)) {
+    set_error("bad n_slow or slow_kind");
+    return SPH_E_ARG;
+  }
+  const double K = m->E / (3.0 * (1.0 - 2.0 * m->nu));
+  const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * nb->h / std::sqrt(K / m->rho0);
+  double dt_slow = cfg->dt_slow;
+  if (cfg->slow_kind == SPH_SLOW_DIFFUSION && !(dt_slow > 0.0)) {
+    if (!(cfg->D > 0.0)) {
+      set_error("diffusion needs D > 0");
+      return SPH_E_ARG;
+    }
+    dt_slow = 0.5 * nb->h * nb->h / cfg->D;
+  }
+  const int64_t k_max = cfg->k_max > 0 ? cfg->k_max : (int64_t)std::floor(dt_slow / dt_s) + 1;
+  const bool adaptive = cfg->k_sched == nullptr && cfg->fixed_inner <= 0;
+  const int chunk = cfg->chunk > 0 ? cfg->chunk : 64;
+  if (rep) {
+    rep->dt_s = dt_s;
+    rep->dt_slow = dt_slow;
+    rep->k_max = k_max;
+    rep->total_inner = 0;
+  }
+  hipStream_t user = (hipStream_t)stream;
+  hipStream_t s = user;
+  hipStream_t own = nullptr;
+  hipEvent_t ev = nullptr;
+  GraphChunk gc;
+  const bool graph = cfg->use_graph != 0;
+  if (graph) {
+    // capture needs a non-null stream: run on a private one ordered after `user`
+    SPH_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    SPH_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    SPH_HIP(hipEventRecord(ev, user));
+    SPH_HIP(hipStreamWaitEvent(own, ev, 0));
+    s = own;
+    SPH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rc = inner_steps(nb, m, st, dt_s, cfg->eta, chunk, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    gc.graph = g;
+    if (rc == SPH_OK && e != hipSuccess) {
+      set_error("graph capture failed: %s", hipGetErrorString(e));
+      rc = SPH_E_DEVICE;
+    }
+    if (rc == SPH_OK && hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0) != hipSuccess) {
+      set_error("graph instantiation failed");
+      rc = SPH_E_DEVICE;
+    }
+  }
+  int warn = 0;
+  for (int32_t l = 0; l < cfg->n_slow && rc == SPH_OK; ++l) {
+    if (cfg->slow_kind == SPH_SLOW_LOAD)
+      rc = load_step(nb, st, dt_slow, s);
+    else
+      rc = diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
+    if (rc) break;
+    const int64_t nk = cfg->k_sched ? cfg->k_sched[l] : (cfg->fixed_inner > 0 ? cfg->fixed_inner : k_max);
+    Ctrl* hc = nb->ctrl_host;
+    if (nk <= 0) {
+      if (rep && rep->k) rep->k[l] = 0;
+      if (rep && rep->ke) rep->ke[l] = 0.0;
+      if (rep && rep->converged) rep->converged[l] = 1;
+      continue;
+    }
+    rc = reset_ctrl(nb, nk, adaptive ? cfg->ke_tol : -1.0, s);
+    if (rc) break;
+    int64_t launched = 0;
+    for (;;) {
+      int64_t mcount = graph ? chunk : std::min<int64_t>(chunk, nk - launched);
+      if (graph) {
+        if (hipGraphLaunch(gc.exec, s) != hipSuccess) {
+          set_error("graph launch failed");
+          rc = SPH_E_DEVICE;
+          break;
+        }
+      } else {
+        rc = inner_steps(nb, m, st, dt_s, cfg->eta, (int)mcount, s);
+        if (rc) break;
+      }
+      launched += mcount;
+      if (hipMemcpyAsync(hc, nb->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        set_error("polling the inner-loop state failed");
+        rc = SPH_E_DEVICE;
+        break;
+      }
+      if (hc->done || launched >= nk) break;
+    }
+    if (rc) break;
+    if (rep && rep->k) rep->k[l] = hc->k;
+    if (rep && rep->ke) rep->ke[l] = hc->ke;
+    const int conv = hc->ke <= cfg->ke_tol;
+    if (rep && rep->converged) rep->converged[l] = conv;
+    if (rep) rep->total_inner += hc->k;
+    if (adaptive && !hc->stopped_by_ke) warn = 1;
+    if (hc->status) {
+      set_error("device status bits 0x%x at slow step %d", hc->status, l);
+      rc = SPH_E_NUMERIC;
+      break;
+    }
+  }
+  if (graph) {
+    hipEvent_t ev2 = nullptr;
+    if (hipEventCreateWithFlags(&ev2, hipEventDisableTiming) == hipSuccess) {
+      hipEventRecord(ev2, s);
+      hipStreamWaitEvent(user, ev2, 0);
+      hipStreamSynchronize(s);
+      hipEventDestroy(ev2);
+    }
+    hipEventDestroy(ev);
+    hipStreamDestroy(own);
+  }
+  if (rc) return rc;
+  return warn ? SPH_W_NOT_CONVERGED : SPH_OK;
+}
