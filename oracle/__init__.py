@@ -61,7 +61,7 @@ def _lib(cplx: bool):
     lib.orc_get_schedule.argtypes = [vp] * 8
     lib.orc_constitutive.restype = i32
     lib.orc_constitutive.argtypes = [vp, vp, vp, _real_t(cplx), vp]
-    lib.orc_deformation_gradient.argtypes = [vp, vp, vp]
+    lib.orc_displacement_gradient.argtypes = [vp, vp, vp]
     lib.orc_stress.restype = i32
     lib.orc_stress.argtypes = [vp] * 7
     lib.orc_momentum.argtypes = [vp] * 4
@@ -212,23 +212,35 @@ class Oracle:
         return self.lib.orc_kernel_dW_over_r(self.dim, self.h, float(r))
 
     # -- steps ----------------------------------------------------------
-    def constitutive(self, mat, F, plastic7=None, p=0.0):
-        F = np.ascontiguousarray(F, dtype=self.dtype).reshape(9)
-        pl = (np.array([1, 1, 1, 0, 0, 0, 0], self.dtype) if plastic7 is None
+    def constitutive(self, mat, F=None, plastic7=None, p=0.0, H=None):
+        """Stress of one particle from F (or from H = F - I).  plastic7 holds
+        Cbar_p^-1 - I (xx yy zz xy yz xz) and alpha; zeros = virgin state."""
+        if H is None:
+            H = np.asarray(F, dtype=self.dtype).reshape(3, 3) - np.eye(3)
+        H = np.ascontiguousarray(H, dtype=self.dtype).reshape(9)
+        pl = (np.zeros(7, self.dtype) if plastic7 is None
               else np.ascontiguousarray(plastic7, dtype=self.dtype).copy())
         P = np.zeros(9, self.dtype)
-        rc = self.lib.orc_constitutive(C.byref(mat), _ptr(F), _ptr(pl), _to_real(p, self.cplx), _ptr(P))
+        rc = self.lib.orc_constitutive(C.byref(mat), _ptr(H), _ptr(pl), _to_real(p, self.cplx), _ptr(P))
         return rc, P.reshape(3, 3), pl
 
+    def displacement_gradient(self, u):
+        H9 = self.arr(9, self.n)
+        self.lib.orc_displacement_gradient(self._h, _ptr(self._a(u)), _ptr(H9))
+        return H9
+
     def deformation_gradient(self, u):
-        F9 = self.arr(9, self.n)
-        self.lib.orc_deformation_gradient(self._h, _ptr(self._a(u)), _ptr(F9))
+        F9 = self.displacement_gradient(u)
+        F9[0] += 1.0
+        F9[4] += 1.0
+        F9[8] += 1.0
         return F9
 
-    def stress(self, mat, F9, plastic=None, p=None):
+    def stress(self, mat, H9, plastic=None, p=None):
+        """Stress from H9 = F - I ([9, n]); returns (rc, P9, PB)."""
         P9 = self.arr(9, self.n)
         PB = self.arr(self.dim * self.dim, self.n)
-        rc = self.lib.orc_stress(self._h, C.byref(mat), _ptr(self._a(F9)), _ptr(self._a(plastic)),
+        rc = self.lib.orc_stress(self._h, C.byref(mat), _ptr(self._a(H9)), _ptr(self._a(plastic)),
                                  _ptr(self._a(p)), _ptr(P9), _ptr(PB))
         return rc, P9, PB
 

@@ -520,67 +520,108 @@ static real hardening_slope(const orc_material* m, real a) {
   return (m->sigma_inf - m->sigma0) * m->delta * r_exp(-m->delta * a) + m->H;
 }
 
-/* Constitutive update for one particle.  F is the 3x3 deformation gradient
- * (plane strain in 2D: F33 = 1, no out-of-plane shear).  Moduli from eq.
+/* Constitutive update for one particle, from the displacement gradient
+ * H = F - I (eq. deformationtensor-displacement: F = grad u + I).  Strain
+ * measures are formed from H by exact identities, so that small strains keep
+ * their relative precision:
+ *   det(I + H) - 1 = tr H + ((tr H)^2 - tr(H^2))/2 + det H,
+ *   F F^T - I = H + H^T + H H^T.
+ * Plane strain in 2D: H has no third row or column.  Moduli from eq.
  * (relation-modulus): mu = E/(2(1+nu)), K = E/(3(1-2nu)).
- *   LE  small-strain reading: eps = sym(F) - I, P = lambda tr(eps) I + 2 mu eps,
+ *   LE  small-strain reading: eps = sym H, P = lambda tr(eps) I + 2 mu eps,
  *       lambda = K - 2mu/3 (App. B.2).
  *   NH  eq. (kirchoff_stress_equation) with the elastic part F:
  *       tau = K/2 (J^2 - 1) I + mu dev(bbar),  bbar = J^(-2/3) F F^T,
  *       P = tau F^-T (eq. stress_trans).
- *   J2  Algorithm 1: the stored internal variable is Cbar_p^-1 (it starts as
- *       I and the last line of the algorithm produces exactly this inverse),
- *       committed at every call.  Delta-gamma from Newton iterations from 0.
+ *   J2  Algorithm 1.  The internal variable of the algorithm is Cbar_p^-1
+ *       (it starts as I and the algorithm's last line produces exactly this
+ *       inverse); it is stored as Y = Cbar_p^-1 - I (xx yy zz xy yz xz) with
+ *       alpha, and committed at every call.  Delta-gamma from Newton
+ *       iterations started at 0.
  * Effective stress with fluid pressure (App. B.2): sigma = sigma_s - p I, so
  * P = P_s - J p F^-T.                                                        */
-int orc_constitutive(const orc_material* m, const real* F, real* pl, real p, real* P) {
+static void sym_sum(const real* A, real* S) { /* S = A + A^T + A A^T */
+  real AAt[9];
+  mul3_bt(A, A, AAt);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) S[i * 3 + j] = A[i * 3 + j] + A[j * 3 + i] + AAt[i * 3 + j];
+}
+
+static real det_minus_one(const real* H) {
+  real tr = trace3(H);
+  real H2[9];
+  mul3(H, H, H2);
+  return tr + 0.5 * (tr * tr - trace3(H2)) + det3(H);
+}
+
+#ifdef ORC_COMPLEX
+static real r_log1p(real x) { return clog(1.0 + x); }
+static real r_expm1(real x) { return cexp(x) - 1.0; }
+#else
+static real r_log1p(real x) { return log1p(x); }
+static real r_expm1(real x) { return expm1(x); }
+#endif
+
+int orc_constitutive(const orc_material* m, const real* H, real* pl, real p, real* P) {
   real mu = m->E / (2.0 * (1.0 + m->nu));
   real K = m->E / (3.0 * (1.0 - 2.0 * m->nu));
-  real J = det3(F);
-  real Fi[9], FiT[9];
+  real jm1 = det_minus_one(H);
+  real J = 1.0 + jm1;
+  real F[9], Fi[9], FiT[9];
+  for (int i = 0; i < 9; ++i) F[i] = H[i];
+  F[0] += 1.0;
+  F[4] += 1.0;
+  F[8] += 1.0;
   inv3(F, Fi);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) FiT[i * 3 + j] = Fi[j * 3 + i];
+  real vol = 0.5 * K * jm1 * (2.0 + jm1); /* K/2 (J^2 - 1) */
   int rc = 0;
   if (m->model == ORC_LE) {
     real lam = K - 2.0 * mu / 3.0;
     real eps[9];
     for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) eps[i * 3 + j] = 0.5 * (F[i * 3 + j] + F[j * 3 + i]);
-    eps[0] -= 1.0;
-    eps[4] -= 1.0;
-    eps[8] -= 1.0;
+      for (int j = 0; j < 3; ++j) eps[i * 3 + j] = 0.5 * (H[i * 3 + j] + H[j * 3 + i]);
     real tr = trace3(eps);
     for (int i = 0; i < 9; ++i) P[i] = 2.0 * mu * eps[i];
     P[0] += lam * tr;
     P[4] += lam * tr;
     P[8] += lam * tr;
   } else if (m->model == ORC_NH) {
-    real b[9], db[9], tau[9];
-    mul3_bt(F, F, b);
+    real Bm[9], db[9], tau[9];
+    sym_sum(H, Bm);             /* b - I */
     real s23 = r_pow(J, -2.0 / 3.0);
-    for (int i = 0; i < 9; ++i) b[i] *= s23;
-    dev3(b, db);
-    for (int i = 0; i < 9; ++i) tau[i] = mu * db[i];
-    real vol = 0.5 * K * (J * J - 1.0);
+    dev3(Bm, db);               /* dev(b) = dev(b - I) */
+    for (int i = 0; i < 9; ++i) tau[i] = mu * s23 * db[i];
     tau[0] += vol;
     tau[4] += vol;
     tau[8] += vol;
     mul3(tau, FiT, P);
   } else {
     /* Algorithm 1 */
-    real s13 = r_pow(J, -1.0 / 3.0);
-    real Fb[9], Xb[9], tmp[9], bpre[9], spre[9], s[9], tau[9];
-    for (int i = 0; i < 9; ++i) Fb[i] = s13 * F[i];
-    /* stored symmetric Cbar_p^-1: xx yy zz xy yz xz */
-    Xb[0] = pl[0]; Xb[4] = pl[1]; Xb[8] = pl[2];
-    Xb[1] = Xb[3] = pl[3];
-    Xb[5] = Xb[7] = pl[4];
-    Xb[2] = Xb[6] = pl[5];
+    real c = r_pow(J, -1.0 / 3.0);
+    real cm1 = r_expm1(-r_log1p(jm1) / 3.0);
+    real Hb[9], Fb[9], Y[9], E[9], tmp[9], t3[9], spre[9], s[9], tau[9];
+    for (int i = 0; i < 9; ++i) Hb[i] = c * H[i];
+    Hb[0] += cm1;
+    Hb[4] += cm1;
+    Hb[8] += cm1; /* Fbar - I */
+    for (int i = 0; i < 9; ++i) Fb[i] = Hb[i];
+    Fb[0] += 1.0;
+    Fb[4] += 1.0;
+    Fb[8] += 1.0;
+    Y[0] = pl[0]; Y[4] = pl[1]; Y[8] = pl[2];
+    Y[1] = Y[3] = pl[3];
+    Y[5] = Y[7] = pl[4];
+    Y[2] = Y[6] = pl[5];
     real alpha = pl[6];
-    mul3(Fb, Xb, tmp);
-    mul3_bt(tmp, Fb, bpre); /* predictor bbar_e = Fbar Cbar_p^-1 Fbar^T */
-    dev3(bpre, spre);
+    /* predictor bbar_e,pre = Fbar Cbar_p^-1 Fbar^T; E = bbar_e,pre - I */
+    real FFm[9];
+    sym_sum(Hb, FFm); /* Fbar Fbar^T - I */
+    mul3(Fb, Y, tmp);
+    mul3_bt(tmp, Fb, t3);
+    for (int i = 0; i < 9; ++i) E[i] = FFm[i] + t3[i];
+    dev3(E, spre);
     for (int i = 0; i < 9; ++i) spre[i] *= mu; /* s_pre = mu dev(bbar_e,pre) */
     real n2 = 0.0;
     for (int i = 0; i < 9; ++i) n2 += spre[i] * spre[i];
@@ -588,9 +629,9 @@ int orc_constitutive(const orc_material* m, const real* F, real* pl, real p, rea
     const double r23 = sqrt(2.0 / 3.0);
     real f = snorm - r23 * hardening(m, alpha); /* von Mises check */
     for (int i = 0; i < 9; ++i) s[i] = spre[i];
-    real trb3 = trace3(bpre) / 3.0;
+    real trE3 = trace3(E) / 3.0; /* tr(bbar_pre)/3 - 1 */
     if (RE(f) > 0.0) {
-      real mubar = mu * trb3; /* normalised shear modulus */
+      real mubar = mu * (1.0 + trE3); /* normalised shear modulus */
       real dg = 0.0;
       int it, ok = 0;
       double tol = 1e-13 * (RE(snorm) > 1.0 ? RE(snorm) : 1.0);
@@ -614,23 +655,22 @@ int orc_constitutive(const orc_material* m, const real* F, real* pl, real p, rea
       alpha = alpha + r23 * dg;
     }
     for (int i = 0; i < 9; ++i) tau[i] = s[i];
-    real vol = 0.5 * K * (J * J - 1.0);
     tau[0] += vol;
     tau[4] += vol;
     tau[8] += vol;
     mul3(tau, FiT, P);
-    /* update the internal variable: bbar_e = s/mu + tr(bbar_pre)/3 I,
-     * Cbar_p^-1 = Fbar^-1 bbar_e Fbar^-T */
-    real be[9], Fbi[9], t2[9], Xn[9];
-    for (int i = 0; i < 9; ++i) be[i] = s[i] / mu;
-    be[0] += trb3;
-    be[4] += trb3;
-    be[8] += trb3;
+    /* update: bbar_e = s/mu + tr(bbar_pre)/3 I and Cbar_p^-1 = Fbar^-1 bbar_e
+     * Fbar^-T, i.e. Y = Fbar^-1 ((bbar_e - I) - (Fbar Fbar^T - I)) Fbar^-T */
+    real D[9], Fbi[9], t2[9], Yn[9];
+    for (int i = 0; i < 9; ++i) D[i] = s[i] / mu - FFm[i];
+    D[0] += trE3;
+    D[4] += trE3;
+    D[8] += trE3;
     inv3(Fb, Fbi);
-    mul3(Fbi, be, t2);
-    mul3_bt(t2, Fbi, Xn);
-    pl[0] = Xn[0]; pl[1] = Xn[4]; pl[2] = Xn[8];
-    pl[3] = Xn[1]; pl[4] = Xn[5]; pl[5] = Xn[2];
+    mul3(Fbi, D, t2);
+    mul3_bt(t2, Fbi, Yn);
+    pl[0] = Yn[0]; pl[1] = Yn[4]; pl[2] = Yn[8];
+    pl[3] = Yn[1]; pl[4] = Yn[5]; pl[5] = Yn[2];
     pl[6] = alpha;
   }
   for (int i = 0; i < 9; ++i) P[i] -= J * p * FiT[i];
@@ -638,8 +678,8 @@ int orc_constitutive(const orc_material* m, const real* F, real* pl, real p, rea
 }
 
 /* ------------------------------------------------------------------------ */
-/* F_a = I + (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a   (F9: [9][n]) */
-void orc_deformation_gradient(const orc_sys* s, const real* u, real* F9) {
+/* H_a = F_a - I = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a   (H9: [9][n]) */
+void orc_displacement_gradient(const orc_sys* s, const real* u, real* H9) {
   int d = s->dim;
   int64_t n = s->n;
   for (int64_t a = 0; a < n; ++a) {
@@ -653,26 +693,26 @@ void orc_deformation_gradient(const orc_sys* s, const real* u, real* F9) {
         for (int k = 0; k < d; ++k) G[i * 3 + k] += s->V[b] * du * gw[k];
       }
     }
-    real F[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    real Hm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int i = 0; i < d; ++i)
       for (int k = 0; k < d; ++k) {
         real acc = 0.0;
         for (int l = 0; l < d; ++l) acc += G[i * 3 + l] * s->B0[(l * d + k) * n + a];
-        F[i * 3 + k] += acc;
+        Hm[i * 3 + k] = acc;
       }
-    for (int i = 0; i < 9; ++i) F9[i * n + a] = F[i];
+    for (int i = 0; i < 9; ++i) H9[i * n + a] = Hm[i];
   }
 }
 
 /* stress at every particle and PB = P B0 (in-plane d x d block) */
-int orc_stress(const orc_sys* s, const orc_material* m, const real* F9, real* plastic,
+int orc_stress(const orc_sys* s, const orc_material* m, const real* H9, real* plastic,
                const real* p, real* P9, real* PB) {
   int d = s->dim;
   int64_t n = s->n;
   int rc = 0;
   for (int64_t a = 0; a < n; ++a) {
     real F[9], P[9], pl[7];
-    for (int i = 0; i < 9; ++i) F[i] = F9[i * n + a];
+    for (int i = 0; i < 9; ++i) F[i] = H9[i * n + a];
     if (m->model == ORC_J2)
       for (int i = 0; i < 7; ++i) pl[i] = plastic[i * n + a];
     int r = orc_constitutive(m, F, pl, p ? p[a] : 0.0, P);
@@ -718,7 +758,7 @@ int orc_solid_step(const orc_sys* s, const orc_material* m, double dt, const rea
   real* F9 = (real*)malloc(9 * n * sizeof(real));
   real* PBl = PB ? PB : (real*)malloc(d * d * n * sizeof(real));
   real* accl = acc ? acc : (real*)malloc(d * n * sizeof(real));
-  orc_deformation_gradient(s, u, F9);
+  orc_displacement_gradient(s, u, F9);
   int rc = orc_stress(s, m, F9, plastic, p, NULL, PBl);
   orc_momentum(s, m, PBl, accl);
   for (int64_t a = 0; a < n; ++a) {

@@ -78,13 +78,14 @@ void orc_get_schedule(const orc_sys* s, uint32_t* pa, uint32_t* pb, uint32_t* pl
                       uint32_t* anchor_key, int64_t* anchor_off, uint32_t* anchor_nlev,
                       int64_t* color_off);
 
-/* one-particle constitutive update (3x3 row-major F); returns 0, or -4 if the
+/* one-particle constitutive update from H = F - I (3x3 row-major); plastic7 =
+ * (Cbar_p^-1 - I: xx yy zz xy yz xz, alpha); returns 0, or -4 if the
  * return-mapping Newton iteration fails */
-int orc_constitutive(const orc_material* m, const real* F, real* plastic7, real p, real* P);
+int orc_constitutive(const orc_material* m, const real* H, real* plastic7, real p, real* P);
 
 /* inner-step pieces */
-void orc_deformation_gradient(const orc_sys* s, const real* u, real* F9);
-int orc_stress(const orc_sys* s, const orc_material* m, const real* F9, real* plastic,
+void orc_displacement_gradient(const orc_sys* s, const real* u, real* H9);
+int orc_stress(const orc_sys* s, const orc_material* m, const real* H9, real* plastic,
                const real* p, real* P9, real* PB);
 void orc_momentum(const orc_sys* s, const orc_material* m, const real* PB, real* acc);
 int orc_solid_step(const orc_sys* s, const orc_material* m, double dt, const real* u, real* v,

@@ -26,8 +26,10 @@ SPH_FLAG_FIXED, SPH_FLAG_CDIR, SPH_FLAG_GRIP = 1, 2, 4
 EXPORTED = [
     "sph_build_neighbors", "sph_nbr_destroy", "sph_nbr_query", "sph_solid_relax_step",
     "sph_damping_sweep", "sph_drift_ke", "sph_load_step", "sph_diffusion_step",
-    "sph_advance_multirate", "sph_status", "sph_last_error",
+    "sph_advance_multirate", "sph_status", "sph_profile_enable", "sph_profile_read",
+    "sph_last_error",
 ]
+SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load"]
 
 
 class SphError(RuntimeError):
@@ -92,6 +94,8 @@ def lib():
     L.sph_advance_multirate.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
                                         C.POINTER(MultirateCfg), C.POINTER(Report), vp]
     L.sph_status.argtypes = [vp, vp, C.POINTER(i32)]
+    L.sph_profile_enable.argtypes = [vp, C.c_int]
+    L.sph_profile_read.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)]
     L.sph_last_error.restype = C.c_char_p
     for name in EXPORTED:
         getattr(L, name).restype = C.c_int if name != "sph_last_error" else C.c_char_p
@@ -262,9 +266,7 @@ def new_state(nbr, prec, with_plastic=False, with_diffusion=False, with_acc=Fals
     z = lambda *s, dt=T: torch.zeros(s, dtype=dt, device=device)  # noqa: E731
     st = SphState(prec, z(d, n, dt=torch.float64), z(d, n), z(d * d, n))
     if with_plastic:
-        pl = z(7, n)
-        pl[0:3] = 1.0
-        st.plastic = pl
+        st.plastic = z(7, n)   # Cbar_p^-1 - I and alpha: virgin state is zero
     if with_diffusion:
         st.c, st.q, st.p = z(n), z(d, n), z(n)
     if with_acc:
@@ -329,3 +331,17 @@ def sph_advance_multirate(nbr, mat, st, cfg, stream=None):
     rc = _check(lib().sph_advance_multirate(nbr.handle, C.byref(mat), C.byref(cs), C.byref(cfg),
                                             C.byref(rep), _stream(stream)), allow_warning=True)
     return rc, k[:ns], ke[:ns], conv[:ns], rep
+
+
+def sph_profile_enable(nbr, enable=True):
+    _check(lib().sph_profile_enable(nbr.handle, 1 if enable else 0))
+
+
+def sph_profile_read(nbr):
+    """{kernel class: (launches, total ms)} of the launches timed so far."""
+    out = {}
+    for k, name in enumerate(SPH_KERNEL_NAMES):
+        cnt, ms = i64(0), dbl(0.0)
+        _check(lib().sph_profile_read(nbr.handle, k, C.byref(cnt), C.byref(ms)))
+        out[name] = (cnt.value, ms.value)
+    return out

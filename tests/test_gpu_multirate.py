@@ -34,7 +34,6 @@ def _run_pair(oracle_mod, case, prec, use_graph=0, chunk=64, k_sched=None, run_o
     plo = None
     if plastic:
         plo = np.zeros((7, n))
-        plo[:3] = 1
     co = qo = po = None
     vg = None
     if case.vgrip is not None:

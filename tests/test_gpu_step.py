@@ -53,7 +53,6 @@ def test_solid_stage(oracle_mod, dim, model, prec):
     u, v, flags = _fields(o, dim, rng, amp)
     p = np.ascontiguousarray(rng.uniform(0, 1e6, o.n)) if model != "J2" else None
     pl = np.zeros((7, o.n))
-    pl[:3] = 1.0
     T = torch_dtype(prec)
     st = B.new_state(nb, prec, with_plastic=(model == "J2"), with_acc=True)
     st.u.copy_(dev(u))

@@ -119,7 +119,7 @@ def test_j2_elastic_below_yield(o):
     rc, Pj, pl = o.constitutive(j2, F)
     assert rc == 0
     assert np.allclose(Pj, Pn, rtol=1e-12, atol=1e-12 * np.abs(Pn).max())
-    assert np.allclose(pl, [1, 1, 1, 0, 0, 0, 0], atol=1e-13)
+    assert np.allclose(pl, 0.0, atol=1e-13)
 
 
 def _dev_tau(F, P):
@@ -152,13 +152,13 @@ def test_j2_nonlinear_consistency_and_bisection(o):
     s0, sinf, dl = 2.0e8, 4.0e8, 16.0
     j2 = o.material(cases.J2, E, NU, 7850.0, sigma0=s0, sigma_inf=sinf, delta=dl)
     k = lambda a: s0 + (sinf - s0) * (1 - np.exp(-dl * a))  # noqa: E731
-    pl = np.array([1, 1, 1, 0, 0, 0, 0.0])
+    pl = np.zeros(7)
     for step in range(1, 6):
         F = np.diag([1 + 0.004 * step, 1 - 0.002 * step, 1 - 0.002 * step])
         F[0, 1] = 0.001 * step
         J = np.linalg.det(F)
         Fb = J ** (-1 / 3) * F
-        Xb = np.array([[pl[0], pl[3], pl[5]], [pl[3], pl[1], pl[4]], [pl[5], pl[4], pl[2]]])
+        Xb = np.eye(3) + np.array([[pl[0], pl[3], pl[5]], [pl[3], pl[1], pl[4]], [pl[5], pl[4], pl[2]]])
         b = Fb @ Xb @ Fb.T
         s = MU * (b - np.trace(b) / 3 * np.eye(3))
         sn = np.linalg.norm(s)

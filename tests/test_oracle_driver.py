@@ -39,8 +39,8 @@ def test_bar_converges_to_analytic_elastic_solution(oracle_mod):
     L, W = nx * c.dp, ny * c.dp
     ua = np.vstack([eps * (o.X[0] - 0.5 * L), -nu / (1 - nu) * eps * (o.X[1] - 0.5 * W)])
     assert np.abs(u - ua).max() <= 1e-6 * np.abs(ua).max()
-    F9 = o.deformation_gradient(u)
-    _, P9, _ = o.stress(mat, F9)
+    H9 = o.displacement_gradient(u)
+    _, P9, _ = o.stress(mat, H9)
     sxx = E / (1 - nu * nu) * eps
     assert np.abs(P9[0] - sxx).max() <= 1e-6 * sxx
     assert np.abs(P9[4]).max() <= 1e-6 * sxx
