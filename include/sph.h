@@ -229,6 +229,23 @@ int sph_advance_multirate(const sph_nbr* nbr, const sph_material* mat, const sph
  * *status_bits (may be NULL): SPH_OK, or SPH_E_NUMERIC if any bit was set. */
 int sph_status(const sph_nbr* nbr, void* stream, int32_t* status_bits);
 
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel the handle launches (eager launches only; launches replayed
+ * from a captured graph are not timed).  sph_profile_enable resets the
+ * counters; sph_profile_read synchronises on the recorded events and returns
+ * the number of launches and their summed duration for one kernel class.
+ * Timing adds two event records per launch. */
+#define SPH_KERNEL_STRESS 0    /* deformation gradient + stress + PB */
+#define SPH_KERNEL_MOMENTUM 1  /* pair momentum sum + kick */
+#define SPH_KERNEL_DAMPING 2   /* one colour pass of the damping sweep */
+#define SPH_KERNEL_DRIFT_KE 3  /* drift + kinetic energy + stop test */
+#define SPH_KERNEL_DIFF_GRAD 4 /* diffusion flux */
+#define SPH_KERNEL_DIFF_DIV 5  /* diffusion divergence + Dirichlet + pressure */
+#define SPH_KERNEL_LOAD 6      /* grip displacement increment */
+#define SPH_KERNEL_COUNT 7
+int sph_profile_enable(sph_nbr* nbr, int enable);
+int sph_profile_read(sph_nbr* nbr, int kernel_class, int64_t* launches, double* total_ms);
+
 /* Thread-local description of the last error ("" if none). */
 const char* sph_last_error(void);
 

@@ -527,14 +527,184 @@ __global__ void k_sched_fill(const uint32_t* key, const uint32_t* cs, const int6
 }
 
 // ---------------------------------------------------------------------------
+// tiles: ELL of window-local neighbour indices
+__global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __restrict__ off,
+                           const uint32_t* __restrict__ idx, int tmax, uint16_t* __restrict__ ell,
+                           int32_t* err) {
+  const TileDesc& td = tiles[blockIdx.x];
+  for (int t = threadIdx.x; t < tmax; t += blockDim.x) {
+    uint32_t own = td.own_base + t;
+    int64_t j0 = 0, deg = 0;
+    if ((uint32_t)t < td.count) {
+      int64_t a = (int64_t)td.p0 + t;
+      j0 = off[a];
+      deg = off[a + 1] - j0;
+    } else {
+      own = td.own_base;  // unused column: any valid index
+    }
+    for (uint32_t j = 0; j < td.width; ++j) {
+      uint32_t loc = own;
+      if ((int64_t)j < deg) {
+        uint32_t b = idx[j0 + j];
+        uint32_t base = 0;
+        bool found = false;
+        for (uint32_t r = 0; r < td.nruns; ++r) {
+          uint32_t rel = b - td.run_start[r];
+          if (rel < td.run_count[r]) {
+            loc = base + rel;
+            found = true;
+            break;
+          }
+          base += td.run_count[r];
+        }
+        if (!found) atomicOr(err, 4);
+      }
+      ell[(int64_t)td.ell_off + (int64_t)j * tmax + t] = (uint16_t)loc;
+    }
+  }
+}
+
+// damping: pack each canonical pair as (a_loc, b_loc, level) inside its anchor block
+__global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __restrict__ aoff,
+                            const uint32_t* __restrict__ sa, const uint32_t* __restrict__ sb,
+                            const uint32_t* __restrict__ slev, const uint32_t* __restrict__ cs,
+                            Grid g, int64_t n_anchors, uint32_t* __restrict__ dpair,
+                            uint32_t* __restrict__ ablk, unsigned long long* bmax,
+                            unsigned long long* pmax, int32_t* err) {
+  int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (ai >= n_anchors) return;
+  Block blk = anchor_block(akey[ai], g, cs);
+  int64_t lbase[4], acc = 0;
+  for (int r = 0; r < 4; ++r) {
+    ablk[8 * ai + 2 * r] = r < blk.nr ? (uint32_t)blk.beg[r] : 0u;
+    ablk[8 * ai + 2 * r + 1] = r < blk.nr ? (uint32_t)(blk.end[r] - blk.beg[r]) : 0u;
+  }
+  for (int r = 0; r < blk.nr; ++r) {
+    lbase[r] = acc;
+    acc += blk.end[r] - blk.beg[r];
+  }
+  atomicMax(bmax, (unsigned long long)acc);
+  atomicMax(pmax, (unsigned long long)(aoff[ai + 1] - aoff[ai]));
+  if (acc > kDampMaxLocal) {
+    atomicOr(err, 8);
+    return;
+  }
+  for (int64_t i = aoff[ai]; i < aoff[ai + 1]; ++i) {
+    int64_t loc[2] = {-1, -1};
+    uint32_t pp[2] = {sa[i], sb[i]};
+    for (int e = 0; e < 2; ++e)
+      for (int r = 0; r < blk.nr; ++r)
+        if ((int64_t)pp[e] >= blk.beg[r] && (int64_t)pp[e] < blk.end[r]) loc[e] = lbase[r] + (pp[e] - blk.beg[r]);
+    if (loc[0] < 0 || loc[1] < 0 || slev[i] >= (uint32_t)kDampMaxLevel) {
+      atomicOr(err, 16);
+      continue;
+    }
+    dpair[i] = (uint32_t)loc[0] | ((uint32_t)loc[1] << kDampLocBits) | (slev[i] << (2 * kDampLocBits));
+  }
+}
+
+// host planning of row tiles (setup only)
+static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
+                      const std::vector<int64_t>& off, int tmax, int64_t wmax,
+                      std::vector<TileDesc>& out, int64_t& window_max, int64_t& ell_len) {
+  const int64_t nc0 = nb->nc[0], nc1 = nb->nc[1], nc2 = nb->nc[2];
+  const int dim = nb->dim;
+  auto key = [&](int64_t x, int64_t y, int64_t z) { return x + nc0 * (y + nc1 * z); };
+  auto ccount = [&](int64_t x, int64_t y, int64_t z) {
+    int64_t k = key(x, y, z);
+    return (int64_t)cs[k + 1] - (int64_t)cs[k];
+  };
+  auto make = [&](int64_t x0, int64_t x1, int64_t y, int64_t z, int64_t p0, int64_t cnt,
+                  TileDesc& td) -> int64_t {
+    std::memset(&td, 0, sizeof(td));
+    td.p0 = (uint32_t)p0;
+    td.count = (uint32_t)cnt;
+    int64_t xa = x0 > 0 ? x0 - 1 : 0, xb = x1 + 1 < nc0 ? x1 + 1 : nc0 - 1;
+    int64_t w = 0;
+    int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+      int64_t zz = z + dz;
+      if (zz < 0 || zz >= nc2) continue;
+      for (int dy = -1; dy <= 1; ++dy) {
+        int64_t yy = y + dy;
+        if (yy < 0 || yy >= nc1) continue;
+        int64_t s0 = cs[key(xa, yy, zz)], s1 = cs[key(xb, yy, zz) + 1];
+        if (dz == 0 && dy == 0) td.own_base = (uint32_t)(w + (p0 - s0));
+        td.run_start[td.nruns] = (uint32_t)s0;
+        td.run_count[td.nruns] = (uint32_t)(s1 - s0);
+        ++td.nruns;
+        w += s1 - s0;
+      }
+    }
+    td.window = (uint32_t)w;
+    return w;
+  };
+  out.clear();
+  window_max = 0;
+  ell_len = 0;
+  auto emit = [&](TileDesc& td) {
+    uint32_t width = 0;
+    for (uint32_t t = 0; t < td.count; ++t) {
+      int64_t a = (int64_t)td.p0 + t;
+      width = std::max<uint32_t>(width, (uint32_t)(off[a + 1] - off[a]));
+    }
+    td.width = width;
+    td.ell_off = (uint32_t)ell_len;
+    ell_len += (int64_t)width * tmax;
+    window_max = std::max<int64_t>(window_max, td.window);
+    out.push_back(td);
+  };
+  for (int64_t z = 0; z < nc2; ++z)
+    for (int64_t y = 0; y < nc1; ++y) {
+      int64_t x = 0;
+      while (x < nc0) {
+        int64_t cnt = ccount(x, y, z);
+        if (cnt == 0) {
+          ++x;
+          continue;
+        }
+        TileDesc td;
+        if (cnt > tmax) {  // one dense cell: split it into chunks
+          int64_t p0 = cs[key(x, y, z)];
+          for (int64_t c0 = 0; c0 < cnt; c0 += tmax) {
+            if (make(x, x, y, z, p0 + c0, std::min<int64_t>(tmax, cnt - c0), td) > wmax) return SPH_E_CAPACITY;
+            emit(td);
+          }
+          ++x;
+          continue;
+        }
+        int64_t x1 = x;
+        while (x1 + 1 < nc0) {
+          int64_t nxt = ccount(x1 + 1, y, z);
+          if (cnt + nxt > tmax) break;
+          if (make(x, x1 + 1, y, z, cs[key(x, y, z)], cnt + nxt, td) > wmax) break;
+          cnt += nxt;
+          ++x1;
+        }
+        if (make(x, x1, y, z, cs[key(x, y, z)], cnt, td) > wmax) return SPH_E_CAPACITY;
+        emit(td);
+        x = x1 + 1;
+      }
+    }
+  if (ell_len >= (1LL << 32)) return SPH_E_CAPACITY;
+  return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
 static void free_nbr(sph_nbr* h) {
   if (!h) return;
   void* ptrs[] = {h->key, h->perm, h->cell_start, h->nbr_off, h->nbr_idx, h->X,   h->V,
                   h->B0,  h->Vf,   h->B0f,        h->sa,      h->sb,      h->slev, h->akey,
-                  h->aoff, h->anlev, h->ctrl,     h->ke_partial};
+                  h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk,
+                  h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->ctrl_host) hipHostFree(h->ctrl_host);
+  if (h->prof) {
+    prof_resolve(h);
+    for (hipEvent_t e : h->prof->pool) hipEventDestroy(e);
+    delete h->prof;
+  }
   delete h;
 }
 
@@ -728,6 +898,80 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
     return SPH_E_CAPACITY;
   }
   nb->max_level = (int64_t)hmaxlev;
+
+  // damping pairs packed inside their anchor blocks
+  {
+    unsigned long long* mx = nullptr;
+    int32_t* derr = nullptr;
+    if ((rc_ = dalloc(&nb->dpair, npu)) || (rc_ = dalloc(&nb->ablk, 8 * std::max<int64_t>(base, 1))) ||
+        (rc_ = dalloc(&mx, 2)) || (rc_ = dalloc(&derr, 1)))
+      return rc_;
+    SPH_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned long long), s));
+    SPH_HIP(hipMemsetAsync(derr, 0, sizeof(int32_t), s));
+    if (base > 0) {
+      k_damp_pack<<<nblocks(base, 64), 64, 0, s>>>(nb->akey, nb->aoff, nb->sa, nb->sb, nb->slev,
+                                                   nb->cell_start, g, base, nb->dpair, nb->ablk,
+                                                   mx, mx + 1, derr);
+      SPH_LAUNCH_CHECK();
+    }
+    unsigned long long hm[2] = {0, 0};
+    int32_t he = 0;
+    SPH_HIP(hipMemcpyAsync(hm, mx, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(&he, derr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    hipFree(mx);
+    hipFree(derr);
+    if (he) {
+      set_error("damping schedule exceeds %d block particles or %d levels", kDampMaxLocal,
+                kDampMaxLevel);
+      return SPH_E_CAPACITY;
+    }
+    nb->damp_block_max = (int64_t)hm[0];
+    nb->damp_pairs_max = (int64_t)hm[1];
+  }
+
+  // row tiles for the LDS-staged gathers, one tiling per precision
+  {
+    std::vector<uint32_t> hcs(nb->n_cells + 1);
+    std::vector<int64_t> hoff(n + 1);
+    SPH_HIP(hipMemcpyAsync(hcs.data(), nb->cell_start, (nb->n_cells + 1) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(hoff.data(), nb->nbr_off, (n + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    int32_t* terr = nullptr;
+    if ((rc_ = dalloc(&terr, 1))) return rc_;
+    for (int prec = 0; prec < 2; ++prec) {
+      Tiling& T = nb->tiling[prec];
+      T.tmax = tile_tmax(prec);
+      std::vector<TileDesc> tv;
+      rc_ = plan_tiles(nb, hcs, hoff, T.tmax, tile_wmax(prec, dim), tv, T.window_max, T.ell_len);
+      if (rc_) {
+        hipFree(terr);
+        set_error("tile planning failed (a cell row window exceeds the LDS budget)");
+        return rc_;
+      }
+      T.n_tiles = (int64_t)tv.size();
+      if ((rc_ = dalloc(&T.tiles, T.n_tiles)) || (rc_ = dalloc(&T.ell, T.ell_len))) return rc_;
+      SPH_HIP(hipMemcpyAsync(T.tiles, tv.data(), T.n_tiles * sizeof(TileDesc),
+                             hipMemcpyHostToDevice, s));
+      SPH_HIP(hipMemsetAsync(terr, 0, sizeof(int32_t), s));
+      if (T.n_tiles > 0) {
+        k_tile_ell<<<(unsigned)T.n_tiles, 128, 0, s>>>(T.tiles, nb->nbr_off, nb->nbr_idx, T.tmax,
+                                                       T.ell, terr);
+        SPH_LAUNCH_CHECK();
+      }
+      int32_t he = 0;
+      SPH_HIP(hipMemcpyAsync(&he, terr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      SPH_HIP(hipStreamSynchronize(s));
+      if (he) {
+        hipFree(terr);
+        set_error("tile ELL build failed (code %d)", he);
+        return SPH_E_DEVICE;
+      }
+    }
+    hipFree(terr);
+  }
 
   // inner-loop control block
   SPH_HIP(hipMalloc(&nb->ctrl, sizeof(Ctrl)));

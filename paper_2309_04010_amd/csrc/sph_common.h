@@ -5,9 +5,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "sph.h"
 
@@ -46,8 +48,51 @@ struct Ctrl {
   int32_t stopped_by_ke;
 };
 
+// per-kernel event timing (see sph_profile_enable)
+struct Prof {
+  bool on = false;
+  bool suspend = false;  // set while a graph is being captured
+  struct Pend {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pend> pend;
+  int64_t count[SPH_KERNEL_COUNT] = {0};
+  double ms[SPH_KERNEL_COUNT] = {0};
+};
+
 constexpr int kKeThreads = 256;
 constexpr int kKeMaxBlocks = 2048;
+
+// A tile is a run of consecutive sorted particles inside one row of cells
+// (fixed y, z).  Its neighbours all lie in the "window": the 3^(d-1) rows
+// around it, each clipped to cells [x0-1, x1+1] -- contiguous particle runs,
+// which a workgroup stages in LDS.  Neighbour lists of the tile are stored as
+// window-local 16-bit indices in an ELL layout: entry j of tile particle t is
+// ell[ell_off + j * tmax + t]; rows past a particle's degree hold its own
+// index (a zero contribution).
+struct TileDesc {
+  uint32_t p0, count, ell_off, width;
+  uint32_t nruns, window, own_base, pad;
+  uint32_t run_start[9];
+  uint32_t run_count[9];
+};
+
+struct Tiling {
+  int tmax = 0;            // particles per tile (threads per particle x tmax = block)
+  int64_t n_tiles = 0;
+  int64_t window_max = 0;  // largest window, sizes the dynamic LDS
+  int64_t ell_len = 0;
+  TileDesc* tiles = nullptr;  // device
+  uint16_t* ell = nullptr;    // device
+};
+
+// damping pair word: a_loc | b_loc << 12 | level << 24 (locals inside the
+// anchor's 2^d-cell block, in ascending sorted order)
+constexpr int kDampLocBits = 12;
+constexpr int kDampMaxLocal = 1 << kDampLocBits;
+constexpr int kDampMaxLevel = 256;
 
 }  // namespace sph
 
@@ -77,11 +122,17 @@ struct sph_nbr {
   uint32_t* akey = nullptr;
   int64_t* aoff = nullptr;
   uint32_t* anlev = nullptr;
+  uint32_t* dpair = nullptr;         // [n_upairs] packed damping pairs (canonical order)
+  uint32_t* ablk = nullptr;          // [n_anchors][8] anchor block runs (begin, count) x 4
+  int64_t damp_block_max = 0;        // largest anchor block (particles)
+  int64_t damp_pairs_max = 0;        // largest pair count of one anchor
+  sph::Tiling tiling[2];             // [SPH_F32], [SPH_F64]
   // inner-loop control
   sph::Ctrl* ctrl = nullptr;         // device
   sph::Ctrl* ctrl_host = nullptr;    // pinned host mirror
   double* ke_partial = nullptr;      // device [kKeMaxBlocks]
   int device = 0;
+  sph::Prof* prof = nullptr;         // host-side timing state
 };
 
 namespace sph {
@@ -94,6 +145,24 @@ __device__ __forceinline__ T dw_over_r(T r2, T inv_h, T c5) {
   T t = T(1) - T(0.5) * q;
   return c5 * t * t * t;
 }
+
+// ---- tiling parameters per precision -----------------------------------------
+// LDS bytes per staged window particle of the widest tiled kernel (momentum:
+// position + volume as one 4-vector, P B0 padded to whole 4-vectors).
+inline int tile_tmax(int prec) { return prec == SPH_F64 ? 64 : 128; }
+inline int64_t tile_lds_bytes_per_particle(int prec, int dim) {
+  const int t = prec == SPH_F64 ? 8 : 4;
+  return (int64_t)t * 4 * (1 + (dim * dim + 3) / 4);
+}
+constexpr int64_t kTileLdsBudget = 80 * 1024;
+inline int64_t tile_wmax(int prec, int dim) {
+  return std::min<int64_t>(65535, kTileLdsBudget / tile_lds_bytes_per_particle(prec, dim));
+}
+
+// ---- event timing around launches --------------------------------------------
+hipEvent_t prof_begin(const sph_nbr* nb, hipStream_t s);
+void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s);
+int prof_resolve(const sph_nbr* nb);
 
 // ---- host entry points implemented per translation unit ----------------------
 int solid_stage(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,

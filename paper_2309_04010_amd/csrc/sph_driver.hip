@@ -14,6 +14,92 @@
 
 using namespace sph;
 
+namespace sph {
+
+hipEvent_t prof_begin(const sph_nbr* nb, hipStream_t s) {
+  Prof* p = nb->prof;
+  if (!p || !p->on || p->suspend) return nullptr;
+  hipEvent_t e = nullptr;
+  if (!p->pool.empty()) {
+    e = p->pool.back();
+    p->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  if (hipEventRecord(e, s) != hipSuccess) {
+    p->pool.push_back(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s) {
+  Prof* p = nb->prof;
+  if (!a || !p) return;
+  hipEvent_t b = nullptr;
+  if (!p->pool.empty()) {
+    b = p->pool.back();
+    p->pool.pop_back();
+  } else if (hipEventCreate(&b) != hipSuccess) {
+    p->pool.push_back(a);
+    return;
+  }
+  hipEventRecord(b, s);
+  p->pend.push_back(Prof::Pend{kind, a, b});
+  if (p->pend.size() > 65536) prof_resolve(nb);
+}
+
+int prof_resolve(const sph_nbr* nb) {
+  Prof* p = nb->prof;
+  if (!p) return SPH_OK;
+  for (auto& q : p->pend) {
+    SPH_HIP(hipEventSynchronize(q.b));
+    float ms = 0.f;
+    SPH_HIP(hipEventElapsedTime(&ms, q.a, q.b));
+    p->count[q.kind] += 1;
+    p->ms[q.kind] += ms;
+    p->pool.push_back(q.a);
+    p->pool.push_back(q.b);
+  }
+  p->pend.clear();
+  return SPH_OK;
+}
+
+}  // namespace sph
+
+extern "C" int sph_profile_enable(sph_nbr* nb, int enable) {
+  clear_error();
+  if (!nb) {
+    set_error("null handle");
+    return SPH_E_ARG;
+  }
+  if (!nb->prof) nb->prof = new Prof();
+  int rc = prof_resolve(nb);
+  for (int k = 0; k < SPH_KERNEL_COUNT; ++k) {
+    nb->prof->count[k] = 0;
+    nb->prof->ms[k] = 0.0;
+  }
+  nb->prof->on = enable != 0;
+  return rc;
+}
+
+extern "C" int sph_profile_read(sph_nbr* nb, int kind, int64_t* launches, double* total_ms) {
+  clear_error();
+  if (!nb || kind < 0 || kind >= SPH_KERNEL_COUNT) {
+    set_error("bad handle or kernel class");
+    return SPH_E_ARG;
+  }
+  if (!nb->prof) {
+    if (launches) *launches = 0;
+    if (total_ms) *total_ms = 0.0;
+    return SPH_OK;
+  }
+  int rc = prof_resolve(nb);
+  if (launches) *launches = nb->prof->count[kind];
+  if (total_ms) *total_ms = nb->prof->ms[kind];
+  return rc;
+}
+
 namespace {
 
 int inner_steps(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
@@ -162,10 +248,12 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     SPH_HIP(hipEventRecord(ev, user));
     SPH_HIP(hipStreamWaitEvent(own, ev, 0));
     s = own;
+    if (nb->prof) nb->prof->suspend = true;
     SPH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     rc = inner_steps(nb, m, st, dt_s, cfg->eta, chunk, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
+    if (nb->prof) nb->prof->suspend = false;
     gc.graph = g;
     if (rc == SPH_OK && e != hipSuccess) {
       set_error("graph capture failed: %s", hipGetErrorString(e));
@@ -213,6 +301,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
         rc = SPH_E_DEVICE;
         break;
       }
+      if (nb->prof) prof_resolve(nb);
       if (hc->done || launched >= nk) break;
     }
     if (rc) break;

@@ -88,70 +88,103 @@ __device__ __forceinline__ T hardening_slope(const MatP<T>& m, T a) {
   return (m.sinf - m.s0) * m.delta * exp(-m.delta * a) + m.H;
 }
 
-// First Piola-Kirchhoff stress of one particle; returns SPH_STATUS_NEWTON on a
-// failed return mapping.  App. A.2-A.4 and B.2 of the paper; LE is the
-// small-strain reading.  pl: Cbar_p^-1 (xx,yy,zz,xy,yz,xz) and alpha.
+// S = A + A^T + A A^T  (= (I+A)(I+A)^T - I)
 template <typename T>
-__device__ int constitutive(const MatP<T>& m, const T* F, T* pl, T p, T* P) {
-  T J = det3(F);
+__device__ __forceinline__ void sym_sum(const T* A, T* S) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      S[i * 3 + j] = A[i * 3 + j] + A[j * 3 + i] + A[i * 3] * A[j * 3] + A[i * 3 + 1] * A[j * 3 + 1] +
+                     A[i * 3 + 2] * A[j * 3 + 2];
+}
+
+// First Piola-Kirchhoff stress of one particle from H = F - I; returns
+// SPH_STATUS_NEWTON on a failed return mapping.  App. A.2-A.4 and B.2 of the
+// paper (LE is the small-strain reading).  Strain measures come from H by
+// exact identities (det(I+H) - 1, F F^T - I) so FP32 keeps small strains.
+// pl: Cbar_p^-1 - I (xx,yy,zz,xy,yz,xz) and alpha.
+template <typename T>
+__device__ int constitutive(const MatP<T>& m, const T* H, T* pl, T p, T* P) {
+  T trH = H[0] + H[4] + H[8];
+  T trH2 = H[0] * H[0] + H[4] * H[4] + H[8] * H[8] + T(2) * (H[1] * H[3] + H[2] * H[6] + H[5] * H[7]);
+  T jm1 = trH + T(0.5) * (trH * trH - trH2) + det3(H);
+  T J = T(1) + jm1;
+  T F[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) F[i] = H[i];
+  F[0] += T(1);
+  F[4] += T(1);
+  F[8] += T(1);
   T Fi[9];
   inv3(F, J, Fi);
   int st = 0;
   T tau[9];
+  const T vol = T(0.5) * m.K * jm1 * (T(2) + jm1);
   if (m.model == SPH_MODEL_LE) {
-    T e0 = F[0] - T(1), e4 = F[4] - T(1), e8 = F[8] - T(1);
-    T tr = e0 + e4 + e8;
     T tm = T(2) * m.mu;
-    P[0] = tm * e0 + m.lam * tr;
-    P[4] = tm * e4 + m.lam * tr;
-    P[8] = tm * e8 + m.lam * tr;
-    P[1] = P[3] = m.mu * (F[1] + F[3]);
-    P[2] = P[6] = m.mu * (F[2] + F[6]);
-    P[5] = P[7] = m.mu * (F[5] + F[7]);
+    P[0] = tm * H[0] + m.lam * trH;
+    P[4] = tm * H[4] + m.lam * trH;
+    P[8] = tm * H[8] + m.lam * trH;
+    P[1] = P[3] = m.mu * (H[1] + H[3]);
+    P[2] = P[6] = m.mu * (H[2] + H[6]);
+    P[5] = P[7] = m.mu * (H[5] + H[7]);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) P[i * 3 + j] -= J * p * Fi[j * 3 + i];
     return 0;
   }
-  T cb = cbrt(J);
-  T vol = T(0.5) * m.K * (J * J - T(1));
   if (m.model == SPH_MODEL_NH) {
-    T b[9];
-    mul3_bt(F, F, b);
+    T Bm[9];
+    sym_sum(H, Bm);
+    T cb = cbrt(J);
     T s23 = T(1) / (cb * cb);
-    T trb = (b[0] + b[4] + b[8]) * s23 * (T(1) / T(3));
+    T tr3 = (Bm[0] + Bm[4] + Bm[8]) * (T(1) / T(3));
+    T ms = m.mu * s23;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) tau[i] = m.mu * b[i] * s23;
-    tau[0] += vol - m.mu * trb;
-    tau[4] += vol - m.mu * trb;
-    tau[8] += vol - m.mu * trb;
+    for (int i = 0; i < 9; ++i) tau[i] = ms * Bm[i];
+    tau[0] += vol - ms * tr3;
+    tau[4] += vol - ms * tr3;
+    tau[8] += vol - ms * tr3;
   } else {
-    // Algorithm 1
-    T s13 = T(1) / cb;
-    T Fb[9], Xb[9], tmp[9], bp[9], s[9];
+    // Algorithm 1 with Fbar = c F, c = J^(-1/3); Hb = Fbar - I; E = bbar_pre - I
+    T c = T(1) / cbrt(J);
+    T cm1 = expm1(log1p(jm1) * T(-1.0 / 3.0));
+    T Hb[9], Fb[9], Y[9], FFm[9], tmp[9], E[9], s[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Fb[i] = s13 * F[i];
-    Xb[0] = pl[0]; Xb[4] = pl[1]; Xb[8] = pl[2];
-    Xb[1] = Xb[3] = pl[3];
-    Xb[5] = Xb[7] = pl[4];
-    Xb[2] = Xb[6] = pl[5];
+    for (int i = 0; i < 9; ++i) Hb[i] = c * H[i];
+    Hb[0] += cm1;
+    Hb[4] += cm1;
+    Hb[8] += cm1;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Fb[i] = Hb[i];
+    Fb[0] += T(1);
+    Fb[4] += T(1);
+    Fb[8] += T(1);
+    Y[0] = pl[0]; Y[4] = pl[1]; Y[8] = pl[2];
+    Y[1] = Y[3] = pl[3];
+    Y[5] = Y[7] = pl[4];
+    Y[2] = Y[6] = pl[5];
     T alpha = pl[6];
-    mul3(Fb, Xb, tmp);
-    mul3_bt(tmp, Fb, bp);
-    T trb3 = (bp[0] + bp[4] + bp[8]) * (T(1) / T(3));
+    sym_sum(Hb, FFm);
+    mul3(Fb, Y, tmp);
+    mul3_bt(tmp, Fb, E);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) E[i] += FFm[i];
+    T trE3 = (E[0] + E[4] + E[8]) * (T(1) / T(3));
     T n2 = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      s[i] = m.mu * bp[i];
-      if (i == 0 || i == 4 || i == 8) s[i] -= m.mu * trb3;
+      s[i] = m.mu * E[i];
+      if (i == 0 || i == 4 || i == 8) s[i] -= m.mu * trE3;
       n2 += s[i] * s[i];
     }
     T sn = sqrt(n2);
     const T r23 = T(0.816496580927726);  // sqrt(2/3)
     T f = sn - r23 * hardening(m, alpha);
     if (f > T(0)) {
-      T mub = m.mu * trb3;
+      T mub = m.mu * (T(1) + trE3);
       T dg = 0;
       T tol = m.newton_tol * (sn > T(1) ? sn : T(1));
       bool ok = false;
@@ -176,19 +209,19 @@ __device__ int constitutive(const MatP<T>& m, const T* F, T* pl, T p, T* P) {
     tau[0] += vol;
     tau[4] += vol;
     tau[8] += vol;
-    // internal variable: bbar_e = s/mu + tr(bbar_pre)/3 I; Cbar_p^-1 = Fbar^-1 bbar_e Fbar^-T
-    T be[9], Fbi[9], t2[9], Xn[9];
+    // Y = Fbar^-1 ((bbar_e - I) - (Fbar Fbar^T - I)) Fbar^-T, bbar_e = s/mu + tr(bbar_pre)/3 I
+    T Dm[9], Fbi[9], t2[9], Yn[9];
     T imu = T(1) / m.mu;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) be[i] = s[i] * imu;
-    be[0] += trb3;
-    be[4] += trb3;
-    be[8] += trb3;
+    for (int i = 0; i < 9; ++i) Dm[i] = s[i] * imu - FFm[i];
+    Dm[0] += trE3;
+    Dm[4] += trE3;
+    Dm[8] += trE3;
     inv3(Fb, det3(Fb), Fbi);
-    mul3(Fbi, be, t2);
-    mul3_bt(t2, Fbi, Xn);
-    pl[0] = Xn[0]; pl[1] = Xn[4]; pl[2] = Xn[8];
-    pl[3] = Xn[1]; pl[4] = Xn[5]; pl[5] = Xn[2];
+    mul3(Fbi, Dm, t2);
+    mul3_bt(t2, Fbi, Yn);
+    pl[0] = Yn[0]; pl[1] = Yn[4]; pl[2] = Yn[8];
+    pl[3] = Yn[1]; pl[4] = Yn[5]; pl[5] = Yn[2];
     pl[6] = alpha;
   }
   // P = (tau - J p I) F^-T
@@ -204,38 +237,107 @@ __device__ int constitutive(const MatP<T>& m, const T* F, T* pl, T p, T* P) {
 }
 
 // ---------------------------------------------------------------------------
-// stress stage: F from u (corrected gradient), constitutive, PB = P B0
+// LDS-staged tile kernels.  One workgroup per tile; LPP lanes per particle
+// (adjacent lanes of one wavefront) split its neighbour list and reduce with
+// lane shuffles.  Tiles are taken in an XCD-aware order: workgroup b runs on
+// XCD (b mod 8) and gets a tile from a contiguous eighth of the tile list, so
+// neighbouring tiles -- which share most of their windows -- hit one L2.
+template <typename T>
+using vec4 = T __attribute__((ext_vector_type(4)));
+
+constexpr int kLPP = 2;
+
+template <typename T>
+struct TileGeo {
+  const TileDesc* tiles;
+  const uint16_t* ell;
+  int tmax;
+  int64_t n_tiles;
+  const double* X;
+  const T* V;
+  const T* B0;
+  int64_t n;
+  T inv_h, c5;
+};
+
+template <typename T>
+static TileGeo<T> tile_geo(const sph_nbr* nb, int prec) {
+  const Tiling& t = nb->tiling[prec];
+  Geo<T> g = geo<T>(nb);
+  return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5};
+}
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t n_tiles) {
+  const int64_t per = (n_tiles + 7) / 8;
+  return (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_sum(T x) {
+#pragma unroll
+  for (int m = 1; m < kLPP; m <<= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+// stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_stress(Geo<T> g, MatP<T> m, const double* __restrict__ u,
+__global__ __launch_bounds__(256) void k_stress(TileGeo<T> g, MatP<T> m, const double* __restrict__ u,
                                                 T* __restrict__ PB, T* __restrict__ plastic,
                                                 const T* __restrict__ p, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* su = sx + window;
   const int64_t n = g.n;
-  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  double xa[D], ua[D];
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0}, uo[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    xa[k] = g.X[k * n + a];
-    ua[k] = u[k * n + a];
+    xo[k] = g.X[k * n + p0];
+    uo[k] = u[k * n + p0];
   }
+  uint32_t base = 0;
+  for (uint32_t r = 0; r < td.nruns; ++r) {
+    const uint32_t rs = td.run_start[r], rc = td.run_count[r];
+    for (uint32_t i = threadIdx.x; i < rc; i += blockDim.x) {
+      const int64_t gi = (int64_t)rs + i;
+      vec4<T> xv, uv;
+      xv.x = (T)(g.X[gi] - xo[0]);
+      xv.y = (T)(g.X[n + gi] - xo[1]);
+      xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+      xv.w = g.V[gi];
+      uv.x = (T)(u[gi] - uo[0]);
+      uv.y = (T)(u[n + gi] - uo[1]);
+      uv.z = D == 3 ? (T)(u[2 * n + gi] - uo[2]) : T(0);
+      uv.w = T(0);
+      sx[base + i] = xv;
+      su[base + i] = uv;
+    }
+    base += rc;
+  }
+  __syncthreads();
+  const int t = threadIdx.x / kLPP, h = threadIdx.x % kLPP;
+  if ((uint32_t)t >= td.count) return;
+  const int64_t a = p0 + t;
+  const vec4<T> xa = sx[td.own_base + t], ua = su[td.own_base + t];
   T G[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) G[i][k] = T(0);
-  const int64_t j1 = g.off[a + 1];
-  for (int64_t j = g.off[a]; j < j1; ++j) {
-    const uint32_t b = g.idx[j];
-    T d[D], du[D];
-    T r2 = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      d[k] = (T)(xa[k] - g.X[k * n + b]);
-      du[k] = (T)(u[k * n + b] - ua[k]);
-      r2 += d[k] * d[k];
-    }
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b];
+  const uint16_t* ell = g.ell + td.ell_off + t;
+  for (uint32_t j = h; j < td.width; j += kLPP) {
+    const uint32_t l = ell[(int64_t)j * g.tmax];
+    const vec4<T> xb = sx[l], ub = su[l];
+    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const T wd = w * du[i];
@@ -243,7 +345,12 @@ __global__ __launch_bounds__(256) void k_stress(Geo<T> g, MatP<T> m, const doubl
       for (int k = 0; k < D; ++k) G[i][k] += wd * d[k];
     }
   }
-  T F[9] = {T(1), T(0), T(0), T(0), T(1), T(0), T(0), T(0), T(1)};
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) G[i][k] = lane_sum(G[i][k]);
+  if (h != 0) return;
+  T Hm[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T B[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
@@ -256,7 +363,7 @@ __global__ __launch_bounds__(256) void k_stress(Geo<T> g, MatP<T> m, const doubl
       T acc = T(0);
 #pragma unroll
       for (int l = 0; l < D; ++l) acc += G[i][l] * B[l][k];
-      F[i * 3 + k] += acc;
+      Hm[i * 3 + k] = acc;
     }
   T pl[7];
   if (m.model == SPH_MODEL_J2) {
@@ -264,7 +371,7 @@ __global__ __launch_bounds__(256) void k_stress(Geo<T> g, MatP<T> m, const doubl
     for (int i = 0; i < 7; ++i) pl[i] = plastic[i * n + a];
   }
   T P[9];
-  int st = constitutive(m, F, pl, p ? p[a] : T(0), P);
+  int st = constitutive(m, Hm, pl, p ? p[a] : T(0), P);
   if (st) atomicOr(&ctrl->status, st);
   if (m.model == SPH_MODEL_J2) {
 #pragma unroll
@@ -283,42 +390,94 @@ __global__ __launch_bounds__(256) void k_stress(Geo<T> g, MatP<T> m, const doubl
 
 // momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_momentum(Geo<T> g, const T* __restrict__ PB,
+__global__ __launch_bounds__(256) void k_momentum(TileGeo<T> g, const T* __restrict__ PB,
                                                   T* __restrict__ v, T* __restrict__ acc_out,
                                                   const uint8_t* __restrict__ flags, T inv_rho0,
                                                   T dt, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  constexpr int NP = (D * D + 3) / 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* sp = sx + window;  // [window][NP]
   const int64_t n = g.n;
-  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  double xa[D];
-  T Pa[D * D];
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
+  uint32_t base = 0;
+  for (uint32_t r = 0; r < td.nruns; ++r) {
+    const uint32_t rs = td.run_start[r], rc = td.run_count[r];
+    for (uint32_t i = threadIdx.x; i < rc; i += blockDim.x) {
+      const int64_t gi = (int64_t)rs + i;
+      vec4<T> xv;
+      xv.x = (T)(g.X[gi] - xo[0]);
+      xv.y = (T)(g.X[n + gi] - xo[1]);
+      xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+      xv.w = g.V[gi];
+      sx[base + i] = xv;
+      T pb[NP * 4];
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) Pa[k] = PB[k * n + a];
-  T f[D];
+      for (int c = 0; c < NP * 4; ++c) pb[c] = c < D * D ? PB[c * n + gi] : T(0);
 #pragma unroll
-  for (int k = 0; k < D; ++k) f[k] = T(0);
-  const int64_t j1 = g.off[a + 1];
-  for (int64_t j = g.off[a]; j < j1; ++j) {
-    const uint32_t b = g.idx[j];
-    T d[D];
-    T r2 = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      d[k] = (T)(xa[k] - g.X[k * n + b]);
-      r2 += d[k] * d[k];
+      for (int q = 0; q < NP; ++q) {
+        vec4<T> pv;
+        pv.x = pb[4 * q];
+        pv.y = pb[4 * q + 1];
+        pv.z = pb[4 * q + 2];
+        pv.w = pb[4 * q + 3];
+        sp[(base + i) * NP + q] = pv;
+      }
     }
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b];
+    base += rc;
+  }
+  __syncthreads();
+  const int t = threadIdx.x / kLPP, h = threadIdx.x % kLPP;
+  if ((uint32_t)t >= td.count) return;
+  const int64_t a = p0 + t;
+  const uint32_t la = td.own_base + t;
+  const vec4<T> xa = sx[la];
+  T Pa[NP * 4];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    vec4<T> pv = sp[la * NP + q];
+    Pa[4 * q] = pv.x;
+    Pa[4 * q + 1] = pv.y;
+    Pa[4 * q + 2] = pv.z;
+    Pa[4 * q + 3] = pv.w;
+  }
+  T f[3] = {T(0), T(0), T(0)};
+  const uint16_t* ell = g.ell + td.ell_off + t;
+  for (uint32_t j = h; j < td.width; j += kLPP) {
+    const uint32_t l = ell[(int64_t)j * g.tmax];
+    const vec4<T> xb = sx[l];
+    T Pb[NP * 4];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      vec4<T> pv = sp[l * NP + q];
+      Pb[4 * q] = pv.x;
+      Pb[4 * q + 1] = pv.y;
+      Pb[4 * q + 2] = pv.z;
+      Pb[4 * q + 3] = pv.w;
+    }
+    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       T s = T(0);
 #pragma unroll
-      for (int k = 0; k < D; ++k) s += (Pa[i * D + k] + PB[(i * D + k) * n + b]) * d[k];
+      for (int k = 0; k < D; ++k) s += (Pa[i * D + k] + Pb[i * D + k]) * d[k];
       f[i] += w * s;
     }
   }
+#pragma unroll
+  for (int i = 0; i < D; ++i) f[i] = lane_sum(f[i]);
+  if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -328,67 +487,109 @@ __global__ __launch_bounds__(256) void k_momentum(Geo<T> g, const T* __restrict_
   }
 }
 
-// damping: one wavefront per anchor of one colour; levels in order, the pairs
-// of a level in parallel (they share no particle)
+// damping: one wavefront per anchor of one colour.  The anchor's 2^d-cell
+// block (velocities, positions relative to its first particle, volumes,
+// flags) and its packed pair list are staged in LDS; levels run in order, the
+// pairs of one level in parallel (they share no particle); the block is
+// written back at the end.  Anchors of one colour touch disjoint blocks.
 template <typename T, int D>
-__global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restrict__ sa,
-                                             const uint32_t* __restrict__ sb,
-                                             const uint32_t* __restrict__ slev,
-                                             const int64_t* __restrict__ aoff, int64_t a_begin,
-                                             T* v, const uint8_t* __restrict__ flags, T rho0,
-                                             T beta0, Ctrl* ctrl, bool gated) {
+__global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restrict__ dpair,
+                                             const int64_t* __restrict__ aoff,
+                                             const uint32_t* __restrict__ ablk, int64_t a_begin,
+                                             int bmax, int pmax, T* v,
+                                             const uint8_t* __restrict__ flags, T rho0, T beta0,
+                                             Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sv = reinterpret_cast<T*>(smem_raw);   // [D][bmax]
+  T* sx = sv + D * bmax;                    // [D][bmax]
+  T* sV = sx + D * bmax;                    // [bmax]
+  uint32_t* sp = reinterpret_cast<uint32_t*>(sV + bmax);  // [pmax]
+  uint8_t* sf = reinterpret_cast<uint8_t*>(sp + pmax);    // [bmax]
   const int64_t n = g.n;
   const int64_t ai = a_begin + blockIdx.x;
-  const int64_t lo = aoff[ai], hi = aoff[ai + 1];
+  const uint32_t* bl = ablk + 8 * ai;  // (begin, count) x 4 runs
   const int lane = threadIdx.x;
-  int64_t pos = lo;
-  while (pos < hi) {
-    const uint32_t L = slev[pos];
-    const int64_t i = pos + lane;
-    const bool act = (i < hi) && (slev[i] == L);
+  const int64_t ref = bl[0];
+  double xo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + ref];
+  int lb = 0;
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t rb = bl[2 * r], rc = bl[2 * r + 1];
+    for (uint32_t i = lane; i < rc; i += 64) {
+      const int64_t gi = (int64_t)rb + i;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        sv[k * bmax + lb + i] = v[k * n + gi];
+        sx[k * bmax + lb + i] = (T)(g.X[k * n + gi] - xo[k]);
+      }
+      sV[lb + i] = g.V[gi];
+      sf[lb + i] = flags ? flags[gi] : (uint8_t)0;
+    }
+    lb += rc;
+  }
+  const int64_t lo = aoff[ai];
+  const int np = (int)(aoff[ai + 1] - lo);
+  for (int i = lane; i < np; i += 64) sp[i] = dpair[lo + i];
+  __syncthreads();
+  int pos = 0;
+  while (pos < np) {
+    const uint32_t L = sp[pos] >> 24;
+    const int i = pos + lane;
+    const uint32_t w = i < np ? sp[i] : 0xFFFFFFFFu;
+    const bool act = i < np && (w >> 24) == L;
     if (act) {
-      const uint32_t a = sa[i], b = sb[i];
-      const bool fa = flags && (flags[a] & SPH_FLAG_FIXED);
-      const bool fb = flags && (flags[b] & SPH_FLAG_FIXED);
+      const int a = w & 0xFFFu, b = (w >> 12) & 0xFFFu;
+      const bool fa = sf[a] & SPH_FLAG_FIXED, fb = sf[b] & SPH_FLAG_FIXED;
       if (!(fa && fb)) {
         T r2 = T(0);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          T d = (T)(g.X[k * n + a] - g.X[k * n + b]);
-          r2 += d * d;
+          T dd = sx[k * bmax + a] - sx[k * bmax + b];
+          r2 += dd * dd;
         }
-        const T Va = g.V[a], Vb = g.V[b];
+        const T Va = sV[a], Vb = sV[b];
         const T beta = beta0 * Va * Vb * dw_over_r(r2, g.inv_h, g.c5);
         const T ma = rho0 * Va, mb = rho0 * Vb;
         if (!fa && !fb) {
           const T den = T(1) / (ma * mb - beta * (ma + mb));
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            T va = v[k * n + a], vb = v[k * n + b];
+            T va = sv[k * bmax + a], vb = sv[k * bmax + b];
             T delta = beta * (va - vb) * den;
-            v[k * n + a] = va + mb * delta;
-            v[k * n + b] = vb - ma * delta;
+            sv[k * bmax + a] = va + mb * delta;
+            sv[k * bmax + b] = vb - ma * delta;
           }
         } else if (fb) {
           const T den = T(1) / (ma - beta);
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            T va = v[k * n + a], vb = v[k * n + b];
-            v[k * n + a] = va + beta * (va - vb) * den;
+            T va = sv[k * bmax + a], vb = sv[k * bmax + b];
+            sv[k * bmax + a] = va + beta * (va - vb) * den;
           }
         } else {
           const T den = T(1) / (mb - beta);
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            T va = v[k * n + a], vb = v[k * n + b];
-            v[k * n + b] = vb + beta * (vb - va) * den;
+            T va = sv[k * bmax + a], vb = sv[k * bmax + b];
+            sv[k * bmax + b] = vb + beta * (vb - va) * den;
           }
         }
       }
     }
     pos += __popcll(__ballot(act));
     __syncthreads();
+  }
+  lb = 0;
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t rb = bl[2 * r], rc = bl[2 * r + 1];
+    for (uint32_t i = lane; i < rc; i += 64) {
+      const int64_t gi = (int64_t)rb + i;
+#pragma unroll
+      for (int k = 0; k < D; ++k) v[k * n + gi] = sv[k * bmax + lb + i];
+    }
+    lb += rc;
   }
 }
 
@@ -599,17 +800,45 @@ int check_state(const sph_nbr* nb, const sph_state* st, bool need_v) {
   return SPH_OK;
 }
 
+template <typename K>
+static int lds_attr(K kernel, size_t bytes) {
+  if (bytes > 64 * 1024) {
+    SPH_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  }
+  return SPH_OK;
+}
+
 template <typename T, int D>
 static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
                          hipStream_t s, bool gated) {
-  Geo<T> g = geo<T>(nb);
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  TileGeo<T> g = tile_geo<T>(nb, prec);
+  if (g.n_tiles == 0) return SPH_OK;
   MatP<T> mp = matp<T>(m);
-  k_stress<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, mp, st->u, (T*)st->PB, (T*)st->plastic,
-                                                  (const T*)st->p, nb->ctrl, gated);
+  const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
+  const unsigned block = (unsigned)(g.tmax * kLPP);
+  const size_t wm = (size_t)nb->tiling[prec].window_max;
+  const size_t lds_s = wm * 2 * sizeof(vec4<T>);
+  const size_t lds_m = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
+  int rc = lds_attr(k_stress<T, D>, lds_s);
+  if (rc) return rc;
+  rc = lds_attr(k_momentum<T, D>, lds_m);
+  if (rc) return rc;
+  {
+    hipEvent_t pe_ = prof_begin(nb, s);
+    k_stress<T, D><<<grid, block, lds_s, s>>>(g, mp, st->u, (T*)st->PB, (T*)st->plastic,
+                                              (const T*)st->p, nb->ctrl, gated);
+    prof_end(nb, SPH_KERNEL_STRESS, pe_, s);
+  }
   SPH_LAUNCH_CHECK();
-  k_momentum<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (const T*)st->PB, (T*)st->v, (T*)st->acc,
-                                                    st->flags, (T)(1.0 / m->rho0), (T)dt,
-                                                    nb->ctrl, gated);
+  {
+    hipEvent_t pe_ = prof_begin(nb, s);
+    k_momentum<T, D><<<grid, block, lds_m, s>>>(g, (const T*)st->PB, (T*)st->v, (T*)st->acc,
+                                                st->flags, (T)(1.0 / m->rho0), (T)dt, nb->ctrl,
+                                                gated);
+    prof_end(nb, SPH_KERNEL_MOMENTUM, pe_, s);
+  }
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
@@ -636,12 +865,21 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
                      double dt, hipStream_t s, bool gated) {
   Geo<T> g = geo<T>(nb);
   const int ncol = 1 << D;
+  const int bmax = (int)std::max<int64_t>(nb->damp_block_max, 1);
+  const int pmax = (int)std::max<int64_t>(nb->damp_pairs_max, 1);
+  const size_t lds = (size_t)bmax * (2 * D + 1) * sizeof(T) + (size_t)pmax * 4 + (size_t)bmax;
+  int rc = lds_attr(k_damp<T, D>, lds);
+  if (rc) return rc;
   for (int col = 0; col < ncol; ++col) {
     int64_t a0 = nb->color_off[col], a1 = nb->color_off[col + 1];
     if (a1 <= a0) continue;
-    k_damp<T, D><<<(unsigned)(a1 - a0), 64, 0, s>>>(g, nb->sa, nb->sb, nb->slev, nb->aoff, a0,
-                                                     (T*)st->v, st->flags, (T)m->rho0,
-                                                     (T)(2.0 * eta * dt), nb->ctrl, gated);
+    {
+      hipEvent_t pe_ = prof_begin(nb, s);
+      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, nb->aoff, nb->ablk, a0, bmax,
+                                                       pmax, (T*)st->v, st->flags, (T)m->rho0,
+                                                       (T)(2.0 * eta * dt), nb->ctrl, gated);
+      prof_end(nb, SPH_KERNEL_DAMPING, pe_, s);
+    }
     SPH_LAUNCH_CHECK();
   }
   return SPH_OK;
@@ -660,9 +898,13 @@ template <typename T, int D>
 static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
                    double* ke_out, hipStream_t s, bool gated) {
   int64_t nb_ = std::min<int64_t>(kKeMaxBlocks, std::max<int64_t>(1, (nb->n + kKeThreads - 1) / kKeThreads));
-  k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
+  {
+    hipEvent_t pe_ = prof_begin(nb, s);
+    k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
                                                        nb->V, m->rho0, dt, nb->ctrl,
                                                        nb->ke_partial, ke_out, gated);
+    prof_end(nb, SPH_KERNEL_DRIFT_KE, pe_, s);
+  }
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
@@ -699,11 +941,19 @@ template <typename T, int D>
 static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double Dc,
                        double dt, double c_bc, hipStream_t s) {
   Geo<T> g = geo<T>(nb);
-  k_diff_grad<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc);
+  {
+    hipEvent_t pe_ = prof_begin(nb, s);
+    k_diff_grad<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc);
+    prof_end(nb, SPH_KERNEL_DIFF_GRAD, pe_, s);
+  }
   SPH_LAUNCH_CHECK();
-  k_diff_div<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
+  {
+    hipEvent_t pe_ = prof_begin(nb, s);
+    k_diff_div<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
                                                     st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
                                                     (T)m->c0);
+    prof_end(nb, SPH_KERNEL_DIFF_DIV, pe_, s);
+  }
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
