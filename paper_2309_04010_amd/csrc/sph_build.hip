@@ -569,7 +569,8 @@ __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __
                             const uint32_t* __restrict__ sa, const uint32_t* __restrict__ sb,
                             const uint32_t* __restrict__ slev, const uint32_t* __restrict__ cs,
                             Grid g, int64_t n_anchors, uint32_t* __restrict__ dpair,
-                            uint32_t* __restrict__ ablk, unsigned long long* bmax,
+                            uint16_t* __restrict__ dlev, uint32_t* __restrict__ ablk,
+                            unsigned long long* bmax,
                             unsigned long long* pmax, int32_t* err) {
   int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (ai >= n_anchors) return;
@@ -599,7 +600,8 @@ __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __
       atomicOr(err, 16);
       continue;
     }
-    dpair[i] = (uint32_t)loc[0] | ((uint32_t)loc[1] << kDampLocBits) | (slev[i] << (2 * kDampLocBits));
+    dpair[i] = (uint32_t)loc[0] | ((uint32_t)loc[1] << kDampLocBits);
+    dlev[i] = (uint16_t)slev[i];
   }
 }
 
@@ -695,7 +697,7 @@ static void free_nbr(sph_nbr* h) {
   if (!h) return;
   void* ptrs[] = {h->key, h->perm, h->cell_start, h->nbr_off, h->nbr_idx, h->X,   h->V,
                   h->B0,  h->Vf,   h->B0f,        h->sa,      h->sb,      h->slev, h->akey,
-                  h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk,
+                  h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk, h->dlev,
                   h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -903,14 +905,16 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   {
     unsigned long long* mx = nullptr;
     int32_t* derr = nullptr;
-    if ((rc_ = dalloc(&nb->dpair, npu)) || (rc_ = dalloc(&nb->ablk, 8 * std::max<int64_t>(base, 1))) ||
+    if ((rc_ = dalloc(&nb->dpair, npu)) || (rc_ = dalloc(&nb->dlev, npu)) ||
+        (rc_ = dalloc(&nb->ablk, 8 * std::max<int64_t>(base, 1))) ||
         (rc_ = dalloc(&mx, 2)) || (rc_ = dalloc(&derr, 1)))
       return rc_;
     SPH_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned long long), s));
     SPH_HIP(hipMemsetAsync(derr, 0, sizeof(int32_t), s));
     if (base > 0) {
       k_damp_pack<<<nblocks(base, 64), 64, 0, s>>>(nb->akey, nb->aoff, nb->sa, nb->sb, nb->slev,
-                                                   nb->cell_start, g, base, nb->dpair, nb->ablk,
+                                                   nb->cell_start, g, base, nb->dpair, nb->dlev,
+                                                   nb->ablk,
                                                    mx, mx + 1, derr);
       SPH_LAUNCH_CHECK();
     }
@@ -928,6 +932,15 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
     }
     nb->damp_block_max = (int64_t)hm[0];
     nb->damp_pairs_max = (int64_t)hm[1];
+    // LDS of one anchor in the FP64 sweep: block (v, X, V: 7 doubles, flags)
+    // and pairs (word, level, two coefficients)
+    const int64_t need = nb->damp_block_max * (7 * 8 + 1) + nb->damp_pairs_max * (4 + 2 + 16);
+    if (need > kDampLdsBudget) {
+      set_error("an anchor block needs %lld B of LDS for the damping sweep (limit %lld): "
+                "neighbourhoods this dense are not supported", (long long)need,
+                (long long)kDampLdsBudget);
+      return SPH_E_CAPACITY;
+    }
   }
 
   // row tiles for the LDS-staged gathers, one tiling per precision

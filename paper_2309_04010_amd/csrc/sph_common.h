@@ -63,7 +63,7 @@ struct Prof {
 };
 
 constexpr int kKeThreads = 256;
-constexpr int kKeMaxBlocks = 2048;
+constexpr int kKeMaxBlocks = 256;
 
 // A tile is a run of consecutive sorted particles inside one row of cells
 // (fixed y, z).  Its neighbours all lie in the "window": the 3^(d-1) rows
@@ -88,11 +88,12 @@ struct Tiling {
   uint16_t* ell = nullptr;    // device
 };
 
-// damping pair word: a_loc | b_loc << 12 | level << 24 (locals inside the
-// anchor's 2^d-cell block, in ascending sorted order)
-constexpr int kDampLocBits = 12;
+// damping pair word: a_loc | b_loc << 16 (locals inside the anchor's
+// 2^d-cell block, in ascending sorted order); levels kept beside it (16 bit)
+constexpr int kDampLocBits = 16;
 constexpr int kDampMaxLocal = 1 << kDampLocBits;
-constexpr int kDampMaxLevel = 256;
+constexpr int kDampMaxLevel = 1 << 16;
+constexpr int64_t kDampLdsBudget = 159 * 1024;  // gfx950: 160 KB of LDS per workgroup
 
 }  // namespace sph
 
@@ -123,6 +124,7 @@ struct sph_nbr {
   int64_t* aoff = nullptr;
   uint32_t* anlev = nullptr;
   uint32_t* dpair = nullptr;         // [n_upairs] packed damping pairs (canonical order)
+  uint16_t* dlev = nullptr;          // [n_upairs] their levels
   uint32_t* ablk = nullptr;          // [n_anchors][8] anchor block runs (begin, count) x 4
   int64_t damp_block_max = 0;        // largest anchor block (particles)
   int64_t damp_pairs_max = 0;        // largest pair count of one anchor

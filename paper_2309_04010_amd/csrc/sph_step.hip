@@ -489,11 +489,17 @@ __global__ __launch_bounds__(256) void k_momentum(TileGeo<T> g, const T* __restr
 
 // damping: one wavefront per anchor of one colour.  The anchor's 2^d-cell
 // block (velocities, positions relative to its first particle, volumes,
-// flags) and its packed pair list are staged in LDS; levels run in order, the
-// pairs of one level in parallel (they share no particle); the block is
-// written back at the end.  Anchors of one colour touch disjoint blocks.
+// flags) and its pair list are staged in LDS.  A parallel prologue turns each
+// pair into two coefficients, so that the implicit pair update is
+//   v_a += kA (v_a - v_b),  v_b -= kB (v_a - v_b)
+// (both free: kA = m_b beta / (m_a m_b - beta (m_a + m_b)), kB = m_a beta / (same);
+// b fixed: kA = beta / (m_a - beta), kB = 0; a fixed: kA = 0, kB = beta / (m_b - beta)).
+// The serial part -- levels in order, the pairs of a level in parallel (they
+// share no particle) -- then only reads and writes velocities in LDS.  The
+// block is written back at the end; anchors of one colour touch disjoint blocks.
 template <typename T, int D>
 __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restrict__ dpair,
+                                             const uint16_t* __restrict__ dlev,
                                              const int64_t* __restrict__ aoff,
                                              const uint32_t* __restrict__ ablk, int64_t a_begin,
                                              int bmax, int pmax, T* v,
@@ -504,8 +510,11 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
   T* sv = reinterpret_cast<T*>(smem_raw);   // [D][bmax]
   T* sx = sv + D * bmax;                    // [D][bmax]
   T* sV = sx + D * bmax;                    // [bmax]
-  uint32_t* sp = reinterpret_cast<uint32_t*>(sV + bmax);  // [pmax]
-  uint8_t* sf = reinterpret_cast<uint8_t*>(sp + pmax);    // [bmax]
+  T* kA = sV + bmax;                        // [pmax]
+  T* kB = kA + pmax;                        // [pmax]
+  uint32_t* sp = reinterpret_cast<uint32_t*>(kB + pmax);  // [pmax]
+  uint16_t* sl = reinterpret_cast<uint16_t*>(sp + pmax);  // [pmax]
+  uint8_t* sf = reinterpret_cast<uint8_t*>(sl + pmax);    // [bmax]
   const int64_t n = g.n;
   const int64_t ai = a_begin + blockIdx.x;
   const uint32_t* bl = ablk + 8 * ai;  // (begin, count) x 4 runs
@@ -531,51 +540,53 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
   }
   const int64_t lo = aoff[ai];
   const int np = (int)(aoff[ai + 1] - lo);
-  for (int i = lane; i < np; i += 64) sp[i] = dpair[lo + i];
+  for (int i = lane; i < np; i += 64) {
+    sp[i] = dpair[lo + i];
+    sl[i] = dlev[lo + i];
+  }
+  __syncthreads();
+  for (int i = lane; i < np; i += 64) {
+    const uint32_t w = sp[i];
+    const int a = w & 0xFFFFu, b = w >> 16;
+    const bool fa = sf[a] & SPH_FLAG_FIXED, fb = sf[b] & SPH_FLAG_FIXED;
+    T r2 = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T dd = sx[k * bmax + a] - sx[k * bmax + b];
+      r2 += dd * dd;
+    }
+    const T Va = sV[a], Vb = sV[b];
+    const T beta = beta0 * Va * Vb * dw_over_r(r2, g.inv_h, g.c5);
+    const T ma = rho0 * Va, mb = rho0 * Vb;
+    T ka = T(0), kb = T(0);
+    if (!fa && !fb) {
+      const T q = beta / (ma * mb - beta * (ma + mb));
+      ka = mb * q;
+      kb = ma * q;
+    } else if (fb && !fa) {
+      ka = beta / (ma - beta);
+    } else if (fa && !fb) {
+      kb = beta / (mb - beta);
+    }
+    kA[i] = ka;
+    kB[i] = kb;
+  }
   __syncthreads();
   int pos = 0;
   while (pos < np) {
-    const uint32_t L = sp[pos] >> 24;
     const int i = pos + lane;
-    const uint32_t w = i < np ? sp[i] : 0xFFFFFFFFu;
-    const bool act = i < np && (w >> 24) == L;
+    const uint32_t L = sl[pos];
+    const bool act = i < np && sl[i] == L;
     if (act) {
-      const int a = w & 0xFFFu, b = (w >> 12) & 0xFFFu;
-      const bool fa = sf[a] & SPH_FLAG_FIXED, fb = sf[b] & SPH_FLAG_FIXED;
-      if (!(fa && fb)) {
-        T r2 = T(0);
+      const uint32_t w = sp[i];
+      const int a = w & 0xFFFFu, b = w >> 16;
+      const T ka = kA[i], kb = kB[i];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          T dd = sx[k * bmax + a] - sx[k * bmax + b];
-          r2 += dd * dd;
-        }
-        const T Va = sV[a], Vb = sV[b];
-        const T beta = beta0 * Va * Vb * dw_over_r(r2, g.inv_h, g.c5);
-        const T ma = rho0 * Va, mb = rho0 * Vb;
-        if (!fa && !fb) {
-          const T den = T(1) / (ma * mb - beta * (ma + mb));
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            T va = sv[k * bmax + a], vb = sv[k * bmax + b];
-            T delta = beta * (va - vb) * den;
-            sv[k * bmax + a] = va + mb * delta;
-            sv[k * bmax + b] = vb - ma * delta;
-          }
-        } else if (fb) {
-          const T den = T(1) / (ma - beta);
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            T va = sv[k * bmax + a], vb = sv[k * bmax + b];
-            sv[k * bmax + a] = va + beta * (va - vb) * den;
-          }
-        } else {
-          const T den = T(1) / (mb - beta);
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            T va = sv[k * bmax + a], vb = sv[k * bmax + b];
-            sv[k * bmax + b] = vb + beta * (vb - va) * den;
-          }
-        }
+      for (int k = 0; k < D; ++k) {
+        const T va = sv[k * bmax + a], vb = sv[k * bmax + b];
+        const T dv = va - vb;
+        sv[k * bmax + a] = va + ka * dv;
+        sv[k * bmax + b] = vb - kb * dv;
       }
     }
     pos += __popcll(__ballot(act));
@@ -867,7 +878,8 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
   const int ncol = 1 << D;
   const int bmax = (int)std::max<int64_t>(nb->damp_block_max, 1);
   const int pmax = (int)std::max<int64_t>(nb->damp_pairs_max, 1);
-  const size_t lds = (size_t)bmax * (2 * D + 1) * sizeof(T) + (size_t)pmax * 4 + (size_t)bmax;
+  const size_t lds = (size_t)bmax * (2 * D + 1) * sizeof(T) + (size_t)pmax * (2 * sizeof(T) + 4 + 2) +
+                     (size_t)bmax;
   int rc = lds_attr(k_damp<T, D>, lds);
   if (rc) return rc;
   for (int col = 0; col < ncol; ++col) {
@@ -875,7 +887,7 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
     if (a1 <= a0) continue;
     {
       hipEvent_t pe_ = prof_begin(nb, s);
-      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, nb->aoff, nb->ablk, a0, bmax,
+      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, nb->dlev, nb->aoff, nb->ablk, a0, bmax,
                                                        pmax, (T*)st->v, st->flags, (T)m->rho0,
                                                        (T)(2.0 * eta * dt), nb->ctrl, gated);
       prof_end(nb, SPH_KERNEL_DAMPING, pe_, s);

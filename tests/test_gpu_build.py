@@ -22,7 +22,7 @@ CASES = [
     ("jitter3d-11x9x7", lambda: (3, *jittered((11, 9, 7), jitter=0.2, seed=2))),
     ("plate3d-40x40x4", lambda: (lambda c: (3, c.X, c.V, c.h))(cases.plate3d(nx=40, ny=40))),
     ("random3d", lambda: (3, np.random.default_rng(4).uniform(0, 9e-3, (3, 3000)),
-                          np.full(3000, 1e-9), 1.6e-3)),
+                          np.full(3000, 2.4e-10), 1.0e-3)),
     ("tiny2d-2x2", lambda: (2, *jittered((2, 2), jitter=0.0))),
     ("line3d-1cell", lambda: (3, *jittered((3, 3, 3), jitter=0.05, seed=9))),
 ]
