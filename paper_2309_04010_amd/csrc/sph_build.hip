@@ -564,17 +564,24 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
   }
 }
 
-// damping: pack each canonical pair as (a_loc, b_loc, level) inside its anchor block
+// damping: pack each canonical pair as (a_loc, b_loc) inside its anchor block
+// (level beside it), record the block runs, the per-colour maxima that size
+// each pass's LDS, and the pair geometry 2 V_a V_b (dW/dr)/r
 __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __restrict__ aoff,
                             const uint32_t* __restrict__ sa, const uint32_t* __restrict__ sb,
                             const uint32_t* __restrict__ slev, const uint32_t* __restrict__ cs,
-                            Grid g, int64_t n_anchors, uint32_t* __restrict__ dpair,
-                            uint16_t* __restrict__ dlev, uint32_t* __restrict__ ablk,
-                            unsigned long long* bmax,
+                            const double* __restrict__ X, const double* __restrict__ V,
+                            double inv_h, double c5, Grid g, int64_t n, int64_t n_anchors,
+                            uint32_t* __restrict__ dpair, uint16_t* __restrict__ dlev,
+                            float* __restrict__ dgeo32, double* __restrict__ dgeo64,
+                            uint32_t* __restrict__ ablk, unsigned long long* bmax,
                             unsigned long long* pmax, int32_t* err) {
   int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (ai >= n_anchors) return;
   Block blk = anchor_block(akey[ai], g, cs);
+  int64_t A[3];
+  key_coords(akey[ai], g, A);
+  const int col = (int)((A[0] & 1) | ((A[1] & 1) << 1) | ((A[2] & 1) << 2));
   int64_t lbase[4], acc = 0;
   for (int r = 0; r < 4; ++r) {
     ablk[8 * ai + 2 * r] = r < blk.nr ? (uint32_t)blk.beg[r] : 0u;
@@ -584,8 +591,8 @@ __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __
     lbase[r] = acc;
     acc += blk.end[r] - blk.beg[r];
   }
-  atomicMax(bmax, (unsigned long long)acc);
-  atomicMax(pmax, (unsigned long long)(aoff[ai + 1] - aoff[ai]));
+  atomicMax(bmax + col, (unsigned long long)acc);
+  atomicMax(pmax + col, (unsigned long long)(aoff[ai + 1] - aoff[ai]));
   if (acc > kDampMaxLocal) {
     atomicOr(err, 8);
     return;
@@ -602,6 +609,16 @@ __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __
     }
     dpair[i] = (uint32_t)loc[0] | ((uint32_t)loc[1] << kDampLocBits);
     dlev[i] = (uint16_t)slev[i];
+    double r2 = 0.0;
+    for (int k = 0; k < g.dim; ++k) {
+      double d = X[k * n + pp[0]] - X[k * n + pp[1]];
+      r2 += d * d;
+    }
+    double q = sqrt(r2) * inv_h;
+    double t = 1.0 - 0.5 * q;
+    double geo = 2.0 * V[pp[0]] * V[pp[1]] * (c5 * t * t * t);
+    dgeo64[i] = geo;
+    dgeo32[i] = (float)geo;
   }
 }
 
@@ -698,6 +715,7 @@ static void free_nbr(sph_nbr* h) {
   void* ptrs[] = {h->key, h->perm, h->cell_start, h->nbr_off, h->nbr_idx, h->X,   h->V,
                   h->B0,  h->Vf,   h->B0f,        h->sa,      h->sb,      h->slev, h->akey,
                   h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk, h->dlev,
+                  h->dgeo32, h->dgeo64,
                   h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -906,21 +924,22 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
     unsigned long long* mx = nullptr;
     int32_t* derr = nullptr;
     if ((rc_ = dalloc(&nb->dpair, npu)) || (rc_ = dalloc(&nb->dlev, npu)) ||
+        (rc_ = dalloc(&nb->dgeo32, npu)) || (rc_ = dalloc(&nb->dgeo64, npu)) ||
         (rc_ = dalloc(&nb->ablk, 8 * std::max<int64_t>(base, 1))) ||
-        (rc_ = dalloc(&mx, 2)) || (rc_ = dalloc(&derr, 1)))
+        (rc_ = dalloc(&mx, 16)) || (rc_ = dalloc(&derr, 1)))
       return rc_;
-    SPH_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned long long), s));
+    SPH_HIP(hipMemsetAsync(mx, 0, 16 * sizeof(unsigned long long), s));
     SPH_HIP(hipMemsetAsync(derr, 0, sizeof(int32_t), s));
     if (base > 0) {
-      k_damp_pack<<<nblocks(base, 64), 64, 0, s>>>(nb->akey, nb->aoff, nb->sa, nb->sb, nb->slev,
-                                                   nb->cell_start, g, base, nb->dpair, nb->dlev,
-                                                   nb->ablk,
-                                                   mx, mx + 1, derr);
+      k_damp_pack<<<nblocks(base, 64), 64, 0, s>>>(
+          nb->akey, nb->aoff, nb->sa, nb->sb, nb->slev, nb->cell_start, nb->X, nb->V, nb->inv_h,
+          nb->c5, g, n, base, nb->dpair, nb->dlev, nb->dgeo32, nb->dgeo64, nb->ablk, mx, mx + 8,
+          derr);
       SPH_LAUNCH_CHECK();
     }
-    unsigned long long hm[2] = {0, 0};
+    unsigned long long hm[16] = {0};
     int32_t he = 0;
-    SPH_HIP(hipMemcpyAsync(hm, mx, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(hm, mx, 16 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     SPH_HIP(hipMemcpyAsync(&he, derr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     SPH_HIP(hipStreamSynchronize(s));
     hipFree(mx);
@@ -930,11 +949,18 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
                 kDampMaxLevel);
       return SPH_E_CAPACITY;
     }
-    nb->damp_block_max = (int64_t)hm[0];
-    nb->damp_pairs_max = (int64_t)hm[1];
-    // LDS of one anchor in the FP64 sweep: block (v, X, V: 7 doubles, flags)
-    // and pairs (word, level, two coefficients)
-    const int64_t need = nb->damp_block_max * (7 * 8 + 1) + nb->damp_pairs_max * (4 + 2 + 16);
+    nb->damp_block_max = 0;
+    nb->damp_pairs_max = 0;
+    for (int c = 0; c < 8; ++c) {
+      nb->damp_bmax[c] = (int64_t)hm[c];
+      nb->damp_pmax[c] = (int64_t)hm[8 + c];
+      nb->damp_block_max = std::max(nb->damp_block_max, nb->damp_bmax[c]);
+      nb->damp_pairs_max = std::max(nb->damp_pairs_max, nb->damp_pmax[c]);
+    }
+    // LDS of one anchor in the FP64 sweep: block (v, inverse mass) and pairs
+    // (word, coefficient), plus the level offsets
+    const int64_t need = nb->damp_block_max * (4 * 8) + nb->damp_pairs_max * (4 + 8) +
+                         4 * (kDampMaxLevel + 1);
     if (need > kDampLdsBudget) {
       set_error("an anchor block needs %lld B of LDS for the damping sweep (limit %lld): "
                 "neighbourhoods this dense are not supported", (long long)need,

@@ -63,7 +63,8 @@ struct Prof {
 };
 
 constexpr int kKeThreads = 256;
-constexpr int kKeMaxBlocks = 256;
+constexpr int kKeItems = 4;             // particles per thread in the drift kernel
+constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (16.7M particles)
 
 // A tile is a run of consecutive sorted particles inside one row of cells
 // (fixed y, z).  Its neighbours all lie in the "window": the 3^(d-1) rows
@@ -92,7 +93,7 @@ struct Tiling {
 // 2^d-cell block, in ascending sorted order); levels kept beside it (16 bit)
 constexpr int kDampLocBits = 16;
 constexpr int kDampMaxLocal = 1 << kDampLocBits;
-constexpr int kDampMaxLevel = 1 << 16;
+constexpr int kDampMaxLevel = 255;      // levels of one anchor (offsets held in 4 registers)
 constexpr int64_t kDampLdsBudget = 159 * 1024;  // gfx950: 160 KB of LDS per workgroup
 
 }  // namespace sph
@@ -128,6 +129,10 @@ struct sph_nbr {
   uint32_t* ablk = nullptr;          // [n_anchors][8] anchor block runs (begin, count) x 4
   int64_t damp_block_max = 0;        // largest anchor block (particles)
   int64_t damp_pairs_max = 0;        // largest pair count of one anchor
+  int64_t damp_bmax[8] = {0};        // the same, per colour (sizes each pass's LDS)
+  int64_t damp_pmax[8] = {0};
+  float* dgeo32 = nullptr;           // [n_upairs] 2 V_a V_b (dW/dr)/r per pair
+  double* dgeo64 = nullptr;
   sph::Tiling tiling[2];             // [SPH_F32], [SPH_F64]
   // inner-loop control
   sph::Ctrl* ctrl = nullptr;         // device

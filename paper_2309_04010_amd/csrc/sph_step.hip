@@ -245,7 +245,10 @@ __device__ int constitutive(const MatP<T>& m, const T* H, T* pl, T p, T* P) {
 template <typename T>
 using vec4 = T __attribute__((ext_vector_type(4)));
 
-constexpr int kLPP = 2;
+// lanes per particle in the tile kernels (measured on the 1M-particle plate:
+// stress is fastest with 2, momentum -- more LDS traffic per pair -- with 4)
+constexpr int kLppStress = 2;
+constexpr int kLppMomentum = 4;
 
 template <typename T>
 struct TileGeo {
@@ -272,16 +275,16 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t n_tiles) {
   return (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
 }
 
-template <typename T>
+template <int LPP, typename T>
 __device__ __forceinline__ T lane_sum(T x) {
 #pragma unroll
-  for (int m = 1; m < kLPP; m <<= 1) x += __shfl_xor(x, m, 64);
+  for (int m = 1; m < LPP; m <<= 1) x += __shfl_xor(x, m, 64);
   return x;
 }
 
 // stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_stress(TileGeo<T> g, MatP<T> m, const double* __restrict__ u,
+__global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<T> m, const double* __restrict__ u,
                                                 T* __restrict__ PB, T* __restrict__ plastic,
                                                 const T* __restrict__ p, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(256) void k_stress(TileGeo<T> g, MatP<T> m, const d
     base += rc;
   }
   __syncthreads();
-  const int t = threadIdx.x / kLPP, h = threadIdx.x % kLPP;
+  const int t = threadIdx.x / kLppStress, h = threadIdx.x % kLppStress;
   if ((uint32_t)t >= td.count) return;
   const int64_t a = p0 + t;
   const vec4<T> xa = sx[td.own_base + t], ua = su[td.own_base + t];
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(256) void k_stress(TileGeo<T> g, MatP<T> m, const d
 #pragma unroll
     for (int k = 0; k < D; ++k) G[i][k] = T(0);
   const uint16_t* ell = g.ell + td.ell_off + t;
-  for (uint32_t j = h; j < td.width; j += kLPP) {
+  for (uint32_t j = h; j < td.width; j += kLppStress) {
     const uint32_t l = ell[(int64_t)j * g.tmax];
     const vec4<T> xb = sx[l], ub = su[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(256) void k_stress(TileGeo<T> g, MatP<T> m, const d
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int k = 0; k < D; ++k) G[i][k] = lane_sum(G[i][k]);
+    for (int k = 0; k < D; ++k) G[i][k] = lane_sum<kLppStress>(G[i][k]);
   if (h != 0) return;
   T Hm[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T B[D][D];
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(256) void k_stress(TileGeo<T> g, MatP<T> m, const d
 
 // momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_momentum(TileGeo<T> g, const T* __restrict__ PB,
+__global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g, const T* __restrict__ PB,
                                                   T* __restrict__ v, T* __restrict__ acc_out,
                                                   const uint8_t* __restrict__ flags, T inv_rho0,
                                                   T dt, Ctrl* ctrl, bool gated) {
@@ -435,7 +438,7 @@ __global__ __launch_bounds__(256) void k_momentum(TileGeo<T> g, const T* __restr
     base += rc;
   }
   __syncthreads();
-  const int t = threadIdx.x / kLPP, h = threadIdx.x % kLPP;
+  const int t = threadIdx.x / kLppMomentum, h = threadIdx.x % kLppMomentum;
   if ((uint32_t)t >= td.count) return;
   const int64_t a = p0 + t;
   const uint32_t la = td.own_base + t;
@@ -451,7 +454,7 @@ __global__ __launch_bounds__(256) void k_momentum(TileGeo<T> g, const T* __restr
   }
   T f[3] = {T(0), T(0), T(0)};
   const uint16_t* ell = g.ell + td.ell_off + t;
-  for (uint32_t j = h; j < td.width; j += kLPP) {
+  for (uint32_t j = h; j < td.width; j += kLppMomentum) {
     const uint32_t l = ell[(int64_t)j * g.tmax];
     const vec4<T> xb = sx[l];
     T Pb[NP * 4];
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(256) void k_momentum(TileGeo<T> g, const T* __restr
     }
   }
 #pragma unroll
-  for (int i = 0; i < D; ++i) f[i] = lane_sum(f[i]);
+  for (int i = 0; i < D; ++i) f[i] = lane_sum<kLppMomentum>(f[i]);
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
 #pragma unroll
@@ -487,100 +490,90 @@ __global__ __launch_bounds__(256) void k_momentum(TileGeo<T> g, const T* __restr
   }
 }
 
-// damping: one wavefront per anchor of one colour.  The anchor's 2^d-cell
-// block (velocities, positions relative to its first particle, volumes,
-// flags) and its pair list are staged in LDS.  A parallel prologue turns each
-// pair into two coefficients, so that the implicit pair update is
-//   v_a += kA (v_a - v_b),  v_b -= kB (v_a - v_b)
-// (both free: kA = m_b beta / (m_a m_b - beta (m_a + m_b)), kB = m_a beta / (same);
-// b fixed: kA = beta / (m_a - beta), kB = 0; a fixed: kA = 0, kB = beta / (m_b - beta)).
-// The serial part -- levels in order, the pairs of a level in parallel (they
-// share no particle) -- then only reads and writes velocities in LDS.  The
-// block is written back at the end; anchors of one colour touch disjoint blocks.
+// damping: one wavefront per anchor of one colour.  The implicit update of
+// one pair, with inverse masses i_a, i_b (zero for a fixed particle, which
+// then acts as infinite mass) and beta = eta dt g_ab <= 0, g_ab = 2 V_a V_b
+// (dW/dr)/r (precomputed per pair):
+//   v_ab' = v_ab / (1 - beta (i_a + i_b)),  v_a += beta i_a v_ab',  v_b -= beta i_b v_ab',
+// i.e. v_a += i_a q (v_a - v_b), v_b -= i_b q (v_a - v_b) with
+// q = beta / (1 - beta (i_a + i_b)).  The anchor's 2^d-cell block
+// (velocities, inverse masses) and its pairs live in LDS; a parallel prologue
+// computes q per pair and the offsets of the levels, which are then held in
+// registers.  The levels run in order, the pairs of one level in parallel
+// (they share no particle), with only LDS reads and writes of velocities on
+// the serial path.  The block is written back at the end; anchors of one
+// colour touch disjoint blocks.
 template <typename T, int D>
 __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restrict__ dpair,
                                              const uint16_t* __restrict__ dlev,
+                                             const T* __restrict__ dgeo,
                                              const int64_t* __restrict__ aoff,
                                              const uint32_t* __restrict__ ablk, int64_t a_begin,
                                              int bmax, int pmax, T* v,
-                                             const uint8_t* __restrict__ flags, T rho0, T beta0,
-                                             Ctrl* ctrl, bool gated) {
+                                             const uint8_t* __restrict__ flags, T inv_rho0,
+                                             T eta_dt, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sv = reinterpret_cast<T*>(smem_raw);   // [D][bmax]
-  T* sx = sv + D * bmax;                    // [D][bmax]
-  T* sV = sx + D * bmax;                    // [bmax]
-  T* kA = sV + bmax;                        // [pmax]
-  T* kB = kA + pmax;                        // [pmax]
-  uint32_t* sp = reinterpret_cast<uint32_t*>(kB + pmax);  // [pmax]
-  uint16_t* sl = reinterpret_cast<uint16_t*>(sp + pmax);  // [pmax]
-  uint8_t* sf = reinterpret_cast<uint8_t*>(sl + pmax);    // [bmax]
+  T* si = sv + D * bmax;                    // [bmax] inverse masses
+  T* sq = si + bmax;                        // [pmax]
+  uint32_t* sp = reinterpret_cast<uint32_t*>(sq + pmax);  // [pmax]
+  uint32_t* soff = sp + pmax;                             // [kDampMaxLevel + 1]
+  __shared__ int s_nlev;
   const int64_t n = g.n;
   const int64_t ai = a_begin + blockIdx.x;
   const uint32_t* bl = ablk + 8 * ai;  // (begin, count) x 4 runs
   const int lane = threadIdx.x;
-  const int64_t ref = bl[0];
-  double xo[3] = {0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + ref];
   int lb = 0;
   for (int r = 0; r < 4; ++r) {
     const uint32_t rb = bl[2 * r], rc = bl[2 * r + 1];
     for (uint32_t i = lane; i < rc; i += 64) {
       const int64_t gi = (int64_t)rb + i;
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        sv[k * bmax + lb + i] = v[k * n + gi];
-        sx[k * bmax + lb + i] = (T)(g.X[k * n + gi] - xo[k]);
-      }
-      sV[lb + i] = g.V[gi];
-      sf[lb + i] = flags ? flags[gi] : (uint8_t)0;
+      for (int k = 0; k < D; ++k) sv[k * bmax + lb + i] = v[k * n + gi];
+      const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
+      si[lb + i] = fixed ? T(0) : inv_rho0 / g.V[gi];
     }
     lb += rc;
   }
   const int64_t lo = aoff[ai];
   const int np = (int)(aoff[ai + 1] - lo);
   for (int i = lane; i < np; i += 64) {
+    const uint32_t L = dlev[lo + i];
+    if (i == 0 || dlev[lo + i - 1] != L) soff[L] = (uint32_t)i;
+    if (i == np - 1) {
+      soff[L + 1] = (uint32_t)np;
+      s_nlev = (int)L + 1;
+    }
     sp[i] = dpair[lo + i];
-    sl[i] = dlev[lo + i];
+    sq[i] = dgeo[lo + i];
   }
   __syncthreads();
   for (int i = lane; i < np; i += 64) {
     const uint32_t w = sp[i];
-    const int a = w & 0xFFFFu, b = w >> 16;
-    const bool fa = sf[a] & SPH_FLAG_FIXED, fb = sf[b] & SPH_FLAG_FIXED;
-    T r2 = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      T dd = sx[k * bmax + a] - sx[k * bmax + b];
-      r2 += dd * dd;
-    }
-    const T Va = sV[a], Vb = sV[b];
-    const T beta = beta0 * Va * Vb * dw_over_r(r2, g.inv_h, g.c5);
-    const T ma = rho0 * Va, mb = rho0 * Vb;
-    T ka = T(0), kb = T(0);
-    if (!fa && !fb) {
-      const T q = beta / (ma * mb - beta * (ma + mb));
-      ka = mb * q;
-      kb = ma * q;
-    } else if (fb && !fa) {
-      ka = beta / (ma - beta);
-    } else if (fa && !fb) {
-      kb = beta / (mb - beta);
-    }
-    kA[i] = ka;
-    kB[i] = kb;
+    const T beta = eta_dt * sq[i];
+    sq[i] = beta / (T(1) - beta * (si[w & 0xFFFFu] + si[w >> 16]));
   }
+  const int nlev = s_nlev;
+  // level offsets in registers: lane l holds soff[64 c + l]
+  uint32_t r0 = lane <= nlev ? soff[lane] : 0u;
+  uint32_t r1 = 64 + lane <= nlev ? soff[64 + lane] : 0u;
+  uint32_t r2 = 128 + lane <= nlev ? soff[128 + lane] : 0u;
+  uint32_t r3 = 192 + lane <= nlev ? soff[192 + lane] : 0u;
   __syncthreads();
-  int pos = 0;
-  while (pos < np) {
-    const int i = pos + lane;
-    const uint32_t L = sl[pos];
-    const bool act = i < np && sl[i] == L;
-    if (act) {
+  auto level_off = [&](int L) -> int {
+    const uint32_t rr = L < 64 ? r0 : (L < 128 ? r1 : (L < 192 ? r2 : r3));
+    return __builtin_amdgcn_readlane((int)rr, L & 63);
+  };
+  int hi = level_off(0);
+  for (int L = 0; L < nlev; ++L) {
+    const int lo_l = hi;
+    hi = level_off(L + 1);
+    for (int i = lo_l + lane; i < hi; i += 64) {
       const uint32_t w = sp[i];
       const int a = w & 0xFFFFu, b = w >> 16;
-      const T ka = kA[i], kb = kB[i];
+      const T q = sq[i];
+      const T ka = si[a] * q, kb = si[b] * q;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         const T va = sv[k * bmax + a], vb = sv[k * bmax + b];
@@ -589,9 +582,10 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
         sv[k * bmax + b] = vb - kb * dv;
       }
     }
-    pos += __popcll(__ballot(act));
-    __syncthreads();
+    // one wavefront: its LDS accesses complete in issue order, so the next
+    // level reads what this one wrote without a barrier
   }
+  __syncthreads();
   lb = 0;
   for (int r = 0; r < 4; ++r) {
     const uint32_t rb = bl[2 * r], rc = bl[2 * r + 1];
@@ -604,28 +598,32 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
   }
 }
 
-// drift + kinetic energy with a fixed-order two-stage reduction; the last
-// block to finish reduces the partials, records E_k and updates the stop state
+// drift + kinetic energy: every block writes its partial E_k (fixed-order
+// tree), then one block reduces the partials in a fixed order, records E_k
+// and updates the stop state (deterministic: no floating-point atomics)
 template <typename T, int D>
 __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     int64_t n, double* __restrict__ u, const T* __restrict__ v, const uint8_t* __restrict__ flags,
     const double* __restrict__ V, double rho0, double dt, Ctrl* ctrl, double* partial,
-    double* ke_out, bool gated) {
+    bool gated) {
   if (gated && ctrl->done) return;
   __shared__ double red[kKeThreads];
-  __shared__ bool last;
   double acc = 0.0;
-  for (int64_t a = blockIdx.x * (int64_t)kKeThreads + threadIdx.x; a < n;
-       a += (int64_t)gridDim.x * kKeThreads) {
-    const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
-    double v2 = 0.0;
+  const int64_t a0 = blockIdx.x * (int64_t)(kKeThreads * kKeItems) + threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double vk = (double)v[k * n + a];
-      if (!fixed) u[k * n + a] += dt * vk;
-      v2 += vk * vk;
+  for (int it = 0; it < kKeItems; ++it) {
+    const int64_t a = a0 + it * kKeThreads;
+    if (a < n) {
+      const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
+      double v2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double vk = (double)v[k * n + a];
+        if (!fixed) u[k * n + a] += dt * vk;
+        v2 += vk * vk;
+      }
+      acc += 0.5 * rho0 * V[a] * v2;
     }
-    acc += 0.5 * rho0 * V[a] * v2;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -633,27 +631,24 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x] = red[0];
-    __threadfence();
-    unsigned t = atomicAdd(&ctrl->ticket, 1u);
-    last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_ke_reduce(const double* __restrict__ partial,
+                                                    int nblk, Ctrl* ctrl, double* ke_out,
+                                                    bool gated) {
+  if (gated && ctrl->done) return;
+  __shared__ double red[1024];
   double s = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += kKeThreads)
-    s += __builtin_nontemporal_load(&partial[b]);
+  for (int b = threadIdx.x; b < nblk; b += 1024) s += partial[b];
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int w = kKeThreads / 2; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const double ke = red[0];
-    ctrl->ticket = 0u;
     if (ke_out) *ke_out = ke;
     if (gated) {
       ctrl->ke = ke;
@@ -828,7 +823,8 @@ static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_sta
   if (g.n_tiles == 0) return SPH_OK;
   MatP<T> mp = matp<T>(m);
   const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
-  const unsigned block = (unsigned)(g.tmax * kLPP);
+  const unsigned block_s = (unsigned)(g.tmax * kLppStress);
+  const unsigned block_m = (unsigned)(g.tmax * kLppMomentum);
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds_s = wm * 2 * sizeof(vec4<T>);
   const size_t lds_m = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
@@ -838,14 +834,14 @@ static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_sta
   if (rc) return rc;
   {
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_stress<T, D><<<grid, block, lds_s, s>>>(g, mp, st->u, (T*)st->PB, (T*)st->plastic,
+    k_stress<T, D><<<grid, block_s, lds_s, s>>>(g, mp, st->u, (T*)st->PB, (T*)st->plastic,
                                               (const T*)st->p, nb->ctrl, gated);
     prof_end(nb, SPH_KERNEL_STRESS, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   {
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_momentum<T, D><<<grid, block, lds_m, s>>>(g, (const T*)st->PB, (T*)st->v, (T*)st->acc,
+    k_momentum<T, D><<<grid, block_m, lds_m, s>>>(g, (const T*)st->PB, (T*)st->v, (T*)st->acc,
                                                 st->flags, (T)(1.0 / m->rho0), (T)dt, nb->ctrl,
                                                 gated);
     prof_end(nb, SPH_KERNEL_MOMENTUM, pe_, s);
@@ -875,21 +871,24 @@ template <typename T, int D>
 static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
                      double dt, hipStream_t s, bool gated) {
   Geo<T> g = geo<T>(nb);
+  const T* dgeo = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)nb->dgeo64
+                                                           : (const void*)nb->dgeo32);
   const int ncol = 1 << D;
-  const int bmax = (int)std::max<int64_t>(nb->damp_block_max, 1);
-  const int pmax = (int)std::max<int64_t>(nb->damp_pairs_max, 1);
-  const size_t lds = (size_t)bmax * (2 * D + 1) * sizeof(T) + (size_t)pmax * (2 * sizeof(T) + 4 + 2) +
-                     (size_t)bmax;
-  int rc = lds_attr(k_damp<T, D>, lds);
-  if (rc) return rc;
   for (int col = 0; col < ncol; ++col) {
     int64_t a0 = nb->color_off[col], a1 = nb->color_off[col + 1];
     if (a1 <= a0) continue;
+    const int bmax = (int)std::max<int64_t>(nb->damp_bmax[col], 1);
+    const int pmax = (int)std::max<int64_t>(nb->damp_pmax[col], 1);
+    const size_t lds = (size_t)bmax * (D + 1) * sizeof(T) + (size_t)pmax * (sizeof(T) + 4) +
+                       4 * (size_t)(kDampMaxLevel + 1);
+    int rc = lds_attr(k_damp<T, D>, lds);
+    if (rc) return rc;
     {
       hipEvent_t pe_ = prof_begin(nb, s);
-      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, nb->dlev, nb->aoff, nb->ablk, a0, bmax,
-                                                       pmax, (T*)st->v, st->flags, (T)m->rho0,
-                                                       (T)(2.0 * eta * dt), nb->ctrl, gated);
+      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, nb->dlev, dgeo, nb->aoff,
+                                                       nb->ablk, a0, bmax, pmax, (T*)st->v,
+                                                       st->flags, (T)(1.0 / m->rho0),
+                                                       (T)(eta * dt), nb->ctrl, gated);
       prof_end(nb, SPH_KERNEL_DAMPING, pe_, s);
     }
     SPH_LAUNCH_CHECK();
@@ -909,12 +908,19 @@ int damping_sweep(const sph_nbr* nb, const sph_material* m, const sph_state* st,
 template <typename T, int D>
 static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
                    double* ke_out, hipStream_t s, bool gated) {
-  int64_t nb_ = std::min<int64_t>(kKeMaxBlocks, std::max<int64_t>(1, (nb->n + kKeThreads - 1) / kKeThreads));
+  const int64_t per = (int64_t)kKeThreads * kKeItems;
+  const int64_t nb_ = std::max<int64_t>(1, (nb->n + per - 1) / per);
+  if (nb_ > kKeMaxBlocks) {
+    set_error("too many particles for the kinetic-energy partials");
+    return SPH_E_CAPACITY;
+  }
   {
     hipEvent_t pe_ = prof_begin(nb, s);
     k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
-                                                       nb->V, m->rho0, dt, nb->ctrl,
-                                                       nb->ke_partial, ke_out, gated);
+                                                          nb->V, m->rho0, dt, nb->ctrl,
+                                                          nb->ke_partial, gated);
+    SPH_LAUNCH_CHECK();
+    k_ke_reduce<<<1, 1024, 0, s>>>(nb->ke_partial, (int)nb_, nb->ctrl, ke_out, gated);
     prof_end(nb, SPH_KERNEL_DRIFT_KE, pe_, s);
   }
   SPH_LAUNCH_CHECK();
