@@ -623,8 +623,11 @@ __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __
 }
 
 // host planning of row tiles (setup only)
+// Tiles grow along a row while the window stays within `wmax` (the LDS
+// budget that keeps two workgroups per CU); a single cell may exceed it up
+// to `wmax_hard` (the whole LDS of a CU).
 static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
-                      const std::vector<int64_t>& off, int tmax, int64_t wmax,
+                      const std::vector<int64_t>& off, int tmax, int64_t wmax, int64_t wmax_hard,
                       std::vector<TileDesc>& out, int64_t& window_max, int64_t& ell_len) {
   const int64_t nc0 = nb->nc[0], nc1 = nb->nc[1], nc2 = nb->nc[2];
   const int dim = nb->dim;
@@ -686,7 +689,8 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
         if (cnt > tmax) {  // one dense cell: split it into chunks
           int64_t p0 = cs[key(x, y, z)];
           for (int64_t c0 = 0; c0 < cnt; c0 += tmax) {
-            if (make(x, x, y, z, p0 + c0, std::min<int64_t>(tmax, cnt - c0), td) > wmax) return SPH_E_CAPACITY;
+            if (make(x, x, y, z, p0 + c0, std::min<int64_t>(tmax, cnt - c0), td) > wmax_hard)
+              return SPH_E_CAPACITY;
             emit(td);
           }
           ++x;
@@ -700,7 +704,8 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
           cnt += nxt;
           ++x1;
         }
-        if (make(x, x1, y, z, cs[key(x, y, z)], cnt, td) > wmax) return SPH_E_CAPACITY;
+        if (make(x, x1, y, z, cs[key(x, y, z)], cnt, td) > (x1 == x ? wmax_hard : wmax))
+          return SPH_E_CAPACITY;
         emit(td);
         x = x1 + 1;
       }
@@ -984,7 +989,8 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
       Tiling& T = nb->tiling[prec];
       T.tmax = tile_tmax(prec);
       std::vector<TileDesc> tv;
-      rc_ = plan_tiles(nb, hcs, hoff, T.tmax, tile_wmax(prec, dim), tv, T.window_max, T.ell_len);
+      rc_ = plan_tiles(nb, hcs, hoff, T.tmax, tile_wmax(prec, dim), tile_wmax_hard(prec, dim), tv,
+                       T.window_max, T.ell_len);
       if (rc_) {
         hipFree(terr);
         set_error("tile planning failed (a cell row window exceeds the LDS budget)");

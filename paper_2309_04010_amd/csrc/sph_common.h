@@ -165,6 +165,10 @@ constexpr int64_t kTileLdsBudget = 80 * 1024;
 inline int64_t tile_wmax(int prec, int dim) {
   return std::min<int64_t>(65535, kTileLdsBudget / tile_lds_bytes_per_particle(prec, dim));
 }
+constexpr int64_t kTileLdsHard = 159 * 1024;  // gfx950: 160 KB of LDS per workgroup
+inline int64_t tile_wmax_hard(int prec, int dim) {
+  return std::min<int64_t>(65535, kTileLdsHard / tile_lds_bytes_per_particle(prec, dim));
+}
 
 // ---- event timing around launches --------------------------------------------
 hipEvent_t prof_begin(const sph_nbr* nb, hipStream_t s);

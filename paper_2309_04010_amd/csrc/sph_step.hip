@@ -524,29 +524,50 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
   const int64_t ai = a_begin + blockIdx.x;
   const uint32_t* bl = ablk + 8 * ai;  // (begin, count) x 4 runs
   const int lane = threadIdx.x;
-  int lb = 0;
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t rb = bl[2 * r], rc = bl[2 * r + 1];
-    for (uint32_t i = lane; i < rc; i += 64) {
-      const int64_t gi = (int64_t)rb + i;
+  // block runs flattened: local index l -> run r, global index rb + (l - lbase)
+  const uint32_t c0 = bl[1], c1 = bl[3], c2 = bl[5], c3 = bl[7];
+  const uint32_t e0 = c0, e1 = e0 + c1, e2 = e1 + c2, nblk = e2 + c3;
+  auto gidx = [&](uint32_t l) -> int64_t {
+    return l < e0 ? (int64_t)bl[0] + l
+                  : (l < e1 ? (int64_t)bl[2] + (l - e0)
+                            : (l < e2 ? (int64_t)bl[4] + (l - e1) : (int64_t)bl[6] + (l - e2)));
+  };
+  for (uint32_t l = lane; l < nblk; l += 64) {
+    const int64_t gi = gidx(l);
 #pragma unroll
-      for (int k = 0; k < D; ++k) sv[k * bmax + lb + i] = v[k * n + gi];
-      const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
-      si[lb + i] = fixed ? T(0) : inv_rho0 / g.V[gi];
-    }
-    lb += rc;
+    for (int k = 0; k < D; ++k) sv[k * bmax + l] = v[k * n + gi];
+    const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
+    si[l] = fixed ? T(0) : inv_rho0 / g.V[gi];
   }
   const int64_t lo = aoff[ai];
   const int np = (int)(aoff[ai + 1] - lo);
-  for (int i = lane; i < np; i += 64) {
-    const uint32_t L = dlev[lo + i];
-    if (i == 0 || dlev[lo + i - 1] != L) soff[L] = (uint32_t)i;
-    if (i == np - 1) {
-      soff[L + 1] = (uint32_t)np;
-      s_nlev = (int)L + 1;
+  // pairs, four per lane in flight
+  for (int i0 = lane; i0 < np; i0 += 4 * 64) {
+    uint32_t L[4], Lp[4], w[4];
+    T gg[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u;
+      if (i < np) {
+        L[u] = dlev[lo + i];
+        Lp[u] = i > 0 ? dlev[lo + i - 1] : 0xFFFFFFFFu;
+        w[u] = dpair[lo + i];
+        gg[u] = dgeo[lo + i];
+      }
     }
-    sp[i] = dpair[lo + i];
-    sq[i] = dgeo[lo + i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + 64 * u;
+      if (i < np) {
+        if (L[u] != Lp[u]) soff[L[u]] = (uint32_t)i;
+        if (i == np - 1) {
+          soff[L[u] + 1] = (uint32_t)np;
+          s_nlev = (int)L[u] + 1;
+        }
+        sp[i] = w[u];
+        sq[i] = gg[u];
+      }
+    }
   }
   __syncthreads();
   for (int i = lane; i < np; i += 64) {
@@ -556,23 +577,40 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
   }
   const int nlev = s_nlev;
   // level offsets in registers: lane l holds soff[64 c + l]
-  uint32_t r0 = lane <= nlev ? soff[lane] : 0u;
-  uint32_t r1 = 64 + lane <= nlev ? soff[64 + lane] : 0u;
-  uint32_t r2 = 128 + lane <= nlev ? soff[128 + lane] : 0u;
-  uint32_t r3 = 192 + lane <= nlev ? soff[192 + lane] : 0u;
+  const uint32_t r0 = lane <= nlev ? soff[lane] : 0u;
+  const uint32_t r1 = 64 + lane <= nlev ? soff[64 + lane] : 0u;
+  const uint32_t r2 = 128 + lane <= nlev ? soff[128 + lane] : 0u;
+  const uint32_t r3 = 192 + lane <= nlev ? soff[192 + lane] : 0u;
   __syncthreads();
   auto level_off = [&](int L) -> int {
     const uint32_t rr = L < 64 ? r0 : (L < 128 ? r1 : (L < 192 ? r2 : r3));
     return __builtin_amdgcn_readlane((int)rr, L & 63);
   };
-  int hi = level_off(0);
+  // software pipeline: the pair word and coefficient of a lane's first pair
+  // of the next level are loaded while the current level is applied
+  int lo_l = level_off(0), hi = level_off(1);
+  uint32_t w_nx = 0;
+  T q_nx = T(0);
+  if (lo_l + lane < hi) {
+    w_nx = sp[lo_l + lane];
+    q_nx = sq[lo_l + lane];
+  }
   for (int L = 0; L < nlev; ++L) {
-    const int lo_l = hi;
-    hi = level_off(L + 1);
-    for (int i = lo_l + lane; i < hi; i += 64) {
-      const uint32_t w = sp[i];
+    const uint32_t w_cur = w_nx;
+    const T q_cur = q_nx;
+    const int lo_c = lo_l, hi_c = hi;
+    if (L + 1 < nlev) {
+      lo_l = hi;
+      hi = level_off(L + 2);
+      if (lo_l + lane < hi) {
+        w_nx = sp[lo_l + lane];
+        q_nx = sq[lo_l + lane];
+      }
+    }
+    for (int i = lo_c + lane; i < hi_c; i += 64) {
+      const uint32_t w = i == lo_c + lane ? w_cur : sp[i];
+      const T q = i == lo_c + lane ? q_cur : sq[i];
       const int a = w & 0xFFFFu, b = w >> 16;
-      const T q = sq[i];
       const T ka = si[a] * q, kb = si[b] * q;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
@@ -586,15 +624,10 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     // level reads what this one wrote without a barrier
   }
   __syncthreads();
-  lb = 0;
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t rb = bl[2 * r], rc = bl[2 * r + 1];
-    for (uint32_t i = lane; i < rc; i += 64) {
-      const int64_t gi = (int64_t)rb + i;
+  for (uint32_t l = lane; l < nblk; l += 64) {
+    const int64_t gi = gidx(l);
 #pragma unroll
-      for (int k = 0; k < D; ++k) v[k * n + gi] = sv[k * bmax + lb + i];
-    }
-    lb += rc;
+    for (int k = 0; k < D; ++k) v[k * n + gi] = sv[k * bmax + l];
   }
 }
 
