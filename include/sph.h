@@ -80,7 +80,7 @@ typedef struct {
   int64_t max_deg;         /* largest neighbour count */
   int64_t max_level;       /* largest number of levels of one anchor */
   int64_t color_off[9];    /* host: anchors of colour k are [color_off[k], color_off[k+1]) */
-  double origin[3];        /* componentwise minimum of the reference positions */
+  double origin[3];        /* cell-grid origin (the cloud is centred in the grid) */
   double h;                /* smoothing length; support radius 2h */
   double inv_rc;           /* 1/(2h), as used for the cell keys */
   const uint32_t* key;     /* [n] cell key of each sorted particle */
@@ -157,9 +157,11 @@ typedef struct {
  * in the initial configuration).
  *   X [dim][n], V [n]: device FP64 reference positions and volumes, input order.
  *   h: smoothing length; neighbours are b != a with |X_a - X_b|^2 < (2h)^2
- *      (FP64, no fused multiply-add), found in cells of edge 2h with origin at
- *      the componentwise minimum of X.  Particles are stably sorted by cell
- *      key (x fastest); lists are in ascending sorted position.
+ *      (FP64, no fused multiply-add), found in cells of edge 2h: per axis
+ *      nc = floor(extent / 2h) + 1 cells, the cloud centred in the grid,
+ *      cell index floor((X - origin) / 2h) clamped to [0, nc-1].  Particles
+ *      are stably sorted by cell key (x fastest); lists are in ascending
+ *      sorted position.
  *   Damping schedule: each unordered pair is anchored at the componentwise
  *   minimum of its two cells and coloured by the parity of that anchor
  *   (2^dim colours, so anchors of one colour touch disjoint 2^dim-cell blocks);

@@ -183,7 +183,9 @@ orc_sys* orc_create(int dim, int64_t n, const double* X_id, const double* V_id, 
   s->rc2 = s->rc * s->rc;
   s->inv_rc = 1.0 / s->rc;
 
-  /* --- cell grid: edge 2h, origin at the componentwise minimum --- */
+  /* --- cell grid: edge 2h, nc = floor(extent / 2h) + 1 cells per axis,
+   *     centred on the cloud; cell index floor((X - origin) / 2h), clamped
+   *     to the grid --- */
   double hi[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < 3; ++k) {
     s->origin[k] = 0.0;
@@ -196,9 +198,10 @@ orc_sys* orc_create(int dim, int64_t n, const double* X_id, const double* V_id, 
       if (x < lo) lo = x;
       if (x > top) top = x;
     }
-    s->origin[k] = lo;
     hi[k] = top;
     s->nc[k] = (int64_t)floor((hi[k] - lo) * s->inv_rc) + 1;
+    /* the cloud is centred in the cell grid: equal margins on both sides */
+    s->origin[k] = lo - 0.5 * ((double)s->nc[k] * s->rc - (hi[k] - lo));
   }
   s->ncells = s->nc[0] * s->nc[1] * s->nc[2];
   if (s->ncells > 0xFFFFFFF0LL) {
@@ -211,7 +214,11 @@ orc_sys* orc_create(int dim, int64_t n, const double* X_id, const double* V_id, 
   uint32_t* key_id = (uint32_t*)malloc(n * sizeof(uint32_t));
   for (int64_t i = 0; i < n; ++i) {
     int64_t c[3] = {0, 0, 0};
-    for (int k = 0; k < dim; ++k) c[k] = (int64_t)floor((X_id[k * n + i] - s->origin[k]) * s->inv_rc);
+    for (int k = 0; k < dim; ++k) {
+      c[k] = (int64_t)floor((X_id[k * n + i] - s->origin[k]) * s->inv_rc);
+      if (c[k] < 0) c[k] = 0;
+      if (c[k] > s->nc[k] - 1) c[k] = s->nc[k] - 1;
+    }
     key_id[i] = (uint32_t)(c[0] + s->nc[0] * (c[1] + s->nc[1] * c[2]));
   }
 

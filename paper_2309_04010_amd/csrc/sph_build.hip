@@ -157,6 +157,9 @@ __global__ void k_cellkey(const double* X, int64_t n, Grid g, uint32_t* key, uin
   int64_t c0 = (int64_t)floor((X[i] - g.o0) * g.inv_rc);
   int64_t c1 = g.dim > 1 ? (int64_t)floor((X[n + i] - g.o1) * g.inv_rc) : 0;
   int64_t c2 = g.dim > 2 ? (int64_t)floor((X[2 * n + i] - g.o2) * g.inv_rc) : 0;
+  c0 = c0 < 0 ? 0 : (c0 >= g.nc0 ? g.nc0 - 1 : c0);
+  c1 = c1 < 0 ? 0 : (c1 >= g.nc1 ? g.nc1 - 1 : c1);
+  c2 = c2 < 0 ? 0 : (c2 >= g.nc2 ? g.nc2 - 1 : c2);
   key[i] = (uint32_t)(c0 + g.nc0 * (c1 + g.nc1 * c2));
   val[i] = (uint32_t)i;
 }
@@ -542,7 +545,7 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
     } else {
       own = td.own_base;  // unused column: any valid index
     }
-    for (uint32_t j = 0; j < td.width; ++j) {
+    for (uint32_t j = 0; j < td.width; ++j) {  // width: multiple of 4
       uint32_t loc = own;
       if ((int64_t)j < deg) {
         uint32_t b = idx[j0 + j];
@@ -559,7 +562,7 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
         }
         if (!found) atomicOr(err, 4);
       }
-      ell[(int64_t)td.ell_off + (int64_t)j * tmax + t] = (uint16_t)loc;
+      ell[(int64_t)td.ell_off + (int64_t)(j >> 2) * 4 * tmax + 4 * t + (j & 3)] = (uint16_t)loc;
     }
   }
 }
@@ -670,9 +673,9 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
       int64_t a = (int64_t)td.p0 + t;
       width = std::max<uint32_t>(width, (uint32_t)(off[a + 1] - off[a]));
     }
-    td.width = width;
+    td.width = (width + 3) & ~3u;
     td.ell_off = (uint32_t)ell_len;
-    ell_len += (int64_t)width * tmax;
+    ell_len += (int64_t)td.width * tmax;
     window_max = std::max<int64_t>(window_max, td.window);
     out.push_back(td);
   };
@@ -770,8 +773,9 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
       set_error("non-finite reference positions");
       return SPH_E_ARG;
     }
-    nb->origin[k] = hb[2 * k];
     nb->nc[k] = (int64_t)floor((hb[2 * k + 1] - hb[2 * k]) * nb->inv_rc) + 1;
+    // the cloud is centred in the cell grid (equal margins on both sides)
+    nb->origin[k] = hb[2 * k] - 0.5 * ((double)nb->nc[k] * rc - (hb[2 * k + 1] - hb[2 * k]));
   }
   nb->n_cells = nb->nc[0] * nb->nc[1] * nb->nc[2];
   if (nb->n_cells > 0xFFFFFFF0LL || n > 0xFFFFFFF0LL) {

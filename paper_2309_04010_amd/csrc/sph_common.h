@@ -70,9 +70,12 @@ constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (16.7M particles)
 // (fixed y, z).  Its neighbours all lie in the "window": the 3^(d-1) rows
 // around it, each clipped to cells [x0-1, x1+1] -- contiguous particle runs,
 // which a workgroup stages in LDS.  Neighbour lists of the tile are stored as
-// window-local 16-bit indices in an ELL layout: entry j of tile particle t is
-// ell[ell_off + j * tmax + t]; rows past a particle's degree hold its own
-// index (a zero contribution).
+// window-local 16-bit indices in a blocked ELL layout: entries are grouped in
+// fours, entry j of tile particle t is
+//   ell[ell_off + (j / 4) * 4 * tmax + 4 * t + j % 4],
+// so one lane loads four indices with one 8-byte load and a wavefront's loads
+// are contiguous; entries past a particle's degree hold its own index (a zero
+// contribution).  `width` is a multiple of 4.
 struct TileDesc {
   uint32_t p0, count, ell_off, width;
   uint32_t nruns, window, own_base, pad;
@@ -146,9 +149,12 @@ namespace sph {
 
 // ---- kernel function: Wendland C2, support 2h --------------------------------
 // (dW/dr)/r = c5 (1 - q/2)^3 with q = r/h, c5 = -5 alpha_d / h^2.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }  // 1 ulp
+__device__ __forceinline__ double hw_sqrt(double x) { return sqrt(x); }
+
 template <typename T>
 __device__ __forceinline__ T dw_over_r(T r2, T inv_h, T c5) {
-  T q = sqrt(r2) * inv_h;
+  T q = hw_sqrt(r2) * inv_h;
   T t = T(1) - T(0.5) * q;
   return c5 * t * t * t;
 }

@@ -282,11 +282,72 @@ __device__ __forceinline__ T lane_sum(T x) {
   return x;
 }
 
+// window index -> global particle index: the window is the concatenation of
+// the tile's runs (uniform data, kept in scalar registers)
+struct WinMap {
+  uint32_t start[9];
+  uint32_t lend[9];  // exclusive end of each run in window numbering
+  uint32_t nruns;
+  __device__ __forceinline__ int64_t operator()(uint32_t l) const {
+    uint32_t b = 0;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      if (r < (int)nruns && l >= b && l < lend[r]) return (int64_t)start[r] + (l - b);
+      b = r < (int)nruns ? lend[r] : b;
+    }
+    return (int64_t)start[0];
+  }
+};
+
+__device__ __forceinline__ WinMap win_map(const TileDesc& td) {
+  WinMap m;
+  m.nruns = td.nruns;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    m.start[r] = td.run_start[r];
+    acc += r < (int)td.nruns ? td.run_count[r] : 0u;
+    m.lend[r] = acc;
+  }
+  return m;
+}
+
+// Blocked-ELL walk: lane h of a particle takes the blocks of four neighbour
+// indices c = h, h + LPP, ...; two registers alternate so that the load of
+// block c + 2 LPP is in flight while block c + LPP is applied (a register
+// copy of a pending load would force the wait early).
+template <int LPP, typename F>
+__device__ __forceinline__ void ell_walk(const uint16_t* ell, uint32_t ell_off, int tmax, int t,
+                                         int h, uint32_t width, F&& f) {
+  const uint2* e = reinterpret_cast<const uint2*>(ell + ell_off) + t;
+  const int nb4 = (int)(width >> 2);
+  uint2 bA = make_uint2(0u, 0u), bB = make_uint2(0u, 0u);
+  if (h < nb4) bA = e[(int64_t)h * tmax];
+  if (h + LPP < nb4) bB = e[(int64_t)(h + LPP) * tmax];
+  for (int c = h; c < nb4; c += 2 * LPP) {
+    f(bA.x & 0xFFFFu);
+    f(bA.x >> 16);
+    f(bA.y & 0xFFFFu);
+    f(bA.y >> 16);
+    if (c + 2 * LPP < nb4) bA = e[(int64_t)(c + 2 * LPP) * tmax];
+    if (c + LPP < nb4) {
+      f(bB.x & 0xFFFFu);
+      f(bB.x >> 16);
+      f(bB.y & 0xFFFFu);
+      f(bB.y >> 16);
+      if (c + 3 * LPP < nb4) bB = e[(int64_t)(c + 3 * LPP) * tmax];
+    }
+  }
+}
+
 // stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0
 template <typename T, int D>
-__global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<T> m, const double* __restrict__ u,
-                                                T* __restrict__ PB, T* __restrict__ plastic,
-                                                const T* __restrict__ p, Ctrl* ctrl, bool gated) {
+__global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<T> m,
+                                                             const double* __restrict__ u,
+                                                             T* __restrict__ PB,
+                                                             T* __restrict__ plastic,
+                                                             const T* __restrict__ p, Ctrl* ctrl,
+                                                             bool gated) {
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
@@ -303,24 +364,31 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
     xo[k] = g.X[k * n + p0];
     uo[k] = u[k * n + p0];
   }
-  uint32_t base = 0;
-  for (uint32_t r = 0; r < td.nruns; ++r) {
-    const uint32_t rs = td.run_start[r], rc = td.run_count[r];
-    for (uint32_t i = threadIdx.x; i < rc; i += blockDim.x) {
-      const int64_t gi = (int64_t)rs + i;
-      vec4<T> xv, uv;
-      xv.x = (T)(g.X[gi] - xo[0]);
-      xv.y = (T)(g.X[n + gi] - xo[1]);
-      xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
-      xv.w = g.V[gi];
-      uv.x = (T)(u[gi] - uo[0]);
-      uv.y = (T)(u[n + gi] - uo[1]);
-      uv.z = D == 3 ? (T)(u[2 * n + gi] - uo[2]) : T(0);
-      uv.w = T(0);
-      sx[base + i] = xv;
-      su[base + i] = uv;
+  const WinMap wm = win_map(td);
+  // stage the window, two particles per thread in flight
+  for (uint32_t l0 = threadIdx.x; l0 < window; l0 += 2 * blockDim.x) {
+    vec4<T> xv[2], uv[2];
+    uint32_t ls[2] = {l0, l0 + blockDim.x};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (ls[e] < window) {
+        const int64_t gi = wm(ls[e]);
+        xv[e].x = (T)(g.X[gi] - xo[0]);
+        xv[e].y = (T)(g.X[n + gi] - xo[1]);
+        xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+        xv[e].w = g.V[gi];
+        uv[e].x = (T)(u[gi] - uo[0]);
+        uv[e].y = (T)(u[n + gi] - uo[1]);
+        uv[e].z = D == 3 ? (T)(u[2 * n + gi] - uo[2]) : T(0);
+        uv[e].w = T(0);
+      }
     }
-    base += rc;
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ls[e] < window) {
+        sx[ls[e]] = xv[e];
+        su[ls[e]] = uv[e];
+      }
   }
   __syncthreads();
   const int t = threadIdx.x / kLppStress, h = threadIdx.x % kLppStress;
@@ -332,9 +400,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) G[i][k] = T(0);
-  const uint16_t* ell = g.ell + td.ell_off + t;
-  for (uint32_t j = h; j < td.width; j += kLppStress) {
-    const uint32_t l = ell[(int64_t)j * g.tmax];
+  ell_walk<kLppStress>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
     const vec4<T> xb = sx[l], ub = su[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
@@ -347,7 +413,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
 #pragma unroll
       for (int k = 0; k < D; ++k) G[i][k] += wd * d[k];
     }
-  }
+  });
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -393,10 +459,13 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
 
 // momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a
 template <typename T, int D>
-__global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g, const T* __restrict__ PB,
-                                                  T* __restrict__ v, T* __restrict__ acc_out,
-                                                  const uint8_t* __restrict__ flags, T inv_rho0,
-                                                  T dt, Ctrl* ctrl, bool gated) {
+__global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
+                                                                 const T* __restrict__ PB,
+                                                                 T* __restrict__ v,
+                                                                 T* __restrict__ acc_out,
+                                                                 const uint8_t* __restrict__ flags,
+                                                                 T inv_rho0, T dt, Ctrl* ctrl,
+                                                                 bool gated) {
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
@@ -411,31 +480,37 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g, c
   double xo[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
-  uint32_t base = 0;
-  for (uint32_t r = 0; r < td.nruns; ++r) {
-    const uint32_t rs = td.run_start[r], rc = td.run_count[r];
-    for (uint32_t i = threadIdx.x; i < rc; i += blockDim.x) {
-      const int64_t gi = (int64_t)rs + i;
-      vec4<T> xv;
-      xv.x = (T)(g.X[gi] - xo[0]);
-      xv.y = (T)(g.X[n + gi] - xo[1]);
-      xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
-      xv.w = g.V[gi];
-      sx[base + i] = xv;
-      T pb[NP * 4];
+  const WinMap wm = win_map(td);
+  for (uint32_t l0 = threadIdx.x; l0 < window; l0 += 2 * blockDim.x) {
+    vec4<T> xv[2];
+    T pb[2][NP * 4];
+    uint32_t ls[2] = {l0, l0 + blockDim.x};
 #pragma unroll
-      for (int c = 0; c < NP * 4; ++c) pb[c] = c < D * D ? PB[c * n + gi] : T(0);
+    for (int e = 0; e < 2; ++e) {
+      if (ls[e] < window) {
+        const int64_t gi = wm(ls[e]);
+        xv[e].x = (T)(g.X[gi] - xo[0]);
+        xv[e].y = (T)(g.X[n + gi] - xo[1]);
+        xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+        xv[e].w = g.V[gi];
 #pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        vec4<T> pv;
-        pv.x = pb[4 * q];
-        pv.y = pb[4 * q + 1];
-        pv.z = pb[4 * q + 2];
-        pv.w = pb[4 * q + 3];
-        sp[(base + i) * NP + q] = pv;
+        for (int c = 0; c < NP * 4; ++c) pb[e][c] = c < D * D ? PB[c * n + gi] : T(0);
       }
     }
-    base += rc;
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ls[e] < window) {
+        sx[ls[e]] = xv[e];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          vec4<T> pv;
+          pv.x = pb[e][4 * q];
+          pv.y = pb[e][4 * q + 1];
+          pv.z = pb[e][4 * q + 2];
+          pv.w = pb[e][4 * q + 3];
+          sp[ls[e] * NP + q] = pv;
+        }
+      }
   }
   __syncthreads();
   const int t = threadIdx.x / kLppMomentum, h = threadIdx.x % kLppMomentum;
@@ -453,9 +528,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g, c
     Pa[4 * q + 3] = pv.w;
   }
   T f[3] = {T(0), T(0), T(0)};
-  const uint16_t* ell = g.ell + td.ell_off + t;
-  for (uint32_t j = h; j < td.width; j += kLppMomentum) {
-    const uint32_t l = ell[(int64_t)j * g.tmax];
+  ell_walk<kLppMomentum>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
     const vec4<T> xb = sx[l];
     T Pb[NP * 4];
 #pragma unroll
@@ -477,7 +550,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g, c
       for (int k = 0; k < D; ++k) s += (Pa[i * D + k] + Pb[i * D + k]) * d[k];
       f[i] += w * s;
     }
-  }
+  });
 #pragma unroll
   for (int i = 0; i < D; ++i) f[i] = lane_sum<kLppMomentum>(f[i]);
   if (h != 0) return;
