@@ -625,6 +625,30 @@ __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __
   }
 }
 
+// level offsets of each anchor: dloff[base + L] = first pair of level L
+// (relative to the anchor's first pair), dloff[base + nlev] = pair count
+__global__ void k_lev_count(const uint32_t* __restrict__ anlev, int64_t n_anchors,
+                            int64_t* __restrict__ cnt) {
+  int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (ai < n_anchors) cnt[ai] = (int64_t)anlev[ai] + 1;
+}
+
+__global__ void k_lev_fill(const int64_t* __restrict__ aoff, const uint32_t* __restrict__ slev,
+                           const int64_t* __restrict__ base, int64_t n_anchors,
+                           uint16_t* __restrict__ dloff, uint32_t* __restrict__ dloff_base) {
+  int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (ai >= n_anchors) return;
+  const int64_t lo = aoff[ai], hi = aoff[ai + 1], b = base[ai];
+  dloff_base[ai] = (uint32_t)b;
+  uint32_t prev = 0xFFFFFFFFu;
+  for (int64_t i = lo; i < hi; ++i) {
+    const uint32_t L = slev[i];
+    if (L != prev) dloff[b + L] = (uint16_t)(i - lo);
+    prev = L;
+  }
+  dloff[b + prev + 1] = (uint16_t)(hi - lo);
+}
+
 // host planning of row tiles (setup only)
 // Tiles grow along a row while the window stays within `wmax` (the LDS
 // budget that keeps two workgroups per CU); a single cell may exceed it up
@@ -723,7 +747,7 @@ static void free_nbr(sph_nbr* h) {
   void* ptrs[] = {h->key, h->perm, h->cell_start, h->nbr_off, h->nbr_idx, h->X,   h->V,
                   h->B0,  h->Vf,   h->B0f,        h->sa,      h->sb,      h->slev, h->akey,
                   h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk, h->dlev,
-                  h->dgeo32, h->dgeo64,
+                  h->dgeo32, h->dgeo64, h->dloff, h->dloff_base,
                   h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -968,14 +992,36 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
     }
     // LDS of one anchor in the FP64 sweep: block (v, inverse mass) and pairs
     // (word, coefficient), plus the level offsets
-    const int64_t need = nb->damp_block_max * (4 * 8) + nb->damp_pairs_max * (4 + 8) +
-                         4 * (kDampMaxLevel + 1);
-    if (need > kDampLdsBudget) {
+    const int64_t need = nb->damp_block_max * (4 * 8) + nb->damp_pairs_max * 16;
+    if (need > kDampLdsBudget || nb->damp_pairs_max > 65535) {
       set_error("an anchor block needs %lld B of LDS for the damping sweep (limit %lld): "
                 "neighbourhoods this dense are not supported", (long long)need,
                 (long long)kDampLdsBudget);
       return SPH_E_CAPACITY;
     }
+    // per-anchor level offsets
+    int64_t* lcnt = nullptr;
+    int64_t* lbase = nullptr;
+    if ((rc_ = dalloc(&lcnt, base + 1)) || (rc_ = dalloc(&lbase, base + 1)) ||
+        (rc_ = dalloc(&nb->dloff_base, std::max<int64_t>(base, 1))))
+      return rc_;
+    if (base > 0) {
+      k_lev_count<<<nblocks(base, 256), 256, 0, s>>>(nb->anlev, base, lcnt);
+      SPH_LAUNCH_CHECK();
+    }
+    if ((rc_ = scan_exclusive(lcnt, lbase, base, lbase + base, s))) return rc_;
+    int64_t nloff = 0;
+    SPH_HIP(hipMemcpyAsync(&nloff, lbase + base, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    if ((rc_ = dalloc(&nb->dloff, nloff))) return rc_;
+    if (base > 0) {
+      k_lev_fill<<<nblocks(base, 64), 64, 0, s>>>(nb->aoff, nb->slev, lbase, base, nb->dloff,
+                                                  nb->dloff_base);
+      SPH_LAUNCH_CHECK();
+    }
+    SPH_HIP(hipStreamSynchronize(s));
+    hipFree(lcnt);
+    hipFree(lbase);
   }
 
   // row tiles for the LDS-staged gathers, one tiling per precision

@@ -129,6 +129,8 @@ struct sph_nbr {
   uint32_t* anlev = nullptr;
   uint32_t* dpair = nullptr;         // [n_upairs] packed damping pairs (canonical order)
   uint16_t* dlev = nullptr;          // [n_upairs] their levels
+  uint16_t* dloff = nullptr;         // level offsets of every anchor (relative to its first pair)
+  uint32_t* dloff_base = nullptr;    // [n_anchors] start of each anchor's offsets in dloff
   uint32_t* ablk = nullptr;          // [n_anchors][8] anchor block runs (begin, count) x 4
   int64_t damp_block_max = 0;        // largest anchor block (particles)
   int64_t damp_pairs_max = 0;        // largest pair count of one anchor

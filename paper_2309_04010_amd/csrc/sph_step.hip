@@ -569,17 +569,31 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
 // (dW/dr)/r (precomputed per pair):
 //   v_ab' = v_ab / (1 - beta (i_a + i_b)),  v_a += beta i_a v_ab',  v_b -= beta i_b v_ab',
 // i.e. v_a += i_a q (v_a - v_b), v_b -= i_b q (v_a - v_b) with
-// q = beta / (1 - beta (i_a + i_b)).  The anchor's 2^d-cell block
-// (velocities, inverse masses) and its pairs live in LDS; a parallel prologue
-// computes q per pair and the offsets of the levels, which are then held in
-// registers.  The levels run in order, the pairs of one level in parallel
-// (they share no particle), with only LDS reads and writes of velocities on
-// the serial path.  The block is written back at the end; anchors of one
-// colour touch disjoint blocks.
+// q = beta / (1 - beta (i_a + i_b)).  The anchor's 2^d-cell block lives in
+// LDS as one 4-vector per particle (velocity, inverse mass) and its pairs as
+// (pair word, q); the level offsets sit in registers.  Levels run in order,
+// the pairs of one level in parallel (they share no particle): two 4-vector
+// reads and writes per pair on the serial path.  The block is written back
+// at the end; anchors of one colour touch disjoint blocks.
+template <typename T>
+struct PairQ;
+template <>
+struct alignas(8) PairQ<float> {
+  uint32_t w;
+  float q;
+};
+template <>
+struct alignas(16) PairQ<double> {
+  uint32_t w, pad;
+  double q;
+};
+
 template <typename T, int D>
 __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restrict__ dpair,
-                                             const uint16_t* __restrict__ dlev,
                                              const T* __restrict__ dgeo,
+                                             const uint16_t* __restrict__ dloff,
+                                             const uint32_t* __restrict__ dloff_base,
+                                             const uint32_t* __restrict__ anlev,
                                              const int64_t* __restrict__ aoff,
                                              const uint32_t* __restrict__ ablk, int64_t a_begin,
                                              int bmax, int pmax, T* v,
@@ -587,17 +601,12 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
                                              T eta_dt, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sv = reinterpret_cast<T*>(smem_raw);   // [D][bmax]
-  T* si = sv + D * bmax;                    // [bmax] inverse masses
-  T* sq = si + bmax;                        // [pmax]
-  uint32_t* sp = reinterpret_cast<uint32_t*>(sq + pmax);  // [pmax]
-  uint32_t* soff = sp + pmax;                             // [kDampMaxLevel + 1]
-  __shared__ int s_nlev;
+  vec4<T>* sv = reinterpret_cast<vec4<T>*>(smem_raw);           // [bmax] (v, inverse mass)
+  PairQ<T>* sp = reinterpret_cast<PairQ<T>*>(sv + bmax);          // [pmax]
   const int64_t n = g.n;
   const int64_t ai = a_begin + blockIdx.x;
   const uint32_t* bl = ablk + 8 * ai;  // (begin, count) x 4 runs
   const int lane = threadIdx.x;
-  // block runs flattened: local index l -> run r, global index rb + (l - lbase)
   const uint32_t c0 = bl[1], c1 = bl[3], c2 = bl[5], c3 = bl[7];
   const uint32_t e0 = c0, e1 = e0 + c1, e2 = e1 + c2, nblk = e2 + c3;
   auto gidx = [&](uint32_t l) -> int64_t {
@@ -607,23 +616,31 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
   };
   for (uint32_t l = lane; l < nblk; l += 64) {
     const int64_t gi = gidx(l);
-#pragma unroll
-    for (int k = 0; k < D; ++k) sv[k * bmax + l] = v[k * n + gi];
+    vec4<T> x;
+    x.x = v[gi];
+    x.y = v[n + gi];
+    x.z = D == 3 ? v[2 * n + gi] : T(0);
     const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
-    si[l] = fixed ? T(0) : inv_rho0 / g.V[gi];
+    x.w = fixed ? T(0) : inv_rho0 / g.V[gi];
+    sv[l] = x;
   }
   const int64_t lo = aoff[ai];
   const int np = (int)(aoff[ai + 1] - lo);
-  // pairs, four per lane in flight
+  const int nlev = (int)anlev[ai];
+  const uint16_t* lof = dloff + dloff_base[ai];
+  // level offsets in registers: lane l holds offset 64 c + l
+  const uint32_t r0 = lane <= nlev ? lof[lane] : 0u;
+  const uint32_t r1 = 64 + lane <= nlev ? lof[64 + lane] : 0u;
+  const uint32_t r2 = 128 + lane <= nlev ? lof[128 + lane] : 0u;
+  const uint32_t r3 = 192 + lane <= nlev ? lof[192 + lane] : 0u;
+  __syncthreads();
   for (int i0 = lane; i0 < np; i0 += 4 * 64) {
-    uint32_t L[4], Lp[4], w[4];
+    uint32_t w[4];
     T gg[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = i0 + 64 * u;
       if (i < np) {
-        L[u] = dlev[lo + i];
-        Lp[u] = i > 0 ? dlev[lo + i - 1] : 0xFFFFFFFFu;
         w[u] = dpair[lo + i];
         gg[u] = dgeo[lo + i];
       }
@@ -632,66 +649,37 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     for (int u = 0; u < 4; ++u) {
       const int i = i0 + 64 * u;
       if (i < np) {
-        if (L[u] != Lp[u]) soff[L[u]] = (uint32_t)i;
-        if (i == np - 1) {
-          soff[L[u] + 1] = (uint32_t)np;
-          s_nlev = (int)L[u] + 1;
-        }
-        sp[i] = w[u];
-        sq[i] = gg[u];
+        const T beta = eta_dt * gg[u];
+        PairQ<T> pq;
+        pq.w = w[u];
+        pq.q = beta / (T(1) - beta * (sv[w[u] & 0xFFFFu].w + sv[w[u] >> 16].w));
+        sp[i] = pq;
       }
     }
   }
-  __syncthreads();
-  for (int i = lane; i < np; i += 64) {
-    const uint32_t w = sp[i];
-    const T beta = eta_dt * sq[i];
-    sq[i] = beta / (T(1) - beta * (si[w & 0xFFFFu] + si[w >> 16]));
-  }
-  const int nlev = s_nlev;
-  // level offsets in registers: lane l holds soff[64 c + l]
-  const uint32_t r0 = lane <= nlev ? soff[lane] : 0u;
-  const uint32_t r1 = 64 + lane <= nlev ? soff[64 + lane] : 0u;
-  const uint32_t r2 = 128 + lane <= nlev ? soff[128 + lane] : 0u;
-  const uint32_t r3 = 192 + lane <= nlev ? soff[192 + lane] : 0u;
   __syncthreads();
   auto level_off = [&](int L) -> int {
     const uint32_t rr = L < 64 ? r0 : (L < 128 ? r1 : (L < 192 ? r2 : r3));
     return __builtin_amdgcn_readlane((int)rr, L & 63);
   };
-  // software pipeline: the pair word and coefficient of a lane's first pair
-  // of the next level are loaded while the current level is applied
-  int lo_l = level_off(0), hi = level_off(1);
-  uint32_t w_nx = 0;
-  T q_nx = T(0);
-  if (lo_l + lane < hi) {
-    w_nx = sp[lo_l + lane];
-    q_nx = sq[lo_l + lane];
-  }
+  int hi = level_off(0);
   for (int L = 0; L < nlev; ++L) {
-    const uint32_t w_cur = w_nx;
-    const T q_cur = q_nx;
-    const int lo_c = lo_l, hi_c = hi;
-    if (L + 1 < nlev) {
-      lo_l = hi;
-      hi = level_off(L + 2);
-      if (lo_l + lane < hi) {
-        w_nx = sp[lo_l + lane];
-        q_nx = sq[lo_l + lane];
-      }
-    }
-    for (int i = lo_c + lane; i < hi_c; i += 64) {
-      const uint32_t w = i == lo_c + lane ? w_cur : sp[i];
-      const T q = i == lo_c + lane ? q_cur : sq[i];
-      const int a = w & 0xFFFFu, b = w >> 16;
-      const T ka = si[a] * q, kb = si[b] * q;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const T va = sv[k * bmax + a], vb = sv[k * bmax + b];
-        const T dv = va - vb;
-        sv[k * bmax + a] = va + ka * dv;
-        sv[k * bmax + b] = vb - kb * dv;
-      }
+    const int lo_l = hi;
+    hi = level_off(L + 1);
+    for (int i = lo_l + lane; i < hi; i += 64) {
+      const PairQ<T> pq = sp[i];
+      const int a = pq.w & 0xFFFFu, b = pq.w >> 16;
+      vec4<T> va = sv[a], vb = sv[b];
+      const T ka = va.w * pq.q, kb = vb.w * pq.q;
+      const T dx = va.x - vb.x, dy = va.y - vb.y, dz = va.z - vb.z;
+      va.x += ka * dx;
+      va.y += ka * dy;
+      va.z += ka * dz;
+      vb.x -= kb * dx;
+      vb.y -= kb * dy;
+      vb.z -= kb * dz;
+      sv[a] = va;
+      sv[b] = vb;
     }
     // one wavefront: its LDS accesses complete in issue order, so the next
     // level reads what this one wrote without a barrier
@@ -699,8 +687,10 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
   __syncthreads();
   for (uint32_t l = lane; l < nblk; l += 64) {
     const int64_t gi = gidx(l);
-#pragma unroll
-    for (int k = 0; k < D; ++k) v[k * n + gi] = sv[k * bmax + l];
+    const vec4<T> x = sv[l];
+    v[gi] = x.x;
+    v[n + gi] = x.y;
+    if (D == 3) v[2 * n + gi] = x.z;
   }
 }
 
@@ -985,13 +975,13 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
     if (a1 <= a0) continue;
     const int bmax = (int)std::max<int64_t>(nb->damp_bmax[col], 1);
     const int pmax = (int)std::max<int64_t>(nb->damp_pmax[col], 1);
-    const size_t lds = (size_t)bmax * (D + 1) * sizeof(T) + (size_t)pmax * (sizeof(T) + 4) +
-                       4 * (size_t)(kDampMaxLevel + 1);
+    const size_t lds = (size_t)bmax * sizeof(vec4<T>) + (size_t)pmax * sizeof(PairQ<T>);
     int rc = lds_attr(k_damp<T, D>, lds);
     if (rc) return rc;
     {
       hipEvent_t pe_ = prof_begin(nb, s);
-      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, nb->dlev, dgeo, nb->aoff,
+      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, dgeo, nb->dloff,
+                                                       nb->dloff_base, nb->anlev, nb->aoff,
                                                        nb->ablk, a0, bmax, pmax, (T*)st->v,
                                                        st->flags, (T)(1.0 / m->rho0),
                                                        (T)(eta * dt), nb->ctrl, gated);
