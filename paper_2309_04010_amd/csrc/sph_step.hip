@@ -588,7 +588,10 @@ struct alignas(16) PairQ<double> {
   double q;
 };
 
-template <typename T, int D>
+// G lanes per anchor, 64 / G anchors per wavefront (one workgroup): the
+// lane groups run their anchors side by side, so every LDS instruction of
+// the serial level loop serves several anchors.
+template <typename T, int D, int G>
 __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restrict__ dpair,
                                              const T* __restrict__ dgeo,
                                              const uint16_t* __restrict__ dloff,
@@ -596,50 +599,68 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
                                              const uint32_t* __restrict__ anlev,
                                              const int64_t* __restrict__ aoff,
                                              const uint32_t* __restrict__ ablk, int64_t a_begin,
-                                             int bmax, int pmax, T* v,
+                                             int64_t a_end, int bmax, int pmax, int lmax, T* v,
                                              const uint8_t* __restrict__ flags, T inv_rho0,
                                              T eta_dt, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
+  constexpr int APW = 64 / G;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  vec4<T>* sv = reinterpret_cast<vec4<T>*>(smem_raw);           // [bmax] (v, inverse mass)
-  PairQ<T>* sp = reinterpret_cast<PairQ<T>*>(sv + bmax);          // [pmax]
+  const int grp = threadIdx.x / G, lg = threadIdx.x % G;
+  const size_t per = (size_t)bmax * sizeof(vec4<T>) + (size_t)pmax * sizeof(PairQ<T>) +
+                     (size_t)((lmax + 2) & ~1) * 2;
+  unsigned char* base_g = smem_raw + grp * ((per + 15) & ~(size_t)15);
+  vec4<T>* sv = reinterpret_cast<vec4<T>*>(base_g);           // [bmax] (v, inverse mass)
+  PairQ<T>* sp = reinterpret_cast<PairQ<T>*>(sv + bmax);      // [pmax]
+  uint16_t* so = reinterpret_cast<uint16_t*>(sp + pmax);      // [lmax + 1] level offsets
   const int64_t n = g.n;
-  const int64_t ai = a_begin + blockIdx.x;
-  const uint32_t* bl = ablk + 8 * ai;  // (begin, count) x 4 runs
-  const int lane = threadIdx.x;
-  const uint32_t c0 = bl[1], c1 = bl[3], c2 = bl[5], c3 = bl[7];
-  const uint32_t e0 = c0, e1 = e0 + c1, e2 = e1 + c2, nblk = e2 + c3;
+  const int64_t ai = a_begin + (int64_t)blockIdx.x * APW + grp;
+  const bool live = ai < a_end;
+  uint32_t nblk = 0, e0 = 0, e1 = 0, e2 = 0;
+  const uint32_t* bl = ablk + 8 * (live ? ai : a_begin);
+  if (live) {
+    e0 = bl[1];
+    e1 = e0 + bl[3];
+    e2 = e1 + bl[5];
+    nblk = e2 + bl[7];
+  }
   auto gidx = [&](uint32_t l) -> int64_t {
     return l < e0 ? (int64_t)bl[0] + l
                   : (l < e1 ? (int64_t)bl[2] + (l - e0)
                             : (l < e2 ? (int64_t)bl[4] + (l - e1) : (int64_t)bl[6] + (l - e2)));
   };
-  for (uint32_t l = lane; l < nblk; l += 64) {
-    const int64_t gi = gidx(l);
-    vec4<T> x;
-    x.x = v[gi];
-    x.y = v[n + gi];
-    x.z = D == 3 ? v[2 * n + gi] : T(0);
-    const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
-    x.w = fixed ? T(0) : inv_rho0 / g.V[gi];
-    sv[l] = x;
+  for (uint32_t l0 = lg; l0 < nblk; l0 += 2 * G) {
+    vec4<T> x[2];
+    const uint32_t ls[2] = {l0, l0 + G};
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ls[e] < nblk) {
+        const int64_t gi = gidx(ls[e]);
+        x[e].x = v[gi];
+        x[e].y = v[n + gi];
+        x[e].z = D == 3 ? v[2 * n + gi] : T(0);
+        const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
+        x[e].w = fixed ? T(0) : inv_rho0 / g.V[gi];
+      }
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ls[e] < nblk) sv[ls[e]] = x[e];
   }
-  const int64_t lo = aoff[ai];
-  const int np = (int)(aoff[ai + 1] - lo);
-  const int nlev = (int)anlev[ai];
-  const uint16_t* lof = dloff + dloff_base[ai];
-  // level offsets in registers: lane l holds offset 64 c + l
-  const uint32_t r0 = lane <= nlev ? lof[lane] : 0u;
-  const uint32_t r1 = 64 + lane <= nlev ? lof[64 + lane] : 0u;
-  const uint32_t r2 = 128 + lane <= nlev ? lof[128 + lane] : 0u;
-  const uint32_t r3 = 192 + lane <= nlev ? lof[192 + lane] : 0u;
+  int64_t lo = 0;
+  int np = 0, nlev = 0;
+  if (live) {
+    lo = aoff[ai];
+    np = (int)(aoff[ai + 1] - lo);
+    nlev = (int)anlev[ai];
+    const uint16_t* lof = dloff + dloff_base[ai];
+    for (int L = lg; L <= nlev; L += G) so[L] = lof[L];
+  }
   __syncthreads();
-  for (int i0 = lane; i0 < np; i0 += 4 * 64) {
+  for (int i0 = lg; i0 < np; i0 += 4 * G) {
     uint32_t w[4];
     T gg[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int i = i0 + 64 * u;
+      const int i = i0 + G * u;
       if (i < np) {
         w[u] = dpair[lo + i];
         gg[u] = dgeo[lo + i];
@@ -647,7 +668,7 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int i = i0 + 64 * u;
+      const int i = i0 + G * u;
       if (i < np) {
         const T beta = eta_dt * gg[u];
         PairQ<T> pq;
@@ -658,15 +679,11 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     }
   }
   __syncthreads();
-  auto level_off = [&](int L) -> int {
-    const uint32_t rr = L < 64 ? r0 : (L < 128 ? r1 : (L < 192 ? r2 : r3));
-    return __builtin_amdgcn_readlane((int)rr, L & 63);
-  };
-  int hi = level_off(0);
+  int hi = nlev > 0 ? so[0] : 0;
   for (int L = 0; L < nlev; ++L) {
     const int lo_l = hi;
-    hi = level_off(L + 1);
-    for (int i = lo_l + lane; i < hi; i += 64) {
+    hi = so[L + 1];
+    for (int i = lo_l + lg; i < hi; i += G) {
       const PairQ<T> pq = sp[i];
       const int a = pq.w & 0xFFFFu, b = pq.w >> 16;
       vec4<T> va = sv[a], vb = sv[b];
@@ -685,7 +702,7 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     // level reads what this one wrote without a barrier
   }
   __syncthreads();
-  for (uint32_t l = lane; l < nblk; l += 64) {
+  for (uint32_t l = lg; l < nblk; l += G) {
     const int64_t gi = gidx(l);
     const vec4<T> x = sv[l];
     v[gi] = x.x;
@@ -963,31 +980,64 @@ int solid_stage(const sph_nbr* nb, const sph_material* m, const sph_state* st, d
                       : solid_stage_t<float, 3>(nb, m, st, dt, s, gated);
 }
 
-template <typename T, int D>
-static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
-                     double dt, hipStream_t s, bool gated) {
+template <typename T, int D, int G>
+static int damp_launch(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
+                       double dt, hipStream_t s, bool gated, int col) {
   Geo<T> g = geo<T>(nb);
   const T* dgeo = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)nb->dgeo64
                                                            : (const void*)nb->dgeo32);
+  constexpr int APW = 64 / G;
+  const int64_t a0 = nb->color_off[col], a1 = nb->color_off[col + 1];
+  const int bmax = (int)std::max<int64_t>(nb->damp_bmax[col], 1);
+  const int pmax = (int)std::max<int64_t>(nb->damp_pmax[col], 1);
+  const int lmax = (int)std::max<int64_t>(nb->max_level, 1);
+  const size_t per = (size_t)bmax * sizeof(vec4<T>) + (size_t)pmax * sizeof(PairQ<T>) +
+                     (size_t)((lmax + 2) & ~1) * 2;
+  const size_t lds = APW * ((per + 15) & ~(size_t)15);
+  int rc = lds_attr(k_damp<T, D, G>, lds);
+  if (rc) return rc;
+  const unsigned grid = (unsigned)((a1 - a0 + APW - 1) / APW);
+  hipEvent_t pe_ = prof_begin(nb, s);
+  k_damp<T, D, G><<<grid, 64, lds, s>>>(g, nb->dpair, dgeo, nb->dloff, nb->dloff_base, nb->anlev,
+                                        nb->aoff, nb->ablk, a0, a1, bmax, pmax, lmax, (T*)st->v,
+                                        st->flags, (T)(1.0 / m->rho0), (T)(eta * dt), nb->ctrl,
+                                        gated);
+  prof_end(nb, SPH_KERNEL_DAMPING, pe_, s);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+#ifndef SPH_DAMP_LANES
+#define SPH_DAMP_LANES 32  // measured on the 1M-particle plate: 32 beats 16 and 64
+#endif
+
+template <typename T>
+static size_t damp_lds_per_anchor(const sph_nbr* nb, int col) {
+  const size_t bmax = (size_t)std::max<int64_t>(nb->damp_bmax[col], 1);
+  const size_t pmax = (size_t)std::max<int64_t>(nb->damp_pmax[col], 1);
+  const size_t lmax = (size_t)std::max<int64_t>(nb->max_level, 1);
+  return ((bmax * sizeof(vec4<T>) + pmax * sizeof(PairQ<T>) + ((lmax + 2) & ~(size_t)1) * 2) + 15) &
+         ~(size_t)15;
+}
+
+// Lanes per anchor: the preferred group width while the wavefront's LDS
+// stays within 64 KB (so that several wavefronts share a CU), else wider
+// groups, down to one anchor per wavefront for very dense blocks.
+template <typename T, int D>
+static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
+                     double dt, hipStream_t s, bool gated) {
   const int ncol = 1 << D;
   for (int col = 0; col < ncol; ++col) {
-    int64_t a0 = nb->color_off[col], a1 = nb->color_off[col + 1];
-    if (a1 <= a0) continue;
-    const int bmax = (int)std::max<int64_t>(nb->damp_bmax[col], 1);
-    const int pmax = (int)std::max<int64_t>(nb->damp_pmax[col], 1);
-    const size_t lds = (size_t)bmax * sizeof(vec4<T>) + (size_t)pmax * sizeof(PairQ<T>);
-    int rc = lds_attr(k_damp<T, D>, lds);
+    if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
+    const size_t per = damp_lds_per_anchor<T>(nb, col);
+    int rc;
+    if (SPH_DAMP_LANES <= 16 && 4 * per <= 64 * 1024)
+      rc = damp_launch<T, D, 16>(nb, m, st, eta, dt, s, gated, col);
+    else if (SPH_DAMP_LANES <= 32 && 2 * per <= 64 * 1024)
+      rc = damp_launch<T, D, 32>(nb, m, st, eta, dt, s, gated, col);
+    else
+      rc = damp_launch<T, D, 64>(nb, m, st, eta, dt, s, gated, col);
     if (rc) return rc;
-    {
-      hipEvent_t pe_ = prof_begin(nb, s);
-      k_damp<T, D><<<(unsigned)(a1 - a0), 64, lds, s>>>(g, nb->dpair, dgeo, nb->dloff,
-                                                       nb->dloff_base, nb->anlev, nb->aoff,
-                                                       nb->ablk, a0, bmax, pmax, (T*)st->v,
-                                                       st->flags, (T)(1.0 / m->rho0),
-                                                       (T)(eta * dt), nb->ctrl, gated);
-      prof_end(nb, SPH_KERNEL_DAMPING, pe_, s);
-    }
-    SPH_LAUNCH_CHECK();
   }
   return SPH_OK;
 }
