@@ -1,0 +1,277 @@
+"""Throughput of the multi-time-step TL-SPH hot path on one MI355X.
+
+Workload (default): the 3D membrane plate, 500 x 500 x 4 = 1,000,000
+particles (60,256,216 directed neighbour pairs), neo-Hookean solid with the
+fluid-pressure coupling, diffusion slow steps.  One bench "step" is one slow
+step: the diffusion update, then 1000 inner steps of {deformation gradient +
+stress, pair momentum + kick, implicit pairwise damping sweep (8 colour
+passes), drift + kinetic energy}, FP32 bulk arithmetic with FP64
+displacements and reductions, launched by the library's multi-time-step
+driver.  The neighbour build (once per configuration, total-Lagrangian) is
+setup and is not timed.
+
+Metric: inner-step particle-interactions/s = directed pairs x inner steps /
+wall time, inputs resident in HBM.  Also reported: the same run in plain FP64,
+the roofline of the dominant kernel (live event timing of every launch in the
+timed region), and the CPU oracle timed on a bounded sample.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner M] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def algorithmic_bytes(kernel, dim, prec_bytes, model_j2=False, n_colors=8):
+    """Minimum HBM bytes per particle per launch: each per-particle array the
+    kernel must read or write, once (neighbour lists and re-reads of
+    neighbours' data are not algorithmic)."""
+    T = prec_bytes
+    d, dd = dim, dim * dim
+    if kernel == "stress":
+        b = 8 * d + 8 * d + T + T * dd + T + T * dd      # u, X, V, B0, p | PB
+        if model_j2:
+            b += 2 * 7 * T
+        return b
+    if kernel == "momentum":
+        return 8 * d + T + T * dd + 2 * T * d + 1         # X, V, PB, v(rw), flags
+    if kernel == "damping":
+        return 8 * d + T + 2 * T * d + 1                  # X, V, v(rw), flags: every pass touches
+                                                          # each particle's block once
+    if kernel == "drift_ke":
+        return 2 * 8 * d + T * d + 8 + 1                  # u(rw), v, V, flags
+    if kernel == "diff_grad":
+        return 8 * d + T + T * dd + T + T * d             # X, V, B0, c | q
+    if kernel == "diff_div":
+        return 8 * d + T + T * dd + T * d + 2 * T + 1 + T  # X, V, B0, q, c(rw), flags | p
+    return 0.0
+
+
+def flops_per_pair(kernel, dim):
+    """Useful floating-point operations per directed pair (FMA = 2)."""
+    d = dim
+    geo = 3 * d + 6            # dx, r^2, sqrt, q, (1-q/2)^3 and scaling
+    if kernel == "stress":
+        return geo + d + 2 * d * d + 2 * d   # du, outer-product accumulation
+    if kernel == "momentum":
+        return geo + d * d + 2 * d * d + 2 * d
+    return 0
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: counter-based traffic is only reported while
+    the kernels are the ones the counters were taken on."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2309_04010_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def setup(case, prec, torch, B):
+    import numpy as np
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    nb = B.sph_build_neighbors(dev(case.X), dev(case.V), case.h)
+    perm = nb.host("perm").astype(np.int64)
+    st = B.new_state(nb, prec, with_diffusion=case.c_init is not None,
+                     with_plastic=case.material["model"] == 2)
+    st.flags = dev(case.flags[perm])
+    if case.c_init is not None:
+        T = torch.float32 if prec == B.SPH_F32 else torch.float64
+        st.c.copy_(dev(case.c_init[perm]).to(T))
+    if case.vgrip is not None:
+        T = torch.float32 if prec == B.SPH_F32 else torch.float64
+        st.vgrip = dev(case.vgrip[:, perm]).to(T).contiguous()
+    return nb, st
+
+
+def run_gpu(case, prec, steps, warmup, inner, torch, B, profile=True):
+    nb, st = setup(case, prec, torch, B)
+    mat = B.material(**case.material)
+    run = dict(case.run)
+    run.update(n_slow=1, fixed_inner=inner)
+    cfg = B.multirate_cfg(**run, chunk=min(inner, 250), use_graph=0)
+    for _ in range(warmup):
+        B.sph_advance_multirate(nb, mat, st, cfg)
+    torch.cuda.synchronize()
+    if profile:
+        B.sph_profile_enable(nb, True)
+    t0 = time.perf_counter()
+    total_inner = 0
+    for _ in range(steps):
+        rc, k, ke, conv, rep = B.sph_advance_multirate(nb, mat, st, cfg)
+        total_inner += int(k.sum())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = B.sph_profile_read(nb) if profile else {}
+    B.sph_profile_enable(nb, False)
+    rc, bits = B.sph_status(nb)
+    info = dict(n=nb.info.n, pairs=nb.info.n_pairs, dim=nb.info.dim, n_colors=nb.info.n_colors,
+                total_inner=total_inner, seconds=t1 - t0, status=bits,
+                u_finite=bool(torch.isfinite(st.u).all().item()))
+    nb.close()
+    return info, prof
+
+
+def cpu_baseline(case, seconds_budget=15.0):
+    """The oracle as it stands, single-threaded, on the same workload: build
+    (untimed), one diffusion step, then inner steps until the budget is
+    spent (at least one)."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(case.dim, case.X, case.V, case.h)
+    perm = o.perm
+    flags = np.ascontiguousarray(case.flags[perm])
+    mat = o.material(**case.material)
+    d, n = case.dim, o.n
+    u, v = o.arr(d, n), o.arr(d, n)
+    c = np.ascontiguousarray(case.c_init[perm]) if case.c_init is not None else None
+    q, p = o.arr(d, n), o.arr(n)
+    K = case.material["E"] / (3 * (1 - 2 * case.material["nu"]))
+    dt = 0.6 * case.h / np.sqrt(K / case.material["rho0"])
+    rho0 = case.material["rho0"]
+    t0 = time.perf_counter()
+    if c is not None:
+        o.diffusion_step(case.run["D"], 0.5 * case.h ** 2 / case.run["D"], case.run["c_bc"],
+                         case.material.get("C_swell", 0.0), case.material.get("c0", 0.0), c, q, p, flags)
+    steps = 0
+    while True:
+        o.solid_step(mat, dt, u, v, p=p, flags=flags)
+        o.damping_sweep(rho0, case.run["eta"], dt, v, flags)
+        o.drift_ke(rho0, dt, u, v, flags)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds_budget:
+            break
+    t1 = time.perf_counter()
+    return dict(value=o.n_pairs * steps / (t1 - t0), unit="interactions/s", cores=1, kind="oracle",
+                sample=f"{case.name} full size ({n} particles): one diffusion step + {steps} inner "
+                       f"steps, single thread, {t1 - t0:.1f} s (build not timed)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--nx", type=int, default=500)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2309_04010_amd import binding as B
+    from paper_2309_04010_amd import cases
+
+    torch.cuda.set_device(0)
+    case = cases.plate3d(nx=args.nx, ny=args.nx)
+    print(f"[bench] workload {case.name} n={case.n} inner={args.inner} steps={args.steps}", flush=True)
+    info32, prof32 = run_gpu(case, B.SPH_F32, args.steps, args.warmup, args.inner, torch, B)
+    print(f"[bench] fp32 done: {info32['seconds']:.3f} s", flush=True)
+    P = info32["pairs"]
+    value = P * info32["total_inner"] / info32["seconds"]
+    ms_per_step = 1000.0 * info32["seconds"] / args.steps
+
+    fp64 = None
+    if not args.no_fp64:
+        info64, prof64 = run_gpu(case, B.SPH_F64, max(1, args.steps - 1), args.warmup, args.inner,
+                                 torch, B, profile=False)
+        print(f"[bench] fp64 done: {info64['seconds']:.3f} s", flush=True)
+        v64 = P * info64["total_inner"] / info64["seconds"]
+        fp64 = dict(value=v64, ms_per_step=1000.0 * info64["seconds"] / max(1, args.steps - 1),
+                    speedup_fp32=value / v64, status=info64["status"])
+
+    # dominant kernel of the timed FP32 region
+    kern = max(prof32, key=lambda k: prof32[k][1])
+    launches, kms = prof32[kern]
+    avg_s = kms / 1000.0 / max(launches, 1)
+    nper = info32["n"]
+    alg_bytes = algorithmic_bytes(kern, info32["dim"], 4, n_colors=info32["n_colors"]) * nper
+    achieved_gbs = alg_bytes / avg_s / 1e9
+    workload_key = f"plate3d-{args.nx}x{args.nx}x4-fp32"
+    roofline = dict(bound="hbm", kernel=kern, achieved=achieved_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved_gbs / HBM_PEAK_GBS, traffic=measured_traffic(kern, workload_key),
+                    avg_launch_us=avg_s * 1e6, launches=launches,
+                    alg_bytes_per_launch=alg_bytes)
+    fpp = flops_per_pair(kern, info32["dim"])
+    if fpp:
+        roofline["alu_tflops"] = fpp * P / avg_s / 1e12
+        roofline["alu_frac_fp32"] = roofline["alu_tflops"] / FP32_PEAK_TFLOPS
+    kernels = {k: dict(launches=c, avg_us=(1000.0 * ms / c if c else 0.0), total_ms=ms)
+               for k, (c, ms) in prof32.items() if c}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None if args.no_cpu else cpu_baseline(case)
+    out = {
+        "metric": "inner-step particle-interactions/s FP32+adjoint vs FP64 plain; %HBM roofline",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plate3d {args.nx}x{args.nx}x4 membrane ({info32['n']} particles, {P} directed "
+                        f"pairs), neo-Hookean + fluid pressure, diffusion slow step + {args.inner} "
+                        f"inner steps per step, FP32 bulk / FP64 displacement, forward only",
+            "adjoint": False,
+            "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+        "kernels": kernels,
+        "fp64_plain": fp64,
+        "cpu_baseline": cpu,
+        "status_bits": info32["status"],
+        "u_finite": info32["u_finite"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
