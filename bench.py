@@ -3,16 +3,20 @@
 Workload (default): the 3D membrane plate, 500 x 500 x 4 = 1,000,000
 particles (60,256,216 directed neighbour pairs), neo-Hookean solid with the
 fluid-pressure coupling, diffusion slow steps.  One bench "step" is one slow
-step: the diffusion update, then 1000 inner steps of {deformation gradient +
-stress, pair momentum + kick, implicit pairwise damping sweep (8 colour
-passes), drift + kinetic energy}, FP32 bulk arithmetic with FP64
-displacements and reductions, launched by the library's multi-time-step
-driver.  The neighbour build (once per configuration, total-Lagrangian) is
-setup and is not timed.
+step run forward and then in reverse: the diffusion update and 1000 inner
+steps of {deformation gradient + stress, pair momentum + kick, implicit
+pairwise damping sweep (8 colour passes), drift + kinetic energy}, with u
+before every inner step recorded, followed by the reverse pass (1000
+transposed inner steps and the transposed diffusion step) that gives the
+gradient of the mean centre deflection with respect to E, D and C.  FP32 bulk
+arithmetic with FP64 displacements and reductions.  The neighbour build (once
+per configuration, total-Lagrangian) is setup and is not timed.
 
 Metric: inner-step particle-interactions/s = directed pairs x inner steps /
-wall time, inputs resident in HBM.  Also reported: the same run in plain FP64,
-the roofline of the dominant kernel (live event timing of every launch in the
+wall time of forward + reverse, inputs resident in HBM.  Also reported: the
+FP32 forward alone, the plain FP64 forward (the baseline of the speedup), the
+FP32 state and gradient errors against an FP64 run of the same step, the
+roofline of the dominant kernel (live event timing of every launch in the
 timed region), and the CPU oracle timed on a bounded sample.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner M] [--no-cpu]
@@ -56,6 +60,16 @@ def algorithmic_bytes(kernel, dim, prec_bytes, model_j2=False, n_colors=8):
         return 8 * d + T + T * dd + T + T * d             # X, V, B0, c | q
     if kernel == "diff_div":
         return 8 * d + T + T * dd + T * d + 2 * T + 1 + T  # X, V, B0, q, c(rw), flags | p
+    if kernel == "adj_stress":
+        # X, V, B0, u_k, w, flags, p | G_bar, p_bar(rw, f64)
+        b = 8 * d + T + T * dd + 8 * d + T * d + 1 + T + T * dd + 16
+        if model_j2:
+            b += 7 * T + 2 * 7 * T
+        return b
+    if kernel == "adj_gather":
+        return 8 * d + T + T * dd + 16 * d + 2 * T * d + 1   # X, V, G_bar, u_bar(rw), w(rw), flags
+    if kernel == "adj_damping":
+        return 8 * d + T + 2 * T * d + 1
     return 0.0
 
 
@@ -176,6 +190,51 @@ def cpu_baseline(case, seconds_budget=15.0):
                        f"steps, single thread, {t1 - t0:.1f} s (build not timed)")
 
 
+def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
+    """Forward (taped) + reverse of one slow step, `steps` times; returns
+    timing, the final u of the last forward run and the gradient."""
+    import numpy as np
+    import dataclasses
+    run = dict(case.run)
+    run.update(n_slow=1, fixed_inner=inner)
+    c = dataclasses.replace(case, run=run)
+    pr = A.MultirateProblem(c, prec, k_hist=inner, chunk=min(inner, 250))
+    th = pr.theta0()
+    idx = pr.perm.argsort()[case.observable["J_index"]]
+    w = torch.zeros((case.dim, case.n), dtype=torch.float64, device="cuda")
+    w[case.observable["J_component"], torch.as_tensor(idx).cuda()] = 1.0 / len(idx)
+    for _ in range(warmup):
+        pr.forward(th)
+        pr.backward(w)
+    torch.cuda.synchronize()
+    if profile:
+        B.sph_profile_enable(pr.nb, True)
+    t0 = time.perf_counter()
+    t_fwd = 0.0
+    total_inner = 0
+    g = None
+    for _ in range(steps):
+        ta = time.perf_counter()
+        pr.forward(th)
+        torch.cuda.synchronize()
+        t_fwd += time.perf_counter() - ta
+        total_inner += int(pr.last["k"].sum())
+        g = pr.backward(w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = B.sph_profile_read(pr.nb) if profile else {}
+    B.sph_profile_enable(pr.nb, False)
+    rc, bits = B.sph_status(pr.nb)
+    u = pr.st.u.detach().double().cpu().numpy()
+    info = dict(n=pr.nb.info.n, pairs=pr.nb.info.n_pairs, dim=pr.nb.info.dim,
+                n_colors=pr.nb.info.n_colors, total_inner=total_inner, seconds=t1 - t0,
+                seconds_forward=t_fwd, status=bits, grad=g.cpu().numpy(),
+                J=float((pr.st.u * w).sum().item()), u=u,
+                u_finite=bool(np.isfinite(u).all()))
+    pr.close()
+    return info, prof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,47 +252,71 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
+    from paper_2309_04010_amd import adjoint as A
     from paper_2309_04010_amd import binding as B
     from paper_2309_04010_amd import cases
 
     torch.cuda.set_device(0)
     case = cases.plate3d(nx=args.nx, ny=args.nx)
     print(f"[bench] workload {case.name} n={case.n} inner={args.inner} steps={args.steps}", flush=True)
-    info32, prof32 = run_gpu(case, B.SPH_F32, args.steps, args.warmup, args.inner, torch, B)
-    print(f"[bench] fp32 done: {info32['seconds']:.3f} s", flush=True)
-    P = info32["pairs"]
-    value = P * info32["total_inner"] / info32["seconds"]
-    ms_per_step = 1000.0 * info32["seconds"] / args.steps
+    adj32, prof32 = run_adjoint(case, B.SPH_F32, args.steps, args.warmup, args.inner, torch, B, A)
+    print(f"[bench] fp32 forward+adjoint done: {adj32['seconds']:.3f} s", flush=True)
+    P = adj32["pairs"]
+    value = P * adj32["total_inner"] / adj32["seconds"]
+    ms_per_step = 1000.0 * adj32["seconds"] / args.steps
+    fwd32 = dict(value=P * adj32["total_inner"] / adj32["seconds_forward"],
+                 ms_per_step=1000.0 * adj32["seconds_forward"] / args.steps)
 
     fp64 = None
+    accuracy = None
     if not args.no_fp64:
-        info64, prof64 = run_gpu(case, B.SPH_F64, max(1, args.steps - 1), args.warmup, args.inner,
-                                 torch, B, profile=False)
-        print(f"[bench] fp64 done: {info64['seconds']:.3f} s", flush=True)
+        info64, _ = run_gpu(case, B.SPH_F64, max(1, args.steps - 1), args.warmup, args.inner,
+                            torch, B, profile=False)
+        print(f"[bench] fp64 plain done: {info64['seconds']:.3f} s", flush=True)
         v64 = P * info64["total_inner"] / info64["seconds"]
         fp64 = dict(value=v64, ms_per_step=1000.0 * info64["seconds"] / max(1, args.steps - 1),
-                    speedup_fp32=value / v64, status=info64["status"])
+                    status=info64["status"])
+        # accuracy of the FP32 step (state and gradient) against the same step in FP64
+        adj64, _ = run_adjoint(case, B.SPH_F64, 1, 0, args.inner, torch, B, A, profile=False)
+        print("[bench] fp64 forward+adjoint reference done", flush=True)
+        ue = float(np.abs(adj32["u"] - adj64["u"]).max() / np.abs(adj64["u"]).max())
+        gr = {B.GRAD_NAMES[i]: dict(fp32=float(adj32["grad"][i]), fp64=float(adj64["grad"][i]),
+                                    rel_err=float(abs(adj32["grad"][i] - adj64["grad"][i]) /
+                                                  abs(adj64["grad"][i])))
+              for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)}
+        accuracy = dict(reference="the same step on the FP64 GPU path (itself within 1e-10 of the "
+                                  "FP64 oracle in the parity tests)",
+                        u_rel_err=ue, J_fp32=adj32["J"], J_fp64=adj64["J"], grad=gr)
 
-    # dominant kernel of the timed FP32 region
+    # dominant kernel class of the timed FP32 region
     kern = max(prof32, key=lambda k: prof32[k][1])
     launches, kms = prof32[kern]
     avg_s = kms / 1000.0 / max(launches, 1)
-    nper = info32["n"]
-    alg_bytes = algorithmic_bytes(kern, info32["dim"], 4, n_colors=info32["n_colors"]) * nper
+    nper = adj32["n"]
+    alg_bytes = algorithmic_bytes(kern, adj32["dim"], 4, n_colors=adj32["n_colors"]) * nper
     achieved_gbs = alg_bytes / avg_s / 1e9
     workload_key = f"plate3d-{args.nx}x{args.nx}x4-fp32"
     roofline = dict(bound="hbm", kernel=kern, achieved=achieved_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved_gbs / HBM_PEAK_GBS, traffic=measured_traffic(kern, workload_key),
                     avg_launch_us=avg_s * 1e6, launches=launches,
                     alg_bytes_per_launch=alg_bytes)
-    fpp = flops_per_pair(kern, info32["dim"])
+    fpp = flops_per_pair(kern, adj32["dim"])
     if fpp:
         roofline["alu_tflops"] = fpp * P / avg_s / 1e12
         roofline["alu_frac_fp32"] = roofline["alu_tflops"] / FP32_PEAK_TFLOPS
-    kernels = {k: dict(launches=c, avg_us=(1000.0 * ms / c if c else 0.0), total_ms=ms)
-               for k, (c, ms) in prof32.items() if c}
+    kernels = {}
+    for k, (c, ms) in prof32.items():
+        if not c:
+            continue
+        kernels[k] = dict(launches=c, avg_us=1000.0 * ms / c, total_ms=ms)
+        try:
+            ab = algorithmic_bytes(k, adj32["dim"], 4) * nper
+            kernels[k]["alg_GBps"] = ab / (ms / 1000.0 / c) / 1e9
+        except TypeError:
+            pass
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -257,18 +340,24 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"plate3d {args.nx}x{args.nx}x4 membrane ({info32['n']} particles, {P} directed "
-                        f"pairs), neo-Hookean + fluid pressure, diffusion slow step + {args.inner} "
-                        f"inner steps per step, FP32 bulk / FP64 displacement, forward only",
-            "adjoint": False,
+            "workload": f"plate3d {args.nx}x{args.nx}x4 membrane ({adj32['n']} particles, {P} directed "
+                        f"pairs), neo-Hookean + fluid pressure; per step one diffusion slow step + "
+                        f"{args.inner} inner steps forward (taped), then the reverse pass for "
+                        f"d(mean centre deflection)/d(E, D, C); FP32 bulk / FP64 displacement",
+            "adjoint": True,
             "parallelism": "single GPU",
         },
         "roofline": roofline,
         "kernels": kernels,
+        "fp32_forward_only": fwd32,
         "fp64_plain": fp64,
+        "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
+        "accuracy": accuracy,
+        "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
+                     for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,
-        "status_bits": info32["status"],
-        "u_finite": info32["u_finite"],
+        "status_bits": adj32["status"],
+        "u_finite": adj32["u_finite"],
     }
     print(json.dumps(out), flush=True)
 

@@ -116,7 +116,8 @@ typedef struct {
   double* u;     /* [dim][n] displacement, always FP64 */
   void* v;       /* [dim][n] velocity */
   void* PB;      /* [dim*dim][n] P B0 (written by the stress stage, read by momentum) */
-  void* plastic; /* [7][n] J2 state: Cbar_p^-1 (xx,yy,zz,xy,yz,xz) and alpha; NULL unless J2 */
+  void* plastic; /* [7][n] J2 state: Cbar_p^-1 - I (xx,yy,zz,xy,yz,xz) and alpha (zeros = virgin
+                    material); NULL unless J2 */
   void* c;       /* [n] saturation (diffusion) or NULL */
   void* q;       /* [dim][n] flux scratch of the diffusion step or NULL */
   void* p;       /* [n] fluid pressure used by the stress stage, or NULL (no swelling) */
@@ -218,14 +219,132 @@ int sph_load_step(const sph_nbr* nbr, const sph_state* st, double dt_l, void* st
 int sph_diffusion_step(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
                        double D, double dt_d, double c_bc, void* stream);
 
+/* Recording of a forward multi-time-step run for the reverse pass
+ * (sph_advance_multirate_backward).  All arrays are caller-owned DEVICE
+ * memory except k_rec (host).  Slice l of a checkpoint array holds the state
+ * at the start of slow step l (before its load or diffusion update); slice
+ * n_slow holds the final state.  hist_u receives u before every inner step of
+ * one slow step (the last one of the forward run, when it fits, and each slow
+ * step again while the reverse pass recomputes it), hist_plastic the J2 state
+ * likewise.  Sizes: ck_u [n_slow_cap+1][dim][n] f64, ck_v [n_slow_cap+1][dim][n],
+ * ck_plastic [n_slow_cap+1][7][n] (J2 only, else NULL), ck_c [n_slow_cap+1][n]
+ * (diffusion only, else NULL), hist_u [k_hist_cap][dim][n] f64,
+ * hist_plastic [k_hist_cap][7][n] (J2 only, else NULL); prec-typed arrays
+ * follow sph_state.prec. */
+typedef struct {
+  int32_t n_slow_cap;  /* slow steps that fit */
+  int32_t pad_;
+  int64_t k_hist_cap;  /* inner steps of one slow step that fit in hist_u */
+  double* ck_u;
+  void* ck_v;
+  void* ck_plastic;
+  void* ck_c;
+  double* hist_u;
+  void* hist_plastic;
+  int64_t* k_rec;      /* host [n_slow_cap]: inner steps taken per slow step (out) */
+  int32_t n_rec;       /* out: slow steps recorded */
+  int32_t hist_slow;   /* out: slow step whose inner states hist_u holds, -1 if none */
+  double dt_s;         /* out: inner step used (frozen for the reverse pass) */
+  double dt_slow;      /* out: slow step used */
+} sph_tape;
+
 /* Multi-time-step driver (Sec. 4.2): for l = 1..n_slow, one slow step (load
  * or diffusion), then inner steps {solid stage, damping sweep, drift + E_k}
  * until E_k <= ke_tol, or k = k_max (warning), or exactly fixed_inner /
  * k_sched[l] steps.  The stop test runs on the device; the host polls once per
- * chunk of inner steps.  Synchronous; fills the host report.  Returns SPH_OK,
- * SPH_W_NOT_CONVERGED, or an error. */
+ * chunk of inner steps.  `tape` (may be NULL) records the run for the reverse
+ * pass; it requires cfg->use_graph == 0 for the slow step whose inner states
+ * are recorded.  Synchronous; fills the host report.  Returns SPH_OK,
+ * SPH_W_NOT_CONVERGED, or an error (SPH_E_CAPACITY: n_slow > n_slow_cap). */
 int sph_advance_multirate(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
-                          const sph_multirate_cfg* cfg, sph_report* report, void* stream);
+                          const sph_multirate_cfg* cfg, sph_report* report, sph_tape* tape,
+                          void* stream);
+
+/* ------------------------------------------------------------------------
+ * Reverse mode.  The pass runs the transposed linear maps of the inner step
+ * in reverse order -- drift, damping sweep (colours, levels and pair maps
+ * reversed), kick, momentum sum, stress (exact derivative of the constitutive
+ * update, the J2 return mapping through the implicit-function theorem on its
+ * scalar residual), displacement-gradient sum -- then the transposed slow
+ * step.  The schedule (inner counts, dt_s, dt_slow) is held fixed: the
+ * gradient is that of the discrete map the forward run executed.  Parameter
+ * gradients accumulate in FP64, in a fixed order (deterministic). */
+#define SPH_GRAD_E 0      /* Young's modulus (mu and K scale with E at fixed nu) */
+#define SPH_GRAD_D 1      /* diffusion coefficient */
+#define SPH_GRAD_C 2      /* fluid-pressure coefficient C_swell */
+#define SPH_GRAD_S0 3     /* hardening sigma0 */
+#define SPH_GRAD_SINF 4   /* hardening sigma_inf */
+#define SPH_GRAD_DELTA 5  /* hardening delta */
+#define SPH_GRAD_H 6      /* hardening H (linear term) */
+#define SPH_NGRAD 7
+
+/* Adjoint state: the derivative of a scalar objective with respect to each
+ * state array.  Caller-owned device memory; prec as in sph_state. */
+typedef struct {
+  int32_t prec;
+  int32_t pad_;
+  double* u;      /* [dim][n] adjoint of u (FP64) */
+  void* v;        /* [dim][n] adjoint of v */
+  void* plastic;  /* [7][n] adjoint of the J2 state, NULL unless J2 */
+  void* c;        /* [n] adjoint of the saturation, NULL without diffusion */
+  double* p;      /* [n] adjoint of the fluid pressure, accumulated over the inner steps
+                     of a slow step (FP64), or NULL */
+  void* work;     /* [dim*dim][n] scratch */
+  double* grad;   /* [SPH_NGRAD] parameter gradients, accumulated (+=) */
+} sph_adjoint;
+
+/* Reverse of sph_solid_relax_step.  Inputs: st->u and st->plastic as they
+ * were BEFORE the forward step (neither is modified), st->p, st->flags;
+ * adj->v = adjoint of v after the kick (unchanged: the kick passes it
+ * through); adj->plastic = adjoint of the J2 state after the step, replaced
+ * by the adjoint before it.  Accumulates: adj->u (+=), adj->p (+=, if not
+ * NULL), adj->grad[E, S0, SINF, DELTA, H] (+=).  Uses adj->work.  Async. */
+int sph_solid_relax_step_vjp(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                             const sph_adjoint* adj, double dt_s, void* stream);
+
+/* Reverse of sph_damping_sweep: adj->v <- S^T adj->v, S the (linear) sweep
+ * map.  st supplies flags.  Async. */
+int sph_damping_sweep_vjp(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                          const sph_adjoint* adj, double eta, double dt_s, void* stream);
+
+/* Reverse of the drift: adj->v += dt_s adj->u for free particles.  Async. */
+int sph_drift_vjp(const sph_nbr* nbr, const sph_state* st, const sph_adjoint* adj, double dt_s,
+                  void* stream);
+
+/* Reverse of sph_diffusion_step.  st->c = saturation AFTER the forward step,
+ * c_before = saturation before it (device, prec-typed [n]); adj->c = adjoint
+ * of c after the step (replaced by the adjoint before it); adj->p = adjoint of
+ * p after the step (consumed: zeroed).  Accumulates adj->grad[D, C].  Uses
+ * adj->work ([dim][n]).  Async. */
+int sph_diffusion_step_vjp(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                           const void* c_before, const sph_adjoint* adj, double D, double dt_d,
+                           double c_bc, void* stream);
+
+/* Reverse pass of a taped sph_advance_multirate run with the same cfg.  On
+ * entry adj->u, adj->v (and adj->plastic, adj->c) hold the adjoint of the
+ * final state; on return they hold the adjoint of the initial state and
+ * adj->grad has the parameter gradients added.  The pass re-runs each slow
+ * step from its checkpoint (recording its inner states, k_rec[l] <=
+ * k_hist_cap required) unless hist_u already holds it; st is used as working
+ * storage and restored to the final state on return.  adj->p must be zero on
+ * entry.  Synchronous.  Errors: SPH_E_ARG (tape incomplete), SPH_E_CAPACITY. */
+int sph_advance_multirate_backward(const sph_nbr* nbr, const sph_material* mat,
+                                   const sph_state* st, const sph_multirate_cfg* cfg,
+                                   sph_tape* tape, const sph_adjoint* adj, void* stream);
+
+/* Point evaluation of the constitutive update (App. A) and its reverse, per
+ * particle, for n independent particles: H [9][n] = F - I (row-major 3x3),
+ * plastic [7][n] (J2, updated in place by sph_constitutive; read-only in the
+ * vjp), p [n] or NULL, P [9][n] first Piola-Kirchhoff stress.  The vjp takes
+ * Pbar [9][n] and plastic_bar [7][n] (adjoint of the updated state; replaced
+ * by the adjoint of the state before) and writes Hbar [9][n], pbar [n] and
+ * theta_bar [5][n] (per-particle derivatives with respect to E, sigma0,
+ * sigma_inf, delta, H).  prec-typed arrays.  Async. */
+int sph_constitutive(const sph_material* mat, int prec, int64_t n, const void* H, void* plastic,
+                     const void* p, void* P, void* stream);
+int sph_constitutive_vjp(const sph_material* mat, int prec, int64_t n, const void* H,
+                         const void* plastic, const void* p, const void* Pbar, void* plastic_bar,
+                         void* Hbar, void* pbar, void* theta_bar, void* stream);
 
 /* Synchronise `stream` and return (and clear) the latched status bits in
  * *status_bits (may be NULL): SPH_OK, or SPH_E_NUMERIC if any bit was set. */
@@ -244,7 +363,10 @@ int sph_status(const sph_nbr* nbr, void* stream, int32_t* status_bits);
 #define SPH_KERNEL_DIFF_GRAD 4 /* diffusion flux */
 #define SPH_KERNEL_DIFF_DIV 5  /* diffusion divergence + Dirichlet + pressure */
 #define SPH_KERNEL_LOAD 6      /* grip displacement increment */
-#define SPH_KERNEL_COUNT 7
+#define SPH_KERNEL_ADJ_STRESS 7  /* reverse: stress + momentum transpose */
+#define SPH_KERNEL_ADJ_GATHER 8  /* reverse: displacement-gradient transpose (+ drift) */
+#define SPH_KERNEL_ADJ_DAMPING 9 /* reverse: one colour pass of the transposed sweep */
+#define SPH_KERNEL_COUNT 10
 int sph_profile_enable(sph_nbr* nbr, int enable);
 int sph_profile_read(sph_nbr* nbr, int kernel_class, int64_t* launches, double* total_ms);
 

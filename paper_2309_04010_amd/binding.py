@@ -27,9 +27,15 @@ EXPORTED = [
     "sph_build_neighbors", "sph_nbr_destroy", "sph_nbr_query", "sph_solid_relax_step",
     "sph_damping_sweep", "sph_drift_ke", "sph_load_step", "sph_diffusion_step",
     "sph_advance_multirate", "sph_status", "sph_profile_enable", "sph_profile_read",
-    "sph_last_error",
+    "sph_last_error", "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_drift_vjp",
+    "sph_diffusion_step_vjp", "sph_advance_multirate_backward", "sph_constitutive",
+    "sph_constitutive_vjp",
 ]
-SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load"]
+SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load",
+                    "adj_stress", "adj_gather", "adj_damping"]
+SPH_GRAD_E, SPH_GRAD_D, SPH_GRAD_C, SPH_GRAD_S0, SPH_GRAD_SINF, SPH_GRAD_DELTA, SPH_GRAD_H = range(7)
+SPH_NGRAD = 7
+GRAD_NAMES = ["E", "D", "C_swell", "sigma0", "sigma_inf", "delta", "H"]
 
 
 class SphError(RuntimeError):
@@ -67,6 +73,17 @@ class MultirateCfg(C.Structure):
                 ("chunk", i32), ("use_graph", i32), ("k_sched", vp)]
 
 
+class Tape(C.Structure):
+    _fields_ = [("n_slow_cap", i32), ("pad_", i32), ("k_hist_cap", i64), ("ck_u", vp), ("ck_v", vp),
+                ("ck_plastic", vp), ("ck_c", vp), ("hist_u", vp), ("hist_plastic", vp), ("k_rec", vp),
+                ("n_rec", i32), ("hist_slow", i32), ("dt_s", dbl), ("dt_slow", dbl)]
+
+
+class Adjoint(C.Structure):
+    _fields_ = [("prec", i32), ("pad_", i32), ("u", vp), ("v", vp), ("plastic", vp), ("c", vp),
+                ("p", vp), ("work", vp), ("grad", vp)]
+
+
 class Report(C.Structure):
     _fields_ = [("k", vp), ("ke", vp), ("converged", vp), ("dt_s", dbl), ("dt_slow", dbl),
                 ("k_max", i64), ("total_inner", i64)]
@@ -92,7 +109,20 @@ def lib():
     L.sph_load_step.argtypes = [vp, C.POINTER(State), dbl, vp]
     L.sph_diffusion_step.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, dbl, vp]
     L.sph_advance_multirate.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
-                                        C.POINTER(MultirateCfg), C.POINTER(Report), vp]
+                                        C.POINTER(MultirateCfg), C.POINTER(Report), C.POINTER(Tape), vp]
+    L.sph_advance_multirate_backward.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
+                                                 C.POINTER(MultirateCfg), C.POINTER(Tape),
+                                                 C.POINTER(Adjoint), vp]
+    L.sph_solid_relax_step_vjp.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
+                                           C.POINTER(Adjoint), dbl, vp]
+    L.sph_damping_sweep_vjp.argtypes = [vp, C.POINTER(Material), C.POINTER(State), C.POINTER(Adjoint),
+                                        dbl, dbl, vp]
+    L.sph_drift_vjp.argtypes = [vp, C.POINTER(State), C.POINTER(Adjoint), dbl, vp]
+    L.sph_diffusion_step_vjp.argtypes = [vp, C.POINTER(Material), C.POINTER(State), vp,
+                                         C.POINTER(Adjoint), dbl, dbl, dbl, vp]
+    L.sph_constitutive.argtypes = [C.POINTER(Material), C.c_int, i64, vp, vp, vp, vp, vp]
+    L.sph_constitutive_vjp.argtypes = [C.POINTER(Material), C.c_int, i64, vp, vp, vp, vp, vp, vp, vp,
+                                       vp, vp]
     L.sph_status.argtypes = [vp, vp, C.POINTER(i32)]
     L.sph_profile_enable.argtypes = [vp, C.c_int]
     L.sph_profile_read.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)]
@@ -320,7 +350,7 @@ def multirate_cfg(n_slow, slow_kind, dt_slow=0.0, dt_s=0.0, eta=0.0, k_max=0, fi
     return cfg
 
 
-def sph_advance_multirate(nbr, mat, st, cfg, stream=None):
+def sph_advance_multirate(nbr, mat, st, cfg, tape=None, stream=None):
     """Returns (rc, k[n_slow], ke[n_slow], converged[n_slow], report)."""
     cs = st.cstruct(nbr)
     ns = cfg.n_slow
@@ -328,9 +358,168 @@ def sph_advance_multirate(nbr, mat, st, cfg, stream=None):
     ke = np.zeros(max(ns, 1))
     conv = np.zeros(max(ns, 1), np.int32)
     rep = Report(k.ctypes.data_as(vp), ke.ctypes.data_as(vp), conv.ctypes.data_as(vp), 0.0, 0.0, 0, 0)
+    tp = None if tape is None else C.byref(tape.cstruct(nbr, st))
     rc = _check(lib().sph_advance_multirate(nbr.handle, C.byref(mat), C.byref(cs), C.byref(cfg),
-                                            C.byref(rep), _stream(stream)), allow_warning=True)
+                                            C.byref(rep), tp, _stream(stream)), allow_warning=True)
+    if tape is not None:
+        tape.sync_out()
     return rc, k[:ns], ke[:ns], conv[:ns], rep
+
+
+# --- reverse mode -------------------------------------------------------------
+class SphTape:
+    """Device checkpoints of a forward multi-time-step run (sph_tape)."""
+
+    def __init__(self, nbr, prec, n_slow, k_hist, with_plastic=False, with_diffusion=False,
+                 device="cuda"):
+        import torch
+        d, n = nbr.dim, nbr.n
+        T = torch.float32 if prec == SPH_F32 else torch.float64
+        z = lambda *s, dt=T: torch.zeros(s, dtype=dt, device=device)  # noqa: E731
+        self.prec = prec
+        self.n_slow_cap = int(n_slow)
+        self.k_hist_cap = int(k_hist)
+        self.ck_u = z(n_slow + 1, d, n, dt=torch.float64)
+        self.ck_v = z(n_slow + 1, d, n)
+        self.ck_plastic = z(n_slow + 1, 7, n) if with_plastic else None
+        self.ck_c = z(n_slow + 1, n) if with_diffusion else None
+        self.hist_u = z(max(k_hist, 1), d, n, dt=torch.float64)
+        self.hist_plastic = z(max(k_hist, 1), 7, n) if with_plastic else None
+        self.k_rec = np.zeros(max(n_slow, 1), np.int64)
+        self._c = Tape(self.n_slow_cap, 0, self.k_hist_cap, _dptr(self.ck_u), _dptr(self.ck_v),
+                       _dptr(self.ck_plastic), _dptr(self.ck_c), _dptr(self.hist_u),
+                       _dptr(self.hist_plastic), self.k_rec.ctypes.data_as(vp), 0, -1, 0.0, 0.0)
+
+    def cstruct(self, nbr, st):
+        if st.prec != self.prec:
+            raise SphError(SPH_E_ARG, "tape and state precisions differ")
+        return self._c
+
+    def sync_out(self):
+        self.n_rec = self._c.n_rec
+        self.hist_slow = self._c.hist_slow
+        self.dt_s = self._c.dt_s
+        self.dt_slow = self._c.dt_slow
+
+
+@dataclass
+class SphAdjoint:
+    """Adjoint state (sph_adjoint): device tensors, same layout as SphState."""
+    prec: int
+    u: object
+    v: object
+    work: object
+    grad: object
+    plastic: object = None
+    c: object = None
+    p: object = None
+
+    def cstruct(self, nbr):
+        import torch
+        d, n = nbr.dim, nbr.n
+        T = torch.float32 if self.prec == SPH_F32 else torch.float64
+        _need(self.u, torch.float64, (d, n), "adj.u")
+        _need(self.v, T, (d, n), "adj.v")
+        _need(self.work, T, (d * d, n), "adj.work")
+        _need(self.grad, torch.float64, (SPH_NGRAD,), "adj.grad")
+        _need(self.plastic, T, (7, n), "adj.plastic")
+        _need(self.c, T, (n,), "adj.c")
+        _need(self.p, torch.float64, (n,), "adj.p")
+        return Adjoint(int(self.prec), 0, _dptr(self.u), _dptr(self.v), _dptr(self.plastic), _dptr(self.c),
+                       _dptr(self.p), _dptr(self.work), _dptr(self.grad))
+
+    def zero_(self):
+        for t in (self.u, self.v, self.work, self.grad, self.plastic, self.c, self.p):
+            if t is not None:
+                t.zero_()
+        return self
+
+
+def new_adjoint(nbr, prec, with_plastic=False, with_diffusion=False, with_p=False, device="cuda"):
+    import torch
+    d, n = nbr.dim, nbr.n
+    T = torch.float32 if prec == SPH_F32 else torch.float64
+    z = lambda *s, dt=T: torch.zeros(s, dtype=dt, device=device)  # noqa: E731
+    a = SphAdjoint(prec, z(d, n, dt=torch.float64), z(d, n), z(d * d, n), z(SPH_NGRAD, dt=torch.float64))
+    if with_plastic:
+        a.plastic = z(7, n)
+    if with_diffusion:
+        a.c = z(n)
+    if with_diffusion or with_p:
+        a.p = z(n, dt=torch.float64)
+    return a
+
+
+def sph_advance_multirate_backward(nbr, mat, st, cfg, tape, adj, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_advance_multirate_backward(nbr.handle, C.byref(mat), C.byref(cs), C.byref(cfg),
+                                                C.byref(tape.cstruct(nbr, st)), C.byref(adj.cstruct(nbr)),
+                                                _stream(stream)))
+    tape.sync_out()
+
+
+def sph_solid_relax_step_vjp(nbr, mat, st, adj, dt_s, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_solid_relax_step_vjp(nbr.handle, C.byref(mat), C.byref(cs), C.byref(adj.cstruct(nbr)),
+                                          float(dt_s), _stream(stream)))
+
+
+def sph_damping_sweep_vjp(nbr, mat, st, adj, eta, dt_s, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_damping_sweep_vjp(nbr.handle, C.byref(mat), C.byref(cs), C.byref(adj.cstruct(nbr)),
+                                       float(eta), float(dt_s), _stream(stream)))
+
+
+def sph_drift_vjp(nbr, st, adj, dt_s, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_drift_vjp(nbr.handle, C.byref(cs), C.byref(adj.cstruct(nbr)), float(dt_s),
+                               _stream(stream)))
+
+
+def sph_diffusion_step_vjp(nbr, mat, st, c_before, adj, D, dt_d, c_bc, stream=None):
+    import torch
+    cs = st.cstruct(nbr)
+    _need(c_before, torch.float32 if st.prec == SPH_F32 else torch.float64, (nbr.n,), "c_before")
+    _check(lib().sph_diffusion_step_vjp(nbr.handle, C.byref(mat), C.byref(cs), _dptr(c_before),
+                                        C.byref(adj.cstruct(nbr)), float(D), float(dt_d), float(c_bc),
+                                        _stream(stream)))
+
+
+def _point_check(prec, n, **arrs):
+    import torch
+    T = torch.float32 if prec == SPH_F32 else torch.float64
+    rows = {"H": 9, "plastic": 7, "p": 0, "P": 9, "Pbar": 9, "plastic_bar": 7, "Hbar": 9, "pbar": 0,
+            "theta_bar": 5}
+    for name, t in arrs.items():
+        r = rows[name]
+        _need(t, T, (r, n) if r else (n,), name)
+
+
+def sph_constitutive(mat, prec, H, plastic=None, p=None, P=None, stream=None):
+    """H [9][n] = F - I; returns P [9][n] (plastic updated in place)."""
+    import torch
+    n = H.shape[1]
+    if P is None:
+        P = torch.empty_like(H)
+    _point_check(prec, n, H=H, plastic=plastic, p=p, P=P)
+    _check(lib().sph_constitutive(C.byref(mat), int(prec), int(n), _dptr(H), _dptr(plastic), _dptr(p),
+                                  _dptr(P), _stream(stream)))
+    return P
+
+
+def sph_constitutive_vjp(mat, prec, H, Pbar, plastic=None, plastic_bar=None, p=None, stream=None):
+    """Returns (Hbar [9][n], pbar [n], theta_bar [5][n]); plastic_bar is replaced in place."""
+    import torch
+    n = H.shape[1]
+    Hbar = torch.empty_like(H)
+    pbar = torch.empty(n, dtype=H.dtype, device=H.device)
+    thb = torch.empty(5, n, dtype=H.dtype, device=H.device)
+    _point_check(prec, n, H=H, Pbar=Pbar, plastic=plastic, plastic_bar=plastic_bar, p=p, Hbar=Hbar,
+                 pbar=pbar, theta_bar=thb)
+    _check(lib().sph_constitutive_vjp(C.byref(mat), int(prec), int(n), _dptr(H), _dptr(plastic), _dptr(p),
+                                      _dptr(Pbar), _dptr(plastic_bar), _dptr(Hbar), _dptr(pbar), _dptr(thb),
+                                      _stream(stream)))
+    return Hbar, pbar, thb
 
 
 def sph_profile_enable(nbr, enable=True):

@@ -1,0 +1,1115 @@
+// sph_adjoint.hip -- reverse mode of the TL-SPH multi-time-step path on gfx950.
+//
+// Every map of the inner step is either linear in the state (displacement
+// gradient sum, momentum sum, kick, damping sweep, drift) or local to one
+// particle (the constitutive update), so its transpose is written directly:
+//   drift^T      w += dt u_bar                      (free particles)
+//   sweep^T      pair maps transposed, colours and levels in reverse
+//   kick^T       a_bar = dt w                       (free particles)
+//   momentum^T   PB_bar_a = (1/rho0) sum_b (V_b a_bar_a - V_a a_bar_b) (x) grad_a W_ab
+//   stress^T     P_bar = PB_bar B0^T, exact derivative of P(H, state, p; theta)
+//   grad^T       G_bar = H_bar B0^T,
+//                u_bar_a -= sum_b (V_a G_bar_b + V_b G_bar_a) grad_a W_ab
+// The stress transpose and the momentum transpose share one pass over the
+// neighbours (both gather in the same LDS window), the displacement-gradient
+// transpose is a second pass shaped like the momentum kernel.  Parameter
+// gradients are summed per workgroup in FP64 into fixed slots and reduced in
+// a fixed order, so the reverse pass is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "sph_device.h"
+
+namespace sph {
+
+constexpr int kNTheta = 5;  // E, sigma0, sigma_inf, delta, H (the stress-stage parameters)
+
+template <typename T>
+__device__ __forceinline__ T dot9(const T* A, const T* B) {
+  T s = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s += A[i] * B[i];
+  return s;
+}
+// C = A^T B
+template <typename T>
+__device__ __forceinline__ void mul3_tn(const T* A, const T* B, T* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[i * 3 + j] = A[i] * B[j] + A[3 + i] * B[3 + j] + A[6 + i] * B[6 + j];
+}
+// D += (S + S^T) A
+template <typename T>
+__device__ __forceinline__ void add_symx(const T* S, const T* A, T* D) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s += (S[i * 3 + k] + S[k * 3 + i]) * A[k * 3 + j];
+      D[i * 3 + j] += s;
+    }
+}
+
+// Reverse of constitutive(): given P_bar (adjoint of P) and plb (adjoint of
+// the updated J2 state, 7 entries; replaced by the adjoint of the state
+// before the update), returns H_bar, p_bar and th = adjoints of (E, sigma0,
+// sigma_inf, delta, H).  pl is the state BEFORE the update.  The forward
+// quantities are recomputed as constitutive() computes them; the return
+// mapping's increment dgamma is differentiated through its scalar residual
+//   f(dg) = |s_pre| - sqrt(2/3) k(alpha + sqrt(2/3) dg) - 2 mubar dg = 0
+// (implicit-function theorem: d dg = -(df/dx dx) / (df/d dg)).
+template <typename T>
+__device__ int constitutive_vjp(const MatP<T>& m, const T* H, const T* pl, T p, const T* Pb,
+                                T* plb, T* Hbar, T& pbar, T* th) {
+  const T trH = H[0] + H[4] + H[8];
+  const T trH2 =
+      H[0] * H[0] + H[4] * H[4] + H[8] * H[8] + T(2) * (H[1] * H[3] + H[2] * H[6] + H[5] * H[7]);
+  const T jm1 = trH + T(0.5) * (trH * trH - trH2) + det3(H);
+  const T J = T(1) + jm1;
+  T F[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) F[i] = H[i];
+  F[0] += T(1);
+  F[4] += T(1);
+  F[8] += T(1);
+  T Fi[9];
+  inv3(F, J, Fi);
+#pragma unroll
+  for (int i = 0; i < kNTheta; ++i) th[i] = T(0);
+  T mub = T(0), Kb = T(0), Jb = T(0);
+  int st = 0;
+  if (m.model == SPH_MODEL_LE) {
+    // P = 2 mu sym(H) + lam tr(H) I - p J F^-T, lam = K - 2 mu / 3
+    const T trPb = Pb[0] + Pb[4] + Pb[8];
+    T sHP = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Hbar[i * 3 + j] = m.mu * (Pb[i * 3 + j] + Pb[j * 3 + i]);
+        sHP += Pb[i * 3 + j] * T(0.5) * (H[i * 3 + j] + H[j * 3 + i]);
+      }
+    Hbar[0] += m.lam * trPb;
+    Hbar[4] += m.lam * trPb;
+    Hbar[8] += m.lam * trPb;
+    mub = T(2) * sHP - T(2.0 / 3.0) * trH * trPb;
+    Kb = trH * trPb;
+    // d(J F^-T)[dF] = J tr(F^-1 dF) F^-T - J F^-T dF^T F^-T
+    T cd = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cd += Pb[i * 3 + j] * Fi[j * 3 + i];
+    pbar = -J * cd;
+    T t[9], N[9];
+    mul3(Fi, Pb, t);
+    mul3(t, Fi, N);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Hbar[i * 3 + j] -= p * J * (cd * Fi[j * 3 + i] - N[j * 3 + i]);
+    th[0] = mub * m.dmu_dE + Kb * m.dK_dE;
+    return 0;
+  }
+  const T vol = T(0.5) * m.K * jm1 * (T(2) + jm1);
+  T Fbar[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fbar[i] = T(0);
+  // ---- forward values -------------------------------------------------------
+  T s[9];  // deviatoric Kirchhoff stress
+  // NH
+  T dB[9], s23 = T(0);
+  // J2
+  T c = T(0), Fb[9], Y[9], FFm[9], E[9], spre[9], Dm[9], G[9];
+  T trE3 = T(0), sn = T(0), mubr = T(0), dg = T(0), fac = T(1), alpha = T(0);
+  bool plastic = false;
+  const T r23 = T(0.816496580927726);  // sqrt(2/3)
+  if (m.model == SPH_MODEL_NH) {
+    T Bm[9];
+    sym_sum(H, Bm);
+    const T cb = cbrt(J);
+    s23 = T(1) / (cb * cb);
+    const T tr3 = (Bm[0] + Bm[4] + Bm[8]) * (T(1) / T(3));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dB[i] = Bm[i];
+    dB[0] -= tr3;
+    dB[4] -= tr3;
+    dB[8] -= tr3;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s[i] = m.mu * s23 * dB[i];
+  } else {
+    c = T(1) / cbrt(J);
+    const T cm1 = expm1(log1p(jm1) * T(-1.0 / 3.0));
+    T Hb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Hb[i] = c * H[i];
+    Hb[0] += cm1;
+    Hb[4] += cm1;
+    Hb[8] += cm1;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Fb[i] = Hb[i];
+    Fb[0] += T(1);
+    Fb[4] += T(1);
+    Fb[8] += T(1);
+    Y[0] = pl[0];
+    Y[4] = pl[1];
+    Y[8] = pl[2];
+    Y[1] = Y[3] = pl[3];
+    Y[5] = Y[7] = pl[4];
+    Y[2] = Y[6] = pl[5];
+    alpha = pl[6];
+    sym_sum(Hb, FFm);
+    T tmp[9];
+    mul3(Fb, Y, tmp);
+    mul3_bt(tmp, Fb, E);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) E[i] += FFm[i];
+    trE3 = (E[0] + E[4] + E[8]) * (T(1) / T(3));
+    T n2 = T(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      spre[i] = m.mu * E[i];
+      if (i == 0 || i == 4 || i == 8) spre[i] -= m.mu * trE3;
+      n2 += spre[i] * spre[i];
+    }
+    sn = sqrt(n2);
+    const T f = sn - r23 * hardening(m, alpha);
+    if (f > T(0)) {
+      plastic = true;
+      mubr = m.mu * (T(1) + trE3);
+      const T tol = m.newton_tol * (sn > T(1) ? sn : T(1));
+      bool ok = false;
+      for (int it = 0; it < 50; ++it) {
+        const T a1 = alpha + r23 * dg;
+        const T fh = sn - r23 * hardening(m, a1) - T(2) * mubr * dg;
+        if (fabs(fh) <= tol) {
+          ok = true;
+          break;
+        }
+        const T dfh = -(T(2) / T(3)) * hardening_slope(m, a1) - T(2) * mubr;
+        dg -= fh / dfh;
+      }
+      if (!ok) st = SPH_STATUS_NEWTON;
+      fac = T(1) - T(2) * mubr * dg / sn;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s[i] = fac * spre[i];
+    const T imu = T(1) / m.mu;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Dm[i] = s[i] * imu - FFm[i];
+    Dm[0] += trE3;
+    Dm[4] += trE3;
+    Dm[8] += trE3;
+    inv3(Fb, det3(Fb), G);
+  }
+  // ---- P = (s + (vol - J p) I) F^-T ------------------------------------------
+  T tauT[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) tauT[i] = s[i];
+  tauT[0] += vol - J * p;
+  tauT[4] += vol - J * p;
+  tauT[8] += vol - J * p;
+  T sb[9], Fib[9];
+  mul3(Pb, Fi, sb);       // tau_bar = P_bar F^-1
+  mul3_tn(Pb, tauT, Fib);  // (F^-1)_bar = P_bar^T tau
+  const T trtb = sb[0] + sb[4] + sb[8];
+  pbar = -J * trtb;
+  Jb += (m.K * J - p) * trtb;
+  Kb += T(0.5) * jm1 * (T(2) + jm1) * trtb;
+  if (m.model == SPH_MODEL_NH) {
+    // s = mu J^(-2/3) dev(F F^T - I)
+    const T dBd = dot9(sb, dB);
+    mub += s23 * dBd;
+    const T s23b = m.mu * dBd;
+    T Bmb[9];
+    const T trs3 = (sb[0] + sb[4] + sb[8]) * (T(1) / T(3));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Bmb[i] = m.mu * s23 * sb[i];
+    Bmb[0] -= m.mu * s23 * trs3;
+    Bmb[4] -= m.mu * s23 * trs3;
+    Bmb[8] -= m.mu * s23 * trs3;
+    Jb += s23b * T(-2.0 / 3.0) * s23 / J;
+    add_symx(Bmb, F, Fbar);
+  } else {
+    // state update Y' = G Dm G^T, G = Fbar^-1, Dm = s/mu + trE3 I - (Fb Fb^T - I)
+    T Yb[9];
+    Yb[0] = plb[0];
+    Yb[4] = plb[1];
+    Yb[8] = plb[2];
+    Yb[1] = Yb[3] = T(0.5) * plb[3];
+    Yb[5] = Yb[7] = T(0.5) * plb[4];
+    Yb[2] = Yb[6] = T(0.5) * plb[5];
+    const T ab = plb[6];
+    T t[9], t2[9], Dmb[9], Gb[9], Fbb[9];
+    mul3_tn(G, Yb, t);
+    mul3(t, G, Dmb);  // Dm_bar = G^T Y'_bar G
+    mul3(Yb, G, t);
+    mul3(t, Dm, Gb);  // G_bar = 2 Y'_bar G Dm  (Y'_bar, Dm symmetric)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Gb[i] *= T(2);
+    mul3_tn(G, Gb, t);
+    mul3_bt(t, G, t2);  // Fb_bar = -G^T G_bar G^T
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Fbb[i] = -t2[i];
+    const T imu = T(1) / m.mu;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sb[i] += Dmb[i] * imu;
+    mub -= dot9(Dmb, s) * imu * imu;
+    T trE3b = Dmb[0] + Dmb[4] + Dmb[8];
+    T FFmb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) FFmb[i] = -Dmb[i];
+    // return mapping: s = fac s_pre, alpha' = alpha + sqrt(2/3) dg
+    T spb[9];
+    T snb = T(0);
+    T alphab = ab;
+    if (plastic) {
+      const T facb = dot9(sb, spre);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) spb[i] = fac * sb[i];
+      T mubrb = -T(2) * dg / sn * facb;
+      const T dgb = -T(2) * mubr / sn * facb + r23 * ab;
+      snb = T(2) * mubr * dg / (sn * sn) * facb;
+      const T a1 = alpha + r23 * dg;
+      const T kp = hardening_slope(m, a1);
+      const T Rg = -(T(2) / T(3)) * kp - T(2) * mubr;
+      const T lam = -dgb / Rg;
+      snb += lam;
+      alphab -= lam * r23 * kp;
+      mubrb -= T(2) * dg * lam;
+      const T e = exp(-m.delta * a1);
+      th[1] -= lam * r23 * e;
+      th[2] -= lam * r23 * (T(1) - e);
+      th[3] -= lam * r23 * (m.sinf - m.s0) * a1 * e;
+      th[4] -= lam * r23 * a1;
+      mub += mubrb * (T(1) + trE3);
+      trE3b += mubrb * m.mu;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) spb[i] = sb[i];
+    }
+    if (sn > T(0)) {
+      const T r = snb / sn;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) spb[i] += r * spre[i];
+    }
+    // s_pre = mu dev(E), trE3 = tr(E)/3
+    mub += dot9(spb, spre) * imu;
+    T Eb[9];
+    const T trsp3 = (spb[0] + spb[4] + spb[8]) * (T(1) / T(3));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Eb[i] = m.mu * spb[i];
+    const T dd = -m.mu * trsp3 + trE3b * (T(1) / T(3));
+    Eb[0] += dd;
+    Eb[4] += dd;
+    Eb[8] += dd;
+    // E = Fb Y Fb^T + (Fb Fb^T - I)
+    T Yf[9];
+    mul3_tn(Fb, Eb, t);
+    mul3(t, Fb, Yf);  // Y_bar = Fb^T E_bar Fb
+    mul3(Fb, Y, t);
+    add_symx(Eb, t, Fbb);  // += (E_bar + E_bar^T) Fb Y
+#pragma unroll
+    for (int i = 0; i < 9; ++i) FFmb[i] += Eb[i];
+    add_symx(FFmb, Fb, Fbb);  // += (FFm_bar + FFm_bar^T) Fb
+    // Fb = c F, c = J^(-1/3)
+    const T cbar = dot9(Fbb, F);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Fbar[i] += c * Fbb[i];
+    Jb += cbar * T(-1.0 / 3.0) * c / J;
+    plb[0] = Yf[0];
+    plb[1] = Yf[4];
+    plb[2] = Yf[8];
+    plb[3] = Yf[1] + Yf[3];
+    plb[4] = Yf[5] + Yf[7];
+    plb[5] = Yf[2] + Yf[6];
+    plb[6] = alphab;
+  }
+  // F^-1 and J = det F
+  {
+    T t[9], t2[9];
+    mul3_tn(Fi, Fib, t);
+    mul3_bt(t, Fi, t2);  // F_bar -= F^-T (F^-1)_bar F^-T
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Fbar[i * 3 + j] += Jb * J * Fi[j * 3 + i] - t2[i * 3 + j];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Hbar[i] = Fbar[i];
+  th[0] = mub * m.dmu_dE + Kb * m.dK_dE;
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// point evaluation (n independent particles)
+template <typename T>
+__global__ void k_constitutive(MatP<T> m, int64_t n, const T* __restrict__ H, T* plastic,
+                               const T* __restrict__ p, T* __restrict__ P, Ctrl* ctrl) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  T Hm[9], pl[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)}, Pm[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Hm[i] = H[i * n + a];
+  if (plastic)
+#pragma unroll
+    for (int i = 0; i < 7; ++i) pl[i] = plastic[i * n + a];
+  const int st = constitutive(m, Hm, pl, p ? p[a] : T(0), Pm);
+  if (st) atomicOr(&ctrl->status, st);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P[i * n + a] = Pm[i];
+  if (plastic)
+#pragma unroll
+    for (int i = 0; i < 7; ++i) plastic[i * n + a] = pl[i];
+}
+
+template <typename T>
+__global__ void k_constitutive_vjp(MatP<T> m, int64_t n, const T* __restrict__ H,
+                                   const T* __restrict__ plastic, const T* __restrict__ p,
+                                   const T* __restrict__ Pbar, T* plb, T* __restrict__ Hbar,
+                                   T* __restrict__ pbar, T* __restrict__ thb, Ctrl* ctrl) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  T Hm[9], pl[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)}, Pb[9], pv[7], Hb[9], th[kNTheta];
+  T pb = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    Hm[i] = H[i * n + a];
+    Pb[i] = Pbar[i * n + a];
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    pl[i] = plastic ? plastic[i * n + a] : T(0);
+    pv[i] = plb ? plb[i * n + a] : T(0);
+  }
+  const int st = constitutive_vjp(m, Hm, pl, p ? p[a] : T(0), Pb, pv, Hb, pb, th);
+  if (st) atomicOr(&ctrl->status, st);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Hbar[i * n + a] = Hb[i];
+  if (plb)
+#pragma unroll
+    for (int i = 0; i < 7; ++i) plb[i * n + a] = pv[i];
+  if (pbar) pbar[a] = pb;
+  if (thb)
+#pragma unroll
+    for (int i = 0; i < kNTheta; ++i) thb[i * n + a] = th[i];
+}
+
+// ---------------------------------------------------------------------------
+// block sum of a few doubles (all threads call it); thread 0 adds the totals
+// into this workgroup's gradient slots
+template <int NV>
+__device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot)[NV],
+                                               double* gpart) {
+  __shared__ double wsum[NV][16];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double x = v[j];
+#pragma unroll
+    for (int mk = 1; mk < 64; mk <<= 1) x += __shfl_xor(x, mk, 64);
+    v[j] = x;
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) wsum[j][w] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* g = gpart + (int64_t)blockIdx.x * SPH_NGRAD;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < nw; ++k) s += wsum[j][k];
+      g[slot[j]] += s;
+    }
+  }
+}
+
+// reverse of the stress stage + momentum sum + kick, one tile per workgroup:
+// gathers the neighbours' u (for H) and a_bar = dt w (free particles) from the
+// LDS window; writes G_bar = H_bar B0^T, updates the J2 state adjoint,
+// accumulates p_bar and the parameter partials
+template <typename T, int D>
+__global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
+    TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
+    const uint8_t* __restrict__ flags, T dt, T inv_rho0, const T* __restrict__ plastic,
+    T* __restrict__ plb, const T* __restrict__ p, double* __restrict__ pbar, T* __restrict__ Gb,
+    double* __restrict__ gpart, Ctrl* ctrl) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* su = sx + window;  // 2D: (u.x, u.y, a.x, a.y); 3D: (u.x, u.y, u.z, -)
+  vec4<T>* sa = su + window;  // 3D only: (a.x, a.y, a.z, -)
+  const int64_t n = g.n;
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0}, uo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    xo[k] = g.X[k * n + p0];
+    uo[k] = u[k * n + p0];
+  }
+  const WinMap wm = win_map(td);
+  for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
+    const int64_t gi = wm(l);
+    vec4<T> xv, uv, av;
+    xv.x = (T)(g.X[gi] - xo[0]);
+    xv.y = (T)(g.X[n + gi] - xo[1]);
+    xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+    xv.w = g.V[gi];
+    const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
+    const T kf = fixed ? T(0) : dt;
+    uv.x = (T)(u[gi] - uo[0]);
+    uv.y = (T)(u[n + gi] - uo[1]);
+    if (D == 2) {
+      uv.z = kf * w[gi];
+      uv.w = kf * w[n + gi];
+    } else {
+      uv.z = (T)(u[2 * n + gi] - uo[2]);
+      uv.w = T(0);
+      av.x = kf * w[gi];
+      av.y = kf * w[n + gi];
+      av.z = kf * w[2 * n + gi];
+      av.w = T(0);
+    }
+    sx[l] = xv;
+    su[l] = uv;
+    if (D == 3) sa[l] = av;
+  }
+  __syncthreads();
+  const int t = threadIdx.x / kLppStress, h = threadIdx.x % kLppStress;
+  const bool active = (uint32_t)t < td.count;
+  const uint32_t la = td.own_base + (active ? t : 0);
+  const vec4<T> xa = sx[la], ua = su[la];
+  vec4<T> aa;
+  if (D == 3) aa = sa[la];
+  else {
+    aa.x = ua.z;
+    aa.y = ua.w;
+    aa.z = T(0);
+  }
+  const T Va = xa.w;
+  T Gs[D][D], Qs[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) Gs[i][k] = Qs[i][k] = T(0);
+  if (active)
+    ell_walk<kLppStress>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+      const vec4<T> xb = sx[l], ub = su[l];
+      T ab[3];
+      if (D == 3) {
+        const vec4<T> av = sa[l];
+        ab[0] = av.x;
+        ab[1] = av.y;
+        ab[2] = av.z;
+      } else {
+        ab[0] = ub.z;
+        ab[1] = ub.w;
+        ab[2] = T(0);
+      }
+      const T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+      T du[3] = {ub.x - ua.x, ub.y - ua.y, T(0)};
+      if (D == 3) du[2] = ub.z - ua.z;
+      T r2 = d[0] * d[0] + d[1] * d[1];
+      if (D == 3) r2 += d[2] * d[2];
+      const T w0 = dw_over_r(r2, g.inv_h, g.c5);
+      const T wb = w0 * xb.w, wa = w0 * Va;
+      const T aav[3] = {aa.x, aa.y, aa.z};
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const T gu = wb * du[i];
+        const T qa = wb * aav[i] - wa * ab[i];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          Gs[i][k] += gu * d[k];
+          Qs[i][k] += qa * d[k];
+        }
+      }
+    });
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      Gs[i][k] = lane_sum<kLppStress>(Gs[i][k]);
+      Qs[i][k] = lane_sum<kLppStress>(Qs[i][k]);
+    }
+  double thd[kNTheta] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (active && h == 0) {
+    const int64_t a = p0 + t;
+    T B[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) B[i][k] = g.B0[(i * D + k) * n + a];
+    T Hm[9], Pb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Hm[i] = Pb[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        T hs = T(0), ps = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+          hs += Gs[i][l] * B[l][k];
+          ps += Qs[i][l] * B[k][l];
+        }
+        Hm[i * 3 + k] = hs;
+        Pb[i * 3 + k] = ps * inv_rho0;
+      }
+    T pl[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)}, pv[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    if (m.model == SPH_MODEL_J2) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) {
+        pl[i] = plastic[i * n + a];
+        pv[i] = plb[i * n + a];
+      }
+    }
+    T Hb[9], th[kNTheta], pb = T(0);
+    const int st = constitutive_vjp(m, Hm, pl, p ? p[a] : T(0), Pb, pv, Hb, pb, th);
+    if (st) atomicOr(&ctrl->status, st);
+    if (m.model == SPH_MODEL_J2) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) plb[i * n + a] = pv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) acc += Hb[i * 3 + l] * B[k][l];
+        Gb[(i * D + k) * n + a] = acc;
+      }
+    if (pbar) pbar[a] += (double)pb;
+#pragma unroll
+    for (int i = 0; i < kNTheta; ++i) thd[i] = (double)th[i];
+  }
+  const int slots[kNTheta] = {SPH_GRAD_E, SPH_GRAD_S0, SPH_GRAD_SINF, SPH_GRAD_DELTA, SPH_GRAD_H};
+  block_grad_add<kNTheta>(thd, slots, gpart);
+}
+
+// reverse of the displacement-gradient sum:
+//   u_bar_a -= sum_b (V_a G_bar_b + V_b G_bar_a) grad_a W_ab,
+// then (drift_dt != 0) the drift transpose of the previous inner step,
+// w_a += drift_dt u_bar_a for free particles
+template <typename T, int D>
+__global__ __launch_bounds__(128 * kLppMomentum) void k_adj_gather(
+    TileGeo<T> g, const T* __restrict__ Gb, double* __restrict__ ub, T* __restrict__ w,
+    const uint8_t* __restrict__ flags, double drift_dt) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  constexpr int NP = (D * D + 3) / 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* sp = sx + window;  // [window][NP]
+  const int64_t n = g.n;
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
+  const WinMap wm = win_map(td);
+  for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
+    const int64_t gi = wm(l);
+    vec4<T> xv;
+    xv.x = (T)(g.X[gi] - xo[0]);
+    xv.y = (T)(g.X[n + gi] - xo[1]);
+    xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+    xv.w = g.V[gi];
+    sx[l] = xv;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      vec4<T> pv;
+      pv.x = 4 * q < D * D ? Gb[(4 * q) * n + gi] : T(0);
+      pv.y = 4 * q + 1 < D * D ? Gb[(4 * q + 1) * n + gi] : T(0);
+      pv.z = 4 * q + 2 < D * D ? Gb[(4 * q + 2) * n + gi] : T(0);
+      pv.w = 4 * q + 3 < D * D ? Gb[(4 * q + 3) * n + gi] : T(0);
+      sp[l * NP + q] = pv;
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x / kLppMomentum, h = threadIdx.x % kLppMomentum;
+  if ((uint32_t)t >= td.count) return;
+  const int64_t a = p0 + t;
+  const uint32_t la = td.own_base + t;
+  const vec4<T> xa = sx[la];
+  T Ga[NP * 4];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const vec4<T> pv = sp[la * NP + q];
+    Ga[4 * q] = pv.x;
+    Ga[4 * q + 1] = pv.y;
+    Ga[4 * q + 2] = pv.z;
+    Ga[4 * q + 3] = pv.w;
+  }
+  const T Va = xa.w;
+  T f[3] = {T(0), T(0), T(0)};
+  ell_walk<kLppMomentum>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    const vec4<T> xb = sx[l];
+    T Gbb[NP * 4];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const vec4<T> pv = sp[l * NP + q];
+      Gbb[4 * q] = pv.x;
+      Gbb[4 * q + 1] = pv.y;
+      Gbb[4 * q + 2] = pv.z;
+      Gbb[4 * q + 3] = pv.w;
+    }
+    const T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w0 = dw_over_r(r2, g.inv_h, g.c5);
+    const T wa = w0 * Va, wb = w0 * xb.w;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += (wa * Gbb[i * D + k] + wb * Ga[i * D + k]) * d[k];
+      f[i] += s;
+    }
+  });
+#pragma unroll
+  for (int i = 0; i < D; ++i) f[i] = lane_sum<kLppMomentum>(f[i]);
+  if (h != 0) return;
+  const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double un = ub[i * n + a] - (double)f[i];
+    ub[i * n + a] = un;
+    if (drift_dt != 0.0 && !fixed) w[i * n + a] += (T)(drift_dt * un);
+  }
+}
+
+template <typename T, int D>
+__global__ void k_adj_drift(int64_t n, const double* __restrict__ ub, T* __restrict__ w,
+                            const uint8_t* __restrict__ flags, double dt) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  if (flags && (flags[a] & SPH_FLAG_FIXED)) return;
+#pragma unroll
+  for (int k = 0; k < D; ++k) w[k * n + a] += (T)(dt * ub[k * n + a]);
+}
+
+// reverse of the diffusion step, first pass (per particle a, gather over b):
+//   cdot_bar_b = dt (c_bar_b + C p_bar_b) (0 on Dirichlet particles)
+//   r_bar_a = -sum_b (V_b cdot_bar_a - V_a cdot_bar_b) grad_a W_ab,  q_bar = B0^T r_bar
+//   D_bar += q_bar . (-B0 s_a),  s_a = sum_b V_b (c_b - c_a) grad_a W_ab (c before the step)
+//   s_bar_a = -D B0^T q_bar,     C_bar += p_bar_a (c'_a - c0)
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_adiff_a(Geo<T> g, const T* __restrict__ cold,
+                                                 const T* __restrict__ cnew,
+                                                 const T* __restrict__ cb,
+                                                 const double* __restrict__ pbar,
+                                                 const uint8_t* __restrict__ flags, T dt, T Dc,
+                                                 T Cs, T c0, T* __restrict__ sbar,
+                                                 double* __restrict__ gpart) {
+  const int64_t n = g.n;
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double gd[2] = {0.0, 0.0};
+  if (a < n) {
+    auto cdb = [&](int64_t i) -> T {
+      if (flags && (flags[i] & SPH_FLAG_CDIR)) return T(0);
+      return dt * (cb[i] + (pbar ? Cs * (T)pbar[i] : T(0)));
+    };
+    double xa[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
+    const T ca = cold[a], Va = g.V[a], cda = cdb(a);
+    T r[D], s[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) r[k] = s[k] = T(0);
+    for (int64_t j = g.off[a]; j < g.off[a + 1]; ++j) {
+      const uint32_t b = g.idx[j];
+      T d[D];
+      T r2 = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        d[k] = (T)(xa[k] - g.X[k * n + b]);
+        r2 += d[k] * d[k];
+      }
+      const T w0 = dw_over_r(r2, g.inv_h, g.c5);
+      const T Vb = g.V[b];
+      const T cr = -w0 * (Vb * cda - Va * cdb(b));
+      const T cs = w0 * Vb * (cold[b] - ca);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        r[k] += cr * d[k];
+        s[k] += cs * d[k];
+      }
+    }
+    T qb[D], Bs[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T x = T(0), y = T(0);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        x += g.B0[(i * D + k) * n + a] * r[i];
+        y += g.B0[(k * D + i) * n + a] * s[i];
+      }
+      qb[k] = x;
+      Bs[k] = y;
+    }
+    double dsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      dsum -= (double)qb[k] * (double)Bs[k];
+      T x = T(0);
+#pragma unroll
+      for (int i = 0; i < D; ++i) x += g.B0[(i * D + k) * n + a] * qb[i];
+      sbar[k * n + a] = -Dc * x;
+    }
+    gd[0] = dsum;
+    gd[1] = pbar ? pbar[a] * ((double)cnew[a] - (double)c0) : 0.0;
+  }
+  const int slots[2] = {SPH_GRAD_D, SPH_GRAD_C};
+  block_grad_add<2>(gd, slots, gpart);
+}
+
+// second pass: c_bar_a <- (0 on Dirichlet particles, else c_bar_a + C p_bar_a)
+//   - sum_b (V_a s_bar_b + V_b s_bar_a) . grad_a W_ab;  p_bar_a <- 0
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_adiff_b(Geo<T> g, const T* __restrict__ sbar,
+                                                 T* __restrict__ cb, double* __restrict__ pbar,
+                                                 const uint8_t* __restrict__ flags, T Cs) {
+  const int64_t n = g.n;
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double xa[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
+  const T Va = g.V[a];
+  T sa[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) sa[k] = sbar[k * n + a];
+  T acc = T(0);
+  for (int64_t j = g.off[a]; j < g.off[a + 1]; ++j) {
+    const uint32_t b = g.idx[j];
+    T d[D];
+    T r2 = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      d[k] = (T)(xa[k] - g.X[k * n + b]);
+      r2 += d[k] * d[k];
+    }
+    const T w0 = dw_over_r(r2, g.inv_h, g.c5);
+    const T Vb = g.V[b];
+    T x = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) x += (Va * sbar[k * n + b] + Vb * sa[k]) * d[k];
+    acc += w0 * x;
+  }
+  const bool dir = flags && (flags[a] & SPH_FLAG_CDIR);
+  const T direct = dir ? T(0) : cb[a] + (pbar ? Cs * (T)pbar[a] : T(0));
+  cb[a] = direct - acc;
+  if (pbar) pbar[a] = 0.0;
+}
+
+// fixed-order reduction of the gradient partials into grad (+=); clears them
+__global__ __launch_bounds__(256) void k_grad_reduce(double* __restrict__ gpart, int64_t slots,
+                                                     double* __restrict__ grad) {
+  __shared__ double red[256];
+  for (int gi = 0; gi < SPH_NGRAD; ++gi) {
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < slots; j += 256) {
+      s += gpart[j * SPH_NGRAD + gi];
+      gpart[j * SPH_NGRAD + gi] = 0.0;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[gi] += red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+static inline unsigned nblk256(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+
+int grad_reduce(const sph_nbr* nb, double* grad, hipStream_t s) {
+  k_grad_reduce<<<1, 256, 0, s>>>(nb->gpart, nb->gpart_slots, grad);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+template <typename T, int D>
+static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const double* u,
+                       const void* plastic, const sph_state* st, const sph_adjoint* adj,
+                       double dt, double drift_dt, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  TileGeo<T> g = tile_geo<T>(nb, prec);
+  if (g.n_tiles == 0) return SPH_OK;
+  MatP<T> mp = matp<T>(m);
+  const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
+  if ((int64_t)grid > nb->gpart_slots) {
+    set_error("gradient partial slots too few");
+    return SPH_E_CAPACITY;
+  }
+  const size_t wm = (size_t)nb->tiling[prec].window_max;
+  const size_t lds_s = wm * (D == 3 ? 3 : 2) * sizeof(vec4<T>);
+  const size_t lds_g = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
+  int rc = lds_attr(k_adj_stress<T, D>, lds_s);
+  if (rc) return rc;
+  rc = lds_attr(k_adj_gather<T, D>, lds_g);
+  if (rc) return rc;
+  {
+    hipEvent_t pe_ = prof_begin(nb, s);
+    k_adj_stress<T, D><<<grid, (unsigned)(g.tmax * kLppStress), lds_s, s>>>(
+        g, mp, u, (const T*)adj->v, st->flags, (T)dt, (T)(1.0 / m->rho0), (const T*)plastic,
+        (T*)adj->plastic, (const T*)st->p, adj->p, (T*)adj->work, nb->gpart, nb->ctrl);
+    prof_end(nb, SPH_KERNEL_ADJ_STRESS, pe_, s);
+  }
+  SPH_LAUNCH_CHECK();
+  {
+    hipEvent_t pe_ = prof_begin(nb, s);
+    k_adj_gather<T, D><<<grid, (unsigned)(g.tmax * kLppMomentum), lds_g, s>>>(
+        g, (const T*)adj->work, adj->u, (T*)adj->v, st->flags, drift_dt);
+    prof_end(nb, SPH_KERNEL_ADJ_GATHER, pe_, s);
+  }
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+static int check_adj(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                     const sph_adjoint* adj) {
+  int rc = check_state(nb, st, false);
+  if (rc) return rc;
+  if (!m || !adj) {
+    set_error("material or adjoint is NULL");
+    return SPH_E_ARG;
+  }
+  if (adj->prec != st->prec) {
+    set_error("adjoint and state precisions differ");
+    return SPH_E_ARG;
+  }
+  if (!adj->u || !adj->v || !adj->work || !adj->grad) {
+    set_error("adjoint arrays u, v, work and grad are required");
+    return SPH_E_ARG;
+  }
+  if (m->model == SPH_MODEL_J2 && (!st->plastic || !adj->plastic)) {
+    set_error("J2 needs the plastic state and its adjoint");
+    return SPH_E_ARG;
+  }
+  return SPH_OK;
+}
+
+int adj_solid(const sph_nbr* nb, const sph_material* m, const double* u, const void* plastic,
+              const sph_state* st, const sph_adjoint* adj, double dt, double drift_dt,
+              hipStream_t s) {
+  if (st->prec == SPH_F64)
+    return nb->dim == 2 ? adj_solid_t<double, 2>(nb, m, u, plastic, st, adj, dt, drift_dt, s)
+                        : adj_solid_t<double, 3>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+  return nb->dim == 2 ? adj_solid_t<float, 2>(nb, m, u, plastic, st, adj, dt, drift_dt, s)
+                      : adj_solid_t<float, 3>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+}
+
+int adj_damping(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                const sph_adjoint* adj, double eta, double dt, hipStream_t s) {
+  sph_state w = *st;
+  w.prec = adj->prec;
+  w.v = adj->v;
+  return damping_sweep_rev(nb, m, &w, eta, dt, s);
+}
+
+int adj_drift(const sph_nbr* nb, const sph_state* st, const sph_adjoint* adj, double dt,
+              hipStream_t s) {
+  const unsigned gr = nblk256(nb->n);
+  if (adj->prec == SPH_F64) {
+    if (nb->dim == 2) k_adj_drift<double, 2><<<gr, 256, 0, s>>>(nb->n, adj->u, (double*)adj->v, st->flags, dt);
+    else k_adj_drift<double, 3><<<gr, 256, 0, s>>>(nb->n, adj->u, (double*)adj->v, st->flags, dt);
+  } else {
+    if (nb->dim == 2) k_adj_drift<float, 2><<<gr, 256, 0, s>>>(nb->n, adj->u, (float*)adj->v, st->flags, dt);
+    else k_adj_drift<float, 3><<<gr, 256, 0, s>>>(nb->n, adj->u, (float*)adj->v, st->flags, dt);
+  }
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+template <typename T, int D>
+static int adj_diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                           const void* c_before, const sph_adjoint* adj, double Dc, double dt,
+                           hipStream_t s) {
+  Geo<T> g = geo<T>(nb);
+  const unsigned gr = nblk256(nb->n);
+  if ((int64_t)gr > nb->gpart_slots) {
+    set_error("gradient partial slots too few");
+    return SPH_E_CAPACITY;
+  }
+  k_adiff_a<T, D><<<gr, 256, 0, s>>>(g, (const T*)c_before, (const T*)st->c, (const T*)adj->c,
+                                     adj->p, st->flags, (T)dt, (T)Dc, (T)m->C_swell, (T)m->c0,
+                                     (T*)adj->work, nb->gpart);
+  SPH_LAUNCH_CHECK();
+  k_adiff_b<T, D><<<gr, 256, 0, s>>>(g, (const T*)adj->work, (T*)adj->c, adj->p, st->flags,
+                                     (T)m->C_swell);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+int adj_diffusion(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                  const void* c_before, const sph_adjoint* adj, double Dc, double dt,
+                  hipStream_t s) {
+  if (!st->c || !c_before || !adj->c || !adj->work) {
+    set_error("the diffusion reverse needs c, c_before and the adjoint c and work arrays");
+    return SPH_E_ARG;
+  }
+  if (st->prec == SPH_F64)
+    return nb->dim == 2 ? adj_diffusion_t<double, 2>(nb, m, st, c_before, adj, Dc, dt, s)
+                        : adj_diffusion_t<double, 3>(nb, m, st, c_before, adj, Dc, dt, s);
+  return nb->dim == 2 ? adj_diffusion_t<float, 2>(nb, m, st, c_before, adj, Dc, dt, s)
+                      : adj_diffusion_t<float, 3>(nb, m, st, c_before, adj, Dc, dt, s);
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" int sph_solid_relax_step_vjp(const sph_nbr* nb, const sph_material* mat,
+                                        const sph_state* st, const sph_adjoint* adj, double dt_s,
+                                        void* stream) {
+  clear_error();
+  int rc = check_adj(nb, mat, st, adj);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = adj_solid(nb, mat, st->u, st->plastic, st, adj, dt_s, 0.0, s);
+  if (rc) return rc;
+  return grad_reduce(nb, adj->grad, s);
+}
+
+extern "C" int sph_damping_sweep_vjp(const sph_nbr* nb, const sph_material* mat,
+                                     const sph_state* st, const sph_adjoint* adj, double eta,
+                                     double dt_s, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, false);
+  if (rc) return rc;
+  if (!mat || !adj || !adj->v || adj->prec != st->prec) {
+    set_error("material and the adjoint v (in the state's precision) are required");
+    return SPH_E_ARG;
+  }
+  return adj_damping(nb, mat, st, adj, eta, dt_s, (hipStream_t)stream);
+}
+
+extern "C" int sph_drift_vjp(const sph_nbr* nb, const sph_state* st, const sph_adjoint* adj,
+                             double dt_s, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, false);
+  if (rc) return rc;
+  if (!adj || !adj->u || !adj->v || adj->prec != st->prec) {
+    set_error("adjoint u and v required, in the state's precision");
+    return SPH_E_ARG;
+  }
+  return adj_drift(nb, st, adj, dt_s, (hipStream_t)stream);
+}
+
+extern "C" int sph_diffusion_step_vjp(const sph_nbr* nb, const sph_material* mat,
+                                      const sph_state* st, const void* c_before,
+                                      const sph_adjoint* adj, double D, double dt_d, double c_bc,
+                                      void* stream) {
+  clear_error();
+  (void)c_bc;  // the Dirichlet value is a constant: it has no derivative
+  int rc = check_adj(nb, mat, st, adj);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = adj_diffusion(nb, mat, st, c_before, adj, D, dt_d, s);
+  if (rc) return rc;
+  return grad_reduce(nb, adj->grad, s);
+}
+
+namespace {
+Ctrl* g_point_ctrl = nullptr;  // status word of the point evaluations (per process)
+
+int point_ctrl(Ctrl** out) {
+  if (!g_point_ctrl) {
+    SPH_HIP(hipMalloc(&g_point_ctrl, sizeof(Ctrl)));
+    SPH_HIP(hipMemset(g_point_ctrl, 0, sizeof(Ctrl)));
+  }
+  *out = g_point_ctrl;
+  return SPH_OK;
+}
+
+int point_status(hipStream_t s) {
+  Ctrl h;
+  SPH_HIP(hipMemcpyAsync(&h, g_point_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  if (h.status) {
+    SPH_HIP(hipMemset(g_point_ctrl, 0, sizeof(Ctrl)));
+    set_error("device status bits 0x%x", h.status);
+    return SPH_E_NUMERIC;
+  }
+  return SPH_OK;
+}
+}  // namespace
+
+extern "C" int sph_constitutive(const sph_material* mat, int prec, int64_t n, const void* H,
+                                void* plastic, const void* p, void* P, void* stream) {
+  clear_error();
+  if (!mat || n < 0 || (n > 0 && (!H || !P)) || (mat->model == SPH_MODEL_J2 && n > 0 && !plastic)) {
+    set_error("bad arguments");
+    return SPH_E_ARG;
+  }
+  if (prec != SPH_F32 && prec != SPH_F64) {
+    set_error("prec must be SPH_F32 or SPH_F64");
+    return SPH_E_UNSUPPORTED;
+  }
+  if (n == 0) return SPH_OK;
+  Ctrl* c = nullptr;
+  int rc = point_ctrl(&c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void* pl = mat->model == SPH_MODEL_J2 ? plastic : nullptr;
+  if (prec == SPH_F64)
+    k_constitutive<double><<<nblk256(n), 256, 0, s>>>(matp<double>(mat), n, (const double*)H,
+                                                      (double*)pl, (const double*)p, (double*)P, c);
+  else
+    k_constitutive<float><<<nblk256(n), 256, 0, s>>>(matp<float>(mat), n, (const float*)H,
+                                                     (float*)pl, (const float*)p, (float*)P, c);
+  SPH_LAUNCH_CHECK();
+  return point_status(s);
+}
+
+extern "C" int sph_constitutive_vjp(const sph_material* mat, int prec, int64_t n, const void* H,
+                                    const void* plastic, const void* p, const void* Pbar,
+                                    void* plastic_bar, void* Hbar, void* pbar, void* theta_bar,
+                                    void* stream) {
+  clear_error();
+  if (!mat || n < 0 || (n > 0 && (!H || !Pbar || !Hbar)) ||
+      (mat->model == SPH_MODEL_J2 && n > 0 && (!plastic || !plastic_bar))) {
+    set_error("bad arguments");
+    return SPH_E_ARG;
+  }
+  if (prec != SPH_F32 && prec != SPH_F64) {
+    set_error("prec must be SPH_F32 or SPH_F64");
+    return SPH_E_UNSUPPORTED;
+  }
+  if (n == 0) return SPH_OK;
+  Ctrl* c = nullptr;
+  int rc = point_ctrl(&c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const bool j2 = mat->model == SPH_MODEL_J2;
+  if (prec == SPH_F64)
+    k_constitutive_vjp<double><<<nblk256(n), 256, 0, s>>>(
+        matp<double>(mat), n, (const double*)H, j2 ? (const double*)plastic : nullptr,
+        (const double*)p, (const double*)Pbar, j2 ? (double*)plastic_bar : nullptr, (double*)Hbar,
+        (double*)pbar, (double*)theta_bar, c);
+  else
+    k_constitutive_vjp<float><<<nblk256(n), 256, 0, s>>>(
+        matp<float>(mat), n, (const float*)H, j2 ? (const float*)plastic : nullptr,
+        (const float*)p, (const float*)Pbar, j2 ? (float*)plastic_bar : nullptr, (float*)Hbar,
+        (float*)pbar, (float*)theta_bar, c);
+  SPH_LAUNCH_CHECK();
+  return point_status(s);
+}

@@ -568,14 +568,14 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
 }
 
 // damping: pack each canonical pair as (a_loc, b_loc) inside its anchor block
-// (level beside it), record the block runs, the per-colour maxima that size
+// record the block runs, the per-colour maxima that size
 // each pass's LDS, and the pair geometry 2 V_a V_b (dW/dr)/r
 __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __restrict__ aoff,
                             const uint32_t* __restrict__ sa, const uint32_t* __restrict__ sb,
                             const uint32_t* __restrict__ slev, const uint32_t* __restrict__ cs,
                             const double* __restrict__ X, const double* __restrict__ V,
                             double inv_h, double c5, Grid g, int64_t n, int64_t n_anchors,
-                            uint32_t* __restrict__ dpair, uint16_t* __restrict__ dlev,
+                            uint32_t* __restrict__ dpair,
                             float* __restrict__ dgeo32, double* __restrict__ dgeo64,
                             uint32_t* __restrict__ ablk, unsigned long long* bmax,
                             unsigned long long* pmax, int32_t* err) {
@@ -611,7 +611,6 @@ __global__ void k_damp_pack(const uint32_t* __restrict__ akey, const int64_t* __
       continue;
     }
     dpair[i] = (uint32_t)loc[0] | ((uint32_t)loc[1] << kDampLocBits);
-    dlev[i] = (uint16_t)slev[i];
     double r2 = 0.0;
     for (int k = 0; k < g.dim; ++k) {
       double d = X[k * n + pp[0]] - X[k * n + pp[1]];
@@ -746,7 +745,7 @@ static void free_nbr(sph_nbr* h) {
   if (!h) return;
   void* ptrs[] = {h->key, h->perm, h->cell_start, h->nbr_off, h->nbr_idx, h->X,   h->V,
                   h->B0,  h->Vf,   h->B0f,        h->sa,      h->sb,      h->slev, h->akey,
-                  h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk, h->dlev,
+                  h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk, h->gpart,
                   h->dgeo32, h->dgeo64, h->dloff, h->dloff_base,
                   h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell};
   for (void* p : ptrs)
@@ -956,7 +955,7 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   {
     unsigned long long* mx = nullptr;
     int32_t* derr = nullptr;
-    if ((rc_ = dalloc(&nb->dpair, npu)) || (rc_ = dalloc(&nb->dlev, npu)) ||
+    if ((rc_ = dalloc(&nb->dpair, npu)) ||
         (rc_ = dalloc(&nb->dgeo32, npu)) || (rc_ = dalloc(&nb->dgeo64, npu)) ||
         (rc_ = dalloc(&nb->ablk, 8 * std::max<int64_t>(base, 1))) ||
         (rc_ = dalloc(&mx, 16)) || (rc_ = dalloc(&derr, 1)))
@@ -966,7 +965,7 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
     if (base > 0) {
       k_damp_pack<<<nblocks(base, 64), 64, 0, s>>>(
           nb->akey, nb->aoff, nb->sa, nb->sb, nb->slev, nb->cell_start, nb->X, nb->V, nb->inv_h,
-          nb->c5, g, n, base, nb->dpair, nb->dlev, nb->dgeo32, nb->dgeo64, nb->ablk, mx, mx + 8,
+          nb->c5, g, n, base, nb->dpair, nb->dgeo32, nb->dgeo64, nb->ablk, mx, mx + 8,
           derr);
       SPH_LAUNCH_CHECK();
     }
@@ -1073,6 +1072,15 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   SPH_HIP(hipMemsetAsync(nb->ctrl, 0, sizeof(Ctrl), s));
   SPH_HIP(hipHostMalloc((void**)&nb->ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
   SPH_HIP(hipMalloc(&nb->ke_partial, kKeMaxBlocks * sizeof(double)));
+  // per-workgroup partial sums of the parameter gradients (reverse mode)
+  {
+    int64_t slots = (n + 255) / 256;
+    for (int prec = 0; prec < 2; ++prec)
+      slots = std::max<int64_t>(slots, 8 * ((nb->tiling[prec].n_tiles + 7) / 8));
+    nb->gpart_slots = std::max<int64_t>(slots, 1);
+    SPH_HIP(hipMalloc(&nb->gpart, nb->gpart_slots * SPH_NGRAD * sizeof(double)));
+    SPH_HIP(hipMemsetAsync(nb->gpart, 0, nb->gpart_slots * SPH_NGRAD * sizeof(double), s));
+  }
   SPH_HIP(hipStreamSynchronize(s));
   return SPH_OK;
 }

@@ -93,7 +93,8 @@ struct Tiling {
 };
 
 // damping pair word: a_loc | b_loc << 16 (locals inside the anchor's
-// 2^d-cell block, in ascending sorted order); levels kept beside it (16 bit)
+// 2^d-cell block, in ascending sorted order); each anchor's level offsets sit
+// in dloff
 constexpr int kDampLocBits = 16;
 constexpr int kDampMaxLocal = 1 << kDampLocBits;
 constexpr int kDampMaxLevel = 255;      // levels of one anchor (offsets held in 4 registers)
@@ -128,7 +129,6 @@ struct sph_nbr {
   int64_t* aoff = nullptr;
   uint32_t* anlev = nullptr;
   uint32_t* dpair = nullptr;         // [n_upairs] packed damping pairs (canonical order)
-  uint16_t* dlev = nullptr;          // [n_upairs] their levels
   uint16_t* dloff = nullptr;         // level offsets of every anchor (relative to its first pair)
   uint32_t* dloff_base = nullptr;    // [n_anchors] start of each anchor's offsets in dloff
   uint32_t* ablk = nullptr;          // [n_anchors][8] anchor block runs (begin, count) x 4
@@ -143,6 +143,11 @@ struct sph_nbr {
   sph::Ctrl* ctrl = nullptr;         // device
   sph::Ctrl* ctrl_host = nullptr;    // pinned host mirror
   double* ke_partial = nullptr;      // device [kKeMaxBlocks]
+  double* gpart = nullptr;           // device [gpart_slots][SPH_NGRAD] gradient partials
+  int64_t gpart_slots = 0;
+  // inner-step recording of a taped run (set by the driver while it runs)
+  mutable double* rec_u = nullptr;   // [k][dim][n]: u before inner step k
+  mutable void* rec_pl = nullptr;    // [k][7][n]: J2 state before inner step k
   int device = 0;
   sph::Prof* prof = nullptr;         // host-side timing state
 };
@@ -188,6 +193,8 @@ int solid_stage(const sph_nbr* nb, const sph_material* m, const sph_state* st, d
                 hipStream_t s, bool gated);
 int damping_sweep(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
                   double dt, hipStream_t s, bool gated);
+int damping_sweep_rev(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
+                      double dt, hipStream_t s);
 int drift_ke(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
              double* ke_out, hipStream_t s, bool gated);
 int load_step(const sph_nbr* nb, const sph_state* st, double dt_l, hipStream_t s);
@@ -195,5 +202,17 @@ int diffusion_step(const sph_nbr* nb, const sph_material* m, const sph_state* st
                    double dt_d, double c_bc, hipStream_t s);
 int reset_ctrl(const sph_nbr* nb, int64_t k_limit, double ke_tol, hipStream_t s);
 int check_state(const sph_nbr* nb, const sph_state* st, bool need_v);
+// reverse mode (sph_adjoint.hip)
+int adj_solid(const sph_nbr* nb, const sph_material* m, const double* u, const void* plastic,
+              const sph_state* st, const sph_adjoint* adj, double dt, double drift_dt,
+              hipStream_t s);
+int adj_damping(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                const sph_adjoint* adj, double eta, double dt, hipStream_t s);
+int adj_drift(const sph_nbr* nb, const sph_state* st, const sph_adjoint* adj, double dt,
+              hipStream_t s);
+int adj_diffusion(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                  const void* c_before, const sph_adjoint* adj, double Dc, double dt,
+                  hipStream_t s);
+int grad_reduce(const sph_nbr* nb, double* grad, hipStream_t s);
 
 }  // namespace sph

@@ -124,6 +124,47 @@ struct GraphChunk {
   }
 };
 
+// checkpoint slice l of a tape <-> the state arrays
+int tape_copy(const sph_nbr* nb, const sph_material* m, const sph_state* st, const sph_tape* tp,
+              int l, bool to_tape, hipStream_t s) {
+  const size_t n = (size_t)nb->n, d = (size_t)nb->dim;
+  const size_t T = st->prec == SPH_F64 ? 8 : 4;
+  auto cp = [&](void* tape_base, void* arr, size_t bytes) -> int {
+    if (!tape_base || !arr || bytes == 0) return SPH_OK;
+    char* t = (char*)tape_base + (size_t)l * bytes;
+    SPH_HIP(hipMemcpyAsync(to_tape ? (void*)t : arr, to_tape ? arr : (void*)t, bytes,
+                           hipMemcpyDeviceToDevice, s));
+    return SPH_OK;
+  };
+  int rc = cp(tp->ck_u, st->u, d * n * 8);
+  if (!rc) rc = cp(tp->ck_v, st->v, d * n * T);
+  if (!rc && m->model == SPH_MODEL_J2) rc = cp(tp->ck_plastic, st->plastic, 7 * n * T);
+  if (!rc) rc = cp(tp->ck_c, st->c, n * T);
+  return rc;
+}
+
+int check_tape(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+               const sph_multirate_cfg* cfg, const sph_tape* tp) {
+  if (cfg->n_slow > tp->n_slow_cap) {
+    set_error("tape holds %d slow steps, the run has %d", tp->n_slow_cap, cfg->n_slow);
+    return SPH_E_CAPACITY;
+  }
+  if (!tp->ck_u || !tp->ck_v || !tp->k_rec || (m->model == SPH_MODEL_J2 && !tp->ck_plastic) ||
+      (cfg->slow_kind == SPH_SLOW_DIFFUSION && (!tp->ck_c || !st->c))) {
+    set_error("tape checkpoint arrays missing");
+    return SPH_E_ARG;
+  }
+  return SPH_OK;
+}
+
+struct RecGuard {  // inner-state recording is switched off on every exit
+  const sph_nbr* nb;
+  ~RecGuard() {
+    nb->rec_u = nullptr;
+    nb->rec_pl = nullptr;
+  }
+};
+
 }  // namespace
 
 extern "C" int sph_solid_relax_step(const sph_nbr* nb, const sph_material* mat,
@@ -204,7 +245,7 @@ extern "C" int sph_status(const sph_nbr* nb, void* stream, int32_t* bits) {
 
 extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
                                      const sph_state* st, const sph_multirate_cfg* cfg,
-                                     sph_report* rep, void* stream) {
+                                     sph_report* rep, sph_tape* tape, void* stream) {
   clear_error();
   int rc = check_state(nb, st, true);
   if (rc) return rc;
@@ -229,6 +270,9 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
   const int64_t k_max = cfg->k_max > 0 ? cfg->k_max : (int64_t)std::floor(dt_slow / dt_s) + 1;
   const bool adaptive = cfg->k_sched == nullptr && cfg->fixed_inner <= 0;
   const int chunk = cfg->chunk > 0 ? cfg->chunk : 64;
+  if (tape && (rc = check_tape(nb, m, st, cfg, tape))) return rc;
+  RecGuard rec_guard{nb};
+  bool recorded = false;
   if (rep) {
     rep->dt_s = dt_s;
     rep->dt_slow = dt_slow;
@@ -266,6 +310,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
   }
   int warn = 0;
   for (int32_t l = 0; l < cfg->n_slow && rc == SPH_OK; ++l) {
+    if (tape && (rc = tape_copy(nb, m, st, tape, l, true, s))) break;
     if (cfg->slow_kind == SPH_SLOW_LOAD)
       rc = load_step(nb, st, dt_slow, s);
     else
@@ -274,6 +319,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     const int64_t nk = cfg->k_sched ? cfg->k_sched[l] : (cfg->fixed_inner > 0 ? cfg->fixed_inner : k_max);
     Ctrl* hc = nb->ctrl_host;
     if (nk <= 0) {
+      if (tape) tape->k_rec[l] = 0;
       if (rep && rep->k) rep->k[l] = 0;
       if (rep && rep->ke) rep->ke[l] = 0.0;
       if (rep && rep->converged) rep->converged[l] = 1;
@@ -281,6 +327,15 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     }
     rc = reset_ctrl(nb, nk, adaptive ? cfg->ke_tol : -1.0, s);
     if (rc) break;
+    // the last slow step's inner states go to the tape when they fit (eager launches only)
+    const bool rec = tape && l == cfg->n_slow - 1 && !graph && tape->hist_u &&
+                     nk <= tape->k_hist_cap &&
+                     (m->model != SPH_MODEL_J2 || tape->hist_plastic);
+    if (rec) {
+      nb->rec_u = tape->hist_u;
+      nb->rec_pl = tape->hist_plastic;
+      recorded = true;
+    }
     int64_t launched = 0;
     for (;;) {
       int64_t mcount = graph ? chunk : std::min<int64_t>(chunk, nk - launched);
@@ -304,7 +359,10 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
       if (nb->prof) prof_resolve(nb);
       if (hc->done || launched >= nk) break;
     }
+    nb->rec_u = nullptr;
+    nb->rec_pl = nullptr;
     if (rc) break;
+    if (tape) tape->k_rec[l] = hc->k;
     if (rep && rep->k) rep->k[l] = hc->k;
     if (rep && rep->ke) rep->ke[l] = hc->ke;
     const int conv = hc->ke <= cfg->ke_tol;
@@ -329,5 +387,105 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     hipStreamDestroy(own);
   }
   if (rc) return rc;
+  if (tape) {
+    if ((rc = tape_copy(nb, m, st, tape, cfg->n_slow, true, user))) return rc;
+    tape->n_rec = cfg->n_slow;
+    tape->hist_slow = recorded ? cfg->n_slow - 1 : -1;
+    tape->dt_s = dt_s;
+    tape->dt_slow = dt_slow;
+    SPH_HIP(hipStreamSynchronize(user));
+  }
   return warn ? SPH_W_NOT_CONVERGED : SPH_OK;
+}
+
+// Reverse pass: slow steps last to first; each is re-run from its checkpoint
+// with its inner states recorded (unless the tape already holds them), then
+// its inner steps are reversed, then its slow update.
+extern "C" int sph_advance_multirate_backward(const sph_nbr* nb, const sph_material* m,
+                                              const sph_state* st, const sph_multirate_cfg* cfg,
+                                              sph_tape* tape, const sph_adjoint* adj,
+                                              void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!m || !cfg || !tape || !adj) {
+    set_error("material, cfg, tape or adjoint is NULL");
+    return SPH_E_ARG;
+  }
+  if (adj->prec != st->prec || !adj->u || !adj->v || !adj->work || !adj->grad ||
+      (m->model == SPH_MODEL_J2 && !adj->plastic) ||
+      (cfg->slow_kind == SPH_SLOW_DIFFUSION && !adj->c)) {
+    set_error("adjoint arrays missing or of the wrong precision");
+    return SPH_E_ARG;
+  }
+  if ((rc = check_tape(nb, m, st, cfg, tape))) return rc;
+  if (tape->n_rec != cfg->n_slow) {
+    set_error("the tape holds %d slow steps, cfg asks for %d", tape->n_rec, cfg->n_slow);
+    return SPH_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int L = cfg->n_slow;
+  const double dt = tape->dt_s, dt_slow = tape->dt_slow;
+  const size_t n = (size_t)nb->n, d = (size_t)nb->dim;
+  const size_t T = st->prec == SPH_F64 ? 8 : 4;
+  std::vector<int64_t> before(L + 1, 0);
+  for (int l = 0; l < L; ++l) before[l + 1] = before[l] + tape->k_rec[l];
+  RecGuard rec_guard{nb};
+  bool first = true;  // the next reversed inner step is the run's last one
+  for (int l = L - 1; l >= 0; --l) {
+    const int64_t kl = tape->k_rec[l];
+    if (tape->hist_slow != l) {
+      if (kl > 0 && (kl > tape->k_hist_cap || !tape->hist_u ||
+                     (m->model == SPH_MODEL_J2 && !tape->hist_plastic))) {
+        set_error("slow step %d has %lld inner steps; the tape records %lld", l, (long long)kl,
+                  (long long)tape->k_hist_cap);
+        return SPH_E_CAPACITY;
+      }
+      if ((rc = tape_copy(nb, m, st, tape, l, false, s))) return rc;
+      rc = cfg->slow_kind == SPH_SLOW_LOAD ? load_step(nb, st, dt_slow, s)
+                                           : diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
+      if (rc) return rc;
+      if (kl > 0) {
+        if ((rc = reset_ctrl(nb, kl, -1.0, s))) return rc;
+        nb->rec_u = tape->hist_u;
+        nb->rec_pl = tape->hist_plastic;
+        tape->hist_slow = -1;
+        for (int64_t done = 0; done < kl;) {
+          const int c = (int)std::min<int64_t>(kl - done, 256);
+          if ((rc = inner_steps(nb, m, st, dt, cfg->eta, c, s))) return rc;
+          done += c;
+        }
+        nb->rec_u = nullptr;
+        nb->rec_pl = nullptr;
+        tape->hist_slow = l;
+      }
+    }
+    for (int64_t k = kl - 1; k >= 0; --k) {
+      if (first) {
+        if ((rc = adj_drift(nb, st, adj, dt, s))) return rc;
+        first = false;
+      }
+      if ((rc = adj_damping(nb, m, st, adj, cfg->eta, dt, s))) return rc;
+      const double* uk = tape->hist_u + (size_t)k * d * n;
+      const void* plk = m->model == SPH_MODEL_J2
+                            ? (const void*)((const char*)tape->hist_plastic + (size_t)k * 7 * n * T)
+                            : nullptr;
+      const bool has_prev = before[l] + k > 0;
+      if ((rc = adj_solid(nb, m, uk, plk, st, adj, dt, has_prev ? dt : 0.0, s))) return rc;
+    }
+    if (cfg->slow_kind == SPH_SLOW_DIFFUSION) {
+      const void* c_before = (const char*)tape->ck_c + (size_t)l * n * T;
+      if ((rc = adj_diffusion(nb, m, st, c_before, adj, cfg->D, dt_slow, s))) return rc;
+    }
+  }
+  if ((rc = grad_reduce(nb, adj->grad, s))) return rc;
+  if ((rc = tape_copy(nb, m, st, tape, L, false, s))) return rc;
+  SPH_HIP(hipMemcpyAsync(nb->ctrl_host, nb->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  if (nb->prof) prof_resolve(nb);
+  if (nb->ctrl_host->status) {
+    set_error("device status bits 0x%x in the reverse pass", nb->ctrl_host->status);
+    return SPH_E_NUMERIC;
+  }
+  return SPH_OK;
 }
