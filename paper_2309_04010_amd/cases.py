@@ -134,6 +134,7 @@ def strip2d(nx=200, ny=10, dp=12.5e-6, clamp_layers=3, E=100.0e6, nu=0.4, D=1.0e
     flags[(idx[0] < clamp_layers) | (idx[0] >= nx - clamp_layers)] |= FIXED
     flags[idx[1] == ny - 1] |= CDIR
     c_init = np.zeros(n)
+    c_init[idx[1] == ny - 1] = a_por      # the boundary value holds from t = 0
     # density kinetic energy sum(1/2 m v^2) / sum(V) <= frac * C * a; the
     # paper's frac = 5e-4 stops after a single inner step at this spacing, so
     # the workload uses 1e-8 (about 150-250 inner steps per diffusion step)
@@ -190,6 +191,7 @@ def plate3d(nx=500, ny=500, nz=4, dp=31.25e-6, clamp_layers=3, patch=0.3, wet_la
            (idx[2] >= nz - wet_layers))
     flags[wet] |= CDIR
     c_init = np.zeros(n)
+    c_init[wet] = 0.4                     # the boundary value holds from t = 0
     ci, cj = (nx - 1) // 2, (ny - 1) // 2
     centre = np.isin(idx[0], [ci, ci + 1]) & np.isin(idx[1], [cj, cj + 1])
     return Case("plate3d", 3, (nx, ny, nz), dp, X, V, 1.3 * dp, flags, None, c_init,

@@ -173,3 +173,23 @@ def test_j2_nonlinear_consistency_and_bisection(o):
             snew = np.linalg.norm(_dev_tau(F, P))
             assert abs(snew - np.sqrt(2 / 3) * k(pl[6])) <= 1e-10 * snew
     assert pl[6] > 0
+
+
+def test_j2_state_update_is_idempotent(o):
+    """After a plastic return at F, the updated state Cbar_p^-1 rebuilds the
+    returned elastic strain: evaluating again at the same F from that state is
+    an elastic step on the yield surface, so the stress repeats and alpha does
+    not grow (App. A.4: the state update closes Algorithm 1).  A transposed or
+    mis-signed state update fails this."""
+    s0, sinf, dl = 2.0e8, 4.0e8, 16.0
+    j2 = o.material(cases.J2, E, NU, 7850.0, sigma0=s0, sigma_inf=sinf, delta=dl)
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        F = np.eye(3) + rng.normal(0.0, 6e-3, (3, 3))
+        rc, P1, pl1 = o.constitutive(j2, F)
+        assert rc == 0 and pl1[6] > 0.0          # the first call yields
+        rc, P2, pl2 = o.constitutive(j2, F, pl1)
+        assert rc == 0
+        assert np.abs(P2 - P1).max() <= 1e-9 * np.abs(P1).max()
+        assert abs(pl2[6] - pl1[6]) <= 1e-9 * pl1[6]
+        assert np.abs(pl2[:6] - pl1[:6]).max() <= 1e-9 * max(np.abs(pl1[:6]).max(), 1e-12)
