@@ -140,6 +140,7 @@ typedef struct {
   int32_t chunk;       /* inner steps launched between host polls (<= 0: 64) */
   int32_t use_graph;   /* 1: replay each chunk as a captured hipGraph */
   const int64_t* k_sched; /* host, optional [n_slow]: frozen inner counts */
+  const struct sph_batch* batch; /* optional: per-specimen parameters (see sph_build_neighbors_batched) */
 } sph_multirate_cfg;
 
 typedef struct {
@@ -345,6 +346,55 @@ int sph_constitutive(const sph_material* mat, int prec, int64_t n, const void* H
 int sph_constitutive_vjp(const sph_material* mat, int prec, int64_t n, const void* H,
                          const void* plastic, const void* p, const void* Pbar, void* plastic_bar,
                          void* Hbar, void* pbar, void* theta_bar, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent specimens (parameter sweeps).  Several specimens
+ * share one particle set and one neighbour handle, and every kernel runs over
+ * all of them in a single launch.  Each specimen gets its own segment of the
+ * cell grid -- its own origin and cell counts, cell keys offset by those of
+ * the specimens before it -- so its cells, sorted order, neighbour lists,
+ * correction matrices and damping order are exactly those it has when built
+ * alone, and specimens may overlap in space.  Per-specimen scalars come from
+ * small device tables indexed by each particle's specimen id.
+ *
+ * sph_build_neighbors_batched: as sph_build_neighbors, with spec_id [n]
+ * (device int32, input order) assigning particles to specimens 0..n_spec-1 in
+ * contiguous ascending runs.  Sorted positions then hold specimen after
+ * specimen.  With n_spec == 1 it is sph_build_neighbors.  Errors as
+ * sph_build_neighbors, plus SPH_E_ARG for ids that are not contiguous
+ * ascending runs and SPH_E_CAPACITY for more than 65535 specimens. */
+int sph_build_neighbors_batched(int dim, int64_t n, const double* X, const double* V, double h,
+                                int32_t n_spec, const int32_t* spec_id, void* stream,
+                                sph_nbr** out);
+
+/* Per-specimen values that replace the uniform ones of sph_material (E) and
+ * sph_multirate_cfg (D, dt_s, dt_slow) when cfg->batch is set.  Host arrays of
+ * n_spec doubles, copied to the device at the start of each run.  The other
+ * material and schedule values are shared by all specimens.  A batched run
+ * needs fixed inner counts (fixed_inner or k_sched): one specimen's kinetic
+ * energy does not decide another's stop.  `grad` (device [n_spec][SPH_NGRAD],
+ * may be NULL) receives the reverse pass's per-specimen gradients (+=). */
+typedef struct sph_batch {
+  int32_t n_spec;
+  int32_t pad_;
+  const double* E;
+  const double* D;
+  const double* dt_s;
+  const double* dt_slow;
+  double* grad;
+} sph_batch;
+
+/* Forward run, and the reverse pass when adj is not NULL, recorded as ONE
+ * hipGraph and launched once; the instantiated graph is kept in the handle
+ * and launched again while the arguments (the structures' contents) stay
+ * the same -- per-specimen values may change between launches.  Needs fixed
+ * inner counts and a tape whose k_hist_cap covers one slow step's inner
+ * count.  Results equal the eager
+ * sph_advance_multirate + sph_advance_multirate_backward bitwise.
+ * Synchronous.  Fills the report's counts. */
+int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                                const sph_multirate_cfg* cfg, sph_report* report, sph_tape* tape,
+                                const sph_adjoint* adj, void* stream);
 
 /* Synchronise `stream` and return (and clear) the latched status bits in
  * *status_bits (may be NULL): SPH_OK, or SPH_E_NUMERIC if any bit was set. */

@@ -29,7 +29,7 @@ EXPORTED = [
     "sph_advance_multirate", "sph_status", "sph_profile_enable", "sph_profile_read",
     "sph_last_error", "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_drift_vjp",
     "sph_diffusion_step_vjp", "sph_advance_multirate_backward", "sph_constitutive",
-    "sph_constitutive_vjp",
+    "sph_constitutive_vjp", "sph_build_neighbors_batched", "sph_advance_multirate_graph",
 ]
 SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load",
                     "adj_stress", "adj_gather", "adj_damping"]
@@ -70,7 +70,12 @@ class State(C.Structure):
 class MultirateCfg(C.Structure):
     _fields_ = [("n_slow", i32), ("slow_kind", i32), ("dt_slow", dbl), ("dt_s", dbl), ("eta", dbl),
                 ("k_max", i64), ("fixed_inner", i64), ("ke_tol", dbl), ("D", dbl), ("c_bc", dbl),
-                ("chunk", i32), ("use_graph", i32), ("k_sched", vp)]
+                ("chunk", i32), ("use_graph", i32), ("k_sched", vp), ("batch", vp)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_spec", i32), ("pad_", i32), ("E", vp), ("D", vp), ("dt_s", vp), ("dt_slow", vp),
+                ("grad", vp)]
 
 
 class Tape(C.Structure):
@@ -123,6 +128,10 @@ def lib():
     L.sph_constitutive.argtypes = [C.POINTER(Material), C.c_int, i64, vp, vp, vp, vp, vp]
     L.sph_constitutive_vjp.argtypes = [C.POINTER(Material), C.c_int, i64, vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp]
+    L.sph_build_neighbors_batched.argtypes = [C.c_int, i64, vp, vp, dbl, i32, vp, vp, C.POINTER(vp)]
+    L.sph_advance_multirate_graph.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
+                                              C.POINTER(MultirateCfg), C.POINTER(Report), C.POINTER(Tape),
+                                              C.POINTER(Adjoint), vp]
     L.sph_status.argtypes = [vp, vp, C.POINTER(i32)]
     L.sph_profile_enable.argtypes = [vp, C.c_int]
     L.sph_profile_read.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)]
@@ -339,15 +348,71 @@ def sph_status(nbr, stream=None):
 
 
 def multirate_cfg(n_slow, slow_kind, dt_slow=0.0, dt_s=0.0, eta=0.0, k_max=0, fixed_inner=0,
-                  ke_tol=0.0, D=0.0, c_bc=0.0, chunk=64, use_graph=0, k_sched=None):
+                  ke_tol=0.0, D=0.0, c_bc=0.0, chunk=64, use_graph=0, k_sched=None, batch=None):
     cfg = MultirateCfg(int(n_slow), int(slow_kind), float(dt_slow), float(dt_s), float(eta), int(k_max),
                        int(fixed_inner), float(ke_tol), float(D), float(c_bc), int(chunk), int(use_graph),
-                       None)
+                       None, None)
     if k_sched is not None:
         ks = np.ascontiguousarray(k_sched, dtype=np.int64)
         cfg._ks = ks
         cfg.k_sched = ks.ctypes.data_as(vp)
+    if batch is not None:
+        cfg._batch = batch
+        cfg.batch = C.cast(C.pointer(batch.cstruct()), vp)
     return cfg
+
+
+class SphBatch:
+    """Per-specimen values of a batched run (sph_batch): host arrays of n_spec
+    doubles for E, D, dt_s, dt_slow; `grad` a device [n_spec, SPH_NGRAD] tensor."""
+
+    def __init__(self, E, D, dt_s, dt_slow, grad=None):
+        self.E = np.ascontiguousarray(E, dtype=np.float64)
+        n = self.E.size
+        self.D = np.ascontiguousarray(D, dtype=np.float64)
+        self.dt_s = np.ascontiguousarray(dt_s, dtype=np.float64)
+        self.dt_slow = np.ascontiguousarray(dt_slow, dtype=np.float64)
+        assert self.D.size == n and self.dt_s.size == n and self.dt_slow.size == n
+        self.grad = grad
+        self._c = None
+
+    def cstruct(self):
+        import torch
+        if self.grad is not None:
+            _need(self.grad, torch.float64, (self.E.size, SPH_NGRAD), "batch.grad")
+        self._c = Batch(int(self.E.size), 0, self.E.ctypes.data_as(vp), self.D.ctypes.data_as(vp),
+                        self.dt_s.ctypes.data_as(vp), self.dt_slow.ctypes.data_as(vp), _dptr(self.grad))
+        return self._c
+
+
+def sph_build_neighbors_batched(X, V, h, spec_id, stream=None):
+    """X: cuda float64 [dim, n]; V: cuda float64 [n]; spec_id: cuda int32 [n]
+    (contiguous ascending runs 0..n_spec-1), all in input order."""
+    import torch
+    dim, n = X.shape
+    _need(X, torch.float64, (dim, n), "X")
+    _need(V, torch.float64, (n,), "V")
+    _need(spec_id, torch.int32, (n,), "spec_id")
+    n_spec = int(spec_id.max().item()) + 1
+    out = C.c_void_p()
+    _check(lib().sph_build_neighbors_batched(int(dim), int(n), _dptr(X), _dptr(V), float(h), n_spec,
+                                             _dptr(spec_id), _stream(stream), C.byref(out)))
+    return Neighbors(out, (X, V, spec_id))
+
+
+def sph_advance_multirate_graph(nbr, mat, st, cfg, tape=None, adj=None, stream=None):
+    """Forward (+ reverse when adj is given) as one recorded graph; returns k."""
+    cs = st.cstruct(nbr)
+    ns = cfg.n_slow
+    k = np.zeros(max(ns, 1), np.int64)
+    rep_ = Report(k.ctypes.data_as(vp), None, None, 0.0, 0.0, 0, 0)
+    tp = None if tape is None else C.byref(tape.cstruct(nbr, st))
+    ad = None if adj is None else C.byref(adj.cstruct(nbr))
+    _check(lib().sph_advance_multirate_graph(nbr.handle, C.byref(mat), C.byref(cs), C.byref(cfg),
+                                             C.byref(rep_), tp, ad, _stream(stream)))
+    if tape is not None:
+        tape.sync_out()
+    return k[:ns]
 
 
 def sph_advance_multirate(nbr, mat, st, cfg, tape=None, stream=None):

@@ -217,5 +217,60 @@ def strips_sweep(n_strips=64, seed=5, dp=12.5e-6, n_min=1000, n_max=50000, rows=
     return out
 
 
+@dataclass
+class Batch:
+    """Several specimens as one particle set, specimen after specimen in input
+    order.  Each specimen keeps its own cell grid, so they may overlap in
+    space; `batch(..., stack=True)` still stacks them along y for clarity."""
+    cases: list
+    X: np.ndarray          # [dim, n] input order, specimen after specimen
+    V: np.ndarray
+    h: float
+    flags: np.ndarray
+    c_init: np.ndarray
+    spec: np.ndarray       # [n] int32 specimen id
+    offsets: np.ndarray    # [n_spec + 1] input-order ranges
+    material: dict         # shared values (E is per specimen)
+    run: dict              # shared schedule (D, dt_s, dt_slow per specimen)
+    E: np.ndarray
+    D: np.ndarray
+    dt_s: np.ndarray
+    dt_slow: np.ndarray
+
+    @property
+    def n(self):
+        return self.X.shape[1]
+
+    @property
+    def dim(self):
+        return self.X.shape[0]
+
+
+def batch(cs, gap_dp=4.0, stack=True):
+    """2D diffusion specimens of equal dp, h, nu, rho0, C_swell, eta and
+    schedule as one Batch; per-specimen E, D and step sizes."""
+    c0 = cs[0]
+    dp, h = c0.dp, c0.h
+    Xs, y0, offs = [], 0.0, [0]
+    for c in cs:
+        assert c.dim == 2 and c.dp == dp and c.h == h
+        X = c.X.copy()
+        if stack:
+            X[1] += y0 - X[1].min() + 0.5 * dp
+            y0 = X[1].max() + gap_dp * dp
+        Xs.append(X)
+        offs.append(offs[-1] + c.n)
+    E = np.array([c.material["E"] for c in cs])
+    D = np.array([c.run["D"] for c in cs])
+    m = c0.material
+    K = E / (3.0 * (1.0 - 2.0 * m["nu"]))
+    dt_s = 0.6 * h / np.sqrt(K / m["rho0"])
+    dt_slow = 0.5 * h * h / D
+    spec = np.concatenate([np.full(c.n, i, np.int32) for i, c in enumerate(cs)])
+    return Batch(list(cs), np.hstack(Xs), np.concatenate([c.V for c in cs]), h,
+                 np.concatenate([c.flags for c in cs]), np.concatenate([c.c_init for c in cs]),
+                 spec, np.array(offs), dict(m), dict(c0.run), E, D, dt_s, dt_slow)
+
+
 def by_name(name, **kw):
     return {"bar2d": bar2d, "strip2d": strip2d, "neck3d": neck3d, "plate3d": plate3d}[name](**kw)

@@ -440,7 +440,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
     TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
     const uint8_t* __restrict__ flags, T dt, T inv_rho0, const T* __restrict__ plastic,
     T* __restrict__ plb, const T* __restrict__ p, double* __restrict__ pbar, T* __restrict__ Gb,
-    double* __restrict__ gpart, Ctrl* ctrl) {
+    double* __restrict__ gpart, Ctrl* ctrl, Bat bt) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
     xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
     xv.w = g.V[gi];
     const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
-    const T kf = fixed ? T(0) : dt;
+    const T kf = fixed ? T(0) : (bt.spec ? bt.get<T>(BT_DT, bt.spec[gi]) : dt);
     uv.x = (T)(u[gi] - uo[0]);
     uv.y = (T)(u[n + gi] - uo[1]);
     if (D == 2) {
@@ -575,7 +575,14 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
       }
     }
     T Hb[9], th[kNTheta], pb = T(0);
-    const int st = constitutive_vjp(m, Hm, pl, p ? p[a] : T(0), Pb, pv, Hb, pb, th);
+    MatP<T> mm = m;
+    if (bt.spec) {
+      const int sp = bt.spec[a];
+      mm.mu = bt.get<T>(BT_MU, sp);
+      mm.K = bt.get<T>(BT_K, sp);
+      mm.lam = bt.get<T>(BT_LAM, sp);
+    }
+    const int st = constitutive_vjp(mm, Hm, pl, p ? p[a] : T(0), Pb, pv, Hb, pb, th);
     if (st) atomicOr(&ctrl->status, st);
     if (m.model == SPH_MODEL_J2) {
 #pragma unroll
@@ -605,7 +612,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
 template <typename T, int D>
 __global__ __launch_bounds__(128 * kLppMomentum) void k_adj_gather(
     TileGeo<T> g, const T* __restrict__ Gb, double* __restrict__ ub, T* __restrict__ w,
-    const uint8_t* __restrict__ flags, double drift_dt) {
+    const uint8_t* __restrict__ flags, double drift_dt, Bat bt) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
   constexpr int NP = (D * D + 3) / 4;
@@ -683,22 +690,24 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_adj_gather(
   for (int i = 0; i < D; ++i) f[i] = lane_sum<kLppMomentum>(f[i]);
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
+  const double ddt = (drift_dt != 0.0 && bt.spec) ? bt.get<double>(BT_DT, bt.spec[a]) : drift_dt;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const double un = ub[i * n + a] - (double)f[i];
     ub[i * n + a] = un;
-    if (drift_dt != 0.0 && !fixed) w[i * n + a] += (T)(drift_dt * un);
+    if (ddt != 0.0 && !fixed) w[i * n + a] += (T)(ddt * un);
   }
 }
 
 template <typename T, int D>
 __global__ void k_adj_drift(int64_t n, const double* __restrict__ ub, T* __restrict__ w,
-                            const uint8_t* __restrict__ flags, double dt) {
+                            const uint8_t* __restrict__ flags, double dt, Bat bt) {
   const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (a >= n) return;
   if (flags && (flags[a] & SPH_FLAG_FIXED)) return;
+  const double dta = bt.spec ? bt.get<double>(BT_DT, bt.spec[a]) : dt;
 #pragma unroll
-  for (int k = 0; k < D; ++k) w[k * n + a] += (T)(dt * ub[k * n + a]);
+  for (int k = 0; k < D; ++k) w[k * n + a] += (T)(dta * ub[k * n + a]);
 }
 
 // reverse of the diffusion step, first pass (per particle a, gather over b):
@@ -713,15 +722,18 @@ __global__ __launch_bounds__(256) void k_adiff_a(Geo<T> g, const T* __restrict__
                                                  const double* __restrict__ pbar,
                                                  const uint8_t* __restrict__ flags, T dt, T Dc,
                                                  T Cs, T c0, T* __restrict__ sbar,
-                                                 double* __restrict__ gpart) {
+                                                 double* __restrict__ gpart, Bat bt,
+                                                 double* __restrict__ gdiff) {
   const int64_t n = g.n;
   const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double gd[2] = {0.0, 0.0};
   if (a < n) {
     auto cdb = [&](int64_t i) -> T {
       if (flags && (flags[i] & SPH_FLAG_CDIR)) return T(0);
-      return dt * (cb[i] + (pbar ? Cs * (T)pbar[i] : T(0)));
+      const T dti = bt.spec ? bt.get<T>(BT_DTD, bt.spec[i]) : dt;
+      return dti * (cb[i] + (pbar ? Cs * (T)pbar[i] : T(0)));
     };
+    const T Da = bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc;
     double xa[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
@@ -767,10 +779,17 @@ __global__ __launch_bounds__(256) void k_adiff_a(Geo<T> g, const T* __restrict__
       T x = T(0);
 #pragma unroll
       for (int i = 0; i < D; ++i) x += g.B0[(i * D + k) * n + a] * qb[i];
-      sbar[k * n + a] = -Dc * x;
+      sbar[k * n + a] = -Da * x;
     }
     gd[0] = dsum;
     gd[1] = pbar ? pbar[a] * ((double)cnew[a] - (double)c0) : 0.0;
+  }
+  if (bt.spec) {  // batched: per-particle partials, reduced per specimen later
+    if (a < n) {
+      gdiff[a] += gd[0];
+      gdiff[n + a] += gd[1];
+    }
+    return;
   }
   const int slots[2] = {SPH_GRAD_D, SPH_GRAD_C};
   block_grad_add<2>(gd, slots, gpart);
@@ -870,14 +889,15 @@ static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const double* u
     hipEvent_t pe_ = prof_begin(nb, s);
     k_adj_stress<T, D><<<grid, (unsigned)(g.tmax * kLppStress), lds_s, s>>>(
         g, mp, u, (const T*)adj->v, st->flags, (T)dt, (T)(1.0 / m->rho0), (const T*)plastic,
-        (T*)adj->plastic, (const T*)st->p, adj->p, (T*)adj->work, nb->gpart, nb->ctrl);
+        (T*)adj->plastic, (const T*)st->p, adj->p, (T*)adj->work, nb->gpart, nb->ctrl,
+        bat_view(nb));
     prof_end(nb, SPH_KERNEL_ADJ_STRESS, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   {
     hipEvent_t pe_ = prof_begin(nb, s);
     k_adj_gather<T, D><<<grid, (unsigned)(g.tmax * kLppMomentum), lds_g, s>>>(
-        g, (const T*)adj->work, adj->u, (T*)adj->v, st->flags, drift_dt);
+        g, (const T*)adj->work, adj->u, (T*)adj->v, st->flags, drift_dt, bat_view(nb));
     prof_end(nb, SPH_KERNEL_ADJ_GATHER, pe_, s);
   }
   SPH_LAUNCH_CHECK();
@@ -929,11 +949,11 @@ int adj_drift(const sph_nbr* nb, const sph_state* st, const sph_adjoint* adj, do
               hipStream_t s) {
   const unsigned gr = nblk256(nb->n);
   if (adj->prec == SPH_F64) {
-    if (nb->dim == 2) k_adj_drift<double, 2><<<gr, 256, 0, s>>>(nb->n, adj->u, (double*)adj->v, st->flags, dt);
-    else k_adj_drift<double, 3><<<gr, 256, 0, s>>>(nb->n, adj->u, (double*)adj->v, st->flags, dt);
+    if (nb->dim == 2) k_adj_drift<double, 2><<<gr, 256, 0, s>>>(nb->n, adj->u, (double*)adj->v, st->flags, dt, bat_view(nb));
+    else k_adj_drift<double, 3><<<gr, 256, 0, s>>>(nb->n, adj->u, (double*)adj->v, st->flags, dt, bat_view(nb));
   } else {
-    if (nb->dim == 2) k_adj_drift<float, 2><<<gr, 256, 0, s>>>(nb->n, adj->u, (float*)adj->v, st->flags, dt);
-    else k_adj_drift<float, 3><<<gr, 256, 0, s>>>(nb->n, adj->u, (float*)adj->v, st->flags, dt);
+    if (nb->dim == 2) k_adj_drift<float, 2><<<gr, 256, 0, s>>>(nb->n, adj->u, (float*)adj->v, st->flags, dt, bat_view(nb));
+    else k_adj_drift<float, 3><<<gr, 256, 0, s>>>(nb->n, adj->u, (float*)adj->v, st->flags, dt, bat_view(nb));
   }
   SPH_LAUNCH_CHECK();
   return SPH_OK;
@@ -951,7 +971,7 @@ static int adj_diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_s
   }
   k_adiff_a<T, D><<<gr, 256, 0, s>>>(g, (const T*)c_before, (const T*)st->c, (const T*)adj->c,
                                      adj->p, st->flags, (T)dt, (T)Dc, (T)m->C_swell, (T)m->c0,
-                                     (T*)adj->work, nb->gpart);
+                                     (T*)adj->work, nb->gpart, bat_view(nb), nb->gdiff);
   SPH_LAUNCH_CHECK();
   k_adiff_b<T, D><<<gr, 256, 0, s>>>(g, (const T*)adj->work, (T*)adj->c, adj->p, st->flags,
                                      (T)m->C_swell);

@@ -136,32 +136,98 @@ __global__ __launch_bounds__(1024) void k_bounds(const double* X, int64_t n, int
   }
 }
 
+// The cell grid is a list of segments, one per specimen (one for an
+// ordinary build): each has its own origin and cell counts, and its keys
+// follow those of the previous segment, key = koff + x + nc0 (y + nc1 z).
+// A specimen therefore gets exactly the cells, order and schedule it gets
+// alone, and no cell or neighbour search crosses specimens.
 struct Grid {
   int dim;
-  int64_t nc0, nc1, nc2;
-  double o0, o1, o2;
+  int nseg;
+  GridSeg g0;                 // the only segment when nseg == 1
+  const GridSeg* seg;         // device [nseg]
+  const uint16_t* cell_seg;   // device [n_cells]: segment of each cell (nseg > 1)
   double inv_rc;
 };
 
-__device__ __forceinline__ void key_coords(uint32_t key, const Grid& g, int64_t c[3]) {
-  int64_t k = key;
-  c[0] = k % g.nc0;
-  k /= g.nc0;
-  c[1] = k % g.nc1;
-  c[2] = k / g.nc1;
+__device__ __forceinline__ GridSeg seg_of_cell(const Grid& g, uint32_t key) {
+  return g.nseg == 1 ? g.g0 : g.seg[g.cell_seg[key]];
 }
 
-__global__ void k_cellkey(const double* X, int64_t n, Grid g, uint32_t* key, uint32_t* val) {
+__device__ __forceinline__ void key_coords_s(uint32_t key, const GridSeg& sg, int64_t c[3]) {
+  int64_t k = (int64_t)key - sg.koff;
+  c[0] = k % sg.nc0;
+  k /= sg.nc0;
+  c[1] = k % sg.nc1;
+  c[2] = k / sg.nc1;
+}
+
+__device__ __forceinline__ void key_coords(uint32_t key, const Grid& g, int64_t c[3]) {
+  key_coords_s(key, seg_of_cell(g, key), c);
+}
+
+__device__ __forceinline__ int64_t seg_key(const GridSeg& sg, int64_t x, int64_t y, int64_t z) {
+  return sg.koff + x + sg.nc0 * (y + sg.nc1 * z);
+}
+
+__global__ void k_cellkey(const double* X, int64_t n, Grid g, const int32_t* __restrict__ spec_in,
+                          uint32_t* key, uint32_t* val) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int64_t c0 = (int64_t)floor((X[i] - g.o0) * g.inv_rc);
-  int64_t c1 = g.dim > 1 ? (int64_t)floor((X[n + i] - g.o1) * g.inv_rc) : 0;
-  int64_t c2 = g.dim > 2 ? (int64_t)floor((X[2 * n + i] - g.o2) * g.inv_rc) : 0;
-  c0 = c0 < 0 ? 0 : (c0 >= g.nc0 ? g.nc0 - 1 : c0);
-  c1 = c1 < 0 ? 0 : (c1 >= g.nc1 ? g.nc1 - 1 : c1);
-  c2 = c2 < 0 ? 0 : (c2 >= g.nc2 ? g.nc2 - 1 : c2);
-  key[i] = (uint32_t)(c0 + g.nc0 * (c1 + g.nc1 * c2));
+  const GridSeg sg = g.nseg == 1 ? g.g0 : g.seg[spec_in[i]];
+  int64_t c0 = (int64_t)floor((X[i] - sg.o0) * g.inv_rc);
+  int64_t c1 = g.dim > 1 ? (int64_t)floor((X[n + i] - sg.o1) * g.inv_rc) : 0;
+  int64_t c2 = g.dim > 2 ? (int64_t)floor((X[2 * n + i] - sg.o2) * g.inv_rc) : 0;
+  c0 = c0 < 0 ? 0 : (c0 >= sg.nc0 ? sg.nc0 - 1 : c0);
+  c1 = c1 < 0 ? 0 : (c1 >= sg.nc1 ? sg.nc1 - 1 : c1);
+  c2 = c2 < 0 ? 0 : (c2 >= sg.nc2 ? sg.nc2 - 1 : c2);
+  key[i] = (uint32_t)seg_key(sg, c0, c1, c2);
   val[i] = (uint32_t)i;
+}
+
+// segment of every cell (binary search over the segments' first keys)
+__global__ void k_cell_seg(const GridSeg* __restrict__ seg, int nseg, int64_t ncells,
+                           uint16_t* __restrict__ cell_seg) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (seg[mid].koff <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  cell_seg[c] = (uint16_t)lo;
+}
+
+// componentwise bounds of each specimen (one block per specimen)
+__global__ __launch_bounds__(256) void k_bounds_seg(const double* X, int64_t n, int dim,
+                                                    const int64_t* __restrict__ in_off,
+                                                    double* out /*[nseg][6]*/) {
+  __shared__ double slo[256], shi[256];
+  const int64_t i0 = in_off[blockIdx.x], i1 = in_off[blockIdx.x + 1];
+  for (int k = 0; k < dim; ++k) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const double x = X[k * n + i];
+      lo = fmin(lo, x);
+      hi = fmax(hi, x);
+    }
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + w]);
+        shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      out[blockIdx.x * 6 + 2 * k] = slo[0];
+      out[blockIdx.x * 6 + 2 * k + 1] = shi[0];
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -286,21 +352,22 @@ __global__ void k_nbr(const double* X, const uint32_t* key, const uint32_t* cs, 
   int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (a >= n) return;
   int64_t c[3];
-  key_coords(key[a], g, c);
+  const GridSeg sg = seg_of_cell(g, key[a]);
+  key_coords_s(key[a], sg, c);
   double xa = X[a], ya = g.dim > 1 ? X[n + a] : 0.0, za = g.dim > 2 ? X[2 * n + a] : 0.0;
   int64_t cnt = 0;
   int64_t base = FILL ? off[a] : 0;
   int zlo = g.dim > 2 ? -1 : 0, zhi = g.dim > 2 ? 1 : 0;
   for (int dz = zlo; dz <= zhi; ++dz) {
     int64_t z = c[2] + dz;
-    if (z < 0 || z >= g.nc2) continue;
+    if (z < 0 || z >= sg.nc2) continue;
     for (int dy = -1; dy <= 1; ++dy) {
       int64_t y = c[1] + dy;
-      if (y < 0 || y >= g.nc1) continue;
+      if (y < 0 || y >= sg.nc1) continue;
       int64_t x0 = c[0] > 0 ? c[0] - 1 : 0;
-      int64_t x1 = c[0] + 1 < g.nc0 ? c[0] + 1 : g.nc0 - 1;
-      int64_t k0 = x0 + g.nc0 * (y + g.nc1 * z);
-      int64_t k1 = x1 + g.nc0 * (y + g.nc1 * z);
+      int64_t x1 = c[0] + 1 < sg.nc0 ? c[0] + 1 : sg.nc0 - 1;
+      int64_t k0 = seg_key(sg, x0, y, z);
+      int64_t k1 = seg_key(sg, x1, y, z);
       for (int64_t b = cs[k0]; b < cs[k1 + 1]; ++b) {
         if (b == a) continue;
         double dx = X[b] - xa;
@@ -389,18 +456,19 @@ struct Block {
 
 __device__ __forceinline__ Block anchor_block(uint32_t akey, const Grid& g, const uint32_t* cs) {
   int64_t A[3];
-  key_coords(akey, g, A);
+  const GridSeg sg = seg_of_cell(g, akey);
+  key_coords_s(akey, sg, A);
   Block blk;
   blk.nr = 0;
   int zmax = g.dim > 2 ? 1 : 0;
   for (int dz = 0; dz <= zmax; ++dz) {
     int64_t z = A[2] + dz;
-    if (z >= g.nc2) continue;
+    if (z >= sg.nc2) continue;
     for (int dy = 0; dy <= 1; ++dy) {
       int64_t y = A[1] + dy;
-      if (y >= g.nc1) continue;
-      int64_t k0 = A[0] + g.nc0 * (y + g.nc1 * z);
-      int64_t k1 = k0 + (A[0] + 1 < g.nc0 ? 2 : 1);
+      if (y >= sg.nc1) continue;
+      int64_t k0 = seg_key(sg, A[0], y, z);
+      int64_t k1 = k0 + (A[0] + 1 < sg.nc0 ? 2 : 1);
       blk.beg[blk.nr] = cs[k0];
       blk.end[blk.nr] = cs[k1];
       ++blk.nr;
@@ -655,38 +723,7 @@ __global__ void k_lev_fill(const int64_t* __restrict__ aoff, const uint32_t* __r
 static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
                       const std::vector<int64_t>& off, int tmax, int64_t wmax, int64_t wmax_hard,
                       std::vector<TileDesc>& out, int64_t& window_max, int64_t& ell_len) {
-  const int64_t nc0 = nb->nc[0], nc1 = nb->nc[1], nc2 = nb->nc[2];
   const int dim = nb->dim;
-  auto key = [&](int64_t x, int64_t y, int64_t z) { return x + nc0 * (y + nc1 * z); };
-  auto ccount = [&](int64_t x, int64_t y, int64_t z) {
-    int64_t k = key(x, y, z);
-    return (int64_t)cs[k + 1] - (int64_t)cs[k];
-  };
-  auto make = [&](int64_t x0, int64_t x1, int64_t y, int64_t z, int64_t p0, int64_t cnt,
-                  TileDesc& td) -> int64_t {
-    std::memset(&td, 0, sizeof(td));
-    td.p0 = (uint32_t)p0;
-    td.count = (uint32_t)cnt;
-    int64_t xa = x0 > 0 ? x0 - 1 : 0, xb = x1 + 1 < nc0 ? x1 + 1 : nc0 - 1;
-    int64_t w = 0;
-    int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
-    for (int dz = zlo; dz <= zhi; ++dz) {
-      int64_t zz = z + dz;
-      if (zz < 0 || zz >= nc2) continue;
-      for (int dy = -1; dy <= 1; ++dy) {
-        int64_t yy = y + dy;
-        if (yy < 0 || yy >= nc1) continue;
-        int64_t s0 = cs[key(xa, yy, zz)], s1 = cs[key(xb, yy, zz) + 1];
-        if (dz == 0 && dy == 0) td.own_base = (uint32_t)(w + (p0 - s0));
-        td.run_start[td.nruns] = (uint32_t)s0;
-        td.run_count[td.nruns] = (uint32_t)(s1 - s0);
-        ++td.nruns;
-        w += s1 - s0;
-      }
-    }
-    td.window = (uint32_t)w;
-    return w;
-  };
   out.clear();
   window_max = 0;
   ell_len = 0;
@@ -702,40 +739,73 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
     window_max = std::max<int64_t>(window_max, td.window);
     out.push_back(td);
   };
-  for (int64_t z = 0; z < nc2; ++z)
-    for (int64_t y = 0; y < nc1; ++y) {
-      int64_t x = 0;
-      while (x < nc0) {
-        int64_t cnt = ccount(x, y, z);
-        if (cnt == 0) {
-          ++x;
-          continue;
+  for (const GridSeg& sg : nb->segs) {  // rows never cross segments (specimens)
+    const int64_t nc0 = sg.nc0, nc1 = sg.nc1, nc2 = sg.nc2;
+    auto key = [&](int64_t x, int64_t y, int64_t z) { return sg.koff + x + nc0 * (y + nc1 * z); };
+    auto ccount = [&](int64_t x, int64_t y, int64_t z) {
+      int64_t k = key(x, y, z);
+      return (int64_t)cs[k + 1] - (int64_t)cs[k];
+    };
+    auto make = [&](int64_t x0, int64_t x1, int64_t y, int64_t z, int64_t p0, int64_t cnt,
+                    TileDesc& td) -> int64_t {
+      std::memset(&td, 0, sizeof(td));
+      td.p0 = (uint32_t)p0;
+      td.count = (uint32_t)cnt;
+      int64_t xa = x0 > 0 ? x0 - 1 : 0, xb = x1 + 1 < nc0 ? x1 + 1 : nc0 - 1;
+      int64_t w = 0;
+      int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+      for (int dz = zlo; dz <= zhi; ++dz) {
+        int64_t zz = z + dz;
+        if (zz < 0 || zz >= nc2) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+          int64_t yy = y + dy;
+          if (yy < 0 || yy >= nc1) continue;
+          int64_t s0 = cs[key(xa, yy, zz)], s1 = cs[key(xb, yy, zz) + 1];
+          if (dz == 0 && dy == 0) td.own_base = (uint32_t)(w + (p0 - s0));
+          td.run_start[td.nruns] = (uint32_t)s0;
+          td.run_count[td.nruns] = (uint32_t)(s1 - s0);
+          ++td.nruns;
+          w += s1 - s0;
         }
-        TileDesc td;
-        if (cnt > tmax) {  // one dense cell: split it into chunks
-          int64_t p0 = cs[key(x, y, z)];
-          for (int64_t c0 = 0; c0 < cnt; c0 += tmax) {
-            if (make(x, x, y, z, p0 + c0, std::min<int64_t>(tmax, cnt - c0), td) > wmax_hard)
-              return SPH_E_CAPACITY;
-            emit(td);
-          }
-          ++x;
-          continue;
-        }
-        int64_t x1 = x;
-        while (x1 + 1 < nc0) {
-          int64_t nxt = ccount(x1 + 1, y, z);
-          if (cnt + nxt > tmax) break;
-          if (make(x, x1 + 1, y, z, cs[key(x, y, z)], cnt + nxt, td) > wmax) break;
-          cnt += nxt;
-          ++x1;
-        }
-        if (make(x, x1, y, z, cs[key(x, y, z)], cnt, td) > (x1 == x ? wmax_hard : wmax))
-          return SPH_E_CAPACITY;
-        emit(td);
-        x = x1 + 1;
       }
-    }
+      td.window = (uint32_t)w;
+      return w;
+    };
+    for (int64_t z = 0; z < nc2; ++z)
+      for (int64_t y = 0; y < nc1; ++y) {
+        int64_t x = 0;
+        while (x < nc0) {
+          int64_t cnt = ccount(x, y, z);
+          if (cnt == 0) {
+            ++x;
+            continue;
+          }
+          TileDesc td;
+          if (cnt > tmax) {  // one dense cell: split it into chunks
+            int64_t p0 = cs[key(x, y, z)];
+            for (int64_t c0 = 0; c0 < cnt; c0 += tmax) {
+              if (make(x, x, y, z, p0 + c0, std::min<int64_t>(tmax, cnt - c0), td) > wmax_hard)
+                return SPH_E_CAPACITY;
+              emit(td);
+            }
+            ++x;
+            continue;
+          }
+          int64_t x1 = x;
+          while (x1 + 1 < nc0) {
+            int64_t nxt = ccount(x1 + 1, y, z);
+            if (cnt + nxt > tmax) break;
+            if (make(x, x1 + 1, y, z, cs[key(x, y, z)], cnt + nxt, td) > wmax) break;
+            cnt += nxt;
+            ++x1;
+          }
+          if (make(x, x1, y, z, cs[key(x, y, z)], cnt, td) > (x1 == x ? wmax_hard : wmax))
+            return SPH_E_CAPACITY;
+          emit(td);
+          x = x1 + 1;
+        }
+      }
+  }
   if (ell_len >= (1LL << 32)) return SPH_E_CAPACITY;
   return SPH_OK;
 }
@@ -750,6 +820,10 @@ static void free_nbr(sph_nbr* h) {
                   h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  for (void* p : {(void*)h->spec, (void*)h->spec_off_dev, (void*)h->bt32, (void*)h->bt64,
+                  (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg})
+    if (p) hipFree(p);
+  free_graph_cache(h);
   if (h->ctrl_host) hipHostFree(h->ctrl_host);
   if (h->prof) {
     prof_resolve(h);
@@ -768,8 +842,8 @@ static int dalloc(T** p, int64_t count) {
 
 static inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-static int build(int dim, int64_t n, const double* X, const double* V, double h, hipStream_t s,
-                 sph_nbr* nb) {
+static int build(int dim, int64_t n, const double* X, const double* V, double h, int32_t nseg,
+                 const int32_t* spec_in, hipStream_t s, sph_nbr* nb) {
   nb->dim = dim;
   nb->n = n;
   nb->h = h;
@@ -782,31 +856,84 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   nb->inv_h = 1.0 / h;
   SPH_HIP(hipGetDevice(&nb->device));
 
-  // bounds
+  // bounds: of the whole cloud, or of each specimen (contiguous input ranges)
+  std::vector<double> hb(6 * (size_t)nseg, 0.0);
   double* dbounds = nullptr;
-  SPH_HIP(hipMalloc(&dbounds, 6 * sizeof(double)));
-  k_bounds<<<1, 1024, 0, s>>>(X, n, dim, dbounds);
-  SPH_LAUNCH_CHECK();
-  double hb[6] = {0, 0, 0, 0, 0, 0};
-  SPH_HIP(hipMemcpyAsync(hb, dbounds, 2 * dim * sizeof(double), hipMemcpyDeviceToHost, s));
-  SPH_HIP(hipStreamSynchronize(s));
-  hipFree(dbounds);
-  for (int k = 0; k < dim; ++k) {
-    if (!std::isfinite(hb[2 * k]) || !std::isfinite(hb[2 * k + 1])) {
-      set_error("non-finite reference positions");
+  SPH_HIP(hipMalloc(&dbounds, 6 * (size_t)nseg * sizeof(double)));
+  if (nseg == 1) {
+    k_bounds<<<1, 1024, 0, s>>>(X, n, dim, dbounds);
+    SPH_LAUNCH_CHECK();
+  } else {
+    std::vector<int32_t> hs(n);
+    SPH_HIP(hipMemcpy(hs.data(), spec_in, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int64_t> in_off(nseg + 1, 0);
+    if (hs[0] != 0) {
+      hipFree(dbounds);
+      set_error("specimen ids must start at 0");
       return SPH_E_ARG;
     }
-    nb->nc[k] = (int64_t)floor((hb[2 * k + 1] - hb[2 * k]) * nb->inv_rc) + 1;
-    // the cloud is centred in the cell grid (equal margins on both sides)
-    nb->origin[k] = hb[2 * k] - 0.5 * ((double)nb->nc[k] * rc - (hb[2 * k + 1] - hb[2 * k]));
+    for (int64_t i = 1; i < n; ++i) {
+      if (hs[i] != hs[i - 1] && hs[i] != hs[i - 1] + 1) {
+        hipFree(dbounds);
+        set_error("specimen ids must be contiguous ascending runs (particle %lld)", (long long)i);
+        return SPH_E_ARG;
+      }
+      if (hs[i] != hs[i - 1]) in_off[hs[i]] = i;
+    }
+    if (hs[n - 1] != nseg - 1) {
+      hipFree(dbounds);
+      set_error("specimen ids must cover 0..%d", nseg - 1);
+      return SPH_E_ARG;
+    }
+    in_off[nseg] = n;
+    int64_t* din = nullptr;
+    SPH_HIP(hipMalloc(&din, (nseg + 1) * sizeof(int64_t)));
+    SPH_HIP(hipMemcpy(din, in_off.data(), (nseg + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    k_bounds_seg<<<(unsigned)nseg, 256, 0, s>>>(X, n, dim, din, dbounds);
+    SPH_LAUNCH_CHECK();
+    SPH_HIP(hipStreamSynchronize(s));
+    hipFree(din);
   }
-  nb->n_cells = nb->nc[0] * nb->nc[1] * nb->nc[2];
+  SPH_HIP(hipMemcpyAsync(hb.data(), dbounds, (nseg == 1 ? 2 * dim : 6 * nseg) * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  SPH_HIP(hipStreamSynchronize(s));
+  hipFree(dbounds);
+  nb->segs.assign(nseg, GridSeg{1, 1, 1, 0.0, 0.0, 0.0, 0});
+  int64_t koff = 0;
+  for (int sgi = 0; sgi < nseg; ++sgi) {
+    const double* b = hb.data() + (nseg == 1 ? 0 : 6 * sgi);
+    int64_t nc[3] = {1, 1, 1};
+    double org[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) {
+      if (!std::isfinite(b[2 * k]) || !std::isfinite(b[2 * k + 1])) {
+        set_error("non-finite reference positions");
+        return SPH_E_ARG;
+      }
+      nc[k] = (int64_t)floor((b[2 * k + 1] - b[2 * k]) * nb->inv_rc) + 1;
+      // the cloud is centred in the cell grid (equal margins on both sides)
+      org[k] = b[2 * k] - 0.5 * ((double)nc[k] * rc - (b[2 * k + 1] - b[2 * k]));
+    }
+    nb->segs[sgi] = GridSeg{nc[0], nc[1], nc[2], org[0], org[1], org[2], koff};
+    koff += nc[0] * nc[1] * nc[2];
+    if (koff > 0xFFFFFFF0LL) break;
+  }
+  for (int k = 0; k < 3; ++k) {
+    nb->nc[k] = k == 0 ? nb->segs[0].nc0 : (k == 1 ? nb->segs[0].nc1 : nb->segs[0].nc2);
+    nb->origin[k] = k == 0 ? nb->segs[0].o0 : (k == 1 ? nb->segs[0].o1 : nb->segs[0].o2);
+  }
+  nb->n_cells = koff;
   if (nb->n_cells > 0xFFFFFFF0LL || n > 0xFFFFFFF0LL) {
     set_error("too many cells (%lld) or particles", (long long)nb->n_cells);
     return SPH_E_CAPACITY;
   }
-  Grid g{dim, nb->nc[0], nb->nc[1], nb->nc[2], nb->origin[0], nb->origin[1], nb->origin[2],
-         nb->inv_rc};
+  SPH_HIP(hipMalloc(&nb->dsegs, nseg * sizeof(GridSeg)));
+  SPH_HIP(hipMemcpy(nb->dsegs, nb->segs.data(), nseg * sizeof(GridSeg), hipMemcpyHostToDevice));
+  if (nseg > 1) {
+    SPH_HIP(hipMalloc(&nb->cell_seg, nb->n_cells * sizeof(uint16_t)));
+    k_cell_seg<<<nblocks(nb->n_cells, 256), 256, 0, s>>>(nb->dsegs, nseg, nb->n_cells, nb->cell_seg);
+    SPH_LAUNCH_CHECK();
+  }
+  Grid g{dim, nseg, nb->segs[0], nb->dsegs, nb->cell_seg, nb->inv_rc};
 
   // keys and stable sort
   uint32_t *kalt = nullptr, *valt = nullptr;
@@ -814,7 +941,7 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   if ((rc_ = dalloc(&nb->key, n)) || (rc_ = dalloc(&nb->perm, n)) || (rc_ = dalloc(&kalt, n)) ||
       (rc_ = dalloc(&valt, n)))
     return rc_;
-  k_cellkey<<<nblocks(n, 256), 256, 0, s>>>(X, n, g, nb->key, nb->perm);
+  k_cellkey<<<nblocks(n, 256), 256, 0, s>>>(X, n, g, spec_in, nb->key, nb->perm);
   SPH_LAUNCH_CHECK();
   rc_ = radix_sort(nb->key, nb->perm, kalt, valt, n, (uint32_t)(nb->n_cells - 1), s);
   hipFree(kalt);
@@ -1089,8 +1216,8 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
 
 using namespace sph;
 
-extern "C" int sph_build_neighbors(int dim, int64_t n, const double* X, const double* V, double h,
-                                   void* stream, sph_nbr** out) {
+static int build_entry(int dim, int64_t n, const double* X, const double* V, double h,
+                       int32_t n_spec, const int32_t* spec_id, void* stream, sph_nbr** out) {
   clear_error();
   if (!out) {
     set_error("out is NULL");
@@ -1105,15 +1232,41 @@ extern "C" int sph_build_neighbors(int dim, int64_t n, const double* X, const do
     set_error("bad arguments (n=%lld, h=%g)", (long long)n, h);
     return SPH_E_ARG;
   }
+  if (n_spec < 1 || (n_spec > 1 && !spec_id) || n_spec > n) {
+    set_error("bad specimen count %d", n_spec);
+    return SPH_E_ARG;
+  }
+  if (n_spec > 65535) {
+    set_error("at most 65535 specimens");
+    return SPH_E_CAPACITY;
+  }
   sph_nbr* nb = new sph_nbr();
-  int rc = build(dim, n, X, V, h, (hipStream_t)stream, nb);
+  hipStream_t s = (hipStream_t)stream;
+  int rc = build(dim, n, X, V, h, n_spec, n_spec > 1 ? spec_id : nullptr, s, nb);
+  if (rc == SPH_OK && n_spec > 1) rc = batch_finish(nb, n_spec, spec_id, s);
   if (rc != SPH_OK) {
-    hipStreamSynchronize((hipStream_t)stream);
+    hipStreamSynchronize(s);
     free_nbr(nb);
     return rc;
   }
   *out = nb;
   return SPH_OK;
+}
+
+extern "C" int sph_build_neighbors(int dim, int64_t n, const double* X, const double* V, double h,
+                                   void* stream, sph_nbr** out) {
+  return build_entry(dim, n, X, V, h, 1, nullptr, stream, out);
+}
+
+extern "C" int sph_build_neighbors_batched(int dim, int64_t n, const double* X, const double* V,
+                                           double h, int32_t n_spec, const int32_t* spec_id,
+                                           void* stream, sph_nbr** out) {
+  if (n_spec > 1 && !spec_id) {
+    clear_error();
+    set_error("spec_id is NULL");
+    return SPH_E_ARG;
+  }
+  return build_entry(dim, n, X, V, h, n_spec, spec_id, stream, out);
 }
 
 extern "C" int sph_nbr_destroy(sph_nbr* nb) {

@@ -62,6 +62,28 @@ struct Prof {
   double ms[SPH_KERNEL_COUNT] = {0};
 };
 
+// one segment of the cell grid (one specimen): origin, cell counts, first key
+struct GridSeg {
+  int64_t nc0, nc1, nc2;
+  double o0, o1, o2;
+  int64_t koff;
+};
+
+// Per-specimen values of a batched run, one row per field, n_spec columns;
+// kernels read them through each particle's specimen id.
+enum BatchField { BT_MU = 0, BT_K, BT_LAM, BT_DT, BT_DTD, BT_D, BT_ETADT, BT_COUNT };
+struct Bat {
+  const uint16_t* spec = nullptr;  // [n] specimen of each sorted particle; nullptr: not batched
+  const float* t32 = nullptr;      // [BT_COUNT][ns]
+  const double* t64 = nullptr;     // [BT_COUNT][ns]
+  int64_t ns = 0;
+  template <typename T>
+  __device__ __forceinline__ T get(int f, int s) const {
+    if constexpr (sizeof(T) == 8) return t64[f * ns + s];
+    else return t32[f * ns + s];
+  }
+};
+
 constexpr int kKeThreads = 256;
 constexpr int kKeItems = 4;             // particles per thread in the drift kernel
 constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (16.7M particles)
@@ -148,11 +170,36 @@ struct sph_nbr {
   // inner-step recording of a taped run (set by the driver while it runs)
   mutable double* rec_u = nullptr;   // [k][dim][n]: u before inner step k
   mutable void* rec_pl = nullptr;    // [k][7][n]: J2 state before inner step k
+  // cell-grid segments (one per specimen) and the segment of each cell
+  std::vector<sph::GridSeg> segs;
+  sph::GridSeg* dsegs = nullptr;
+  uint16_t* cell_seg = nullptr;
+  // specimen batch (sph_build_neighbors_batched); bat_on is set by the driver during a batched run
+  int64_t n_spec = 0;
+  uint16_t* spec = nullptr;          // [n] specimen of each sorted particle
+  std::vector<int64_t> spec_off;     // host [n_spec+1] sorted-position ranges
+  int64_t* spec_off_dev = nullptr;   // device copy
+  float* bt32 = nullptr;             // [BT_COUNT][n_spec]
+  double* bt64 = nullptr;
+  double* gdiff = nullptr;           // [2][n] per-particle diffusion-gradient partials (batched)
+  mutable bool bat_on = false;
+  void* graph_cache = nullptr;       // instantiated whole-run graph (sph_advance_multirate_graph)
   int device = 0;
   sph::Prof* prof = nullptr;         // host-side timing state
 };
 
 namespace sph {
+
+inline Bat bat_view(const sph_nbr* nb) {
+  Bat b;
+  if (nb->bat_on) {
+    b.spec = nb->spec;
+    b.t32 = nb->bt32;
+    b.t64 = nb->bt64;
+    b.ns = nb->n_spec;
+  }
+  return b;
+}
 
 // ---- kernel function: Wendland C2, support 2h --------------------------------
 // (dW/dr)/r = c5 (1 - q/2)^3 with q = r/h, c5 = -5 alpha_d / h^2.
@@ -214,5 +261,12 @@ int adj_diffusion(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                   const void* c_before, const sph_adjoint* adj, double Dc, double dt,
                   hipStream_t s);
 int grad_reduce(const sph_nbr* nb, double* grad, hipStream_t s);
+// specimen batches (sph_batch.hip)
+int batch_check(const sph_nbr* nb, const sph_multirate_cfg* cfg);
+int batch_finish(sph_nbr* nb, int32_t n_spec, const int32_t* spec_id, hipStream_t s);
+int batch_upload(const sph_nbr* nb, const sph_material* m, const sph_multirate_cfg* cfg,
+                 hipStream_t s);
+int grad_reduce_batched(const sph_nbr* nb, int prec, double* out, hipStream_t s);
+void free_graph_cache(sph_nbr* nb);
 
 }  // namespace sph

@@ -165,6 +165,21 @@ struct RecGuard {  // inner-state recording is switched off on every exit
   }
 };
 
+struct BatGuard {  // per-specimen lookups are switched off on every exit
+  const sph_nbr* nb;
+  ~BatGuard() { nb->bat_on = false; }
+};
+
+int batch_begin(const sph_nbr* nb, const sph_material* m, const sph_multirate_cfg* cfg,
+                hipStream_t s) {
+  if (!cfg->batch) return SPH_OK;
+  int rc = batch_check(nb, cfg);
+  if (rc) return rc;
+  if ((rc = batch_upload(nb, m, cfg, s))) return rc;
+  nb->bat_on = true;
+  return SPH_OK;
+}
+
 }  // namespace
 
 extern "C" int sph_solid_relax_step(const sph_nbr* nb, const sph_material* mat,
@@ -285,6 +300,8 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
   hipEvent_t ev = nullptr;
   GraphChunk gc;
   const bool graph = cfg->use_graph != 0;
+  BatGuard bat_guard{nb};
+  if ((rc = batch_begin(nb, m, cfg, user))) return rc;
   if (graph) {
     // capture needs a non-null stream: run on a private one ordered after `user`
     SPH_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
@@ -398,32 +415,16 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
   return warn ? SPH_W_NOT_CONVERGED : SPH_OK;
 }
 
+namespace {
+
 // Reverse pass: slow steps last to first; each is re-run from its checkpoint
 // with its inner states recorded (unless the tape already holds them), then
-// its inner steps are reversed, then its slow update.
-extern "C" int sph_advance_multirate_backward(const sph_nbr* nb, const sph_material* m,
-                                              const sph_state* st, const sph_multirate_cfg* cfg,
-                                              sph_tape* tape, const sph_adjoint* adj,
-                                              void* stream) {
-  clear_error();
-  int rc = check_state(nb, st, true);
-  if (rc) return rc;
-  if (!m || !cfg || !tape || !adj) {
-    set_error("material, cfg, tape or adjoint is NULL");
-    return SPH_E_ARG;
-  }
-  if (adj->prec != st->prec || !adj->u || !adj->v || !adj->work || !adj->grad ||
-      (m->model == SPH_MODEL_J2 && !adj->plastic) ||
-      (cfg->slow_kind == SPH_SLOW_DIFFUSION && !adj->c)) {
-    set_error("adjoint arrays missing or of the wrong precision");
-    return SPH_E_ARG;
-  }
-  if ((rc = check_tape(nb, m, st, cfg, tape))) return rc;
-  if (tape->n_rec != cfg->n_slow) {
-    set_error("the tape holds %d slow steps, cfg asks for %d", tape->n_rec, cfg->n_slow);
-    return SPH_E_ARG;
-  }
-  hipStream_t s = (hipStream_t)stream;
+// its inner steps are reversed, then its slow update.  Enqueues only (no
+// host synchronisation), so that it can be captured in a graph.
+int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                     const sph_multirate_cfg* cfg, sph_tape* tape, const sph_adjoint* adj,
+                     hipStream_t s) {
+  int rc = SPH_OK;
   const int L = cfg->n_slow;
   const double dt = tape->dt_s, dt_slow = tape->dt_slow;
   const size_t n = (size_t)nb->n, d = (size_t)nb->dim;
@@ -478,14 +479,241 @@ extern "C" int sph_advance_multirate_backward(const sph_nbr* nb, const sph_mater
       if ((rc = adj_diffusion(nb, m, st, c_before, adj, cfg->D, dt_slow, s))) return rc;
     }
   }
-  if ((rc = grad_reduce(nb, adj->grad, s))) return rc;
-  if ((rc = tape_copy(nb, m, st, tape, L, false, s))) return rc;
+  if (cfg->batch)
+    rc = grad_reduce_batched(nb, st->prec, cfg->batch->grad, s);
+  else
+    rc = grad_reduce(nb, adj->grad, s);
+  if (rc) return rc;
+  return tape_copy(nb, m, st, tape, L, false, s);
+}
+
+int check_backward_args(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                        const sph_multirate_cfg* cfg, const sph_tape* tape,
+                        const sph_adjoint* adj) {
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!m || !cfg || !tape || !adj) {
+    set_error("material, cfg, tape or adjoint is NULL");
+    return SPH_E_ARG;
+  }
+  if (adj->prec != st->prec || !adj->u || !adj->v || !adj->work || !adj->grad ||
+      (m->model == SPH_MODEL_J2 && !adj->plastic) ||
+      (cfg->slow_kind == SPH_SLOW_DIFFUSION && !adj->c)) {
+    set_error("adjoint arrays missing or of the wrong precision");
+    return SPH_E_ARG;
+  }
+  return check_tape(nb, m, st, cfg, tape);
+}
+
+int finish(const sph_nbr* nb, hipStream_t s, const char* what) {
   SPH_HIP(hipMemcpyAsync(nb->ctrl_host, nb->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   SPH_HIP(hipStreamSynchronize(s));
   if (nb->prof) prof_resolve(nb);
   if (nb->ctrl_host->status) {
-    set_error("device status bits 0x%x in the reverse pass", nb->ctrl_host->status);
+    set_error("device status bits 0x%x in %s", nb->ctrl_host->status, what);
     return SPH_E_NUMERIC;
   }
   return SPH_OK;
+}
+
+// Forward run with fixed inner counts, enqueued without host polling (the
+// stop flag still ends each inner loop at its count on the device).
+int forward_fixed_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                          const sph_multirate_cfg* cfg, sph_tape* tape, double dt_s,
+                          double dt_slow, std::vector<int64_t>& counts, hipStream_t s) {
+  int rc = SPH_OK;
+  RecGuard rec_guard{nb};
+  bool recorded = false;
+  for (int32_t l = 0; l < cfg->n_slow; ++l) {
+    if (tape && (rc = tape_copy(nb, m, st, tape, l, true, s))) return rc;
+    rc = cfg->slow_kind == SPH_SLOW_LOAD ? load_step(nb, st, dt_slow, s)
+                                         : diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
+    if (rc) return rc;
+    const int64_t nk = counts[l];
+    if (tape) tape->k_rec[l] = nk;
+    if (nk <= 0) continue;
+    if ((rc = reset_ctrl(nb, nk, -1.0, s))) return rc;
+    const bool rec = tape && l == cfg->n_slow - 1 && tape->hist_u && nk <= tape->k_hist_cap &&
+                     (m->model != SPH_MODEL_J2 || tape->hist_plastic);
+    if (rec) {
+      nb->rec_u = tape->hist_u;
+      nb->rec_pl = tape->hist_plastic;
+      recorded = true;
+    }
+    if ((rc = inner_steps(nb, m, st, dt_s, cfg->eta, (int)nk, s))) return rc;
+    nb->rec_u = nullptr;
+    nb->rec_pl = nullptr;
+  }
+  if (tape) {
+    if ((rc = tape_copy(nb, m, st, tape, cfg->n_slow, true, s))) return rc;
+    tape->n_rec = cfg->n_slow;
+    tape->hist_slow = recorded ? cfg->n_slow - 1 : -1;
+    tape->dt_s = dt_s;
+    tape->dt_slow = dt_slow;
+  }
+  return SPH_OK;
+}
+
+struct WholeGraph {
+  std::vector<unsigned char> key;
+  int32_t tape_n_rec = 0, tape_hist_slow = -1;  // the tape's host fields after a run
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~WholeGraph() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  }
+};
+
+template <typename S>
+void key_add(std::vector<unsigned char>& k, const S* p) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+  if (p) k.insert(k.end(), b, b + sizeof(S));
+  else k.push_back(0);
+}
+
+}  // namespace
+
+void sph::free_graph_cache(sph_nbr* nb) {
+  delete reinterpret_cast<WholeGraph*>(nb->graph_cache);
+  nb->graph_cache = nullptr;
+}
+
+extern "C" int sph_advance_multirate_backward(const sph_nbr* nb, const sph_material* m,
+                                              const sph_state* st, const sph_multirate_cfg* cfg,
+                                              sph_tape* tape, const sph_adjoint* adj,
+                                              void* stream) {
+  clear_error();
+  int rc = check_backward_args(nb, m, st, cfg, tape, adj);
+  if (rc) return rc;
+  if (tape->n_rec != cfg->n_slow) {
+    set_error("the tape holds %d slow steps, cfg asks for %d", tape->n_rec, cfg->n_slow);
+    return SPH_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  BatGuard bat_guard{nb};
+  if ((rc = batch_begin(nb, m, cfg, s))) return rc;
+  if ((rc = backward_enqueue(nb, m, st, cfg, tape, adj, s))) return rc;
+  return finish(nb, s, "the reverse pass");
+}
+
+extern "C" int sph_advance_multirate_graph(const sph_nbr* nb, const sph_material* m,
+                                           const sph_state* st, const sph_multirate_cfg* cfg,
+                                           sph_report* rep, sph_tape* tape,
+                                           const sph_adjoint* adj, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!m || !cfg || cfg->n_slow < 0 ||
+      (cfg->slow_kind != SPH_SLOW_LOAD && cfg->slow_kind != SPH_SLOW_DIFFUSION)) {
+    set_error("bad material or cfg");
+    return SPH_E_ARG;
+  }
+  if (cfg->k_sched == nullptr && cfg->fixed_inner <= 0) {
+    set_error("the whole-run graph needs fixed inner counts (fixed_inner or k_sched)");
+    return SPH_E_ARG;
+  }
+  if (adj && (rc = check_backward_args(nb, m, st, cfg, tape, adj))) return rc;
+  if (tape && (rc = check_tape(nb, m, st, cfg, tape))) return rc;
+  std::vector<int64_t> counts(std::max(cfg->n_slow, 1));
+  for (int l = 0; l < cfg->n_slow; ++l)
+    counts[l] = cfg->k_sched ? cfg->k_sched[l] : cfg->fixed_inner;
+  if (adj && cfg->n_slow > 0 && counts[cfg->n_slow - 1] > tape->k_hist_cap) {
+    set_error("the tape must hold the inner states of one slow step (%lld > %lld)",
+              (long long)counts[cfg->n_slow - 1], (long long)tape->k_hist_cap);
+    return SPH_E_CAPACITY;
+  }
+  const double K = m->E / (3.0 * (1.0 - 2.0 * m->nu));
+  const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * nb->h / std::sqrt(K / m->rho0);
+  double dt_slow = cfg->dt_slow;
+  if (cfg->slow_kind == SPH_SLOW_DIFFUSION && !(dt_slow > 0.0)) {
+    if (!(cfg->D > 0.0) && !cfg->batch) {
+      set_error("diffusion needs D > 0");
+      return SPH_E_ARG;
+    }
+    dt_slow = cfg->D > 0.0 ? 0.5 * nb->h * nb->h / cfg->D : 1.0;  // batched: per specimen
+  }
+  hipStream_t user = (hipStream_t)stream;
+  BatGuard bat_guard{nb};
+  if ((rc = batch_begin(nb, m, cfg, user))) return rc;
+  // the key: every argument the recorded launches depend on
+  std::vector<unsigned char> key;
+  key_add(key, m);
+  sph_multirate_cfg c2 = *cfg;
+  c2.k_sched = nullptr;
+  c2.batch = nullptr;
+  key_add(key, &c2);
+  for (int l = 0; l < cfg->n_slow; ++l) key_add(key, &counts[l]);
+  if (cfg->batch) {
+    key_add(key, &cfg->batch->n_spec);
+    key_add(key, &cfg->batch->grad);
+  }
+  key_add(key, st);
+  if (tape) {
+    sph_tape t2 = *tape;
+    t2.n_rec = 0;
+    t2.hist_slow = 0;
+    t2.dt_s = t2.dt_slow = 0.0;
+    key_add(key, &t2);
+  } else {
+    key.push_back(0);
+  }
+  key_add(key, adj);
+  WholeGraph* wg = reinterpret_cast<WholeGraph*>(nb->graph_cache);
+  if (!wg || wg->key != key) {
+    free_graph_cache(const_cast<sph_nbr*>(nb));
+    wg = new WholeGraph();
+    const_cast<sph_nbr*>(nb)->graph_cache = wg;
+    hipStream_t cap = nullptr;
+    SPH_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (nb->prof) nb->prof->suspend = true;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      rc = forward_fixed_enqueue(nb, m, st, cfg, tape, dt_s, dt_slow, counts, cap);
+      if (rc == SPH_OK && adj) rc = backward_enqueue(nb, m, st, cfg, tape, adj, cap);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(cap, &g);
+      wg->graph = g;
+    }
+    if (nb->prof) nb->prof->suspend = false;
+    hipStreamDestroy(cap);
+    if (rc == SPH_OK && e != hipSuccess) {
+      set_error("graph capture failed: %s", hipGetErrorString(e));
+      rc = SPH_E_DEVICE;
+    }
+    if (rc == SPH_OK && hipGraphInstantiate(&wg->exec, wg->graph, nullptr, nullptr, 0) != hipSuccess) {
+      set_error("graph instantiation failed");
+      rc = SPH_E_DEVICE;
+    }
+    if (rc) {
+      free_graph_cache(const_cast<sph_nbr*>(nb));
+      return rc;
+    }
+    wg->key = key;
+    if (tape) {
+      wg->tape_n_rec = tape->n_rec;
+      wg->tape_hist_slow = tape->hist_slow;
+    }
+  } else if (tape) {
+    // the host-side bookkeeping of the recorded run, the same on every launch
+    for (int l = 0; l < cfg->n_slow; ++l) tape->k_rec[l] = counts[l];
+    tape->n_rec = wg->tape_n_rec;
+    tape->hist_slow = wg->tape_hist_slow;
+    tape->dt_s = dt_s;
+    tape->dt_slow = dt_slow;
+  }
+  SPH_HIP(hipGraphLaunch(wg->exec, user));
+  if (rep) {
+    rep->dt_s = dt_s;
+    rep->dt_slow = dt_slow;
+    rep->k_max = 0;
+    rep->total_inner = 0;
+    for (int l = 0; l < cfg->n_slow; ++l) {
+      if (rep->k) rep->k[l] = counts[l];
+      if (rep->ke) rep->ke[l] = 0.0;
+      if (rep->converged) rep->converged[l] = 0;
+      rep->total_inner += counts[l];
+    }
+  }
+  return finish(nb, user, "the whole-run graph");
 }

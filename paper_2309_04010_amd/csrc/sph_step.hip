@@ -19,7 +19,8 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
                                                              T* __restrict__ PB,
                                                              T* __restrict__ plastic,
                                                              const T* __restrict__ p, Ctrl* ctrl,
-                                                             bool gated, T* __restrict__ rec_pl) {
+                                                             bool gated, T* __restrict__ rec_pl,
+                                                             Bat bt) {
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
@@ -117,7 +118,14 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
     }
   }
   T P[9];
-  int st = constitutive(m, Hm, pl, p ? p[a] : T(0), P);
+  MatP<T> mm = m;
+  if (bt.spec) {
+    const int sp = bt.spec[a];
+    mm.mu = bt.get<T>(BT_MU, sp);
+    mm.K = bt.get<T>(BT_K, sp);
+    mm.lam = bt.get<T>(BT_LAM, sp);
+  }
+  int st = constitutive(mm, Hm, pl, p ? p[a] : T(0), P);
   if (st) atomicOr(&ctrl->status, st);
   if (m.model == SPH_MODEL_J2) {
 #pragma unroll
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
                                                                  T* __restrict__ acc_out,
                                                                  const uint8_t* __restrict__ flags,
                                                                  T inv_rho0, T dt, Ctrl* ctrl,
-                                                                 bool gated) {
+                                                                 bool gated, Bat bt) {
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
@@ -232,11 +240,12 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
   for (int i = 0; i < D; ++i) f[i] = lane_sum<kLppMomentum>(f[i]);
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
+  const T dta = bt.spec ? bt.get<T>(BT_DT, bt.spec[a]) : dt;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     T ai = f[i] * inv_rho0;
     if (acc_out) acc_out[i * n + a] = ai;
-    if (!fixed) v[i * n + a] += dt * ai;
+    if (!fixed) v[i * n + a] += dta * ai;
   }
 }
 
@@ -268,7 +277,7 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
                                              const uint32_t* __restrict__ ablk, int64_t a_begin,
                                              int64_t a_end, int bmax, int pmax, int lmax, T* v,
                                              const uint8_t* __restrict__ flags, T inv_rho0,
-                                             T eta_dt, Ctrl* ctrl, bool gated) {
+                                             T eta_dt, Ctrl* ctrl, bool gated, Bat bt) {
   if (gated && ctrl->done) return;
   constexpr int APW = 64 / G;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -318,6 +327,8 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     lo = aoff[ai];
     np = (int)(aoff[ai + 1] - lo);
     nlev = (int)anlev[ai];
+    // batched: every pair of an anchor belongs to the specimen of its first pair
+    if (bt.spec && np > 0) eta_dt = bt.get<T>(BT_ETADT, bt.spec[gidx(dpair[lo] & 0xFFFFu)]);
     const uint16_t* lof = dloff + dloff_base[ai];
     for (int L = lg; L <= nlev; L += G) so[L] = lof[L];
   }
@@ -408,7 +419,7 @@ template <typename T, int D>
 __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     int64_t n, double* __restrict__ u, const T* __restrict__ v, const uint8_t* __restrict__ flags,
     const double* __restrict__ V, double rho0, double dt, Ctrl* ctrl, double* partial,
-    bool gated, double* __restrict__ rec_u) {
+    bool gated, double* __restrict__ rec_u, Bat bt) {
   if (gated && ctrl->done) return;
   __shared__ double red[kKeThreads];
   double acc = 0.0;
@@ -419,12 +430,13 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     const int64_t a = a0 + it * kKeThreads;
     if (a < n) {
       const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
+      const double dta = bt.spec ? bt.get<double>(BT_DT, bt.spec[a]) : dt;
       double v2 = 0.0;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         double vk = (double)v[k * n + a];
         if (rec) rec[k * n + a] = u[k * n + a];
-        if (!fixed) u[k * n + a] += dt * vk;
+        if (!fixed) u[k * n + a] += dta * vk;
         v2 += vk * vk;
       }
       acc += 0.5 * rho0 * V[a] * v2;
@@ -485,17 +497,18 @@ __global__ void k_reset_ctrl(Ctrl* c, int64_t k_limit, double ke_tol) {
 }
 
 template <typename T, int D>
-__global__ void k_load(int64_t n, double* u, const T* vgrip, const uint8_t* flags, double dt) {
+__global__ void k_load(int64_t n, double* u, const T* vgrip, const uint8_t* flags, double dt, Bat bt) {
   int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (a >= n || !(flags[a] & SPH_FLAG_GRIP)) return;
+  const double dta = bt.spec ? bt.get<double>(BT_DTD, bt.spec[a]) : dt;
 #pragma unroll
-  for (int k = 0; k < D; ++k) u[k * n + a] += dt * (double)vgrip[k * n + a];
+  for (int k = 0; k < D; ++k) u[k * n + a] += dta * (double)vgrip[k * n + a];
 }
 
 // diffusion: flux q = -D B0 sum_b V_b (c_b - c_a) grad W
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_diff_grad(Geo<T> g, const T* __restrict__ c,
-                                                   T* __restrict__ q, T Dc) {
+                                                   T* __restrict__ q, T Dc, Bat bt) {
   const int64_t n = g.n;
   int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (a >= n) return;
@@ -524,7 +537,7 @@ __global__ __launch_bounds__(256) void k_diff_grad(Geo<T> g, const T* __restrict
     T acc = T(0);
 #pragma unroll
     for (int k = 0; k < D; ++k) acc += g.B0[(i * D + k) * n + a] * s[k];
-    q[i * n + a] = -Dc * acc;
+    q[i * n + a] = -(bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc) * acc;
   }
 }
 
@@ -533,7 +546,7 @@ template <typename T, int D>
 __global__ __launch_bounds__(256) void k_diff_div(Geo<T> g, T* __restrict__ c,
                                                   const T* __restrict__ q, T* __restrict__ p,
                                                   const uint8_t* __restrict__ flags, T dt,
-                                                  T c_bc, T Cs, T c0) {
+                                                  T c_bc, T Cs, T c0, Bat bt) {
   const int64_t n = g.n;
   int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (a >= n) return;
@@ -569,7 +582,7 @@ __global__ __launch_bounds__(256) void k_diff_div(Geo<T> g, T* __restrict__ c,
     }
     div += w * s;
   }
-  T cn = c[a] - dt * div;
+  T cn = c[a] - (bt.spec ? bt.get<T>(BT_DTD, bt.spec[a]) : dt) * div;
   if (flags && (flags[a] & SPH_FLAG_CDIR)) cn = c_bc;
   c[a] = cn;
   if (p) p[a] = Cs * (cn - c0);
@@ -615,7 +628,8 @@ static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_sta
     hipEvent_t pe_ = prof_begin(nb, s);
     k_stress<T, D><<<grid, block_s, lds_s, s>>>(g, mp, st->u, (T*)st->PB, (T*)st->plastic,
                                               (const T*)st->p, nb->ctrl, gated,
-                                              m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr);
+                                              m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr,
+                                              bat_view(nb));
     prof_end(nb, SPH_KERNEL_STRESS, pe_, s);
   }
   SPH_LAUNCH_CHECK();
@@ -623,7 +637,7 @@ static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_sta
     hipEvent_t pe_ = prof_begin(nb, s);
     k_momentum<T, D><<<grid, block_m, lds_m, s>>>(g, (const T*)st->PB, (T*)st->v, (T*)st->acc,
                                                 st->flags, (T)(1.0 / m->rho0), (T)dt, nb->ctrl,
-                                                gated);
+                                                gated, bat_view(nb));
     prof_end(nb, SPH_KERNEL_MOMENTUM, pe_, s);
   }
   SPH_LAUNCH_CHECK();
@@ -668,7 +682,7 @@ static int damp_launch(const sph_nbr* nb, const sph_material* m, const sph_state
   k_damp<T, D, G, REV><<<grid, 64, lds, s>>>(g, nb->dpair, dgeo, nb->dloff, nb->dloff_base, nb->anlev,
                                         nb->aoff, nb->ablk, a0, a1, bmax, pmax, lmax, (T*)st->v,
                                         st->flags, (T)(1.0 / m->rho0), (T)(eta * dt), nb->ctrl,
-                                        gated);
+                                        gated, bat_view(nb));
   prof_end(nb, REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING, pe_, s);
   SPH_LAUNCH_CHECK();
   return SPH_OK;
@@ -741,7 +755,8 @@ static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st
     hipEvent_t pe_ = prof_begin(nb, s);
     k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
                                                           nb->V, m->rho0, dt, nb->ctrl,
-                                                          nb->ke_partial, gated, nb->rec_u);
+                                                          nb->ke_partial, gated, nb->rec_u,
+                                                          bat_view(nb));
     SPH_LAUNCH_CHECK();
     k_ke_reduce<<<1, 1024, 0, s>>>(nb->ke_partial, (int)nb_, nb->ctrl, ke_out, gated);
     prof_end(nb, SPH_KERNEL_DRIFT_KE, pe_, s);
@@ -768,11 +783,11 @@ int reset_ctrl(const sph_nbr* nb, int64_t k_limit, double ke_tol, hipStream_t s)
 int load_step(const sph_nbr* nb, const sph_state* st, double dt_l, hipStream_t s) {
   if (!st->vgrip || !st->flags) return SPH_OK;
   if (st->prec == SPH_F64) {
-    if (nb->dim == 2) k_load<double, 2><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const double*)st->vgrip, st->flags, dt_l);
-    else k_load<double, 3><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const double*)st->vgrip, st->flags, dt_l);
+    if (nb->dim == 2) k_load<double, 2><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const double*)st->vgrip, st->flags, dt_l, bat_view(nb));
+    else k_load<double, 3><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const double*)st->vgrip, st->flags, dt_l, bat_view(nb));
   } else {
-    if (nb->dim == 2) k_load<float, 2><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const float*)st->vgrip, st->flags, dt_l);
-    else k_load<float, 3><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const float*)st->vgrip, st->flags, dt_l);
+    if (nb->dim == 2) k_load<float, 2><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const float*)st->vgrip, st->flags, dt_l, bat_view(nb));
+    else k_load<float, 3><<<nblk(nb->n, 256), 256, 0, s>>>(nb->n, st->u, (const float*)st->vgrip, st->flags, dt_l, bat_view(nb));
   }
   SPH_LAUNCH_CHECK();
   return SPH_OK;
@@ -784,7 +799,8 @@ static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state
   Geo<T> g = geo<T>(nb);
   {
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_diff_grad<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc);
+    k_diff_grad<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc,
+                                                       bat_view(nb));
     prof_end(nb, SPH_KERNEL_DIFF_GRAD, pe_, s);
   }
   SPH_LAUNCH_CHECK();
@@ -792,7 +808,7 @@ static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state
     hipEvent_t pe_ = prof_begin(nb, s);
     k_diff_div<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
                                                     st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
-                                                    (T)m->c0);
+                                                    (T)m->c0, bat_view(nb));
     prof_end(nb, SPH_KERNEL_DIFF_DIV, pe_, s);
   }
   SPH_LAUNCH_CHECK();

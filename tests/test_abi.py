@@ -22,7 +22,7 @@ def _declared():
 
 def _struct_fields(name):
     text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
-    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text)
+    m = re.search(r"typedef struct (?:\w+ )?\{([^{}]*)\}\s*" + name + r"\s*;", text)
     assert m, name
     fields = []
     for decl in m.group(1).split(";"):
@@ -48,7 +48,8 @@ def test_header_declares_the_boundary():
     d = _declared()
     for name in ["sph_build_neighbors", "sph_solid_relax_step", "sph_damping_sweep",
                  "sph_diffusion_step", "sph_advance_multirate", "sph_advance_multirate_backward",
-                 "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_diffusion_step_vjp"]:
+                 "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_diffusion_step_vjp",
+                 "sph_build_neighbors_batched", "sph_advance_multirate_graph"]:
         assert name in d
 
 
@@ -68,7 +69,8 @@ def test_binding_wraps_exactly_the_declared_set():
 @pytest.mark.parametrize("cname,pycls", [("sph_material", B.Material), ("sph_state", B.State),
                                          ("sph_multirate_cfg", B.MultirateCfg),
                                          ("sph_report", B.Report), ("sph_tape", B.Tape),
-                                         ("sph_adjoint", B.Adjoint), ("sph_nbr_info", B.NbrInfo)])
+                                         ("sph_adjoint", B.Adjoint), ("sph_nbr_info", B.NbrInfo),
+                                         ("sph_batch", B.Batch)])
 def test_ctypes_structs_follow_the_header(cname, pycls):
     assert [f[0] for f in pycls._fields_] == _struct_fields(cname)
 
