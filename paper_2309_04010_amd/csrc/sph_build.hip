@@ -821,7 +821,8 @@ static void free_nbr(sph_nbr* h) {
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (void* p : {(void*)h->spec, (void*)h->spec_off_dev, (void*)h->bt32, (void*)h->bt64,
-                  (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg})
+                  (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg, h->dq[0], h->dq[1],
+                  h->imass[0], h->imass[1]})
     if (p) hipFree(p);
   free_graph_cache(h);
   if (h->ctrl_host) hipHostFree(h->ctrl_host);
@@ -1199,6 +1200,11 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   SPH_HIP(hipMemsetAsync(nb->ctrl, 0, sizeof(Ctrl), s));
   SPH_HIP(hipHostMalloc((void**)&nb->ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
   SPH_HIP(hipMalloc(&nb->ke_partial, kKeMaxBlocks * sizeof(double)));
+  // per-run damping coefficients
+  SPH_HIP(hipMalloc(&nb->dq[SPH_F32], std::max<int64_t>(nb->n_upairs, 1) * sizeof(float)));
+  SPH_HIP(hipMalloc(&nb->dq[SPH_F64], std::max<int64_t>(nb->n_upairs, 1) * sizeof(double)));
+  SPH_HIP(hipMalloc(&nb->imass[SPH_F32], std::max<int64_t>(n, 1) * sizeof(float)));
+  SPH_HIP(hipMalloc(&nb->imass[SPH_F64], std::max<int64_t>(n, 1) * sizeof(double)));
   // per-workgroup partial sums of the parameter gradients (reverse mode)
   {
     int64_t slots = (n + 255) / 256;

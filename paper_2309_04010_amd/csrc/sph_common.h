@@ -183,6 +183,10 @@ struct sph_nbr {
   double* bt64 = nullptr;
   double* gdiff = nullptr;           // [2][n] per-particle diffusion-gradient partials (batched)
   mutable bool bat_on = false;
+  // per-run damping coefficients (k_damp_prep), [SPH_F32] float / [SPH_F64] double
+  void* dq[2] = {nullptr, nullptr};     // [n_upairs] q of every pair
+  void* imass[2] = {nullptr, nullptr};  // [n] inverse mass (0 for fixed particles)
+  mutable bool damp_pre = false;        // set by the driver while they are valid
   void* graph_cache = nullptr;       // instantiated whole-run graph (sph_advance_multirate_graph)
   int device = 0;
   sph::Prof* prof = nullptr;         // host-side timing state
@@ -242,6 +246,8 @@ int damping_sweep(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                   double dt, hipStream_t s, bool gated);
 int damping_sweep_rev(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
                       double dt, hipStream_t s);
+int damp_prepare(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
+                 double dt, hipStream_t s);
 int drift_ke(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
              double* ke_out, hipStream_t s, bool gated);
 int load_step(const sph_nbr* nb, const sph_state* st, double dt_l, hipStream_t s);

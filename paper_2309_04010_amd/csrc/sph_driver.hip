@@ -165,9 +165,12 @@ struct RecGuard {  // inner-state recording is switched off on every exit
   }
 };
 
-struct BatGuard {  // per-specimen lookups are switched off on every exit
+struct BatGuard {  // per-specimen lookups and per-run coefficients end with the run
   const sph_nbr* nb;
-  ~BatGuard() { nb->bat_on = false; }
+  ~BatGuard() {
+    nb->bat_on = false;
+    nb->damp_pre = false;
+  }
 };
 
 int batch_begin(const sph_nbr* nb, const sph_material* m, const sph_multirate_cfg* cfg,
@@ -302,6 +305,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
   const bool graph = cfg->use_graph != 0;
   BatGuard bat_guard{nb};
   if ((rc = batch_begin(nb, m, cfg, user))) return rc;
+  if ((rc = damp_prepare(nb, m, st, cfg->eta, dt_s, user))) return rc;
   if (graph) {
     // capture needs a non-null stream: run on a private one ordered after `user`
     SPH_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
@@ -521,7 +525,8 @@ int finish(const sph_nbr* nb, hipStream_t s, const char* what) {
 int forward_fixed_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                           const sph_multirate_cfg* cfg, sph_tape* tape, double dt_s,
                           double dt_slow, std::vector<int64_t>& counts, hipStream_t s) {
-  int rc = SPH_OK;
+  int rc = damp_prepare(nb, m, st, cfg->eta, dt_s, s);
+  if (rc) return rc;
   RecGuard rec_guard{nb};
   bool recorded = false;
   for (int32_t l = 0; l < cfg->n_slow; ++l) {
@@ -593,6 +598,7 @@ extern "C" int sph_advance_multirate_backward(const sph_nbr* nb, const sph_mater
   hipStream_t s = (hipStream_t)stream;
   BatGuard bat_guard{nb};
   if ((rc = batch_begin(nb, m, cfg, s))) return rc;
+  if ((rc = damp_prepare(nb, m, st, cfg->eta, tape->dt_s, s))) return rc;
   if ((rc = backward_enqueue(nb, m, st, cfg, tape, adj, s))) return rc;
   return finish(nb, s, "the reverse pass");
 }

@@ -277,7 +277,9 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
                                              const uint32_t* __restrict__ ablk, int64_t a_begin,
                                              int64_t a_end, int bmax, int pmax, int lmax, T* v,
                                              const uint8_t* __restrict__ flags, T inv_rho0,
-                                             T eta_dt, Ctrl* ctrl, bool gated, Bat bt) {
+                                             T eta_dt, Ctrl* ctrl, bool gated, Bat bt,
+                                             const T* __restrict__ dq,
+                                             const T* __restrict__ imass) {
   if (gated && ctrl->done) return;
   constexpr int APW = 64 / G;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -314,8 +316,12 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
         x[e].x = v[gi];
         x[e].y = v[n + gi];
         x[e].z = D == 3 ? v[2 * n + gi] : T(0);
-        const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
-        x[e].w = fixed ? T(0) : inv_rho0 / g.V[gi];
+        if (imass) {
+          x[e].w = imass[gi];
+        } else {
+          const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
+          x[e].w = fixed ? T(0) : inv_rho0 / g.V[gi];
+        }
       }
 #pragma unroll
     for (int e = 0; e < 2; ++e)
@@ -333,7 +339,30 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     for (int L = lg; L <= nlev; L += G) so[L] = lof[L];
   }
   __syncthreads();
-  for (int i0 = lg; i0 < np; i0 += 4 * G) {
+  // pair words and coefficients: copied when the run precomputed them
+  for (int i0 = lg; dq && i0 < np; i0 += 4 * G) {
+    uint32_t w[4];
+    T qq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + G * u;
+      if (i < np) {
+        w[u] = dpair[lo + i];
+        qq[u] = dq[lo + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + G * u;
+      if (i < np) {
+        PairQ<T> pq;
+        pq.w = w[u];
+        pq.q = qq[u];
+        sp[i] = pq;
+      }
+    }
+  }
+  for (int i0 = lg; !dq && i0 < np; i0 += 4 * G) {
     uint32_t w[4];
     T gg[4];
 #pragma unroll
@@ -410,6 +439,29 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
     v[n + gi] = x.y;
     if (D == 3) v[2 * n + gi] = x.z;
   }
+}
+
+// Per-run damping coefficients: q of every pair and the inverse mass of
+// every particle depend only on eta dt, rho0, the volumes and the flags,
+// which a multi-time-step run holds fixed, so the run computes them once
+// (the same operations, in the same types, as the sweep's own prologue).
+template <typename T>
+__global__ void k_damp_prep(int64_t n_upairs, int64_t n, const uint32_t* __restrict__ sa,
+                            const uint32_t* __restrict__ sb, const T* __restrict__ dgeo,
+                            const T* __restrict__ V, const uint8_t* __restrict__ flags,
+                            T inv_rho0, T eta_dt, Bat bt, T* __restrict__ dq,
+                            T* __restrict__ imass) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  auto im = [&](int64_t a) -> T {
+    const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
+    return fixed ? T(0) : inv_rho0 / V[a];
+  };
+  if (i < n) imass[i] = im(i);
+  if (i >= n_upairs) return;
+  const uint32_t a = sa[i], b = sb[i];
+  const T edt = bt.spec ? bt.get<T>(BT_ETADT, bt.spec[a]) : eta_dt;
+  const T beta = edt * dgeo[i];
+  dq[i] = beta / (T(1) - beta * (im(a) + im(b)));
 }
 
 // drift + kinetic energy: every block writes its partial E_k (fixed-order
@@ -682,7 +734,9 @@ static int damp_launch(const sph_nbr* nb, const sph_material* m, const sph_state
   k_damp<T, D, G, REV><<<grid, 64, lds, s>>>(g, nb->dpair, dgeo, nb->dloff, nb->dloff_base, nb->anlev,
                                         nb->aoff, nb->ablk, a0, a1, bmax, pmax, lmax, (T*)st->v,
                                         st->flags, (T)(1.0 / m->rho0), (T)(eta * dt), nb->ctrl,
-                                        gated, bat_view(nb));
+                                        gated, bat_view(nb),
+                                        nb->damp_pre ? (const T*)nb->dq[sizeof(T) == 8] : nullptr,
+                                        nb->damp_pre ? (const T*)nb->imass[sizeof(T) == 8] : nullptr);
   prof_end(nb, REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING, pe_, s);
   SPH_LAUNCH_CHECK();
   return SPH_OK;
@@ -731,6 +785,28 @@ int damping_sweep(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                         : damping_t<double, 3, false>(nb, m, st, eta, dt, s, gated);
   return nb->dim == 2 ? damping_t<float, 2, false>(nb, m, st, eta, dt, s, gated)
                       : damping_t<float, 3, false>(nb, m, st, eta, dt, s, gated);
+}
+
+template <typename T>
+static int damp_prepare_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                          double eta, double dt, hipStream_t s) {
+  Geo<T> g = geo<T>(nb);
+  const T* dgeo = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)nb->dgeo64
+                                                           : (const void*)nb->dgeo32);
+  const int64_t m_ = std::max<int64_t>(nb->n_upairs, nb->n);
+  k_damp_prep<T><<<nblk(std::max<int64_t>(m_, 1), 256), 256, 0, s>>>(
+      nb->n_upairs, nb->n, nb->sa, nb->sb, dgeo, g.V, st->flags, (T)(1.0 / m->rho0),
+      (T)(eta * dt), bat_view(nb), (T*)nb->dq[sizeof(T) == 8], (T*)nb->imass[sizeof(T) == 8]);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+int damp_prepare(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
+                 double dt, hipStream_t s) {
+  const int rc = st->prec == SPH_F64 ? damp_prepare_t<double>(nb, m, st, eta, dt, s)
+                                     : damp_prepare_t<float>(nb, m, st, eta, dt, s);
+  if (rc == SPH_OK) nb->damp_pre = true;
+  return rc;
 }
 
 int damping_sweep_rev(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
