@@ -132,6 +132,9 @@ def run_gpu(case, prec, steps, warmup, inner, torch, B, profile=True):
     mat = B.material(**case.material)
     run = dict(case.run)
     run.update(n_slow=1, fixed_inner=inner)
+    K = case.material["E"] / (3.0 * (1.0 - 2.0 * case.material["nu"]))
+    B.sph_autotune(nb, mat, st, run["eta"], 0.6 * case.h / (K / case.material["rho0"]) ** 0.5,
+                   with_adjoint=False)
     cfg = B.multirate_cfg(**run, chunk=min(inner, 250), use_graph=0)
     for _ in range(warmup):
         B.sph_advance_multirate(nb, mat, st, cfg)
@@ -200,6 +203,8 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
     c = dataclasses.replace(case, run=run)
     pr = A.MultirateProblem(c, prec, k_hist=inner, chunk=min(inner, 250))
     th = pr.theta0()
+    tuning = B.sph_autotune(pr.nb, pr._material(th), pr.st, run["eta"], pr.run["dt_s"],
+                            with_adjoint=True).as_dict()
     idx = pr.perm.argsort()[case.observable["J_index"]]
     w = torch.zeros((case.dim, case.n), dtype=torch.float64, device="cuda")
     w[case.observable["J_component"], torch.as_tensor(idx).cuda()] = 1.0 / len(idx)
@@ -230,7 +235,7 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
                 n_colors=pr.nb.info.n_colors, total_inner=total_inner, seconds=t1 - t0,
                 seconds_forward=t_fwd, status=bits, grad=g.cpu().numpy(),
                 J=float((pr.st.u * w).sum().item()), u=u,
-                u_finite=bool(np.isfinite(u).all()))
+                u_finite=bool(np.isfinite(u).all()), tuning=tuning)
     pr.close()
     return info, prof
 
@@ -356,6 +361,7 @@ def main():
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,
+        "launch_shapes": adj32["tuning"],
         "status_bits": adj32["status"],
         "u_finite": adj32["u_finite"],
     }

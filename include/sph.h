@@ -396,6 +396,30 @@ int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, con
                                 const sph_multirate_cfg* cfg, sph_report* report, sph_tape* tape,
                                 const sph_adjoint* adj, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Launch shapes.  The tiled gather kernels split each particle's neighbour
+ * list over 1, 2, 4 or 8 lanes; the damping pass gives each anchor 16, 32 or
+ * 64 lanes.  The fastest choice depends on the particle set and precision.
+ * sph_autotune times every candidate on this handle's data (HIP events, a
+ * few launches each, on scratch copies of v, PB and the J2 state: st is not
+ * modified) and keeps the fastest for st->prec; later launches use them.
+ * with_adjoint also tunes the reverse kernels.  eta and dt_s are those of the
+ * runs to come.  Synchronous; allocates scratch for its own duration.
+ * sph_set_tuning / sph_get_tuning write and read the choices directly
+ * (damp_lanes 0 = automatic by LDS size). */
+typedef struct {
+  int32_t lpp_stress;      /* 1, 2, 4 */
+  int32_t lpp_momentum;    /* 2, 4, 8 */
+  int32_t lpp_adj_stress;  /* 1, 2, 4 */
+  int32_t lpp_adj_gather;  /* 2, 4, 8 */
+  int32_t damp_lanes[8];   /* per colour: 0, 16, 32, 64 */
+  double ms_solid, ms_adjoint, ms_damping_sweep; /* out: best times of sph_autotune */
+} sph_tuning;
+int sph_autotune(sph_nbr* nbr, const sph_material* mat, const sph_state* st, double eta,
+                 double dt_s, int with_adjoint, sph_tuning* out, void* stream);
+int sph_set_tuning(sph_nbr* nbr, int prec, const sph_tuning* tuning);
+int sph_get_tuning(const sph_nbr* nbr, int prec, sph_tuning* tuning);
+
 /* Synchronise `stream` and return (and clear) the latched status bits in
  * *status_bits (may be NULL): SPH_OK, or SPH_E_NUMERIC if any bit was set. */
 int sph_status(const sph_nbr* nbr, void* stream, int32_t* status_bits);

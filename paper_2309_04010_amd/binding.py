@@ -30,6 +30,7 @@ EXPORTED = [
     "sph_last_error", "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_drift_vjp",
     "sph_diffusion_step_vjp", "sph_advance_multirate_backward", "sph_constitutive",
     "sph_constitutive_vjp", "sph_build_neighbors_batched", "sph_advance_multirate_graph",
+    "sph_autotune", "sph_set_tuning", "sph_get_tuning",
 ]
 SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load",
                     "adj_stress", "adj_gather", "adj_damping"]
@@ -89,6 +90,17 @@ class Adjoint(C.Structure):
                 ("p", vp), ("work", vp), ("grad", vp)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("lpp_stress", i32), ("lpp_momentum", i32), ("lpp_adj_stress", i32), ("lpp_adj_gather", i32),
+                ("damp_lanes", i32 * 8), ("ms_solid", dbl), ("ms_adjoint", dbl), ("ms_damping_sweep", dbl)]
+
+    def as_dict(self):
+        return dict(lpp_stress=self.lpp_stress, lpp_momentum=self.lpp_momentum,
+                    lpp_adj_stress=self.lpp_adj_stress, lpp_adj_gather=self.lpp_adj_gather,
+                    damp_lanes=list(self.damp_lanes), ms_solid=self.ms_solid, ms_adjoint=self.ms_adjoint,
+                    ms_damping_sweep=self.ms_damping_sweep)
+
+
 class Report(C.Structure):
     _fields_ = [("k", vp), ("ke", vp), ("converged", vp), ("dt_s", dbl), ("dt_slow", dbl),
                 ("k_max", i64), ("total_inner", i64)]
@@ -132,6 +144,10 @@ def lib():
     L.sph_advance_multirate_graph.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
                                               C.POINTER(MultirateCfg), C.POINTER(Report), C.POINTER(Tape),
                                               C.POINTER(Adjoint), vp]
+    L.sph_autotune.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, C.c_int,
+                               C.POINTER(Tuning), vp]
+    L.sph_set_tuning.argtypes = [vp, C.c_int, C.POINTER(Tuning)]
+    L.sph_get_tuning.argtypes = [vp, C.c_int, C.POINTER(Tuning)]
     L.sph_status.argtypes = [vp, vp, C.POINTER(i32)]
     L.sph_profile_enable.argtypes = [vp, C.c_int]
     L.sph_profile_read.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)]
@@ -585,6 +601,27 @@ def sph_constitutive_vjp(mat, prec, H, Pbar, plastic=None, plastic_bar=None, p=N
                                       _dptr(Pbar), _dptr(plastic_bar), _dptr(Hbar), _dptr(pbar), _dptr(thb),
                                       _stream(stream)))
     return Hbar, pbar, thb
+
+
+def sph_autotune(nbr, mat, st, eta, dt_s, with_adjoint=True, stream=None):
+    """Time the launch-shape candidates on this handle and keep the fastest."""
+    cs = st.cstruct(nbr)
+    t = Tuning()
+    _check(lib().sph_autotune(nbr.handle, C.byref(mat), C.byref(cs), float(eta), float(dt_s),
+                              1 if with_adjoint else 0, C.byref(t), _stream(stream)))
+    return t
+
+
+def sph_set_tuning(nbr, prec, lpp_stress=2, lpp_momentum=4, lpp_adj_stress=2, lpp_adj_gather=4,
+                   damp_lanes=(0,) * 8):
+    t = Tuning(lpp_stress, lpp_momentum, lpp_adj_stress, lpp_adj_gather, (i32 * 8)(*damp_lanes), 0.0, 0.0, 0.0)
+    _check(lib().sph_set_tuning(nbr.handle, int(prec), C.byref(t)))
+
+
+def sph_get_tuning(nbr, prec):
+    t = Tuning()
+    _check(lib().sph_get_tuning(nbr.handle, int(prec), C.byref(t)))
+    return t
 
 
 def sph_profile_enable(nbr, enable=True):

@@ -435,8 +435,8 @@ __device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot
 // gathers the neighbours' u (for H) and a_bar = dt w (free particles) from the
 // LDS window; writes G_bar = H_bar B0^T, updates the J2 state adjoint,
 // accumulates p_bar and the parameter partials
-template <typename T, int D>
-__global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
     const uint8_t* __restrict__ flags, T dt, T inv_rho0, const T* __restrict__ plastic,
     T* __restrict__ plb, const T* __restrict__ p, double* __restrict__ pbar, T* __restrict__ Gb,
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
     if (D == 3) sa[l] = av;
   }
   __syncthreads();
-  const int t = threadIdx.x / kLppStress, h = threadIdx.x % kLppStress;
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   const bool active = (uint32_t)t < td.count;
   const uint32_t la = td.own_base + (active ? t : 0);
   const vec4<T> xa = sx[la], ua = su[la];
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
 #pragma unroll
     for (int k = 0; k < D; ++k) Gs[i][k] = Qs[i][k] = T(0);
   if (active)
-    ell_walk<kLppStress>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
       const vec4<T> xb = sx[l], ub = su[l];
       T ab[3];
       if (D == 3) {
@@ -539,8 +539,8 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      Gs[i][k] = lane_sum<kLppStress>(Gs[i][k]);
-      Qs[i][k] = lane_sum<kLppStress>(Qs[i][k]);
+      Gs[i][k] = lane_sum<LPP>(Gs[i][k]);
+      Qs[i][k] = lane_sum<LPP>(Qs[i][k]);
     }
   double thd[kNTheta] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (active && h == 0) {
@@ -609,8 +609,8 @@ __global__ __launch_bounds__(128 * kLppStress) void k_adj_stress(
 //   u_bar_a -= sum_b (V_a G_bar_b + V_b G_bar_a) grad_a W_ab,
 // then (drift_dt != 0) the drift transpose of the previous inner step,
 // w_a += drift_dt u_bar_a for free particles
-template <typename T, int D>
-__global__ __launch_bounds__(128 * kLppMomentum) void k_adj_gather(
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_adj_gather(
     TileGeo<T> g, const T* __restrict__ Gb, double* __restrict__ ub, T* __restrict__ w,
     const uint8_t* __restrict__ flags, double drift_dt, Bat bt) {
   const int64_t tile = xcd_tile(g.n_tiles);
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_adj_gather(
     }
   }
   __syncthreads();
-  const int t = threadIdx.x / kLppMomentum, h = threadIdx.x % kLppMomentum;
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
   const int64_t a = p0 + t;
   const uint32_t la = td.own_base + t;
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_adj_gather(
   }
   const T Va = xa.w;
   T f[3] = {T(0), T(0), T(0)};
-  ell_walk<kLppMomentum>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
     const vec4<T> xb = sx[l];
     T Gbb[NP * 4];
 #pragma unroll
@@ -687,7 +687,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_adj_gather(
     }
   });
 #pragma unroll
-  for (int i = 0; i < D; ++i) f[i] = lane_sum<kLppMomentum>(f[i]);
+  for (int i = 0; i < D; ++i) f[i] = lane_sum<LPP>(f[i]);
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
   const double ddt = (drift_dt != 0.0 && bt.spec) ? bt.get<double>(BT_DT, bt.spec[a]) : drift_dt;
@@ -865,8 +865,8 @@ int grad_reduce(const sph_nbr* nb, double* grad, hipStream_t s) {
   return SPH_OK;
 }
 
-template <typename T, int D>
-static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const double* u,
+template <typename T, int D, int LS, int LG>
+static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u,
                        const void* plastic, const sph_state* st, const sph_adjoint* adj,
                        double dt, double drift_dt, hipStream_t s) {
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
@@ -881,27 +881,45 @@ static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const double* u
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds_s = wm * (D == 3 ? 3 : 2) * sizeof(vec4<T>);
   const size_t lds_g = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
-  int rc = lds_attr(k_adj_stress<T, D>, lds_s);
-  if (rc) return rc;
-  rc = lds_attr(k_adj_gather<T, D>, lds_g);
-  if (rc) return rc;
-  {
+  int rc = SPH_OK;
+  if constexpr (LS > 0) {
+    if ((rc = lds_attr(k_adj_stress<T, D, LS>, lds_s))) return rc;
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_adj_stress<T, D><<<grid, (unsigned)(g.tmax * kLppStress), lds_s, s>>>(
+    k_adj_stress<T, D, LS><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
         g, mp, u, (const T*)adj->v, st->flags, (T)dt, (T)(1.0 / m->rho0), (const T*)plastic,
         (T*)adj->plastic, (const T*)st->p, adj->p, (T*)adj->work, nb->gpart, nb->ctrl,
         bat_view(nb));
     prof_end(nb, SPH_KERNEL_ADJ_STRESS, pe_, s);
+    SPH_LAUNCH_CHECK();
   }
-  SPH_LAUNCH_CHECK();
-  {
+  if constexpr (LG > 0) {
+    if ((rc = lds_attr(k_adj_gather<T, D, LG>, lds_g))) return rc;
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_adj_gather<T, D><<<grid, (unsigned)(g.tmax * kLppMomentum), lds_g, s>>>(
+    k_adj_gather<T, D, LG><<<grid, (unsigned)(g.tmax * LG), lds_g, s>>>(
         g, (const T*)adj->work, adj->u, (T*)adj->v, st->flags, drift_dt, bat_view(nb));
     prof_end(nb, SPH_KERNEL_ADJ_GATHER, pe_, s);
+    SPH_LAUNCH_CHECK();
   }
-  SPH_LAUNCH_CHECK();
   return SPH_OK;
+}
+
+template <typename T, int D>
+static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const double* u,
+                       const void* plastic, const sph_state* st, const sph_adjoint* adj,
+                       double dt, double drift_dt, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  int rc;
+  switch (nb->tune.lpp[TUNE_ADJ_STRESS][prec]) {
+    case 1: rc = adj_solid_l<T, D, 1, 0>(nb, m, u, plastic, st, adj, dt, drift_dt, s); break;
+    case 4: rc = adj_solid_l<T, D, 4, 0>(nb, m, u, plastic, st, adj, dt, drift_dt, s); break;
+    default: rc = adj_solid_l<T, D, 2, 0>(nb, m, u, plastic, st, adj, dt, drift_dt, s); break;
+  }
+  if (rc) return rc;
+  switch (nb->tune.lpp[TUNE_ADJ_GATHER][prec]) {
+    case 2: return adj_solid_l<T, D, 0, 2>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+    case 8: return adj_solid_l<T, D, 0, 8>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+    default: return adj_solid_l<T, D, 0, 4>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+  }
 }
 
 static int check_adj(const sph_nbr* nb, const sph_material* m, const sph_state* st,

@@ -84,6 +84,15 @@ struct Bat {
   }
 };
 
+// tuned launch shapes of one handle (sph_autotune): lanes per particle of the
+// four tiled gather kernels, per precision, and the damping lane-group width
+// per precision and colour (0: the automatic rule)
+enum TuneKernel { TUNE_STRESS = 0, TUNE_MOMENTUM, TUNE_ADJ_STRESS, TUNE_ADJ_GATHER, TUNE_COUNT };
+struct Tune {
+  int lpp[TUNE_COUNT][2] = {{2, 2}, {4, 4}, {2, 2}, {4, 4}};
+  int damp_g[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
+};
+
 constexpr int kKeThreads = 256;
 constexpr int kKeItems = 4;             // particles per thread in the drift kernel
 constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (16.7M particles)
@@ -188,6 +197,7 @@ struct sph_nbr {
   void* imass[2] = {nullptr, nullptr};  // [n] inverse mass (0 for fixed particles)
   mutable bool damp_pre = false;        // set by the driver while they are valid
   void* graph_cache = nullptr;       // instantiated whole-run graph (sph_advance_multirate_graph)
+  sph::Tune tune;                    // launch shapes (sph_autotune)
   int device = 0;
   sph::Prof* prof = nullptr;         // host-side timing state
 };

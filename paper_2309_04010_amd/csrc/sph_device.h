@@ -240,10 +240,10 @@ __device__ int constitutive(const MatP<T>& m, const T* H, T* pl, T p, T* P) {
 template <typename T>
 using vec4 = T __attribute__((ext_vector_type(4)));
 
-// lanes per particle in the tile kernels (measured on the 1M-particle plate:
-// stress is fastest with 2, momentum -- more LDS traffic per pair -- with 4)
-constexpr int kLppStress = 2;
-constexpr int kLppMomentum = 4;
+// lanes per particle of the tile kernels: per-handle choices (Tune), set by
+// sph_autotune; the defaults are the fastest on the 1M-particle plate (the
+// stress kernels with 2, the momentum-shaped ones -- more LDS traffic per
+// pair -- with 4)
 
 template <typename T>
 struct TileGeo {

@@ -13,8 +13,8 @@
 namespace sph {
 
 // stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0
-template <typename T, int D>
-__global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<T> m,
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
                                                              const double* __restrict__ u,
                                                              T* __restrict__ PB,
                                                              T* __restrict__ plastic,
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
       }
   }
   __syncthreads();
-  const int t = threadIdx.x / kLppStress, h = threadIdx.x % kLppStress;
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
   const int64_t a = p0 + t;
   const vec4<T> xa = sx[td.own_base + t], ua = su[td.own_base + t];
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) G[i][k] = T(0);
-  ell_walk<kLppStress>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
     const vec4<T> xb = sx[l], ub = su[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int k = 0; k < D; ++k) G[i][k] = lane_sum<kLppStress>(G[i][k]);
+    for (int k = 0; k < D; ++k) G[i][k] = lane_sum<LPP>(G[i][k]);
   if (h != 0) return;
   T Hm[9] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   T B[D][D];
@@ -143,8 +143,8 @@ __global__ __launch_bounds__(128 * kLppStress) void k_stress(TileGeo<T> g, MatP<
 }
 
 // momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a
-template <typename T, int D>
-__global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
                                                                  const T* __restrict__ PB,
                                                                  T* __restrict__ v,
                                                                  T* __restrict__ acc_out,
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
       }
   }
   __syncthreads();
-  const int t = threadIdx.x / kLppMomentum, h = threadIdx.x % kLppMomentum;
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
   const int64_t a = p0 + t;
   const uint32_t la = td.own_base + t;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
     Pa[4 * q + 3] = pv.w;
   }
   T f[3] = {T(0), T(0), T(0)};
-  ell_walk<kLppMomentum>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
     const vec4<T> xb = sx[l];
     T Pb[NP * 4];
 #pragma unroll
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(128 * kLppMomentum) void k_momentum(TileGeo<T> g,
     }
   });
 #pragma unroll
-  for (int i = 0; i < D; ++i) f[i] = lane_sum<kLppMomentum>(f[i]);
+  for (int i = 0; i < D; ++i) f[i] = lane_sum<LPP>(f[i]);
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
   const T dta = bt.spec ? bt.get<T>(BT_DT, bt.spec[a]) : dt;
@@ -659,41 +659,58 @@ int check_state(const sph_nbr* nb, const sph_state* st, bool need_v) {
 }
 
 
-template <typename T, int D>
-static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
+template <typename T, int D, int LS, int LM>
+static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
                          hipStream_t s, bool gated) {
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   TileGeo<T> g = tile_geo<T>(nb, prec);
   if (g.n_tiles == 0) return SPH_OK;
   MatP<T> mp = matp<T>(m);
   const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
-  const unsigned block_s = (unsigned)(g.tmax * kLppStress);
-  const unsigned block_m = (unsigned)(g.tmax * kLppMomentum);
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds_s = wm * 2 * sizeof(vec4<T>);
   const size_t lds_m = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
-  int rc = lds_attr(k_stress<T, D>, lds_s);
-  if (rc) return rc;
-  rc = lds_attr(k_momentum<T, D>, lds_m);
-  if (rc) return rc;
-  {
+  int rc = SPH_OK;
+  if constexpr (LS > 0) {
+    if ((rc = lds_attr(k_stress<T, D, LS>, lds_s))) return rc;
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_stress<T, D><<<grid, block_s, lds_s, s>>>(g, mp, st->u, (T*)st->PB, (T*)st->plastic,
-                                              (const T*)st->p, nb->ctrl, gated,
-                                              m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr,
-                                              bat_view(nb));
+    k_stress<T, D, LS><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
+        g, mp, st->u, (T*)st->PB, (T*)st->plastic, (const T*)st->p, nb->ctrl, gated,
+        m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr, bat_view(nb));
     prof_end(nb, SPH_KERNEL_STRESS, pe_, s);
+    SPH_LAUNCH_CHECK();
   }
-  SPH_LAUNCH_CHECK();
-  {
+  if constexpr (LM > 0) {
+    if ((rc = lds_attr(k_momentum<T, D, LM>, lds_m))) return rc;
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_momentum<T, D><<<grid, block_m, lds_m, s>>>(g, (const T*)st->PB, (T*)st->v, (T*)st->acc,
-                                                st->flags, (T)(1.0 / m->rho0), (T)dt, nb->ctrl,
-                                                gated, bat_view(nb));
+    k_momentum<T, D, LM><<<grid, (unsigned)(g.tmax * LM), lds_m, s>>>(
+        g, (const T*)st->PB, (T*)st->v, (T*)st->acc, st->flags, (T)(1.0 / m->rho0), (T)dt,
+        nb->ctrl, gated, bat_view(nb));
     prof_end(nb, SPH_KERNEL_MOMENTUM, pe_, s);
+    SPH_LAUNCH_CHECK();
   }
-  SPH_LAUNCH_CHECK();
   return SPH_OK;
+}
+
+// lanes per particle of the two tiled kernels: the handle's tuned choice
+// (sph_autotune), else the defaults
+template <typename T, int D>
+static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
+                         hipStream_t s, bool gated) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  const int ls = nb->tune.lpp[TUNE_STRESS][prec], lm = nb->tune.lpp[TUNE_MOMENTUM][prec];
+  int rc;
+  switch (ls) {
+    case 1: rc = solid_stage_l<T, D, 1, 0>(nb, m, st, dt, s, gated); break;
+    case 4: rc = solid_stage_l<T, D, 4, 0>(nb, m, st, dt, s, gated); break;
+    default: rc = solid_stage_l<T, D, 2, 0>(nb, m, st, dt, s, gated); break;
+  }
+  if (rc) return rc;
+  switch (lm) {
+    case 2: return solid_stage_l<T, D, 0, 2>(nb, m, st, dt, s, gated);
+    case 8: return solid_stage_l<T, D, 0, 8>(nb, m, st, dt, s, gated);
+    default: return solid_stage_l<T, D, 0, 4>(nb, m, st, dt, s, gated);
+  }
 }
 
 int solid_stage(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
@@ -766,10 +783,14 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
     const int col = REV ? ncol - 1 - c_ : c_;
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
     const size_t per = damp_lds_per_anchor<T>(nb, col);
+    const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+    int want = nb->tune.damp_g[prec][col];
+    if (want == 16 && 4 * per > (size_t)kDampLdsBudget) want = 32;  // tuned width must fit
+    if (want == 32 && 2 * per > (size_t)kDampLdsBudget) want = 64;
     int rc;
-    if (SPH_DAMP_LANES <= 16 && 4 * per <= 64 * 1024)
+    if (want == 16 || (want == 0 && SPH_DAMP_LANES <= 16 && 4 * per <= 64 * 1024))
       rc = damp_launch<T, D, 16, REV>(nb, m, st, eta, dt, s, gated, col);
-    else if (SPH_DAMP_LANES <= 32 && 2 * per <= 64 * 1024)
+    else if (want == 32 || (want == 0 && SPH_DAMP_LANES <= 32 && 2 * per <= 64 * 1024))
       rc = damp_launch<T, D, 32, REV>(nb, m, st, eta, dt, s, gated, col);
     else
       rc = damp_launch<T, D, 64, REV>(nb, m, st, eta, dt, s, gated, col);

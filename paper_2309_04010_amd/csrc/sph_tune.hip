@@ -1,0 +1,214 @@
+// sph_tune.hip -- launch-shape autotuner.
+//
+// The best number of lanes per particle of the tiled gather kernels, and the
+// best lane-group width of each damping colour pass, depend on the particle
+// set (neighbour counts, tile windows, anchor block sizes) and on the
+// precision.  sph_autotune times every candidate on the handle's own data,
+// with HIP events, on scratch copies of the state, and keeps the fastest in
+// the handle; later launches on that handle use them.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "sph_common.h"
+
+using namespace sph;
+
+namespace {
+
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  template <typename P>
+  int alloc(P** p, size_t bytes) {
+    if (bytes == 0) {
+      *p = nullptr;
+      return SPH_OK;
+    }
+    if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
+      set_error("autotune scratch allocation of %zu bytes failed", bytes);
+      return SPH_E_DEVICE;
+    }
+    ptrs.push_back(*p);
+    return SPH_OK;
+  }
+};
+
+// mean milliseconds of `reps` calls of f, after one untimed call
+template <typename F>
+int time_ms(hipStream_t s, int reps, F&& f, double* ms) {
+  int rc = f();
+  if (rc) return rc;
+  hipEvent_t a = nullptr, b = nullptr;
+  SPH_HIP(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    set_error("event creation failed");
+    return SPH_E_DEVICE;
+  }
+  hipEventRecord(a, s);
+  for (int i = 0; i < reps && rc == SPH_OK; ++i) rc = f();
+  hipEventRecord(b, s);
+  hipEventSynchronize(b);
+  float t = 0.f;
+  hipEventElapsedTime(&t, a, b);
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  *ms = (double)t / reps;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int sph_set_tuning(sph_nbr* nb, int prec, const sph_tuning* t) {
+  clear_error();
+  if (!nb || !t || (prec != SPH_F32 && prec != SPH_F64)) {
+    set_error("bad arguments");
+    return SPH_E_ARG;
+  }
+  auto ok_s = [](int v) { return v == 1 || v == 2 || v == 4; };
+  auto ok_m = [](int v) { return v == 2 || v == 4 || v == 8; };
+  if (!ok_s(t->lpp_stress) || !ok_m(t->lpp_momentum) || !ok_s(t->lpp_adj_stress) ||
+      !ok_m(t->lpp_adj_gather)) {
+    set_error("lanes per particle: stress kernels 1, 2 or 4; momentum-shaped kernels 2, 4 or 8");
+    return SPH_E_ARG;
+  }
+  for (int c = 0; c < 8; ++c)
+    if (t->damp_lanes[c] != 0 && t->damp_lanes[c] != 16 && t->damp_lanes[c] != 32 &&
+        t->damp_lanes[c] != 64) {
+      set_error("damping lanes per anchor: 0 (automatic), 16, 32 or 64");
+      return SPH_E_ARG;
+    }
+  nb->tune.lpp[TUNE_STRESS][prec] = t->lpp_stress;
+  nb->tune.lpp[TUNE_MOMENTUM][prec] = t->lpp_momentum;
+  nb->tune.lpp[TUNE_ADJ_STRESS][prec] = t->lpp_adj_stress;
+  nb->tune.lpp[TUNE_ADJ_GATHER][prec] = t->lpp_adj_gather;
+  for (int c = 0; c < 8; ++c) nb->tune.damp_g[prec][c] = t->damp_lanes[c];
+  return SPH_OK;
+}
+
+extern "C" int sph_get_tuning(const sph_nbr* nb, int prec, sph_tuning* t) {
+  clear_error();
+  if (!nb || !t || (prec != SPH_F32 && prec != SPH_F64)) {
+    set_error("bad arguments");
+    return SPH_E_ARG;
+  }
+  *t = sph_tuning{};
+  t->lpp_stress = nb->tune.lpp[TUNE_STRESS][prec];
+  t->lpp_momentum = nb->tune.lpp[TUNE_MOMENTUM][prec];
+  t->lpp_adj_stress = nb->tune.lpp[TUNE_ADJ_STRESS][prec];
+  t->lpp_adj_gather = nb->tune.lpp[TUNE_ADJ_GATHER][prec];
+  for (int c = 0; c < 8; ++c) t->damp_lanes[c] = nb->tune.damp_g[prec][c];
+  return SPH_OK;
+}
+
+extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
+                            double dt_s, int with_adjoint, sph_tuning* out, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!m || !st->PB || (m->model == SPH_MODEL_J2 && !st->plastic)) {
+    set_error("material, PB (and the J2 state) are required");
+    return SPH_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int prec = st->prec;
+  const size_t n = (size_t)nb->n, d = (size_t)nb->dim, T = prec == SPH_F64 ? 8 : 4;
+  const bool j2 = m->model == SPH_MODEL_J2;
+  Scratch sc;
+  sph_state w = *st;  // scratch copies of everything the kernels write
+  w.acc = nullptr;
+  if ((rc = sc.alloc(&w.v, d * n * T)) || (rc = sc.alloc(&w.PB, d * d * n * T))) return rc;
+  SPH_HIP(hipMemcpyAsync(w.v, st->v, d * n * T, hipMemcpyDeviceToDevice, s));
+  if (j2) {
+    if ((rc = sc.alloc(&w.plastic, 7 * n * T))) return rc;
+    SPH_HIP(hipMemcpyAsync(w.plastic, st->plastic, 7 * n * T, hipMemcpyDeviceToDevice, s));
+  }
+  sph_adjoint a{};
+  a.prec = prec;
+  if (with_adjoint) {
+    if ((rc = sc.alloc(&a.u, d * n * 8)) || (rc = sc.alloc(&a.v, d * n * T)) ||
+        (rc = sc.alloc(&a.work, d * d * n * T)) || (rc = sc.alloc(&a.grad, SPH_NGRAD * 8)) ||
+        (rc = sc.alloc(&a.p, n * 8)))
+      return rc;
+    SPH_HIP(hipMemsetAsync(a.u, 0, d * n * 8, s));
+    SPH_HIP(hipMemcpyAsync(a.v, st->v, d * n * T, hipMemcpyDeviceToDevice, s));
+    SPH_HIP(hipMemsetAsync(a.p, 0, n * 8, s));
+    SPH_HIP(hipMemsetAsync(a.grad, 0, SPH_NGRAD * 8, s));
+    if (j2) {
+      if ((rc = sc.alloc(&a.plastic, 7 * n * T))) return rc;
+      SPH_HIP(hipMemsetAsync(a.plastic, 0, 7 * n * T, s));
+    }
+  }
+  if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) return rc;
+  sph_tuning res{};
+  const int reps = 3;
+  Tune& tn = nb->tune;
+  // tiled kernels: vary one kernel's lanes at a time (the other launch of
+  // the pair is the same in every candidate, so the fastest sum picks it)
+  auto pick = [&](int k, std::initializer_list<int> cands, auto&& run, double* best_ms) -> int {
+    int best = tn.lpp[k][prec];
+    double bt = 1e300;
+    for (int c : cands) {
+      tn.lpp[k][prec] = c;
+      double ms = 0.0;
+      int r = time_ms(s, reps, run, &ms);
+      if (r) return r;
+      if (ms < bt) {
+        bt = ms;
+        best = c;
+      }
+    }
+    tn.lpp[k][prec] = best;
+    *best_ms = bt;
+    return SPH_OK;
+  };
+  auto solid = [&]() { return solid_stage(nb, m, &w, dt_s, s, false); };
+  double ms = 0.0;
+  if ((rc = pick(TUNE_STRESS, {1, 2, 4}, solid, &ms))) return rc;
+  res.ms_solid = ms;
+  if ((rc = pick(TUNE_MOMENTUM, {2, 4, 8}, solid, &ms))) return rc;
+  res.ms_solid = ms;
+  if (with_adjoint) {
+    auto adjr = [&]() { return adj_solid(nb, m, st->u, w.plastic, &w, &a, dt_s, dt_s, s); };
+    if ((rc = pick(TUNE_ADJ_STRESS, {1, 2, 4}, adjr, &ms))) return rc;
+    if ((rc = pick(TUNE_ADJ_GATHER, {2, 4, 8}, adjr, &ms))) return rc;
+    res.ms_adjoint = ms;
+    if ((rc = grad_reduce(nb, a.grad, s))) return rc;  // clears the partials it accumulated
+  }
+  // damping: each colour pass separately
+  const int ncol = 1 << nb->dim;
+  double sweep = 0.0;
+  for (int col = 0; col < ncol; ++col) {
+    if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
+    int best = 0;
+    double bt = 1e300;
+    for (int g : {16, 32, 64}) {
+      tn.damp_g[prec][col] = g;
+      // time the whole sweep: only this colour's launch differs between candidates
+      double t = 0.0;
+      rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
+      if (rc) break;
+      if (t < bt) {
+        bt = t;
+        best = g;
+      }
+    }
+    if (rc) break;
+    tn.damp_g[prec][col] = best;
+    sweep = bt;
+  }
+  nb->damp_pre = false;
+  if (rc) return rc;
+  SPH_HIP(hipStreamSynchronize(s));
+  res.ms_damping_sweep = sweep;
+  res.lpp_stress = tn.lpp[TUNE_STRESS][prec];
+  res.lpp_momentum = tn.lpp[TUNE_MOMENTUM][prec];
+  res.lpp_adj_stress = tn.lpp[TUNE_ADJ_STRESS][prec];
+  res.lpp_adj_gather = tn.lpp[TUNE_ADJ_GATHER][prec];
+  for (int c = 0; c < 8; ++c) res.damp_lanes[c] = tn.damp_g[prec][c];
+  if (out) *out = res;
+  return SPH_OK;
+}

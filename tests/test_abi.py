@@ -70,7 +70,7 @@ def test_binding_wraps_exactly_the_declared_set():
                                          ("sph_multirate_cfg", B.MultirateCfg),
                                          ("sph_report", B.Report), ("sph_tape", B.Tape),
                                          ("sph_adjoint", B.Adjoint), ("sph_nbr_info", B.NbrInfo),
-                                         ("sph_batch", B.Batch)])
+                                         ("sph_batch", B.Batch), ("sph_tuning", B.Tuning)])
 def test_ctypes_structs_follow_the_header(cname, pycls):
     assert [f[0] for f in pycls._fields_] == _struct_fields(cname)
 

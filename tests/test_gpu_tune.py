@@ -1,0 +1,128 @@
+"""Launch shapes and the autotuner.
+
+Every lanes-per-particle variant of the four tiled gather kernels and every
+damping lane-group width must give the oracle's results (FP64 1e-10, FP32
+1e-4; the reverse kernels as transposes, 1e-9 / 2e-3).  The autotuner must
+leave the state untouched, choose valid shapes, and a run with them must
+still match the oracle.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2309_04010_amd import binding as B
+from paper_2309_04010_amd import cases
+
+from .parity_util import TOL, build_pair, dev, host, jittered, rel_err, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+NH = dict(model=cases.NH, E=1.0e8, nu=0.4, rho0=2000.0, C_swell=3.0e6, c0=0.0)
+
+
+def _setup(oracle_mod, dim, prec, seed=5):
+    shape = (37, 23) if dim == 2 else (13, 9, 7)
+    X, V, h = jittered(shape, jitter=0.1, seed=seed)
+    o, nb = build_pair(oracle_mod, dim, X, V, h)
+    rng = np.random.default_rng(seed)
+    u = np.ascontiguousarray(5e-3 * rng.normal(0, 1, (dim, o.n)) * 1e-3 +
+                             5e-3 * np.diag(rng.normal(0, 1, dim)) @ o.X)
+    v = np.ascontiguousarray(rng.normal(0, 1e-3, (dim, o.n)))
+    flags = np.zeros(o.n, np.uint8)
+    flags[rng.random(o.n) < 0.1] = cases.FIXED
+    p = np.ascontiguousarray(rng.uniform(0, 1e6, o.n))
+    T = torch_dtype(prec)
+    st = B.new_state(nb, prec, with_acc=True)
+    st.u.copy_(dev(u))
+    st.v.copy_(dev(v, T))
+    st.flags = dev(flags)
+    st.p = dev(p, T)
+    return o, nb, st, u, v, flags, p
+
+
+@pytest.mark.parametrize("prec", [B.SPH_F64, B.SPH_F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_every_forward_launch_shape_matches_oracle(oracle_mod, dim, prec):
+    o, nb, st, u, v, flags, p = _setup(oracle_mod, dim, prec)
+    mo, mg = o.material(**NH), B.material(**NH)
+    dt = 1e-7
+    vo = v.copy()
+    _, PBo, acco = o.solid_step(mo, dt, u, vo, p=p, flags=flags)
+    T = torch_dtype(prec)
+    for ls, lm in itertools.product((1, 2, 4), (2, 4, 8)):
+        print(f"[tune] dim={dim} prec={prec} stress lanes {ls} momentum lanes {lm}", flush=True)
+        B.sph_set_tuning(nb, prec, lpp_stress=ls, lpp_momentum=lm)
+        st.v.copy_(dev(v, T))
+        B.sph_solid_relax_step(nb, mg, st, dt)
+        assert rel_err(host(st.PB), PBo) < TOL[prec], (ls, lm)
+        assert rel_err(host(st.acc), acco) < TOL[prec], (ls, lm)
+    # damping widths, all colours alike
+    eta = 5.0
+    w = v.copy()
+    o.damping_sweep(NH["rho0"], eta, dt, w, flags)
+    for g in (16, 32, 64):
+        B.sph_set_tuning(nb, prec, damp_lanes=(g,) * 8)
+        st.v.copy_(dev(v, T))
+        B.sph_damping_sweep(nb, mg, st, eta, dt)
+        assert rel_err(host(st.v), w) < TOL[prec], g
+    nb.close()
+
+
+@pytest.mark.parametrize("prec", [B.SPH_F64, B.SPH_F32], ids=["f64", "f32"])
+def test_every_reverse_launch_shape_is_the_same_transpose(oracle_mod, prec):
+    """All reverse shapes give the reverse of the default shape (the default
+    is checked against the oracle's tangents in the adjoint tests)."""
+    o, nb, st, u, v, flags, p = _setup(oracle_mod, 3, prec)
+    mg = B.material(**NH)
+    T = torch_dtype(prec)
+    w = np.random.default_rng(2).normal(0, 1, (3, o.n))
+
+    def vjp():
+        adj = B.new_adjoint(nb, prec, with_p=True)
+        adj.v.copy_(dev(w, T))
+        B.sph_solid_relax_step_vjp(nb, mg, st, adj, 1e-7)
+        return host(adj.u), host(adj.p), host(adj.grad)
+
+    B.sph_set_tuning(nb, prec)
+    ref = vjp()
+    tol = 1e-12 if prec == B.SPH_F64 else 1e-5
+    for la, lg in itertools.product((1, 2, 4), (2, 4, 8)):
+        B.sph_set_tuning(nb, prec, lpp_adj_stress=la, lpp_adj_gather=lg)
+        got = vjp()
+        for g_, r_ in zip(got, ref):
+            assert rel_err(g_, r_) < tol, (la, lg)
+    nb.close()
+
+
+def test_autotune_leaves_state_and_keeps_parity(oracle_mod):
+    c = cases.strip2d(nx=60, ny=8, n_slow=2, fixed_inner=40, k_max=0)
+    o, nb = build_pair(oracle_mod, 2, c.X, c.V, c.h)
+    perm = o.perm
+    st = B.new_state(nb, B.SPH_F64, with_diffusion=True)
+    st.flags = dev(c.flags[perm])
+    st.c.copy_(dev(c.c_init[perm]))
+    st.v.copy_(dev(np.random.default_rng(1).normal(0, 1e-4, (2, c.n))))
+    before = [t.clone() for t in (st.u, st.v, st.c)]
+    mat = B.material(**c.material)
+    K = c.material["E"] / (3 * (1 - 2 * c.material["nu"]))
+    dt = 0.6 * c.h / np.sqrt(K / c.material["rho0"])
+    t = B.sph_autotune(nb, mat, st, c.run["eta"], dt, with_adjoint=True)
+    for a, b in zip(before, (st.u, st.v, st.c)):
+        assert (a == b).all()
+    assert t.lpp_stress in (1, 2, 4) and t.lpp_momentum in (2, 4, 8)
+    assert t.lpp_adj_stress in (1, 2, 4) and t.lpp_adj_gather in (2, 4, 8)
+    assert all(g in (16, 32, 64) for g in list(t.damp_lanes)[:4])
+    assert t.ms_solid > 0 and t.ms_damping_sweep > 0
+    got = B.sph_get_tuning(nb, B.SPH_F64)
+    assert got.lpp_stress == t.lpp_stress and list(got.damp_lanes) == list(t.damp_lanes)
+    # a run with the tuned shapes against the oracle
+    st.v.zero_()
+    flags = np.ascontiguousarray(c.flags[perm])
+    uo, vo = o.arr(2, c.n), o.arr(2, c.n)
+    co = np.ascontiguousarray(c.c_init[perm])
+    qo, po = o.arr(2, c.n), o.arr(c.n)
+    o.advance(o.material(**c.material), o.cfg(**c.run), uo, vo, c=co, q=qo, p=po, flags=flags)
+    B.sph_advance_multirate(nb, mat, st, B.multirate_cfg(**c.run))
+    assert rel_err(host(st.u), uo) < 1e-10
+    nb.close()
