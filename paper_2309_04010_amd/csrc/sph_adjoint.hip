@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "sph_device.h"
@@ -64,7 +65,7 @@ __device__ __forceinline__ void add_symx(const T* S, const T* A, T* D) {
 // mapping's increment dgamma is differentiated through its scalar residual
 //   f(dg) = |s_pre| - sqrt(2/3) k(alpha + sqrt(2/3) dg) - 2 mubar dg = 0
 // (implicit-function theorem: d dg = -(df/dx dx) / (df/d dg)).
-template <typename T>
+template <typename T, int MODEL = -1>
 __device__ int constitutive_vjp(const MatP<T>& m, const T* H, const T* pl, T p, const T* Pb,
                                 T* plb, T* Hbar, T& pbar, T* th) {
   const T trH = H[0] + H[4] + H[8];
@@ -84,7 +85,7 @@ __device__ int constitutive_vjp(const MatP<T>& m, const T* H, const T* pl, T p, 
   for (int i = 0; i < kNTheta; ++i) th[i] = T(0);
   T mub = T(0), Kb = T(0), Jb = T(0);
   int st = 0;
-  if (m.model == SPH_MODEL_LE) {
+  if (model_is<MODEL>(m, SPH_MODEL_LE)) {
     // P = 2 mu sym(H) + lam tr(H) I - p J F^-T, lam = K - 2 mu / 3
     const T trPb = Pb[0] + Pb[4] + Pb[8];
     T sHP = T(0);
@@ -130,7 +131,7 @@ __device__ int constitutive_vjp(const MatP<T>& m, const T* H, const T* pl, T p, 
   T trE3 = T(0), sn = T(0), mubr = T(0), dg = T(0), fac = T(1), alpha = T(0);
   bool plastic = false;
   const T r23 = T(0.816496580927726);  // sqrt(2/3)
-  if (m.model == SPH_MODEL_NH) {
+  if (model_is<MODEL>(m, SPH_MODEL_NH)) {
     T Bm[9];
     sym_sum(H, Bm);
     const T cb = cbrt(J);
@@ -222,7 +223,7 @@ __device__ int constitutive_vjp(const MatP<T>& m, const T* H, const T* pl, T p, 
   pbar = -J * trtb;
   Jb += (m.K * J - p) * trtb;
   Kb += T(0.5) * jm1 * (T(2) + jm1) * trtb;
-  if (m.model == SPH_MODEL_NH) {
+  if (model_is<MODEL>(m, SPH_MODEL_NH)) {
     // s = mu J^(-2/3) dev(F F^T - I)
     const T dBd = dot9(sb, dB);
     mub += s23 * dBd;
@@ -435,7 +436,7 @@ __device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot
 // gathers the neighbours' u (for H) and a_bar = dt w (free particles) from the
 // LDS window; writes G_bar = H_bar B0^T, updates the J2 state adjoint,
 // accumulates p_bar and the parameter partials
-template <typename T, int D, int LPP>
+template <typename T, int D, int LPP, int MODEL>
 __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
     const uint8_t* __restrict__ flags, T dt, T inv_rho0, const T* __restrict__ plastic,
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
         Pb[i * 3 + k] = ps * inv_rho0;
       }
     T pl[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)}, pv[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-    if (m.model == SPH_MODEL_J2) {
+    if (model_is<MODEL>(m, SPH_MODEL_J2)) {
 #pragma unroll
       for (int i = 0; i < 7; ++i) {
         pl[i] = plastic[i * n + a];
@@ -582,9 +583,9 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
       mm.K = bt.get<T>(BT_K, sp);
       mm.lam = bt.get<T>(BT_LAM, sp);
     }
-    const int st = constitutive_vjp(mm, Hm, pl, p ? p[a] : T(0), Pb, pv, Hb, pb, th);
+    const int st = constitutive_vjp<T, MODEL>(mm, Hm, pl, p ? p[a] : T(0), Pb, pv, Hb, pb, th);
     if (st) atomicOr(&ctrl->status, st);
-    if (m.model == SPH_MODEL_J2) {
+    if (model_is<MODEL>(m, SPH_MODEL_J2)) {
 #pragma unroll
       for (int i = 0; i < 7; ++i) plb[i * n + a] = pv[i];
     }
@@ -865,7 +866,7 @@ int grad_reduce(const sph_nbr* nb, double* grad, hipStream_t s) {
   return SPH_OK;
 }
 
-template <typename T, int D, int LS, int LG>
+template <typename T, int D, int LS, int LG, int MODEL>
 static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u,
                        const void* plastic, const sph_state* st, const sph_adjoint* adj,
                        double dt, double drift_dt, hipStream_t s) {
@@ -883,9 +884,9 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
   const size_t lds_g = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
   int rc = SPH_OK;
   if constexpr (LS > 0) {
-    if ((rc = lds_attr(k_adj_stress<T, D, LS>, lds_s))) return rc;
+    if ((rc = lds_attr(k_adj_stress<T, D, LS, MODEL>, lds_s))) return rc;
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_adj_stress<T, D, LS><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
+    k_adj_stress<T, D, LS, MODEL><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
         g, mp, u, (const T*)adj->v, st->flags, (T)dt, (T)(1.0 / m->rho0), (const T*)plastic,
         (T*)adj->plastic, (const T*)st->p, adj->p, (T*)adj->work, nb->gpart, nb->ctrl,
         bat_view(nb));
@@ -909,16 +910,25 @@ static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const double* u
                        double dt, double drift_dt, hipStream_t s) {
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   int rc;
-  switch (nb->tune.lpp[TUNE_ADJ_STRESS][prec]) {
-    case 1: rc = adj_solid_l<T, D, 1, 0>(nb, m, u, plastic, st, adj, dt, drift_dt, s); break;
-    case 4: rc = adj_solid_l<T, D, 4, 0>(nb, m, u, plastic, st, adj, dt, drift_dt, s); break;
-    default: rc = adj_solid_l<T, D, 2, 0>(nb, m, u, plastic, st, adj, dt, drift_dt, s); break;
+  const int ls = nb->tune.lpp[TUNE_ADJ_STRESS][prec];
+  auto stress = [&](auto model_c) -> int {
+    constexpr int M = decltype(model_c)::value;
+    switch (ls) {
+      case 1: return adj_solid_l<T, D, 1, 0, M>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+      case 4: return adj_solid_l<T, D, 4, 0, M>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+      default: return adj_solid_l<T, D, 2, 0, M>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+    }
+  };
+  switch (m->model) {
+    case SPH_MODEL_LE: rc = stress(std::integral_constant<int, SPH_MODEL_LE>{}); break;
+    case SPH_MODEL_NH: rc = stress(std::integral_constant<int, SPH_MODEL_NH>{}); break;
+    default: rc = stress(std::integral_constant<int, SPH_MODEL_J2>{}); break;
   }
   if (rc) return rc;
   switch (nb->tune.lpp[TUNE_ADJ_GATHER][prec]) {
-    case 2: return adj_solid_l<T, D, 0, 2>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
-    case 8: return adj_solid_l<T, D, 0, 8>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
-    default: return adj_solid_l<T, D, 0, 4>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+    case 2: return adj_solid_l<T, D, 0, 2, -1>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+    case 8: return adj_solid_l<T, D, 0, 8, -1>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+    default: return adj_solid_l<T, D, 0, 4, -1>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
   }
 }
 

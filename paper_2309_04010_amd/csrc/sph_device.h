@@ -99,7 +99,16 @@ __device__ __forceinline__ void sym_sum(const T* A, T* S) {
 // paper (LE is the small-strain reading).  Strain measures come from H by
 // exact identities (det(I+H) - 1, F F^T - I) so FP32 keeps small strains.
 // pl: Cbar_p^-1 - I (xx,yy,zz,xy,yz,xz) and alpha.
-template <typename T>
+// MODEL >= 0 fixes the material model at compile time (a kernel specialised
+// for one model carries only that model's code and registers); -1 reads it
+// from m at run time
+template <int MODEL, typename T>
+__device__ __forceinline__ bool model_is(const MatP<T>& m, int k) {
+  if constexpr (MODEL >= 0) return MODEL == k;
+  else return m.model == k;
+}
+
+template <typename T, int MODEL = -1>
 __device__ int constitutive(const MatP<T>& m, const T* H, T* pl, T p, T* P) {
   T trH = H[0] + H[4] + H[8];
   T trH2 = H[0] * H[0] + H[4] * H[4] + H[8] * H[8] + T(2) * (H[1] * H[3] + H[2] * H[6] + H[5] * H[7]);
@@ -116,7 +125,7 @@ __device__ int constitutive(const MatP<T>& m, const T* H, T* pl, T p, T* P) {
   int st = 0;
   T tau[9];
   const T vol = T(0.5) * m.K * jm1 * (T(2) + jm1);
-  if (m.model == SPH_MODEL_LE) {
+  if (model_is<MODEL>(m, SPH_MODEL_LE)) {
     T tm = T(2) * m.mu;
     P[0] = tm * H[0] + m.lam * trH;
     P[4] = tm * H[4] + m.lam * trH;
@@ -130,7 +139,7 @@ __device__ int constitutive(const MatP<T>& m, const T* H, T* pl, T p, T* P) {
       for (int j = 0; j < 3; ++j) P[i * 3 + j] -= J * p * Fi[j * 3 + i];
     return 0;
   }
-  if (m.model == SPH_MODEL_NH) {
+  if (model_is<MODEL>(m, SPH_MODEL_NH)) {
     T Bm[9];
     sym_sum(H, Bm);
     T cb = cbrt(J);

@@ -8,12 +8,14 @@
 // type T (float or double), so the FP32 path loses nothing to cancellation.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sph_device.h"
 
 namespace sph {
 
 // stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0
-template <typename T, int D, int LPP>
+template <typename T, int D, int LPP, int MODEL>
 __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
                                                              const double* __restrict__ u,
                                                              T* __restrict__ PB,
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
       Hm[i * 3 + k] = acc;
     }
   T pl[7];
-  if (m.model == SPH_MODEL_J2) {
+  if (model_is<MODEL>(m, SPH_MODEL_J2)) {
 #pragma unroll
     for (int i = 0; i < 7; ++i) pl[i] = plastic[i * n + a];
     if (rec_pl) {
@@ -125,9 +127,9 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
     mm.K = bt.get<T>(BT_K, sp);
     mm.lam = bt.get<T>(BT_LAM, sp);
   }
-  int st = constitutive(mm, Hm, pl, p ? p[a] : T(0), P);
+  int st = constitutive<T, MODEL>(mm, Hm, pl, p ? p[a] : T(0), P);
   if (st) atomicOr(&ctrl->status, st);
-  if (m.model == SPH_MODEL_J2) {
+  if (model_is<MODEL>(m, SPH_MODEL_J2)) {
 #pragma unroll
     for (int i = 0; i < 7; ++i) plastic[i * n + a] = pl[i];
   }
@@ -659,7 +661,7 @@ int check_state(const sph_nbr* nb, const sph_state* st, bool need_v) {
 }
 
 
-template <typename T, int D, int LS, int LM>
+template <typename T, int D, int LS, int LM, int MODEL>
 static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
                          hipStream_t s, bool gated) {
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
@@ -672,9 +674,9 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
   const size_t lds_m = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
   int rc = SPH_OK;
   if constexpr (LS > 0) {
-    if ((rc = lds_attr(k_stress<T, D, LS>, lds_s))) return rc;
+    if ((rc = lds_attr(k_stress<T, D, LS, MODEL>, lds_s))) return rc;
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_stress<T, D, LS><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
+    k_stress<T, D, LS, MODEL><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
         g, mp, st->u, (T*)st->PB, (T*)st->plastic, (const T*)st->p, nb->ctrl, gated,
         m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr, bat_view(nb));
     prof_end(nb, SPH_KERNEL_STRESS, pe_, s);
@@ -700,16 +702,24 @@ static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_sta
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   const int ls = nb->tune.lpp[TUNE_STRESS][prec], lm = nb->tune.lpp[TUNE_MOMENTUM][prec];
   int rc;
-  switch (ls) {
-    case 1: rc = solid_stage_l<T, D, 1, 0>(nb, m, st, dt, s, gated); break;
-    case 4: rc = solid_stage_l<T, D, 4, 0>(nb, m, st, dt, s, gated); break;
-    default: rc = solid_stage_l<T, D, 2, 0>(nb, m, st, dt, s, gated); break;
+  auto stress = [&](auto model_c) -> int {
+    constexpr int M = decltype(model_c)::value;
+    switch (ls) {
+      case 1: return solid_stage_l<T, D, 1, 0, M>(nb, m, st, dt, s, gated);
+      case 4: return solid_stage_l<T, D, 4, 0, M>(nb, m, st, dt, s, gated);
+      default: return solid_stage_l<T, D, 2, 0, M>(nb, m, st, dt, s, gated);
+    }
+  };
+  switch (m->model) {
+    case SPH_MODEL_LE: rc = stress(std::integral_constant<int, SPH_MODEL_LE>{}); break;
+    case SPH_MODEL_NH: rc = stress(std::integral_constant<int, SPH_MODEL_NH>{}); break;
+    default: rc = stress(std::integral_constant<int, SPH_MODEL_J2>{}); break;
   }
   if (rc) return rc;
   switch (lm) {
-    case 2: return solid_stage_l<T, D, 0, 2>(nb, m, st, dt, s, gated);
-    case 8: return solid_stage_l<T, D, 0, 8>(nb, m, st, dt, s, gated);
-    default: return solid_stage_l<T, D, 0, 4>(nb, m, st, dt, s, gated);
+    case 2: return solid_stage_l<T, D, 0, 2, -1>(nb, m, st, dt, s, gated);
+    case 8: return solid_stage_l<T, D, 0, 8, -1>(nb, m, st, dt, s, gated);
+    default: return solid_stage_l<T, D, 0, 4, -1>(nb, m, st, dt, s, gated);
   }
 }
 
