@@ -240,6 +240,71 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
     return info, prof
 
 
+def run_sweep(torch, B, launches=2):
+    """The batched parameter sweep: 64 strips of log-uniform size (1e3-5e4
+    particles), each with its own E and D, 10 diffusion slow steps x 200
+    inner steps, forward and reverse recorded as one hipGraph and launched
+    whole; per-specimen gradients of the mid-span top deflection."""
+    import numpy as np
+    from paper_2309_04010_amd import cases
+    bt = cases.batch(cases.strips_sweep(64))
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    t0 = time.perf_counter()
+    nb = B.sph_build_neighbors_batched(dev(bt.X), dev(bt.V), bt.h, dev(bt.spec))
+    t_build = time.perf_counter() - t0
+    perm = nb.host("perm").astype(np.int64)
+    prec = B.SPH_F32
+    st = B.new_state(nb, prec, with_diffusion=True)
+    st.flags = dev(bt.flags[perm])
+    c0 = dev(bt.c_init[perm]).float()
+    grad = torch.zeros((len(bt.cases), B.SPH_NGRAD), dtype=torch.float64, device="cuda")
+    batch = B.SphBatch(bt.E, bt.D, bt.dt_s, bt.dt_slow, grad=grad)
+    run = dict(bt.run)
+    cfg = B.multirate_cfg(**run, batch=batch)
+    mat = B.material(**bt.material)
+    tape = B.SphTape(nb, prec, run["n_slow"], run["fixed_inner"], with_diffusion=True)
+    adj = B.new_adjoint(nb, prec, with_diffusion=True)
+    # objective: mid-span top deflection of every strip
+    w = torch.zeros((2, bt.n), dtype=torch.float64, device="cuda")
+    inv = np.argsort(perm)
+    for i, c in enumerate(bt.cases):
+        j = bt.offsets[i] + c.observable["J_index"]
+        w[1, torch.as_tensor(inv[j]).cuda()] = 1.0 / len(j)
+    B.sph_autotune(nb, mat, st, run["eta"], float(bt.dt_s.min()), with_adjoint=True)
+
+    def launch():
+        st.u.zero_()
+        st.v.zero_()
+        st.c.copy_(c0)
+        adj.zero_()
+        adj.u.copy_(w)
+        grad.zero_()
+        return B.sph_advance_multirate_graph(nb, mat, st, cfg, tape, adj)
+
+    t0 = time.perf_counter()
+    launch()                                  # records and instantiates the graph
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(launches):
+        k = launch()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / launches
+    P = nb.info.n_pairs
+    inner = int(np.sum(k))
+    g = grad.cpu().numpy()
+    out = dict(workload=f"64 strips, {bt.n} particles in total ({int(np.diff(bt.offsets).min())}.."
+                        f"{int(np.diff(bt.offsets).max())} per strip), {P} directed pairs, "
+                        f"{run['n_slow']} slow x {run['fixed_inner']} inner steps, forward + reverse, FP32",
+               value=P * inner / t, unit="interactions/s (forward inner steps / forward+reverse time)",
+               seconds_per_launch=t, seconds_first_launch_incl_recording=t_first,
+               build_seconds=t_build,
+               dJ_dE_first3=g[:3, B.SPH_GRAD_E].tolist(), dJ_dD_first3=g[:3, B.SPH_GRAD_D].tolist(),
+               grad_finite=bool(np.isfinite(g).all()))
+    nb.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +314,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nx", type=int, default=500)
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -330,6 +396,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    sweep = None
+    if not args.no_sweep:
+        sweep = run_sweep(torch, B)
+        print(f"[bench] batched sweep done: {sweep['seconds_per_launch']:.3f} s per launch", flush=True)
+
     cpu = None if args.no_cpu else cpu_baseline(case)
     out = {
         "metric": "inner-step particle-interactions/s FP32+adjoint vs FP64 plain; %HBM roofline",
@@ -358,6 +429,7 @@ def main():
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
         "accuracy": accuracy,
+        "batched_sweep": sweep,
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,
