@@ -771,8 +771,10 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
       td.window = (uint32_t)w;
       return w;
     };
-    for (int64_t z = 0; z < nc2; ++z)
-      for (int64_t y = 0; y < nc1; ++y) {
+    // rows in (y, z) order: the z-neighbour rows a tile's window needs were
+    // just staged by the previous rows' tiles, so they are still in L2
+    for (int64_t y = 0; y < nc1; ++y)
+      for (int64_t z = 0; z < nc2; ++z) {
         int64_t x = 0;
         while (x < nc0) {
           int64_t cnt = ccount(x, y, z);
