@@ -198,7 +198,9 @@ int sph_solid_relax_step(const sph_nbr* nbr, const sph_material* mat, const sph_
  *   v_a += m_b delta, v_b -= m_a delta,
  * with a fixed particle acting as infinite mass.  Pairs of one level of one
  * anchor are disjoint and anchors of one colour touch disjoint particles, so
- * the parallel sweep equals the sequential canonical order.  Asynchronous. */
+ * the parallel sweep equals the sequential canonical order.  The per-pair
+ * coefficients are recomputed by every call (a multi-time-step run computes
+ * them once); calls on one handle must not overlap.  Asynchronous. */
 int sph_damping_sweep(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
                       double eta, double dt_s, void* stream);
 
@@ -398,21 +400,22 @@ int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, con
 
 /* ------------------------------------------------------------------------
  * Launch shapes.  The tiled gather kernels split each particle's neighbour
- * list over 1, 2, 4 or 8 lanes; the damping pass gives each anchor 16, 32 or
- * 64 lanes.  The fastest choice depends on the particle set and precision.
+ * list over 1, 2, 4 or 8 lanes; the damping pass gives each anchor 8, 16, 32
+ * or 64 lanes.  The fastest choice depends on the particle set and precision.
  * sph_autotune times every candidate on this handle's data (HIP events, a
  * few launches each, on scratch copies of v, PB and the J2 state: st is not
  * modified) and keeps the fastest for st->prec; later launches use them.
  * with_adjoint also tunes the reverse kernels.  eta and dt_s are those of the
  * runs to come.  Synchronous; allocates scratch for its own duration.
  * sph_set_tuning / sph_get_tuning write and read the choices directly
- * (damp_lanes 0 = automatic by LDS size). */
+ * (damp_lanes 0 = automatic: 16, widened while a wavefront's anchors would
+ * exceed the LDS). */
 typedef struct {
   int32_t lpp_stress;      /* 1, 2, 4 */
   int32_t lpp_momentum;    /* 2, 4, 8 */
   int32_t lpp_adj_stress;  /* 1, 2, 4 */
   int32_t lpp_adj_gather;  /* 2, 4, 8 */
-  int32_t damp_lanes[8];   /* per colour: 0, 16, 32, 64 */
+  int32_t damp_lanes[8];   /* per colour: 0, 8, 16, 32, 64 */
   double ms_solid, ms_adjoint, ms_damping_sweep; /* out: best times of sph_autotune */
 } sph_tuning;
 int sph_autotune(sph_nbr* nbr, const sph_material* mat, const sph_state* st, double eta,

@@ -716,6 +716,62 @@ __global__ void k_lev_fill(const int64_t* __restrict__ aoff, const uint32_t* __r
   dloff[b + prev + 1] = (uint16_t)(hi - lo);
 }
 
+// Rows of the damping sweep for one lane-group width G: the pairs of each
+// level in consecutive chunks of at most G (a level's pairs share no
+// particle, so splitting it keeps the result).  A row word is
+// first | end << 16, relative to the anchor's first pair; an empty row is 0.
+// Each anchor's list is padded with empty rows to the longest list of its
+// wavefront (64 / G consecutive anchors of its colour) and framed by
+// kDampRowPad empty rows on either side, so that the sweep reads rows ahead
+// in either direction without bounds tests.
+__global__ void k_rows_count(const uint32_t* __restrict__ anlev, const uint16_t* __restrict__ dloff,
+                             const uint32_t* __restrict__ dloff_base, int64_t n_anchors, int G,
+                             int64_t* __restrict__ cnt) {
+  const int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (ai >= n_anchors) return;
+  const uint16_t* lo = dloff + dloff_base[ai];
+  const int nl = (int)anlev[ai];
+  int64_t r = 0;
+  for (int L = 0; L < nl; ++L) r += ((int)lo[L + 1] - (int)lo[L] + G - 1) / G;
+  cnt[ai] = r;
+}
+
+struct ColourOffsets {
+  int64_t off[9];
+};
+
+// padded list length of every anchor: its wavefront's longest list + frames
+__global__ void k_rows_wave(const int64_t* __restrict__ cnt, ColourOffsets co, int64_t n_anchors,
+                            int apw, int64_t* __restrict__ padded) {
+  const int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (ai >= n_anchors) return;
+  int c = 0;
+  while (c < 7 && ai >= co.off[c + 1]) ++c;
+  const int64_t w0 = co.off[c] + (ai - co.off[c]) / apw * apw;
+  const int64_t w1 = w0 + apw < co.off[c + 1] ? w0 + apw : co.off[c + 1];
+  int64_t m = 0;
+  for (int64_t a = w0; a < w1; ++a) m = cnt[a] > m ? cnt[a] : m;
+  padded[ai] = m + 2 * kDampRowPad;
+}
+
+__global__ void k_rows_fill(const uint32_t* __restrict__ anlev, const uint16_t* __restrict__ dloff,
+                            const uint32_t* __restrict__ dloff_base, const int64_t* __restrict__ base,
+                            int64_t n_anchors, int G, uint32_t* __restrict__ rows) {
+  const int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (ai >= n_anchors) return;
+  const uint16_t* lo = dloff + dloff_base[ai];
+  const int nl = (int)anlev[ai];
+  const int64_t b = base[ai], e = base[ai + 1];
+  int64_t j = b;
+  for (int r = 0; r < kDampRowPad; ++r) rows[j++] = 0u;
+  for (int L = 0; L < nl; ++L)
+    for (uint32_t f = lo[L]; f < lo[L + 1]; f += (uint32_t)G) {
+      const uint32_t en = f + (uint32_t)G < lo[L + 1] ? f + (uint32_t)G : lo[L + 1];
+      rows[j++] = f | (en << 16);
+    }
+  while (j < e) rows[j++] = 0u;
+}
+
 // host planning of row tiles (setup only)
 // Tiles grow along a row while the window stays within `wmax` (the LDS
 // budget that keeps two workgroups per CU); a single cell may exceed it up
@@ -823,9 +879,13 @@ static void free_nbr(sph_nbr* h) {
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (void* p : {(void*)h->spec, (void*)h->spec_off_dev, (void*)h->bt32, (void*)h->bt64,
-                  (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg, h->dq[0], h->dq[1],
+                  (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg, h->dwq[0], h->dwq[1],
                   h->imass[0], h->imass[1]})
     if (p) hipFree(p);
+  for (int gi = 0; gi < kDampWidths; ++gi) {
+    if (h->drow[gi]) hipFree(h->drow[gi]);
+    if (h->drow_base[gi]) hipFree(h->drow_base[gi]);
+  }
   free_graph_cache(h);
   if (h->ctrl_host) hipHostFree(h->ctrl_host);
   if (h->prof) {
@@ -1119,9 +1179,8 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
       nb->damp_block_max = std::max(nb->damp_block_max, nb->damp_bmax[c]);
       nb->damp_pairs_max = std::max(nb->damp_pairs_max, nb->damp_pmax[c]);
     }
-    // LDS of one anchor in the FP64 sweep: block (v, inverse mass) and pairs
-    // (word, coefficient), plus the level offsets
-    const int64_t need = nb->damp_block_max * (4 * 8) + nb->damp_pairs_max * 16;
+    // LDS of one anchor in the FP64 sweep: its block (v, inverse mass)
+    const int64_t need = nb->damp_block_max * (4 * 8);
     if (need > kDampLdsBudget || nb->damp_pairs_max > 65535) {
       set_error("an anchor block needs %lld B of LDS for the damping sweep (limit %lld): "
                 "neighbourhoods this dense are not supported", (long long)need,
@@ -1147,6 +1206,50 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
       k_lev_fill<<<nblocks(base, 64), 64, 0, s>>>(nb->aoff, nb->slev, lbase, base, nb->dloff,
                                                   nb->dloff_base);
       SPH_LAUNCH_CHECK();
+    }
+    // rows of every lane-group width; after the last list, empty rows twice
+    // as many as the longest list holds (read, from its middle, by the unused
+    // lane groups of a colour's last wavefront)
+    ColourOffsets co;
+    for (int c = 0; c < 9; ++c) co.off[c] = nb->color_off[c];
+    int64_t* lpad = nullptr;
+    if ((rc_ = dalloc(&lpad, base + 1))) return rc_;
+    std::vector<int64_t> hpad(base);
+    for (int gi = 0; gi < kDampWidths; ++gi) {
+      const int G = 8 << gi;
+      if (base > 0) {
+        k_rows_count<<<nblocks(base, 256), 256, 0, s>>>(nb->anlev, nb->dloff, nb->dloff_base, base, G,
+                                                        lcnt);
+        SPH_LAUNCH_CHECK();
+        k_rows_wave<<<nblocks(base, 256), 256, 0, s>>>(lcnt, co, base, 64 / G, lpad);
+        SPH_LAUNCH_CHECK();
+      }
+      if ((rc_ = dalloc(&nb->drow_base[gi], base + 1))) return rc_;
+      if ((rc_ = scan_exclusive(lpad, nb->drow_base[gi], base, nb->drow_base[gi] + base, s)))
+        return rc_;
+      int64_t nrows = 0;
+      SPH_HIP(hipMemcpyAsync(&nrows, nb->drow_base[gi] + base, sizeof(int64_t), hipMemcpyDeviceToHost,
+                             s));
+      if (base > 0)
+        SPH_HIP(hipMemcpyAsync(hpad.data(), lpad, base * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      SPH_HIP(hipStreamSynchronize(s));
+      int64_t longest = 2 * kDampRowPad;
+      for (int64_t a = 0; a < base; ++a) longest = std::max(longest, hpad[a]);
+      nb->drow_empty[gi] = nrows + longest;
+      if ((rc_ = dalloc(&nb->drow[gi], nrows + 2 * longest))) return rc_;
+      SPH_HIP(hipMemsetAsync(nb->drow[gi] + nrows, 0, 2 * longest * sizeof(uint32_t), s));
+      if (base > 0) {
+        k_rows_fill<<<nblocks(base, 64), 64, 0, s>>>(nb->anlev, nb->dloff, nb->dloff_base,
+                                                     nb->drow_base[gi], base, G, nb->drow[gi]);
+        SPH_LAUNCH_CHECK();
+      }
+    }
+    SPH_HIP(hipStreamSynchronize(s));
+    hipFree(lpad);
+    // first pair of every colour
+    for (int c = 0; c < 9; ++c) {
+      const int64_t a = std::min<int64_t>(nb->color_off[c], base);
+      SPH_HIP(hipMemcpy(&nb->damp_pair_off[c], nb->aoff + a, sizeof(int64_t), hipMemcpyDeviceToHost));
     }
     SPH_HIP(hipStreamSynchronize(s));
     hipFree(lcnt);
@@ -1203,8 +1306,10 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   SPH_HIP(hipHostMalloc((void**)&nb->ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
   SPH_HIP(hipMalloc(&nb->ke_partial, kKeMaxBlocks * sizeof(double)));
   // per-run damping coefficients
-  SPH_HIP(hipMalloc(&nb->dq[SPH_F32], std::max<int64_t>(nb->n_upairs, 1) * sizeof(float)));
-  SPH_HIP(hipMalloc(&nb->dq[SPH_F64], std::max<int64_t>(nb->n_upairs, 1) * sizeof(double)));
+  // (pair word, q) records, 8 B in FP32, 16 B (word, pad, q) in FP64, and a
+  // sentinel record after the last pair
+  SPH_HIP(hipMalloc(&nb->dwq[SPH_F32], (nb->n_upairs + 1) * 8));
+  SPH_HIP(hipMalloc(&nb->dwq[SPH_F64], (nb->n_upairs + 1) * 16));
   SPH_HIP(hipMalloc(&nb->imass[SPH_F32], std::max<int64_t>(n, 1) * sizeof(float)));
   SPH_HIP(hipMalloc(&nb->imass[SPH_F64], std::max<int64_t>(n, 1) * sizeof(double)));
   // per-workgroup partial sums of the parameter gradients (reverse mode)

@@ -125,8 +125,10 @@ struct Tiling {
 
 // damping pair word: a_loc | b_loc << 16 (locals inside the anchor's
 // 2^d-cell block, in ascending sorted order); each anchor's level offsets sit
-// in dloff
+// in dloff, its rows for lane-group width 8 << i in drow[i]
 constexpr int kDampLocBits = 16;
+constexpr int kDampWidths = 4;          // lane-group widths 8, 16, 32, 64
+constexpr int kDampRowPad = 48;         // empty rows framing each anchor's row list
 constexpr int kDampMaxLocal = 1 << kDampLocBits;
 constexpr int kDampMaxLevel = 255;      // levels of one anchor (offsets held in 4 registers)
 constexpr int64_t kDampLdsBudget = 159 * 1024;  // gfx950: 160 KB of LDS per workgroup
@@ -167,6 +169,10 @@ struct sph_nbr {
   int64_t damp_pairs_max = 0;        // largest pair count of one anchor
   int64_t damp_bmax[8] = {0};        // the same, per colour (sizes each pass's LDS)
   int64_t damp_pmax[8] = {0};
+  uint32_t* drow[sph::kDampWidths] = {};       // rows (first | end << 16) per lane-group width
+  int64_t* drow_base[sph::kDampWidths] = {};   // [n_anchors + 1] start of each anchor's framed list
+  int64_t drow_empty[sph::kDampWidths] = {};   // middle of the empty rows after the last list
+  int64_t damp_pair_off[9] = {};               // first pair of each colour (canonical order)
   float* dgeo32 = nullptr;           // [n_upairs] 2 V_a V_b (dW/dr)/r per pair
   double* dgeo64 = nullptr;
   sph::Tiling tiling[2];             // [SPH_F32], [SPH_F64]
@@ -193,7 +199,7 @@ struct sph_nbr {
   double* gdiff = nullptr;           // [2][n] per-particle diffusion-gradient partials (batched)
   mutable bool bat_on = false;
   // per-run damping coefficients (k_damp_prep), [SPH_F32] float / [SPH_F64] double
-  void* dq[2] = {nullptr, nullptr};     // [n_upairs] q of every pair
+  void* dwq[2] = {nullptr, nullptr};    // [n_upairs] PairQ: pair word and q of every pair
   void* imass[2] = {nullptr, nullptr};  // [n] inverse mass (0 for fixed particles)
   mutable bool damp_pre = false;        // set by the driver while they are valid
   void* graph_cache = nullptr;       // instantiated whole-run graph (sph_advance_multirate_graph)

@@ -251,186 +251,151 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
   }
 }
 
-// damping: one wavefront per anchor of one colour.  The implicit update of
-// one pair, with inverse masses i_a, i_b (zero for a fixed particle, which
-// then acts as infinite mass) and beta = eta dt g_ab <= 0, g_ab = 2 V_a V_b
-// (dW/dr)/r (precomputed per pair):
+// damping: anchors of one colour, G lanes per anchor, 64 / G anchors per
+// wavefront (one workgroup).  The implicit update of one pair, with inverse
+// masses i_a, i_b (zero for a fixed particle, which then acts as infinite
+// mass) and beta = eta dt g_ab <= 0, g_ab = 2 V_a V_b (dW/dr)/r:
 //   v_ab' = v_ab / (1 - beta (i_a + i_b)),  v_a += beta i_a v_ab',  v_b -= beta i_b v_ab',
 // i.e. v_a += i_a q (v_a - v_b), v_b -= i_b q (v_a - v_b) with
-// q = beta / (1 - beta (i_a + i_b)).  The anchor's 2^d-cell block lives in
-// LDS as one 4-vector per particle (velocity, inverse mass) and its pairs as
-// (pair word, q); the level offsets sit in registers.  Levels run in order,
-// the pairs of one level in parallel (they share no particle): two 4-vector
-// reads and writes per pair on the serial path.  The block is written back
-// at the end; anchors of one colour touch disjoint blocks.
-
-// G lanes per anchor, 64 / G anchors per wavefront (one workgroup): the
-// lane groups run their anchors side by side, so every LDS instruction of
-// the serial level loop serves several anchors.
-// REV: the transposed sweep used by the reverse pass: levels in reverse order
+// q = beta / (1 - beta (i_a + i_b)), precomputed per run with i_a, i_b.
+//
+// The anchor's 2^d-cell block lives in LDS as one 4-vector per particle
+// (velocity, inverse mass).  A row is a level of the schedule, or a chunk of
+// at most G of its pairs; its pairs share no particle and run on the group's
+// lanes in parallel, the rows in order.  Row words and (pair word, q) records
+// stream from memory through two register rings (the row word 2K steps
+// ahead, the record K steps ahead), so the serial row loop has one LDS round
+// trip per row and the LDS holds only the blocks: many wavefronts share a
+// CU.  The row lists of one wavefront's anchors are padded to one length and
+// framed by empty rows, so the ring reads need no bounds tests; a record is
+// addressed by a 32-bit offset from the colour's first pair, and a pair word
+// holds the two particles' LDS byte offsets.  One wavefront: its LDS
+// accesses complete in issue order, so a row reads what the previous row
+// wrote without a barrier.  The block is written back at the end; anchors
+// of one colour touch disjoint blocks.
+//
+// REV: the transposed sweep used by the reverse pass: rows in reverse order
 // and the transposed pair map  s = q (i_a w_a - i_b w_b),  w_a += s,  w_b -= s.
+constexpr uint32_t kNoPair = 0xFFFFFFFFu;  // the record after the last pair holds (kNoPair, 0)
+
 template <typename T, int D, int G, bool REV>
-__global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restrict__ dpair,
-                                             const T* __restrict__ dgeo,
-                                             const uint16_t* __restrict__ dloff,
-                                             const uint32_t* __restrict__ dloff_base,
-                                             const uint32_t* __restrict__ anlev,
+__global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c, uint32_t sent,
+                                             int64_t pair_off_c, const T* __restrict__ imass,
+                                             const uint32_t* __restrict__ rows,
+                                             const int64_t* __restrict__ rbase, int64_t empty_mid,
                                              const int64_t* __restrict__ aoff,
                                              const uint32_t* __restrict__ ablk, int64_t a_begin,
-                                             int64_t a_end, int bmax, int pmax, int lmax, T* v,
-                                             const uint8_t* __restrict__ flags, T inv_rho0,
-                                             T eta_dt, Ctrl* ctrl, bool gated, Bat bt,
-                                             const T* __restrict__ dq,
-                                             const T* __restrict__ imass) {
+                                             int64_t a_end, int bmax, int64_t n, T* v, Ctrl* ctrl,
+                                             bool gated) {
   if (gated && ctrl->done) return;
   constexpr int APW = 64 / G;
+  constexpr int K = sizeof(T) == 4 ? 16 : 8;  // steps of records in flight
+  // the last pass of the step loop runs up to K - 1 steps past the list and
+  // reads row words 2K steps ahead: every row read stays within the frames
+  static_assert(3 * K <= kDampRowPad, "row frames too short for the ring");
+  constexpr int SB = 8;  // block particles per lane in flight while staging
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int grp = threadIdx.x / G, lg = threadIdx.x % G;
-  const size_t per = (size_t)bmax * sizeof(vec4<T>) + (size_t)pmax * sizeof(PairQ<T>) +
-                     (size_t)((lmax + 2) & ~1) * 2;
-  unsigned char* base_g = smem_raw + grp * ((per + 15) & ~(size_t)15);
-  vec4<T>* sv = reinterpret_cast<vec4<T>*>(base_g);           // [bmax] (v, inverse mass)
-  PairQ<T>* sp = reinterpret_cast<PairQ<T>*>(sv + bmax);      // [pmax]
-  uint16_t* so = reinterpret_cast<uint16_t*>(sp + pmax);      // [lmax + 1] level offsets
-  const int64_t n = g.n;
+  const size_t per = ((size_t)bmax * sizeof(vec4<T>) + 15) & ~(size_t)15;
+  unsigned char* svb = smem_raw + grp * per;  // [bmax] (v, inverse mass), by byte offset
+  vec4<T>* sv = reinterpret_cast<vec4<T>*>(svb);
   const int64_t ai = a_begin + (int64_t)blockIdx.x * APW + grp;
   const bool live = ai < a_end;
-  uint32_t nblk = 0, e0 = 0, e1 = 0, e2 = 0;
-  const uint32_t* bl = ablk + 8 * (live ? ai : a_begin);
+  uint32_t b0 = 0, b2 = 0, b4 = 0, b6 = 0, e0 = 0, e1 = 0, e2 = 0, nblk = 0, lo_rel = 0;
+  const uint32_t* rp = rows + empty_mid;  // row of step 0; then forward, or backward in REV
+  int nrw = 0;
   if (live) {
+    const uint32_t* bl = ablk + 8 * ai;
+    b0 = bl[0];
+    b2 = bl[2];
+    b4 = bl[4];
+    b6 = bl[6];
     e0 = bl[1];
     e1 = e0 + bl[3];
     e2 = e1 + bl[5];
     nblk = e2 + bl[7];
+    lo_rel = (uint32_t)(aoff[ai] - pair_off_c);
+    const int64_t rb = rbase[ai];
+    nrw = (int)(rbase[ai + 1] - rb) - 2 * kDampRowPad;
+    rp = rows + rb + kDampRowPad + (REV ? nrw - 1 : 0);
+  }
+  auto row = [&](const uint32_t* p, int k) -> uint32_t { return REV ? p[-k] : p[k]; };
+  // this lane's record in a row (the sentinel when the lane has no pair there)
+  const unsigned char* dwqb = reinterpret_cast<const unsigned char*>(dwq_c);
+  auto rec = [&](uint32_t rw) -> PairQ<T> {
+    const uint32_t i = (rw & 0xFFFFu) + (uint32_t)lg;
+    const uint32_t idx = i < (rw >> 16) ? lo_rel + i : sent;
+    return *reinterpret_cast<const PairQ<T>*>(dwqb + (size_t)(idx * (uint32_t)sizeof(PairQ<T>)));
+  };
+  uint32_t rwr[K];
+  PairQ<T> ring[K];
+  {
+    uint32_t rw0[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) rw0[k] = row(rp, k);
+#pragma unroll
+    for (int k = 0; k < K; ++k) rwr[k] = row(rp, K + k);
+#pragma unroll
+    for (int k = 0; k < K; ++k) ring[k] = rec(rw0[k]);
   }
   auto gidx = [&](uint32_t l) -> int64_t {
-    return l < e0 ? (int64_t)bl[0] + l
-                  : (l < e1 ? (int64_t)bl[2] + (l - e0)
-                            : (l < e2 ? (int64_t)bl[4] + (l - e1) : (int64_t)bl[6] + (l - e2)));
+    return l < e0 ? (int64_t)b0 + l
+                  : (l < e1 ? (int64_t)b2 + (l - e0)
+                            : (l < e2 ? (int64_t)b4 + (l - e1) : (int64_t)b6 + (l - e2)));
   };
-  for (uint32_t l0 = lg; l0 < nblk; l0 += 2 * G) {
-    vec4<T> x[2];
-    const uint32_t ls[2] = {l0, l0 + G};
+  // stage the block (loads clamped to valid entries)
+  for (uint32_t l0 = lg; l0 < nblk; l0 += SB * G) {
+    vec4<T> x[SB];
 #pragma unroll
-    for (int e = 0; e < 2; ++e)
-      if (ls[e] < nblk) {
-        const int64_t gi = gidx(ls[e]);
-        x[e].x = v[gi];
-        x[e].y = v[n + gi];
-        x[e].z = D == 3 ? v[2 * n + gi] : T(0);
-        if (imass) {
-          x[e].w = imass[gi];
+    for (int e = 0; e < SB; ++e) {
+      const uint32_t l = l0 + e * G;
+      const int64_t gi = gidx(l < nblk ? l : l0);
+      x[e].x = v[gi];
+      x[e].y = v[n + gi];
+      x[e].z = D == 3 ? v[2 * n + gi] : T(0);
+      x[e].w = imass[gi];
+    }
+#pragma unroll
+    for (int e = 0; e < SB; ++e)
+      if (l0 + e * G < nblk) sv[l0 + e * G] = x[e];
+  }
+  __syncthreads();
+  for (int t0 = 0; __any(t0 < nrw); t0 += K) {
+    const uint32_t* pi = REV ? rp - t0 : rp + t0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const PairQ<T> pq = ring[k];
+      if (pq.w != kNoPair) {
+        vec4<T>* pa = reinterpret_cast<vec4<T>*>(svb + (pq.w & 0xFFFFu));
+        vec4<T>* pb = reinterpret_cast<vec4<T>*>(svb + (pq.w >> 16));
+        vec4<T> va = *pa, vb = *pb;
+        const T ka = va.w * pq.q, kb = vb.w * pq.q;
+        if constexpr (!REV) {
+          const T dx = va.x - vb.x, dy = va.y - vb.y, dz = va.z - vb.z;
+          va.x += ka * dx;
+          va.y += ka * dy;
+          va.z += ka * dz;
+          vb.x -= kb * dx;
+          vb.y -= kb * dy;
+          vb.z -= kb * dz;
         } else {
-          const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
-          x[e].w = fixed ? T(0) : inv_rho0 / g.V[gi];
+          const T sx = ka * va.x - kb * vb.x, sy = ka * va.y - kb * vb.y,
+                  sz = ka * va.z - kb * vb.z;
+          va.x += sx;
+          va.y += sy;
+          va.z += sz;
+          vb.x -= sx;
+          vb.y -= sy;
+          vb.z -= sz;
         }
+        *pa = va;
+        *pb = vb;
       }
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-      if (ls[e] < nblk) sv[ls[e]] = x[e];
-  }
-  int64_t lo = 0;
-  int np = 0, nlev = 0;
-  if (live) {
-    lo = aoff[ai];
-    np = (int)(aoff[ai + 1] - lo);
-    nlev = (int)anlev[ai];
-    // batched: every pair of an anchor belongs to the specimen of its first pair
-    if (bt.spec && np > 0) eta_dt = bt.get<T>(BT_ETADT, bt.spec[gidx(dpair[lo] & 0xFFFFu)]);
-    const uint16_t* lof = dloff + dloff_base[ai];
-    for (int L = lg; L <= nlev; L += G) so[L] = lof[L];
-  }
-  __syncthreads();
-  // pair words and coefficients: copied when the run precomputed them
-  for (int i0 = lg; dq && i0 < np; i0 += 4 * G) {
-    uint32_t w[4];
-    T qq[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + G * u;
-      if (i < np) {
-        w[u] = dpair[lo + i];
-        qq[u] = dq[lo + i];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + G * u;
-      if (i < np) {
-        PairQ<T> pq;
-        pq.w = w[u];
-        pq.q = qq[u];
-        sp[i] = pq;
-      }
-    }
-  }
-  for (int i0 = lg; !dq && i0 < np; i0 += 4 * G) {
-    uint32_t w[4];
-    T gg[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + G * u;
-      if (i < np) {
-        w[u] = dpair[lo + i];
-        gg[u] = dgeo[lo + i];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + G * u;
-      if (i < np) {
-        const T beta = eta_dt * gg[u];
-        PairQ<T> pq;
-        pq.w = w[u];
-        pq.q = beta / (T(1) - beta * (sv[w[u] & 0xFFFFu].w + sv[w[u] >> 16].w));
-        sp[i] = pq;
-      }
-    }
-  }
-  __syncthreads();
-  if constexpr (!REV) {
-    int hi = nlev > 0 ? so[0] : 0;
-    for (int L = 0; L < nlev; ++L) {
-      const int lo_l = hi;
-      hi = so[L + 1];
-      for (int i = lo_l + lg; i < hi; i += G) {
-        const PairQ<T> pq = sp[i];
-        const int a = pq.w & 0xFFFFu, b = pq.w >> 16;
-        vec4<T> va = sv[a], vb = sv[b];
-        const T ka = va.w * pq.q, kb = vb.w * pq.q;
-        const T dx = va.x - vb.x, dy = va.y - vb.y, dz = va.z - vb.z;
-        va.x += ka * dx;
-        va.y += ka * dy;
-        va.z += ka * dz;
-        vb.x -= kb * dx;
-        vb.y -= kb * dy;
-        vb.z -= kb * dz;
-        sv[a] = va;
-        sv[b] = vb;
-      }
-      // one wavefront: its LDS accesses complete in issue order, so the next
-      // level reads what this one wrote without a barrier
-    }
-  } else {
-    int lo = nlev > 0 ? so[nlev] : 0;
-    for (int L = nlev - 1; L >= 0; --L) {
-      const int hi_l = lo;
-      lo = so[L];
-      for (int i = lo + lg; i < hi_l; i += G) {
-        const PairQ<T> pq = sp[i];
-        const int a = pq.w & 0xFFFFu, b = pq.w >> 16;
-        vec4<T> va = sv[a], vb = sv[b];
-        const T ka = va.w * pq.q, kb = vb.w * pq.q;
-        const T sx = ka * va.x - kb * vb.x, sy = ka * va.y - kb * vb.y, sz = ka * va.z - kb * vb.z;
-        va.x += sx;
-        va.y += sy;
-        va.z += sz;
-        vb.x -= sx;
-        vb.y -= sy;
-        vb.z -= sz;
-        sv[a] = va;
-        sv[b] = vb;
-      }
+      // refill after the record's last use, into the same registers (a
+      // copy would have to wait for the load); rwr[k] holds the row word of
+      // step t0 + k + K
+      ring[k] = rec(rwr[k]);
+      rwr[k] = row(pi, k + 2 * K);
     }
   }
   __syncthreads();
@@ -445,25 +410,36 @@ __global__ __launch_bounds__(64) void k_damp(Geo<T> g, const uint32_t* __restric
 
 // Per-run damping coefficients: q of every pair and the inverse mass of
 // every particle depend only on eta dt, rho0, the volumes and the flags,
-// which a multi-time-step run holds fixed, so the run computes them once
-// (the same operations, in the same types, as the sweep's own prologue).
+// which a multi-time-step run holds fixed, so they are computed once per run
+// (or per call of a lone sweep) and stored beside the pair words.
 template <typename T>
 __global__ void k_damp_prep(int64_t n_upairs, int64_t n, const uint32_t* __restrict__ sa,
-                            const uint32_t* __restrict__ sb, const T* __restrict__ dgeo,
-                            const T* __restrict__ V, const uint8_t* __restrict__ flags,
-                            T inv_rho0, T eta_dt, Bat bt, T* __restrict__ dq,
-                            T* __restrict__ imass) {
+                            const uint32_t* __restrict__ sb, const uint32_t* __restrict__ dpair,
+                            const T* __restrict__ dgeo, const T* __restrict__ V,
+                            const uint8_t* __restrict__ flags, T inv_rho0, T eta_dt, Bat bt,
+                            PairQ<T>* __restrict__ dwq, T* __restrict__ imass) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   auto im = [&](int64_t a) -> T {
     const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
     return fixed ? T(0) : inv_rho0 / V[a];
   };
   if (i < n) imass[i] = im(i);
+  if (i == n_upairs) {
+    PairQ<T> none{};
+    none.w = 0xFFFFFFFFu;
+    dwq[i] = none;
+  }
   if (i >= n_upairs) return;
   const uint32_t a = sa[i], b = sb[i];
   const T edt = bt.spec ? bt.get<T>(BT_ETADT, bt.spec[a]) : eta_dt;
   const T beta = edt * dgeo[i];
-  dq[i] = beta / (T(1) - beta * (im(a) + im(b)));
+  // the pair word as the two particles' byte offsets in the sweep's LDS block
+  constexpr uint32_t S = sizeof(vec4<T>);
+  const uint32_t w = dpair[i];
+  PairQ<T> pq{};
+  pq.w = ((w & 0xFFFFu) * S) | (((w >> 16) * S) << 16);
+  pq.q = beta / (T(1) - beta * (im(a) + im(b)));
+  dwq[i] = pq;
 }
 
 // drift + kinetic energy: every block writes its partial E_k (fixed-order
@@ -740,70 +716,85 @@ int solid_stage(const sph_nbr* nb, const sph_material* m, const sph_state* st, d
                       : solid_stage_t<float, 3>(nb, m, st, dt, s, gated);
 }
 
+template <int G>
+constexpr int damp_width_index() {
+  return G == 8 ? 0 : (G == 16 ? 1 : (G == 32 ? 2 : 3));
+}
+
+template <typename T>
+static size_t damp_lds_per_anchor(const sph_nbr* nb, int col) {
+  const size_t bmax = (size_t)std::max<int64_t>(nb->damp_bmax[col], 1);
+  return (bmax * sizeof(vec4<T>) + 15) & ~(size_t)15;
+}
+
 template <typename T, int D, int G, bool REV>
-static int damp_launch(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
-                       double dt, hipStream_t s, bool gated, int col) {
-  Geo<T> g = geo<T>(nb);
-  const T* dgeo = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)nb->dgeo64
-                                                           : (const void*)nb->dgeo32);
-  constexpr int APW = 64 / G;
+static int damp_launch(const sph_nbr* nb, const sph_state* st, hipStream_t s, bool gated,
+                       int col) {
+  constexpr int APW = 64 / G, gi = damp_width_index<G>();
   const int64_t a0 = nb->color_off[col], a1 = nb->color_off[col + 1];
   const int bmax = (int)std::max<int64_t>(nb->damp_bmax[col], 1);
-  const int pmax = (int)std::max<int64_t>(nb->damp_pmax[col], 1);
-  const int lmax = (int)std::max<int64_t>(nb->max_level, 1);
-  const size_t per = (size_t)bmax * sizeof(vec4<T>) + (size_t)pmax * sizeof(PairQ<T>) +
-                     (size_t)((lmax + 2) & ~1) * 2;
-  const size_t lds = APW * ((per + 15) & ~(size_t)15);
+  const size_t lds = APW * damp_lds_per_anchor<T>(nb, col);
   int rc = lds_attr(k_damp<T, D, G, REV>, lds);
   if (rc) return rc;
   const unsigned grid = (unsigned)((a1 - a0 + APW - 1) / APW);
+  const int p = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  const int64_t po = nb->damp_pair_off[col];
   hipEvent_t pe_ = prof_begin(nb, s);
-  k_damp<T, D, G, REV><<<grid, 64, lds, s>>>(g, nb->dpair, dgeo, nb->dloff, nb->dloff_base, nb->anlev,
-                                        nb->aoff, nb->ablk, a0, a1, bmax, pmax, lmax, (T*)st->v,
-                                        st->flags, (T)(1.0 / m->rho0), (T)(eta * dt), nb->ctrl,
-                                        gated, bat_view(nb),
-                                        nb->damp_pre ? (const T*)nb->dq[sizeof(T) == 8] : nullptr,
-                                        nb->damp_pre ? (const T*)nb->imass[sizeof(T) == 8] : nullptr);
+  k_damp<T, D, G, REV><<<grid, 64, lds, s>>>(
+      (const PairQ<T>*)nb->dwq[p] + po, (uint32_t)(nb->n_upairs - po), po, (const T*)nb->imass[p],
+      nb->drow[gi], nb->drow_base[gi], nb->drow_empty[gi], nb->aoff, nb->ablk, a0, a1, bmax,
+      nb->n, (T*)st->v, nb->ctrl, gated);
   prof_end(nb, REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING, pe_, s);
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
 
-#ifndef SPH_DAMP_LANES
-#define SPH_DAMP_LANES 32  // measured on the 1M-particle plate: 32 beats 16 and 64
-#endif
-
 template <typename T>
-static size_t damp_lds_per_anchor(const sph_nbr* nb, int col) {
-  const size_t bmax = (size_t)std::max<int64_t>(nb->damp_bmax[col], 1);
-  const size_t pmax = (size_t)std::max<int64_t>(nb->damp_pmax[col], 1);
-  const size_t lmax = (size_t)std::max<int64_t>(nb->max_level, 1);
-  return ((bmax * sizeof(vec4<T>) + pmax * sizeof(PairQ<T>) + ((lmax + 2) & ~(size_t)1) * 2) + 15) &
-         ~(size_t)15;
+static int damp_prepare_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                          double eta, double dt, hipStream_t s) {
+  // pair words hold LDS byte offsets (16 bits), records 32-bit byte offsets
+  if ((int64_t)nb->damp_block_max * (int64_t)sizeof(vec4<T>) > 65535 ||
+      (nb->n_upairs + 1) * (int64_t)sizeof(PairQ<T>) > (int64_t)0xFFFFFFFF) {
+    set_error("damping sweep: anchor blocks of %lld particles or %lld pairs exceed its addressing",
+              (long long)nb->damp_block_max, (long long)nb->n_upairs);
+    return SPH_E_CAPACITY;
+  }
+  Geo<T> g = geo<T>(nb);
+  const T* dgeo = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)nb->dgeo64
+                                                           : (const void*)nb->dgeo32);
+  const int p = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  const int64_t m_ = std::max<int64_t>(nb->n_upairs + 1, nb->n);
+  k_damp_prep<T><<<nblk(std::max<int64_t>(m_, 1), 256), 256, 0, s>>>(
+      nb->n_upairs, nb->n, nb->sa, nb->sb, nb->dpair, dgeo, g.V, st->flags, (T)(1.0 / m->rho0),
+      (T)(eta * dt), bat_view(nb), (PairQ<T>*)nb->dwq[p], (T*)nb->imass[p]);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
 }
 
-// Lanes per anchor: the preferred group width while the wavefront's LDS
-// stays within 64 KB (so that several wavefronts share a CU), else wider
-// groups, down to one anchor per wavefront for very dense blocks.
+// Lanes per anchor of each colour pass: the tuned width (sph_autotune), else
+// 16; widened while the wavefront's LDS would exceed the budget.  Outside a
+// run (no per-run coefficients) the coefficients are computed first.
 template <typename T, int D, bool REV>
 static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
                      double dt, hipStream_t s, bool gated) {
+  int rc;
+  if (!nb->damp_pre && (rc = damp_prepare_t<T>(nb, m, st, eta, dt, s))) return rc;
   const int ncol = 1 << D;
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   for (int c_ = 0; c_ < ncol; ++c_) {
     const int col = REV ? ncol - 1 - c_ : c_;
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
-    const size_t per = damp_lds_per_anchor<T>(nb, col);
-    const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
     int want = nb->tune.damp_g[prec][col];
-    if (want == 16 && 4 * per > (size_t)kDampLdsBudget) want = 32;  // tuned width must fit
-    if (want == 32 && 2 * per > (size_t)kDampLdsBudget) want = 64;
-    int rc;
-    if (want == 16 || (want == 0 && SPH_DAMP_LANES <= 16 && 4 * per <= 64 * 1024))
-      rc = damp_launch<T, D, 16, REV>(nb, m, st, eta, dt, s, gated, col);
-    else if (want == 32 || (want == 0 && SPH_DAMP_LANES <= 32 && 2 * per <= 64 * 1024))
-      rc = damp_launch<T, D, 32, REV>(nb, m, st, eta, dt, s, gated, col);
-    else
-      rc = damp_launch<T, D, 64, REV>(nb, m, st, eta, dt, s, gated, col);
+    if (want == 0) want = 16;
+    while (want < 64 && (size_t)(64 / want) * damp_lds_per_anchor<T>(nb, col) >
+                            (size_t)kDampLdsBudget)
+      want *= 2;
+    switch (want) {
+      case 8: rc = damp_launch<T, D, 8, REV>(nb, st, s, gated, col); break;
+      case 16: rc = damp_launch<T, D, 16, REV>(nb, st, s, gated, col); break;
+      case 32: rc = damp_launch<T, D, 32, REV>(nb, st, s, gated, col); break;
+      default: rc = damp_launch<T, D, 64, REV>(nb, st, s, gated, col); break;
+    }
     if (rc) return rc;
   }
   return SPH_OK;
@@ -816,20 +807,6 @@ int damping_sweep(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                         : damping_t<double, 3, false>(nb, m, st, eta, dt, s, gated);
   return nb->dim == 2 ? damping_t<float, 2, false>(nb, m, st, eta, dt, s, gated)
                       : damping_t<float, 3, false>(nb, m, st, eta, dt, s, gated);
-}
-
-template <typename T>
-static int damp_prepare_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
-                          double eta, double dt, hipStream_t s) {
-  Geo<T> g = geo<T>(nb);
-  const T* dgeo = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)nb->dgeo64
-                                                           : (const void*)nb->dgeo32);
-  const int64_t m_ = std::max<int64_t>(nb->n_upairs, nb->n);
-  k_damp_prep<T><<<nblk(std::max<int64_t>(m_, 1), 256), 256, 0, s>>>(
-      nb->n_upairs, nb->n, nb->sa, nb->sb, dgeo, g.V, st->flags, (T)(1.0 / m->rho0),
-      (T)(eta * dt), bat_view(nb), (T*)nb->dq[sizeof(T) == 8], (T*)nb->imass[sizeof(T) == 8]);
-  SPH_LAUNCH_CHECK();
-  return SPH_OK;
 }
 
 int damp_prepare(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,

@@ -76,9 +76,9 @@ extern "C" int sph_set_tuning(sph_nbr* nb, int prec, const sph_tuning* t) {
     return SPH_E_ARG;
   }
   for (int c = 0; c < 8; ++c)
-    if (t->damp_lanes[c] != 0 && t->damp_lanes[c] != 16 && t->damp_lanes[c] != 32 &&
-        t->damp_lanes[c] != 64) {
-      set_error("damping lanes per anchor: 0 (automatic), 16, 32 or 64");
+    if (t->damp_lanes[c] != 0 && t->damp_lanes[c] != 8 && t->damp_lanes[c] != 16 &&
+        t->damp_lanes[c] != 32 && t->damp_lanes[c] != 64) {
+      set_error("damping lanes per anchor: 0 (automatic), 8, 16, 32 or 64");
       return SPH_E_ARG;
     }
   nb->tune.lpp[TUNE_STRESS][prec] = t->lpp_stress;
@@ -185,7 +185,7 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
     int best = 0;
     double bt = 1e300;
-    for (int g : {16, 32, 64}) {
+    for (int g : {8, 16, 32, 64}) {
       tn.damp_g[prec][col] = g;
       // time the whole sweep: only this colour's launch differs between candidates
       double t = 0.0;

@@ -2,7 +2,9 @@
 
 Every lanes-per-particle variant of the four tiled gather kernels and every
 damping lane-group width must give the oracle's results (FP64 1e-10, FP32
-1e-4; the reverse kernels as transposes, 1e-9 / 2e-3).  The autotuner must
+1e-4; the reverse kernels as transposes: the tiled ones equal to the default
+shape's, the damping sweep's by the dot-product identity with the oracle's
+sweep, 1e-12 / 1e-5).  The autotuner must
 leave the state untouched, choose valid shapes, and a run with them must
 still match the oracle.
 """
@@ -57,15 +59,30 @@ def test_every_forward_launch_shape_matches_oracle(oracle_mod, dim, prec):
         B.sph_solid_relax_step(nb, mg, st, dt)
         assert rel_err(host(st.PB), PBo) < TOL[prec], (ls, lm)
         assert rel_err(host(st.acc), acco) < TOL[prec], (ls, lm)
-    # damping widths, all colours alike
+    # damping widths, all colours alike, forward against the oracle and the
+    # transposed sweep against it: <wbar, S dv> = <S^T wbar, dv>
     eta = 5.0
     w = v.copy()
     o.damping_sweep(NH["rho0"], eta, dt, w, flags)
-    for g in (16, 32, 64):
+    rng = np.random.default_rng(11)
+    wbar = rng.normal(0.0, 1.0, (dim, o.n))
+    if prec == B.SPH_F32:
+        wbar = wbar.astype(np.float32).astype(np.float64)
+    dv = rng.normal(0.0, 1.0, (dim, o.n))
+    Sdv = dv.copy()
+    o.damping_sweep(NH["rho0"], eta, dt, Sdv, flags)
+    rhs = (wbar * Sdv).sum()
+    for g in (8, 16, 32, 64):
+        print(f"[tune] dim={dim} prec={prec} damping lanes {g}", flush=True)
         B.sph_set_tuning(nb, prec, damp_lanes=(g,) * 8)
         st.v.copy_(dev(v, T))
         B.sph_damping_sweep(nb, mg, st, eta, dt)
         assert rel_err(host(st.v), w) < TOL[prec], g
+        adj = B.new_adjoint(nb, prec)
+        adj.v.copy_(dev(wbar, T))
+        B.sph_damping_sweep_vjp(nb, mg, st, adj, eta, dt)
+        lhs = (host(adj.v) * dv).sum()
+        assert abs(lhs - rhs) <= (1e-12 if prec == B.SPH_F64 else 1e-5) * abs(rhs), g
     nb.close()
 
 
@@ -112,7 +129,7 @@ def test_autotune_leaves_state_and_keeps_parity(oracle_mod):
         assert (a == b).all()
     assert t.lpp_stress in (1, 2, 4) and t.lpp_momentum in (2, 4, 8)
     assert t.lpp_adj_stress in (1, 2, 4) and t.lpp_adj_gather in (2, 4, 8)
-    assert all(g in (16, 32, 64) for g in list(t.damp_lanes)[:4])
+    assert all(g in (8, 16, 32, 64) for g in list(t.damp_lanes)[:4])
     assert t.ms_solid > 0 and t.ms_damping_sweep > 0
     got = B.sph_get_tuning(nb, B.SPH_F64)
     assert got.lpp_stress == t.lpp_stress and list(got.damp_lanes) == list(t.damp_lanes)
