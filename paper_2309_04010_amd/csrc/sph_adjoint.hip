@@ -717,32 +717,34 @@ __global__ void k_adj_drift(int64_t n, const double* __restrict__ ub, T* __restr
 //   D_bar += q_bar . (-B0 s_a),  s_a = sum_b V_b (c_b - c_a) grad_a W_ab (c before the step)
 //   s_bar_a = -D B0^T q_bar,     C_bar += p_bar_a (c'_a - c0)
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_adiff_a(Geo<T> g, const T* __restrict__ cold,
-                                                 const T* __restrict__ cnew,
-                                                 const T* __restrict__ cb,
-                                                 const double* __restrict__ pbar,
-                                                 const uint8_t* __restrict__ flags, T dt, T Dc,
-                                                 T Cs, T c0, T* __restrict__ sbar,
-                                                 double* __restrict__ gpart, Bat bt,
-                                                 double* __restrict__ gdiff) {
+__global__ __launch_bounds__(kDiffBlock) void k_adiff_a(Geo<T> g, const T* __restrict__ cold,
+                                                        const T* __restrict__ cnew,
+                                                        const T* __restrict__ cb,
+                                                        const double* __restrict__ pbar,
+                                                        const uint8_t* __restrict__ flags, T dt,
+                                                        T Dc, T Cs, T c0, T* __restrict__ sbar,
+                                                        double* __restrict__ gpart, Bat bt,
+                                                        double* __restrict__ gdiff) {
+  constexpr int L = kDiffLanes;  // lanes per particle, each a strided share of its list
   const int64_t n = g.n;
-  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
+  const int h = threadIdx.x % L;
+  const bool live = a < n;  // uniform over a lane group
   double gd[2] = {0.0, 0.0};
-  if (a < n) {
-    auto cdb = [&](int64_t i) -> T {
-      if (flags && (flags[i] & SPH_FLAG_CDIR)) return T(0);
-      const T dti = bt.spec ? bt.get<T>(BT_DTD, bt.spec[i]) : dt;
-      return dti * (cb[i] + (pbar ? Cs * (T)pbar[i] : T(0)));
-    };
-    const T Da = bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc;
+  auto cdb = [&](int64_t i) -> T {
+    if (flags && (flags[i] & SPH_FLAG_CDIR)) return T(0);
+    const T dti = bt.spec ? bt.get<T>(BT_DTD, bt.spec[i]) : dt;
+    return dti * (cb[i] + (pbar ? Cs * (T)pbar[i] : T(0)));
+  };
+  T r[D], s[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) r[k] = s[k] = T(0);
+  if (live) {
     double xa[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
     const T ca = cold[a], Va = g.V[a], cda = cdb(a);
-    T r[D], s[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) r[k] = s[k] = T(0);
-    for (int64_t j = g.off[a]; j < g.off[a + 1]; ++j) {
+    for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
       const uint32_t b = g.idx[j];
       T d[D];
       T r2 = T(0);
@@ -761,6 +763,14 @@ __global__ __launch_bounds__(256) void k_adiff_a(Geo<T> g, const T* __restrict__
         s[k] += cs * d[k];
       }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    r[k] = lane_sum<L>(r[k]);
+    s[k] = lane_sum<L>(s[k]);
+  }
+  if (live && h == 0) {
+    const T Da = bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc;
     T qb[D], Bs[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -786,7 +796,7 @@ __global__ __launch_bounds__(256) void k_adiff_a(Geo<T> g, const T* __restrict__
     gd[1] = pbar ? pbar[a] * ((double)cnew[a] - (double)c0) : 0.0;
   }
   if (bt.spec) {  // batched: per-particle partials, reduced per specimen later
-    if (a < n) {
+    if (live && h == 0) {
       gdiff[a] += gd[0];
       gdiff[n + a] += gd[1];
     }
@@ -799,12 +809,14 @@ __global__ __launch_bounds__(256) void k_adiff_a(Geo<T> g, const T* __restrict__
 // second pass: c_bar_a <- (0 on Dirichlet particles, else c_bar_a + C p_bar_a)
 //   - sum_b (V_a s_bar_b + V_b s_bar_a) . grad_a W_ab;  p_bar_a <- 0
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_adiff_b(Geo<T> g, const T* __restrict__ sbar,
-                                                 T* __restrict__ cb, double* __restrict__ pbar,
-                                                 const uint8_t* __restrict__ flags, T Cs) {
+__global__ __launch_bounds__(kDiffBlock) void k_adiff_b(Geo<T> g, const T* __restrict__ sbar,
+                                                        T* __restrict__ cb, double* __restrict__ pbar,
+                                                        const uint8_t* __restrict__ flags, T Cs) {
+  constexpr int L = kDiffLanes;
   const int64_t n = g.n;
-  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (a >= n) return;
+  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
+  const int h = threadIdx.x % L;
+  if (a >= n) return;  // the whole lane group
   double xa[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
@@ -813,7 +825,7 @@ __global__ __launch_bounds__(256) void k_adiff_b(Geo<T> g, const T* __restrict__
 #pragma unroll
   for (int k = 0; k < D; ++k) sa[k] = sbar[k * n + a];
   T acc = T(0);
-  for (int64_t j = g.off[a]; j < g.off[a + 1]; ++j) {
+  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
     const uint32_t b = g.idx[j];
     T d[D];
     T r2 = T(0);
@@ -829,6 +841,8 @@ __global__ __launch_bounds__(256) void k_adiff_b(Geo<T> g, const T* __restrict__
     for (int k = 0; k < D; ++k) x += (Va * sbar[k * n + b] + Vb * sa[k]) * d[k];
     acc += w0 * x;
   }
+  acc = lane_sum<L>(acc);
+  if (h != 0) return;
   const bool dir = flags && (flags[a] & SPH_FLAG_CDIR);
   const T direct = dir ? T(0) : cb[a] + (pbar ? Cs * (T)pbar[a] : T(0));
   cb[a] = direct - acc;
@@ -992,16 +1006,16 @@ static int adj_diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_s
                            const void* c_before, const sph_adjoint* adj, double Dc, double dt,
                            hipStream_t s) {
   Geo<T> g = geo<T>(nb);
-  const unsigned gr = nblk256(nb->n);
+  const unsigned gr = nblk(nb->n, kDiffPerBlock);
   if ((int64_t)gr > nb->gpart_slots) {
     set_error("gradient partial slots too few");
     return SPH_E_CAPACITY;
   }
-  k_adiff_a<T, D><<<gr, 256, 0, s>>>(g, (const T*)c_before, (const T*)st->c, (const T*)adj->c,
+  k_adiff_a<T, D><<<gr, kDiffBlock, 0, s>>>(g, (const T*)c_before, (const T*)st->c, (const T*)adj->c,
                                      adj->p, st->flags, (T)dt, (T)Dc, (T)m->C_swell, (T)m->c0,
                                      (T*)adj->work, nb->gpart, bat_view(nb), nb->gdiff);
   SPH_LAUNCH_CHECK();
-  k_adiff_b<T, D><<<gr, 256, 0, s>>>(g, (const T*)adj->work, (T*)adj->c, adj->p, st->flags,
+  k_adiff_b<T, D><<<gr, kDiffBlock, 0, s>>>(g, (const T*)adj->work, (T*)adj->c, adj->p, st->flags,
                                      (T)m->C_swell);
   SPH_LAUNCH_CHECK();
   return SPH_OK;

@@ -1314,7 +1314,7 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   SPH_HIP(hipMalloc(&nb->imass[SPH_F64], std::max<int64_t>(n, 1) * sizeof(double)));
   // per-workgroup partial sums of the parameter gradients (reverse mode)
   {
-    int64_t slots = (n + 255) / 256;
+    int64_t slots = (n + kDiffPerBlock - 1) / kDiffPerBlock;
     for (int prec = 0; prec < 2; ++prec)
       slots = std::max<int64_t>(slots, 8 * ((nb->tiling[prec].n_tiles + 7) / 8));
     nb->gpart_slots = std::max<int64_t>(slots, 1);

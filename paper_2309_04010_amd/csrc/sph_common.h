@@ -93,6 +93,11 @@ struct Tune {
   int damp_g[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
 };
 
+// diffusion gathers (slow step and its reverse): lanes per particle, threads per block
+constexpr int kDiffLanes = 8;
+constexpr int kDiffBlock = 1024;
+constexpr int kDiffPerBlock = kDiffBlock / kDiffLanes;
+
 constexpr int kKeThreads = 256;
 constexpr int kKeItems = 4;             // particles per thread in the drift kernel
 constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (16.7M particles)

@@ -537,11 +537,13 @@ __global__ void k_load(int64_t n, double* u, const T* vgrip, const uint8_t* flag
 
 // diffusion: flux q = -D B0 sum_b V_b (c_b - c_a) grad W
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_diff_grad(Geo<T> g, const T* __restrict__ c,
-                                                   T* __restrict__ q, T Dc, Bat bt) {
+__global__ __launch_bounds__(kDiffBlock) void k_diff_grad(Geo<T> g, const T* __restrict__ c,
+                                                          T* __restrict__ q, T Dc, Bat bt) {
+  constexpr int L = kDiffLanes;  // lanes per particle, each a strided share of its list
   const int64_t n = g.n;
-  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (a >= n) return;
+  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
+  const int h = threadIdx.x % L;
+  if (a >= n) return;  // the whole lane group
   double xa[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(256) void k_diff_grad(Geo<T> g, const T* __restrict
   T s[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) s[k] = T(0);
-  for (int64_t j = g.off[a]; j < g.off[a + 1]; ++j) {
+  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
     const uint32_t b = g.idx[j];
     T d[D];
     T r2 = T(0);
@@ -563,6 +565,9 @@ __global__ __launch_bounds__(256) void k_diff_grad(Geo<T> g, const T* __restrict
     for (int k = 0; k < D; ++k) s[k] += w * d[k];
   }
 #pragma unroll
+  for (int k = 0; k < D; ++k) s[k] = lane_sum<L>(s[k]);
+  if (h != 0) return;
+#pragma unroll
   for (int i = 0; i < D; ++i) {
     T acc = T(0);
 #pragma unroll
@@ -573,12 +578,14 @@ __global__ __launch_bounds__(256) void k_diff_grad(Geo<T> g, const T* __restrict
 
 // c += dt (-sum_b V_b (B0_a q_a + B0_b q_b) . grad W); Dirichlet; p = C (c - c0)
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_diff_div(Geo<T> g, T* __restrict__ c,
-                                                  const T* __restrict__ q, T* __restrict__ p,
-                                                  const uint8_t* __restrict__ flags, T dt,
-                                                  T c_bc, T Cs, T c0, Bat bt) {
+__global__ __launch_bounds__(kDiffBlock) void k_diff_div(Geo<T> g, T* __restrict__ c,
+                                                         const T* __restrict__ q, T* __restrict__ p,
+                                                         const uint8_t* __restrict__ flags, T dt,
+                                                         T c_bc, T Cs, T c0, Bat bt) {
+  constexpr int L = kDiffLanes;
   const int64_t n = g.n;
-  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
+  const int h = threadIdx.x % L;
   if (a >= n) return;
   double xa[D];
 #pragma unroll
@@ -592,7 +599,7 @@ __global__ __launch_bounds__(256) void k_diff_div(Geo<T> g, T* __restrict__ c,
     ga[i] = acc;
   }
   T div = T(0);
-  for (int64_t j = g.off[a]; j < g.off[a + 1]; ++j) {
+  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
     const uint32_t b = g.idx[j];
     T d[D];
     T r2 = T(0);
@@ -612,6 +619,8 @@ __global__ __launch_bounds__(256) void k_diff_div(Geo<T> g, T* __restrict__ c,
     }
     div += w * s;
   }
+  div = lane_sum<L>(div);
+  if (h != 0) return;
   T cn = c[a] - (bt.spec ? bt.get<T>(BT_DTD, bt.spec[a]) : dt) * div;
   if (flags && (flags[a] & SPH_FLAG_CDIR)) cn = c_bc;
   c[a] = cn;
@@ -883,14 +892,14 @@ static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state
   Geo<T> g = geo<T>(nb);
   {
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_diff_grad<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc,
+    k_diff_grad<T, D><<<nblk(nb->n, kDiffPerBlock), kDiffBlock, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc,
                                                        bat_view(nb));
     prof_end(nb, SPH_KERNEL_DIFF_GRAD, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   {
     hipEvent_t pe_ = prof_begin(nb, s);
-    k_diff_div<T, D><<<nblk(nb->n, 256), 256, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
+    k_diff_div<T, D><<<nblk(nb->n, kDiffPerBlock), kDiffBlock, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
                                                     st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
                                                     (T)m->c0, bat_view(nb));
     prof_end(nb, SPH_KERNEL_DIFF_DIV, pe_, s);
