@@ -662,7 +662,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
     Ga[4 * q + 3] = pv.w;
   }
   const T Va = xa.w;
-  T f[3] = {T(0), T(0), T(0)};
+  T f[3] = {T(0), T(0), T(0)}, m[3] = {T(0), T(0), T(0)};
   ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
     const vec4<T> xb = sx[l];
     T Gbb[NP * 4];
@@ -678,17 +678,25 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
     const T w0 = dw_over_r(r2, g.inv_h, g.c5);
-    const T wa = w0 * Va, wb = w0 * xb.w;
+    const T wb = w0 * xb.w;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       T s = T(0);
 #pragma unroll
-      for (int k = 0; k < D; ++k) s += (wa * Gbb[i * D + k] + wb * Ga[i * D + k]) * d[k];
-      f[i] += s;
+      for (int k = 0; k < D; ++k) s += Gbb[i * D + k] * d[k];
+      f[i] += w0 * s;
     }
-  });
 #pragma unroll
-  for (int i = 0; i < D; ++i) f[i] = lane_sum<LPP>(f[i]);
+    for (int k = 0; k < D; ++k) m[k] += wb * d[k];
+  });
+  // V_a sum_b G_bar_b grad W + G_bar_a sum_b V_b grad W, the second once per lane
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T x = Va * f[i];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x += Ga[i * D + k] * m[k];
+    f[i] = lane_sum<LPP>(x);
+  }
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
   const double ddt = (drift_dt != 0.0 && bt.spec) ? bt.get<double>(BT_DT, bt.spec[a]) : drift_dt;

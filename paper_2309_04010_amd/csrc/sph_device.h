@@ -279,10 +279,30 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t n_tiles) {
   return (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
 }
 
+// value of the lane that the DPP control CTRL selects (within a row of 16)
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF,
+                                                            0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// sum over the LPP consecutive lanes of one particle (every lane gets it), by
+// lane swaps within the row: quad_perm [1,0,3,2], quad_perm [2,3,0,1], then
+// the mirror within each half row (lane i <-> 7 - i), which pairs the two
+// quads of a group of eight.  All lanes of a group are active together.
 template <int LPP, typename T>
 __device__ __forceinline__ T lane_sum(T x) {
-#pragma unroll
-  for (int m = 1; m < LPP; m <<= 1) x += __shfl_xor(x, m, 64);
+  static_assert(LPP == 1 || LPP == 2 || LPP == 4 || LPP == 8, "lanes per particle");
+  if constexpr (LPP >= 2) x += dpp_mov<0xB1>(x);
+  if constexpr (LPP >= 4) x += dpp_mov<0x4E>(x);
+  if constexpr (LPP >= 8) x += dpp_mov<0x141>(x);
   return x;
 }
 

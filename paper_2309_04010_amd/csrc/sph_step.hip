@@ -144,7 +144,8 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
     }
 }
 
-// momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a
+// momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a.
+// Summed as PB_a (sum_b V_b grad_a W_ab) + sum_b V_b PB_b grad_a W_ab.
 template <typename T, int D, int LPP>
 __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
                                                                  const T* __restrict__ PB,
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
     Pa[4 * q + 2] = pv.z;
     Pa[4 * q + 3] = pv.w;
   }
-  T f[3] = {T(0), T(0), T(0)};
+  T f[3] = {T(0), T(0), T(0)}, m[3] = {T(0), T(0), T(0)};
   ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
     const vec4<T> xb = sx[l];
     T Pb[NP * 4];
@@ -234,12 +235,19 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
     for (int i = 0; i < D; ++i) {
       T s = T(0);
 #pragma unroll
-      for (int k = 0; k < D; ++k) s += (Pa[i * D + k] + Pb[i * D + k]) * d[k];
+      for (int k = 0; k < D; ++k) s += Pb[i * D + k] * d[k];
       f[i] += w * s;
     }
-  });
 #pragma unroll
-  for (int i = 0; i < D; ++i) f[i] = lane_sum<LPP>(f[i]);
+    for (int k = 0; k < D; ++k) m[k] += w * d[k];
+  });
+  // the own term PB_a sum_b V_b grad W, once per lane instead of per pair
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) f[i] += Pa[i * D + k] * m[k];
+    f[i] = lane_sum<LPP>(f[i]);
+  }
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
   const T dta = bt.spec ? bt.get<T>(BT_DT, bt.spec[a]) : dt;
