@@ -488,7 +488,8 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   const bool active = (uint32_t)t < td.count;
-  const uint32_t la = td.own_base + (active ? t : 0);
+  uint32_t la;
+  const int64_t a_own = tile_own(td, active ? (uint32_t)t : 0u, la);
   const vec4<T> xa = sx[la], ua = su[la];
   vec4<T> aa;
   if (D == 3) aa = sa[la];
@@ -545,7 +546,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     }
   double thd[kNTheta] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (active && h == 0) {
-    const int64_t a = p0 + t;
+    const int64_t a = a_own;
     T B[D][D];
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -649,8 +650,8 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  const int64_t a = p0 + t;
-  const uint32_t la = td.own_base + t;
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
   const vec4<T> xa = sx[la];
   T Ga[NP * 4];
 #pragma unroll

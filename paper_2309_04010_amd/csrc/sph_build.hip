@@ -604,14 +604,16 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
                            int32_t* err) {
   const TileDesc& td = tiles[blockIdx.x];
   for (int t = threadIdx.x; t < tmax; t += blockDim.x) {
-    uint32_t own = td.own_base + t;
+    uint32_t own = 0;
     int64_t j0 = 0, deg = 0;
     if ((uint32_t)t < td.count) {
-      int64_t a = (int64_t)td.p0 + t;
+      const int64_t a = (uint32_t)t < td.count0 ? (int64_t)td.p0 + t
+                                                : (int64_t)td.p1 + (t - td.count0);
+      own = (uint32_t)t < td.count0 ? td.own_base + t : td.own_base1 + (t - td.count0);
       j0 = off[a];
       deg = off[a + 1] - j0;
     } else {
-      own = td.own_base;  // unused column: any valid index
+      own = td.count0 > 0 ? td.own_base : td.own_base1;  // unused column: any valid index
     }
     for (uint32_t j = 0; j < td.width; ++j) {  // width: multiple of 4
       uint32_t loc = own;
@@ -773,9 +775,12 @@ __global__ void k_rows_fill(const uint32_t* __restrict__ anlev, const uint16_t* 
 }
 
 // host planning of row tiles (setup only)
-// Tiles grow along a row while the window stays within `wmax` (the LDS
-// budget that keeps two workgroups per CU); a single cell may exceed it up
-// to `wmax_hard` (the whole LDS of a CU).
+// A tile's own particles are a run of cells along x in one row of cells, or
+// in two stacked rows (the two z-rows of a slab two cells thick in 3D, pairs
+// of y-rows in 2D), which then share one window: its neighbouring rows over
+// the x-range widened by one cell.  Tiles grow along x while the window stays
+// within `wmax` (the LDS budget that keeps two workgroups per CU); a single
+// cell may exceed it up to `wmax_hard` (the whole LDS of a CU).
 static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
                       const std::vector<int64_t>& off, int tmax, int64_t wmax, int64_t wmax_hard,
                       std::vector<TileDesc>& out, int64_t& window_max, int64_t& ell_len) {
@@ -783,10 +788,13 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
   out.clear();
   window_max = 0;
   ell_len = 0;
+  auto own_index = [](const TileDesc& td, uint32_t t) -> int64_t {
+    return t < td.count0 ? (int64_t)td.p0 + t : (int64_t)td.p1 + (t - td.count0);
+  };
   auto emit = [&](TileDesc& td) {
     uint32_t width = 0;
     for (uint32_t t = 0; t < td.count; ++t) {
-      int64_t a = (int64_t)td.p0 + t;
+      const int64_t a = own_index(td, t);
       width = std::max<uint32_t>(width, (uint32_t)(off[a + 1] - off[a]));
     }
     td.width = (width + 3) & ~3u;
@@ -798,71 +806,113 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
   for (const GridSeg& sg : nb->segs) {  // rows never cross segments (specimens)
     const int64_t nc0 = sg.nc0, nc1 = sg.nc1, nc2 = sg.nc2;
     auto key = [&](int64_t x, int64_t y, int64_t z) { return sg.koff + x + nc0 * (y + nc1 * z); };
-    auto ccount = [&](int64_t x, int64_t y, int64_t z) {
-      int64_t k = key(x, y, z);
-      return (int64_t)cs[k + 1] - (int64_t)cs[k];
+    // rows of one tile: (y, z) of each own row; stacked rows share the window
+    struct Rows {
+      int n;
+      int64_t y[2], z[2];
     };
-    auto make = [&](int64_t x0, int64_t x1, int64_t y, int64_t z, int64_t p0, int64_t cnt,
+    auto col_count = [&](const Rows& R, int64_t x) {
+      int64_t c = 0;
+      for (int r = 0; r < R.n; ++r) c += (int64_t)cs[key(x, R.y[r], R.z[r]) + 1] - cs[key(x, R.y[r], R.z[r])];
+      return c;
+    };
+    // the tile of rows R over cells x0..x1; `chunk` (single row only) limits
+    // the own particles to [c0, c0 + cn) of that one cell
+    auto make = [&](const Rows& R, int64_t x0, int64_t x1, bool chunk, int64_t c0, int64_t cn,
                     TileDesc& td) -> int64_t {
       std::memset(&td, 0, sizeof(td));
-      td.p0 = (uint32_t)p0;
-      td.count = (uint32_t)cnt;
-      int64_t xa = x0 > 0 ? x0 - 1 : 0, xb = x1 + 1 < nc0 ? x1 + 1 : nc0 - 1;
+      const int64_t xa = x0 > 0 ? x0 - 1 : 0, xb = x1 + 1 < nc0 ? x1 + 1 : nc0 - 1;
+      int64_t ylo = R.y[0], yhi = R.y[R.n - 1], zlo = R.z[0], zhi = R.z[R.n - 1];
+      ylo = std::max<int64_t>(ylo - 1, 0);
+      yhi = std::min<int64_t>(yhi + 1, nc1 - 1);
+      if (dim == 3) {
+        zlo = std::max<int64_t>(zlo - 1, 0);
+        zhi = std::min<int64_t>(zhi + 1, nc2 - 1);
+      }
+      int64_t op[2] = {0, 0}, oc[2] = {0, 0}, ob[2] = {0, 0};
+      for (int r = 0; r < R.n; ++r) {
+        op[r] = cs[key(x0, R.y[r], R.z[r])];
+        oc[r] = (int64_t)cs[key(x1, R.y[r], R.z[r]) + 1] - op[r];
+        if (chunk) {
+          op[r] += c0;
+          oc[r] = cn;
+        }
+      }
       int64_t w = 0;
-      int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
-      for (int dz = zlo; dz <= zhi; ++dz) {
-        int64_t zz = z + dz;
-        if (zz < 0 || zz >= nc2) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-          int64_t yy = y + dy;
-          if (yy < 0 || yy >= nc1) continue;
-          int64_t s0 = cs[key(xa, yy, zz)], s1 = cs[key(xb, yy, zz) + 1];
-          if (dz == 0 && dy == 0) td.own_base = (uint32_t)(w + (p0 - s0));
+      for (int64_t zz = zlo; zz <= zhi; ++zz)
+        for (int64_t yy = ylo; yy <= yhi; ++yy) {
+          const int64_t s0 = cs[key(xa, yy, zz)], s1 = cs[key(xb, yy, zz) + 1];
+          for (int r = 0; r < R.n; ++r)
+            if (yy == R.y[r] && zz == R.z[r]) ob[r] = w + (op[r] - s0);
           td.run_start[td.nruns] = (uint32_t)s0;
           td.run_count[td.nruns] = (uint32_t)(s1 - s0);
           ++td.nruns;
           w += s1 - s0;
         }
-      }
+      // an empty first row: the second one alone (p0 stays a valid own particle)
+      const int f = (R.n == 2 && oc[0] == 0) ? 1 : 0;
+      td.p0 = (uint32_t)op[f];
+      td.own_base = (uint32_t)ob[f];
+      td.count0 = (uint32_t)oc[f];
+      td.p1 = (uint32_t)(R.n == 2 && f == 0 ? op[1] : op[f]);
+      td.own_base1 = (uint32_t)(R.n == 2 && f == 0 ? ob[1] : ob[f]);
+      td.count = (uint32_t)(oc[f] + (R.n == 2 && f == 0 ? oc[1] : 0));
       td.window = (uint32_t)w;
       return w;
     };
-    // rows in (y, z) order: the z-neighbour rows a tile's window needs were
-    // just staged by the previous rows' tiles, so they are still in L2
-    for (int64_t y = 0; y < nc1; ++y)
-      for (int64_t z = 0; z < nc2; ++z) {
-        int64_t x = 0;
-        while (x < nc0) {
-          int64_t cnt = ccount(x, y, z);
-          if (cnt == 0) {
-            ++x;
-            continue;
-          }
-          TileDesc td;
-          if (cnt > tmax) {  // one dense cell: split it into chunks
-            int64_t p0 = cs[key(x, y, z)];
-            for (int64_t c0 = 0; c0 < cnt; c0 += tmax) {
-              if (make(x, x, y, z, p0 + c0, std::min<int64_t>(tmax, cnt - c0), td) > wmax_hard)
+    auto walk = [&](const Rows& R) -> int {
+      int64_t x = 0;
+      while (x < nc0) {
+        int64_t cnt = col_count(R, x);
+        if (cnt == 0) {
+          ++x;
+          continue;
+        }
+        TileDesc td;
+        if (cnt > tmax) {  // one dense column: each row's cell in chunks
+          for (int r = 0; r < R.n; ++r) {
+            const Rows R1{1, {R.y[r], 0}, {R.z[r], 0}};
+            const int64_t cc = col_count(R1, x);
+            for (int64_t c0 = 0; c0 < cc; c0 += tmax) {
+              if (make(R1, x, x, true, c0, std::min<int64_t>(tmax, cc - c0), td) > wmax_hard)
                 return SPH_E_CAPACITY;
               emit(td);
             }
-            ++x;
-            continue;
           }
-          int64_t x1 = x;
-          while (x1 + 1 < nc0) {
-            int64_t nxt = ccount(x1 + 1, y, z);
-            if (cnt + nxt > tmax) break;
-            if (make(x, x1 + 1, y, z, cs[key(x, y, z)], cnt + nxt, td) > wmax) break;
-            cnt += nxt;
-            ++x1;
-          }
-          if (make(x, x1, y, z, cs[key(x, y, z)], cnt, td) > (x1 == x ? wmax_hard : wmax))
-            return SPH_E_CAPACITY;
-          emit(td);
-          x = x1 + 1;
+          ++x;
+          continue;
         }
+        int64_t x1 = x;
+        while (x1 + 1 < nc0) {
+          const int64_t nxt = col_count(R, x1 + 1);
+          if (cnt + nxt > tmax) break;
+          if (make(R, x, x1 + 1, false, 0, 0, td) > wmax) break;
+          cnt += nxt;
+          ++x1;
+        }
+        if (make(R, x, x1, false, 0, 0, td) > (x1 == x ? wmax_hard : wmax)) return SPH_E_CAPACITY;
+        emit(td);
+        x = x1 + 1;
       }
+      return SPH_OK;
+    };
+    int rc;
+    if (dim == 3 && nc2 == 2) {
+      // a slab two cells thick: both z-rows of each y share one window
+      for (int64_t y = 0; y < nc1; ++y)
+        if ((rc = walk(Rows{2, {y, y}, {0, 1}}))) return rc;
+    } else if (dim == 2) {
+      // pairs of y-rows: four window rows for two own rows
+      for (int64_t y = 0; y < nc1; y += 2)
+        if ((rc = walk(y + 1 < nc1 ? Rows{2, {y, y + 1}, {0, 0}} : Rows{1, {y, 0}, {0, 0}})))
+          return rc;
+    } else {
+      // rows in (y, z) order: the z-neighbour rows a tile's window needs were
+      // just staged by the previous rows' tiles, so they are still in L2
+      for (int64_t y = 0; y < nc1; ++y)
+        for (int64_t z = 0; z < nc2; ++z)
+          if ((rc = walk(Rows{1, {y, 0}, {z, 0}}))) return rc;
+    }
   }
   if (ell_len >= (1LL << 32)) return SPH_E_CAPACITY;
   return SPH_OK;

@@ -112,9 +112,15 @@ constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (16.7M particles)
 // so one lane loads four indices with one 8-byte load and a wavefront's loads
 // are contiguous; entries past a particle's degree hold its own index (a zero
 // contribution).  `width` is a multiple of 4.
+// A tile's own particles are one run of a row of cells, or two runs (the same
+// x-range of two stacked rows): thread t < count0 takes particle p0 + t at
+// window position own_base + t, the others p1 + (t - count0) at own_base1 +
+// (t - count0).  The window is the concatenation of nruns runs of sorted
+// particles (the neighbouring rows' cells over the x-range widened by one).
 struct TileDesc {
   uint32_t p0, count, ell_off, width;
-  uint32_t nruns, window, own_base, pad;
+  uint32_t nruns, window, own_base, count0;
+  uint32_t p1, own_base1, pad0, pad1;
   uint32_t run_start[9];
   uint32_t run_count[9];
 };

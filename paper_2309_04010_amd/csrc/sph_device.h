@@ -274,6 +274,16 @@ static TileGeo<T> tile_geo(const sph_nbr* nb, int prec) {
   return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5};
 }
 
+// own particle t of a tile: its sorted index and its window position
+__device__ __forceinline__ int64_t tile_own(const TileDesc& td, uint32_t t, uint32_t& la) {
+  if (t < td.count0) {
+    la = td.own_base + t;
+    return (int64_t)td.p0 + t;
+  }
+  la = td.own_base1 + (t - td.count0);
+  return (int64_t)td.p1 + (t - td.count0);
+}
+
 __device__ __forceinline__ int64_t xcd_tile(int64_t n_tiles) {
   const int64_t per = (n_tiles + 7) / 8;
   return (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);

@@ -68,8 +68,9 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  const int64_t a = p0 + t;
-  const vec4<T> xa = sx[td.own_base + t], ua = su[td.own_base + t];
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
+  const vec4<T> xa = sx[la], ua = su[la];
   T G[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
@@ -203,8 +204,8 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  const int64_t a = p0 + t;
-  const uint32_t la = td.own_base + t;
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
   const vec4<T> xa = sx[la];
   T Pa[NP * 4];
 #pragma unroll
