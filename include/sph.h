@@ -432,7 +432,9 @@ int sph_status(const sph_nbr* nbr, void* stream, int32_t* status_bits);
  * from a captured graph are not timed).  sph_profile_enable resets the
  * counters; sph_profile_read synchronises on the recorded events and returns
  * the number of launches and their summed duration for one kernel class.
- * Timing adds two event records per launch. */
+ * Timing adds two event records per timed launch (a few microseconds of
+ * queue time each); sph_profile_classes limits it to the classes whose bit
+ * (1 << class) is set in `mask` (all by default; kept across enables). */
 #define SPH_KERNEL_STRESS 0    /* deformation gradient + stress + PB */
 #define SPH_KERNEL_MOMENTUM 1  /* pair momentum sum + kick */
 #define SPH_KERNEL_DAMPING 2   /* one colour pass of the damping sweep */
@@ -445,6 +447,7 @@ int sph_status(const sph_nbr* nbr, void* stream, int32_t* status_bits);
 #define SPH_KERNEL_ADJ_DAMPING 9 /* reverse: one colour pass of the transposed sweep */
 #define SPH_KERNEL_COUNT 10
 int sph_profile_enable(sph_nbr* nbr, int enable);
+int sph_profile_classes(sph_nbr* nbr, uint32_t mask);
 int sph_profile_read(sph_nbr* nbr, int kernel_class, int64_t* launches, double* total_ms);
 
 /* Thread-local description of the last error ("" if none). */

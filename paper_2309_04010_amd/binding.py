@@ -26,7 +26,7 @@ SPH_FLAG_FIXED, SPH_FLAG_CDIR, SPH_FLAG_GRIP = 1, 2, 4
 EXPORTED = [
     "sph_build_neighbors", "sph_nbr_destroy", "sph_nbr_query", "sph_solid_relax_step",
     "sph_damping_sweep", "sph_drift_ke", "sph_load_step", "sph_diffusion_step",
-    "sph_advance_multirate", "sph_status", "sph_profile_enable", "sph_profile_read",
+    "sph_advance_multirate", "sph_status", "sph_profile_enable", "sph_profile_classes", "sph_profile_read",
     "sph_last_error", "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_drift_vjp",
     "sph_diffusion_step_vjp", "sph_advance_multirate_backward", "sph_constitutive",
     "sph_constitutive_vjp", "sph_build_neighbors_batched", "sph_advance_multirate_graph",
@@ -150,6 +150,7 @@ def lib():
     L.sph_get_tuning.argtypes = [vp, C.c_int, C.POINTER(Tuning)]
     L.sph_status.argtypes = [vp, vp, C.POINTER(i32)]
     L.sph_profile_enable.argtypes = [vp, C.c_int]
+    L.sph_profile_classes.argtypes = [vp, C.c_uint32]
     L.sph_profile_read.argtypes = [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)]
     L.sph_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -626,6 +627,18 @@ def sph_get_tuning(nbr, prec):
 
 def sph_profile_enable(nbr, enable=True):
     _check(lib().sph_profile_enable(nbr.handle, 1 if enable else 0))
+
+
+def sph_profile_classes(nbr, classes=None):
+    """Time only these kernel classes (names of SPH_KERNEL_NAMES or indices);
+    None: all."""
+    if classes is None:
+        mask = 0xFFFFFFFF
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << (SPH_KERNEL_NAMES.index(c) if isinstance(c, str) else int(c))
+    _check(lib().sph_profile_classes(nbr.handle, mask))
 
 
 def sph_profile_read(nbr):

@@ -908,7 +908,7 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
   int rc = SPH_OK;
   if constexpr (LS > 0) {
     if ((rc = lds_attr(k_adj_stress<T, D, LS, MODEL>, lds_s))) return rc;
-    hipEvent_t pe_ = prof_begin(nb, s);
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_ADJ_STRESS, s);
     k_adj_stress<T, D, LS, MODEL><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
         g, mp, u, (const T*)adj->v, st->flags, (T)dt, (T)(1.0 / m->rho0), (const T*)plastic,
         (T*)adj->plastic, (const T*)st->p, adj->p, (T*)adj->work, nb->gpart, nb->ctrl,
@@ -918,7 +918,7 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
   }
   if constexpr (LG > 0) {
     if ((rc = lds_attr(k_adj_gather<T, D, LG>, lds_g))) return rc;
-    hipEvent_t pe_ = prof_begin(nb, s);
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_ADJ_GATHER, s);
     k_adj_gather<T, D, LG><<<grid, (unsigned)(g.tmax * LG), lds_g, s>>>(
         g, (const T*)adj->work, adj->u, (T*)adj->v, st->flags, drift_dt, bat_view(nb));
     prof_end(nb, SPH_KERNEL_ADJ_GATHER, pe_, s);

@@ -51,6 +51,7 @@ struct Ctrl {
 // per-kernel event timing (see sph_profile_enable)
 struct Prof {
   bool on = false;
+  uint32_t mask = 0xFFFFFFFFu;  // kernel classes timed while on
   bool suspend = false;  // set while a graph is being captured
   struct Pend {
     int kind;
@@ -262,7 +263,7 @@ inline int64_t tile_wmax_hard(int prec, int dim) {
 }
 
 // ---- event timing around launches --------------------------------------------
-hipEvent_t prof_begin(const sph_nbr* nb, hipStream_t s);
+hipEvent_t prof_begin(const sph_nbr* nb, int kind, hipStream_t s);
 void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s);
 int prof_resolve(const sph_nbr* nb);
 

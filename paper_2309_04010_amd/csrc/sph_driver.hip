@@ -16,9 +16,9 @@ using namespace sph;
 
 namespace sph {
 
-hipEvent_t prof_begin(const sph_nbr* nb, hipStream_t s) {
+hipEvent_t prof_begin(const sph_nbr* nb, int kind, hipStream_t s) {
   Prof* p = nb->prof;
-  if (!p || !p->on || p->suspend) return nullptr;
+  if (!p || !p->on || p->suspend || !((p->mask >> kind) & 1u)) return nullptr;
   hipEvent_t e = nullptr;
   if (!p->pool.empty()) {
     e = p->pool.back();
@@ -81,6 +81,17 @@ extern "C" int sph_profile_enable(sph_nbr* nb, int enable) {
   }
   nb->prof->on = enable != 0;
   return rc;
+}
+
+extern "C" int sph_profile_classes(sph_nbr* nb, uint32_t mask) {
+  clear_error();
+  if (!nb) {
+    set_error("bad handle");
+    return SPH_E_ARG;
+  }
+  if (!nb->prof) nb->prof = new Prof();
+  nb->prof->mask = mask;
+  return SPH_OK;
 }
 
 extern "C" int sph_profile_read(sph_nbr* nb, int kind, int64_t* launches, double* total_ms) {

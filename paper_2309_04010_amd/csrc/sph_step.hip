@@ -669,7 +669,7 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
   int rc = SPH_OK;
   if constexpr (LS > 0) {
     if ((rc = lds_attr(k_stress<T, D, LS, MODEL>, lds_s))) return rc;
-    hipEvent_t pe_ = prof_begin(nb, s);
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_STRESS, s);
     k_stress<T, D, LS, MODEL><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
         g, mp, st->u, (T*)st->PB, (T*)st->plastic, (const T*)st->p, nb->ctrl, gated,
         m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr, bat_view(nb));
@@ -678,7 +678,7 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
   }
   if constexpr (LM > 0) {
     if ((rc = lds_attr(k_momentum<T, D, LM>, lds_m))) return rc;
-    hipEvent_t pe_ = prof_begin(nb, s);
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_MOMENTUM, s);
     k_momentum<T, D, LM><<<grid, (unsigned)(g.tmax * LM), lds_m, s>>>(
         g, (const T*)st->PB, (T*)st->v, (T*)st->acc, st->flags, (T)(1.0 / m->rho0), (T)dt,
         nb->ctrl, gated, bat_view(nb));
@@ -757,7 +757,7 @@ static int damp_launch(const sph_nbr* nb, const sph_state* st, hipStream_t s, bo
   const unsigned grid = (unsigned)((a1 - a0 + APW - 1) / APW);
   const int p = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   const int64_t po = nb->damp_pair_off[col];
-  hipEvent_t pe_ = prof_begin(nb, s);
+  hipEvent_t pe_ = prof_begin(nb, REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING, s);
   k_damp<T, D, G, REV><<<grid, 64, lds, s>>>(
       (const PairQ<T>*)nb->dwq[p] + po, (uint32_t)(nb->n_upairs - po), po, (const T*)nb->imass[p],
       nb->drow[gi], nb->drow_base[gi], nb->drow_empty[gi], nb->aoff, nb->ablk, a0, a1, bmax,
@@ -854,7 +854,7 @@ static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st
     return SPH_E_CAPACITY;
   }
   {
-    hipEvent_t pe_ = prof_begin(nb, s);
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DRIFT_KE, s);
     k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
                                                           nb->V, m->rho0, dt, nb->ctrl,
                                                           nb->ke_partial, gated, nb->rec_u,
@@ -900,14 +900,14 @@ static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state
                        double dt, double c_bc, hipStream_t s) {
   Geo<T> g = geo<T>(nb);
   {
-    hipEvent_t pe_ = prof_begin(nb, s);
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_GRAD, s);
     k_diff_grad<T, D><<<nblk(nb->n, kDiffPerBlock), kDiffBlock, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc,
                                                        bat_view(nb));
     prof_end(nb, SPH_KERNEL_DIFF_GRAD, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   {
-    hipEvent_t pe_ = prof_begin(nb, s);
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_DIV, s);
     k_diff_div<T, D><<<nblk(nb->n, kDiffPerBlock), kDiffBlock, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
                                                     st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
                                                     (T)m->c0, bat_view(nb));
