@@ -140,7 +140,7 @@ struct Tiling {
 // in dloff, its rows for lane-group width 8 << i in drow[i]
 constexpr int kDampLocBits = 16;
 constexpr int kDampWidths = 4;          // lane-group widths 8, 16, 32, 64
-constexpr int kDampRowPad = 48;         // empty rows framing each anchor's row list
+constexpr int kDampRowPad = 24;         // empty rows framing each anchor's row list (3K)
 constexpr int kDampMaxLocal = 1 << kDampLocBits;
 constexpr int kDampMaxLevel = 255;      // levels of one anchor (offsets held in 4 registers)
 constexpr int64_t kDampLdsBudget = 159 * 1024;  // gfx950: 160 KB of LDS per workgroup

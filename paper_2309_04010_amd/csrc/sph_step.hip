@@ -298,7 +298,7 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
                                              bool gated) {
   if (gated && ctrl->done) return;
   constexpr int APW = 64 / G;
-  constexpr int K = sizeof(T) == 4 ? 16 : 8;  // steps of records in flight
+  constexpr int K = 8;  // steps of records in flight (deeper rings measured slower)
   // the last pass of the step loop runs up to K - 1 steps past the list and
   // reads row words 2K steps ahead: every row read stays within the frames
   static_assert(3 * K <= kDampRowPad, "row frames too short for the ring");
@@ -453,7 +453,9 @@ __global__ void k_damp_prep(int64_t n_upairs, int64_t n, const uint32_t* __restr
 
 // drift + kinetic energy: every block writes its partial E_k (fixed-order
 // tree), then one block reduces the partials in a fixed order, records E_k
-// and updates the stop state (deterministic: no floating-point atomics)
+// and updates the stop state (deterministic: no floating-point atomics).
+// (Electing the last block with a ticket instead costs a device-scope release
+// fence per block, an L2 write-back, which is slower than the extra launch.)
 template <typename T, int D>
 __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     int64_t n, double* __restrict__ u, const T* __restrict__ v, const uint8_t* __restrict__ flags,
@@ -461,24 +463,57 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     bool gated, double* __restrict__ rec_u, Bat bt) {
   if (gated && ctrl->done) return;
   __shared__ double red[kKeThreads];
-  double acc = 0.0;
-  double* rec = rec_u ? rec_u + ctrl->k * D * n : nullptr;
+  double* __restrict__ rec = rec_u ? rec_u + ctrl->k * D * n : nullptr;
   const int64_t a0 = blockIdx.x * (int64_t)(kKeThreads * kKeItems) + threadIdx.x;
+  // every load of the thread's particles first, then the updates
+  double uo[kKeItems][D], Va[kKeItems], dta[kKeItems];
+  T vv[kKeItems][D];
+  uint8_t fl[kKeItems];
+#pragma unroll
+  for (int it = 0; it < kKeItems; ++it) {
+    const int64_t a = a0 + it * kKeThreads;
+    fl[it] = SPH_FLAG_FIXED;
+    Va[it] = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      vv[it][k] = T(0);
+      uo[it][k] = 0.0;
+    }
+    if (a < n) {
+      fl[it] = flags ? flags[a] : (uint8_t)0;
+      Va[it] = V[a];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        vv[it][k] = v[k * n + a];
+        uo[it][k] = u[k * n + a];
+      }
+    }
+  }
+  if (bt.spec) {  // batched: each particle's own time step
+#pragma unroll
+    for (int it = 0; it < kKeItems; ++it) {
+      const int64_t a = a0 + it * kKeThreads;
+      dta[it] = a < n ? bt.get<double>(BT_DT, bt.spec[a]) : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < kKeItems; ++it) dta[it] = dt;
+  }
+  double acc = 0.0;
 #pragma unroll
   for (int it = 0; it < kKeItems; ++it) {
     const int64_t a = a0 + it * kKeThreads;
     if (a < n) {
-      const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
-      const double dta = bt.spec ? bt.get<double>(BT_DT, bt.spec[a]) : dt;
+      const bool fixed = fl[it] & SPH_FLAG_FIXED;
       double v2 = 0.0;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        double vk = (double)v[k * n + a];
-        if (rec) rec[k * n + a] = u[k * n + a];
-        if (!fixed) u[k * n + a] += dta * vk;
+        const double vk = (double)vv[it][k];
+        if (rec) rec[k * n + a] = uo[it][k];
+        if (!fixed) u[k * n + a] = uo[it][k] + dta[it] * vk;
         v2 += vk * vk;
       }
-      acc += 0.5 * rho0 * V[a] * v2;
+      acc += 0.5 * rho0 * Va[it] * v2;
     }
   }
   red[threadIdx.x] = acc;
