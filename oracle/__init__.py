@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "sph_oracle.c")
 _LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_cs.so")}
 
 LE, NH, J2 = 0, 1, 2
-LOAD, DIFFUSION = 0, 1
+LOAD, DIFFUSION, DIFFUSION_COUPLED = 0, 1, 2
 FIXED, CDIR, GRIP = 1, 2, 4
 
 
@@ -72,6 +72,8 @@ def _lib(cplx: bool):
     lib.orc_drift_ke.argtypes = [vp, dbl, dbl, vp, vp, vp]
     lib.orc_load_step.argtypes = [vp, dbl, vp, vp, vp]
     lib.orc_diffusion_step.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, vp, vp, vp, vp]
+    lib.orc_diffusion_step_coupled.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, C.c_int,
+                                               vp, vp, vp, vp, vp]
     lib.orc_advance.restype = i32
     lib.orc_advance.argtypes = [vp] * 15
     _cache[cplx] = lib
@@ -109,7 +111,8 @@ def _cfg_t(cplx):
     class Cfg(C.Structure):
         _fields_ = [("n_slow", C.c_int32), ("slow_kind", C.c_int32), ("dt_slow", C.c_double),
                     ("dt_s", C.c_double), ("eta", C.c_double), ("k_max", C.c_int64),
-                    ("fixed_inner", C.c_int64), ("ke_tol", C.c_double), ("D", R), ("c_bc", C.c_double)]
+                    ("fixed_inner", C.c_int64), ("ke_tol", C.c_double), ("D", R), ("c_bc", C.c_double),
+                    ("nonlinear", C.c_int32), ("pad2_", C.c_int32)]
     return Cfg
 
 
@@ -195,10 +198,10 @@ class Oracle:
                  r(H), r(C_swell), float(c0))
 
     def cfg(self, n_slow, slow_kind, dt_slow, dt_s=0.0, eta=0.0, k_max=0, fixed_inner=0, ke_tol=0.0,
-            D=0.0, c_bc=0.0):
+            D=0.0, c_bc=0.0, nonlinear=0):
         Cf = _cfg_t(self.cplx)
         return Cf(int(n_slow), int(slow_kind), float(dt_slow), float(dt_s), float(eta), int(k_max),
-                  int(fixed_inner), float(ke_tol), _to_real(D, self.cplx), float(c_bc))
+                  int(fixed_inner), float(ke_tol), _to_real(D, self.cplx), float(c_bc), int(nonlinear), 0)
 
     @staticmethod
     def _from_real(x):
@@ -271,6 +274,14 @@ class Oracle:
         self.lib.orc_diffusion_step(self._h, _to_real(D, self.cplx), float(dt_d), float(c_bc),
                                     _to_real(C_swell, self.cplx), float(c0), _ptr(self._a(c)),
                                     _ptr(self._a(q)), _ptr(self._a(p)), _ptr(flags))
+
+    def diffusion_step_coupled(self, D, dt_d, c_bc, C_swell, c0, nonlinear, u, c, q, p, flags=None):
+        """Two-way coupled diffusion step: c is the fluid content per reference
+        volume, the saturation c / J follows u; q receives the reference flux."""
+        self.lib.orc_diffusion_step_coupled(self._h, _to_real(D, self.cplx), float(dt_d), float(c_bc),
+                                            _to_real(C_swell, self.cplx), float(c0), int(nonlinear),
+                                            _ptr(self._a(u)), _ptr(self._a(c)), _ptr(self._a(q)),
+                                            _ptr(self._a(p)), _ptr(flags))
 
     def advance(self, mat, cfg, u, v, plastic=None, c=None, q=None, p=None, vgrip=None, flags=None,
                 k_sched=None):

@@ -31,7 +31,10 @@
  *                                  and diffusion step sizes, and k0 of Sec. 4.2
  *   diffusion (slow process) ..... Sec. 2.2.2 Fick's law, eq. (grad_q) and
  *                                  eq. (fluid_mass_der); Sec. 3.2 eqs.
- *                                  (fluid_mass_sph), (ralative_velocity_sph)
+ *                                  (fluid_mass_sph), (ralative_velocity_sph);
+ *                                  the two-way coupled form with the
+ *                                  updated-Lagrangian gradient stated after
+ *                                  eq. (fluid_mass_sph)
  *   multi-time-step driver ....... Sec. 4.2 (outer loop l, inner loop k,
  *                                  kinetic-energy early exit)
  *
@@ -889,6 +892,97 @@ void orc_diffusion_step(const orc_sys* s, real D, double dt_d, double c_bc, real
   free(cn);
 }
 
+/* Two-way coupled diffusion slow step.  Reading of Sec. 2.2.2 eqs. (grad_q),
+ * (fluid_mass_der) and Sec. 3.2 eqs. (fluid_mass_sph), (ralative_velocity_sph)
+ * with the updated-Lagrangian kernel gradient stated after eq.
+ * (fluid_mass_sph):
+ *   - the fluid mass per reference volume, divided by the reference fluid
+ *     density, is c; the saturation is a = c / J (J-dilution), J = det F,
+ *     F = I + H(u) from eq. (deformationtensor-displacement);
+ *   - the flux q = -K rho^l grad a of eq. (grad_q) with rho^l = rho^l_0 a and
+ *     D = K rho^l_0 is q = -D a grad a (nonlinear) or, with rho^l frozen at
+ *     rho^l_0, q = -D grad a; grad is the current-configuration gradient
+ *     F^-T grad0 applied to the B0-corrected reference gradient:
+ *       g_a = F_a^-T B0_a sum_b V_b (a_b - a_a) grad0_a W_ab,  q_a = -D w_a g_a;
+ *   - the mass balance of eq. (fluid_mass_der) is taken on the reference
+ *     configuration with the Piola flux Q = J F^-1 q and the same
+ *     antisymmetric corrected divergence as the linear step:
+ *       c_a += dt_d ( - sum_b V_b (B0_a Q_a + B0_b Q_b) . grad0_a W_ab );
+ *   - Dirichlet particles take a = c_bc (c = c_bc J); p = C (a - c0).
+ * With u = 0 and the linear flux this is orc_diffusion_step operation by
+ * operation.  q receives Q.                                                */
+void orc_diffusion_step_coupled(const orc_sys* s, real D, double dt_d, double c_bc, real C_swell,
+                                double c0, int nonlinear, const real* u, real* c, real* q, real* p,
+                                const uint8_t* flags) {
+  int d = s->dim;
+  int64_t n = s->n;
+  real* H9 = (real*)malloc(9 * n * sizeof(real));
+  real* Fi = (real*)malloc(9 * n * sizeof(real));
+  real* J = (real*)malloc(n * sizeof(real));
+  real* a = (real*)malloc(n * sizeof(real));
+  orc_displacement_gradient(s, u, H9);
+  for (int64_t i = 0; i < n; ++i) {
+    real F[9];
+    for (int k = 0; k < 9; ++k) F[k] = H9[k * n + i];
+    F[0] += 1.0;
+    F[4] += 1.0;
+    F[8] += 1.0;
+    real Fin[9];
+    J[i] = det3(F);
+    inv3(F, Fin);
+    for (int k = 0; k < 9; ++k) Fi[k * n + i] = Fin[k];
+    a[i] = c[i] / J[i];
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    real g[3] = {0, 0, 0};
+    for (int64_t j = s->nbr_off[i]; j < s->nbr_off[i + 1]; ++j) {
+      int64_t b = s->nbr_idx[j];
+      double gw[3];
+      pair_w(s, i, b, gw);
+      for (int k = 0; k < d; ++k) g[k] += s->V[b] * (a[b] - a[i]) * gw[k];
+    }
+    real gr[3] = {0, 0, 0}, gc[3] = {0, 0, 0}, qc[3] = {0, 0, 0};
+    for (int m = 0; m < d; ++m)
+      for (int k = 0; k < d; ++k) gr[m] += s->B0[(m * d + k) * n + i] * g[k];
+    for (int m = 0; m < d; ++m)
+      for (int k = 0; k < d; ++k) gc[m] += Fi[(k * 3 + m) * n + i] * gr[k];  /* F^-T */
+    const real w = nonlinear ? a[i] : 1.0;
+    for (int m = 0; m < d; ++m) qc[m] = -D * w * gc[m];
+    for (int m = 0; m < d; ++m) {
+      real acc = 0.0;
+      for (int k = 0; k < d; ++k) acc += Fi[(m * 3 + k) * n + i] * qc[k];     /* F^-1 */
+      q[m * n + i] = J[i] * acc;
+    }
+  }
+  real* cn = (real*)malloc(n * sizeof(real));
+  for (int64_t i = 0; i < n; ++i) {
+    real div = 0.0;
+    for (int64_t j = s->nbr_off[i]; j < s->nbr_off[i + 1]; ++j) {
+      int64_t b = s->nbr_idx[j];
+      double gw[3];
+      pair_w(s, i, b, gw);
+      for (int m = 0; m < d; ++m) {
+        real ga = 0.0, gb = 0.0;
+        for (int k = 0; k < d; ++k) {
+          ga += s->B0[(m * d + k) * n + i] * q[k * n + i];
+          gb += s->B0[(m * d + k) * n + b] * q[k * n + b];
+        }
+        div += s->V[b] * (ga + gb) * gw[m];
+      }
+    }
+    cn[i] = c[i] - dt_d * div;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    c[i] = (flags && (flags[i] & ORC_CDIR)) ? c_bc * J[i] : cn[i];
+    if (p) p[i] = C_swell * (c[i] / J[i] - c0);
+  }
+  free(cn);
+  free(a);
+  free(J);
+  free(Fi);
+  free(H9);
+}
+
 /* Multi-time-step driver, Sec. 4.2.  Defaults: dt_s = 0.6 h / c_s with
  * c_s = sqrt(K/rho0) evaluated once at rest (eq. dts-advection with |v| = 0);
  * diffusion step 0.5 h^2 / D; k_max = k0 = floor(dt_slow/dt_s) + 1. */
@@ -899,13 +993,16 @@ int orc_advance(const orc_sys* s, const orc_material* m, const orc_cfg* cfg, rea
   double K = RE(m->E) / (3.0 * (1.0 - 2.0 * m->nu));
   double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * s->h / sqrt(K / m->rho0);
   double dt_slow = cfg->dt_slow;
-  if (cfg->slow_kind == ORC_DIFFUSION && !(dt_slow > 0.0)) dt_slow = 0.5 * s->h * s->h / RE(cfg->D);
+  if (cfg->slow_kind != ORC_LOAD && !(dt_slow > 0.0)) dt_slow = 0.5 * s->h * s->h / RE(cfg->D);
   int64_t k_max = cfg->k_max > 0 ? cfg->k_max : (int64_t)floor(dt_slow / dt_s) + 1;
   int adaptive = (k_sched == NULL && cfg->fixed_inner <= 0);
   int warn = 0, rc = 0;
   for (int32_t l = 0; l < cfg->n_slow; ++l) {
     if (cfg->slow_kind == ORC_LOAD)
       orc_load_step(s, dt_slow, u, vgrip, flags);
+    else if (cfg->slow_kind == ORC_DIFFUSION_COUPLED)
+      orc_diffusion_step_coupled(s, cfg->D, dt_slow, cfg->c_bc, m->C_swell, m->c0, cfg->nonlinear, u,
+                                 c, q, p, flags);
     else
       orc_diffusion_step(s, cfg->D, dt_slow, cfg->c_bc, m->C_swell, m->c0, c, q, p, flags);
     int64_t nk = k_sched ? k_sched[l] : (cfg->fixed_inner > 0 ? cfg->fixed_inner : k_max);

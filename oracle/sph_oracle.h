@@ -34,7 +34,7 @@ typedef double real;
 #define ORC_GRIP  4u  /* receives prescribed displacement increments (loading)     */
 
 enum { ORC_LE = 0, ORC_NH = 1, ORC_J2 = 2 };
-enum { ORC_LOAD = 0, ORC_DIFFUSION = 1 };
+enum { ORC_LOAD = 0, ORC_DIFFUSION = 1, ORC_DIFFUSION_COUPLED = 2 };
 
 typedef struct {
   int32_t model;              /* ORC_LE / ORC_NH / ORC_J2 */
@@ -49,7 +49,7 @@ typedef struct {
 
 typedef struct {
   int32_t n_slow;
-  int32_t slow_kind;          /* ORC_LOAD / ORC_DIFFUSION */
+  int32_t slow_kind;          /* ORC_LOAD / ORC_DIFFUSION / ORC_DIFFUSION_COUPLED */
   double dt_slow;             /* loading step; for diffusion <=0 means 0.5 h^2/D */
   double dt_s;                /* <=0 means 0.6 h / sqrt(K/rho0) */
   double eta;                 /* damping viscosity */
@@ -58,6 +58,8 @@ typedef struct {
   double ke_tol;              /* absolute kinetic-energy threshold */
   real D;                     /* diffusion coefficient */
   double c_bc;                /* Dirichlet saturation */
+  int32_t nonlinear;          /* coupled diffusion: flux -D a grad a (1) or -D grad a (0) */
+  int32_t pad2_;
 } orc_cfg;
 
 typedef struct orc_sys orc_sys;
@@ -98,6 +100,12 @@ real orc_drift_ke(const orc_sys* s, double rho0, double dt, real* u, const real*
 void orc_load_step(const orc_sys* s, double dt_l, real* u, const real* vgrip, const uint8_t* flags);
 void orc_diffusion_step(const orc_sys* s, real D, double dt_d, double c_bc, real C_swell,
                         double c0, real* c, real* q, real* p, const uint8_t* flags);
+/* two-way coupled form: c is the fluid content per reference volume, the
+ * saturation a = c / J follows the deformation u; q receives the reference
+ * flux J F^-1 q */
+void orc_diffusion_step_coupled(const orc_sys* s, real D, double dt_d, double c_bc, real C_swell,
+                                double c0, int nonlinear, const real* u, real* c, real* q, real* p,
+                                const uint8_t* flags);
 /* multi-time-step driver; k_sched (optional) freezes the inner counts */
 int orc_advance(const orc_sys* s, const orc_material* m, const orc_cfg* cfg, real* u, real* v,
                 real* plastic, real* c, real* q, real* p, const real* vgrip,

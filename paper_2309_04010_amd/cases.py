@@ -36,7 +36,7 @@ import numpy as np
 
 FIXED, CDIR, GRIP = 1, 2, 4
 LE, NH, J2 = 0, 1, 2
-LOAD, DIFFUSION = 0, 1
+LOAD, DIFFUSION, DIFFUSION_COUPLED = 0, 1, 2
 
 
 def lattice(shape, dp, jitter=0.0, seed=None):
