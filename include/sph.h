@@ -53,6 +53,7 @@ extern "C" {
 
 #define SPH_SLOW_LOAD 0      /* slow step = prescribed grip displacement increment */
 #define SPH_SLOW_DIFFUSION 1 /* slow step = SPH diffusion of the saturation */
+#define SPH_SLOW_DIFFUSION_COUPLED 2 /* slow step = two-way coupled diffusion (sph_diffusion_step_coupled) */
 
 /* per-particle flag bits (uint8) */
 #define SPH_FLAG_FIXED 1u /* velocity held (zero) in the inner loop; infinite mass in damping */
@@ -128,7 +129,7 @@ typedef struct {
 
 typedef struct {
   int32_t n_slow;      /* outer (slow) steps */
-  int32_t slow_kind;   /* SPH_SLOW_LOAD / SPH_SLOW_DIFFUSION */
+  int32_t slow_kind;   /* SPH_SLOW_LOAD / SPH_SLOW_DIFFUSION / SPH_SLOW_DIFFUSION_COUPLED */
   double dt_slow;      /* loading step; diffusion: <= 0 selects 0.5 h^2 / D (Sec. 4.1) */
   double dt_s;         /* inner step; <= 0 selects 0.6 h / sqrt(K/rho0) (eq. dts-advection at rest) */
   double eta;          /* damping viscosity (eq. damping-sph) */
@@ -141,6 +142,8 @@ typedef struct {
   int32_t use_graph;   /* 1: replay each chunk as a captured hipGraph */
   const int64_t* k_sched; /* host, optional [n_slow]: frozen inner counts */
   const struct sph_batch* batch; /* optional: per-specimen parameters (see sph_build_neighbors_batched) */
+  int32_t diff_nonlinear; /* SPH_SLOW_DIFFUSION_COUPLED: flux -D a grad a (1) or -D grad a (0) */
+  int32_t pad2_;
 } sph_multirate_cfg;
 
 typedef struct {
@@ -221,6 +224,23 @@ int sph_load_step(const sph_nbr* nbr, const sph_state* st, double dt_l, void* st
  * (eq. fluid_pressure) when st->p is not NULL.  Needs st->c and st->q.  Async. */
 int sph_diffusion_step(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
                        double D, double dt_d, double c_bc, void* stream);
+
+/* Two-way coupled diffusion slow step: the reading of eqs. grad_q,
+ * fluid_mass_der, fluid_mass_sph and ralative_velocity_sph (Sec. 2.2.2, 3.2)
+ * with the updated-Lagrangian kernel gradient stated after fluid_mass_sph.
+ * st->c holds the fluid content per reference volume (over the reference
+ * fluid density); the saturation is a = c / J, J = det F, F = I + H(st->u)
+ * (eq. deformationtensor-displacement).  Then
+ *   q_a = -D w_a F_a^-T B0_a sum_b V_b (a_b - a_a) grad0_a W_ab,
+ *         w_a = a_a if nonlinear (eq. grad_q with rho^l = rho^l_0 a), else 1,
+ *   st->q <- Q_a = J_a F_a^-1 q_a (the reference flux),
+ *   c_a  += dt_d (- sum_b V_b (B0_a Q_a + B0_b Q_b) . grad0_a W_ab),
+ * c = c_bc J on SPH_FLAG_CDIR particles (saturation c_bc) and
+ * p = C_swell (c / J - c0).  Needs st->u, c, q, p; uses st->PB as scratch
+ * (overwritten: F^-1).  With u = 0 and nonlinear = 0 it is
+ * sph_diffusion_step.  No reverse pass.  Asynchronous. */
+int sph_diffusion_step_coupled(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                               double D, double dt_d, double c_bc, int32_t nonlinear, void* stream);
 
 /* Recording of a forward multi-time-step run for the reverse pass
  * (sph_advance_multirate_backward).  All arrays are caller-owned DEVICE

@@ -20,12 +20,12 @@ SPH_OK, SPH_E_ARG, SPH_E_CAPACITY, SPH_E_DEVICE, SPH_E_NUMERIC, SPH_E_UNSUPPORTE
 SPH_W_NOT_CONVERGED = 1
 SPH_F32, SPH_F64 = 0, 1
 SPH_MODEL_LE, SPH_MODEL_NH, SPH_MODEL_J2 = 0, 1, 2
-SPH_SLOW_LOAD, SPH_SLOW_DIFFUSION = 0, 1
+SPH_SLOW_LOAD, SPH_SLOW_DIFFUSION, SPH_SLOW_DIFFUSION_COUPLED = 0, 1, 2
 SPH_FLAG_FIXED, SPH_FLAG_CDIR, SPH_FLAG_GRIP = 1, 2, 4
 
 EXPORTED = [
     "sph_build_neighbors", "sph_nbr_destroy", "sph_nbr_query", "sph_solid_relax_step",
-    "sph_damping_sweep", "sph_drift_ke", "sph_load_step", "sph_diffusion_step",
+    "sph_damping_sweep", "sph_drift_ke", "sph_load_step", "sph_diffusion_step", "sph_diffusion_step_coupled",
     "sph_advance_multirate", "sph_status", "sph_profile_enable", "sph_profile_classes", "sph_profile_read",
     "sph_last_error", "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_drift_vjp",
     "sph_diffusion_step_vjp", "sph_advance_multirate_backward", "sph_constitutive",
@@ -71,7 +71,8 @@ class State(C.Structure):
 class MultirateCfg(C.Structure):
     _fields_ = [("n_slow", i32), ("slow_kind", i32), ("dt_slow", dbl), ("dt_s", dbl), ("eta", dbl),
                 ("k_max", i64), ("fixed_inner", i64), ("ke_tol", dbl), ("D", dbl), ("c_bc", dbl),
-                ("chunk", i32), ("use_graph", i32), ("k_sched", vp), ("batch", vp)]
+                ("chunk", i32), ("use_graph", i32), ("k_sched", vp), ("batch", vp),
+                ("diff_nonlinear", i32), ("pad2_", i32)]
 
 
 class Batch(C.Structure):
@@ -125,6 +126,8 @@ def lib():
     L.sph_drift_ke.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp, vp]
     L.sph_load_step.argtypes = [vp, C.POINTER(State), dbl, vp]
     L.sph_diffusion_step.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, dbl, vp]
+    L.sph_diffusion_step_coupled.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, dbl,
+                                             i32, vp]
     L.sph_advance_multirate.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
                                         C.POINTER(MultirateCfg), C.POINTER(Report), C.POINTER(Tape), vp]
     L.sph_advance_multirate_backward.argtypes = [vp, C.POINTER(Material), C.POINTER(State),
@@ -352,6 +355,12 @@ def sph_load_step(nbr, st, dt_l, stream=None):
     _check(lib().sph_load_step(nbr.handle, C.byref(cs), float(dt_l), _stream(stream)))
 
 
+def sph_diffusion_step_coupled(nbr, mat, st, D, dt_d, c_bc, nonlinear=0, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_diffusion_step_coupled(nbr.handle, C.byref(mat), C.byref(cs), float(D), float(dt_d),
+                                            float(c_bc), int(nonlinear), _stream(stream)))
+
+
 def sph_diffusion_step(nbr, mat, st, D, dt_d, c_bc, stream=None):
     cs = st.cstruct(nbr)
     _check(lib().sph_diffusion_step(nbr.handle, C.byref(mat), C.byref(cs), float(D), float(dt_d),
@@ -365,10 +374,11 @@ def sph_status(nbr, stream=None):
 
 
 def multirate_cfg(n_slow, slow_kind, dt_slow=0.0, dt_s=0.0, eta=0.0, k_max=0, fixed_inner=0,
-                  ke_tol=0.0, D=0.0, c_bc=0.0, chunk=64, use_graph=0, k_sched=None, batch=None):
+                  ke_tol=0.0, D=0.0, c_bc=0.0, chunk=64, use_graph=0, k_sched=None, batch=None,
+                  diff_nonlinear=0):
     cfg = MultirateCfg(int(n_slow), int(slow_kind), float(dt_slow), float(dt_s), float(eta), int(k_max),
                        int(fixed_inner), float(ke_tol), float(D), float(c_bc), int(chunk), int(use_graph),
-                       None, None)
+                       None, None, int(diff_nonlinear), 0)
     if k_sched is not None:
         ks = np.ascontiguousarray(k_sched, dtype=np.int64)
         cfg._ks = ks

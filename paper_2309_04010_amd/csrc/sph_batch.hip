@@ -76,7 +76,7 @@ int batch_check(const sph_nbr* nb, const sph_multirate_cfg* cfg) {
               (long long)nb->n_spec);
     return SPH_E_ARG;
   }
-  if (!b->E || !b->dt_s || !b->dt_slow || (cfg->slow_kind == SPH_SLOW_DIFFUSION && !b->D)) {
+  if (!b->E || !b->dt_s || !b->dt_slow || (cfg->slow_kind != SPH_SLOW_LOAD && !b->D)) {
     set_error("cfg->batch arrays missing");
     return SPH_E_ARG;
   }
@@ -101,7 +101,7 @@ int batch_upload(const sph_nbr* nb, const sph_material* m, const sph_multirate_c
     const double dt = b->dt_s[i] > 0.0 ? b->dt_s[i] : 0.6 * nb->h / std::sqrt(K / m->rho0);
     const double D = b->D ? b->D[i] : cfg->D;
     double dtd = b->dt_slow[i];
-    if (!(dtd > 0.0)) dtd = cfg->slow_kind == SPH_SLOW_DIFFUSION ? 0.5 * nb->h * nb->h / D : cfg->dt_slow;
+    if (!(dtd > 0.0)) dtd = cfg->slow_kind != SPH_SLOW_LOAD ? 0.5 * nb->h * nb->h / D : cfg->dt_slow;
     const double v[BT_COUNT] = {mu, K, K - 2.0 * mu / 3.0, dt, dtd, D, cfg->eta * dt};
     for (int f = 0; f < BT_COUNT; ++f) {
       t64[f * ns + i] = v[f];

@@ -279,6 +279,8 @@ int damp_prepare(const sph_nbr* nb, const sph_material* m, const sph_state* st, 
 int drift_ke(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
              double* ke_out, hipStream_t s, bool gated);
 int load_step(const sph_nbr* nb, const sph_state* st, double dt_l, hipStream_t s);
+int diffusion_step_coupled(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                           double D, double dt, double c_bc, int nonlinear, hipStream_t s);
 int diffusion_step(const sph_nbr* nb, const sph_material* m, const sph_state* st, double D,
                    double dt_d, double c_bc, hipStream_t s);
 int reset_ctrl(const sph_nbr* nb, int64_t k_limit, double ke_tol, hipStream_t s);

@@ -161,7 +161,7 @@ int check_tape(const sph_nbr* nb, const sph_material* m, const sph_state* st,
     return SPH_E_CAPACITY;
   }
   if (!tp->ck_u || !tp->ck_v || !tp->k_rec || (m->model == SPH_MODEL_J2 && !tp->ck_plastic) ||
-      (cfg->slow_kind == SPH_SLOW_DIFFUSION && (!tp->ck_c || !st->c))) {
+      (cfg->slow_kind != SPH_SLOW_LOAD && (!tp->ck_c || !st->c))) {
     set_error("tape checkpoint arrays missing");
     return SPH_E_ARG;
   }
@@ -239,6 +239,19 @@ extern "C" int sph_load_step(const sph_nbr* nb, const sph_state* st, double dt_l
   return load_step(nb, st, dt_l, (hipStream_t)stream);
 }
 
+extern "C" int sph_diffusion_step_coupled(const sph_nbr* nb, const sph_material* mat,
+                                          const sph_state* st, double D, double dt_d, double c_bc,
+                                          int32_t nonlinear, void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!mat) {
+    set_error("material is NULL");
+    return SPH_E_ARG;
+  }
+  return diffusion_step_coupled(nb, mat, st, D, dt_d, c_bc, nonlinear, (hipStream_t)stream);
+}
+
 extern "C" int sph_diffusion_step(const sph_nbr* nb, const sph_material* mat, const sph_state* st,
                                   double D, double dt_d, double c_bc, void* stream) {
   clear_error();
@@ -282,14 +295,15 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     set_error("material or cfg is NULL");
     return SPH_E_ARG;
   }
-  if (cfg->n_slow < 0 || (cfg->slow_kind != SPH_SLOW_LOAD && cfg->slow_kind != SPH_SLOW_DIFFUSION)) {
+  if (cfg->n_slow < 0 || (cfg->slow_kind != SPH_SLOW_LOAD && cfg->slow_kind != SPH_SLOW_DIFFUSION &&
+                           cfg->slow_kind != SPH_SLOW_DIFFUSION_COUPLED)) {
     set_error("bad n_slow or slow_kind");
     return SPH_E_ARG;
   }
   const double K = m->E / (3.0 * (1.0 - 2.0 * m->nu));
   const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * nb->h / std::sqrt(K / m->rho0);
   double dt_slow = cfg->dt_slow;
-  if (cfg->slow_kind == SPH_SLOW_DIFFUSION && !(dt_slow > 0.0)) {
+  if (cfg->slow_kind != SPH_SLOW_LOAD && !(dt_slow > 0.0)) {
     if (!(cfg->D > 0.0)) {
       set_error("diffusion needs D > 0");
       return SPH_E_ARG;
@@ -345,6 +359,8 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     if (tape && (rc = tape_copy(nb, m, st, tape, l, true, s))) break;
     if (cfg->slow_kind == SPH_SLOW_LOAD)
       rc = load_step(nb, st, dt_slow, s);
+    else if (cfg->slow_kind == SPH_SLOW_DIFFUSION_COUPLED)
+      rc = diffusion_step_coupled(nb, m, st, cfg->D, dt_slow, cfg->c_bc, cfg->diff_nonlinear, s);
     else
       rc = diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
     if (rc) break;
@@ -511,6 +527,10 @@ int check_backward_args(const sph_nbr* nb, const sph_material* m, const sph_stat
     set_error("material, cfg, tape or adjoint is NULL");
     return SPH_E_ARG;
   }
+  if (cfg->slow_kind == SPH_SLOW_DIFFUSION_COUPLED) {
+    set_error("the reverse pass covers the loading and linear diffusion slow steps only");
+    return SPH_E_UNSUPPORTED;
+  }
   if (adj->prec != st->prec || !adj->u || !adj->v || !adj->work || !adj->grad ||
       (m->model == SPH_MODEL_J2 && !adj->plastic) ||
       (cfg->slow_kind == SPH_SLOW_DIFFUSION && !adj->c)) {
@@ -623,7 +643,7 @@ extern "C" int sph_advance_multirate_graph(const sph_nbr* nb, const sph_material
   if (rc) return rc;
   if (!m || !cfg || cfg->n_slow < 0 ||
       (cfg->slow_kind != SPH_SLOW_LOAD && cfg->slow_kind != SPH_SLOW_DIFFUSION)) {
-    set_error("bad material or cfg");
+    set_error("bad material or cfg (the whole-run graph takes loading and linear diffusion steps)");
     return SPH_E_ARG;
   }
   if (cfg->k_sched == nullptr && cfg->fixed_inner <= 0) {

@@ -620,12 +620,167 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff_grad(Geo<T> g, const T* __r
   }
 }
 
+// determinant and inverse of a D x D matrix (row-major)
+template <typename T, int D>
+__device__ __forceinline__ T det_d(const T* A) {
+  if constexpr (D == 2) return A[0] * A[3] - A[1] * A[2];
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+template <typename T, int D>
+__device__ __forceinline__ void inv_d(const T* A, T det, T* Ai) {
+  if constexpr (D == 2) {
+    Ai[0] = A[3] / det;
+    Ai[1] = -A[1] / det;
+    Ai[2] = -A[2] / det;
+    Ai[3] = A[0] / det;
+  } else {
+    Ai[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+    Ai[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    Ai[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    Ai[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+    Ai[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    Ai[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    Ai[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+    Ai[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    Ai[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+  }
+}
+
+// coupled diffusion, first pass: the deformation gradient F = I + H with
+// H = (sum_b V_b (u_b - u_a) (x) grad0 W_ab) B0_a (eq. deformationtensor-
+// displacement), kept as F^-1 in Fi [D*D][n], and the saturation c / det F
+// in sat [n]
+template <typename T, int D>
+__global__ __launch_bounds__(kDiffBlock) void k_diff_F(Geo<T> g, const double* __restrict__ u,
+                                                       const T* __restrict__ c, T* __restrict__ Fi,
+                                                       T* __restrict__ sat) {
+  constexpr int L = kDiffLanes;
+  const int64_t n = g.n;
+  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
+  const int h = threadIdx.x % L;
+  if (a >= n) return;  // the whole lane group
+  double xa[D], ua[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    xa[k] = g.X[k * n + a];
+    ua[k] = u[k * n + a];
+  }
+  T G[D * D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) G[i] = T(0);
+  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
+    const uint32_t b = g.idx[j];
+    T d[D], du[D];
+    T r2 = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      d[k] = (T)(xa[k] - g.X[k * n + b]);
+      du[k] = (T)(u[k * n + b] - ua[k]);
+      r2 += d[k] * d[k];
+    }
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) G[i * D + k] += w * du[i] * d[k];
+  }
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) G[i] = lane_sum<L>(G[i]);
+  if (h != 0) return;
+  T F[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) acc += G[i * D + l] * g.B0[(l * D + k) * n + a];
+      F[i * D + k] = (i == k ? T(1) : T(0)) + acc;
+    }
+  const T J = det_d<T, D>(F);
+  T Fin[D * D];
+  inv_d<T, D>(F, J, Fin);
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) Fi[i * n + a] = Fin[i];
+  sat[a] = c[a] / J;
+}
+
+// coupled diffusion, flux: g = F^-T B0 sum_b V_b (a_b - a_a) grad0 W (the
+// current-configuration gradient of the saturation a), q = -D w g with w = a
+// (nonlinear) or 1, stored as the reference (Piola) flux J F^-1 q
+template <typename T, int D>
+__global__ __launch_bounds__(kDiffBlock) void k_diff_grad_coupled(Geo<T> g, const T* __restrict__ sat,
+                                                                  const T* __restrict__ Fi,
+                                                                  T* __restrict__ q, T Dc,
+                                                                  int nonlinear, Bat bt) {
+  constexpr int L = kDiffLanes;
+  const int64_t n = g.n;
+  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
+  const int h = threadIdx.x % L;
+  if (a >= n) return;
+  double xa[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
+  const T sa = sat[a];
+  T s[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) s[k] = T(0);
+  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
+    const uint32_t b = g.idx[j];
+    T d[D];
+    T r2 = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      d[k] = (T)(xa[k] - g.X[k * n + b]);
+      r2 += d[k] * d[k];
+    }
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b] * (sat[b] - sa);
+#pragma unroll
+    for (int k = 0; k < D; ++k) s[k] += w * d[k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) s[k] = lane_sum<L>(s[k]);
+  if (h != 0) return;
+  T Fa[D * D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) Fa[i] = Fi[i * n + a];
+  const T J = T(1) / det_d<T, D>(Fa);
+  T gr[D], gc[D], qc[D];
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc += g.B0[(m * D + k) * n + a] * s[k];
+    gr[m] = acc;
+  }
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc += Fa[k * D + m] * gr[k];  // F^-T
+    gc[m] = acc;
+  }
+  const T Da = bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc;
+  const T wa = nonlinear ? sa : T(1);
+#pragma unroll
+  for (int m = 0; m < D; ++m) qc[m] = -Da * wa * gc[m];
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc += Fa[m * D + k] * qc[k];  // F^-1
+    q[m * n + a] = J * acc;
+  }
+}
+
 // c += dt (-sum_b V_b (B0_a q_a + B0_b q_b) . grad W); Dirichlet; p = C (c - c0)
 template <typename T, int D>
 __global__ __launch_bounds__(kDiffBlock) void k_diff_div(Geo<T> g, T* __restrict__ c,
                                                          const T* __restrict__ q, T* __restrict__ p,
                                                          const uint8_t* __restrict__ flags, T dt,
-                                                         T c_bc, T Cs, T c0, Bat bt) {
+                                                         T c_bc, T Cs, T c0, Bat bt,
+                                                         const T* __restrict__ Fi) {
   constexpr int L = kDiffLanes;
   const int64_t n = g.n;
   const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
@@ -666,6 +821,16 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff_div(Geo<T> g, T* __restrict
   div = lane_sum<L>(div);
   if (h != 0) return;
   T cn = c[a] - (bt.spec ? bt.get<T>(BT_DTD, bt.spec[a]) : dt) * div;
+  if (Fi) {  // coupled: c is the content per reference volume, the saturation c / J
+    T Fa[D * D];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Fa[i] = Fi[i * n + a];
+    const T J = T(1) / det_d<T, D>(Fa);
+    if (flags && (flags[a] & SPH_FLAG_CDIR)) cn = c_bc * J;
+    c[a] = cn;
+    if (p) p[a] = Cs * (cn / J - c0);
+    return;
+  }
   if (flags && (flags[a] & SPH_FLAG_CDIR)) cn = c_bc;
   c[a] = cn;
   if (p) p[a] = Cs * (cn - c0);
@@ -945,11 +1110,53 @@ static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_DIV, s);
     k_diff_div<T, D><<<nblk(nb->n, kDiffPerBlock), kDiffBlock, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
                                                     st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
-                                                    (T)m->c0, bat_view(nb));
+                                                    (T)m->c0, bat_view(nb), nullptr);
     prof_end(nb, SPH_KERNEL_DIFF_DIV, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   return SPH_OK;
+}
+
+// two-way coupled form: deformation pass (F^-1 into the PB scratch, the
+// saturation into p), flux, then the divergence with the J-aware epilogue
+template <typename T, int D>
+static int diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                               double Dc, double dt, double c_bc, int nonlinear, hipStream_t s) {
+  Geo<T> g = geo<T>(nb);
+  const unsigned gr = nblk(nb->n, kDiffPerBlock);
+  T* Fi = (T*)st->PB;
+  T* sat = (T*)st->p;
+  {
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_GRAD, s);
+    k_diff_F<T, D><<<gr, kDiffBlock, 0, s>>>(g, st->u, (const T*)st->c, Fi, sat);
+    SPH_LAUNCH_CHECK();
+    k_diff_grad_coupled<T, D><<<gr, kDiffBlock, 0, s>>>(g, sat, Fi, (T*)st->q, (T)Dc, nonlinear,
+                                                        bat_view(nb));
+    prof_end(nb, SPH_KERNEL_DIFF_GRAD, pe_, s);
+  }
+  SPH_LAUNCH_CHECK();
+  {
+    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_DIV, s);
+    k_diff_div<T, D><<<gr, kDiffBlock, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p, st->flags,
+                                               (T)dt, (T)c_bc, (T)m->C_swell, (T)m->c0,
+                                               bat_view(nb), Fi);
+    prof_end(nb, SPH_KERNEL_DIFF_DIV, pe_, s);
+  }
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+int diffusion_step_coupled(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                           double Dc, double dt, double c_bc, int nonlinear, hipStream_t s) {
+  if (!st->c || !st->q || !st->p || !st->PB) {
+    set_error("coupled diffusion needs c, q, p and the PB scratch");
+    return SPH_E_ARG;
+  }
+  if (st->prec == SPH_F64)
+    return nb->dim == 2 ? diffusion_coupled_t<double, 2>(nb, m, st, Dc, dt, c_bc, nonlinear, s)
+                        : diffusion_coupled_t<double, 3>(nb, m, st, Dc, dt, c_bc, nonlinear, s);
+  return nb->dim == 2 ? diffusion_coupled_t<float, 2>(nb, m, st, Dc, dt, c_bc, nonlinear, s)
+                      : diffusion_coupled_t<float, 3>(nb, m, st, Dc, dt, c_bc, nonlinear, s);
 }
 
 int diffusion_step(const sph_nbr* nb, const sph_material* m, const sph_state* st, double Dc,
