@@ -255,6 +255,48 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
     return info, prof
 
 
+def run_coupled(case, torch, B, reps=10):
+    """The slow step's variants on the same deformed FP32 state: the
+    reference-configuration step, and the two-way coupled step with the
+    linear and the nonlinear flux.  Per variant: average wall time of one
+    slow step over `reps` back-to-back calls, and the per-class kernel times
+    of one further profiled call."""
+    import numpy as np
+    nb, st = setup(case, B.SPH_F32, torch, B)
+    mat = B.material(**case.material)
+    run = dict(case.run)
+    run.update(n_slow=1, fixed_inner=200)
+    B.sph_advance_multirate(nb, mat, st, B.multirate_cfg(**run, chunk=200, use_graph=0))
+    Dc, dtd, cbc = run["D"], 0.5 * case.h ** 2 / run["D"], run["c_bc"]
+    c_keep = st.c.clone()
+    variants = {
+        "reference": lambda: B.sph_diffusion_step(nb, mat, st, Dc, dtd, cbc),
+        "coupled_linear": lambda: B.sph_diffusion_step_coupled(nb, mat, st, Dc, dtd, cbc, 0),
+        "coupled_nonlinear": lambda: B.sph_diffusion_step_coupled(nb, mat, st, Dc, dtd, cbc, 1),
+    }
+    out = {}
+    for name, call in variants.items():
+        st.c.copy_(c_keep)
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        us = 1e6 * (time.perf_counter() - t0) / reps
+        B.sph_profile_enable(nb, True)
+        call()
+        prof = B.sph_profile_read(nb)
+        B.sph_profile_enable(nb, False)
+        out[name] = dict(us_per_slow_step=us,
+                         kernels_us={k: 1000.0 * ms for k, (c, ms) in prof.items() if c})
+    out["c_finite"] = bool(torch.isfinite(st.c).all().item())
+    out["note"] = ("one slow step on the relaxed plate (200 inner steps), FP32; "
+                   "diff_grad of the coupled step includes its deformation pass")
+    nb.close()
+    return out
+
+
 def run_sweep(torch, B, launches=2):
     """The batched parameter sweep: 64 strips of log-uniform size (1e3-5e4
     particles), each with its own E and D, 10 diffusion slow steps x 200
@@ -330,6 +372,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nx", type=int, default=500)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -412,6 +455,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    coupled = None
+    if not args.no_coupled:
+        coupled = run_coupled(case, torch, B)
+        print("[bench] slow-step variants done", flush=True)
+
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep(torch, B)
@@ -448,6 +496,7 @@ def main():
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
         "accuracy": accuracy,
         "batched_sweep": sweep,
+        "slow_step_variants": coupled,
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,

@@ -107,3 +107,14 @@ def test_full_size_steps(plate, prec):
     B.sph_diffusion_step(nb, mg, st, Dc, dtd, c.run["c_bc"])
     assert rel_err(host(st.c) - cc, co - cc) < tol
     assert rel_err(host(st.p), po) < tol
+
+    # two-way coupled diffusion (nonlinear flux) from the deformed state
+    print(f"[fullsize] coupled diffusion prec={prec}", flush=True)
+    u3, c3 = host(st.u), host(st.c)
+    co = c3.copy()
+    qo, po = o.arr(3, c.n), o.arr(c.n)
+    o.diffusion_step_coupled(Dc, dtd, c.run["c_bc"], m["C_swell"], m["c0"], 1,
+                             np.ascontiguousarray(u3), co, qo, po, flags)
+    B.sph_diffusion_step_coupled(nb, mg, st, Dc, dtd, c.run["c_bc"], nonlinear=1)
+    assert rel_err(host(st.c) - c3, co - c3) < tol
+    assert rel_err(host(st.p), po) < tol
