@@ -75,7 +75,7 @@ def _lib(cplx: bool):
     lib.orc_diffusion_step_coupled.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, C.c_int,
                                                vp, vp, vp, vp, vp]
     lib.orc_advance.restype = i32
-    lib.orc_advance.argtypes = [vp] * 15
+    lib.orc_advance.argtypes = [vp] * 16
     _cache[cplx] = lib
     return lib
 
@@ -284,7 +284,9 @@ class Oracle:
                                             _ptr(self._a(p)), _ptr(flags))
 
     def advance(self, mat, cfg, u, v, plastic=None, c=None, q=None, p=None, vgrip=None, flags=None,
-                k_sched=None):
+                k_sched=None, acc=None):
+        """Multi-time-step run; `acc` ([d, n], optional) receives the last
+        inner step's momentum sum per unit mass, fixed particles included."""
         k_out = np.zeros(cfg.n_slow, np.int64)
         ke_out = np.zeros(cfg.n_slow)
         conv = np.zeros(cfg.n_slow, np.int32)
@@ -293,5 +295,5 @@ class Oracle:
         rc = self.lib.orc_advance(self._h, C.byref(mat), C.byref(cfg), _ptr(self._a(u)), _ptr(self._a(v)),
                                   _ptr(self._a(plastic)), _ptr(self._a(c)), _ptr(self._a(q)), _ptr(self._a(p)),
                                   _ptr(self._a(vgrip)), _ptr(flags), _ptr(k_sched), _ptr(k_out), _ptr(ke_out),
-                                  _ptr(conv))
+                                  _ptr(conv), _ptr(self._a(acc)))
         return rc, k_out, ke_out, conv

@@ -989,7 +989,7 @@ void orc_diffusion_step_coupled(const orc_sys* s, real D, double dt_d, double c_
 int orc_advance(const orc_sys* s, const orc_material* m, const orc_cfg* cfg, real* u, real* v,
                 real* plastic, real* c, real* q, real* p, const real* vgrip,
                 const uint8_t* flags, const int64_t* k_sched, int64_t* k_out, double* ke_out,
-                int32_t* conv_out) {
+                int32_t* conv_out, real* acc_out) {
   double K = RE(m->E) / (3.0 * (1.0 - 2.0 * m->nu));
   double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * s->h / sqrt(K / m->rho0);
   double dt_slow = cfg->dt_slow;
@@ -1010,7 +1010,7 @@ int orc_advance(const orc_sys* s, const orc_material* m, const orc_cfg* cfg, rea
     real ke = 0.0;
     int conv = 0;
     while (k < nk) {
-      int r = orc_solid_step(s, m, dt_s, u, v, plastic, p, flags, NULL, NULL);
+      int r = orc_solid_step(s, m, dt_s, u, v, plastic, p, flags, NULL, acc_out);
       if (r) rc = r;
       orc_damping_sweep(s, m->rho0, cfg->eta, dt_s, v, flags);
       ke = orc_drift_ke(s, m->rho0, dt_s, u, v, flags);

@@ -106,9 +106,11 @@ void orc_diffusion_step(const orc_sys* s, real D, double dt_d, double c_bc, real
 void orc_diffusion_step_coupled(const orc_sys* s, real D, double dt_d, double c_bc, real C_swell,
                                 double c0, int nonlinear, const real* u, real* c, real* q, real* p,
                                 const uint8_t* flags);
-/* multi-time-step driver; k_sched (optional) freezes the inner counts */
+/* multi-time-step driver; k_sched (optional) freezes the inner counts;
+   acc_out (optional, [d][n]) receives the momentum sum per unit mass of the
+   last inner step, fixed particles included (their reaction) */
 int orc_advance(const orc_sys* s, const orc_material* m, const orc_cfg* cfg, real* u, real* v,
                 real* plastic, real* c, real* q, real* p, const real* vgrip,
                 const uint8_t* flags, const int64_t* k_sched, int64_t* k_out, double* ke_out,
-                int32_t* conv_out);
+                int32_t* conv_out, real* acc_out);
 #endif

@@ -14,6 +14,8 @@ and parameter values of the five benchmark workloads:
   strip2d   2D strip 200 x 10, neo-Hookean + swelling, diffusion from the top.
   neck3d    3D bar 100 x 20 x 20, J2 nonlinear hardening, symmetric pull.
   plate3d   3D plate 500 x 500 x 4, neo-Hookean + swelling, diffusion patch.
+  necking2d the paper's 2D necking bar (53.334 x 12.826 mm, 1.8% imperfection).
+  necking3d the paper's 3D necking cylinder (r 6.413 mm, 53.334 mm, dp 0.3 mm).
   strips2d  64 strips of log-uniform sizes (batched parameter sweep).
 
 Damping viscosity eta: the bars use the paper's 1e4.  For the swelling strip
@@ -172,6 +174,131 @@ def neck3d(nx=100, ny=20, nz=20, dp=0.53334e-3, grip_layers=3, total_stretch=7.0
                      fixed_inner=fixed_inner, D=0.0, c_bc=0.0))
 
 
+# Necking table (Sec. 5.1): shear and bulk moduli, initial and saturation flow
+# stress, saturation exponent, linear hardening coefficient
+NECK_TABLE = dict(mu=80.1938e9, K=164.21e9, sigma0=450.0e6, sigma_inf=715.0e6, delta=16.93,
+                  H=129.24e6)
+NECK_LENGTH, NECK_WIDTH, NECK_RADIUS = 53.334e-3, 12.826e-3, 6.413e-3
+
+
+def _neck_material(rho0=7850.0):
+    t = NECK_TABLE
+    mu, K = t["mu"], t["K"]
+    E = 9.0 * K * mu / (3.0 * K + mu)
+    nu = (3.0 * K - 2.0 * mu) / (2.0 * (3.0 * K + mu))
+    return dict(model=J2, E=E, nu=nu, rho0=rho0, sigma0=t["sigma0"], sigma_inf=t["sigma_inf"],
+                delta=t["delta"], H=t["H"])
+
+
+def _taper(x, x_c, half_length, imperfection):
+    """Cross-section scale of the imperfect specimen: 1 - imperfection at the
+    centre, rising linearly to 1 at the specimen's ends (and beyond)."""
+    return 1.0 - imperfection * np.clip(1.0 - np.abs(x - x_c) / half_length, 0.0, 1.0)
+
+
+def _neck_run(n_slow, t_end, inner, eta):
+    return dict(n_slow=n_slow, slow_kind=LOAD, dt_slow=t_end / n_slow, eta=eta, ke_tol=0.0,
+                k_max=0, fixed_inner=inner, D=0.0, c_bc=0.0)
+
+
+def necking2d(across=50, grip_layers=3, total_stretch=10.0e-3, t_end=100.0, n_slow=10000,
+              inner=33, eta=1.0e4, imperfection=0.018):
+    """2D tensile necking bar (Sec. 5.1), plane strain.
+
+    The specimen is 53.334 x 12.826 mm with dp = width / `across` (0.25652 mm
+    at 50), its width reduced by `imperfection` at the centre, tapering
+    linearly to the full width at its ends: y is scaled about the centre line
+    and the volumes with it.  `grip_layers` extra columns at each end are
+    the grips, pulled apart symmetrically at total_stretch / (2 t_end) each.
+    Loading is displacement control in `n_slow` increments; every increment
+    is followed by `inner` relaxation steps (see the workload notes for why a
+    fixed count).  Observables, as weights: the reaction force per unit depth
+    on the right grip (`w_acc`, applied to the momentum sum per unit mass of
+    the last inner step) and the inward displacement of the width at the
+    centre section, averaged over its top and bottom particles (`w_u`)."""
+    _sizes_ok((across,))
+    dp = NECK_WIDTH / across
+    nxs = int(round(NECK_LENGTH / dp))
+    nx, ny = nxs + 2 * grip_layers, across
+    X, idx = lattice((nx, ny), dp)
+    n = X.shape[1]
+    x_c, y_c = 0.5 * nx * dp, 0.5 * ny * dp
+    s = _taper(X[0], x_c, 0.5 * nxs * dp, imperfection)
+    X[1] = y_c + (X[1] - y_c) * s
+    V = dp * dp * s
+    mat = _neck_material()
+    flags = np.zeros(n, np.uint8)
+    vgrip = np.zeros((2, n))
+    left = idx[0] < grip_layers
+    right = idx[0] >= nx - grip_layers
+    flags[left | right] = FIXED | GRIP
+    v_pull = 0.5 * total_stretch / t_end
+    vgrip[0, left] = -v_pull
+    vgrip[0, right] = v_pull
+    w_acc = np.zeros((2, n))
+    w_acc[0, right] = -mat["rho0"] * V[right]
+    centre = np.isin(idx[0], [(nx - 1) // 2, nx // 2])
+    top, bot = centre & (idx[1] == ny - 1), centre & (idx[1] == 0)
+    w_u = np.zeros((2, n))
+    w_u[1, top] = -0.5 / top.sum()
+    w_u[1, bot] = 0.5 / bot.sum()
+    return Case("necking2d", 2, (nx, ny), dp, X, V, 1.3 * dp, flags, vgrip, None, mat,
+                _neck_run(n_slow, t_end, inner, eta),
+                dict(w_acc=w_acc, w_u=w_u, v_pull=v_pull, length=nxs * dp, width=NECK_WIDTH,
+                     radius=0.5 * NECK_WIDTH, total_stretch=total_stretch,
+                     J_index=np.nonzero(top)[0], J_component=1))
+
+
+def necking3d(dp=0.3e-3, grip_layers=3, total_stretch=14.0e-3, t_end=100.0, n_slow=10000,
+              inner=32, eta=1.0e4, imperfection=0.018):
+    """3D tensile necking cylinder (Sec. 5.2): radius 6.413 mm, length
+    53.334 mm, axis along x.  Particles are the cubic-lattice sites (spacing
+    dp, sites at half-integer offsets from the axis) within the radius; the
+    radius is reduced by `imperfection` at the centre, tapering linearly to
+    the ends (y, z scaled about the axis, volumes by the square of the
+    scale).  `grip_layers` extra slices at each end are the grips, pulled
+    apart at total_stretch / (2 t_end) each (0.7e-4 m/s, 7 mm per end).
+    Observables: the reaction force on the right grip (`w_acc`) and the
+    inward radial displacement of the outer ring of the centre section
+    (`w_u`)."""
+    R = NECK_RADIUS
+    m = int(np.ceil(R / dp))
+    nxs = int(round(NECK_LENGTH / dp))
+    nx = nxs + 2 * grip_layers
+    Xb, idx = lattice((nx, 2 * m, 2 * m), dp)
+    yz = Xb[1:] - m * dp
+    rho = np.sqrt((yz ** 2).sum(axis=0))
+    keep = rho <= R
+    X = np.ascontiguousarray(np.vstack([Xb[:1], yz])[:, keep])
+    idx = idx[:, keep]
+    rho = rho[keep]
+    n = X.shape[1]
+    x_c = 0.5 * nx * dp
+    s = _taper(X[0], x_c, 0.5 * nxs * dp, imperfection)
+    X[1:] *= s
+    V = dp ** 3 * s * s
+    mat = _neck_material()
+    flags = np.zeros(n, np.uint8)
+    vgrip = np.zeros((3, n))
+    left = idx[0] < grip_layers
+    right = idx[0] >= nx - grip_layers
+    flags[left | right] = FIXED | GRIP
+    v_pull = 0.5 * total_stretch / t_end
+    vgrip[0, left] = -v_pull
+    vgrip[0, right] = v_pull
+    w_acc = np.zeros((3, n))
+    w_acc[0, right] = -mat["rho0"] * V[right]
+    centre = np.isin(idx[0], [(nx - 1) // 2, nx // 2])
+    ring = centre & (rho > rho[centre].max() - 0.5 * dp)
+    w_u = np.zeros((3, n))
+    w_u[1, ring] = -(X[1, ring] / np.sqrt(X[1, ring] ** 2 + X[2, ring] ** 2)) / ring.sum()
+    w_u[2, ring] = -(X[2, ring] / np.sqrt(X[1, ring] ** 2 + X[2, ring] ** 2)) / ring.sum()
+    return Case("necking3d", 3, (nx, 2 * m, 2 * m), dp, X, V, 1.3 * dp, flags, vgrip, None, mat,
+                _neck_run(n_slow, t_end, inner, eta),
+                dict(w_acc=w_acc, w_u=w_u, v_pull=v_pull, length=nxs * dp, radius=R,
+                     total_stretch=total_stretch, J_index=np.nonzero(ring)[0], J_component=1))
+
+
 def plate3d(nx=500, ny=500, nz=4, dp=31.25e-6, clamp_layers=3, patch=0.3, wet_layers=2,
             E=100.0e6, nu=0.4, D=1.0e-10, C_swell=3.0e6, n_slow=50, fixed_inner=1000,
             eta=20.0):
@@ -273,4 +400,5 @@ def batch(cs, gap_dp=4.0, stack=True):
 
 
 def by_name(name, **kw):
-    return {"bar2d": bar2d, "strip2d": strip2d, "neck3d": neck3d, "plate3d": plate3d}[name](**kw)
+    return {"bar2d": bar2d, "strip2d": strip2d, "neck3d": neck3d, "plate3d": plate3d,
+            "necking2d": necking2d, "necking3d": necking3d}[name](**kw)
