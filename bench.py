@@ -297,6 +297,47 @@ def run_coupled(case, torch, B, reps=10):
     return out
 
 
+def run_necking(name, prec, n_slow, torch, B, record_every=100):
+    """A necking run (Sec. 5.1 / 5.2) of `n_slow` of the case's load
+    increments on the GPU: iteration counts as in the paper's efficiency
+    tables, wall time, and the reaction-force / neck-displacement curve."""
+    import numpy as np
+    from paper_2309_04010_amd import cases
+    from paper_2309_04010_amd.necking import NeckingRun
+    c = cases.by_name(name)
+    r = NeckingRun(c, prec, record_every=record_every)
+    def progress(done, F, dr):
+        if done % 2000 == 0:
+            print(f"[bench] {name}: {done} load increments, reaction {F:.4g}, neck {dr:.4g}", flush=True)
+
+    try:
+        res = r.run(n_slow=n_slow, progress=progress)
+    finally:
+        r.close()
+    h = res["history"]
+    m = c.material
+    K = m["E"] / (3.0 * (1.0 - 2.0 * m["nu"]))
+    dt_s = 0.6 * c.h / (K / m["rho0"]) ** 0.5
+    t_end = c.run["dt_slow"] * c.run["n_slow"]
+    ipk = int(np.argmax(h["reaction"]))
+    stride = max(1, len(h["increment"]) // 20)
+    return dict(
+        workload=f"{name}: {res['N_p']} particles, {res['pairs']} directed pairs, J2 (necking table), "
+                 f"{c.run['fixed_inner']} relaxation steps per load increment, "
+                 f"{'FP64' if prec == B.SPH_F64 else 'FP32 bulk / FP64 displacement'}",
+        N_p=res["N_p"], N_S=res["N_S"], N_s=res["N_s"], N_d=res["N_d"],
+        N_S_paper_run=c.run["n_slow"], fraction_of_paper_run=res["N_S"] / c.run["n_slow"],
+        straightforward_N_s=t_end / dt_s,
+        seconds=res["seconds"], us_per_inner_step=1e6 * res["seconds"] / max(res["N_s"], 1),
+        interactions_per_s=res["interactions_per_s"], status_bits=res["status_bits"],
+        reaction_unit="N per metre of depth" if c.dim == 2 else "N",
+        peak_reaction=float(h["reaction"][ipk]), stretch_at_peak=float(h["stretch"][ipk]),
+        final_stretch=float(h["stretch"][-1]), final_reaction=float(h["reaction"][-1]),
+        final_neck_displacement=float(h["radius"][-1]),
+        curve_stretch_reaction_neck=[[float(h["stretch"][i]), float(h["reaction"][i]), float(h["radius"][i])]
+                                     for i in range(stride - 1, len(h["increment"]), stride)])
+
+
 def run_sweep(torch, B, launches=2):
     """The batched parameter sweep: 64 strips of log-uniform size (1e3-5e4
     particles), each with its own E and D, 10 diffusion slow steps x 200
@@ -373,6 +414,9 @@ def main():
     ap.add_argument("--nx", type=int, default=500)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
+    ap.add_argument("--necking", choices=["none", "sample", "full"], default="sample",
+                    help="necking runs: sample = the full 2D run and the first 1000 load increments "
+                         "of the 3D one; full = both full runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -460,6 +504,14 @@ def main():
         coupled = run_coupled(case, torch, B)
         print("[bench] slow-step variants done", flush=True)
 
+    necking = None
+    if args.necking != "none":
+        necking = {}
+        for name, n3 in (("necking2d", None), ("necking3d", None if args.necking == "full" else 1000)):
+            necking[name] = run_necking(name, B.SPH_F64 if name == "necking2d" else B.SPH_F32, n3,
+                                        torch, B)
+            print(f"[bench] {name} done: {necking[name]['seconds']:.1f} s", flush=True)
+
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep(torch, B)
@@ -497,6 +549,7 @@ def main():
         "accuracy": accuracy,
         "batched_sweep": sweep,
         "slow_step_variants": coupled,
+        "necking": necking,
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,
