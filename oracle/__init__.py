@@ -64,12 +64,13 @@ def _lib(cplx: bool):
     lib.orc_displacement_gradient.argtypes = [vp, vp, vp]
     lib.orc_stress.restype = i32
     lib.orc_stress.argtypes = [vp] * 7
-    lib.orc_momentum.argtypes = [vp] * 4
+    lib.orc_momentum.argtypes = [vp] * 5
+    lib.orc_mixture_flux.argtypes = [vp] * 7
     lib.orc_solid_step.restype = i32
-    lib.orc_solid_step.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]
-    lib.orc_damping_sweep.argtypes = [vp, dbl, dbl, dbl, vp, vp]
+    lib.orc_solid_step.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_damping_sweep.argtypes = [vp, dbl, dbl, dbl, vp, vp, dbl, vp]
     lib.orc_drift_ke.restype = _real_t(cplx)
-    lib.orc_drift_ke.argtypes = [vp, dbl, dbl, vp, vp, vp]
+    lib.orc_drift_ke.argtypes = [vp, dbl, dbl, vp, vp, vp, dbl, vp]
     lib.orc_load_step.argtypes = [vp, dbl, vp, vp, vp]
     lib.orc_diffusion_step.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, vp, vp, vp, vp]
     lib.orc_diffusion_step_coupled.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, C.c_int,
@@ -101,7 +102,7 @@ def _material_t(cplx):
     class Material(C.Structure):
         _fields_ = [("model", C.c_int32), ("pad_", C.c_int32), ("E", R), ("nu", C.c_double),
                     ("rho0", C.c_double), ("sigma0", R), ("sigma_inf", R), ("delta", R), ("H", R),
-                    ("C_swell", R), ("c0", C.c_double)]
+                    ("C_swell", R), ("c0", C.c_double), ("rho_l0", C.c_double)]
     return Material
 
 
@@ -191,11 +192,11 @@ class Oracle:
         return x
 
     def material(self, model, E, nu, rho0, sigma0=0.0, sigma_inf=0.0, delta=0.0, H=0.0,
-                 C_swell=0.0, c0=0.0):
+                 C_swell=0.0, c0=0.0, rho_l0=0.0):
         M = _material_t(self.cplx)
         r = lambda x: _to_real(x, self.cplx)  # noqa: E731
         return M(int(model), 0, r(E), float(nu), float(rho0), r(sigma0), r(sigma_inf), r(delta),
-                 r(H), r(C_swell), float(c0))
+                 r(H), r(C_swell), float(c0), float(rho_l0))
 
     def cfg(self, n_slow, slow_kind, dt_slow, dt_s=0.0, eta=0.0, k_max=0, fixed_inner=0, ke_tol=0.0,
             D=0.0, c_bc=0.0, nonlinear=0):
@@ -247,24 +248,31 @@ class Oracle:
                                  _ptr(self._a(p)), _ptr(P9), _ptr(PB))
         return rc, P9, PB
 
-    def momentum(self, mat, PB):
+    def momentum(self, mat, PB, c=None):
         acc = self.arr(self.dim, self.n)
-        self.lib.orc_momentum(self._h, C.byref(mat), _ptr(self._a(PB)), _ptr(acc))
+        self.lib.orc_momentum(self._h, C.byref(mat), _ptr(self._a(PB)), _ptr(self._a(c)), _ptr(acc))
         return acc
 
-    def solid_step(self, mat, dt, u, v, plastic=None, p=None, flags=None):
+    def mixture_flux(self, mat, H9, v, c, q, PB):
+        """PB -= rho_l0 v^l (x) Q B0 in place (mixture momentum flux)."""
+        self.lib.orc_mixture_flux(self._h, C.byref(mat), _ptr(self._a(H9)), _ptr(self._a(v)),
+                                  _ptr(self._a(c)), _ptr(self._a(q)), _ptr(self._a(PB)))
+
+    def solid_step(self, mat, dt, u, v, plastic=None, p=None, flags=None, c=None, q=None):
         PB = self.arr(self.dim * self.dim, self.n)
         acc = self.arr(self.dim, self.n)
         rc = self.lib.orc_solid_step(self._h, C.byref(mat), float(dt), _ptr(self._a(u)), _ptr(self._a(v)),
-                                     _ptr(self._a(plastic)), _ptr(self._a(p)), _ptr(flags), _ptr(PB), _ptr(acc))
+                                     _ptr(self._a(plastic)), _ptr(self._a(p)), _ptr(flags), _ptr(PB), _ptr(acc),
+                                     _ptr(self._a(c)), _ptr(self._a(q)))
         return rc, PB, acc
 
-    def damping_sweep(self, rho0, eta, dt, v, flags=None):
-        self.lib.orc_damping_sweep(self._h, float(rho0), float(eta), float(dt), _ptr(self._a(v)), _ptr(flags))
+    def damping_sweep(self, rho0, eta, dt, v, flags=None, rho_l0=0.0, c=None):
+        self.lib.orc_damping_sweep(self._h, float(rho0), float(eta), float(dt), _ptr(self._a(v)), _ptr(flags),
+                                   float(rho_l0), _ptr(self._a(c)))
 
-    def drift_ke(self, rho0, dt, u, v, flags=None):
+    def drift_ke(self, rho0, dt, u, v, flags=None, rho_l0=0.0, c=None):
         ke = self.lib.orc_drift_ke(self._h, float(rho0), float(dt), _ptr(self._a(u)), _ptr(self._a(v)),
-                                   _ptr(flags))
+                                   _ptr(flags), float(rho_l0), _ptr(self._a(c)))
         return self._from_real(ke)
 
     def load_step(self, dt_l, u, vgrip, flags):

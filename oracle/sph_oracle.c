@@ -741,9 +741,54 @@ int orc_stress(const orc_sys* s, const orc_material* m, const real* H9, real* pl
   return rc;
 }
 
-/* dv_a/dt = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab  (eq. sph-mechanical-mom
- * with P~_ab = (P_a B0_a + P_b B0_b)/2; the density is the reference density) */
-void orc_momentum(const orc_sys* s, const orc_material* m, const real* PB, real* acc) {
+/* Reference density of particle a: the solid's rho0, plus, for a mixture
+ * (Sec. 2.2.1: rho = rho^s + rho^l, rho^l = rho^l_0 times the fluid
+ * content), the fluid mass per reference volume rho_l0 c_a. */
+static real mix_rho(double rho0, double rho_l0, const real* c, int64_t a) {
+  if (rho_l0 > 0.0 && c) return rho0 + rho_l0 * c[a];
+  return rho0;
+}
+
+/* Mixture momentum flux, Sec. 2.2.1 eq. (totalmomentumupdate) and Sec. 3.2
+ * eq. (totalmomentumupdatesph), in the reference configuration.  The
+ * momentum carried by the fluid, v^l (x) q with the mass flux
+ * q = rho^l (v^l - v^s), enters the momentum balance beside the stress.
+ * Its Piola transform J (v^l (x) q) F^-T = v^l (x) (rho_l0 Q), with Q the
+ * reference flux of fluid content the slow step left, joins P:
+ *   Pi_a = rho_l0 v^l_a (x) Q_a,   PB_a -= Pi_a B0_a.
+ * The fluid velocity follows from the definition of q:
+ *   v^l - v^s = q / rho^l = F Q / c   (c = content per reference volume),
+ * with v^s the current velocity v_a; where c_a <= 0 the relative part is
+ * dropped (no fluid there). */
+void orc_mixture_flux(const orc_sys* s, const orc_material* m, const real* H9, const real* v,
+                      const real* c, const real* q, real* PB) {
+  int d = s->dim;
+  int64_t n = s->n;
+  for (int64_t a = 0; a < n; ++a) {
+    real vl[3] = {0, 0, 0};
+    for (int i = 0; i < d; ++i) {
+      vl[i] = v[i * n + a];
+      if (RE(c[a]) > 0.0) {
+        real Fq = 0.0;
+        for (int k = 0; k < d; ++k)
+          Fq += ((i == k ? 1.0 : 0.0) + H9[(i * 3 + k) * n + a]) * q[k * n + a];
+        vl[i] += Fq / c[a];
+      }
+    }
+    for (int i = 0; i < d; ++i)
+      for (int k = 0; k < d; ++k) {
+        real acc = 0.0;
+        for (int l = 0; l < d; ++l)
+          acc += m->rho_l0 * vl[i] * q[l * n + a] * s->B0[(l * d + k) * n + a];
+        PB[(i * d + k) * n + a] -= acc;
+      }
+  }
+}
+
+/* dv_a/dt = (1/rho_a) sum_b V_b (PB_a + PB_b) grad_a W_ab  (eq. sph-mechanical-mom
+ * with P~_ab = (P_a B0_a + P_b B0_b)/2; rho_a is the reference density,
+ * of the mixture when there is one) */
+void orc_momentum(const orc_sys* s, const orc_material* m, const real* PB, const real* c, real* acc) {
   int d = s->dim;
   int64_t n = s->n;
   for (int64_t a = 0; a < n; ++a) {
@@ -756,13 +801,15 @@ void orc_momentum(const orc_sys* s, const orc_material* m, const real* PB, real*
         for (int k = 0; k < d; ++k)
           f[i] += s->V[b] * (PB[(i * d + k) * n + a] + PB[(i * d + k) * n + b]) * gw[k];
     }
-    for (int i = 0; i < d; ++i) acc[i * n + a] = f[i] / m->rho0;
+    real rho = mix_rho(m->rho0, m->rho_l0, c, a);
+    for (int i = 0; i < d; ++i) acc[i * n + a] = f[i] / rho;
   }
 }
 
 /* rows: deformation gradient -> stress -> momentum -> velocity kick */
 int orc_solid_step(const orc_sys* s, const orc_material* m, double dt, const real* u, real* v,
-                   real* plastic, const real* p, const uint8_t* flags, real* PB, real* acc) {
+                   real* plastic, const real* p, const uint8_t* flags, real* PB, real* acc,
+                   const real* c, const real* q) {
   int64_t n = s->n;
   int d = s->dim;
   real* F9 = (real*)malloc(9 * n * sizeof(real));
@@ -770,7 +817,9 @@ int orc_solid_step(const orc_sys* s, const orc_material* m, double dt, const rea
   real* accl = acc ? acc : (real*)malloc(d * n * sizeof(real));
   orc_displacement_gradient(s, u, F9);
   int rc = orc_stress(s, m, F9, plastic, p, NULL, PBl);
-  orc_momentum(s, m, PBl, accl);
+  const int mixture = m->rho_l0 > 0.0 && c && q;
+  if (mixture) orc_mixture_flux(s, m, F9, v, c, q, PBl);
+  orc_momentum(s, m, PBl, m->rho_l0 > 0.0 ? c : NULL, accl);
   for (int64_t a = 0; a < n; ++a) {
     if (flags && (flags[a] & ORC_FIXED)) continue;
     for (int i = 0; i < d; ++i) v[i * n + a] += dt * accl[i * n + a];
@@ -788,7 +837,7 @@ int orc_solid_step(const orc_sys* s, const orc_material* m, double dt, const rea
  * closed form so that the pair momentum is conserved.  A constrained particle
  * acts as infinite mass.  Pairs are taken in the canonical schedule order. */
 void orc_damping_sweep(const orc_sys* s, double rho0, double eta, double dt, real* v,
-                       const uint8_t* flags) {
+                       const uint8_t* flags, double rho_l0, const real* c) {
   int d = s->dim;
   int64_t n = s->n;
   for (int64_t i = 0; i < s->n_upairs; ++i) {
@@ -799,7 +848,7 @@ void orc_damping_sweep(const orc_sys* s, double rho0, double eta, double dt, rea
     double gw[3];
     double w = pair_w(s, a, b, gw);
     double beta = 2.0 * eta * s->V[a] * s->V[b] * w * dt;
-    double ma = rho0 * s->V[a], mb = rho0 * s->V[b];
+    real ma = mix_rho(rho0, rho_l0, c, a) * s->V[a], mb = mix_rho(rho0, rho_l0, c, b) * s->V[b];
     for (int k = 0; k < d; ++k) {
       real va = v[k * n + a], vb = v[k * n + b];
       if (!fa && !fb) {
@@ -818,7 +867,7 @@ void orc_damping_sweep(const orc_sys* s, double rho0, double eta, double dt, rea
 /* drift u += dt v (free particles), then E_k = sum 1/2 m |v|^2 in ascending
  * sorted order */
 real orc_drift_ke(const orc_sys* s, double rho0, double dt, real* u, const real* v,
-                  const uint8_t* flags) {
+                  const uint8_t* flags, double rho_l0, const real* c) {
   int d = s->dim;
   int64_t n = s->n;
   real ke = 0.0;
@@ -829,7 +878,7 @@ real orc_drift_ke(const orc_sys* s, double rho0, double dt, real* u, const real*
       if (!fixed) u[k * n + a] += dt * v[k * n + a];
       v2 += v[k * n + a] * v[k * n + a];
     }
-    ke += 0.5 * rho0 * s->V[a] * v2;
+    ke += 0.5 * mix_rho(rho0, rho_l0, c, a) * s->V[a] * v2;
   }
   return ke;
 }
@@ -1010,10 +1059,10 @@ int orc_advance(const orc_sys* s, const orc_material* m, const orc_cfg* cfg, rea
     real ke = 0.0;
     int conv = 0;
     while (k < nk) {
-      int r = orc_solid_step(s, m, dt_s, u, v, plastic, p, flags, NULL, acc_out);
+      int r = orc_solid_step(s, m, dt_s, u, v, plastic, p, flags, NULL, acc_out, c, q);
       if (r) rc = r;
-      orc_damping_sweep(s, m->rho0, cfg->eta, dt_s, v, flags);
-      ke = orc_drift_ke(s, m->rho0, dt_s, u, v, flags);
+      orc_damping_sweep(s, m->rho0, cfg->eta, dt_s, v, flags, m->rho_l0, c);
+      ke = orc_drift_ke(s, m->rho0, dt_s, u, v, flags, m->rho_l0, c);
       ++k;
       if (!isfinite(RE(ke))) {
         rc = -4;

@@ -45,6 +45,7 @@ typedef struct {
   real sigma0, sigma_inf, delta, H;  /* hardening law k(alpha) */
   real C_swell;               /* fluid-pressure coefficient C */
   double c0;                  /* initial saturation */
+  double rho_l0;              /* fluid reference density (mixture momentum); 0: dry solid */
 } orc_material;
 
 typedef struct {
@@ -89,13 +90,19 @@ int orc_constitutive(const orc_material* m, const real* H, real* plastic7, real 
 void orc_displacement_gradient(const orc_sys* s, const real* u, real* H9);
 int orc_stress(const orc_sys* s, const orc_material* m, const real* H9, real* plastic,
                const real* p, real* P9, real* PB);
-void orc_momentum(const orc_sys* s, const orc_material* m, const real* PB, real* acc);
+/* mixture momentum flux (Sec. 2.2.1, Sec. 3.2): PB_a -= rho_l0 v^l_a (x) Q_a B0_a */
+void orc_mixture_flux(const orc_sys* s, const orc_material* m, const real* H9, const real* v,
+                      const real* c, const real* q, real* PB);
+void orc_momentum(const orc_sys* s, const orc_material* m, const real* PB, const real* c, real* acc);
+/* c, q (optional): content and reference flux of the last slow step; with
+   m->rho_l0 > 0 they give the mixture terms */
 int orc_solid_step(const orc_sys* s, const orc_material* m, double dt, const real* u, real* v,
-                   real* plastic, const real* p, const uint8_t* flags, real* PB, real* acc);
+                   real* plastic, const real* p, const uint8_t* flags, real* PB, real* acc,
+                   const real* c, const real* q);
 void orc_damping_sweep(const orc_sys* s, double rho0, double eta, double dt, real* v,
-                       const uint8_t* flags);
+                       const uint8_t* flags, double rho_l0, const real* c);
 real orc_drift_ke(const orc_sys* s, double rho0, double dt, real* u, const real* v,
-                  const uint8_t* flags);
+                  const uint8_t* flags, double rho_l0, const real* c);
 /* slow steps */
 void orc_load_step(const orc_sys* s, double dt_l, real* u, const real* vgrip, const uint8_t* flags);
 void orc_diffusion_step(const orc_sys* s, real D, double dt_d, double c_bc, real C_swell,
