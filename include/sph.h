@@ -109,6 +109,16 @@ typedef struct {
   double sigma0, sigma_inf, delta, H; /* hardening k(a) = s0 + (sinf-s0)(1-exp(-delta a)) + H a (App. A.3) */
   double C_swell; /* fluid-pressure coefficient: p = C (c - c0), eq. (fluid_pressure) */
   double c0;      /* initial saturation */
+  double rho_l0;  /* fluid reference density (Sec. 2.2.1, rho^l = rho^l_0 times the content);
+                     0: a dry solid.  > 0 turns on the mixture momentum of the inner step,
+                     which needs the state's c and q (the content and the reference flux Q
+                     the last slow step left):
+                       PB_a -= rho_l0 v^l_a (x) Q_a B0_a,  v^l = v + F Q / c (c > 0),
+                     the fluid's momentum flux v^l (x) q of eq. (totalmomentumupdatesph) as
+                     a Piola tensor; the inertia of the kick, the damping sweep's masses
+                     and the kinetic energy become (rho0 + rho_l0 c_a) V_a.  The time step
+                     stays 0.6 h / sqrt(K / rho0).  The reverse pass refuses it
+                     (SPH_E_UNSUPPORTED). */
 } sph_material;
 
 typedef struct {

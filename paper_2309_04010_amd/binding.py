@@ -60,7 +60,7 @@ class NbrInfo(C.Structure):
 class Material(C.Structure):
     _fields_ = [("model", i32), ("pad_", i32), ("E", dbl), ("nu", dbl), ("rho0", dbl),
                 ("sigma0", dbl), ("sigma_inf", dbl), ("delta", dbl), ("H", dbl),
-                ("C_swell", dbl), ("c0", dbl)]
+                ("C_swell", dbl), ("c0", dbl), ("rho_l0", dbl)]
 
 
 class State(C.Structure):
@@ -275,9 +275,10 @@ def sph_build_neighbors(X, V, h, stream=None):
     return Neighbors(out, (X, V))
 
 
-def material(model, E, nu, rho0, sigma0=0.0, sigma_inf=0.0, delta=0.0, H=0.0, C_swell=0.0, c0=0.0):
+def material(model, E, nu, rho0, sigma0=0.0, sigma_inf=0.0, delta=0.0, H=0.0, C_swell=0.0, c0=0.0,
+             rho_l0=0.0):
     return Material(int(model), 0, float(E), float(nu), float(rho0), float(sigma0), float(sigma_inf),
-                    float(delta), float(H), float(C_swell), float(c0))
+                    float(delta), float(H), float(C_swell), float(c0), float(rho_l0))
 
 
 @dataclass

@@ -967,6 +967,10 @@ static int check_adj(const sph_nbr* nb, const sph_material* m, const sph_state* 
     set_error("adjoint and state precisions differ");
     return SPH_E_ARG;
   }
+  if (m->rho_l0 != 0.0) {
+    set_error("the reverse steps cover the dry solid only (rho_l0 = 0)");
+    return SPH_E_UNSUPPORTED;
+  }
   if (!adj->u || !adj->v || !adj->work || !adj->grad) {
     set_error("adjoint arrays u, v, work and grad are required");
     return SPH_E_ARG;

@@ -285,6 +285,7 @@ int diffusion_step(const sph_nbr* nb, const sph_material* m, const sph_state* st
                    double dt_d, double c_bc, hipStream_t s);
 int reset_ctrl(const sph_nbr* nb, int64_t k_limit, double ke_tol, hipStream_t s);
 int check_state(const sph_nbr* nb, const sph_state* st, bool need_v);
+int check_mixture(const sph_material* m, const sph_state* st);
 // reverse mode (sph_adjoint.hip)
 int adj_solid(const sph_nbr* nb, const sph_material* m, const double* u, const void* plastic,
               const sph_state* st, const sph_adjoint* adj, double dt, double drift_dt,

@@ -205,6 +205,7 @@ extern "C" int sph_solid_relax_step(const sph_nbr* nb, const sph_material* mat,
     set_error("material is NULL");
     return SPH_E_ARG;
   }
+  if ((rc = check_mixture(mat, st))) return rc;
   return solid_stage(nb, mat, st, dt_s, (hipStream_t)stream, false);
 }
 
@@ -217,6 +218,7 @@ extern "C" int sph_damping_sweep(const sph_nbr* nb, const sph_material* mat, con
     set_error("material is NULL");
     return SPH_E_ARG;
   }
+  if ((rc = check_mixture(mat, st))) return rc;
   return damping_sweep(nb, mat, st, eta, dt_s, (hipStream_t)stream, false);
 }
 
@@ -229,6 +231,7 @@ extern "C" int sph_drift_ke(const sph_nbr* nb, const sph_material* mat, const sp
     set_error("material is NULL");
     return SPH_E_ARG;
   }
+  if ((rc = check_mixture(mat, st))) return rc;
   return drift_ke(nb, mat, st, dt_s, ke_out, (hipStream_t)stream, false);
 }
 
@@ -295,6 +298,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     set_error("material or cfg is NULL");
     return SPH_E_ARG;
   }
+  if ((rc = check_mixture(m, st))) return rc;
   if (cfg->n_slow < 0 || (cfg->slow_kind != SPH_SLOW_LOAD && cfg->slow_kind != SPH_SLOW_DIFFUSION &&
                            cfg->slow_kind != SPH_SLOW_DIFFUSION_COUPLED)) {
     set_error("bad n_slow or slow_kind");
@@ -364,6 +368,8 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     else
       rc = diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
     if (rc) break;
+    // a mixture's masses follow the content the slow step has just changed
+    if (m->rho_l0 > 0.0 && (rc = damp_prepare(nb, m, st, cfg->eta, dt_s, s))) break;
     const int64_t nk = cfg->k_sched ? cfg->k_sched[l] : (cfg->fixed_inner > 0 ? cfg->fixed_inner : k_max);
     Ctrl* hc = nb->ctrl_host;
     if (nk <= 0) {
@@ -531,6 +537,10 @@ int check_backward_args(const sph_nbr* nb, const sph_material* m, const sph_stat
     set_error("the reverse pass covers the loading and linear diffusion slow steps only");
     return SPH_E_UNSUPPORTED;
   }
+  if (m->rho_l0 != 0.0) {
+    set_error("the reverse pass covers the dry solid only (rho_l0 = 0)");
+    return SPH_E_UNSUPPORTED;
+  }
   if (adj->prec != st->prec || !adj->u || !adj->v || !adj->work || !adj->grad ||
       (m->model == SPH_MODEL_J2 && !adj->plastic) ||
       (cfg->slow_kind == SPH_SLOW_DIFFUSION && !adj->c)) {
@@ -645,6 +655,10 @@ extern "C" int sph_advance_multirate_graph(const sph_nbr* nb, const sph_material
       (cfg->slow_kind != SPH_SLOW_LOAD && cfg->slow_kind != SPH_SLOW_DIFFUSION)) {
     set_error("bad material or cfg (the whole-run graph takes loading and linear diffusion steps)");
     return SPH_E_ARG;
+  }
+  if (m->rho_l0 != 0.0) {
+    set_error("the whole-run graph takes the dry solid only (rho_l0 = 0)");
+    return SPH_E_UNSUPPORTED;
   }
   if (cfg->k_sched == nullptr && cfg->fixed_inner <= 0) {
     set_error("the whole-run graph needs fixed inner counts (fixed_inner or k_sched)");

@@ -14,6 +14,26 @@
 
 namespace sph {
 
+// Mixture terms of an inner step (a solid saturated by a fluid, Sec. 2.2.1):
+// the momentum the fluid carries, beside the stress, and the fluid's mass in
+// the inertia.  Dry (c == nullptr) unless the material has a fluid density
+// and the state holds the content c and the reference flux q of the last
+// slow step.
+template <typename T>
+struct Mix {
+  const T* v;  // [d][n] solid velocity
+  const T* c;  // [n] fluid content per reference volume; nullptr: dry
+  const T* q;  // [d][n] reference flux of fluid content
+  T rho0, rho_l0;
+};
+
+template <typename T>
+static Mix<T> mix_view(const sph_material* m, const sph_state* st) {
+  const bool on = m->rho_l0 > 0.0 && st->c && st->q;
+  return Mix<T>{(const T*)st->v, on ? (const T*)st->c : nullptr, (const T*)st->q, (T)m->rho0,
+                (T)m->rho_l0};
+}
+
 // stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0
 template <typename T, int D, int LPP, int MODEL>
 __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
@@ -22,7 +42,7 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
                                                              T* __restrict__ plastic,
                                                              const T* __restrict__ p, Ctrl* ctrl,
                                                              bool gated, T* __restrict__ rec_pl,
-                                                             Bat bt) {
+                                                             Bat bt, Mix<T> mx) {
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
@@ -134,6 +154,7 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
 #pragma unroll
     for (int i = 0; i < 7; ++i) plastic[i * n + a] = pl[i];
   }
+  T Pb[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -141,8 +162,41 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
       T acc = T(0);
 #pragma unroll
       for (int l = 0; l < D; ++l) acc += P[i * 3 + l] * B[l][k];
-      PB[(i * D + k) * n + a] = acc;
+      Pb[i][k] = acc;
     }
+  if (mx.c) {
+    // the fluid's momentum flux as a Piola tensor: PB -= rho_l0 v^l (x) (B^T Q),
+    // with the fluid velocity v^l = v + F Q / c (no relative part where c <= 0)
+    const T ca = mx.c[a];
+    T Q[D], vl[D], BQ[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) Q[i] = mx.q[i * n + a];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      vl[i] = mx.v[i * n + a];
+      if (ca > T(0)) {
+        T fq = Q[i];
+#pragma unroll
+        for (int k = 0; k < D; ++k) fq += Hm[i * 3 + k] * Q[k];
+        vl[i] += fq / ca;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) acc += Q[l] * B[l][k];
+      BQ[k] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) Pb[i][k] -= mx.rho_l0 * vl[i] * BQ[k];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) PB[(i * D + k) * n + a] = Pb[i][k];
 }
 
 // momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a.
@@ -154,7 +208,7 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
                                                                  T* __restrict__ acc_out,
                                                                  const uint8_t* __restrict__ flags,
                                                                  T inv_rho0, T dt, Ctrl* ctrl,
-                                                                 bool gated, Bat bt) {
+                                                                 bool gated, Bat bt, Mix<T> mx) {
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
@@ -252,9 +306,11 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
   if (h != 0) return;
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
   const T dta = bt.spec ? bt.get<T>(BT_DT, bt.spec[a]) : dt;
+  // the inertia of the mixture: rho0 + rho_l0 c per reference volume
+  const T rho_a = mx.c ? mx.rho0 + mx.rho_l0 * mx.c[a] : T(0);
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    T ai = f[i] * inv_rho0;
+    T ai = mx.c ? f[i] / rho_a : f[i] * inv_rho0;
     if (acc_out) acc_out[i * n + a] = ai;
     if (!fixed) v[i * n + a] += dta * ai;
   }
@@ -426,11 +482,12 @@ __global__ void k_damp_prep(int64_t n_upairs, int64_t n, const uint32_t* __restr
                             const uint32_t* __restrict__ sb, const uint32_t* __restrict__ dpair,
                             const T* __restrict__ dgeo, const T* __restrict__ V,
                             const uint8_t* __restrict__ flags, T inv_rho0, T eta_dt, Bat bt,
-                            PairQ<T>* __restrict__ dwq, T* __restrict__ imass) {
+                            PairQ<T>* __restrict__ dwq, T* __restrict__ imass, Mix<T> mx) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   auto im = [&](int64_t a) -> T {
     const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
-    return fixed ? T(0) : inv_rho0 / V[a];
+    if (fixed) return T(0);
+    return mx.c ? T(1) / ((mx.rho0 + mx.rho_l0 * mx.c[a]) * V[a]) : inv_rho0 / V[a];
   };
   if (i < n) imass[i] = im(i);
   if (i == n_upairs) {
@@ -460,13 +517,13 @@ template <typename T, int D>
 __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     int64_t n, double* __restrict__ u, const T* __restrict__ v, const uint8_t* __restrict__ flags,
     const double* __restrict__ V, double rho0, double dt, Ctrl* ctrl, double* partial,
-    bool gated, double* __restrict__ rec_u, Bat bt) {
+    bool gated, double* __restrict__ rec_u, Bat bt, const T* __restrict__ cmix, double rho_l0) {
   if (gated && ctrl->done) return;
   __shared__ double red[kKeThreads];
   double* __restrict__ rec = rec_u ? rec_u + ctrl->k * D * n : nullptr;
   const int64_t a0 = blockIdx.x * (int64_t)(kKeThreads * kKeItems) + threadIdx.x;
   // every load of the thread's particles first, then the updates
-  double uo[kKeItems][D], Va[kKeItems], dta[kKeItems];
+  double uo[kKeItems][D], Va[kKeItems], dta[kKeItems], ra[kKeItems];
   T vv[kKeItems][D];
   uint8_t fl[kKeItems];
 #pragma unroll
@@ -474,6 +531,7 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     const int64_t a = a0 + it * kKeThreads;
     fl[it] = SPH_FLAG_FIXED;
     Va[it] = 0.0;
+    ra[it] = rho0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       vv[it][k] = T(0);
@@ -482,6 +540,7 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     if (a < n) {
       fl[it] = flags ? flags[a] : (uint8_t)0;
       Va[it] = V[a];
+      if (cmix) ra[it] = rho0 + rho_l0 * (double)cmix[a];  // mixture mass
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         vv[it][k] = v[k * n + a];
@@ -513,7 +572,7 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
         if (!fixed) u[k * n + a] = uo[it][k] + dta[it] * vk;
         v2 += vk * vk;
       }
-      acc += 0.5 * rho0 * Va[it] * v2;
+      acc += 0.5 * ra[it] * Va[it] * v2;
     }
   }
   red[threadIdx.x] = acc;
@@ -838,6 +897,18 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff_div(Geo<T> g, T* __restrict
 
 // ---------------------------------------------------------------------------
 
+int check_mixture(const sph_material* m, const sph_state* st) {
+  if (!(m->rho_l0 >= 0.0)) {
+    set_error("rho_l0 must be >= 0");
+    return SPH_E_ARG;
+  }
+  if (m->rho_l0 > 0.0 && (!st->c || !st->q)) {
+    set_error("a mixture (rho_l0 > 0) needs the state's content c and flux q");
+    return SPH_E_ARG;
+  }
+  return SPH_OK;
+}
+
 int check_state(const sph_nbr* nb, const sph_state* st, bool need_v) {
   if (!nb || !st) {
     set_error("null handle or state");
@@ -872,7 +943,7 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_STRESS, s);
     k_stress<T, D, LS, MODEL><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
         g, mp, st->u, (T*)st->PB, (T*)st->plastic, (const T*)st->p, nb->ctrl, gated,
-        m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr, bat_view(nb));
+        m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr, bat_view(nb), mix_view<T>(m, st));
     prof_end(nb, SPH_KERNEL_STRESS, pe_, s);
     SPH_LAUNCH_CHECK();
   }
@@ -881,7 +952,7 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_MOMENTUM, s);
     k_momentum<T, D, LM><<<grid, (unsigned)(g.tmax * LM), lds_m, s>>>(
         g, (const T*)st->PB, (T*)st->v, (T*)st->acc, st->flags, (T)(1.0 / m->rho0), (T)dt,
-        nb->ctrl, gated, bat_view(nb));
+        nb->ctrl, gated, bat_view(nb), mix_view<T>(m, st));
     prof_end(nb, SPH_KERNEL_MOMENTUM, pe_, s);
     SPH_LAUNCH_CHECK();
   }
@@ -984,7 +1055,7 @@ static int damp_prepare_t(const sph_nbr* nb, const sph_material* m, const sph_st
   const int64_t m_ = std::max<int64_t>(nb->n_upairs + 1, nb->n);
   k_damp_prep<T><<<nblk(std::max<int64_t>(m_, 1), 256), 256, 0, s>>>(
       nb->n_upairs, nb->n, nb->sa, nb->sb, nb->dpair, dgeo, g.V, st->flags, (T)(1.0 / m->rho0),
-      (T)(eta * dt), bat_view(nb), (PairQ<T>*)nb->dwq[p], (T*)nb->imass[p]);
+      (T)(eta * dt), bat_view(nb), (PairQ<T>*)nb->dwq[p], (T*)nb->imass[p], mix_view<T>(m, st));
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
@@ -1058,7 +1129,8 @@ static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st
     k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
                                                           nb->V, m->rho0, dt, nb->ctrl,
                                                           nb->ke_partial, gated, nb->rec_u,
-                                                          bat_view(nb));
+                                                          bat_view(nb), mix_view<T>(m, st).c,
+                                                          m->rho_l0);
     SPH_LAUNCH_CHECK();
     k_ke_reduce<<<1, 1024, 0, s>>>(nb->ke_partial, (int)nb_, nb->ctrl, ke_out, gated);
     prof_end(nb, SPH_KERNEL_DRIFT_KE, pe_, s);

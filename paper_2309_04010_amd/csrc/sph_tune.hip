@@ -113,6 +113,7 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     set_error("material, PB (and the J2 state) are required");
     return SPH_E_ARG;
   }
+  if ((rc = check_mixture(m, st))) return rc;
   hipStream_t s = (hipStream_t)stream;
   const int prec = st->prec;
   const size_t n = (size_t)nb->n, d = (size_t)nb->dim, T = prec == SPH_F64 ? 8 : 4;

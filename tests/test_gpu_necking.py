@@ -77,7 +77,9 @@ def test_necking_graph_equals_eager(oracle_mod):
     c = cases.by_name(name, **kw)
     out = []
     for g in (False, True):
-        r = NeckingRun(c, B.SPH_F64, record_every=5, use_graph=g)
+        # the same launch shapes on both sides (a timed autotune may pick
+        # different ones, and with them a different summation order)
+        r = NeckingRun(c, B.SPH_F64, record_every=5, use_graph=g, autotune=False)
         try:
             res = r.run()
             out.append((host(r.st.u), host(r.st.plastic), res["history"]["reaction"]))
