@@ -338,6 +338,40 @@ def run_necking(name, prec, n_slow, torch, B, record_every=100):
                                      for i in range(stride - 1, len(h["increment"]), stride)])
 
 
+def run_mixture(case, torch, B, inner=200):
+    """Forward cost of the mixture momentum on the same workload (FP32): one
+    two-way coupled (nonlinear) diffusion slow step and `inner` fast steps,
+    dry (rho_l0 = 0) and with the fluid's momentum and mass (rho_l0 = 1000);
+    per inner step: wall time of the run (after a warm-up run) and the
+    per-class kernel times of one profiled run."""
+    import numpy as np
+    out = {}
+    for name, rho_l0 in (("dry", 0.0), ("mixture", 1000.0)):
+        nb, st = setup(case, B.SPH_F32, torch, B)
+        mat = B.material(**dict(case.material, rho_l0=rho_l0))
+        run = dict(case.run, n_slow=1, fixed_inner=inner, slow_kind=B.SPH_SLOW_DIFFUSION_COUPLED)
+        cfg = B.multirate_cfg(**run, chunk=inner, use_graph=0, diff_nonlinear=1)
+        c_keep = st.c.clone()
+        B.sph_advance_multirate(nb, mat, st, cfg)
+        torch.cuda.synchronize()
+        st.c.copy_(c_keep)
+        t0 = time.perf_counter()
+        B.sph_advance_multirate(nb, mat, st, cfg)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        B.sph_profile_enable(nb, True)
+        B.sph_advance_multirate(nb, mat, st, cfg)
+        prof = B.sph_profile_read(nb)
+        B.sph_profile_enable(nb, False)
+        out[name] = dict(us_per_inner_step=1e6 * sec / inner,
+                         kernels_us={k: 1000.0 * ms / c for k, (c, ms) in prof.items() if c},
+                         u_finite=bool(torch.isfinite(st.u).all().item()))
+        nb.close()
+    out["note"] = ("FP32, eager launches; kernels_us: average per launch (damping: per colour pass; "
+                   "diff_*: the slow step's)")
+    return out
+
+
 def run_sweep(torch, B, launches=2):
     """The batched parameter sweep: 64 strips of log-uniform size (1e3-5e4
     particles), each with its own E and D, 10 diffusion slow steps x 200
@@ -504,6 +538,11 @@ def main():
         coupled = run_coupled(case, torch, B)
         print("[bench] slow-step variants done", flush=True)
 
+    mixture = None
+    if not args.no_coupled:
+        mixture = run_mixture(case, torch, B)
+        print("[bench] mixture momentum done", flush=True)
+
     necking = None
     if args.necking != "none":
         necking = {}
@@ -549,6 +588,7 @@ def main():
         "accuracy": accuracy,
         "batched_sweep": sweep,
         "slow_step_variants": coupled,
+        "mixture_momentum": mixture,
         "necking": necking,
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
