@@ -638,48 +638,6 @@ __global__ void k_load(int64_t n, double* u, const T* vgrip, const uint8_t* flag
   for (int k = 0; k < D; ++k) u[k * n + a] += dta * (double)vgrip[k * n + a];
 }
 
-// diffusion: flux q = -D B0 sum_b V_b (c_b - c_a) grad W
-template <typename T, int D>
-__global__ __launch_bounds__(kDiffBlock) void k_diff_grad(Geo<T> g, const T* __restrict__ c,
-                                                          T* __restrict__ q, T Dc, Bat bt) {
-  constexpr int L = kDiffLanes;  // lanes per particle, each a strided share of its list
-  const int64_t n = g.n;
-  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
-  const int h = threadIdx.x % L;
-  if (a >= n) return;  // the whole lane group
-  double xa[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
-  const T ca = c[a];
-  T s[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) s[k] = T(0);
-  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
-    const uint32_t b = g.idx[j];
-    T d[D];
-    T r2 = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      d[k] = (T)(xa[k] - g.X[k * n + b]);
-      r2 += d[k] * d[k];
-    }
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b] * (c[b] - ca);
-#pragma unroll
-    for (int k = 0; k < D; ++k) s[k] += w * d[k];
-  }
-#pragma unroll
-  for (int k = 0; k < D; ++k) s[k] = lane_sum<L>(s[k]);
-  if (h != 0) return;
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    T acc = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) acc += g.B0[(i * D + k) * n + a] * s[k];
-    q[i * n + a] = -(bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc) * acc;
-  }
-}
-
-// determinant and inverse of a D x D matrix (row-major)
 template <typename T, int D>
 __device__ __forceinline__ T det_d(const T* A) {
   if constexpr (D == 2) return A[0] * A[3] - A[1] * A[2];
@@ -706,106 +664,82 @@ __device__ __forceinline__ void inv_d(const T* A, T det, T* Ai) {
   }
 }
 
-// coupled diffusion, first pass: the deformation gradient F = I + H with
-// H = (sum_b V_b (u_b - u_a) (x) grad0 W_ab) B0_a (eq. deformationtensor-
-// displacement), kept as F^-1 in Fi [D*D][n], and the saturation c / det F
-// in sat [n]
-template <typename T, int D>
-__global__ __launch_bounds__(kDiffBlock) void k_diff_F(Geo<T> g, const double* __restrict__ u,
-                                                       const T* __restrict__ c, T* __restrict__ Fi,
-                                                       T* __restrict__ sat) {
-  constexpr int L = kDiffLanes;
-  const int64_t n = g.n;
-  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
-  const int h = threadIdx.x % L;
-  if (a >= n) return;  // the whole lane group
-  double xa[D], ua[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    xa[k] = g.X[k * n + a];
-    ua[k] = u[k * n + a];
-  }
-  T G[D * D];
-#pragma unroll
-  for (int i = 0; i < D * D; ++i) G[i] = T(0);
-  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
-    const uint32_t b = g.idx[j];
-    T d[D], du[D];
-    T r2 = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      d[k] = (T)(xa[k] - g.X[k * n + b]);
-      du[k] = (T)(u[k * n + b] - ua[k]);
-      r2 += d[k] * d[k];
-    }
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int k = 0; k < D; ++k) G[i * D + k] += w * du[i] * d[k];
-  }
-#pragma unroll
-  for (int i = 0; i < D * D; ++i) G[i] = lane_sum<L>(G[i]);
-  if (h != 0) return;
-  T F[D * D];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      T acc = T(0);
-#pragma unroll
-      for (int l = 0; l < D; ++l) acc += G[i * D + l] * g.B0[(l * D + k) * n + a];
-      F[i * D + k] = (i == k ? T(1) : T(0)) + acc;
-    }
-  const T J = det_d<T, D>(F);
-  T Fin[D * D];
-  inv_d<T, D>(F, J, Fin);
-#pragma unroll
-  for (int i = 0; i < D * D; ++i) Fi[i * n + a] = Fin[i];
-  sat[a] = c[a] / J;
-}
+// The diffusion kernels work on the LDS tiles of the inner-step kernels: a
+// tile stages its window (positions relative to the tile origin and volumes,
+// plus one per-particle field), then LPP lanes per own particle walk its
+// ELL list in LDS.  Padding entries of a list point at the particle itself
+// (d = 0) and add nothing.
 
-// coupled diffusion, flux: g = F^-T B0 sum_b V_b (a_b - a_a) grad0 W (the
-// current-configuration gradient of the saturation a), q = -D w g with w = a
-// (nonlinear) or 1, stored as the reference (Piola) flux J F^-1 q
-template <typename T, int D>
-__global__ __launch_bounds__(kDiffBlock) void k_diff_grad_coupled(Geo<T> g, const T* __restrict__ sat,
-                                                                  const T* __restrict__ Fi,
-                                                                  T* __restrict__ q, T Dc,
-                                                                  int nonlinear, Bat bt) {
-  constexpr int L = kDiffLanes;
+// Flux of one slow step.  Reference configuration (Fi == nullptr):
+//   q = -D B0 sum_b V_b (f_b - f_a) grad0 W      (f = c, the saturation).
+// Two-way coupled (Fi = F^-1, f = the saturation a = c / J): the gradient is
+// taken in the current configuration, g = F^-T B0 sum_b V_b (a_b - a_a)
+// grad0 W, the flux is q = -D w g with w = a (nonlinear) or 1, and what is
+// stored is the reference (Piola) flux J F^-1 q.
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_diff_grad(TileGeo<T> g, const T* __restrict__ f,
+                                                         const T* __restrict__ Fi,
+                                                         T* __restrict__ q, T Dc, int nonlinear,
+                                                         Bat bt) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  T* sf = reinterpret_cast<T*>(sx + window);
   const int64_t n = g.n;
-  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
-  const int h = threadIdx.x % L;
-  if (a >= n) return;
-  double xa[D];
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
-  const T sa = sat[a];
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
+  const WinMap wm = win_map(td);
+  for (uint32_t l0 = threadIdx.x; l0 < window; l0 += 2 * blockDim.x) {
+    vec4<T> xv[2];
+    T fv[2];
+    uint32_t ls[2] = {l0, l0 + blockDim.x};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (ls[e] < window) {
+        const int64_t gi = wm(ls[e]);
+        xv[e].x = (T)(g.X[gi] - xo[0]);
+        xv[e].y = (T)(g.X[n + gi] - xo[1]);
+        xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+        xv[e].w = g.V[gi];
+        fv[e] = f[gi];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ls[e] < window) {
+        sx[ls[e]] = xv[e];
+        sf[ls[e]] = fv[e];
+      }
+  }
+  __syncthreads();
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
+  if ((uint32_t)t >= td.count) return;
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
+  const vec4<T> xa = sx[la];
+  const T fa = sf[la];
   T s[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) s[k] = T(0);
-  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
-    const uint32_t b = g.idx[j];
-    T d[D];
-    T r2 = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      d[k] = (T)(xa[k] - g.X[k * n + b]);
-      r2 += d[k] * d[k];
-    }
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b] * (sat[b] - sa);
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    const vec4<T> xb = sx[l];
+    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w * (sf[l] - fa);
 #pragma unroll
     for (int k = 0; k < D; ++k) s[k] += w * d[k];
-  }
+  });
 #pragma unroll
-  for (int k = 0; k < D; ++k) s[k] = lane_sum<L>(s[k]);
+  for (int k = 0; k < D; ++k) s[k] = lane_sum<LPP>(s[k]);
   if (h != 0) return;
-  T Fa[D * D];
-#pragma unroll
-  for (int i = 0; i < D * D; ++i) Fa[i] = Fi[i * n + a];
-  const T J = T(1) / det_d<T, D>(Fa);
-  T gr[D], gc[D], qc[D];
+  const T Da = bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc;
+  T gr[D];
 #pragma unroll
   for (int m = 0; m < D; ++m) {
     T acc = T(0);
@@ -813,6 +747,16 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff_grad_coupled(Geo<T> g, cons
     for (int k = 0; k < D; ++k) acc += g.B0[(m * D + k) * n + a] * s[k];
     gr[m] = acc;
   }
+  if (!Fi) {
+#pragma unroll
+    for (int m = 0; m < D; ++m) q[m * n + a] = -Da * gr[m];
+    return;
+  }
+  T Fa[D * D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) Fa[i] = Fi[i * n + a];
+  const T J = T(1) / det_d<T, D>(Fa);
+  T gc[D], qc[D];
 #pragma unroll
   for (int m = 0; m < D; ++m) {
     T acc = T(0);
@@ -820,8 +764,7 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff_grad_coupled(Geo<T> g, cons
     for (int k = 0; k < D; ++k) acc += Fa[k * D + m] * gr[k];  // F^-T
     gc[m] = acc;
   }
-  const T Da = bt.spec ? bt.get<T>(BT_D, bt.spec[a]) : Dc;
-  const T wa = nonlinear ? sa : T(1);
+  const T wa = nonlinear ? fa : T(1);
 #pragma unroll
   for (int m = 0; m < D; ++m) qc[m] = -Da * wa * gc[m];
 #pragma unroll
@@ -833,54 +776,185 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff_grad_coupled(Geo<T> g, cons
   }
 }
 
-// c += dt (-sum_b V_b (B0_a q_a + B0_b q_b) . grad W); Dirichlet; p = C (c - c0)
-template <typename T, int D>
-__global__ __launch_bounds__(kDiffBlock) void k_diff_div(Geo<T> g, T* __restrict__ c,
-                                                         const T* __restrict__ q, T* __restrict__ p,
-                                                         const uint8_t* __restrict__ flags, T dt,
-                                                         T c_bc, T Cs, T c0, Bat bt,
-                                                         const T* __restrict__ Fi) {
-  constexpr int L = kDiffLanes;
+// coupled diffusion, first pass: the deformation gradient F = I + H with
+// H = (sum_b V_b (u_b - u_a) (x) grad0 W_ab) B0_a (eq. deformationtensor-
+// displacement), kept as F^-1 in Fi [D*D][n], and the saturation c / det F
+// in sat [n]
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_diff_F(TileGeo<T> g, const double* __restrict__ u,
+                                                      const T* __restrict__ c, T* __restrict__ Fi,
+                                                      T* __restrict__ sat) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* su = sx + window;
   const int64_t n = g.n;
-  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L;
-  const int h = threadIdx.x % L;
-  if (a >= n) return;
-  double xa[D];
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0}, uo[3] = {0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < D; ++k) xa[k] = g.X[k * n + a];
-  T ga[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    T acc = T(0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) acc += g.B0[(i * D + k) * n + a] * q[k * n + a];
-    ga[i] = acc;
+  for (int k = 0; k < D; ++k) {
+    xo[k] = g.X[k * n + p0];
+    uo[k] = u[k * n + p0];
   }
-  T div = T(0);
-  for (int64_t j = g.off[a] + h; j < g.off[a + 1]; j += L) {
-    const uint32_t b = g.idx[j];
-    T d[D];
-    T r2 = T(0);
+  const WinMap wm = win_map(td);
+  for (uint32_t l0 = threadIdx.x; l0 < window; l0 += 2 * blockDim.x) {
+    vec4<T> xv[2], uv[2];
+    uint32_t ls[2] = {l0, l0 + blockDim.x};
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      d[k] = (T)(xa[k] - g.X[k * n + b]);
-      r2 += d[k] * d[k];
+    for (int e = 0; e < 2; ++e) {
+      if (ls[e] < window) {
+        const int64_t gi = wm(ls[e]);
+        xv[e].x = (T)(g.X[gi] - xo[0]);
+        xv[e].y = (T)(g.X[n + gi] - xo[1]);
+        xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+        xv[e].w = g.V[gi];
+        uv[e].x = (T)(u[gi] - uo[0]);
+        uv[e].y = (T)(u[n + gi] - uo[1]);
+        uv[e].z = D == 3 ? (T)(u[2 * n + gi] - uo[2]) : T(0);
+        uv[e].w = T(0);
+      }
     }
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * g.V[b];
-    T s = T(0);
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ls[e] < window) {
+        sx[ls[e]] = xv[e];
+        su[ls[e]] = uv[e];
+      }
+  }
+  __syncthreads();
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
+  if ((uint32_t)t >= td.count) return;
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
+  const vec4<T> xa = sx[la], ua = su[la];
+  T G[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) G[i][k] = T(0);
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    const vec4<T> xb = sx[l], ub = su[l];
+    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      T gb = T(0);
+      const T wd = w * du[i];
 #pragma unroll
-      for (int k = 0; k < D; ++k) gb += g.B0[(i * D + k) * n + b] * q[k * n + b];
-      s += (ga[i] + gb) * d[i];
+      for (int k = 0; k < D; ++k) G[i][k] += wd * d[k];
     }
-    div += w * s;
+  });
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) G[i][k] = lane_sum<LPP>(G[i][k]);
+  if (h != 0) return;
+  T F[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) acc += G[i][l] * g.B0[(l * D + k) * n + a];
+      F[i * D + k] = (i == k ? T(1) : T(0)) + acc;
+    }
+  const T J = det_d<T, D>(F);
+  T Fin[D * D];
+  inv_d<T, D>(F, J, Fin);
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) Fi[i * n + a] = Fin[i];
+  sat[a] = c[a] / J;
+}
+
+// c += dt (-sum_b V_b (B0_a q_a + B0_b q_b) . grad W); Dirichlet; p = C (c - c0).
+// The window stages y_b = B0_b q_b; the own term is y_a . sum_b V_b grad W,
+// once per lane.  With Fi (coupled), c is the content per reference volume:
+// the Dirichlet value is c_bc J and p = C (c / J - c0).
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_diff_div(TileGeo<T> g, T* __restrict__ c,
+                                                        const T* __restrict__ q, T* __restrict__ p,
+                                                        const uint8_t* __restrict__ flags, T dt,
+                                                        T c_bc, T Cs, T c0, Bat bt,
+                                                        const T* __restrict__ Fi) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* sy = sx + window;
+  const int64_t n = g.n;
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
+  const WinMap wm = win_map(td);
+  for (uint32_t l0 = threadIdx.x; l0 < window; l0 += 2 * blockDim.x) {
+    vec4<T> xv[2], yv[2];
+    uint32_t ls[2] = {l0, l0 + blockDim.x};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (ls[e] < window) {
+        const int64_t gi = wm(ls[e]);
+        xv[e].x = (T)(g.X[gi] - xo[0]);
+        xv[e].y = (T)(g.X[n + gi] - xo[1]);
+        xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+        xv[e].w = g.V[gi];
+        T qb[D], y[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < D; ++k) qb[k] = q[k * n + gi];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          T acc = T(0);
+#pragma unroll
+          for (int k = 0; k < D; ++k) acc += g.B0[(i * D + k) * n + gi] * qb[k];
+          y[i] = acc;
+        }
+        yv[e].x = y[0];
+        yv[e].y = y[1];
+        yv[e].z = y[2];
+        yv[e].w = T(0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ls[e] < window) {
+        sx[ls[e]] = xv[e];
+        sy[ls[e]] = yv[e];
+      }
   }
-  div = lane_sum<L>(div);
+  __syncthreads();
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
+  if ((uint32_t)t >= td.count) return;
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
+  const vec4<T> xa = sx[la], ya = sy[la];
+  T m[3] = {T(0), T(0), T(0)};
+  T tb = T(0);
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    const vec4<T> xb = sx[l], yb = sy[l];
+    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
+    T yd = yb.x * d[0] + yb.y * d[1];
+    if (D == 3) yd += yb.z * d[2];
+    tb += w * yd;
+#pragma unroll
+    for (int k = 0; k < D; ++k) m[k] += w * d[k];
+  });
+  T div = tb + ya.x * m[0] + ya.y * m[1];
+  if (D == 3) div += ya.z * m[2];
+  div = lane_sum<LPP>(div);
   if (h != 0) return;
   T cn = c[a] - (bt.spec ? bt.get<T>(BT_DTD, bt.spec[a]) : dt) * div;
-  if (Fi) {  // coupled: c is the content per reference volume, the saturation c / J
+  if (Fi) {
     T Fa[D * D];
 #pragma unroll
     for (int i = 0; i < D * D; ++i) Fa[i] = Fi[i * n + a];
@@ -1167,22 +1241,50 @@ int load_step(const sph_nbr* nb, const sph_state* st, double dt_l, hipStream_t s
   return SPH_OK;
 }
 
+// lanes per particle of the tiled diffusion kernels
+constexpr int kDiffLpp = 2;
+
+template <typename T>
+struct DiffLaunch {
+  TileGeo<T> g;
+  unsigned grid, block;
+  size_t lds1, lds2;  // window of one vec4 + one scalar, of two vec4
+};
+
+template <typename T>
+static DiffLaunch<T> diff_launch(const sph_nbr* nb) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  DiffLaunch<T> L;
+  L.g = tile_geo<T>(nb, prec);
+  L.grid = (unsigned)(8 * ((L.g.n_tiles + 7) / 8));
+  L.block = (unsigned)(L.g.tmax * kDiffLpp);
+  const size_t wm = (size_t)nb->tiling[prec].window_max;
+  L.lds1 = wm * (sizeof(vec4<T>) + sizeof(T));
+  L.lds2 = wm * 2 * sizeof(vec4<T>);
+  return L;
+}
+
 template <typename T, int D>
 static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double Dc,
                        double dt, double c_bc, hipStream_t s) {
-  Geo<T> g = geo<T>(nb);
+  const DiffLaunch<T> L = diff_launch<T>(nb);
+  if (L.g.n_tiles == 0) return SPH_OK;
+  int rc;
+  if ((rc = lds_attr(k_diff_grad<T, D, kDiffLpp>, L.lds1)) ||
+      (rc = lds_attr(k_diff_div<T, D, kDiffLpp>, L.lds2)))
+    return rc;
   {
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_GRAD, s);
-    k_diff_grad<T, D><<<nblk(nb->n, kDiffPerBlock), kDiffBlock, 0, s>>>(g, (const T*)st->c, (T*)st->q, (T)Dc,
-                                                       bat_view(nb));
+    k_diff_grad<T, D, kDiffLpp><<<L.grid, L.block, L.lds1, s>>>(
+        L.g, (const T*)st->c, nullptr, (T*)st->q, (T)Dc, 0, bat_view(nb));
     prof_end(nb, SPH_KERNEL_DIFF_GRAD, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   {
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_DIV, s);
-    k_diff_div<T, D><<<nblk(nb->n, kDiffPerBlock), kDiffBlock, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p,
-                                                    st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
-                                                    (T)m->c0, bat_view(nb), nullptr);
+    k_diff_div<T, D, kDiffLpp><<<L.grid, L.block, L.lds2, s>>>(
+        L.g, (T*)st->c, (const T*)st->q, (T*)st->p, st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
+        (T)m->c0, bat_view(nb), nullptr);
     prof_end(nb, SPH_KERNEL_DIFF_DIV, pe_, s);
   }
   SPH_LAUNCH_CHECK();
@@ -1194,24 +1296,29 @@ static int diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_state
 template <typename T, int D>
 static int diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                                double Dc, double dt, double c_bc, int nonlinear, hipStream_t s) {
-  Geo<T> g = geo<T>(nb);
-  const unsigned gr = nblk(nb->n, kDiffPerBlock);
+  const DiffLaunch<T> L = diff_launch<T>(nb);
+  if (L.g.n_tiles == 0) return SPH_OK;
+  int rc;
+  if ((rc = lds_attr(k_diff_F<T, D, kDiffLpp>, L.lds2)) ||
+      (rc = lds_attr(k_diff_grad<T, D, kDiffLpp>, L.lds1)) ||
+      (rc = lds_attr(k_diff_div<T, D, kDiffLpp>, L.lds2)))
+    return rc;
   T* Fi = (T*)st->PB;
   T* sat = (T*)st->p;
   {
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_GRAD, s);
-    k_diff_F<T, D><<<gr, kDiffBlock, 0, s>>>(g, st->u, (const T*)st->c, Fi, sat);
+    k_diff_F<T, D, kDiffLpp><<<L.grid, L.block, L.lds2, s>>>(L.g, st->u, (const T*)st->c, Fi, sat);
     SPH_LAUNCH_CHECK();
-    k_diff_grad_coupled<T, D><<<gr, kDiffBlock, 0, s>>>(g, sat, Fi, (T*)st->q, (T)Dc, nonlinear,
-                                                        bat_view(nb));
+    k_diff_grad<T, D, kDiffLpp><<<L.grid, L.block, L.lds1, s>>>(L.g, sat, Fi, (T*)st->q, (T)Dc,
+                                                                nonlinear, bat_view(nb));
     prof_end(nb, SPH_KERNEL_DIFF_GRAD, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   {
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DIFF_DIV, s);
-    k_diff_div<T, D><<<gr, kDiffBlock, 0, s>>>(g, (T*)st->c, (const T*)st->q, (T*)st->p, st->flags,
-                                               (T)dt, (T)c_bc, (T)m->C_swell, (T)m->c0,
-                                               bat_view(nb), Fi);
+    k_diff_div<T, D, kDiffLpp><<<L.grid, L.block, L.lds2, s>>>(
+        L.g, (T*)st->c, (const T*)st->q, (T*)st->p, st->flags, (T)dt, (T)c_bc, (T)m->C_swell,
+        (T)m->c0, bat_view(nb), Fi);
     prof_end(nb, SPH_KERNEL_DIFF_DIV, pe_, s);
   }
   SPH_LAUNCH_CHECK();
