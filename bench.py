@@ -581,7 +581,9 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "kernels_measured": "one profiled step after the warmup, outside the timed region (HIP events "
-                            "around every launch); the timed region times the roofline kernel only",
+                            "around every launch, around every sweep for the damping classes, whose "
+                            "passes share the sweep's time); the timed region times the roofline "
+                            "kernel class only",
         "fp32_forward_only": fwd32,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,

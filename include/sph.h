@@ -462,19 +462,22 @@ int sph_status(const sph_nbr* nbr, void* stream, int32_t* status_bits);
  * from a captured graph are not timed).  sph_profile_enable resets the
  * counters; sph_profile_read synchronises on the recorded events and returns
  * the number of launches and their summed duration for one kernel class.
- * Timing adds two event records per timed launch (a few microseconds of
- * queue time each); sph_profile_classes limits it to the classes whose bit
+ * Timing adds two event records per timed launch, or per sweep for the
+ * damping classes (a few microseconds of queue time each); sph_profile_classes limits it to the classes whose bit
  * (1 << class) is set in `mask` (all by default; kept across enables). */
 #define SPH_KERNEL_STRESS 0    /* deformation gradient + stress + PB */
 #define SPH_KERNEL_MOMENTUM 1  /* pair momentum sum + kick */
-#define SPH_KERNEL_DAMPING 2   /* one colour pass of the damping sweep */
+#define SPH_KERNEL_DAMPING 2   /* one colour pass of the damping sweep (timed per
+                                  sweep: one event pair around its colour passes,
+                                  which share its time) */
 #define SPH_KERNEL_DRIFT_KE 3  /* drift + kinetic energy + stop test */
 #define SPH_KERNEL_DIFF_GRAD 4 /* diffusion flux */
 #define SPH_KERNEL_DIFF_DIV 5  /* diffusion divergence + Dirichlet + pressure */
 #define SPH_KERNEL_LOAD 6      /* grip displacement increment */
 #define SPH_KERNEL_ADJ_STRESS 7  /* reverse: stress + momentum transpose */
 #define SPH_KERNEL_ADJ_GATHER 8  /* reverse: displacement-gradient transpose (+ drift) */
-#define SPH_KERNEL_ADJ_DAMPING 9 /* reverse: one colour pass of the transposed sweep */
+#define SPH_KERNEL_ADJ_DAMPING 9 /* reverse: one colour pass of the transposed sweep
+                                    (timed per sweep, as SPH_KERNEL_DAMPING) */
 #define SPH_KERNEL_COUNT 10
 int sph_profile_enable(sph_nbr* nbr, int enable);
 int sph_profile_classes(sph_nbr* nbr, uint32_t mask);

@@ -56,6 +56,7 @@ struct Prof {
   struct Pend {
     int kind;
     hipEvent_t a, b;
+    int launches;  // kernels between the two events
   };
   std::vector<hipEvent_t> pool;
   std::vector<Pend> pend;
@@ -264,7 +265,7 @@ inline int64_t tile_wmax_hard(int prec, int dim) {
 
 // ---- event timing around launches --------------------------------------------
 hipEvent_t prof_begin(const sph_nbr* nb, int kind, hipStream_t s);
-void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s);
+void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s, int launches = 1);
 int prof_resolve(const sph_nbr* nb);
 
 // ---- host entry points implemented per translation unit ----------------------

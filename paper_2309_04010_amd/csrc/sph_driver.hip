@@ -33,7 +33,7 @@ hipEvent_t prof_begin(const sph_nbr* nb, int kind, hipStream_t s) {
   return e;
 }
 
-void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s) {
+void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s, int launches) {
   Prof* p = nb->prof;
   if (!a || !p) return;
   hipEvent_t b = nullptr;
@@ -45,7 +45,7 @@ void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s) {
     return;
   }
   hipEventRecord(b, s);
-  p->pend.push_back(Prof::Pend{kind, a, b});
+  p->pend.push_back(Prof::Pend{kind, a, b, launches});
   if (p->pend.size() > 65536) prof_resolve(nb);
 }
 
@@ -56,7 +56,7 @@ int prof_resolve(const sph_nbr* nb) {
     SPH_HIP(hipEventSynchronize(q.b));
     float ms = 0.f;
     SPH_HIP(hipEventElapsedTime(&ms, q.a, q.b));
-    p->count[q.kind] += 1;
+    p->count[q.kind] += q.launches;
     p->ms[q.kind] += ms;
     p->pool.push_back(q.a);
     p->pool.push_back(q.b);

@@ -1102,12 +1102,10 @@ static int damp_launch(const sph_nbr* nb, const sph_state* st, hipStream_t s, bo
   const unsigned grid = (unsigned)((a1 - a0 + APW - 1) / APW);
   const int p = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   const int64_t po = nb->damp_pair_off[col];
-  hipEvent_t pe_ = prof_begin(nb, REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING, s);
   k_damp<T, D, G, REV><<<grid, 64, lds, s>>>(
       (const PairQ<T>*)nb->dwq[p] + po, (uint32_t)(nb->n_upairs - po), po, (const T*)nb->imass[p],
       nb->drow[gi], nb->drow_base[gi], nb->drow_empty[gi], nb->aoff, nb->ablk, a0, a1, bmax,
       nb->n, (T*)st->v, nb->ctrl, gated);
-  prof_end(nb, REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING, pe_, s);
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
@@ -1144,6 +1142,11 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
   if (!nb->damp_pre && (rc = damp_prepare_t<T>(nb, m, st, eta, dt, s))) return rc;
   const int ncol = 1 << D;
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  // timed per sweep: one event pair around its colour passes, which share
+  // the sweep's time (an event pair per pass adds its queue time to each)
+  const int kind = REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING;
+  hipEvent_t pe_ = prof_begin(nb, kind, s);
+  int passes = 0;
   for (int c_ = 0; c_ < ncol; ++c_) {
     const int col = REV ? ncol - 1 - c_ : c_;
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
@@ -1158,8 +1161,13 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
       case 32: rc = damp_launch<T, D, 32, REV>(nb, st, s, gated, col); break;
       default: rc = damp_launch<T, D, 64, REV>(nb, st, s, gated, col); break;
     }
-    if (rc) return rc;
+    if (rc) {
+      prof_end(nb, kind, pe_, s, passes);
+      return rc;
+    }
+    ++passes;
   }
+  prof_end(nb, kind, pe_, s, passes);
   return SPH_OK;
 }
 
