@@ -79,3 +79,7 @@ def test_build_errors(oracle_mod):
     with pytest.raises(B.SphError) as e:
         B.sph_build_neighbors(dev(X), dev(np.ones(10)), -1.0)
     assert e.value.code == B.SPH_E_ARG
+    # no particles
+    with pytest.raises(B.SphError) as e:
+        B.sph_build_neighbors(dev(np.zeros((3, 0))), dev(np.zeros(0)), 1.0)
+    assert e.value.code == B.SPH_E_ARG

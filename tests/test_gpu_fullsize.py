@@ -7,7 +7,8 @@ steps), copied to the host, and one application of each step is then
 compared, element by element, with the oracle applied to the same input:
 the solid stage (stress, P B0, momentum, kick), the damping sweep, its
 transpose (as a dot product with the oracle's sweep), drift + kinetic
-energy, and the diffusion step.  Tolerances: FP64 1e-10, FP32 1e-4 (1e-5
+energy, the diffusion step, a solid stage with the mixture momentum and the
+two-way coupled diffusion step.  Tolerances: FP64 1e-10, FP32 1e-4 (1e-5
 for the transposed sweep's dot product).
 """
 import numpy as np
@@ -107,6 +108,20 @@ def test_full_size_steps(plate, prec):
     B.sph_diffusion_step(nb, mg, st, Dc, dtd, c.run["c_bc"])
     assert rel_err(host(st.c) - cc, co - cc) < tol
     assert rel_err(host(st.p), po) < tol
+
+    # one solid stage with the mixture momentum (fluid density 1000), from the
+    # state and the flux the diffusion step has just left
+    print(f"[fullsize] mixture solid stage prec={prec}", flush=True)
+    mm = dict(m, rho_l0=1000.0)
+    u4, v4, c4, q4, p4 = host(st.u), host(st.v), host(st.c), host(st.q), host(st.p)
+    vo = v4.copy()
+    rc, PBo, acco = o.solid_step(o.material(**mm), dt, np.ascontiguousarray(u4), vo, p=p4, flags=flags,
+                                 c=c4, q=q4)
+    assert rc == 0
+    B.sph_solid_relax_step(nb, B.material(**mm), st, dt)
+    assert rel_err(host(st.PB), PBo) < tol
+    assert rel_err(host(st.acc), acco) < tol
+    assert rel_err(host(st.v) - v4, vo - v4) < tol
 
     # two-way coupled diffusion (nonlinear flux) from the deformed state
     print(f"[fullsize] coupled diffusion prec={prec}", flush=True)
