@@ -372,6 +372,23 @@ def run_mixture(case, torch, B, inner=200):
     return out
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of `nbytes` (torch's copy kernel), timed
+    with events: the practical HBM ceiling beside the published peak."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1000.0 / reps
+    del a, b
+    return dict(GBps=2.0 * nbytes / s / 1e9, bytes=nbytes, note="read + write of a 1 GiB copy")
+
+
 def run_sweep(torch, B, launches=2):
     """The batched parameter sweep: 64 strips of log-uniform size (1e3-5e4
     particles), each with its own E and D, 10 diffusion slow steps x 200
@@ -507,10 +524,12 @@ def main():
     alg_bytes = algorithmic_bytes(kern, adj32["dim"], 4, n_colors=adj32["n_colors"]) * nper
     achieved_gbs = alg_bytes / avg_s / 1e9
     workload_key = f"plate3d-{args.nx}x{args.nx}x4-fp32"
+    copy_bw = copy_bandwidth(torch)
     roofline = dict(bound="hbm", kernel=kern, achieved=achieved_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved_gbs / HBM_PEAK_GBS, traffic=measured_traffic(kern, workload_key),
                     avg_launch_us=avg_s * 1e6, launches=launches,
-                    alg_bytes_per_launch=alg_bytes)
+                    alg_bytes_per_launch=alg_bytes, copy_GBps=copy_bw["GBps"],
+                    frac_of_copy=achieved_gbs / copy_bw["GBps"])
     fpp = flops_per_pair(kern, adj32["dim"])
     if fpp:
         roofline["alu_tflops"] = fpp * P / avg_s / 1e12
