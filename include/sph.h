@@ -2,7 +2,9 @@
  * sph.h -- C ABI of the MI355X (gfx950) library for the fast process of
  * total-Lagrangian SPH solid dynamic relaxation inside an explicit
  * multi-time-step scheme (Tang, Wu, Wang, Haidn, Hu, arXiv 2309.04010), with
- * the slow-process SPH diffusion update beside it.
+ * the slow processes beside it: displacement loading, the SPH diffusion
+ * update (one-way, or two-way coupled to the deformation), and, optionally,
+ * the momentum of the fluid in a saturated solid (sph_material.rho_l0).
  *
  * Conventions
  *  - Every function returns int: SPH_OK (0), a negative SPH_E_* error, or the

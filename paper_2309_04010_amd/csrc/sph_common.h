@@ -95,7 +95,7 @@ struct Tune {
   int damp_g[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
 };
 
-// diffusion gathers (slow step and its reverse): lanes per particle, threads per block
+// reverse diffusion gathers (CSR lists): lanes per particle, threads per block
 constexpr int kDiffLanes = 8;
 constexpr int kDiffBlock = 1024;
 constexpr int kDiffPerBlock = kDiffBlock / kDiffLanes;
