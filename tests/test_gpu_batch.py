@@ -2,7 +2,8 @@
 E, D and step sizes, run forward and in reverse in single launches.
 
 * each specimen of an FP64 batched run equals the oracle run of that
-  specimen alone (1e-10), and FP32 is within 1e-4;
+  specimen alone (1e-10), and FP32 is within 1e-4; also with the two-way
+  coupled nonlinear slow step and the mixture momentum;
 * with each specimen at its own coordinates (overlapping in space), a
   batched specimen equals its own GPU run bitwise: same cells, order,
   neighbours and schedule;
@@ -74,19 +75,22 @@ class _Run:
         return out
 
 
-def _oracle_strip(oracle_mod, c, E, D, dt_s, dt_slow, complex_step=False, pert=None):
+def _oracle_strip(oracle_mod, c, E, D, dt_s, dt_slow, complex_step=False, pert=None, slow_kind=None,
+                  nonlinear=0, rho_l0=0.0):
     o = oracle_mod.Oracle(2, c.X, c.V, c.h, complex_step=complex_step)
     perm = o.perm
     flags = np.ascontiguousarray(c.flags[perm])
-    m = dict(c.material, E=E)
+    m = dict(c.material, E=E, rho_l0=rho_l0)
     r = dict(c.run, D=D, dt_s=dt_s, dt_slow=dt_slow)
+    if slow_kind is not None:
+        r["slow_kind"] = slow_kind
     if pert:
         (nm, val), = pert.items()
         if nm == "D":
             r["D"] = val
         else:
             m[nm] = val
-    cfg = o.cfg(**{k: v for k, v in r.items() if k != "D"}, D=r["D"])
+    cfg = o.cfg(**{k: v for k, v in r.items() if k != "D"}, D=r["D"], nonlinear=nonlinear)
     u, v = o.arr(2, c.n), o.arr(2, c.n)
     cc = np.ascontiguousarray(c.c_init[perm], dtype=o.dtype)
     q, p = o.arr(2, c.n), o.arr(c.n)
@@ -112,6 +116,29 @@ def test_batched_forward_equals_each_specimen_alone(oracle_mod, prec):
         got = u[:, bt.offsets[i]:bt.offsets[i + 1]]
         assert np.abs(want).max() > 0
         assert rel_err(got, want) < tol, (i, rel_err(got, want))
+    R.nb.close()
+
+
+def test_batched_coupled_mixture_equals_each_specimen_alone(oracle_mod):
+    """The two-way coupled nonlinear slow step and the mixture momentum in a
+    batched run: per-specimen D and step sizes reach the coupled kernels, the
+    mixture masses and the kinetic energy."""
+    bt = _small_batch()
+    print(f"[batch] coupled + mixture, {len(bt.cases)} strips, n={bt.n}", flush=True)
+    R = _Run(bt, B.SPH_F64)
+    R.reset()
+    r = dict(bt.run, slow_kind=cases.DIFFUSION_COUPLED)
+    cfg = B.multirate_cfg(**r, batch=R.batch, diff_nonlinear=1)
+    mat = B.material(**dict(bt.material, rho_l0=1000.0))
+    rc, k, _, _, _ = B.sph_advance_multirate(R.nb, mat, R.st, cfg)
+    assert np.all(k == bt.run["fixed_inner"])
+    u = R.u_input_order()
+    for i, c in enumerate(bt.cases):
+        want = _oracle_strip(oracle_mod, c, bt.E[i], bt.D[i], bt.dt_s[i], bt.dt_slow[i],
+                             slow_kind=cases.DIFFUSION_COUPLED, nonlinear=1, rho_l0=1000.0)
+        got = u[:, bt.offsets[i]:bt.offsets[i + 1]]
+        assert np.abs(want).max() > 0
+        assert rel_err(got, want) < 1e-10, (i, rel_err(got, want))
     R.nb.close()
 
 
