@@ -468,6 +468,9 @@ def main():
     ap.add_argument("--necking", choices=["none", "sample", "full"], default="sample",
                     help="necking runs: sample = the full 2D run and the first 1000 load increments "
                          "of the 3D one; full = both full runs")
+    ap.add_argument("--necking-compare", action="store_true",
+                    help="run each necking case in FP32 and in FP64 and report how far the FP32 "
+                         "curves deviate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -569,6 +572,20 @@ def main():
             necking[name] = run_necking(name, B.SPH_F64 if name == "necking2d" else B.SPH_F32, n3,
                                         torch, B)
             print(f"[bench] {name} done: {necking[name]['seconds']:.1f} s", flush=True)
+            if args.necking_compare:
+                other = B.SPH_F32 if name == "necking2d" else B.SPH_F64
+                r2 = run_necking(name, other, n3, torch, B)
+                print(f"[bench] {name} in the other precision done: {r2['seconds']:.1f} s", flush=True)
+                r32, r64 = (r2, necking[name]) if other == B.SPH_F32 else (necking[name], r2)
+                c32 = np.array(r32["curve_stretch_reaction_neck"])
+                c64 = np.array(r64["curve_stretch_reaction_neck"])
+                necking[name]["fp32_vs_fp64"] = dict(
+                    seconds_fp32=r32["seconds"], seconds_fp64=r64["seconds"],
+                    reaction_max_rel_dev=float(np.abs(c32[:, 1] - c64[:, 1]).max() / np.abs(c64[:, 1]).max()),
+                    neck_max_rel_dev=float(np.abs(c32[:, 2] - c64[:, 2]).max() / np.abs(c64[:, 2]).max()),
+                    peak_reaction_fp32=r32["peak_reaction"], peak_reaction_fp64=r64["peak_reaction"],
+                    final_neck_fp32=r32["final_neck_displacement"],
+                    final_neck_fp64=r64["final_neck_displacement"])
 
     sweep = None
     if not args.no_sweep:
