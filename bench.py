@@ -16,10 +16,17 @@ Metric: inner-step particle-interactions/s = directed pairs x inner steps /
 wall time of forward + reverse, inputs resident in HBM.  Also reported: the
 FP32 forward alone, the plain FP64 forward (the baseline of the speedup), the
 FP32 state and gradient errors against an FP64 run of the same step, the
-roofline of the dominant kernel (live event timing of every launch in the
-timed region), and the CPU oracle timed on a bounded sample.
+roofline of the dominant kernel class (live HIP-event timing of its launches
+in the timed region, the calibrated counter traffic, a measured copy
+bandwidth), the per-kernel breakdown, the CPU oracle timed on a bounded
+sample, and, outside the timed region: the slow-step variants (one-way and
+two-way coupled diffusion), the cost of the mixture momentum, the necking
+runs of Sec. 5.1/5.2 with their iteration counts (N_S, N_s, N_d) and
+curves, and the batched sweep of 64 strips.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner M] [--no-cpu]
+                  [--no-fp64] [--no-sweep] [--no-coupled] [--necking none|sample|full]
+                  [--necking-compare] [--nx N] [--copy-calibration]
 """
 from __future__ import annotations
 
