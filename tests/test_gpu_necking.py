@@ -87,3 +87,26 @@ def test_necking_graph_equals_eager(oracle_mod):
             r.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,prec,n_inc", [("necking2d", B.SPH_F64, 20), ("necking3d", B.SPH_F32, 2)],
+                         ids=["bar-f64", "cylinder-f32"])
+def test_necking_full_size(oracle_mod, name, prec, n_inc):
+    """The paper's specimens at full size (10,700 and 264,224 particles), in
+    the precisions the bench runs them, for the first load increments: one
+    oracle run of the same increments."""
+    c = cases.by_name(name, n_slow=n_inc, total_stretch=n_inc * cases.by_name(name).observable["total_stretch"]
+                      / cases.by_name(name).run["n_slow"], t_end=n_inc * 0.01)
+    print(f"[necking] full size {name} n={c.n} prec={prec} increments={n_inc}", flush=True)
+    o, want = _oracle_run(oracle_mod, c, prec)
+    r = NeckingRun(c, prec, record_every=n_inc)
+    try:
+        res = r.run()
+        tol = TOL[prec]
+        assert res["N_s"] == n_inc * c.run["fixed_inner"] and res["status_bits"] == 0
+        assert rel_err(host(r.st.u), want["u"]) < tol
+        assert rel_err(host(r.st.acc), want["acc"]) < tol
+        assert abs(res["history"]["radius"][-1] - want["dr"]) <= tol * np.abs(want["u"]).max()
+    finally:
+        r.close()
