@@ -317,12 +317,15 @@ orc_sys* orc_create(int dim, int64_t n, const double* X_id, const double* V_id, 
       for (int k = 0; k < dim; ++k) s->B0[(i * dim + k) * n + a] = Mi[i * 3 + k];
   }
 
-  /* --- damping schedule.  Every unordered pair {a<b} is anchored at the
-   *     componentwise minimum of the two particles' cells; its colour is
-   *     the parity vector of the anchor.  Within an anchor, pairs are
-   *     taken in ascending (a, b) and given the smallest level not used by
-   *     an earlier pair of the same anchor that shares a particle (first
-   *     fit).  Canonical order: colour, anchor key, level, a, b. --- */
+  /* --- damping schedule (Sec. 4.3).  Every unordered pair {a<b} is
+   *     anchored at the componentwise minimum of the two particles' cells,
+   *     except along an axis only two cells deep, where the anchor takes
+   *     the first cell: the block then spans that axis, and the two colours
+   *     along it would touch the same cells anyway.  The colour is the
+   *     parity vector of the anchor.  Within an anchor, pairs are taken in
+   *     ascending (a, b) and given the smallest level not used by an
+   *     earlier pair of the same anchor that shares a particle (first fit).
+   *     Canonical order: colour, anchor key, level, a, b. --- */
   int64_t np = s->n_pairs / 2;
   s->n_upairs = np;
   uint32_t* ua = (uint32_t*)malloc((np > 0 ? np : 1) * sizeof(uint32_t));
@@ -336,7 +339,7 @@ orc_sys* orc_create(int dim, int64_t n, const double* X_id, const double* V_id, 
       int64_t ca[3], cb[3], an[3];
       cell_coords(s, s->key[a], ca);
       cell_coords(s, s->key[b], cb);
-      for (int k = 0; k < 3; ++k) an[k] = ca[k] < cb[k] ? ca[k] : cb[k];
+      for (int k = 0; k < 3; ++k) an[k] = s->nc[k] == 2 ? 0 : (ca[k] < cb[k] ? ca[k] : cb[k]);
       ua[m] = (uint32_t)a;
       ub[m] = (uint32_t)b;
       uk[m] = (uint32_t)(an[0] + s->nc[0] * (an[1] + s->nc[1] * an[2]));

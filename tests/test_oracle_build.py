@@ -140,7 +140,8 @@ def test_schedule_invariants(oracle_mod, name, dim, gen):
             prev = -1
             for i in range(lo, hi):
                 ca, cb = coords(int(o.key[a[i]])), coords(int(o.key[b[i]]))
-                assert np.array_equal(np.minimum(ca, cb), A), "anchor = componentwise min cell"
+                want = np.where(np.array(nc) == 2, 0, np.minimum(ca, cb))
+                assert np.array_equal(want, A), "anchor = componentwise min cell (first cell on a 2-cell axis)"
                 assert lev[i] >= prev
                 prev = lev[i]
                 for p in (a[i], b[i]):
@@ -151,6 +152,15 @@ def test_schedule_invariants(oracle_mod, name, dim, gen):
                 owner[(int(a[i]), int(b[i]))] = ak
             assert o.anchor_nlev[ai] == lev[hi - 1] + 1
     assert len(owner) == o.n_upairs
+    # along an axis two cells deep every block spans the axis: the colours
+    # with odd parity along it hold no anchor
+    for ax in range(dim):
+        if nc[ax] == 2:
+            for col in range(ncol):
+                if (col >> ax) & 1:
+                    assert o.color_off[col + 1] == o.color_off[col]
+    if name == "lattice3d":
+        assert list(nc[:3]) == [3, 2, 2], "the case must exercise two-cell axes"
 
 
 def test_schedule_first_fit(oracle_mod):
