@@ -81,14 +81,44 @@ def algorithmic_bytes(kernel, dim, prec_bytes, model_j2=False, n_colors=8):
 
 
 def flops_per_pair(kernel, dim):
-    """Useful floating-point operations per directed pair (FMA = 2)."""
+    """Useful floating-point operations per directed pair (FMA = 2); the
+    per-particle epilogues (constitutive update and its transpose) are not
+    counted."""
     d = dim
     geo = 3 * d + 6            # dx, r^2, sqrt, q, (1-q/2)^3 and scaling
     if kernel == "stress":
         return geo + d + 2 * d * d + 2 * d   # du, outer-product accumulation
     if kernel == "momentum":
         return geo + d * d + 2 * d * d + 2 * d
+    if kernel == "adj_stress":
+        # V_b, V_a scalings; du; w du; w_b a_a - w_a a_b; two outer-product sums
+        return geo + 2 + d + d + 3 * d + 2 * d * d + 2 * d * d
+    if kernel == "adj_gather":
+        # V_b scaling; G_bar_b d; its weighted sum; sum_b V_b grad W
+        return geo + 1 + 2 * d * d + 2 * d + 2 * d
     return 0
+
+
+def roofline_of(kern, prof, dim, n, n_pairs, n_colors, workload_key):
+    """Roofline of one kernel class from its timed launches: the HBM roof
+    (algorithmic bytes per launch) or, when the class's algorithmic intensity
+    (flops per byte) exceeds the ridge of the two peaks, the FP32 vector roof
+    (useful flops per launch)."""
+    launches, kms = prof[kern]
+    avg_s = kms / 1000.0 / max(launches, 1)
+    alg_bytes = algorithmic_bytes(kern, dim, 4, n_colors=n_colors) * n
+    flops = flops_per_pair(kern, dim) * n_pairs
+    ridge = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    common = dict(kernel=kern, traffic=measured_traffic(kern, workload_key), avg_launch_us=avg_s * 1e6,
+                  launches=launches, alg_bytes_per_launch=alg_bytes, alg_flops_per_launch=flops,
+                  intensity_flop_per_byte=flops / alg_bytes if alg_bytes else None)
+    if flops and flops / alg_bytes > ridge:
+        ach = flops / avg_s / 1e12
+        return dict(bound="alu", achieved=ach, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / FP32_PEAK_TFLOPS, **common)
+    ach = alg_bytes / avg_s / 1e9
+    return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                **common)
 
 
 def kernel_source_hash():
@@ -526,34 +556,33 @@ def main():
                         u_rel_err=ue, J_fp32=adj32["J"], J_fp64=adj64["J"], grad=gr)
 
     # dominant kernel class (by total time in the profiled untimed step),
-    # timed with HIP events around each of its launches in the timed region
+    # timed with HIP events around its launches in the timed region
     kern = adj32["dominant"]
-    launches, kms = prof32[kern]
-    avg_s = kms / 1000.0 / max(launches, 1)
     nper = adj32["n"]
-    alg_bytes = algorithmic_bytes(kern, adj32["dim"], 4, n_colors=adj32["n_colors"]) * nper
-    achieved_gbs = alg_bytes / avg_s / 1e9
     workload_key = f"plate3d-{args.nx}x{args.nx}x4-fp32"
     copy_bw = copy_bandwidth(torch)
-    roofline = dict(bound="hbm", kernel=kern, achieved=achieved_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved_gbs / HBM_PEAK_GBS, traffic=measured_traffic(kern, workload_key),
-                    avg_launch_us=avg_s * 1e6, launches=launches,
-                    alg_bytes_per_launch=alg_bytes, copy_GBps=copy_bw["GBps"],
-                    frac_of_copy=achieved_gbs / copy_bw["GBps"])
-    fpp = flops_per_pair(kern, adj32["dim"])
-    if fpp:
-        roofline["alu_tflops"] = fpp * P / avg_s / 1e12
-        roofline["alu_frac_fp32"] = roofline["alu_tflops"] / FP32_PEAK_TFLOPS
+    roofline = roofline_of(kern, prof32, adj32["dim"], nper, P, adj32["n_colors"], workload_key)
+    roofline.update(copy_GBps=copy_bw["GBps"])
+    if roofline["bound"] == "hbm":
+        roofline["frac_of_copy"] = roofline["achieved"] / copy_bw["GBps"]
+    # the damping pass beside it, from the profiled step (HBM view)
+    damping_view = None
+    if kern != "damping" and adj32["breakdown"].get("damping", (0, 0))[0]:
+        damping_view = roofline_of("damping", adj32["breakdown"], adj32["dim"], nper, P,
+                                   adj32["n_colors"], workload_key)
+        damping_view["frac_of_copy"] = damping_view["achieved"] / copy_bw["GBps"]
+        damping_view["measured"] = "the profiled step outside the timed region"
     kernels = {}
     for k, (c, ms) in adj32["breakdown"].items():
         if not c:
             continue
         kernels[k] = dict(launches=c, avg_us=1000.0 * ms / c, total_ms=ms)
-        try:
-            ab = algorithmic_bytes(k, adj32["dim"], 4) * nper
+        ab = algorithmic_bytes(k, adj32["dim"], 4) * nper
+        if ab:
             kernels[k]["alg_GBps"] = ab / (ms / 1000.0 / c) / 1e9
-        except TypeError:
-            pass
+        fl = flops_per_pair(k, adj32["dim"]) * P
+        if fl:
+            kernels[k]["alu_TFLOPs"] = fl / (ms / 1000.0 / c) / 1e12
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -622,6 +651,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": roofline,
+        "roofline_damping": damping_view,
         "kernels": kernels,
         "kernels_measured": "one profiled step after the warmup, outside the timed region (HIP events "
                             "around every launch, around every sweep for the damping classes, whose "

@@ -477,13 +477,21 @@ __device__ __forceinline__ Block anchor_block(uint32_t akey, const Grid& g, cons
   return blk;
 }
 
+// a pair's anchor: the componentwise minimum of its two cells, except along
+// an axis of exactly two cells (of its specimen's grid segment), where it is
+// the first cell, so that the block spans the axis and one colour pass covers
+// what the two parities along it would (same-colour blocks stay disjoint)
 __device__ __forceinline__ bool anchored_at(uint32_t ks, uint32_t kt, const int64_t A[3],
                                             const Grid& g) {
+  const GridSeg sg = seg_of_cell(g, ks);  // neighbours never cross specimens
   int64_t cs_[3], ct[3];
-  key_coords(ks, g, cs_);
-  key_coords(kt, g, ct);
-  for (int k = 0; k < 3; ++k)
-    if ((cs_[k] < ct[k] ? cs_[k] : ct[k]) != A[k]) return false;
+  key_coords_s(ks, sg, cs_);
+  key_coords_s(kt, sg, ct);
+  const int64_t nc[3] = {sg.nc0, sg.nc1, sg.nc2};
+  for (int k = 0; k < 3; ++k) {
+    const int64_t m = nc[k] == 2 ? 0 : (cs_[k] < ct[k] ? cs_[k] : ct[k]);
+    if (m != A[k]) return false;
+  }
   return true;
 }
 
