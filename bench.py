@@ -426,6 +426,51 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     return dict(GBps=2.0 * nbytes / s / 1e9, bytes=nbytes, note="read + write of a 1 GiB copy")
 
 
+def run_full_adjoint(case, torch, B, A, n_slow=50, inner=1000):
+    """The whole checkpointed adjoint run of the plate: `n_slow` diffusion
+    slow steps x `inner` inner steps forward (one checkpoint per slow step,
+    the inner states of the last one), then the reverse pass, which re-runs
+    each earlier slow step from its checkpoint to record its inner states.
+    FP32, then FP64 for the gradient's error."""
+    import numpy as np
+    import dataclasses
+    out = {}
+    for prec, tag in ((B.SPH_F32, "f32"), (B.SPH_F64, "f64")):
+        run = dict(case.run)
+        run.update(n_slow=n_slow, fixed_inner=inner)
+        c = dataclasses.replace(case, run=run)
+        pr = A.MultirateProblem(c, prec, k_hist=inner, chunk=min(inner, 250))
+        th = pr.theta0()
+        B.sph_autotune(pr.nb, pr._material(th), pr.st, run["eta"], pr.run["dt_s"], with_adjoint=True)
+        idx = pr.perm.argsort()[case.observable["J_index"]]
+        w = torch.zeros((case.dim, case.n), dtype=torch.float64, device="cuda")
+        w[case.observable["J_component"], torch.as_tensor(idx).cuda()] = 1.0 / len(idx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr.forward(th)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        print(f"[bench] full adjoint {tag}: forward {t1 - t0:.1f} s", flush=True)
+        J = float((pr.st.u * w).sum().item())
+        g = pr.backward(w).cpu().numpy()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        print(f"[bench] full adjoint {tag}: reverse {t2 - t1:.1f} s", flush=True)
+        total_inner = int(pr.last["k"].sum())
+        out[tag] = dict(seconds_forward=t1 - t0, seconds_reverse=t2 - t1, inner_steps=total_inner,
+                        interactions_per_s=pr.nb.info.n_pairs * total_inner / (t2 - t0), J=J,
+                        grad={B.GRAD_NAMES[i]: float(g[i]) for i in (B.SPH_GRAD_E, B.SPH_GRAD_D,
+                                                                      B.SPH_GRAD_C)})
+        pr.close()
+    out["grad_rel_err_f32"] = {k: abs(out["f32"]["grad"][k] - out["f64"]["grad"][k]) /
+                               abs(out["f64"]["grad"][k]) for k in out["f64"]["grad"]}
+    out["J_rel_err_f32"] = abs(out["f32"]["J"] - out["f64"]["J"]) / abs(out["f64"]["J"])
+    out["workload"] = (f"plate3d {case.shape[0]}x{case.shape[1]}x{case.shape[2]}, {n_slow} diffusion slow steps x "
+                       f"{inner} inner steps, forward with checkpoints, then the reverse pass "
+                       f"(d mean centre deflection / d(E, D, C))")
+    return out
+
+
 def run_sweep(torch, B, launches=2):
     """The batched parameter sweep: 64 strips of log-uniform size (1e3-5e4
     particles), each with its own E and D, 10 diffusion slow steps x 200
@@ -505,6 +550,9 @@ def main():
     ap.add_argument("--necking", choices=["none", "sample", "full"], default="sample",
                     help="necking runs: sample = the full 2D run and the first 1000 load increments "
                          "of the 3D one; full = both full runs")
+    ap.add_argument("--full-adjoint", action="store_true",
+                    help="also run the whole checkpointed adjoint (50 slow x 1000 inner steps) in FP32 "
+                         "and FP64")
     ap.add_argument("--necking-compare", action="store_true",
                     help="run each necking case in FP32 and in FP64 and report how far the FP32 "
                          "curves deviate")
@@ -623,6 +671,8 @@ def main():
                     final_neck_fp32=r32["final_neck_displacement"],
                     final_neck_fp64=r64["final_neck_displacement"])
 
+    full_adjoint = run_full_adjoint(case, torch, B, A) if args.full_adjoint else None
+
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep(torch, B)
@@ -665,6 +715,7 @@ def main():
         "slow_step_variants": coupled,
         "mixture_momentum": mixture,
         "necking": necking,
+        "full_adjoint": full_adjoint,
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,
