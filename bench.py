@@ -164,7 +164,7 @@ def setup(case, prec, torch, B):
     return nb, st
 
 
-def run_gpu(case, prec, steps, warmup, inner, torch, B, profile=True):
+def run_gpu(case, prec, steps, warmup, inner, torch, B, profile=True, use_graph=0):
     nb, st = setup(case, prec, torch, B)
     mat = B.material(**case.material)
     run = dict(case.run)
@@ -172,7 +172,7 @@ def run_gpu(case, prec, steps, warmup, inner, torch, B, profile=True):
     K = case.material["E"] / (3.0 * (1.0 - 2.0 * case.material["nu"]))
     B.sph_autotune(nb, mat, st, run["eta"], 0.6 * case.h / (K / case.material["rho0"]) ** 0.5,
                    with_adjoint=False)
-    cfg = B.multirate_cfg(**run, chunk=min(inner, 250), use_graph=0)
+    cfg = B.multirate_cfg(**run, chunk=min(inner, 250), use_graph=use_graph)
     for _ in range(warmup):
         B.sph_advance_multirate(nb, mat, st, cfg)
     torch.cuda.synchronize()
@@ -550,6 +550,7 @@ def main():
     ap.add_argument("--necking", choices=["none", "sample", "full"], default="sample",
                     help="necking runs: sample = the full 2D run and the first 1000 load increments "
                          "of the 3D one; full = both full runs")
+    ap.add_argument("--no-neck3d", action="store_true")
     ap.add_argument("--full-adjoint", action="store_true",
                     help="also run the whole checkpointed adjoint (50 slow x 1000 inner steps) in FP32 "
                          "and FP64")
@@ -673,6 +674,21 @@ def main():
 
     full_adjoint = run_full_adjoint(case, torch, B, A) if args.full_adjoint else None
 
+    # the 3D J2 bar (100 x 20 x 20): its whole schedule, 100 loading slow steps
+    # x 1000 inner steps, forward, in FP32 and in plain FP64
+    neck = None
+    if not args.no_neck3d:
+        nc = cases.neck3d()
+        neck = {"workload": f"neck3d 100x20x20 ({nc.n} particles), J2, 100 loading slow steps x 1000 inner "
+                            f"steps, forward"}
+        for prec, tag in ((B.SPH_F32, "f32"), (B.SPH_F64, "f64")):
+            info, _ = run_gpu(nc, prec, 100, 1, 1000, torch, B, profile=False)
+            neck[tag] = dict(seconds=info["seconds"], inner_steps=info["total_inner"], pairs=info["pairs"],
+                             interactions_per_s=info["pairs"] * info["total_inner"] / info["seconds"],
+                             status=info["status"], u_finite=info["u_finite"])
+            print(f"[bench] neck3d {tag} done: {info['seconds']:.1f} s", flush=True)
+        neck["f32_over_f64"] = neck["f32"]["interactions_per_s"] / neck["f64"]["interactions_per_s"]
+
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep(torch, B)
@@ -716,6 +732,7 @@ def main():
         "mixture_momentum": mixture,
         "necking": necking,
         "full_adjoint": full_adjoint,
+        "neck3d": neck,
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,
