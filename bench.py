@@ -471,6 +471,36 @@ def run_full_adjoint(case, torch, B, A, n_slow=50, inner=1000):
     return out
 
 
+def run_small_configs(torch, B):
+    """The 2D bar (plain FP64) and the swelling strip (FP32, and FP64 as its
+    reference) over their whole schedules of 100 slow steps, the inner
+    counts chosen by the kinetic-energy stop test."""
+    import numpy as np
+    from paper_2309_04010_amd import cases
+    out = {}
+    runs = (("bar2d", cases.bar2d(), B.SPH_F64), ("strip2d_f32", cases.strip2d(), B.SPH_F32),
+            ("strip2d_f64", cases.strip2d(), B.SPH_F64))
+    u_end = {}
+    for tag, c, prec in runs:
+        nb, st = setup(c, prec, torch, B)
+        cfg = B.multirate_cfg(**c.run, chunk=250)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, k, ke, conv, rep = B.sph_advance_multirate(nb, B.material(**c.material), st, cfg)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        u_end[tag] = st.u.double().cpu().numpy()
+        out[tag] = dict(particles=nb.info.n, pairs=nb.info.n_pairs, N_S=int(len(k)), N_s=int(k.sum()),
+                        k_min=int(k.min()), k_max=int(k.max()), converged=int(conv.sum()), seconds=sec,
+                        interactions_per_s=nb.info.n_pairs * float(k.sum()) / sec)
+        nb.close()
+    out["strip2d_f32_u_rel_err"] = float(np.abs(u_end["strip2d_f32"] - u_end["strip2d_f64"]).max() /
+                                         np.abs(u_end["strip2d_f64"]).max())
+    out["note"] = ("bar2d: 40x8, LE, 100 loading slow steps; strip2d: 200x10, NH + swelling, 100 diffusion "
+                   "slow steps; inner counts by the kinetic-energy stop test (N_s inner steps in all)")
+    return out
+
+
 def run_sweep(torch, B, launches=2):
     """The batched parameter sweep: 64 strips of log-uniform size (1e3-5e4
     particles), each with its own E and D, 10 diffusion slow steps x 200
@@ -550,7 +580,7 @@ def main():
     ap.add_argument("--necking", choices=["none", "sample", "full"], default="sample",
                     help="necking runs: sample = the full 2D run and the first 1000 load increments "
                          "of the 3D one; full = both full runs")
-    ap.add_argument("--no-neck3d", action="store_true")
+    ap.add_argument("--no-neck3d", action="store_true", help="skip the neck3d, bar2d and strip2d runs")
     ap.add_argument("--full-adjoint", action="store_true",
                     help="also run the whole checkpointed adjoint (50 slow x 1000 inner steps) in FP32 "
                          "and FP64")
@@ -674,6 +704,10 @@ def main():
 
     full_adjoint = run_full_adjoint(case, torch, B, A) if args.full_adjoint else None
 
+    small = None if args.no_neck3d else run_small_configs(torch, B)
+    if small:
+        print("[bench] bar2d / strip2d done", flush=True)
+
     # the 3D J2 bar (100 x 20 x 20): its whole schedule, 100 loading slow steps
     # x 1000 inner steps, forward, in FP32 and in plain FP64
     neck = None
@@ -733,6 +767,7 @@ def main():
         "necking": necking,
         "full_adjoint": full_adjoint,
         "neck3d": neck,
+        "bar2d_strip2d": small,
         "gradient": {B.GRAD_NAMES[i]: float(adj32["grad"][i])
                      for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)},
         "cpu_baseline": cpu,
