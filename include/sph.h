@@ -119,8 +119,8 @@ typedef struct {
                      the fluid's momentum flux v^l (x) q of eq. (totalmomentumupdatesph) as
                      a Piola tensor; the inertia of the kick, the damping sweep's masses
                      and the kinetic energy become (rho0 + rho_l0 c_a) V_a.  The time step
-                     stays 0.6 h / sqrt(K / rho0).  The reverse pass refuses it
-                     (SPH_E_UNSUPPORTED). */
+                     stays 0.6 h / sqrt(K / rho0).  The reverse pass refuses a
+                     mixture (SPH_E_UNSUPPORTED). */
 } sph_material;
 
 typedef struct {
@@ -250,7 +250,8 @@ int sph_diffusion_step(const sph_nbr* nbr, const sph_material* mat, const sph_st
  * c = c_bc J on SPH_FLAG_CDIR particles (saturation c_bc) and
  * p = C_swell (c / J - c0).  Needs st->u, c, q, p; uses st->PB as scratch
  * (overwritten: F^-1).  With u = 0 and nonlinear = 0 it is
- * sph_diffusion_step.  No reverse pass.  Asynchronous. */
+ * sph_diffusion_step.  Its reverse runs inside sph_advance_multirate_backward
+ * (there is no single-step VJP entry).  Asynchronous. */
 int sph_diffusion_step_coupled(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
                                double D, double dt_d, double c_bc, int32_t nonlinear, void* stream);
 
@@ -362,7 +363,10 @@ int sph_diffusion_step_vjp(const sph_nbr* nbr, const sph_material* mat, const sp
  * step from its checkpoint (recording its inner states, k_rec[l] <=
  * k_hist_cap required) unless hist_u already holds it; st is used as working
  * storage and restored to the final state on return.  adj->p must be zero on
- * entry.  Synchronous.  Errors: SPH_E_ARG (tape incomplete), SPH_E_CAPACITY. */
+ * entry.  Slow steps: loading, diffusion, and the two-way coupled diffusion
+ * (one specimen; its u-dependence through F, J and F^-1 goes to adj->u).
+ * Synchronous.  Errors: SPH_E_ARG (tape incomplete), SPH_E_CAPACITY,
+ * SPH_E_UNSUPPORTED (a mixture, or a batched coupled run). */
 int sph_advance_multirate_backward(const sph_nbr* nbr, const sph_material* mat,
                                    const sph_state* st, const sph_multirate_cfg* cfg,
                                    sph_tape* tape, const sph_adjoint* adj, void* stream);

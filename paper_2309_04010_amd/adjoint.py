@@ -34,7 +34,7 @@ class MultirateProblem:
         self.nb = B.sph_build_neighbors(dev(case.X), dev(case.V), case.h)
         self.perm = self.nb.host("perm").astype(np.int64)
         self.j2 = case.material["model"] == B.SPH_MODEL_J2
-        self.diff = case.run["slow_kind"] == B.SPH_SLOW_DIFFUSION
+        self.diff = case.run["slow_kind"] != B.SPH_SLOW_LOAD
         self.st = B.new_state(self.nb, prec, with_plastic=self.j2, with_diffusion=self.diff)
         self.st.flags = torch.as_tensor(np.ascontiguousarray(case.flags[self.perm])).cuda()
         if case.vgrip is not None:

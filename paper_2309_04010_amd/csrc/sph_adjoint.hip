@@ -609,12 +609,14 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
 
 // reverse of the displacement-gradient sum:
 //   u_bar_a -= sum_b (V_a G_bar_b + V_b G_bar_a) grad_a W_ab,
-// then (drift_dt != 0) the drift transpose of the previous inner step,
-// w_a += drift_dt u_bar_a for free particles
+// then (drift_dt != 0) the drift transpose of the previous inner step for
+// free particles: w_a += drift_dt u_bar_a, or, with drift_incr, only this
+// gather's increment, w_a -= drift_dt sum_b (...) (for a term added after
+// that drift's transpose has already taken the rest of u_bar)
 template <typename T, int D, int LPP>
 __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
     TileGeo<T> g, const T* __restrict__ Gb, double* __restrict__ ub, T* __restrict__ w,
-    const uint8_t* __restrict__ flags, double drift_dt, Bat bt) {
+    const uint8_t* __restrict__ flags, double drift_dt, Bat bt, int drift_incr = 0) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
   constexpr int NP = (D * D + 3) / 4;
@@ -705,7 +707,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
   for (int i = 0; i < D; ++i) {
     const double un = ub[i * n + a] - (double)f[i];
     ub[i * n + a] = un;
-    if (ddt != 0.0 && !fixed) w[i * n + a] += (T)(ddt * un);
+    if (ddt != 0.0 && !fixed) w[i * n + a] += (T)(ddt * (drift_incr ? -(double)f[i] : un));
   }
 }
 
@@ -856,6 +858,319 @@ __global__ __launch_bounds__(kDiffBlock) void k_adiff_b(Geo<T> g, const T* __res
   const T direct = dir ? T(0) : cb[a] + (pbar ? Cs * (T)pbar[a] : T(0));
   cb[a] = direct - acc;
   if (pbar) pbar[a] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// reverse of the two-way coupled diffusion step.  Forward, per particle a,
+// with F from u (F^-1 = Fi, J = det F), a = c / J the saturation:
+//   s = sum_b V_b (a_b - a_a) grad0 W,  gr = B0 s,  gc = Fi^T gr,
+//   qc = -D w gc (w = a or 1),  Q = J Fi qc,  y = B0 Q,
+//   c' = c - dt sum_b V_b (y_a + y_b) . grad0 W   (Dirichlet: c' = c_bc J),
+//   p = C (c' / J - c0).
+// Three passes after the recomputation of Fi and a (the forward deformation
+// pass): the pressure and Dirichlet terms per particle; a gather over a and
+// div_bar = -dt c'_bar giving s_bar, Fi_bar and the J_bar, D and own-saturation
+// terms; a gather over s_bar giving the rest of a_bar, then
+// F_bar = -Fi^T Fi_bar Fi^T + J_bar J Fi^T and G_bar = F_bar B0^T, which the
+// displacement-gradient transpose turns into u_bar.
+
+template <typename T, int D>
+__device__ __forceinline__ T adet(const T* A) {
+  if constexpr (D == 2) return A[0] * A[3] - A[1] * A[2];
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// pass 1 (per particle): p_bar -> C gradient, c'_bar, J_bar; Dirichlet rows;
+// div_bar = -dt c'_bar; the direct part of c_bar; p_bar is consumed
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_acd_pre(int64_t n, const T* __restrict__ Fi,
+                                                 const T* __restrict__ cnew, T* __restrict__ cb,
+                                                 double* __restrict__ pbar,
+                                                 const uint8_t* __restrict__ flags, T dt, T c_bc,
+                                                 T Cs, T c0, T* __restrict__ divb,
+                                                 T* __restrict__ Jb, double* __restrict__ gpart) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double gC = 0.0;
+  if (a < n) {
+    T Fa[D * D];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Fa[i] = Fi[i * n + a];
+    const T J = T(1) / adet<T, D>(Fa);
+    const T cp = cnew[a];
+    const double pb = pbar ? pbar[a] : 0.0;
+    gC = pb * ((double)cp / (double)J - (double)c0);
+    const T cbp = cb[a] + Cs * (T)pb / J;
+    T Jbar = -(Cs * (T)pb) * cp / (J * J);
+    T dv = T(0), direct = T(0);
+    if (flags && (flags[a] & SPH_FLAG_CDIR)) {
+      Jbar += c_bc * cbp;
+    } else {
+      dv = -dt * cbp;
+      direct = cbp;
+    }
+    divb[a] = dv;
+    Jb[a] = Jbar;
+    cb[a] = direct;
+    if (pbar) pbar[a] = 0.0;
+  }
+  double v[1] = {gC};
+  const int slot[1] = {SPH_GRAD_C};
+  block_grad_add<1>(v, slot, gpart);
+}
+
+// pass 2 (tiled gather over the saturation and div_bar)
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_acd_a(
+    TileGeo<T> g, const T* __restrict__ sat, const T* __restrict__ divb, const T* __restrict__ Fi,
+    T* __restrict__ Jb, T* __restrict__ sbar, T* __restrict__ Fib, T* __restrict__ cb,
+    const T* __restrict__ cold, T Dc, int nonlinear, double* __restrict__ gpart) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;  // the whole block
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* sf = sx + window;  // (saturation, div_bar, -, -)
+  const int64_t n = g.n;
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
+  const WinMap wm = win_map(td);
+  for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
+    const int64_t gi = wm(l);
+    vec4<T> xv, fv;
+    xv.x = (T)(g.X[gi] - xo[0]);
+    xv.y = (T)(g.X[n + gi] - xo[1]);
+    xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+    xv.w = g.V[gi];
+    fv.x = sat[gi];
+    fv.y = divb[gi];
+    fv.z = T(0);
+    fv.w = T(0);
+    sx[l] = xv;
+    sf[l] = fv;
+  }
+  __syncthreads();
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
+  const bool active = (uint32_t)t < td.count;
+  uint32_t la;
+  const int64_t a = tile_own(td, active ? (uint32_t)t : 0u, la);
+  const vec4<T> xa = sx[la], fa = sf[la];
+  T sv[3] = {T(0), T(0), T(0)}, m[3] = {T(0), T(0), T(0)}, e[3] = {T(0), T(0), T(0)};
+  if (active)
+    ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+      const vec4<T> xb = sx[l], fb = sf[l];
+      T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+      T r2 = d[0] * d[0] + d[1] * d[1];
+      if (D == 3) r2 += d[2] * d[2];
+      const T w0 = dw_over_r(r2, g.inv_h, g.c5);
+      const T wb = w0 * xb.w;
+      const T ws = wb * (fb.x - fa.x), we = w0 * fb.y;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        sv[k] += ws * d[k];
+        m[k] += wb * d[k];
+        e[k] += we * d[k];
+      }
+    });
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    sv[k] = lane_sum<LPP>(sv[k]);
+    m[k] = lane_sum<LPP>(m[k]);
+    e[k] = lane_sum<LPP>(e[k]);
+  }
+  double gD = 0.0;
+  if (active && h == 0) {
+    T B[D][D], Fa[D * D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) B[i][k] = g.B0[(i * D + k) * n + a];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Fa[i] = Fi[i * n + a];
+    const T J = T(1) / adet<T, D>(Fa);
+    // y_bar = div_bar_a sum_b V_b grad W - V_a sum_b div_bar_b grad W
+    T yb[D], gr[D], gc[D], qc[D], Qb[D], qcb[D], gcb[D], grb[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) yb[k] = fa.y * m[k] - xa.w * e[k];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T x = T(0), y = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        x += B[i][k] * sv[k];   // gr = B0 s
+        y += B[k][i] * yb[k];   // Q_bar = B0^T y_bar
+      }
+      gr[i] = x;
+      Qb[i] = y;
+    }
+#pragma unroll
+    for (int mm = 0; mm < D; ++mm) {
+      T x = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) x += Fa[k * D + mm] * gr[k];  // Fi^T gr
+      gc[mm] = x;
+    }
+    const T wa = nonlinear ? fa.x : T(1);
+#pragma unroll
+    for (int mm = 0; mm < D; ++mm) qc[mm] = -Dc * wa * gc[mm];
+    // Q = J Fi qc
+    T Jbar = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T x = T(0);
+#pragma unroll
+      for (int mm = 0; mm < D; ++mm) x += Fa[mm * D + k] * Qb[mm];
+      qcb[k] = J * x;  // J Fi^T Q_bar
+    }
+#pragma unroll
+    for (int mm = 0; mm < D; ++mm) {
+      T x = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) x += Fa[mm * D + k] * qc[k];
+      Jbar += Qb[mm] * x;  // Q_bar . (Fi qc)
+    }
+    // qc = -D w gc
+    T gq = T(0);
+#pragma unroll
+    for (int mm = 0; mm < D; ++mm) {
+      gcb[mm] = -Dc * wa * qcb[mm];
+      gq += gc[mm] * qcb[mm];
+    }
+    gD = -(double)wa * (double)gq;
+    const T a_own = nonlinear ? -Dc * gq : T(0);  // w_bar, w = a
+    // gc = Fi^T gr
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T x = T(0);
+#pragma unroll
+      for (int mm = 0; mm < D; ++mm) x += Fa[k * D + mm] * gcb[mm];
+      grb[k] = x;  // Fi gc_bar
+    }
+    // Fi_bar = J Q_bar (x) qc + gr (x) gc_bar
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) Fib[(i * D + k) * n + a] = J * Qb[i] * qc[k] + gr[i] * gcb[k];
+    // s_bar = B0^T gr_bar
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T x = T(0);
+#pragma unroll
+      for (int i = 0; i < D; ++i) x += B[i][k] * grb[i];
+      sbar[k * n + a] = x;
+    }
+    // a = c / J: the own saturation term of the nonlinear flux
+    const T ca = cold[a];
+    cb[a] += a_own / J;
+    Jb[a] += Jbar - a_own * ca / (J * J);
+  }
+  double v[1] = {gD};
+  const int slot[1] = {SPH_GRAD_D};
+  block_grad_add<1>(v, slot, gpart);
+}
+
+// pass 3 (tiled gather over s_bar): a_bar_a = -sum_b (V_a s_bar_b + V_b s_bar_a) . grad0 W;
+// c_bar += a_bar / J, J_bar -= a_bar c / J^2; F_bar and G_bar = F_bar B0^T (into Fib)
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_acd_b(TileGeo<T> g, const T* __restrict__ sbar,
+                                                     const T* __restrict__ Fi, T* __restrict__ Fib,
+                                                     const T* __restrict__ Jb, T* __restrict__ cb,
+                                                     const T* __restrict__ cold) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  vec4<T>* ss = sx + window;
+  const int64_t n = g.n;
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
+  const WinMap wm = win_map(td);
+  for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
+    const int64_t gi = wm(l);
+    vec4<T> xv, sv;
+    xv.x = (T)(g.X[gi] - xo[0]);
+    xv.y = (T)(g.X[n + gi] - xo[1]);
+    xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+    xv.w = g.V[gi];
+    sv.x = sbar[gi];
+    sv.y = sbar[n + gi];
+    sv.z = D == 3 ? sbar[2 * n + gi] : T(0);
+    sv.w = T(0);
+    sx[l] = xv;
+    ss[l] = sv;
+  }
+  __syncthreads();
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
+  if ((uint32_t)t >= td.count) return;
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
+  const vec4<T> xa = sx[la], sa = ss[la];
+  T t1 = T(0), m[3] = {T(0), T(0), T(0)};
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    const vec4<T> xb = sx[l], sb = ss[l];
+    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w0 = dw_over_r(r2, g.inv_h, g.c5);
+    T sd = sb.x * d[0] + sb.y * d[1];
+    if (D == 3) sd += sb.z * d[2];
+    t1 += w0 * sd;
+    const T wb = w0 * xb.w;
+#pragma unroll
+    for (int k = 0; k < D; ++k) m[k] += wb * d[k];
+  });
+  T tot = xa.w * t1 + sa.x * m[0] + sa.y * m[1];
+  if (D == 3) tot += sa.z * m[2];
+  tot = lane_sum<LPP>(tot);
+  if (h != 0) return;
+  const T abar = -tot;
+  T Fa[D * D], M[D * D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) {
+    Fa[i] = Fi[i * n + a];
+    M[i] = Fib[i * n + a];
+  }
+  const T J = T(1) / adet<T, D>(Fa);
+  const T ca = cold[a];
+  cb[a] += abar / J;
+  const T Jbar = Jb[a] - abar * ca / (J * J);
+  // F_bar = -Fi^T Fi_bar Fi^T + J_bar J Fi^T
+  T P[D * D], Fb[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T x = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) x += M[i * D + l] * Fa[k * D + l];  // Fi_bar Fi^T
+      P[i * D + k] = x;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T x = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) x += Fa[l * D + i] * P[l * D + k];  // Fi^T (...)
+      Fb[i * D + k] = -x + Jbar * J * Fa[k * D + i];
+    }
+  // G_bar = F_bar B0^T
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T x = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) x += Fb[i * D + l] * g.B0[(k * D + l) * n + a];
+      Fib[(i * D + k) * n + a] = x;
+    }
 }
 
 // fixed-order reduction of the gradient partials into grad (+=); clears them
@@ -1032,6 +1347,73 @@ static int adj_diffusion_t(const sph_nbr* nb, const sph_material* m, const sph_s
                                      (T)m->C_swell);
   SPH_LAUNCH_CHECK();
   return SPH_OK;
+}
+
+template <typename T, int D>
+static int adj_diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                                   const double* u_before, const void* c_before,
+                                   const sph_adjoint* adj, double Dc, double dt, double c_bc,
+                                   int nonlinear, double drift_dt, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  const int64_t n = nb->n;
+  TileGeo<T> g = tile_geo<T>(nb, prec);
+  if (g.n_tiles == 0) return SPH_OK;
+  const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
+  const unsigned gr0 = nblk(n, 256);
+  if ((int64_t)grid > nb->gpart_slots || (int64_t)gr0 > nb->gpart_slots) {
+    set_error("gradient partial slots too few");
+    return SPH_E_CAPACITY;
+  }
+  constexpr int L = 2;
+  const size_t wm = (size_t)nb->tiling[prec].window_max;
+  const size_t lds2 = wm * 2 * sizeof(vec4<T>);
+  const size_t lds_g = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
+  int rc;
+  if ((rc = lds_attr(k_acd_a<T, D, L>, lds2)) || (rc = lds_attr(k_acd_b<T, D, L>, lds2)) ||
+      (rc = lds_attr(k_adj_gather<T, D, L>, lds_g)))
+    return rc;
+  // scratch: the state arrays the reverse pass re-runs over anyway
+  T* Fi = (T*)st->PB;              // F^-1 of the step's u
+  T* sat = (T*)st->p;              // c / J
+  T* sbar = (T*)st->q;             // [D][n]
+  T* divb = (T*)st->v;             // first component of v
+  T* Jb = (T*)st->v + n;           // second component of v
+  T* Fib = (T*)adj->work;          // Fi_bar, then G_bar
+  if ((rc = diffusion_F(nb, prec, u_before, c_before, Fi, sat, s))) return rc;
+  k_acd_pre<T, D><<<gr0, 256, 0, s>>>(n, Fi, (const T*)st->c, (T*)adj->c, adj->p, st->flags, (T)dt,
+                                      (T)c_bc, (T)m->C_swell, (T)m->c0, divb, Jb, nb->gpart);
+  SPH_LAUNCH_CHECK();
+  k_acd_a<T, D, L><<<grid, (unsigned)(g.tmax * L), lds2, s>>>(g, sat, divb, Fi, Jb, sbar, Fib,
+                                                               (T*)adj->c, (const T*)c_before,
+                                                               (T)Dc, nonlinear, nb->gpart);
+  SPH_LAUNCH_CHECK();
+  k_acd_b<T, D, L><<<grid, (unsigned)(g.tmax * L), lds2, s>>>(g, sbar, Fi, Fib, Jb, (T*)adj->c,
+                                                               (const T*)c_before);
+  SPH_LAUNCH_CHECK();
+  k_adj_gather<T, D, L><<<grid, (unsigned)(g.tmax * L), lds_g, s>>>(g, Fib, adj->u, (T*)adj->v,
+                                                                     st->flags, drift_dt,
+                                                                     bat_view(nb), 1);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+int adj_diffusion_coupled(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                          const double* u_before, const void* c_before, const sph_adjoint* adj,
+                          double Dc, double dt, double c_bc, int nonlinear, double drift_dt,
+                          hipStream_t s) {
+  if (!st->c || !st->q || !st->p || !st->PB || !st->v || !c_before || !u_before || !adj->c ||
+      !adj->work) {
+    set_error("the coupled diffusion reverse needs c, q, p, PB, v, the step's u and c and the "
+              "adjoint c and work arrays");
+    return SPH_E_ARG;
+  }
+  if (st->prec == SPH_F64)
+    return nb->dim == 2
+               ? adj_diffusion_coupled_t<double, 2>(nb, m, st, u_before, c_before, adj, Dc, dt, c_bc, nonlinear, drift_dt, s)
+               : adj_diffusion_coupled_t<double, 3>(nb, m, st, u_before, c_before, adj, Dc, dt, c_bc, nonlinear, drift_dt, s);
+  return nb->dim == 2
+             ? adj_diffusion_coupled_t<float, 2>(nb, m, st, u_before, c_before, adj, Dc, dt, c_bc, nonlinear, drift_dt, s)
+             : adj_diffusion_coupled_t<float, 3>(nb, m, st, u_before, c_before, adj, Dc, dt, c_bc, nonlinear, drift_dt, s);
 }
 
 int adj_diffusion(const sph_nbr* nb, const sph_material* m, const sph_state* st,

@@ -295,6 +295,15 @@ int adj_damping(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                 const sph_adjoint* adj, double eta, double dt, hipStream_t s);
 int adj_drift(const sph_nbr* nb, const sph_state* st, const sph_adjoint* adj, double dt,
               hipStream_t s);
+int diffusion_F(const sph_nbr* nb, int prec, const double* u, const void* c, void* Fi, void* sat,
+                hipStream_t s);
+// drift_dt: the step of the inner step before the slow step when that inner
+// step's drift transpose has already been taken (0 otherwise); the u_bar
+// this reverse adds then also reaches that drift's velocity
+int adj_diffusion_coupled(const sph_nbr* nb, const sph_material* m, const sph_state* st,
+                          const double* u_before, const void* c_before, const sph_adjoint* adj,
+                          double D, double dt, double c_bc, int nonlinear, double drift_dt,
+                          hipStream_t s);
 int adj_diffusion(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                   const void* c_before, const sph_adjoint* adj, double Dc, double dt,
                   hipStream_t s);

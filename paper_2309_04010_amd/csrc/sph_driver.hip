@@ -481,7 +481,9 @@ int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* 
       }
       if ((rc = tape_copy(nb, m, st, tape, l, false, s))) return rc;
       rc = cfg->slow_kind == SPH_SLOW_LOAD ? load_step(nb, st, dt_slow, s)
-                                           : diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
+           : cfg->slow_kind == SPH_SLOW_DIFFUSION_COUPLED
+               ? diffusion_step_coupled(nb, m, st, cfg->D, dt_slow, cfg->c_bc, cfg->diff_nonlinear, s)
+               : diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
       if (rc) return rc;
       if (kl > 0) {
         if ((rc = reset_ctrl(nb, kl, -1.0, s))) return rc;
@@ -514,6 +516,19 @@ int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* 
     if (cfg->slow_kind == SPH_SLOW_DIFFUSION) {
       const void* c_before = (const char*)tape->ck_c + (size_t)l * n * T;
       if ((rc = adj_diffusion(nb, m, st, c_before, adj, cfg->D, dt_slow, s))) return rc;
+    } else if (cfg->slow_kind == SPH_SLOW_DIFFUSION_COUPLED) {
+      // the step's u is the checkpoint before it (the step leaves u as it is).
+      // That u is also the one the previous inner step's drift produced; the
+      // drift's transpose was folded into the next reversed gather already
+      // (or, if no inner step has been reversed yet, is still to come in
+      // adj_drift), so the u_bar added here reaches its velocity only in the
+      // first case.
+      const void* c_before = (const char*)tape->ck_c + (size_t)l * n * T;
+      const double* u_before = tape->ck_u + (size_t)l * d * n;
+      const double drift = (!first && before[l] > 0) ? dt : 0.0;
+      if ((rc = adj_diffusion_coupled(nb, m, st, u_before, c_before, adj, cfg->D, dt_slow, cfg->c_bc,
+                                      cfg->diff_nonlinear, drift, s)))
+        return rc;
     }
   }
   if (cfg->batch)
@@ -533,8 +548,8 @@ int check_backward_args(const sph_nbr* nb, const sph_material* m, const sph_stat
     set_error("material, cfg, tape or adjoint is NULL");
     return SPH_E_ARG;
   }
-  if (cfg->slow_kind == SPH_SLOW_DIFFUSION_COUPLED) {
-    set_error("the reverse pass covers the loading and linear diffusion slow steps only");
+  if (cfg->slow_kind == SPH_SLOW_DIFFUSION_COUPLED && cfg->batch) {
+    set_error("the reverse of the two-way coupled slow step takes one specimen");
     return SPH_E_UNSUPPORTED;
   }
   if (m->rho_l0 != 0.0) {
@@ -543,7 +558,7 @@ int check_backward_args(const sph_nbr* nb, const sph_material* m, const sph_stat
   }
   if (adj->prec != st->prec || !adj->u || !adj->v || !adj->work || !adj->grad ||
       (m->model == SPH_MODEL_J2 && !adj->plastic) ||
-      (cfg->slow_kind == SPH_SLOW_DIFFUSION && !adj->c)) {
+      (cfg->slow_kind != SPH_SLOW_LOAD && !adj->c)) {
     set_error("adjoint arrays missing or of the wrong precision");
     return SPH_E_ARG;
   }

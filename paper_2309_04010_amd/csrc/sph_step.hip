@@ -1333,6 +1333,29 @@ static int diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, const s
   return SPH_OK;
 }
 
+// the deformation pass alone (F^-1 and the saturation c / J of a given u and
+// c), for the reverse of the coupled step
+template <typename T, int D>
+static int diffusion_F_t(const sph_nbr* nb, const double* u, const void* c, void* Fi, void* sat,
+                         hipStream_t s) {
+  const DiffLaunch<T> L = diff_launch<T>(nb);
+  if (L.g.n_tiles == 0) return SPH_OK;
+  int rc;
+  if ((rc = lds_attr(k_diff_F<T, D, kDiffLpp>, L.lds2))) return rc;
+  k_diff_F<T, D, kDiffLpp><<<L.grid, L.block, L.lds2, s>>>(L.g, u, (const T*)c, (T*)Fi, (T*)sat);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+int diffusion_F(const sph_nbr* nb, int prec, const double* u, const void* c, void* Fi, void* sat,
+                hipStream_t s) {
+  if (prec == SPH_F64)
+    return nb->dim == 2 ? diffusion_F_t<double, 2>(nb, u, c, Fi, sat, s)
+                        : diffusion_F_t<double, 3>(nb, u, c, Fi, sat, s);
+  return nb->dim == 2 ? diffusion_F_t<float, 2>(nb, u, c, Fi, sat, s)
+                      : diffusion_F_t<float, 3>(nb, u, c, Fi, sat, s);
+}
+
 int diffusion_step_coupled(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                            double Dc, double dt, double c_bc, int nonlinear, hipStream_t s) {
   if (!st->c || !st->q || !st->p || !st->PB) {

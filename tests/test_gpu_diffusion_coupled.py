@@ -6,7 +6,10 @@
   pressure p;
 * undeformed with the linear flux it is the linear step (1e-14);
 * a multi-time-step run with coupled slow steps equals the oracle's run;
-* the reverse pass refuses the coupled slow kind.
+* the reverse pass through coupled slow steps gives the complex-step
+  oracle's gradients (2D and 3D, linear and nonlinear flux, FP64 and FP32),
+  also with slow steps that take no inner step; a batched coupled run's
+  reverse is refused.
 """
 import numpy as np
 import pytest
@@ -120,15 +123,104 @@ def test_coupled_multirate_run_matches_oracle(oracle_mod, nonlinear):
     nb.close()
 
 
-def test_reverse_pass_refuses_coupled(oracle_mod):
+def _coupled_case(name, nonlinear):
+    if name == "strip2d":
+        c = cases.strip2d(nx=24, ny=6, n_slow=3, fixed_inner=20, k_max=0)
+    else:
+        c = cases.plate3d(nx=14, ny=14, n_slow=2, fixed_inner=15)
+    c.run["slow_kind"] = cases.DIFFUSION_COUPLED
+    c.run["diff_nonlinear"] = nonlinear
+    return c
+
+
+def _oracle_coupled_objective(oracle_mod, c, run, k_sched, w, param, eps_rel=1e-20):
+    """d<w, u_final>/d(param) of the coupled run by the complex-step oracle."""
+    d, n = c.dim, c.n
+    o = oracle_mod.Oracle(d, c.X, c.V, c.h, complex_step=True)
+    perm = o.perm
+    flags = np.ascontiguousarray(c.flags[perm])
+    m, r = dict(c.material), dict(run)
+    nonlinear = r.pop("diff_nonlinear")
+    base = r["D"] if param == "D" else m[param]
+    e = eps_rel * max(abs(base), 1.0)
+    if param == "D":
+        r["D"] = base + 1j * e
+    else:
+        m[param] = base + 1j * e
+    cfg = o.cfg(**{k: v for k, v in r.items() if k != "D"}, D=r["D"], nonlinear=nonlinear)
+    u, v = o.arr(d, n), o.arr(d, n)
+    cc = np.ascontiguousarray(c.c_init[perm], dtype=complex)
+    q, p = o.arr(d, n), o.arr(n)
+    rc, k, _, _ = o.advance(o.material(**m), cfg, u, v, c=cc, q=q, p=p, flags=flags, k_sched=k_sched)
+    assert rc in (0, 1) and np.array_equal(k, k_sched)
+    return (w * u).sum().imag / e
+
+
+@pytest.mark.parametrize("prec", [B.SPH_F64, B.SPH_F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("nonlinear", [0, 1], ids=["linear", "nonlinear"])
+@pytest.mark.parametrize("name", ["strip2d", "plate3d"])
+def test_coupled_gradient_matches_oracle(oracle_mod, name, nonlinear, prec):
+    """Reverse pass through two-way coupled slow steps: the gradient of
+    <w, u_final> with respect to E, D and C against the complex-step oracle
+    (FP64 1e-8, FP32 1e-2); the u-dependence of the coupled step (through F,
+    J and F^-1) carries the gradient from one slow step to the previous."""
     from paper_2309_04010_amd import adjoint as A
-    c = cases.strip2d(nx=20, ny=6, n_slow=2, fixed_inner=5, k_max=0)
-    pr = A.MultirateProblem(c, B.SPH_F64)
-    th = pr.theta0()
-    pr.run["slow_kind"] = cases.DIFFUSION_COUPLED
-    pr.forward(th)
-    w = dev(np.ones((2, c.n)))
-    with pytest.raises(B.SphError) as e:
-        pr.backward(w)
-    assert e.value.code == B.SPH_E_UNSUPPORTED
+    print(f"[coupled] gradient {name} nonlinear={nonlinear} prec={prec}", flush=True)
+    c = _coupled_case(name, nonlinear)
+    pr = A.MultirateProblem(c, prec, k_hist=c.run["fixed_inner"])
+    pr.forward(pr.theta0())
+    pr.freeze()
+    w = np.random.default_rng(6).normal(0.0, 1.0, (c.dim, c.n))
+    pr.forward(pr.theta0())
+    assert np.abs(host(pr.st.u)).max() > 0
+    g = host(pr.backward(dev(w)))
+    tol = 1e-8 if prec == B.SPH_F64 else 1e-2
+    for nm in ("E", "D", "C_swell"):
+        want = _oracle_coupled_objective(oracle_mod, c, pr.run, pr.k_sched, w, nm)
+        gi = B.GRAD_NAMES.index(nm)
+        print(f"  d/d{nm}: gpu {g[gi]:.10e} oracle {want:.10e}", flush=True)
+        assert abs(g[gi] - want) <= tol * abs(want), (nm, g[gi], want)
     pr.close()
+
+
+@pytest.mark.parametrize("k_sched", [(20, 0, 20), (20, 20, 0), (0, 20, 20)], ids=["mid", "last", "first"])
+def test_coupled_gradient_with_empty_slow_steps(oracle_mod, k_sched):
+    """A slow step with no inner steps: the u_bar of a coupled step reaches
+    the drift of the inner step before it either through the increment the
+    reverse adds at once (some inner step already reversed) or through the
+    last inner step's drift reverse still to come (none reversed yet)."""
+    from paper_2309_04010_amd import adjoint as A
+    print(f"[coupled] gradient with inner counts {k_sched}", flush=True)
+    c = _coupled_case("strip2d", 1)
+    pr = A.MultirateProblem(c, B.SPH_F64, k_hist=c.run["fixed_inner"])
+    pr.k_sched = np.array(k_sched, dtype=np.int64)
+    pr.forward(pr.theta0())
+    assert np.array_equal(pr.last["k"], pr.k_sched)
+    w = np.random.default_rng(7).normal(0.0, 1.0, (c.dim, c.n))
+    g = host(pr.backward(dev(w)))
+    for nm in ("E", "D"):
+        want = _oracle_coupled_objective(oracle_mod, c, pr.run, pr.k_sched, w, nm)
+        gi = B.GRAD_NAMES.index(nm)
+        print(f"  d/d{nm}: gpu {g[gi]:.10e} oracle {want:.10e}", flush=True)
+        assert abs(g[gi] - want) <= 1e-8 * abs(want), (nm, g[gi], want)
+    pr.close()
+
+
+def test_batched_coupled_reverse_is_refused(oracle_mod):
+    bt = cases.batch([cases.strip2d(nx=n, ny=6, n_slow=1, fixed_inner=5, k_max=0) for n in (10, 14)])
+    nb = B.sph_build_neighbors_batched(dev(bt.X), dev(bt.V), bt.h, dev(bt.spec))
+    st = B.new_state(nb, B.SPH_F64, with_diffusion=True)
+    perm = nb.host("perm").astype(np.int64)
+    st.flags = dev(bt.flags[perm])
+    st.c.copy_(dev(bt.c_init[perm]))
+    import torch
+    grad = torch.zeros((2, B.SPH_NGRAD), dtype=torch.float64, device="cuda")
+    batch = B.SphBatch(bt.E, bt.D, bt.dt_s, bt.dt_slow, grad=grad)
+    cfg = B.multirate_cfg(**dict(bt.run, slow_kind=cases.DIFFUSION_COUPLED), batch=batch)
+    tape = B.SphTape(nb, B.SPH_F64, 1, 5, with_diffusion=True)
+    adj = B.new_adjoint(nb, B.SPH_F64, with_diffusion=True)
+    B.sph_advance_multirate(nb, B.material(**bt.material), st, cfg, tape=tape)
+    with pytest.raises(B.SphError) as e:
+        B.sph_advance_multirate_backward(nb, B.material(**bt.material), st, cfg, tape, adj)
+    assert e.value.code == B.SPH_E_UNSUPPORTED
+    nb.close()
