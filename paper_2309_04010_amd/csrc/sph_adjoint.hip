@@ -435,7 +435,12 @@ __device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot
 // reverse of the stress stage + momentum sum + kick, one tile per workgroup:
 // gathers the neighbours' u (for H) and a_bar = dt w (free particles) from the
 // LDS window; writes G_bar = H_bar B0^T, updates the J2 state adjoint,
-// accumulates p_bar and the parameter partials
+// accumulates p_bar and the parameter partials.  Both sums share the pair's
+// e = grad W and take the own particle's term out of the pair loop:
+//   sum_b V_b (u_b - u_a) (x) e       = sum_b (V_b u_b) (x) e - u_a (x) m,
+//   sum_b (V_b a_a - V_a a_b) (x) e   = a_a (x) m - V_a sum_b a_b (x) e,
+// with m = sum_b V_b e and u relative to the tile's first particle (the window
+// stages V_b u_b)
 template <typename T, int D, int LPP, int MODEL>
 __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
@@ -468,13 +473,13 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     xv.w = g.V[gi];
     const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
     const T kf = fixed ? T(0) : (bt.spec ? bt.get<T>(BT_DT, bt.spec[gi]) : dt);
-    uv.x = (T)(u[gi] - uo[0]);
-    uv.y = (T)(u[n + gi] - uo[1]);
+    uv.x = xv.w * (T)(u[gi] - uo[0]);
+    uv.y = xv.w * (T)(u[n + gi] - uo[1]);
     if (D == 2) {
       uv.z = kf * w[gi];
       uv.w = kf * w[n + gi];
     } else {
-      uv.z = (T)(u[2 * n + gi] - uo[2]);
+      uv.z = xv.w * (T)(u[2 * n + gi] - uo[2]);
       uv.w = T(0);
       av.x = kf * w[gi];
       av.y = kf * w[n + gi];
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     aa.z = T(0);
   }
   const T Va = xa.w;
-  T Gs[D][D], Qs[D][D];
+  T Gs[D][D], Qs[D][D], ms[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -507,36 +512,38 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   if (active)
     ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
       const vec4<T> xb = sx[l], ub = su[l];
-      T ab[3];
+      T ab[3], Ub[3] = {ub.x, ub.y, T(0)};
       if (D == 3) {
         const vec4<T> av = sa[l];
         ab[0] = av.x;
         ab[1] = av.y;
         ab[2] = av.z;
+        Ub[2] = ub.z;
       } else {
         ab[0] = ub.z;
         ab[1] = ub.w;
         ab[2] = T(0);
       }
       const T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
-      T du[3] = {ub.x - ua.x, ub.y - ua.y, T(0)};
-      if (D == 3) du[2] = ub.z - ua.z;
       T r2 = d[0] * d[0] + d[1] * d[1];
       if (D == 3) r2 += d[2] * d[2];
       const T w0 = dw_over_r(r2, g.inv_h, g.c5);
-      const T wb = w0 * xb.w, wa = w0 * Va;
-      const T aav[3] = {aa.x, aa.y, aa.z};
+      T e[3];
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        const T gu = wb * du[i];
-        const T qa = wb * aav[i] - wa * ab[i];
+      for (int k = 0; k < D; ++k) {
+        e[k] = w0 * d[k];
+        ms[k] += xb.w * e[k];
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          Gs[i][k] += gu * d[k];
-          Qs[i][k] += qa * d[k];
+          Gs[i][k] += Ub[i] * e[k];
+          Qs[i][k] += ab[i] * e[k];
         }
-      }
     });
+#pragma unroll
+  for (int k = 0; k < D; ++k) ms[k] = lane_sum<LPP>(ms[k]);
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -547,6 +554,17 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   double thd[kNTheta] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (active && h == 0) {
     const int64_t a = a_own;
+    // the own particle's terms
+    const T aav[3] = {aa.x, aa.y, aa.z};
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const T ui = (T)(u[i * n + a] - uo[i]);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        Gs[i][k] -= ui * ms[k];
+        Qs[i][k] = aav[i] * ms[k] - Va * Qs[i][k];
+      }
+    }
     T B[D][D];
 #pragma unroll
     for (int i = 0; i < D; ++i)
