@@ -626,23 +626,25 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
 }
 
 // reverse of the displacement-gradient sum:
-//   u_bar_a -= sum_b (V_a G_bar_b + V_b G_bar_a) grad_a W_ab,
-// then (drift_dt != 0) the drift transpose of the previous inner step for
-// free particles: w_a += drift_dt u_bar_a, or, with drift_incr, only this
-// gather's increment, w_a -= drift_dt sum_b (...) (for a term added after
-// that drift's transpose has already taken the rest of u_bar)
+//   u_bar_a -= sum_b (V_a G_bar_b + V_b G_bar_a) grad_a W_ab
+//            = V_a sum_b G_bar_b grad_a W_ab + G_bar_a g_a,
+// g_a = sum_b V_b grad_a W_ab from the build (the window holds the relative
+// position and G_bar_b, twelve values in 3D); then (drift_dt != 0) the drift
+// transpose of the previous inner step for free particles: w_a += drift_dt
+// u_bar_a, or, with drift_incr, only this gather's increment,
+// w_a -= drift_dt (...) (for a term added after that drift's transpose has
+// already taken the rest of u_bar)
 template <typename T, int D, int LPP>
 __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
     TileGeo<T> g, const T* __restrict__ Gb, double* __restrict__ ub, T* __restrict__ w,
     const uint8_t* __restrict__ flags, double drift_dt, Bat bt, int drift_incr = 0) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
-  constexpr int NP = (D * D + 3) / 4;
+  constexpr int NQ = xtq<D>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileDesc& td = g.tiles[tile];
   const uint32_t window = td.window;
-  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
-  vec4<T>* sp = sx + window;  // [window][NP]
+  vec4<T>* sp = reinterpret_cast<vec4<T>*>(smem_raw);  // [window][NQ]
   const int64_t n = g.n;
   const int64_t p0 = td.p0;
   double xo[3] = {0, 0, 0};
@@ -651,55 +653,30 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
   const WinMap wm = win_map(td);
   for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
     const int64_t gi = wm(l);
-    vec4<T> xv;
-    xv.x = (T)(g.X[gi] - xo[0]);
-    xv.y = (T)(g.X[n + gi] - xo[1]);
-    xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
-    xv.w = g.V[gi];
-    sx[l] = xv;
+    T xv[D], gv[D * D];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      vec4<T> pv;
-      pv.x = 4 * q < D * D ? Gb[(4 * q) * n + gi] : T(0);
-      pv.y = 4 * q + 1 < D * D ? Gb[(4 * q + 1) * n + gi] : T(0);
-      pv.z = 4 * q + 2 < D * D ? Gb[(4 * q + 2) * n + gi] : T(0);
-      pv.w = 4 * q + 3 < D * D ? Gb[(4 * q + 3) * n + gi] : T(0);
-      sp[l * NP + q] = pv;
-    }
+    for (int k = 0; k < D; ++k) xv[k] = (T)(g.X[k * n + gi] - xo[k]);
+#pragma unroll
+    for (int c = 0; c < D * D; ++c) gv[c] = Gb[c * n + gi];
+    xt_store<T, D>(sp + l * NQ, xv, gv);
   }
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
   uint32_t la;
   const int64_t a = tile_own(td, (uint32_t)t, la);
-  const vec4<T> xa = sx[la];
-  T Ga[NP * 4];
-#pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    const vec4<T> pv = sp[la * NP + q];
-    Ga[4 * q] = pv.x;
-    Ga[4 * q + 1] = pv.y;
-    Ga[4 * q + 2] = pv.z;
-    Ga[4 * q + 3] = pv.w;
-  }
-  const T Va = xa.w;
-  T f[3] = {T(0), T(0), T(0)}, m[3] = {T(0), T(0), T(0)};
+  T xa[D], Ga[D * D];
+  xt_load<T, D>(sp + la * NQ, xa, Ga);
+  T f[3] = {T(0), T(0), T(0)};
   ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
-    const vec4<T> xb = sx[l];
-    T Gbb[NP * 4];
+    T xb[D], Gbb[D * D];
+    xt_load<T, D>(sp + l * NQ, xb, Gbb);
+    T d[3] = {T(0), T(0), T(0)};
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const vec4<T> pv = sp[l * NP + q];
-      Gbb[4 * q] = pv.x;
-      Gbb[4 * q + 1] = pv.y;
-      Gbb[4 * q + 2] = pv.z;
-      Gbb[4 * q + 3] = pv.w;
-    }
-    const T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    for (int k = 0; k < D; ++k) d[k] = xa[k] - xb[k];
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
     const T w0 = dw_over_r(r2, g.inv_h, g.c5);
-    const T wb = w0 * xb.w;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       T s = T(0);
@@ -707,18 +684,23 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
       for (int k = 0; k < D; ++k) s += Gbb[i * D + k] * d[k];
       f[i] += w0 * s;
     }
-#pragma unroll
-    for (int k = 0; k < D; ++k) m[k] += wb * d[k];
   });
-  // V_a sum_b G_bar_b grad W + G_bar_a sum_b V_b grad W, the second once per lane
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    T x = Va * f[i];
-#pragma unroll
-    for (int k = 0; k < D; ++k) x += Ga[i * D + k] * m[k];
-    f[i] = lane_sum<LPP>(x);
-  }
+  for (int i = 0; i < D; ++i) f[i] = lane_sum<LPP>(f[i]);
   if (h != 0) return;
+  {
+    const T Va = g.V[a];
+    T ga[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ga[k] = g.gsum[k * n + a];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T x = Va * f[i];
+#pragma unroll
+      for (int k = 0; k < D; ++k) x += Ga[i * D + k] * ga[k];
+      f[i] = x;
+    }
+  }
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
   const double ddt = (drift_dt != 0.0 && bt.spec) ? bt.get<double>(BT_DT, bt.spec[a]) : drift_dt;
 #pragma unroll
@@ -1237,7 +1219,7 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
   }
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds_s = wm * (D == 3 ? 3 : 2) * sizeof(vec4<T>);
-  const size_t lds_g = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
+  const size_t lds_g = wm * xtq<D>() * sizeof(vec4<T>);
   int rc = SPH_OK;
   if constexpr (LS > 0) {
     if ((rc = lds_attr(k_adj_stress<T, D, LS, MODEL>, lds_s))) return rc;
@@ -1385,7 +1367,7 @@ static int adj_diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, con
   constexpr int L = 2;
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds2 = wm * 2 * sizeof(vec4<T>);
-  const size_t lds_g = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
+  const size_t lds_g = wm * xtq<D>() * sizeof(vec4<T>);
   int rc;
   if ((rc = lds_attr(k_acd_a<T, D, L>, lds2)) || (rc = lds_attr(k_acd_b<T, D, L>, lds2)) ||
       (rc = lds_attr(k_adj_gather<T, D, L>, lds_g)))

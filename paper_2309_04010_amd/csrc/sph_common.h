@@ -168,6 +168,8 @@ struct sph_nbr {
   double* B0 = nullptr;
   float* Vf = nullptr;
   float* B0f = nullptr;
+  double* gsum = nullptr;  // [dim][n] sum_b V_b grad_a W_ab (fixed reference configuration)
+  float* gsumf = nullptr;
   uint32_t* sa = nullptr;
   uint32_t* sb = nullptr;
   uint32_t* slev = nullptr;
@@ -247,12 +249,14 @@ __device__ __forceinline__ T dw_over_r(T r2, T inv_h, T c5) {
 }
 
 // ---- tiling parameters per precision -----------------------------------------
-// LDS bytes per staged window particle of the widest tiled kernel (momentum:
-// position + volume as one 4-vector, P B0 padded to whole 4-vectors).
+// LDS bytes per staged window particle of the widest tiled kernels: the
+// momentum sum and its transpose (relative position and a dim x dim tensor
+// packed into whole 4-vectors) and the reverse stress stage (position and
+// volume, u, a: three 4-vectors in 3D, two in 2D).
 inline int tile_tmax(int prec) { return prec == SPH_F64 ? 64 : 128; }
 inline int64_t tile_lds_bytes_per_particle(int prec, int dim) {
   const int t = prec == SPH_F64 ? 8 : 4;
-  return (int64_t)t * 4 * (1 + (dim * dim + 3) / 4);
+  return (int64_t)t * 4 * ((dim + dim * dim + 3) / 4);
 }
 constexpr int64_t kTileLdsBudget = 80 * 1024;
 inline int64_t tile_wmax(int prec, int dim) {

@@ -18,15 +18,17 @@ struct Geo {
   const uint32_t* idx;
   int64_t n;
   T inv_h, c5;
+  const T* gsum;  // [dim][n] sum_b V_b grad_a W_ab
 };
 
 template <typename T>
 static Geo<T> geo(const sph_nbr* nb) {
   if constexpr (sizeof(T) == 8)
-    return Geo<T>{nb->X, nb->V, nb->B0, nb->nbr_off, nb->nbr_idx, nb->n, nb->inv_h, nb->c5};
+    return Geo<T>{nb->X, nb->V, nb->B0, nb->nbr_off, nb->nbr_idx, nb->n, nb->inv_h, nb->c5,
+                  nb->gsum};
   else
     return Geo<T>{nb->X, nb->Vf, nb->B0f, nb->nbr_off, nb->nbr_idx, nb->n, (float)nb->inv_h,
-                  (float)nb->c5};
+                  (float)nb->c5, nb->gsumf};
 }
 
 // ---------------------------------------------------------------------------
@@ -265,13 +267,50 @@ struct TileGeo {
   const T* B0;
   int64_t n;
   T inv_h, c5;
+  const T* gsum;  // [dim][n] sum_b V_b grad_a W_ab
 };
 
 template <typename T>
 static TileGeo<T> tile_geo(const sph_nbr* nb, int prec) {
   const Tiling& t = nb->tiling[prec];
   Geo<T> g = geo<T>(nb);
-  return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5};
+  return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5, g.gsum};
+}
+
+// Window layout of the gathers whose pair term needs no neighbour volume: the
+// relative position (D values) and a D x D tensor packed into XTQ 4-vectors.
+template <int D>
+constexpr int xtq() { return (D + D * D + 3) / 4; }
+template <typename T, int D>
+__device__ __forceinline__ void xt_store(vec4<T>* dst, const T* x, const T* M) {
+  T v[xtq<D>() * 4];
+#pragma unroll
+  for (int c = 0; c < xtq<D>() * 4; ++c) v[c] = c < D ? x[c] : (c < D + D * D ? M[c - D] : T(0));
+#pragma unroll
+  for (int q = 0; q < xtq<D>(); ++q) {
+    vec4<T> pv;
+    pv.x = v[4 * q];
+    pv.y = v[4 * q + 1];
+    pv.z = v[4 * q + 2];
+    pv.w = v[4 * q + 3];
+    dst[q] = pv;
+  }
+}
+template <typename T, int D>
+__device__ __forceinline__ void xt_load(const vec4<T>* src, T* x, T* M) {
+  T v[xtq<D>() * 4];
+#pragma unroll
+  for (int q = 0; q < xtq<D>(); ++q) {
+    const vec4<T> pv = src[q];
+    v[4 * q] = pv.x;
+    v[4 * q + 1] = pv.y;
+    v[4 * q + 2] = pv.z;
+    v[4 * q + 3] = pv.w;
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) x[c] = v[c];
+#pragma unroll
+  for (int c = 0; c < D * D; ++c) M[c] = v[D + c];
 }
 
 // own particle t of a tile: its sorted index and its window position

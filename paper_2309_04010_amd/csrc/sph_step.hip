@@ -200,7 +200,10 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
 }
 
 // momentum: a = (1/rho0) sum_b V_b (PB_a + PB_b) grad_a W_ab; kick v += dt a.
-// Summed as PB_a (sum_b V_b grad_a W_ab) + sum_b V_b PB_b grad_a W_ab.
+// Summed as PB_a g_a + sum_b (V_b PB_b) grad_a W_ab, with the kernel-gradient
+// sum g_a = sum_b V_b grad_a W_ab of the reference configuration taken from
+// the build: the window holds the relative position and V_b PB_b, twelve
+// values in 3D, and the pair loop needs no neighbour volume.
 template <typename T, int D, int LPP>
 __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
                                                                  const T* __restrict__ PB,
@@ -212,12 +215,11 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
-  constexpr int NP = (D * D + 3) / 4;
+  constexpr int NQ = xtq<D>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileDesc& td = g.tiles[tile];
   const uint32_t window = td.window;
-  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
-  vec4<T>* sp = sx + window;  // [window][NP]
+  vec4<T>* sp = reinterpret_cast<vec4<T>*>(smem_raw);  // [window][NQ]
   const int64_t n = g.n;
   const int64_t p0 = td.p0;
   double xo[3] = {0, 0, 0};
@@ -225,67 +227,40 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
   for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
   const WinMap wm = win_map(td);
   for (uint32_t l0 = threadIdx.x; l0 < window; l0 += 2 * blockDim.x) {
-    vec4<T> xv[2];
-    T pb[2][NP * 4];
+    T xv[2][D], pb[2][D * D];
     uint32_t ls[2] = {l0, l0 + blockDim.x};
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       if (ls[e] < window) {
         const int64_t gi = wm(ls[e]);
-        xv[e].x = (T)(g.X[gi] - xo[0]);
-        xv[e].y = (T)(g.X[n + gi] - xo[1]);
-        xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
-        xv[e].w = g.V[gi];
 #pragma unroll
-        for (int c = 0; c < NP * 4; ++c) pb[e][c] = c < D * D ? PB[c * n + gi] : T(0);
+        for (int k = 0; k < D; ++k) xv[e][k] = (T)(g.X[k * n + gi] - xo[k]);
+        const T Vb = g.V[gi];
+#pragma unroll
+        for (int c = 0; c < D * D; ++c) pb[e][c] = Vb * PB[c * n + gi];
       }
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e)
-      if (ls[e] < window) {
-        sx[ls[e]] = xv[e];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          vec4<T> pv;
-          pv.x = pb[e][4 * q];
-          pv.y = pb[e][4 * q + 1];
-          pv.z = pb[e][4 * q + 2];
-          pv.w = pb[e][4 * q + 3];
-          sp[ls[e] * NP + q] = pv;
-        }
-      }
+      if (ls[e] < window) xt_store<T, D>(sp + ls[e] * NQ, xv[e], pb[e]);
   }
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
   uint32_t la;
   const int64_t a = tile_own(td, (uint32_t)t, la);
-  const vec4<T> xa = sx[la];
-  T Pa[NP * 4];
-#pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    vec4<T> pv = sp[la * NP + q];
-    Pa[4 * q] = pv.x;
-    Pa[4 * q + 1] = pv.y;
-    Pa[4 * q + 2] = pv.z;
-    Pa[4 * q + 3] = pv.w;
-  }
-  T f[3] = {T(0), T(0), T(0)}, m[3] = {T(0), T(0), T(0)};
+  T xa[D], Pdum[D * D];
+  xt_load<T, D>(sp + la * NQ, xa, Pdum);
+  T f[3] = {T(0), T(0), T(0)};
   ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
-    const vec4<T> xb = sx[l];
-    T Pb[NP * 4];
+    T xb[D], Pb[D * D];
+    xt_load<T, D>(sp + l * NQ, xb, Pb);
+    T d[3] = {T(0), T(0), T(0)};
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      vec4<T> pv = sp[l * NP + q];
-      Pb[4 * q] = pv.x;
-      Pb[4 * q + 1] = pv.y;
-      Pb[4 * q + 2] = pv.z;
-      Pb[4 * q + 3] = pv.w;
-    }
-    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    for (int k = 0; k < D; ++k) d[k] = xa[k] - xb[k];
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
+    const T w = dw_over_r(r2, g.inv_h, g.c5);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       T s = T(0);
@@ -293,17 +268,18 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
       for (int k = 0; k < D; ++k) s += Pb[i * D + k] * d[k];
       f[i] += w * s;
     }
-#pragma unroll
-    for (int k = 0; k < D; ++k) m[k] += w * d[k];
   });
-  // the own term PB_a sum_b V_b grad W, once per lane instead of per pair
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) f[i] += Pa[i * D + k] * m[k];
-    f[i] = lane_sum<LPP>(f[i]);
-  }
+  for (int i = 0; i < D; ++i) f[i] = lane_sum<LPP>(f[i]);
   if (h != 0) return;
+  // the own term PB_a g_a
+  T ga[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) ga[k] = g.gsum[k * n + a];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) f[i] += PB[(i * D + k) * n + a] * ga[k];
   const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
   const T dta = bt.spec ? bt.get<T>(BT_DT, bt.spec[a]) : dt;
   // the inertia of the mixture: rho0 + rho_l0 c per reference volume
@@ -1010,7 +986,7 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
   const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds_s = wm * 2 * sizeof(vec4<T>);
-  const size_t lds_m = wm * (1 + (D * D + 3) / 4) * sizeof(vec4<T>);
+  const size_t lds_m = wm * xtq<D>() * sizeof(vec4<T>);
   int rc = SPH_OK;
   if constexpr (LS > 0) {
     if ((rc = lds_attr(k_stress<T, D, LS, MODEL>, lds_s))) return rc;
