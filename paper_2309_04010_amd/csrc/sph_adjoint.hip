@@ -437,10 +437,11 @@ __device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot
 // LDS window; writes G_bar = H_bar B0^T, updates the J2 state adjoint,
 // accumulates p_bar and the parameter partials.  Both sums share the pair's
 // e = grad W and take the own particle's term out of the pair loop:
-//   sum_b V_b (u_b - u_a) (x) e       = sum_b (V_b u_b) (x) e - u_a (x) m,
-//   sum_b (V_b a_a - V_a a_b) (x) e   = a_a (x) m - V_a sum_b a_b (x) e,
-// with m = sum_b V_b e and u relative to the tile's first particle (the window
-// stages V_b u_b)
+//   sum_b V_b (u_b - u_a) (x) e       = sum_b (V_b u_b) (x) e - u_a (x) g_a,
+//   sum_b (V_b a_a - V_a a_b) (x) e   = a_a (x) g_a - V_a sum_b a_b (x) e,
+// with g_a = sum_b V_b e from the build and u relative to the tile's first
+// particle: the window holds the relative position, V_b u_b and a_b (nine
+// values in 3D, two 16-byte and one 4-byte LDS read per pair)
 template <typename T, int D, int LPP, int MODEL>
 __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
@@ -449,12 +450,10 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     double* __restrict__ gpart, Ctrl* ctrl, Bat bt) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
+  using PK = Pk<T, 3 * D>;  // (relative position, V_b u_b, a_b)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileDesc& td = g.tiles[tile];
   const uint32_t window = td.window;
-  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
-  vec4<T>* su = sx + window;  // 2D: (u.x, u.y, a.x, a.y); 3D: (u.x, u.y, u.z, -)
-  vec4<T>* sa = su + window;  // 3D only: (a.x, a.y, a.z, -)
   const int64_t n = g.n;
   const int64_t p0 = td.p0;
   double xo[3] = {0, 0, 0}, uo[3] = {0, 0, 0};
@@ -466,84 +465,51 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   const WinMap wm = win_map(td);
   for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
     const int64_t gi = wm(l);
-    vec4<T> xv, uv, av;
-    xv.x = (T)(g.X[gi] - xo[0]);
-    xv.y = (T)(g.X[n + gi] - xo[1]);
-    xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
-    xv.w = g.V[gi];
+    const T Vb = g.V[gi];
     const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
     const T kf = fixed ? T(0) : (bt.spec ? bt.get<T>(BT_DT, bt.spec[gi]) : dt);
-    uv.x = xv.w * (T)(u[gi] - uo[0]);
-    uv.y = xv.w * (T)(u[n + gi] - uo[1]);
-    if (D == 2) {
-      uv.z = kf * w[gi];
-      uv.w = kf * w[n + gi];
-    } else {
-      uv.z = xv.w * (T)(u[2 * n + gi] - uo[2]);
-      uv.w = T(0);
-      av.x = kf * w[gi];
-      av.y = kf * w[n + gi];
-      av.z = kf * w[2 * n + gi];
-      av.w = T(0);
+    T vv[3 * D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      vv[k] = (T)(g.X[k * n + gi] - xo[k]);
+      vv[D + k] = Vb * (T)(u[k * n + gi] - uo[k]);
+      vv[2 * D + k] = kf * w[k * n + gi];
     }
-    sx[l] = xv;
-    su[l] = uv;
-    if (D == 3) sa[l] = av;
+    PK::store(smem_raw, window, l, vv);
   }
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   const bool active = (uint32_t)t < td.count;
   uint32_t la;
   const int64_t a_own = tile_own(td, active ? (uint32_t)t : 0u, la);
-  const vec4<T> xa = sx[la], ua = su[la];
-  vec4<T> aa;
-  if (D == 3) aa = sa[la];
-  else {
-    aa.x = ua.z;
-    aa.y = ua.w;
-    aa.z = T(0);
-  }
-  const T Va = xa.w;
-  T Gs[D][D], Qs[D][D], ms[3] = {T(0), T(0), T(0)};
+  T va[3 * D];
+  PK::load(smem_raw, window, la, va);
+  T Gs[D][D], Qs[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) Gs[i][k] = Qs[i][k] = T(0);
   if (active)
     ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
-      const vec4<T> xb = sx[l], ub = su[l];
-      T ab[3], Ub[3] = {ub.x, ub.y, T(0)};
-      if (D == 3) {
-        const vec4<T> av = sa[l];
-        ab[0] = av.x;
-        ab[1] = av.y;
-        ab[2] = av.z;
-        Ub[2] = ub.z;
-      } else {
-        ab[0] = ub.z;
-        ab[1] = ub.w;
-        ab[2] = T(0);
-      }
-      const T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+      T vb[3 * D];
+      PK::load(smem_raw, window, l, vb);
+      T d[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < D; ++k) d[k] = va[k] - vb[k];
       T r2 = d[0] * d[0] + d[1] * d[1];
       if (D == 3) r2 += d[2] * d[2];
       const T w0 = dw_over_r(r2, g.inv_h, g.c5);
       T e[3];
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        e[k] = w0 * d[k];
-        ms[k] += xb.w * e[k];
-      }
+      for (int k = 0; k < D; ++k) e[k] = w0 * d[k];
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          Gs[i][k] += Ub[i] * e[k];
-          Qs[i][k] += ab[i] * e[k];
+          Gs[i][k] += vb[D + i] * e[k];
+          Qs[i][k] += vb[2 * D + i] * e[k];
         }
     });
-#pragma unroll
-  for (int k = 0; k < D; ++k) ms[k] = lane_sum<LPP>(ms[k]);
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -555,14 +521,17 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   if (active && h == 0) {
     const int64_t a = a_own;
     // the own particle's terms
-    const T aav[3] = {aa.x, aa.y, aa.z};
+    const T Va = g.V[a];
+    T ga[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ga[k] = g.gsum[k * n + a];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const T ui = (T)(u[i * n + a] - uo[i]);
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        Gs[i][k] -= ui * ms[k];
-        Qs[i][k] = aav[i] * ms[k] - Va * Qs[i][k];
+        Gs[i][k] -= ui * ga[k];
+        Qs[i][k] = va[2 * D + i] * ga[k] - Va * Qs[i][k];
       }
     }
     T B[D][D];
@@ -1218,7 +1187,7 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
     return SPH_E_CAPACITY;
   }
   const size_t wm = (size_t)nb->tiling[prec].window_max;
-  const size_t lds_s = wm * (D == 3 ? 3 : 2) * sizeof(vec4<T>);
+  const size_t lds_s = wm * Pk<T, 3 * D>::bytes + 16;
   const size_t lds_g = wm * xtq<D>() * sizeof(vec4<T>);
   int rc = SPH_OK;
   if constexpr (LS > 0) {

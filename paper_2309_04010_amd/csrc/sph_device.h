@@ -277,6 +277,61 @@ static TileGeo<T> tile_geo(const sph_nbr* nb, int prec) {
   return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5, g.gsum};
 }
 
+// N values per window particle as N/4 whole 4-vectors ([window][N/4]) and a
+// remainder array ([window] of 1 or 2 values) after them, so that every LDS
+// read is aligned and no padding is read: 6 values are one 16-byte and one
+// 8-byte read, 9 values two 16-byte reads and one 4-byte read.
+template <typename T, int N>
+struct Pk {
+  static constexpr int Q = N / 4, R = N % 4;
+  static_assert(R != 3, "a remainder of three values is not packed");
+  static constexpr size_t bytes = Q * sizeof(vec4<T>) + R * sizeof(T);  // per particle
+  __device__ static __forceinline__ void store(unsigned char* lds, uint32_t window, uint32_t l,
+                                               const T* v) {
+    vec4<T>* q = reinterpret_cast<vec4<T>*>(lds) + (size_t)l * Q;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      vec4<T> pv;
+      pv.x = v[4 * j];
+      pv.y = v[4 * j + 1];
+      pv.z = v[4 * j + 2];
+      pv.w = v[4 * j + 3];
+      q[j] = pv;
+    }
+    unsigned char* rb = lds + (size_t)window * Q * sizeof(vec4<T>);
+    if constexpr (R == 2) {
+      using v2 = T __attribute__((ext_vector_type(2)));
+      v2 r;
+      r.x = v[4 * Q];
+      r.y = v[4 * Q + 1];
+      reinterpret_cast<v2*>(rb)[l] = r;
+    } else if constexpr (R == 1) {
+      reinterpret_cast<T*>(rb)[l] = v[4 * Q];
+    }
+  }
+  __device__ static __forceinline__ void load(const unsigned char* lds, uint32_t window,
+                                              uint32_t l, T* v) {
+    const vec4<T>* q = reinterpret_cast<const vec4<T>*>(lds) + (size_t)l * Q;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const vec4<T> pv = q[j];
+      v[4 * j] = pv.x;
+      v[4 * j + 1] = pv.y;
+      v[4 * j + 2] = pv.z;
+      v[4 * j + 3] = pv.w;
+    }
+    const unsigned char* rb = lds + (size_t)window * Q * sizeof(vec4<T>);
+    if constexpr (R == 2) {
+      using v2 = T __attribute__((ext_vector_type(2)));
+      const v2 r = reinterpret_cast<const v2*>(rb)[l];
+      v[4 * Q] = r.x;
+      v[4 * Q + 1] = r.y;
+    } else if constexpr (R == 1) {
+      v[4 * Q] = reinterpret_cast<const T*>(rb)[l];
+    }
+  }
+};
+
 // Window layout of the gathers whose pair term needs no neighbour volume: the
 // relative position (D values) and a D x D tensor packed into XTQ 4-vectors.
 template <int D>
