@@ -436,12 +436,12 @@ __device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot
 // gathers the neighbours' u (for H) and a_bar = dt w (free particles) from the
 // LDS window; writes G_bar = H_bar B0^T, updates the J2 state adjoint,
 // accumulates p_bar and the parameter partials.  Both sums share the pair's
-// e = grad W and take the own particle's term out of the pair loop:
-//   sum_b V_b (u_b - u_a) (x) e       = sum_b (V_b u_b) (x) e - u_a (x) g_a,
-//   sum_b (V_b a_a - V_a a_b) (x) e   = a_a (x) g_a - V_a sum_b a_b (x) e,
-// with g_a = sum_b V_b e from the build and u relative to the tile's first
-// particle: the window holds the relative position, V_b u_b and a_b (nine
-// values in 3D, two 16-byte and one 4-byte LDS read per pair)
+// e = grad W and keep their per-pair differences, V_b (u_b - u_a) and
+// V_b a_a - V_a a_b: taking the own particle's terms out of the loop makes
+// them cancel across the pairs, which costs FP32 gradients an order of
+// magnitude on smooth fields.  The window holds the relative position, V_b,
+// u_b and a_b: ten values in 3D, two 16-byte and one 8-byte LDS read per pair
+// (eight in 2D, one of them padding).
 template <typename T, int D, int LPP, int MODEL>
 __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
@@ -450,7 +450,8 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     double* __restrict__ gpart, Ctrl* ctrl, Bat bt) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
-  using PK = Pk<T, 3 * D>;  // (relative position, V_b u_b, a_b)
+  constexpr int OV = D, OU = D + 1, OA = 2 * D + 1;  // offsets of V, u, a
+  using PK = Pk<T, D == 3 ? 10 : 8>;                    // (position, V, u, a[, 0])
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileDesc& td = g.tiles[tile];
   const uint32_t window = td.window;
@@ -465,16 +466,17 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   const WinMap wm = win_map(td);
   for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
     const int64_t gi = wm(l);
-    const T Vb = g.V[gi];
     const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
     const T kf = fixed ? T(0) : (bt.spec ? bt.get<T>(BT_DT, bt.spec[gi]) : dt);
-    T vv[3 * D];
+    T vv[D == 3 ? 10 : 8];
+    vv[OV] = g.V[gi];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       vv[k] = (T)(g.X[k * n + gi] - xo[k]);
-      vv[D + k] = Vb * (T)(u[k * n + gi] - uo[k]);
-      vv[2 * D + k] = kf * w[k * n + gi];
+      vv[OU + k] = (T)(u[k * n + gi] - uo[k]);
+      vv[OA + k] = kf * w[k * n + gi];
     }
+    if (D == 2) vv[7] = T(0);
     PK::store(smem_raw, window, l, vv);
   }
   __syncthreads();
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   const bool active = (uint32_t)t < td.count;
   uint32_t la;
   const int64_t a_own = tile_own(td, active ? (uint32_t)t : 0u, la);
-  T va[3 * D];
+  T va[D == 3 ? 10 : 8];
   PK::load(smem_raw, window, la, va);
   T Gs[D][D], Qs[D][D];
 #pragma unroll
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     for (int k = 0; k < D; ++k) Gs[i][k] = Qs[i][k] = T(0);
   if (active)
     ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
-      T vb[3 * D];
+      T vb[D == 3 ? 10 : 8];
       PK::load(smem_raw, window, l, vb);
       T d[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -499,16 +501,22 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
       T r2 = d[0] * d[0] + d[1] * d[1];
       if (D == 3) r2 += d[2] * d[2];
       const T w0 = dw_over_r(r2, g.inv_h, g.c5);
-      T e[3];
+      T e[3], f[3];
 #pragma unroll
-      for (int k = 0; k < D; ++k) e[k] = w0 * d[k];
+      for (int k = 0; k < D; ++k) {
+        e[k] = w0 * d[k];
+        f[k] = vb[OV] * e[k];
+      }
 #pragma unroll
-      for (int i = 0; i < D; ++i)
+      for (int i = 0; i < D; ++i) {
+        const T du = vb[OU + i] - va[OU + i];
+        const T qa = vb[OV] * va[OA + i] - va[OV] * vb[OA + i];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          Gs[i][k] += vb[D + i] * e[k];
-          Qs[i][k] += vb[2 * D + i] * e[k];
+          Gs[i][k] += du * f[k];
+          Qs[i][k] += qa * e[k];
         }
+      }
     });
 #pragma unroll
   for (int i = 0; i < D; ++i)
@@ -520,20 +528,6 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   double thd[kNTheta] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (active && h == 0) {
     const int64_t a = a_own;
-    // the own particle's terms
-    const T Va = g.V[a];
-    T ga[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) ga[k] = g.gsum[k * n + a];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const T ui = (T)(u[i * n + a] - uo[i]);
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        Gs[i][k] -= ui * ga[k];
-        Qs[i][k] = va[2 * D + i] * ga[k] - Va * Qs[i][k];
-      }
-    }
     T B[D][D];
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -1187,7 +1181,7 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
     return SPH_E_CAPACITY;
   }
   const size_t wm = (size_t)nb->tiling[prec].window_max;
-  const size_t lds_s = wm * Pk<T, 3 * D>::bytes + 16;
+  const size_t lds_s = wm * Pk<T, D == 3 ? 10 : 8>::bytes + 16;
   const size_t lds_g = wm * xtq<D>() * sizeof(vec4<T>);
   int rc = SPH_OK;
   if constexpr (LS > 0) {

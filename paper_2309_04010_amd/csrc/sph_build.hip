@@ -393,15 +393,13 @@ __global__ void k_nbr(const double* X, const uint32_t* key, const uint32_t* cs, 
   }
 }
 
-// B0_a = (sum_b V_b (X_b - X_a) (x) grad_a W_ab)^-1, eq. (sph-correctmatrix),
-// and beside it the kernel-gradient sum g_a = sum_b V_b grad_a W_ab, which the
-// momentum sum and its transpose use for the own particle's term
+// B0_a = (sum_b V_b (X_b - X_a) (x) grad_a W_ab)^-1, eq. (sph-correctmatrix)
 __global__ void k_B0(const double* X, const double* V, const int64_t* off, const uint32_t* idx,
                      int64_t n, int dim, double inv_h, double c5, double* B0, float* B0f,
-                     double* gsum, float* gsumf, int32_t* status) {
+                     int32_t* status) {
   int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (a >= n) return;
-  double M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gs[3] = {0, 0, 0};
+  double M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double xa[3] = {X[a], dim > 1 ? X[n + a] : 0.0, dim > 2 ? X[2 * n + a] : 0.0};
   for (int64_t j = off[a]; j < off[a + 1]; ++j) {
     int64_t b = idx[j];
@@ -414,11 +412,6 @@ __global__ void k_B0(const double* X, const double* V, const int64_t* off, const
     double w = dw_over_r(r2, inv_h, c5);
     for (int i = 0; i < dim; ++i)
       for (int k = 0; k < dim; ++k) M[i * 3 + k] += V[b] * (-d[i]) * (w * d[k]);
-    for (int k = 0; k < dim; ++k) gs[k] += V[b] * (w * d[k]);
-  }
-  for (int k = 0; k < dim; ++k) {
-    gsum[k * n + a] = gs[k];
-    gsumf[k * n + a] = (float)gs[k];
   }
   double Mi[9], det, fro = 0;
   for (int i = 0; i < dim; ++i)
@@ -1113,12 +1106,11 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   // correction matrices
   int32_t* dstat = nullptr;
   if ((rc_ = dalloc(&nb->B0, dim * dim * n)) || (rc_ = dalloc(&nb->B0f, dim * dim * n)) ||
-      (rc_ = dalloc(&nb->gsum, dim * n)) || (rc_ = dalloc(&nb->gsumf, dim * n)) ||
       (rc_ = dalloc(&dstat, 2)))
     return rc_;
   SPH_HIP(hipMemsetAsync(dstat, 0, 2 * sizeof(int32_t), s));
   k_B0<<<nblocks(n, 128), 128, 0, s>>>(nb->X, nb->V, nb->nbr_off, nb->nbr_idx, n, dim, nb->inv_h,
-                                       nb->c5, nb->B0, nb->B0f, nb->gsum, nb->gsumf, dstat);
+                                       nb->c5, nb->B0, nb->B0f, dstat);
   SPH_LAUNCH_CHECK();
   int32_t hstat = 0;
   SPH_HIP(hipMemcpyAsync(&hstat, dstat, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1362,6 +1354,13 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
         set_error("tile ELL build failed (code %d)", he);
         return SPH_E_DEVICE;
       }
+    }
+    // the kernel-gradient sums of both precisions, with the tiled gathers'
+    // arithmetic
+    if ((rc_ = dalloc(&nb->gsum, dim * n)) || (rc_ = dalloc(&nb->gsumf, dim * n)) ||
+        (rc_ = tile_gsum(nb, s))) {
+      hipFree(terr);
+      return rc_;
     }
     hipFree(terr);
   }

@@ -168,7 +168,7 @@ struct sph_nbr {
   double* B0 = nullptr;
   float* Vf = nullptr;
   float* B0f = nullptr;
-  double* gsum = nullptr;  // [dim][n] sum_b V_b grad_a W_ab (fixed reference configuration)
+  double* gsum = nullptr;  // [dim][n] sum_b V_b grad_a W_ab (fixed reference configuration; tile_gsum)
   float* gsumf = nullptr;
   uint32_t* sa = nullptr;
   uint32_t* sb = nullptr;
@@ -299,6 +299,9 @@ int adj_damping(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                 const sph_adjoint* adj, double eta, double dt, hipStream_t s);
 int adj_drift(const sph_nbr* nb, const sph_state* st, const sph_adjoint* adj, double dt,
               hipStream_t s);
+// g_a = sum_b V_b grad_a W_ab into nb->gsum (FP64) and nb->gsumf (FP32), each
+// with the tiled gathers' arithmetic of its precision (needs both tilings)
+int tile_gsum(const sph_nbr* nb, hipStream_t s);
 int diffusion_F(const sph_nbr* nb, int prec, const double* u, const void* c, void* Fi, void* sat,
                 hipStream_t s);
 // drift_dt: the step of the inner step before the slow step when that inner

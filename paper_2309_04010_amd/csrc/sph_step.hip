@@ -1309,6 +1309,81 @@ static int diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, const s
   return SPH_OK;
 }
 
+// g_a = sum_b V_b grad_a W_ab of the reference configuration, computed once
+// per precision with the tiled gathers' own arithmetic: positions relative to
+// the tile's first particle rounded to T, the same kernel-gradient formula.
+// The momentum sum and the reverse passes take their own-particle terms from
+// it; computed this way it cancels against their pair sums as a per-pair
+// evaluation would, where an exact g_a would leave a residual force of the
+// positions' rounding on every particle (visible in FP32 on thin bodies).
+template <typename T, int D, int LPP>
+__global__ __launch_bounds__(128 * LPP) void k_gsum(TileGeo<T> g, T* __restrict__ gs) {
+  const int64_t tile = xcd_tile(g.n_tiles);
+  if (tile >= g.n_tiles) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TileDesc& td = g.tiles[tile];
+  const uint32_t window = td.window;
+  vec4<T>* sx = reinterpret_cast<vec4<T>*>(smem_raw);
+  const int64_t n = g.n;
+  const int64_t p0 = td.p0;
+  double xo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
+  const WinMap wm = win_map(td);
+  for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
+    const int64_t gi = wm(l);
+    vec4<T> xv;
+    xv.x = (T)(g.X[gi] - xo[0]);
+    xv.y = (T)(g.X[n + gi] - xo[1]);
+    xv.z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
+    xv.w = g.V[gi];
+    sx[l] = xv;
+  }
+  __syncthreads();
+  const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
+  if ((uint32_t)t >= td.count) return;
+  uint32_t la;
+  const int64_t a = tile_own(td, (uint32_t)t, la);
+  const vec4<T> xa = sx[la];
+  T m[3] = {T(0), T(0), T(0)};
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    const vec4<T> xb = sx[l];
+    T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
+    T r2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) r2 += d[2] * d[2];
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
+#pragma unroll
+    for (int k = 0; k < D; ++k) m[k] += w * d[k];
+  });
+#pragma unroll
+  for (int k = 0; k < D; ++k) m[k] = lane_sum<LPP>(m[k]);
+  if (h != 0) return;
+#pragma unroll
+  for (int k = 0; k < D; ++k) gs[k * n + a] = m[k];
+}
+
+template <typename T, int D>
+static int tile_gsum_t(const sph_nbr* nb, int prec, T* gs, hipStream_t s) {
+  TileGeo<T> g = tile_geo<T>(nb, prec);
+  if (g.n_tiles == 0) return SPH_OK;
+  constexpr int L = 2;
+  const size_t lds = (size_t)nb->tiling[prec].window_max * sizeof(vec4<T>);
+  int rc = lds_attr(k_gsum<T, D, L>, lds);
+  if (rc) return rc;
+  const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
+  k_gsum<T, D, L><<<grid, (unsigned)(g.tmax * L), lds, s>>>(g, gs);
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+int tile_gsum(const sph_nbr* nb, hipStream_t s) {
+  int rc = nb->dim == 2 ? tile_gsum_t<double, 2>(nb, SPH_F64, nb->gsum, s)
+                        : tile_gsum_t<double, 3>(nb, SPH_F64, nb->gsum, s);
+  if (rc) return rc;
+  return nb->dim == 2 ? tile_gsum_t<float, 2>(nb, SPH_F32, nb->gsumf, s)
+                      : tile_gsum_t<float, 3>(nb, SPH_F32, nb->gsumf, s);
+}
+
 // the deformation pass alone (F^-1 and the saturation c / J of a given u and
 // c), for the reverse of the coupled step
 template <typename T, int D>
