@@ -603,11 +603,10 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
     const uint8_t* __restrict__ flags, double drift_dt, Bat bt, int drift_incr = 0) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
-  constexpr int NQ = xtq<D>();
+  using PK = Pk<T, D + D * D>;  // (relative position, G_bar_b)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileDesc& td = g.tiles[tile];
   const uint32_t window = td.window;
-  vec4<T>* sp = reinterpret_cast<vec4<T>*>(smem_raw);  // [window][NQ]
   const int64_t n = g.n;
   const int64_t p0 = td.p0;
   double xo[3] = {0, 0, 0};
@@ -616,24 +615,26 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_gather(
   const WinMap wm = win_map(td);
   for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
     const int64_t gi = wm(l);
-    T xv[D], gv[D * D];
+    T vv[D + D * D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) xv[k] = (T)(g.X[k * n + gi] - xo[k]);
+    for (int k = 0; k < D; ++k) vv[k] = (T)(g.X[k * n + gi] - xo[k]);
 #pragma unroll
-    for (int c = 0; c < D * D; ++c) gv[c] = Gb[c * n + gi];
-    xt_store<T, D>(sp + l * NQ, xv, gv);
+    for (int c = 0; c < D * D; ++c) vv[D + c] = Gb[c * n + gi];
+    PK::store(smem_raw, window, l, vv);
   }
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
   uint32_t la;
   const int64_t a = tile_own(td, (uint32_t)t, la);
-  T xa[D], Ga[D * D];
-  xt_load<T, D>(sp + la * NQ, xa, Ga);
+  T xa[D + D * D];
+  PK::load(smem_raw, window, la, xa);
+  const T* Ga = xa + D;
   T f[3] = {T(0), T(0), T(0)};
   ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
-    T xb[D], Gbb[D * D];
-    xt_load<T, D>(sp + l * NQ, xb, Gbb);
+    T xb[D + D * D];
+    PK::load(smem_raw, window, l, xb);
+    const T* Gbb = xb + D;
     T d[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < D; ++k) d[k] = xa[k] - xb[k];
@@ -1182,7 +1183,7 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
   }
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds_s = wm * Pk<T, D == 3 ? 10 : 8>::bytes + 16;
-  const size_t lds_g = wm * xtq<D>() * sizeof(vec4<T>);
+  const size_t lds_g = wm * Pk<T, D + D * D>::bytes + 16;
   int rc = SPH_OK;
   if constexpr (LS > 0) {
     if ((rc = lds_attr(k_adj_stress<T, D, LS, MODEL>, lds_s))) return rc;
@@ -1330,7 +1331,7 @@ static int adj_diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, con
   constexpr int L = 2;
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds2 = wm * 2 * sizeof(vec4<T>);
-  const size_t lds_g = wm * xtq<D>() * sizeof(vec4<T>);
+  const size_t lds_g = wm * Pk<T, D + D * D>::bytes + 16;
   int rc;
   if ((rc = lds_attr(k_acd_a<T, D, L>, lds2)) || (rc = lds_attr(k_acd_b<T, D, L>, lds2)) ||
       (rc = lds_attr(k_adj_gather<T, D, L>, lds_g)))

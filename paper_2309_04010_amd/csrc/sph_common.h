@@ -249,10 +249,10 @@ __device__ __forceinline__ T dw_over_r(T r2, T inv_h, T c5) {
 }
 
 // ---- tiling parameters per precision -----------------------------------------
-// LDS bytes per staged window particle of the widest tiled kernels: the
-// momentum sum and its transpose (relative position and a dim x dim tensor
-// packed into whole 4-vectors) and the reverse stress stage (position and
-// volume, u, a: three 4-vectors in 3D, two in 2D).
+// LDS bytes per staged window particle of the widest tiled kernels: in 3D the
+// momentum sum and its transpose (relative position and a 3 x 3 tensor, twelve
+// values), in 2D the stress stages (two 4-vectors); the formula is
+// ceil((dim + dim^2) / 4) 4-vectors, which covers both.
 inline int tile_tmax(int prec) { return prec == SPH_F64 ? 64 : 128; }
 inline int64_t tile_lds_bytes_per_particle(int prec, int dim) {
   const int t = prec == SPH_F64 ? 8 : 4;

@@ -332,42 +332,6 @@ struct Pk {
   }
 };
 
-// Window layout of the gathers whose pair term needs no neighbour volume: the
-// relative position (D values) and a D x D tensor packed into XTQ 4-vectors.
-template <int D>
-constexpr int xtq() { return (D + D * D + 3) / 4; }
-template <typename T, int D>
-__device__ __forceinline__ void xt_store(vec4<T>* dst, const T* x, const T* M) {
-  T v[xtq<D>() * 4];
-#pragma unroll
-  for (int c = 0; c < xtq<D>() * 4; ++c) v[c] = c < D ? x[c] : (c < D + D * D ? M[c - D] : T(0));
-#pragma unroll
-  for (int q = 0; q < xtq<D>(); ++q) {
-    vec4<T> pv;
-    pv.x = v[4 * q];
-    pv.y = v[4 * q + 1];
-    pv.z = v[4 * q + 2];
-    pv.w = v[4 * q + 3];
-    dst[q] = pv;
-  }
-}
-template <typename T, int D>
-__device__ __forceinline__ void xt_load(const vec4<T>* src, T* x, T* M) {
-  T v[xtq<D>() * 4];
-#pragma unroll
-  for (int q = 0; q < xtq<D>(); ++q) {
-    const vec4<T> pv = src[q];
-    v[4 * q] = pv.x;
-    v[4 * q + 1] = pv.y;
-    v[4 * q + 2] = pv.z;
-    v[4 * q + 3] = pv.w;
-  }
-#pragma unroll
-  for (int c = 0; c < D; ++c) x[c] = v[c];
-#pragma unroll
-  for (int c = 0; c < D * D; ++c) M[c] = v[D + c];
-}
-
 // own particle t of a tile: its sorted index and its window position
 __device__ __forceinline__ int64_t tile_own(const TileDesc& td, uint32_t t, uint32_t& la) {
   if (t < td.count0) {

@@ -215,11 +215,10 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
-  constexpr int NQ = xtq<D>();
+  using PK = Pk<T, D + D * D>;  // (relative position, V_b PB_b)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileDesc& td = g.tiles[tile];
   const uint32_t window = td.window;
-  vec4<T>* sp = reinterpret_cast<vec4<T>*>(smem_raw);  // [window][NQ]
   const int64_t n = g.n;
   const int64_t p0 = td.p0;
   double xo[3] = {0, 0, 0};
@@ -227,34 +226,35 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
   for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
   const WinMap wm = win_map(td);
   for (uint32_t l0 = threadIdx.x; l0 < window; l0 += 2 * blockDim.x) {
-    T xv[2][D], pb[2][D * D];
+    T vv[2][D + D * D];
     uint32_t ls[2] = {l0, l0 + blockDim.x};
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       if (ls[e] < window) {
         const int64_t gi = wm(ls[e]);
 #pragma unroll
-        for (int k = 0; k < D; ++k) xv[e][k] = (T)(g.X[k * n + gi] - xo[k]);
+        for (int k = 0; k < D; ++k) vv[e][k] = (T)(g.X[k * n + gi] - xo[k]);
         const T Vb = g.V[gi];
 #pragma unroll
-        for (int c = 0; c < D * D; ++c) pb[e][c] = Vb * PB[c * n + gi];
+        for (int c = 0; c < D * D; ++c) vv[e][D + c] = Vb * PB[c * n + gi];
       }
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e)
-      if (ls[e] < window) xt_store<T, D>(sp + ls[e] * NQ, xv[e], pb[e]);
+      if (ls[e] < window) PK::store(smem_raw, window, ls[e], vv[e]);
   }
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
   uint32_t la;
   const int64_t a = tile_own(td, (uint32_t)t, la);
-  T xa[D], Pdum[D * D];
-  xt_load<T, D>(sp + la * NQ, xa, Pdum);
+  T xa[D + D * D];
+  PK::load(smem_raw, window, la, xa);
   T f[3] = {T(0), T(0), T(0)};
   ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
-    T xb[D], Pb[D * D];
-    xt_load<T, D>(sp + l * NQ, xb, Pb);
+    T xb[D + D * D];
+    PK::load(smem_raw, window, l, xb);
+    const T* Pb = xb + D;
     T d[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < D; ++k) d[k] = xa[k] - xb[k];
@@ -986,7 +986,7 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
   const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
   const size_t wm = (size_t)nb->tiling[prec].window_max;
   const size_t lds_s = wm * 2 * sizeof(vec4<T>);
-  const size_t lds_m = wm * xtq<D>() * sizeof(vec4<T>);
+  const size_t lds_m = wm * Pk<T, D + D * D>::bytes + 16;
   int rc = SPH_OK;
   if constexpr (LS > 0) {
     if ((rc = lds_attr(k_stress<T, D, LS, MODEL>, lds_s))) return rc;
