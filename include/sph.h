@@ -250,8 +250,8 @@ int sph_diffusion_step(const sph_nbr* nbr, const sph_material* mat, const sph_st
  * c = c_bc J on SPH_FLAG_CDIR particles (saturation c_bc) and
  * p = C_swell (c / J - c0).  Needs st->u, c, q, p; uses st->PB as scratch
  * (overwritten: F^-1).  With u = 0 and nonlinear = 0 it is
- * sph_diffusion_step.  Its reverse runs inside sph_advance_multirate_backward
- * (there is no single-step VJP entry).  Asynchronous. */
+ * sph_diffusion_step.  Its reverse: sph_diffusion_step_coupled_vjp, and
+ * inside sph_advance_multirate_backward.  Asynchronous. */
 int sph_diffusion_step_coupled(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
                                double D, double dt_d, double c_bc, int32_t nonlinear, void* stream);
 
@@ -355,6 +355,21 @@ int sph_drift_vjp(const sph_nbr* nbr, const sph_state* st, const sph_adjoint* ad
 int sph_diffusion_step_vjp(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
                            const void* c_before, const sph_adjoint* adj, double D, double dt_d,
                            double c_bc, void* stream);
+
+/* Reverse of sph_diffusion_step_coupled (the same reading of Sec. 2.2.2 and
+ * Sec. 3.2).  st->u = the step's displacement (the step leaves it as it is),
+ * st->c = content AFTER the step, c_before = content before it (device,
+ * prec-typed [n]).  adj->c = adjoint of c after the step (replaced by the
+ * adjoint before it); adj->p = adjoint of p after the step (consumed:
+ * zeroed); adj->u += the adjoint of u through F, J and F^-1;
+ * adj->grad[D, C] accumulated.  Working storage, overwritten: st->PB, st->p,
+ * st->q, the first two components of st->v and adj->work ([dim*dim][n]).
+ * Errors: SPH_E_ARG (arrays missing), SPH_E_UNSUPPORTED (a mixture, or a
+ * batched neighbourhood).  Async. */
+int sph_diffusion_step_coupled_vjp(const sph_nbr* nbr, const sph_material* mat,
+                                   const sph_state* st, const void* c_before,
+                                   const sph_adjoint* adj, double D, double dt_d, double c_bc,
+                                   int32_t nonlinear, void* stream);
 
 /* Reverse pass of a taped sph_advance_multirate run with the same cfg.  On
  * entry adj->u, adj->v (and adj->plastic, adj->c) hold the adjoint of the

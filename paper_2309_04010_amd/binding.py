@@ -28,7 +28,8 @@ EXPORTED = [
     "sph_damping_sweep", "sph_drift_ke", "sph_load_step", "sph_diffusion_step", "sph_diffusion_step_coupled",
     "sph_advance_multirate", "sph_status", "sph_profile_enable", "sph_profile_classes", "sph_profile_read",
     "sph_last_error", "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_drift_vjp",
-    "sph_diffusion_step_vjp", "sph_advance_multirate_backward", "sph_constitutive",
+    "sph_diffusion_step_vjp", "sph_diffusion_step_coupled_vjp", "sph_advance_multirate_backward",
+    "sph_constitutive",
     "sph_constitutive_vjp", "sph_build_neighbors_batched", "sph_advance_multirate_graph",
     "sph_autotune", "sph_set_tuning", "sph_get_tuning",
 ]
@@ -140,6 +141,8 @@ def lib():
     L.sph_drift_vjp.argtypes = [vp, C.POINTER(State), C.POINTER(Adjoint), dbl, vp]
     L.sph_diffusion_step_vjp.argtypes = [vp, C.POINTER(Material), C.POINTER(State), vp,
                                          C.POINTER(Adjoint), dbl, dbl, dbl, vp]
+    L.sph_diffusion_step_coupled_vjp.argtypes = [vp, C.POINTER(Material), C.POINTER(State), vp,
+                                                 C.POINTER(Adjoint), dbl, dbl, dbl, i32, vp]
     L.sph_constitutive.argtypes = [C.POINTER(Material), C.c_int, i64, vp, vp, vp, vp, vp]
     L.sph_constitutive_vjp.argtypes = [C.POINTER(Material), C.c_int, i64, vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp]
@@ -576,6 +579,16 @@ def sph_diffusion_step_vjp(nbr, mat, st, c_before, adj, D, dt_d, c_bc, stream=No
     _check(lib().sph_diffusion_step_vjp(nbr.handle, C.byref(mat), C.byref(cs), _dptr(c_before),
                                         C.byref(adj.cstruct(nbr)), float(D), float(dt_d), float(c_bc),
                                         _stream(stream)))
+
+
+def sph_diffusion_step_coupled_vjp(nbr, mat, st, c_before, adj, D, dt_d, c_bc, nonlinear=0,
+                                   stream=None):
+    import torch
+    cs = st.cstruct(nbr)
+    _need(c_before, torch.float32 if st.prec == SPH_F32 else torch.float64, (nbr.n,), "c_before")
+    _check(lib().sph_diffusion_step_coupled_vjp(nbr.handle, C.byref(mat), C.byref(cs), _dptr(c_before),
+                                                C.byref(adj.cstruct(nbr)), float(D), float(dt_d),
+                                                float(c_bc), int(nonlinear), _stream(stream)))
 
 
 def _point_check(prec, n, **arrs):

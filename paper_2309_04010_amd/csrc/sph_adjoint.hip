@@ -1449,6 +1449,28 @@ extern "C" int sph_diffusion_step_vjp(const sph_nbr* nb, const sph_material* mat
   return grad_reduce(nb, adj->grad, s);
 }
 
+extern "C" int sph_diffusion_step_coupled_vjp(const sph_nbr* nb, const sph_material* mat,
+                                              const sph_state* st, const void* c_before,
+                                              const sph_adjoint* adj, double D, double dt_d,
+                                              double c_bc, int32_t nonlinear, void* stream) {
+  clear_error();
+  int rc = check_adj(nb, mat, st, adj);
+  if (rc) return rc;
+  if (nb->spec) {
+    set_error("the coupled diffusion reverse takes one specimen (D is a scalar here)");
+    return SPH_E_UNSUPPORTED;
+  }
+  if (!st->v) {
+    set_error("the coupled diffusion reverse needs st->v as working storage");
+    return SPH_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // no inner step precedes a lone step: nothing to fold into a drift
+  rc = adj_diffusion_coupled(nb, mat, st, st->u, c_before, adj, D, dt_d, c_bc, nonlinear, 0.0, s);
+  if (rc) return rc;
+  return grad_reduce(nb, adj->grad, s);
+}
+
 namespace {
 Ctrl* g_point_ctrl = nullptr;  // status word of the point evaluations (per process)
 

@@ -49,7 +49,8 @@ def test_header_declares_the_boundary():
     for name in ["sph_build_neighbors", "sph_solid_relax_step", "sph_damping_sweep",
                  "sph_diffusion_step", "sph_advance_multirate", "sph_advance_multirate_backward",
                  "sph_solid_relax_step_vjp", "sph_damping_sweep_vjp", "sph_diffusion_step_vjp",
-                 "sph_build_neighbors_batched", "sph_advance_multirate_graph"]:
+                 "sph_diffusion_step_coupled_vjp", "sph_build_neighbors_batched",
+                 "sph_advance_multirate_graph"]:
         assert name in d
 
 

@@ -9,7 +9,9 @@
 * the reverse pass through coupled slow steps gives the complex-step
   oracle's gradients (2D and 3D, linear and nonlinear flux, FP64 and FP32),
   also with slow steps that take no inner step; a batched coupled run's
-  reverse is refused.
+  reverse is refused;
+* the single-step reverse (sph_diffusion_step_coupled_vjp) against
+  complex-step derivatives of the oracle's step, in c, u, D and C.
 """
 import numpy as np
 import pytest
@@ -120,6 +122,71 @@ def test_coupled_multirate_run_matches_oracle(oracle_mod, nonlinear):
     assert np.abs(uo).max() > 0
     assert rel_err(host(st.u), uo) < 1e-10
     assert rel_err(host(st.c), co) < 1e-10
+    nb.close()
+
+
+@pytest.mark.parametrize("nonlinear", [0, 1], ids=["linear", "nonlinear"])
+@pytest.mark.parametrize("prec", [B.SPH_F64, B.SPH_F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coupled_vjp_is_transpose(oracle_mod, dim, prec, nonlinear):
+    """sph_diffusion_step_coupled_vjp against complex-step derivatives of the
+    oracle's coupled step, for L = <c_bar, c'> + <p_bar, p'>: the adjoints of
+    c and u (through F, J and F^-1) and the D and C gradients (FP64 1e-9,
+    FP32 2e-3); a batched neighbourhood is refused."""
+    print(f"[coupled diffusion] vjp dim={dim} prec={prec} nonlinear={nonlinear}", flush=True)
+    rng = np.random.default_rng(70 + dim)
+    X, V, h = jittered((37, 23) if dim == 2 else (13, 9, 7), jitter=0.1, seed=13)
+    o, nb = build_pair(oracle_mod, dim, X, V, h)
+    oc = oracle_mod.Oracle(dim, X, V, h, complex_step=True)
+    assert np.array_equal(oc.perm, o.perm)
+    n = o.n
+    T = torch_dtype(prec)
+    u = _smooth_u(o, dim, 0.02, 5 + dim)
+    c0 = rng.uniform(0.1, 0.4, n)
+    cb = rng.normal(0.0, 1.0, n)
+    pbv = rng.normal(0.0, 1e-6, n)
+    if prec == B.SPH_F32:
+        c0, cb = (x.astype(np.float32).astype(np.float64) for x in (c0, cb))
+    flags = np.zeros(n, np.uint8)
+    flags[rng.random(n) < 0.05] = cases.CDIR
+    D, c_bc = 1e-10, 0.4
+    dt = 0.5 * o.h ** 2 / D
+    mat = B.material(**NH)
+    st = B.new_state(nb, prec, with_diffusion=True)
+    st.u.copy_(dev(u))
+    st.c.copy_(dev(c0, T))
+    st.flags = dev(flags)
+    c_before = st.c.clone()
+    B.sph_diffusion_step_coupled(nb, mat, st, D, dt, c_bc, nonlinear)
+    adj = B.new_adjoint(nb, prec, with_diffusion=True)
+    adj.c.copy_(dev(cb, T))
+    adj.p.copy_(dev(pbv))
+    B.sph_diffusion_step_coupled_vjp(nb, mat, st, c_before, adj, D, dt, c_bc, nonlinear)
+    cbar, ubar, grad = host(adj.c), host(adj.u), host(adj.grad)
+    assert np.all(host(adj.p) == 0.0)
+
+    def L(cc=c0, uu=u, Dv=D, C=NH["C_swell"]):
+        x = np.ascontiguousarray(cc, dtype=complex).copy()
+        q, p = oc.arr(dim, n), oc.arr(n)
+        oc.diffusion_step_coupled(Dv, dt, c_bc, C, NH["c0"], nonlinear,
+                                  np.ascontiguousarray(uu, dtype=complex), x, q, p, flags)
+        return (cb * x).sum() + (pbv * p).sum()
+
+    eps = 1e-30
+    tol = 1e-9 if prec == B.SPH_F64 else 2e-3
+
+    def close(got, want, what):
+        assert abs(got - want) <= tol * abs(want), (what, got, want)
+
+    dc = rng.normal(0.0, 1.0, n)
+    du = rng.normal(0.0, 1e-3 * np.abs(u).max(), (dim, n))
+    close((cbar * dc).sum(), L(cc=c0 + 1j * eps * dc).imag / eps, "c")
+    want_u = L(uu=u + 1j * eps * du).imag / eps
+    assert abs(want_u) > 1e-6 * abs(L().real)            # the step does depend on u
+    close((ubar * du).sum(), want_u, "u")
+    close(grad[B.GRAD_NAMES.index("D")], L(Dv=D + 1j * eps * D).imag / (eps * D), "D")
+    C = NH["C_swell"]
+    close(grad[B.GRAD_NAMES.index("C_swell")], L(C=C + 1j * eps * C).imag / (eps * C), "C_swell")
     nb.close()
 
 
