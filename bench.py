@@ -2,31 +2,39 @@
 
 Workload (default): the 3D membrane plate, 500 x 500 x 4 = 1,000,000
 particles (60,256,216 directed neighbour pairs), neo-Hookean solid with the
-fluid-pressure coupling, diffusion slow steps.  One bench "step" is one slow
-step run forward and then in reverse: the diffusion update and 1000 inner
-steps of {deformation gradient + stress, pair momentum + kick, implicit
-pairwise damping sweep (8 colour passes), drift + kinetic energy}, with u
-before every inner step recorded, followed by the reverse pass (1000
-transposed inner steps and the transposed diffusion step) that gives the
-gradient of the mean centre deflection with respect to E, D and C.  FP32 bulk
-arithmetic with FP64 displacements and reductions.  The neighbour build (once
-per configuration, total-Lagrangian) is setup and is not timed.
+fluid-pressure coupling, diffusion slow steps, whose gradient runs through
+50 checkpointed slow steps x 1000 inner steps.  One bench "step" is one slow
+step of that checkpointed adjoint: the diffusion update and 1000 inner steps
+of {deformation gradient + stress, pair momentum + kick, implicit pairwise
+damping sweep (4 colour passes on the plate), drift + kinetic energy}
+forward, then the reverse pass of that slow step, which first re-runs it
+from its checkpoint to record u before every inner step (a long run keeps
+only the checkpoints) and then runs the 1000 transposed inner steps and the
+transposed diffusion step, giving the gradient of the mean centre deflection
+with respect to E, D and C.  FP32 bulk arithmetic with FP64 displacements
+and reductions.  The neighbour build (once per configuration,
+total-Lagrangian) is setup and is not timed.
 
-Metric: inner-step particle-interactions/s = directed pairs x inner steps /
-wall time of forward + reverse, inputs resident in HBM.  Also reported: the
-FP32 forward alone, the plain FP64 forward (the baseline of the speedup), the
-FP32 state and gradient errors against an FP64 run of the same step, the
-roofline of the dominant kernel class (live HIP-event timing of its launches
-in the timed region, the calibrated counter traffic, a measured copy
-bandwidth), the per-kernel breakdown, the CPU oracle timed on a bounded
-sample, and, outside the timed region: the slow-step variants (one-way and
-two-way coupled diffusion), the cost of the mixture momentum, the necking
-runs of Sec. 5.1/5.2 with their iteration counts (N_S, N_s, N_d) and
-curves, and the batched sweep of 64 strips.
+Metric: inner-step particle-interactions/s = directed pairs x forward inner
+steps / wall time of forward + re-run + reverse, inputs resident in HBM.
+Also reported: the same step without the re-run (the inner states kept from
+the forward run), the whole 50 x 1000 checkpointed run in FP32 (timed as one
+run), the FP32 forward alone, the plain FP64 forward (the baseline of the
+speedup), the FP32 state and gradient errors against an FP64 run of the same
+step, the roofline of the dominant kernel class (live HIP-event timing of its
+launches in the timed region, the calibrated counter traffic, a measured
+copy bandwidth), the damping sweep's and the whole inner step's fractions of
+the HBM and FP32 roofs, the per-kernel breakdown, the CPU oracle timed on a
+bounded sample (one thread, and all host cores), and, outside the timed
+region: the slow-step variants (one-way and two-way coupled diffusion), the
+cost of the mixture momentum, the necking runs of Sec. 5.1/5.2 with their
+iteration counts (N_S, N_s, N_d) and curves, and the batched sweep of 64
+strips.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner M] [--no-cpu]
                   [--no-fp64] [--no-sweep] [--no-coupled] [--necking none|sample|full]
-                  [--necking-compare] [--nx N] [--copy-calibration]
+                  [--necking-compare] [--nx N] [--copy-calibration] [--full-adjoint]
+                  [--no-full-adjoint]
 """
 from __future__ import annotations
 
@@ -58,9 +66,11 @@ def algorithmic_bytes(kernel, dim, prec_bytes, model_j2=False, n_colors=8):
         return b
     if kernel == "momentum":
         return 8 * d + T + T * dd + 2 * T * d + 1         # X, V, PB, v(rw), flags
-    if kernel == "damping":
-        return 8 * d + T + 2 * T * d + 1                  # X, V, v(rw), flags: every pass touches
-                                                          # each particle's block once
+    if kernel in ("damping", "adj_damping"):
+        # per SWEEP (all colour passes): v read and written once and the
+        # inverse mass read once; the pair schedule and its coefficients are
+        # per-pair data, not algorithmic (the pair geometry is fixed)
+        return 2 * T * d + T
     if kernel == "drift_ke":
         return 2 * 8 * d + T * d + 8 + 1                  # u(rw), v, V, flags
     if kernel == "diff_grad":
@@ -75,8 +85,6 @@ def algorithmic_bytes(kernel, dim, prec_bytes, model_j2=False, n_colors=8):
         return b
     if kernel == "adj_gather":
         return 8 * d + T + T * dd + 16 * d + 2 * T * d + 1   # X, V, G_bar, u_bar(rw), w(rw), flags
-    if kernel == "adj_damping":
-        return 8 * d + T + 2 * T * d + 1
     return 0.0
 
 
@@ -99,12 +107,15 @@ def flops_per_pair(kernel, dim):
     return 0
 
 
-def roofline_of(kern, prof, dim, n, n_pairs, n_colors, workload_key):
+def roofline_of(kern, prof, dim, n, n_pairs, n_colors, workload_key, passes=1):
     """Roofline of one kernel class from its timed launches: the HBM roof
     (algorithmic bytes per launch) or, when the class's algorithmic intensity
     (flops per byte) exceeds the ridge of the two peaks, the FP32 vector roof
-    (useful flops per launch)."""
+    (useful flops per launch).  The damping classes are taken per sweep of
+    `passes` colour passes."""
     launches, kms = prof[kern]
+    if kern in ("damping", "adj_damping"):
+        launches = launches / passes
     avg_s = kms / 1000.0 / max(launches, 1)
     alg_bytes = algorithmic_bytes(kern, dim, 4, n_colors=n_colors) * n
     flops = flops_per_pair(kern, dim) * n_pairs
@@ -169,9 +180,7 @@ def run_gpu(case, prec, steps, warmup, inner, torch, B, profile=True, use_graph=
     mat = B.material(**case.material)
     run = dict(case.run)
     run.update(n_slow=1, fixed_inner=inner)
-    K = case.material["E"] / (3.0 * (1.0 - 2.0 * case.material["nu"]))
-    B.sph_autotune(nb, mat, st, run["eta"], 0.6 * case.h / (K / case.material["rho0"]) ** 0.5,
-                   with_adjoint=False)
+    B.sph_autotune(nb, mat, st, run["eta"], B.sph_default_steps(case.h, mat)[0], with_adjoint=False)
     cfg = B.multirate_cfg(**run, chunk=min(inner, 250), use_graph=use_graph)
     for _ in range(warmup):
         B.sph_advance_multirate(nb, mat, st, cfg)
@@ -195,13 +204,10 @@ def run_gpu(case, prec, steps, warmup, inner, torch, B, profile=True, use_graph=
     return info, prof
 
 
-def cpu_baseline(case, seconds_budget=15.0):
-    """The oracle as it stands, single-threaded, on the same workload: build
-    (untimed), one diffusion step, then inner steps until the budget is
-    spent (at least one)."""
+def _oracle_sample(case, openmp, seconds_budget):
     import numpy as np
     import oracle
-    o = oracle.Oracle(case.dim, case.X, case.V, case.h)
+    o = oracle.Oracle(case.dim, case.X, case.V, case.h, openmp=openmp)
     perm = o.perm
     flags = np.ascontiguousarray(case.flags[perm])
     mat = o.material(**case.material)
@@ -209,13 +215,12 @@ def cpu_baseline(case, seconds_budget=15.0):
     u, v = o.arr(d, n), o.arr(d, n)
     c = np.ascontiguousarray(case.c_init[perm]) if case.c_init is not None else None
     q, p = o.arr(d, n), o.arr(n)
-    K = case.material["E"] / (3 * (1 - 2 * case.material["nu"]))
-    dt = 0.6 * case.h / np.sqrt(K / case.material["rho0"])
+    dt, dtd = o.default_steps(mat, case.run["D"])
     rho0 = case.material["rho0"]
     t0 = time.perf_counter()
     if c is not None:
-        o.diffusion_step(case.run["D"], 0.5 * case.h ** 2 / case.run["D"], case.run["c_bc"],
-                         case.material.get("C_swell", 0.0), case.material.get("c0", 0.0), c, q, p, flags)
+        o.diffusion_step(case.run["D"], dtd, case.run["c_bc"], case.material.get("C_swell", 0.0),
+                         case.material.get("c0", 0.0), c, q, p, flags)
     steps = 0
     while True:
         o.solid_step(mat, dt, u, v, p=p, flags=flags)
@@ -225,14 +230,37 @@ def cpu_baseline(case, seconds_budget=15.0):
         if time.perf_counter() - t0 >= seconds_budget:
             break
     t1 = time.perf_counter()
-    return dict(value=o.n_pairs * steps / (t1 - t0), unit="interactions/s", cores=1, kind="oracle",
-                sample=f"{case.name} full size ({n} particles): one diffusion step + {steps} inner "
-                       f"steps, single thread, {t1 - t0:.1f} s (build not timed)")
+    return o.n_pairs * steps / (t1 - t0), steps, t1 - t0, n
 
 
-def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
-    """Forward (taped) + reverse of one slow step, `steps` times; returns
-    timing, the final u of the last forward run and the gradient."""
+def cpu_baseline(case, seconds_budget=15.0, all_cores_budget=10.0):
+    """The oracle as it stands, single-threaded, on the same workload: build
+    (untimed), one diffusion step, then inner steps until the budget is
+    spent (at least one).  Beside it, the oracle's OpenMP build on all host
+    cores (per-particle loops and the anchors of one damping colour in
+    parallel; the same values)."""
+    val, steps, sec, n = _oracle_sample(case, False, seconds_budget)
+    out = dict(value=val, unit="interactions/s", cores=1, kind="oracle",
+               sample=f"{case.name} full size ({n} particles): one diffusion step + {steps} inner "
+                      f"steps, single thread, {sec:.1f} s (build not timed)")
+    try:
+        ncores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+        val2, steps2, sec2, _ = _oracle_sample(case, True, all_cores_budget)
+        out["all_cores"] = dict(value=val2, unit="interactions/s", cores=ncores, kind="oracle (OpenMP build)",
+                                sample=f"one diffusion step + {steps2} inner steps, {ncores} threads, "
+                                       f"{sec2:.1f} s")
+    except OSError as e:      # no OpenMP runtime on the host: the single-thread figure stands
+        out["all_cores"] = dict(error=str(e))
+    return out
+
+
+def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True, taped_steps=2):
+    """One slow step of the checkpointed adjoint, `steps` times: forward
+    (checkpoint + taped inner states), then the reverse pass with the slow
+    step re-run from its checkpoint (recompute), as every slow step of a long
+    checkpointed run costs.  After the timed region, `taped_steps` more
+    forward + reverse steps without the re-run.  Returns timing, the final u
+    of the last forward run and the gradient."""
     import numpy as np
     import dataclasses
     run = dict(case.run)
@@ -247,12 +275,13 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
     w[case.observable["J_component"], torch.as_tensor(idx).cuda()] = 1.0 / len(idx)
     for _ in range(warmup):
         pr.forward(th)
-        pr.backward(w)
+        pr.backward(w, recompute=True)
     torch.cuda.synchronize()
     breakdown, dominant = {}, None
     if profile:
-        # one more (untimed) step with events around every launch: the
-        # per-kernel breakdown, and the dominant kernel class by total time
+        # one more (untimed) forward + reverse without the re-run, with events
+        # around every launch: the per-kernel breakdown of one inner step
+        # forward and in reverse, and the dominant kernel class by total time
         B.sph_profile_classes(pr.nb, None)
         B.sph_profile_enable(pr.nb, True)
         pr.forward(th)
@@ -274,17 +303,31 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True):
         torch.cuda.synchronize()
         t_fwd += time.perf_counter() - ta
         total_inner += int(pr.last["k"].sum())
-        g = pr.backward(w)
+        g = pr.backward(w, recompute=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = B.sph_profile_read(pr.nb) if profile else {}
     B.sph_profile_enable(pr.nb, False)
     B.sph_profile_classes(pr.nb, None)
+    # the same step with the inner states kept from the forward run (no
+    # re-run): the forward + reverse cost of one inner step
+    t_taped = 0.0
+    if taped_steps:
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(taped_steps):
+            pr.forward(th)
+            pr.backward(w)
+        torch.cuda.synchronize()
+        t_taped = (time.perf_counter() - ta) / taped_steps
     rc, bits = B.sph_status(pr.nb)
     u = pr.st.u.detach().double().cpu().numpy()
     info = dict(n=pr.nb.info.n, pairs=pr.nb.info.n_pairs, dim=pr.nb.info.dim,
                 n_colors=pr.nb.info.n_colors, total_inner=total_inner, seconds=t1 - t0,
-                seconds_forward=t_fwd, status=bits, grad=g.cpu().numpy(),
+                seconds_forward=t_fwd, seconds_taped_step=t_taped,
+                damping_passes=int(sum(1 for k in range(8) if pr.nb.info.color_off[k + 1] >
+                                       pr.nb.info.color_off[k])),
+                status=bits, grad=g.cpu().numpy(),
                 J=float((pr.st.u * w).sum().item()), u=u,
                 u_finite=bool(np.isfinite(u).all()), tuning=tuning, breakdown=breakdown,
                 dominant=dominant)
@@ -304,7 +347,7 @@ def run_coupled(case, torch, B, reps=10):
     run = dict(case.run)
     run.update(n_slow=1, fixed_inner=200)
     B.sph_advance_multirate(nb, mat, st, B.multirate_cfg(**run, chunk=200, use_graph=0))
-    Dc, dtd, cbc = run["D"], 0.5 * case.h ** 2 / run["D"], run["c_bc"]
+    Dc, dtd, cbc = run["D"], B.sph_default_steps(case.h, mat, run["D"])[1], run["c_bc"]
     c_keep = st.c.clone()
     variants = {
         "reference": lambda: B.sph_diffusion_step(nb, mat, st, Dc, dtd, cbc),
@@ -352,9 +395,7 @@ def run_necking(name, prec, n_slow, torch, B, record_every=100):
     finally:
         r.close()
     h = res["history"]
-    m = c.material
-    K = m["E"] / (3.0 * (1.0 - 2.0 * m["nu"]))
-    dt_s = 0.6 * c.h / (K / m["rho0"]) ** 0.5
+    dt_s = B.sph_default_steps(c.h, B.material(**c.material))[0]
     t_end = c.run["dt_slow"] * c.run["n_slow"]
     ipk = int(np.argmax(h["reaction"]))
     stride = max(1, len(h["increment"]) // 20)
@@ -426,16 +467,16 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
     return dict(GBps=2.0 * nbytes / s / 1e9, bytes=nbytes, note="read + write of a 1 GiB copy")
 
 
-def run_full_adjoint(case, torch, B, A, n_slow=50, inner=1000):
+def run_full_adjoint(case, torch, B, A, n_slow=50, inner=1000, with_fp64=False):
     """The whole checkpointed adjoint run of the plate: `n_slow` diffusion
     slow steps x `inner` inner steps forward (one checkpoint per slow step,
     the inner states of the last one), then the reverse pass, which re-runs
     each earlier slow step from its checkpoint to record its inner states.
-    FP32, then FP64 for the gradient's error."""
-    import numpy as np
+    FP32, and with `with_fp64` FP64 for the gradient's error."""
     import dataclasses
     out = {}
-    for prec, tag in ((B.SPH_F32, "f32"), (B.SPH_F64, "f64")):
+    precs = ((B.SPH_F32, "f32"), (B.SPH_F64, "f64")) if with_fp64 else ((B.SPH_F32, "f32"),)
+    for prec, tag in precs:
         run = dict(case.run)
         run.update(n_slow=n_slow, fixed_inner=inner)
         c = dataclasses.replace(case, run=run)
@@ -460,11 +501,13 @@ def run_full_adjoint(case, torch, B, A, n_slow=50, inner=1000):
         out[tag] = dict(seconds_forward=t1 - t0, seconds_reverse=t2 - t1, inner_steps=total_inner,
                         interactions_per_s=pr.nb.info.n_pairs * total_inner / (t2 - t0), J=J,
                         grad={B.GRAD_NAMES[i]: float(g[i]) for i in (B.SPH_GRAD_E, B.SPH_GRAD_D,
-                                                                      B.SPH_GRAD_C)})
+                                                                      B.SPH_GRAD_C)},
+                        grad_finite=bool(all(abs(x) < float("inf") for x in g)))
         pr.close()
-    out["grad_rel_err_f32"] = {k: abs(out["f32"]["grad"][k] - out["f64"]["grad"][k]) /
-                               abs(out["f64"]["grad"][k]) for k in out["f64"]["grad"]}
-    out["J_rel_err_f32"] = abs(out["f32"]["J"] - out["f64"]["J"]) / abs(out["f64"]["J"])
+    if with_fp64:
+        out["grad_rel_err_f32"] = {k: abs(out["f32"]["grad"][k] - out["f64"]["grad"][k]) /
+                                   abs(out["f64"]["grad"][k]) for k in out["f64"]["grad"]}
+        out["J_rel_err_f32"] = abs(out["f32"]["J"] - out["f64"]["J"]) / abs(out["f64"]["J"])
     out["workload"] = (f"plate3d {case.shape[0]}x{case.shape[1]}x{case.shape[2]}, {n_slow} diffusion slow steps x "
                        f"{inner} inner steps, forward with checkpoints, then the reverse pass "
                        f"(d mean centre deflection / d(E, D, C))")
@@ -519,7 +562,7 @@ def run_sweep(torch, B, launches=2):
     st.flags = dev(bt.flags[perm])
     c0 = dev(bt.c_init[perm]).float()
     grad = torch.zeros((len(bt.cases), B.SPH_NGRAD), dtype=torch.float64, device="cuda")
-    batch = B.SphBatch(bt.E, bt.D, bt.dt_s, bt.dt_slow, grad=grad)
+    batch = B.SphBatch(bt.E, bt.D, grad=grad)      # per-specimen steps: the library's
     run = dict(bt.run)
     cfg = B.multirate_cfg(**run, batch=batch)
     mat = B.material(**bt.material)
@@ -531,7 +574,8 @@ def run_sweep(torch, B, launches=2):
     for i, c in enumerate(bt.cases):
         j = bt.offsets[i] + c.observable["J_index"]
         w[1, torch.as_tensor(inv[j]).cuda()] = 1.0 / len(j)
-    B.sph_autotune(nb, mat, st, run["eta"], float(bt.dt_s.min()), with_adjoint=True)
+    dt_min = min(B.sph_default_steps(bt.h, B.material(**dict(bt.material, E=E)))[0] for E in bt.E)
+    B.sph_autotune(nb, mat, st, run["eta"], dt_min, with_adjoint=True)
 
     def launch():
         st.u.zero_()
@@ -582,8 +626,10 @@ def main():
                          "of the 3D one; full = both full runs")
     ap.add_argument("--no-neck3d", action="store_true", help="skip the neck3d, bar2d and strip2d runs")
     ap.add_argument("--full-adjoint", action="store_true",
-                    help="also run the whole checkpointed adjoint (50 slow x 1000 inner steps) in FP32 "
-                         "and FP64")
+                    help="run the whole checkpointed adjoint (50 slow x 1000 inner steps) in FP64 as "
+                         "well as in FP32 (the FP32 run is in the default bench)")
+    ap.add_argument("--no-full-adjoint", action="store_true",
+                    help="skip the whole checkpointed adjoint run")
     ap.add_argument("--necking-compare", action="store_true",
                     help="run each necking case in FP32 and in FP64 and report how far the FP32 "
                          "curves deviate")
@@ -612,6 +658,12 @@ def main():
     ms_per_step = 1000.0 * adj32["seconds"] / args.steps
     fwd32 = dict(value=P * adj32["total_inner"] / adj32["seconds_forward"],
                  ms_per_step=1000.0 * adj32["seconds_forward"] / args.steps)
+    taped = None
+    if adj32["seconds_taped_step"] > 0:
+        taped = dict(value=P * args.inner / adj32["seconds_taped_step"],
+                     ms_per_step=1000.0 * adj32["seconds_taped_step"],
+                     note="forward + reverse of one slow step with the inner states kept from the "
+                          "forward run (no re-run); measured after the timed region")
 
     fp64 = None
     accuracy = None
@@ -640,24 +692,45 @@ def main():
     nper = adj32["n"]
     workload_key = f"plate3d-{args.nx}x{args.nx}x4-fp32"
     copy_bw = copy_bandwidth(torch)
-    roofline = roofline_of(kern, prof32, adj32["dim"], nper, P, adj32["n_colors"], workload_key)
+    npass = adj32["damping_passes"]
+    roofline = roofline_of(kern, prof32, adj32["dim"], nper, P, adj32["n_colors"], workload_key,
+                           passes=npass)
     roofline.update(copy_GBps=copy_bw["GBps"])
     if roofline["bound"] == "hbm":
         roofline["frac_of_copy"] = roofline["achieved"] / copy_bw["GBps"]
-    # the damping pass beside it, from the profiled step (HBM view)
+    # the damping sweep beside it, from the profiled step (HBM view, per
+    # sweep: v read and written once, the inverse mass read once)
     damping_view = None
     if kern != "damping" and adj32["breakdown"].get("damping", (0, 0))[0]:
         damping_view = roofline_of("damping", adj32["breakdown"], adj32["dim"], nper, P,
-                                   adj32["n_colors"], workload_key)
+                                   adj32["n_colors"], workload_key, passes=npass)
         damping_view["frac_of_copy"] = damping_view["achieved"] / copy_bw["GBps"]
+        damping_view["passes_per_sweep"] = npass
+        damping_view["per"] = "sweep (all colour passes)"
         damping_view["measured"] = "the profiled step outside the timed region"
+    # the whole inner step, forward + reverse, against the algorithmic totals
+    # of the path: 883 B per particle (276 forward, 2.2x that in reverse) and
+    # 321 flop per directed pair (107 forward, 2x that in reverse)
+    whole_step = None
+    if taped:
+        t_inner = adj32["seconds_taped_step"] / args.inner
+        hbm = 883.0 * nper / t_inner / 1e9
+        alu = 321.0 * P / t_inner / 1e12
+        whole_step = dict(us_per_inner_step=1e6 * t_inner, bytes_per_particle=883, flops_per_pair=321,
+                          hbm_GBps=hbm, hbm_frac=hbm / HBM_PEAK_GBS, fp32_TFLOPs=alu,
+                          fp32_frac=alu / FP32_PEAK_TFLOPS,
+                          note="forward + reverse inner step (taped step / inner steps) against the "
+                               "algorithmic bytes and flops of the path")
     kernels = {}
     for k, (c, ms) in adj32["breakdown"].items():
         if not c:
             continue
         kernels[k] = dict(launches=c, avg_us=1000.0 * ms / c, total_ms=ms)
         ab = algorithmic_bytes(k, adj32["dim"], 4) * nper
-        if ab:
+        if ab and k in ("damping", "adj_damping"):
+            kernels[k]["avg_us_per_sweep"] = 1000.0 * ms / (c / npass)
+            kernels[k]["alg_GBps"] = ab / (ms / 1000.0 / (c / npass)) / 1e9
+        elif ab:
             kernels[k]["alg_GBps"] = ab / (ms / 1000.0 / c) / 1e9
         fl = flops_per_pair(k, adj32["dim"]) * P
         if fl:
@@ -702,7 +775,10 @@ def main():
                     final_neck_fp32=r32["final_neck_displacement"],
                     final_neck_fp64=r64["final_neck_displacement"])
 
-    full_adjoint = run_full_adjoint(case, torch, B, A) if args.full_adjoint else None
+    full_adjoint = None
+    if not args.no_full_adjoint:
+        full_adjoint = run_full_adjoint(case, torch, B, A, inner=args.inner, with_fp64=args.full_adjoint)
+        print("[bench] whole checkpointed adjoint done", flush=True)
 
     small = None if args.no_neck3d else run_small_configs(torch, B)
     if small:
@@ -744,14 +820,21 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"plate3d {args.nx}x{args.nx}x4 membrane ({adj32['n']} particles, {P} directed "
-                        f"pairs), neo-Hookean + fluid pressure; per step one diffusion slow step + "
-                        f"{args.inner} inner steps forward (taped), then the reverse pass for "
-                        f"d(mean centre deflection)/d(E, D, C); FP32 bulk / FP64 displacement",
+                        f"pairs), neo-Hookean + fluid pressure, checkpointed adjoint; per step one "
+                        f"slow step of it: a diffusion slow step + {args.inner} inner steps forward, "
+                        f"then its reverse pass (the slow step re-run from its checkpoint with u "
+                        f"recorded, {args.inner} transposed inner steps, the transposed diffusion "
+                        f"step) for d(mean centre deflection)/d(E, D, C); FP32 bulk / FP64 "
+                        f"displacement",
+            "headline": "per slow step of the 50 x 1000 checkpointed adjoint, re-run included; "
+                        "full_adjoint times the whole run",
             "adjoint": True,
             "parallelism": "single GPU",
         },
         "roofline": roofline,
         "roofline_damping": damping_view,
+        "whole_step": whole_step,
+        "taped_step": taped,
         "kernels": kernels,
         "kernels_measured": "one profiled step after the warmup, outside the timed region (HIP events "
                             "around every launch, around every sweep for the damping classes, whose "

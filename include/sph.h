@@ -180,10 +180,12 @@ typedef struct {
  *      are stably sorted by cell key (x fastest); lists are in ascending
  *      sorted position.
  *   Damping schedule: each unordered pair is anchored at the componentwise
- *   minimum of its two cells and coloured by the parity of that anchor
- *   (2^dim colours, so anchors of one colour touch disjoint 2^dim-cell blocks);
- *   within an anchor, pairs in ascending (a, b) take the smallest level not
- *   used by an earlier pair sharing a particle.
+ *   minimum of its two cells, except along an axis only two cells deep, where
+ *   the anchor takes the first cell (the block then spans that axis, and the
+ *   colours odd along it stay empty); the pair is coloured by the parity of
+ *   its anchor (2^dim colours, so anchors of one colour touch disjoint
+ *   2^dim-cell blocks); within an anchor, pairs in ascending (a, b) take the
+ *   smallest level not used by an earlier pair sharing a particle.
  *   Synchronous.  On success *out receives a new handle.
  *   Errors: SPH_E_ARG, SPH_E_UNSUPPORTED (dim not 2/3), SPH_E_CAPACITY (more
  *   than 2^32-16 cells, 2^31 pairs, or an anchor block too dense for the level
@@ -422,7 +424,9 @@ int sph_build_neighbors_batched(int dim, int64_t n, const double* X, const doubl
 
 /* Per-specimen values that replace the uniform ones of sph_material (E) and
  * sph_multirate_cfg (D, dt_s, dt_slow) when cfg->batch is set.  Host arrays of
- * n_spec doubles, copied to the device at the start of each run.  The other
+ * n_spec doubles, copied to the device at the start of each run; dt_s and
+ * dt_slow may be NULL, and entries <= 0 take each specimen's
+ * sph_default_steps (the diffusion step from its own D).  The other
  * material and schedule values are shared by all specimens.  A batched run
  * needs fixed inner counts (fixed_inner or k_sched): one specimen's kinetic
  * energy does not decide another's stop.  `grad` (device [n_spec][SPH_NGRAD],
@@ -473,6 +477,17 @@ int sph_autotune(sph_nbr* nbr, const sph_material* mat, const sph_state* st, dou
                  double dt_s, int with_adjoint, sph_tuning* out, void* stream);
 int sph_set_tuning(sph_nbr* nbr, int prec, const sph_tuning* tuning);
 int sph_get_tuning(const sph_nbr* nbr, int prec, sph_tuning* tuning);
+
+/* Step sizes of Sec. 4.1 for smoothing length h and a material: the fast
+ * (stress-relaxation) step of eq. (dts-advection) at rest, where only the
+ * sound-speed term remains,
+ *   dt_s = 0.6 h / sqrt(K / rho0),  K = E / (3 (1 - 2 nu))  (eq. relation-modulus),
+ * and the explicit diffusion step dt_d = 0.5 h^2 / D (0 for D <= 0).  These
+ * are the defaults sph_advance_multirate takes for cfg->dt_s <= 0 and
+ * cfg->dt_slow <= 0, and the per-specimen defaults of sph_batch.  Host
+ * outputs (either may be NULL); a pure host computation, no device call.
+ * Errors: SPH_E_ARG (h <= 0, E <= 0, rho0 <= 0 or nu >= 1/2). */
+int sph_default_steps(double h, const sph_material* mat, double D, double* dt_s, double* dt_d);
 
 /* Synchronise `stream` and return (and clear) the latched status bits in
  * *status_bits (may be NULL): SPH_OK, or SPH_E_NUMERIC if any bit was set. */

@@ -19,7 +19,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sph_oracle.c")
-_LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_cs.so")}
+_LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_cs.so"),
+         "omp": os.path.join(_HERE, "liboracle_omp.so")}
 
 LE, NH, J2 = 0, 1, 2
 LOAD, DIFFUSION, DIFFUSION_COUPLED = 0, 1, 2
@@ -27,20 +28,25 @@ FIXED, CDIR, GRIP = 1, 2, 4
 
 
 def build(force: bool = True) -> None:
-    """Compile both oracle variants with gcc (no FMA contraction)."""
-    for cplx, out in _LIBS.items():
+    """Compile the oracle variants with gcc (no FMA contraction): the plain
+    FP64 oracle, the complex-step one, and the OpenMP build that only the
+    all-core CPU baseline of the benchmark loads."""
+    for kind, out in _LIBS.items():
         if not force and os.path.exists(out) and os.path.getmtime(out) > os.path.getmtime(_SRC):
             continue
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-o", out, _SRC, "-lm"]
-        if cplx:
+        if kind is True:
             cmd.insert(1, "-DORC_COMPLEX")
+        elif kind == "omp":
+            cmd.insert(1, "-fopenmp")
         subprocess.run(cmd, check=True)
 
 
 _cache: dict = {}
 
 
-def _lib(cplx: bool):
+def _lib(cplx):
+    """cplx: False (FP64), True (complex step) or "omp" (FP64, OpenMP)."""
     if cplx in _cache:
         return _cache[cplx]
     path = _LIBS[cplx]
@@ -60,7 +66,8 @@ def _lib(cplx: bool):
     lib.orc_get_build.argtypes = [vp] * 9
     lib.orc_get_schedule.argtypes = [vp] * 8
     lib.orc_constitutive.restype = i32
-    lib.orc_constitutive.argtypes = [vp, vp, vp, _real_t(cplx), vp]
+    cplx_t = cplx is True
+    lib.orc_constitutive.argtypes = [vp, vp, vp, _real_t(cplx_t), vp]
     lib.orc_displacement_gradient.argtypes = [vp, vp, vp]
     lib.orc_stress.restype = i32
     lib.orc_stress.argtypes = [vp] * 7
@@ -69,12 +76,13 @@ def _lib(cplx: bool):
     lib.orc_solid_step.restype = i32
     lib.orc_solid_step.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.orc_damping_sweep.argtypes = [vp, dbl, dbl, dbl, vp, vp, dbl, vp]
-    lib.orc_drift_ke.restype = _real_t(cplx)
+    lib.orc_drift_ke.restype = _real_t(cplx_t)
     lib.orc_drift_ke.argtypes = [vp, dbl, dbl, vp, vp, vp, dbl, vp]
     lib.orc_load_step.argtypes = [vp, dbl, vp, vp, vp]
-    lib.orc_diffusion_step.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, vp, vp, vp, vp]
-    lib.orc_diffusion_step_coupled.argtypes = [vp, _real_t(cplx), dbl, dbl, _real_t(cplx), dbl, C.c_int,
+    lib.orc_diffusion_step.argtypes = [vp, _real_t(cplx_t), dbl, dbl, _real_t(cplx_t), dbl, vp, vp, vp, vp]
+    lib.orc_diffusion_step_coupled.argtypes = [vp, _real_t(cplx_t), dbl, dbl, _real_t(cplx_t), dbl, C.c_int,
                                                vp, vp, vp, vp, vp]
+    lib.orc_default_steps.argtypes = [vp, vp, dbl, vp, vp]
     lib.orc_advance.restype = i32
     lib.orc_advance.argtypes = [vp] * 16
     _cache[cplx] = lib
@@ -124,9 +132,11 @@ def _ptr(a):
 class Oracle:
     """One particle set: build (grid, sort, neighbours, B0, schedule) + steps."""
 
-    def __init__(self, dim, X_id, V_id, h, complex_step=False):
+    def __init__(self, dim, X_id, V_id, h, complex_step=False, openmp=False):
         self.cplx = bool(complex_step)
-        self.lib = _lib(self.cplx)
+        if openmp and self.cplx:
+            raise ValueError("the OpenMP build is FP64 only")
+        self.lib = _lib("omp" if openmp else self.cplx)
         self.dtype = np.complex128 if self.cplx else np.float64
         X_id = np.ascontiguousarray(X_id, dtype=np.float64)
         V_id = np.ascontiguousarray(V_id, dtype=np.float64)
@@ -207,6 +217,12 @@ class Oracle:
     @staticmethod
     def _from_real(x):
         return complex(x.re, x.im) if isinstance(x, _Cplx) else x
+
+    def default_steps(self, mat, D=0.0):
+        """(dt_s, dt_d) of Sec. 4.1 for this particle set and material."""
+        a, b = C.c_double(0), C.c_double(0)
+        self.lib.orc_default_steps(self._h, C.byref(mat), float(D), C.byref(a), C.byref(b))
+        return a.value, b.value
 
     # -- kernel ---------------------------------------------------------
     def W(self, r):

@@ -40,6 +40,12 @@
  *
  * Readings where the paper is silent or garbled are listed in the design
  * notes of the repository and restated at each use below.
+ *
+ * The OpenMP pragmas matter only to a third build, `liboracle_omp.so`
+ * (-fopenmp), which the benchmark times as its all-core CPU baseline: they
+ * split per-particle loops (each particle's sums stay in one thread, in the
+ * same order) and the anchors of one damping colour (disjoint particles),
+ * so that build computes the same values.  The checked builds ignore them.
  */
 #include "sph_oracle.h"
 
@@ -695,6 +701,7 @@ int orc_constitutive(const orc_material* m, const real* H, real* pl, real p, rea
 void orc_displacement_gradient(const orc_sys* s, const real* u, real* H9) {
   int d = s->dim;
   int64_t n = s->n;
+#pragma omp parallel for schedule(static)
   for (int64_t a = 0; a < n; ++a) {
     real G[9] = {0};
     for (int64_t j = s->nbr_off[a]; j < s->nbr_off[a + 1]; ++j) {
@@ -723,6 +730,7 @@ int orc_stress(const orc_sys* s, const orc_material* m, const real* H9, real* pl
   int d = s->dim;
   int64_t n = s->n;
   int rc = 0;
+#pragma omp parallel for schedule(static) reduction(min : rc)
   for (int64_t a = 0; a < n; ++a) {
     real F[9], P[9], pl[7];
     for (int i = 0; i < 9; ++i) F[i] = H9[i * n + a];
@@ -794,6 +802,7 @@ void orc_mixture_flux(const orc_sys* s, const orc_material* m, const real* H9, c
 void orc_momentum(const orc_sys* s, const orc_material* m, const real* PB, const real* c, real* acc) {
   int d = s->dim;
   int64_t n = s->n;
+#pragma omp parallel for schedule(static)
   for (int64_t a = 0; a < n; ++a) {
     real f[3] = {0, 0, 0};
     for (int64_t j = s->nbr_off[a]; j < s->nbr_off[a + 1]; ++j) {
@@ -839,31 +848,44 @@ int orc_solid_step(const orc_sys* s, const orc_material* m, double dt, const rea
  * (v_a' - v_b') with beta = 2 eta V_a V_b (dW/dr / r) dt <= 0, solved in
  * closed form so that the pair momentum is conserved.  A constrained particle
  * acts as infinite mass.  Pairs are taken in the canonical schedule order. */
-void orc_damping_sweep(const orc_sys* s, double rho0, double eta, double dt, real* v,
-                       const uint8_t* flags, double rho_l0, const real* c) {
+static void damp_pair(const orc_sys* s, int64_t i, double rho0, double eta, double dt, real* v,
+                      const uint8_t* flags, double rho_l0, const real* c) {
   int d = s->dim;
   int64_t n = s->n;
-  for (int64_t i = 0; i < s->n_upairs; ++i) {
-    int64_t a = s->pa[i], b = s->pb[i];
-    int fa = flags ? (flags[a] & ORC_FIXED) : 0;
-    int fb = flags ? (flags[b] & ORC_FIXED) : 0;
-    if (fa && fb) continue;
-    double gw[3];
-    double w = pair_w(s, a, b, gw);
-    double beta = 2.0 * eta * s->V[a] * s->V[b] * w * dt;
-    real ma = mix_rho(rho0, rho_l0, c, a) * s->V[a], mb = mix_rho(rho0, rho_l0, c, b) * s->V[b];
-    for (int k = 0; k < d; ++k) {
-      real va = v[k * n + a], vb = v[k * n + b];
-      if (!fa && !fb) {
-        real delta = beta * (va - vb) / (ma * mb - beta * (ma + mb));
-        v[k * n + a] = va + mb * delta;
-        v[k * n + b] = vb - ma * delta;
-      } else if (fb) {
-        v[k * n + a] = va + beta * (va - vb) / (ma - beta);
-      } else {
-        v[k * n + b] = vb + beta * (vb - va) / (mb - beta);
-      }
+  int64_t a = s->pa[i], b = s->pb[i];
+  int fa = flags ? (flags[a] & ORC_FIXED) : 0;
+  int fb = flags ? (flags[b] & ORC_FIXED) : 0;
+  if (fa && fb) return;
+  double gw[3];
+  double w = pair_w(s, a, b, gw);
+  double beta = 2.0 * eta * s->V[a] * s->V[b] * w * dt;
+  real ma = mix_rho(rho0, rho_l0, c, a) * s->V[a], mb = mix_rho(rho0, rho_l0, c, b) * s->V[b];
+  for (int k = 0; k < d; ++k) {
+    real va = v[k * n + a], vb = v[k * n + b];
+    if (!fa && !fb) {
+      real delta = beta * (va - vb) / (ma * mb - beta * (ma + mb));
+      v[k * n + a] = va + mb * delta;
+      v[k * n + b] = vb - ma * delta;
+    } else if (fb) {
+      v[k * n + a] = va + beta * (va - vb) / (ma - beta);
+    } else {
+      v[k * n + b] = vb + beta * (vb - va) / (mb - beta);
     }
+  }
+}
+
+/* The pairs are stored in the canonical order: colour by colour, anchor by
+ * anchor, each anchor's pairs in sequence.  Anchors of one colour touch
+ * disjoint particles, so an OpenMP build (the all-core timing baseline only)
+ * may take them in parallel and still performs the same operations on the
+ * same values; the plain build runs the loops in order. */
+void orc_damping_sweep(const orc_sys* s, double rho0, double eta, double dt, real* v,
+                       const uint8_t* flags, double rho_l0, const real* c) {
+  for (int col = 0; col < 8; ++col) {
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t ai = s->color_off[col]; ai < s->color_off[col + 1]; ++ai)
+      for (int64_t i = s->aoff[ai]; i < s->aoff[ai + 1]; ++i)
+        damp_pair(s, i, rho0, eta, dt, v, flags, rho_l0, c);
   }
 }
 
@@ -1035,17 +1057,29 @@ void orc_diffusion_step_coupled(const orc_sys* s, real D, double dt_d, double c_
   free(H9);
 }
 
-/* Multi-time-step driver, Sec. 4.2.  Defaults: dt_s = 0.6 h / c_s with
- * c_s = sqrt(K/rho0) evaluated once at rest (eq. dts-advection with |v| = 0);
- * diffusion step 0.5 h^2 / D; k_max = k0 = floor(dt_slow/dt_s) + 1. */
+/* Step sizes of Sec. 4.1.  The fast step follows eq. (dts-advection) at
+ * rest: with |v| = 0 and no acceleration yet only the sound-speed term
+ * remains, dt_s = 0.6 h / c_s with c_s = sqrt(K / rho0) and K the bulk
+ * modulus of eq. (relation-modulus).  The diffusion step is the stability
+ * bound 0.5 h^2 / D stated beside it (0 when D <= 0: no diffusion). */
+void orc_default_steps(const orc_sys* s, const orc_material* m, double D, double* dt_s,
+                       double* dt_d) {
+  double K = RE(m->E) / (3.0 * (1.0 - 2.0 * m->nu));
+  if (dt_s) *dt_s = 0.6 * s->h / sqrt(K / m->rho0);
+  if (dt_d) *dt_d = D > 0.0 ? 0.5 * s->h * s->h / D : 0.0;
+}
+
+/* Multi-time-step driver, Sec. 4.2.  Defaults: the steps of
+ * orc_default_steps; k_max = k0 = floor(dt_slow/dt_s) + 1. */
 int orc_advance(const orc_sys* s, const orc_material* m, const orc_cfg* cfg, real* u, real* v,
                 real* plastic, real* c, real* q, real* p, const real* vgrip,
                 const uint8_t* flags, const int64_t* k_sched, int64_t* k_out, double* ke_out,
                 int32_t* conv_out, real* acc_out) {
-  double K = RE(m->E) / (3.0 * (1.0 - 2.0 * m->nu));
-  double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * s->h / sqrt(K / m->rho0);
+  double dt_rest, dt_diff;
+  orc_default_steps(s, m, RE(cfg->D), &dt_rest, &dt_diff);
+  double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : dt_rest;
   double dt_slow = cfg->dt_slow;
-  if (cfg->slow_kind != ORC_LOAD && !(dt_slow > 0.0)) dt_slow = 0.5 * s->h * s->h / RE(cfg->D);
+  if (cfg->slow_kind != ORC_LOAD && !(dt_slow > 0.0)) dt_slow = dt_diff;
   int64_t k_max = cfg->k_max > 0 ? cfg->k_max : (int64_t)floor(dt_slow / dt_s) + 1;
   int adaptive = (k_sched == NULL && cfg->fixed_inner <= 0);
   int warn = 0, rc = 0;

@@ -113,6 +113,10 @@ void orc_diffusion_step(const orc_sys* s, real D, double dt_d, double c_bc, real
 void orc_diffusion_step_coupled(const orc_sys* s, real D, double dt_d, double c_bc, real C_swell,
                                 double c0, int nonlinear, const real* u, real* c, real* q, real* p,
                                 const uint8_t* flags);
+/* step sizes of Sec. 4.1: dt_s = 0.6 h / sqrt(K / rho0) (eq. dts-advection at
+   rest) and dt_d = 0.5 h^2 / D (0 for D <= 0); either output may be NULL */
+void orc_default_steps(const orc_sys* s, const orc_material* m, double D, double* dt_s,
+                       double* dt_d);
 /* multi-time-step driver; k_sched (optional) freezes the inner counts;
    acc_out (optional, [d][n]) receives the momentum sum per unit mass of the
    last inner step, fixed particles included (their reaction) */

@@ -40,11 +40,13 @@ class MultirateProblem:
         if case.vgrip is not None:
             self.st.vgrip = dev(case.vgrip[:, self.perm], self.T)
         self.c_init = dev(case.c_init[self.perm], self.T) if self.diff else None
-        m, r = case.material, dict(case.run)
-        K = m["E"] / (3.0 * (1.0 - 2.0 * m["nu"]))
-        r["dt_s"] = r.get("dt_s") or 0.6 * case.h / np.sqrt(K / m["rho0"])
+        r = dict(case.run)
+        # the schedule is frozen at the library's own step sizes (Sec. 4.1)
+        # for the nominal parameters
+        dt_s, dt_d = B.sph_default_steps(case.h, B.material(**case.material), r.get("D", 0.0))
+        r["dt_s"] = r.get("dt_s") or dt_s
         if self.diff and not r.get("dt_slow"):
-            r["dt_slow"] = 0.5 * case.h ** 2 / r["D"]
+            r["dt_slow"] = dt_d
         self.run = r
         self.chunk, self.use_graph = chunk, use_graph
         self.k_sched = None
@@ -69,10 +71,11 @@ class MultirateProblem:
         m.update(E=th[0], C_swell=th[2], sigma0=th[3], sigma_inf=th[4], delta=th[5], H=th[6])
         return B.material(**m)
 
-    def _cfg(self, th):
+    def _cfg(self, th, k_sched=None):
         r = dict(self.run)
         r["D"] = th[1]
-        return B.multirate_cfg(**r, chunk=self.chunk, use_graph=self.use_graph, k_sched=self.k_sched)
+        ks = self.k_sched if k_sched is None else k_sched
+        return B.multirate_cfg(**r, chunk=self.chunk, use_graph=self.use_graph, k_sched=ks)
 
     # -- runs --------------------------------------------------------------------
     def reset(self):
@@ -87,35 +90,52 @@ class MultirateProblem:
             st.q.zero_()
             st.p.zero_()
 
-    def forward(self, theta, record=True):
-        """Run from the initial state with parameters theta; returns the final
-        u (a view of the state: clone it to keep it)."""
+    def forward(self, theta, record=True, k_sched=None):
+        """Run from the initial state with parameters theta (and, if given,
+        these inner counts instead of the problem's); returns the final u (a
+        view of the state: clone it to keep it)."""
         th = np.asarray(theta, dtype=np.float64)
         self.reset()
-        rc, k, ke, conv, rep = B.sph_advance_multirate(self.nb, self._material(th), self.st, self._cfg(th),
+        cfg = self._cfg(th, k_sched)
+        rc, k, ke, conv, rep = B.sph_advance_multirate(self.nb, self._material(th), self.st, cfg,
                                                        tape=self.tape if record else None)
         self._fwd_id += 1
         if record:
             self._tape_id = self._fwd_id
-        self.last = dict(rc=rc, k=k.copy(), ke=ke.copy(), conv=conv.copy(), theta=th.copy())
+        self.last = dict(rc=rc, k=k.copy(), ke=ke.copy(), conv=conv.copy(), theta=th.copy(),
+                         k_sched=None if k_sched is None else np.array(k_sched))
         return self.st.u
 
     def freeze(self):
         """Fix the inner counts to those of the last forward run."""
         self.k_sched = self.last["k"].copy()
 
-    def backward(self, u_bar, v_bar=None):
+    def backward(self, u_bar, v_bar=None, recompute=False):
         """d(objective)/d(theta) given the objective's derivative with respect
-        to the final u (and v).  Requires the last forward run to be taped."""
+        to the final u (and v).  Requires the last forward run to be taped.
+        recompute: re-run every slow step from its checkpoint, also the last
+        one, whose inner states the forward run kept (the cost of a slow step
+        in a long checkpointed run)."""
         if self._tape_id != self._fwd_id:
             raise RuntimeError("the last forward run was not recorded")
+        if recompute:
+            self.tape.forget_inner_states()
         th = self.last["theta"]
         a = self.adj.zero_()
         a.u.copy_(u_bar)
         if v_bar is not None:
             a.v.copy_(v_bar)
-        B.sph_advance_multirate_backward(self.nb, self._material(th), self.st, self._cfg(th), self.tape, a)
+        B.sph_advance_multirate_backward(self.nb, self._material(th), self.st,
+                                         self._cfg(th, self.last["k_sched"]), self.tape, a)
         return a.grad.clone()
+
+    def _ensure_taped(self, fwd_id, theta, k):
+        """Make the tape hold forward run `fwd_id` (theta, inner counts k):
+        when a later run has replaced it, the same run is recorded again (the
+        forward pass is deterministic, so it is the same run)."""
+        if self._tape_id == fwd_id:
+            return
+        self.forward(theta, record=True, k_sched=k)
 
     def close(self):
         self.nb.close()
@@ -131,10 +151,15 @@ def _function():
         def forward(ctx, theta, problem):
             ctx.problem = problem
             ctx.theta_meta = (theta.dtype, theta.device)
-            return problem.forward(theta.detach().double().cpu().numpy()).clone()
+            u = problem.forward(theta.detach().double().cpu().numpy()).clone()
+            # which run this is: the reverse pass must differentiate this run,
+            # even if the problem has run again (another theta) since
+            ctx.fwd = (problem._fwd_id, problem.last["theta"].copy(), problem.last["k"].copy())
+            return u
 
         @staticmethod
         def backward(ctx, u_bar):
+            ctx.problem._ensure_taped(*ctx.fwd)
             g = ctx.problem.backward(u_bar.contiguous().double())
             dt, dv = ctx.theta_meta
             return g.to(device=dv, dtype=dt), None

@@ -31,7 +31,7 @@ EXPORTED = [
     "sph_diffusion_step_vjp", "sph_diffusion_step_coupled_vjp", "sph_advance_multirate_backward",
     "sph_constitutive",
     "sph_constitutive_vjp", "sph_build_neighbors_batched", "sph_advance_multirate_graph",
-    "sph_autotune", "sph_set_tuning", "sph_get_tuning",
+    "sph_autotune", "sph_set_tuning", "sph_get_tuning", "sph_default_steps",
 ]
 SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load",
                     "adj_stress", "adj_gather", "adj_damping"]
@@ -154,6 +154,7 @@ def lib():
                                C.POINTER(Tuning), vp]
     L.sph_set_tuning.argtypes = [vp, C.c_int, C.POINTER(Tuning)]
     L.sph_get_tuning.argtypes = [vp, C.c_int, C.POINTER(Tuning)]
+    L.sph_default_steps.argtypes = [dbl, C.POINTER(Material), dbl, C.POINTER(dbl), C.POINTER(dbl)]
     L.sph_status.argtypes = [vp, vp, C.POINTER(i32)]
     L.sph_profile_enable.argtypes = [vp, C.c_int]
     L.sph_profile_classes.argtypes = [vp, C.c_uint32]
@@ -337,6 +338,13 @@ def new_state(nbr, prec, with_plastic=False, with_diffusion=False, with_acc=Fals
     return st
 
 
+def sph_default_steps(h, mat, D=0.0):
+    """(dt_s, dt_d): the library's step sizes of Sec. 4.1 (host computation)."""
+    a, b = dbl(0.0), dbl(0.0)
+    _check(lib().sph_default_steps(float(h), C.byref(mat), float(D), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
 def sph_solid_relax_step(nbr, mat, st, dt_s, stream=None):
     cs = st.cstruct(nbr)
     _check(lib().sph_solid_relax_step(nbr.handle, C.byref(mat), C.byref(cs), float(dt_s), _stream(stream)))
@@ -395,14 +403,16 @@ def multirate_cfg(n_slow, slow_kind, dt_slow=0.0, dt_s=0.0, eta=0.0, k_max=0, fi
 
 class SphBatch:
     """Per-specimen values of a batched run (sph_batch): host arrays of n_spec
-    doubles for E, D, dt_s, dt_slow; `grad` a device [n_spec, SPH_NGRAD] tensor."""
+    doubles for E, D, dt_s, dt_slow (dt_s / dt_slow None or entries <= 0: the
+    library's per-specimen sph_default_steps); `grad` a device [n_spec,
+    SPH_NGRAD] tensor."""
 
-    def __init__(self, E, D, dt_s, dt_slow, grad=None):
+    def __init__(self, E, D, dt_s=None, dt_slow=None, grad=None):
         self.E = np.ascontiguousarray(E, dtype=np.float64)
         n = self.E.size
         self.D = np.ascontiguousarray(D, dtype=np.float64)
-        self.dt_s = np.ascontiguousarray(dt_s, dtype=np.float64)
-        self.dt_slow = np.ascontiguousarray(dt_slow, dtype=np.float64)
+        self.dt_s = np.ascontiguousarray(np.zeros(n) if dt_s is None else dt_s, dtype=np.float64)
+        self.dt_slow = np.ascontiguousarray(np.zeros(n) if dt_slow is None else dt_slow, dtype=np.float64)
         assert self.D.size == n and self.dt_s.size == n and self.dt_slow.size == n
         self.grad = grad
         self._c = None
@@ -496,6 +506,13 @@ class SphTape:
         self.hist_slow = self._c.hist_slow
         self.dt_s = self._c.dt_s
         self.dt_slow = self._c.dt_slow
+
+    def forget_inner_states(self):
+        """Mark hist_u as holding no slow step's inner states (hist_slow = -1):
+        the next reverse pass re-runs every slow step from its checkpoint, as
+        a checkpointed run whose inner states were not kept does."""
+        self._c.hist_slow = -1
+        self.hist_slow = -1
 
 
 @dataclass

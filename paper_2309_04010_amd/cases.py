@@ -358,11 +358,9 @@ class Batch:
     spec: np.ndarray       # [n] int32 specimen id
     offsets: np.ndarray    # [n_spec + 1] input-order ranges
     material: dict         # shared values (E is per specimen)
-    run: dict              # shared schedule (D, dt_s, dt_slow per specimen)
+    run: dict              # shared schedule (D per specimen; each side derives the step sizes)
     E: np.ndarray
     D: np.ndarray
-    dt_s: np.ndarray
-    dt_slow: np.ndarray
 
     @property
     def n(self):
@@ -375,7 +373,8 @@ class Batch:
 
 def batch(cs, gap_dp=4.0, stack=True):
     """2D diffusion specimens of equal dp, h, nu, rho0, C_swell, eta and
-    schedule as one Batch; per-specimen E, D and step sizes."""
+    schedule as one Batch; per-specimen E and D (the step sizes that follow
+    from them are left to each side)."""
     c0 = cs[0]
     dp, h = c0.dp, c0.h
     Xs, y0, offs = [], 0.0, [0]
@@ -390,13 +389,10 @@ def batch(cs, gap_dp=4.0, stack=True):
     E = np.array([c.material["E"] for c in cs])
     D = np.array([c.run["D"] for c in cs])
     m = c0.material
-    K = E / (3.0 * (1.0 - 2.0 * m["nu"]))
-    dt_s = 0.6 * h / np.sqrt(K / m["rho0"])
-    dt_slow = 0.5 * h * h / D
     spec = np.concatenate([np.full(c.n, i, np.int32) for i, c in enumerate(cs)])
     return Batch(list(cs), np.hstack(Xs), np.concatenate([c.V for c in cs]), h,
                  np.concatenate([c.flags for c in cs]), np.concatenate([c.c_init for c in cs]),
-                 spec, np.array(offs), dict(m), dict(c0.run), E, D, dt_s, dt_slow)
+                 spec, np.array(offs), dict(m), dict(c0.run), E, D)
 
 
 def by_name(name, **kw):

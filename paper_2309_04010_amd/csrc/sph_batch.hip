@@ -76,7 +76,7 @@ int batch_check(const sph_nbr* nb, const sph_multirate_cfg* cfg) {
               (long long)nb->n_spec);
     return SPH_E_ARG;
   }
-  if (!b->E || !b->dt_s || !b->dt_slow || (cfg->slow_kind != SPH_SLOW_LOAD && !b->D)) {
+  if (!b->E || (cfg->slow_kind != SPH_SLOW_LOAD && !b->D)) {
     set_error("cfg->batch arrays missing");
     return SPH_E_ARG;
   }
@@ -98,10 +98,14 @@ int batch_upload(const sph_nbr* nb, const sph_material* m, const sph_multirate_c
     const double E = b->E[i];
     const double mu = E / (2.0 * (1.0 + m->nu));
     const double K = E / (3.0 * (1.0 - 2.0 * m->nu));
-    const double dt = b->dt_s[i] > 0.0 ? b->dt_s[i] : 0.6 * nb->h / std::sqrt(K / m->rho0);
     const double D = b->D ? b->D[i] : cfg->D;
-    double dtd = b->dt_slow[i];
-    if (!(dtd > 0.0)) dtd = cfg->slow_kind != SPH_SLOW_LOAD ? 0.5 * nb->h * nb->h / D : cfg->dt_slow;
+    sph_material mi = *m;
+    mi.E = E;
+    double dt_rest = 0.0, dt_diff = 0.0;
+    rest_steps(nb->h, &mi, D, &dt_rest, &dt_diff);
+    const double dt = b->dt_s && b->dt_s[i] > 0.0 ? b->dt_s[i] : dt_rest;
+    double dtd = b->dt_slow ? b->dt_slow[i] : 0.0;
+    if (!(dtd > 0.0)) dtd = cfg->slow_kind != SPH_SLOW_LOAD ? dt_diff : cfg->dt_slow;
     const double v[BT_COUNT] = {mu, K, K - 2.0 * mu / 3.0, dt, dtd, D, cfg->eta * dt};
     for (int f = 0; f < BT_COUNT; ++f) {
       t64[f * ns + i] = v[f];

@@ -267,6 +267,15 @@ inline int64_t tile_wmax_hard(int prec, int dim) {
   return std::min<int64_t>(65535, kTileLdsHard / tile_lds_bytes_per_particle(prec, dim));
 }
 
+// ---- step sizes of Sec. 4.1 (sph_default_steps) -------------------------------
+// dt_s = 0.6 h / sqrt(K / rho0), eq. (dts-advection) at rest; dt_d = 0.5 h^2 / D
+// (0 for D <= 0); K from eq. (relation-modulus)
+inline void rest_steps(double h, const sph_material* m, double D, double* dt_s, double* dt_d) {
+  const double K = m->E / (3.0 * (1.0 - 2.0 * m->nu));
+  if (dt_s) *dt_s = 0.6 * h / std::sqrt(K / m->rho0);
+  if (dt_d) *dt_d = D > 0.0 ? 0.5 * h * h / D : 0.0;
+}
+
 // ---- event timing around launches --------------------------------------------
 hipEvent_t prof_begin(const sph_nbr* nb, int kind, hipStream_t s);
 void prof_end(const sph_nbr* nb, int kind, hipEvent_t a, hipStream_t s, int launches = 1);

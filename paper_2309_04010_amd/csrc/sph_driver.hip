@@ -267,6 +267,17 @@ extern "C" int sph_diffusion_step(const sph_nbr* nb, const sph_material* mat, co
   return diffusion_step(nb, mat, st, D, dt_d, c_bc, (hipStream_t)stream);
 }
 
+extern "C" int sph_default_steps(double h, const sph_material* mat, double D, double* dt_s,
+                                 double* dt_d) {
+  clear_error();
+  if (!mat || !(h > 0.0) || !(mat->E > 0.0) || !(mat->rho0 > 0.0) || !(mat->nu < 0.5)) {
+    set_error("need h > 0, a material with E > 0, rho0 > 0 and nu < 1/2");
+    return SPH_E_ARG;
+  }
+  rest_steps(h, mat, D, dt_s, dt_d);
+  return SPH_OK;
+}
+
 extern "C" int sph_status(const sph_nbr* nb, void* stream, int32_t* bits) {
   clear_error();
   if (!nb) {
@@ -304,15 +315,16 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     set_error("bad n_slow or slow_kind");
     return SPH_E_ARG;
   }
-  const double K = m->E / (3.0 * (1.0 - 2.0 * m->nu));
-  const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * nb->h / std::sqrt(K / m->rho0);
+  double dt_rest = 0.0, dt_diff = 0.0;
+  rest_steps(nb->h, m, cfg->D, &dt_rest, &dt_diff);
+  const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : dt_rest;
   double dt_slow = cfg->dt_slow;
   if (cfg->slow_kind != SPH_SLOW_LOAD && !(dt_slow > 0.0)) {
     if (!(cfg->D > 0.0)) {
       set_error("diffusion needs D > 0");
       return SPH_E_ARG;
     }
-    dt_slow = 0.5 * nb->h * nb->h / cfg->D;
+    dt_slow = dt_diff;
   }
   const int64_t k_max = cfg->k_max > 0 ? cfg->k_max : (int64_t)std::floor(dt_slow / dt_s) + 1;
   const bool adaptive = cfg->k_sched == nullptr && cfg->fixed_inner <= 0;
@@ -689,15 +701,16 @@ extern "C" int sph_advance_multirate_graph(const sph_nbr* nb, const sph_material
               (long long)counts[cfg->n_slow - 1], (long long)tape->k_hist_cap);
     return SPH_E_CAPACITY;
   }
-  const double K = m->E / (3.0 * (1.0 - 2.0 * m->nu));
-  const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : 0.6 * nb->h / std::sqrt(K / m->rho0);
+  double dt_rest = 0.0, dt_diff = 0.0;
+  rest_steps(nb->h, m, cfg->D, &dt_rest, &dt_diff);
+  const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : dt_rest;
   double dt_slow = cfg->dt_slow;
   if (cfg->slow_kind == SPH_SLOW_DIFFUSION && !(dt_slow > 0.0)) {
     if (!(cfg->D > 0.0) && !cfg->batch) {
       set_error("diffusion needs D > 0");
       return SPH_E_ARG;
     }
-    dt_slow = cfg->D > 0.0 ? 0.5 * nb->h * nb->h / cfg->D : 1.0;  // batched: per specimen
+    dt_slow = cfg->D > 0.0 ? dt_diff : 1.0;  // batched: per specimen
   }
   hipStream_t user = (hipStream_t)stream;
   BatGuard bat_guard{nb};

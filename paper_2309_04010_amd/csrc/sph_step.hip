@@ -3,9 +3,13 @@
 // Layout: structure-of-arrays [component][n] in cell-sorted order, so that a
 // wavefront of 64 consecutive particles reads 64 consecutive words of every
 // component, and the neighbours it gathers sit in the same few cells.
-// Reference geometry (X) and displacement (u) are FP64; pair geometry and
-// displacement differences are formed in FP64 and then rounded to the working
-// type T (float or double), so the FP32 path loses nothing to cancellation.
+// Reference geometry (X) and displacement (u) are FP64.  A tile stages its
+// window's positions and displacements relative to the tile's first particle,
+// differenced in FP64 and then rounded to the working type T; the per-pair
+// differences are then taken in T.  In FP32 each staged value carries a
+// rounding error of at most 2^-24 of its offset from that particle, so a pair
+// difference is off by at most ~2^-23 times the tile's extent (a few support
+// radii), not by the rounding of the absolute coordinates.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>

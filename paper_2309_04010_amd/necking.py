@@ -46,10 +46,8 @@ class NeckingRun:
         self.st = st
         self.mat = B.material(**case.material)
         if autotune:
-            m = case.material
-            K = m["E"] / (3.0 * (1.0 - 2.0 * m["nu"]))
-            self.tuning = B.sph_autotune(self.nb, self.mat, st, case.run["eta"],
-                                         0.6 * case.h / (K / m["rho0"]) ** 0.5,
+            dt_s, _ = B.sph_default_steps(case.h, self.mat)
+            self.tuning = B.sph_autotune(self.nb, self.mat, st, case.run["eta"], dt_s,
                                          with_adjoint=False).as_dict()
         self.w_acc = dev(case.observable["w_acc"][:, self.perm])
         self.w_u = dev(case.observable["w_u"][:, self.perm])

@@ -17,6 +17,19 @@ def rel_err(got, want):
     return float(np.abs(got - want).max() / scale)
 
 
+def rel_err_elem(got, want, floor):
+    """Largest elementwise error relative to |want| + floor * max|want|: small
+    entries are held to nearly their own size, not to the field's maximum."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    if not want.size:
+        return 0.0
+    scale = np.abs(want) + floor * np.abs(want).max()
+    if not np.all(scale > 0):
+        return float(np.abs(got - want).max())
+    return float((np.abs(got - want) / scale).max())
+
+
 def dev(a, dtype=None):
     import torch
     t = torch.as_tensor(np.ascontiguousarray(a))

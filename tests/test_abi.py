@@ -79,3 +79,29 @@ def test_ctypes_structs_follow_the_header(cname, pycls):
 def test_last_error_is_callable_without_a_gpu(libsph):
     libsph.sph_last_error.restype = ctypes.c_char_p
     assert isinstance(libsph.sph_last_error(), bytes)
+
+
+@pytest.mark.parametrize("name", ["bar2d", "strip2d", "neck3d", "plate3d", "necking2d", "necking3d"])
+def test_default_steps_match_the_oracle(libsph, oracle_mod, name):
+    """Sec. 4.1's step sizes, computed by the library (a host function, no
+    GPU needed) and by the oracle, each on its own: equal to rounding."""
+    from paper_2309_04010_amd import cases
+    small = {"bar2d": dict(nx=8, ny=4), "strip2d": dict(nx=10, ny=4), "neck3d": dict(nx=4, ny=3, nz=3),
+             "plate3d": dict(nx=6, ny=6, nz=4), "necking2d": dict(across=4), "necking3d": dict(dp=2e-3)}
+    c = cases.by_name(name, **small[name])
+    o = oracle_mod.Oracle(c.dim, c.X, c.V, c.h)
+    D = c.run["D"]
+    want = o.default_steps(o.material(**c.material), D)
+    got = B.sph_default_steps(c.h, B.material(**c.material), D)
+    assert want[0] > 0.0 and (want[1] > 0.0) == (D > 0.0)
+    for g, w in zip(got, want):
+        assert abs(g - w) <= 4e-16 * abs(w), (name, got, want)
+
+
+def test_default_steps_reject_bad_arguments(libsph):
+    m = B.material(0, E=1e9, nu=0.5, rho0=1000.0)
+    with pytest.raises(B.SphError) as e:
+        B.sph_default_steps(1e-3, m)
+    assert e.value.code == B.SPH_E_ARG
+    with pytest.raises(B.SphError):
+        B.sph_default_steps(0.0, B.material(0, E=1e9, nu=0.3, rho0=1000.0))

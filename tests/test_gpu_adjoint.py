@@ -10,9 +10,10 @@ and dx, separately for every input group (state arrays and parameters).
 Tolerances: FP64 1e-9 relative (rounding of two different evaluation orders
 of the same derivative); FP32 2e-3 for the point and single-step checks (the
 derivative is evaluated at FP32-rounded states; its terms carry ~1e-6
-relative error that cancellation in the contractions amplifies) and 1e-2 for
+relative error that cancellation in the contractions amplifies) and 1e-3 for
 whole runs against the FP64 oracle (the FP32 forward trajectory itself is
-only within 1e-4 of the FP64 one).
+only within 1e-4 of the FP64 one; the gradients of the plate's whole
+checkpointed run stay within 1e-5).
 """
 import numpy as np
 import pytest
@@ -27,7 +28,7 @@ from .parity_util import dev, host, jittered, torch_dtype
 pytestmark = pytest.mark.gpu
 
 TOL_POINT = {B.SPH_F64: 1e-9, B.SPH_F32: 2e-3}
-TOL_RUN = {B.SPH_F64: 1e-8, B.SPH_F32: 1e-2}
+TOL_RUN = {B.SPH_F64: 1e-8, B.SPH_F32: 1e-3}
 PRECS = [B.SPH_F64, B.SPH_F32]
 PIDS = ["f64", "f32"]
 
@@ -433,4 +434,33 @@ def test_autograd_function(oracle_mod):
     g = pr.backward(w).cpu()
     assert torch.allclose(theta.grad, g, rtol=1e-13, atol=0.0)
     assert theta.grad[B.SPH_GRAD_E] != 0.0 and theta.grad[B.SPH_GRAD_D] != 0.0
+    pr.close()
+
+
+def test_autograd_function_two_solves_before_backward(oracle_mod):
+    """Two solves on one problem at different theta, then the first
+    objective's backward: the gradient is the first run's (the reverse pass
+    re-records that run when a later one replaced its tape)."""
+    c = cases.strip2d(nx=20, ny=6, n_slow=2, fixed_inner=15, k_max=0)
+    pr = A.MultirateProblem(c, B.SPH_F64)
+    th0 = pr.theta0()
+    th1 = th0.copy()
+    th1[B.SPH_GRAD_E] *= 1.7
+    th1[B.SPH_GRAD_D] *= 0.5
+    idx = torch.as_tensor(pr.perm.argsort()[c.observable["J_index"]]).cuda()
+    t0 = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    t1 = torch.tensor(th1, dtype=torch.float64, requires_grad=True)
+    J0 = A.solve(t0, pr)[1, idx].mean()
+    J1 = A.solve(t1, pr)[1, idx].mean()
+    J0.backward()
+    J1.backward()
+    w = torch.zeros((2, c.n), dtype=torch.float64, device="cuda")
+    w[1, idx] = 1.0 / len(idx)
+    want = []
+    for th in (th0, th1):
+        pr.forward(th)
+        want.append(pr.backward(w).cpu())
+    assert not torch.allclose(want[0], want[1])
+    assert torch.allclose(t0.grad, want[0], rtol=1e-13, atol=0.0)
+    assert torch.allclose(t1.grad, want[1], rtol=1e-13, atol=0.0)
     pr.close()

@@ -48,7 +48,8 @@ class _Run:
         self.st.flags = dev(bt.flags[self.perm])
         self.c0 = dev(bt.c_init[self.perm], T)
         self.grad = torch.zeros((len(bt.cases), B.SPH_NGRAD), dtype=torch.float64, device="cuda")
-        self.batch = B.SphBatch(bt.E, bt.D, bt.dt_s, bt.dt_slow, grad=self.grad)
+        # step sizes left to the library: each specimen's sph_default_steps
+        self.batch = B.SphBatch(bt.E, bt.D, grad=self.grad)
         r = dict(bt.run)
         self.cfg = B.multirate_cfg(**r, batch=self.batch)
         self.mat = B.material(**bt.material)
@@ -75,13 +76,15 @@ class _Run:
         return out
 
 
-def _oracle_strip(oracle_mod, c, E, D, dt_s, dt_slow, complex_step=False, pert=None, slow_kind=None,
+def _oracle_strip(oracle_mod, c, E, D, complex_step=False, pert=None, slow_kind=None,
                   nonlinear=0, rho_l0=0.0):
+    """The oracle run of one specimen alone; it derives its own step sizes
+    (Sec. 4.1) from E and D, independently of the library."""
     o = oracle_mod.Oracle(2, c.X, c.V, c.h, complex_step=complex_step)
     perm = o.perm
     flags = np.ascontiguousarray(c.flags[perm])
     m = dict(c.material, E=E, rho_l0=rho_l0)
-    r = dict(c.run, D=D, dt_s=dt_s, dt_slow=dt_slow)
+    r = dict(c.run, D=D, dt_s=0.0, dt_slow=0.0)
     if slow_kind is not None:
         r["slow_kind"] = slow_kind
     if pert:
@@ -112,7 +115,7 @@ def test_batched_forward_equals_each_specimen_alone(oracle_mod, prec):
     u = R.u_input_order()
     tol = 1e-10 if prec == B.SPH_F64 else 1e-4
     for i, c in enumerate(bt.cases):
-        want = _oracle_strip(oracle_mod, c, bt.E[i], bt.D[i], bt.dt_s[i], bt.dt_slow[i])
+        want = _oracle_strip(oracle_mod, c, bt.E[i], bt.D[i])
         got = u[:, bt.offsets[i]:bt.offsets[i + 1]]
         assert np.abs(want).max() > 0
         assert rel_err(got, want) < tol, (i, rel_err(got, want))
@@ -134,7 +137,7 @@ def test_batched_coupled_mixture_equals_each_specimen_alone(oracle_mod):
     assert np.all(k == bt.run["fixed_inner"])
     u = R.u_input_order()
     for i, c in enumerate(bt.cases):
-        want = _oracle_strip(oracle_mod, c, bt.E[i], bt.D[i], bt.dt_s[i], bt.dt_slow[i],
+        want = _oracle_strip(oracle_mod, c, bt.E[i], bt.D[i],
                              slow_kind=cases.DIFFUSION_COUPLED, nonlinear=1, rho_l0=1000.0)
         got = u[:, bt.offsets[i]:bt.offsets[i + 1]]
         assert np.abs(want).max() > 0
@@ -155,7 +158,7 @@ def test_batched_gradients_equal_each_specimen_alone(oracle_mod):
     eps = 1e-20
     for i, c in enumerate(bt.cases):
         wi = w_in[:, bt.offsets[i]:bt.offsets[i + 1]]
-        args = (bt.E[i], bt.D[i], bt.dt_s[i], bt.dt_slow[i])
+        args = (bt.E[i], bt.D[i])
         for nm, gi, base in [("E", B.SPH_GRAD_E, bt.E[i]), ("D", B.SPH_GRAD_D, bt.D[i]),
                              ("C_swell", B.SPH_GRAD_C, bt.material["C_swell"])]:
             h = eps * base
@@ -196,7 +199,6 @@ def test_whole_run_graph_equals_eager_bitwise(oracle_mod, prec):
     # new per-specimen values: the cached graph is relaunched with new tables
     R.batch.E[:] = R.batch.E[::-1].copy()
     R.batch.D[:] = R.batch.D * 1.5
-    R.batch.dt_slow[:] = 0.5 * bt.h ** 2 / R.batch.D
     ue2, ge2, _ = eager()
     ug2, gg2, _ = graph()
     assert not torch.equal(ue2, ue)
@@ -234,7 +236,6 @@ def test_overlapping_specimens_equal_their_own_runs_bitwise(oracle_mod, prec):
     u = R.st.u.clone()
     for i, c in enumerate(bt.cases):
         pr = A.MultirateProblem(c, prec)
-        assert pr.run["dt_s"] == bt.dt_s[i] and pr.run["dt_slow"] == bt.dt_slow[i]
         pr.forward(pr.theta0(), record=False)
         q0, q1 = bt.offsets[i], bt.offsets[i + 1]
         assert torch.equal(u[:, q0:q1], pr.st.u), i

@@ -1,9 +1,16 @@
 """GPU parity of the multi-time-step driver (Sec. 4.2) against the oracle.
 
 FP64: the inner-step counts chosen by the kinetic-energy early exit are
-identical to the oracle's and the fields agree to 1e-10.  FP32 bulk with FP64
+identical to the oracle's and the fields agree to 1e-10, over the whole
+schedules of the 2D bar (100 loading steps, 49,900 inner steps) and of the
+swelling strip (100 diffusion steps, 3,225 inner steps).  FP32 bulk with FP64
 displacement: fields within 1e-4 of the FP64 oracle on runs with a frozen
-schedule (the step at which FP32 crosses the threshold may differ by one).
+schedule.  On an adaptive schedule the FP32 run may cross the kinetic-energy
+threshold some steps earlier or later (the energy oscillates as it decays),
+so the 1e-4 bar applies to frozen schedules; an adaptive FP32 run is held to
+counts within 5% and a displacement within 1e-3 of FP64, below the
+relaxation residual that the FP64 run itself carries at the threshold
+(1.3e-2 of the converged field on the bar at 1e-8 of the reference energy).
 Eager launches and hipGraph chunk replays give bitwise-identical results.
 """
 import numpy as np
@@ -12,7 +19,7 @@ import pytest
 from paper_2309_04010_amd import binding as B
 from paper_2309_04010_amd import cases
 
-from .parity_util import TOL, build_pair, dev, host, rel_err, torch_dtype
+from .parity_util import TOL, build_pair, dev, host, rel_err, rel_err_elem, torch_dtype
 
 pytestmark = pytest.mark.gpu
 
@@ -68,8 +75,47 @@ def test_bar_fp64_adaptive_counts_identical(oracle_mod, use_graph):
     assert np.array_equal(r["k"][0], r["k"][1]), r["k"]
     assert np.all(r["conv"][1] == 1)
     assert rel_err(r["u"][1], r["u"][0]) < 1e-10
-    assert rel_err(r["v"][1], r["v"][0]) < 1e-8 * 0 + 1e-6  # v is near zero at convergence
-    assert rel_err(r["ke"][1], r["ke"][0]) < 1e-6
+    # at the stop, v and E_k are the relaxation residual: the kinetic energy
+    # is below 1e-8 of the reference, |v| about 1e-4 of its size during the
+    # step, so rounding differences of the relaxation (1e-12 of the moving
+    # field) appear 1e4 times larger relative to the residual
+    ev, ek = rel_err(r["v"][1], r["v"][0]), rel_err(r["ke"][1], r["ke"][0])
+    print(f"  rel err u {rel_err(r['u'][1], r['u'][0]):.2e} v {ev:.2e} ke {ek:.2e}", flush=True)
+    assert ev < 1e-7
+    assert ek < 1e-7
+
+
+def test_bar_fp64_whole_schedule(oracle_mod):
+    """The 2D bar over its whole schedule: 100 loading steps, each relaxed
+    until E_k <= 1e-8 E_ref (479-519 inner steps each).  Every count equals
+    the oracle's and the final fields agree to 1e-10, element by element."""
+    print("[multirate] bar2d fp64 whole schedule (100 slow steps)", flush=True)
+    c = cases.bar2d()
+    assert c.run["n_slow"] == 100
+    r = _run_pair(oracle_mod, c, B.SPH_F64)
+    assert r["rc"] == (0, 0)
+    assert np.array_equal(r["k"][0], r["k"][1]), np.nonzero(r["k"][0] != r["k"][1])
+    assert r["k"][1].sum() > 40000 and np.all(r["conv"][1] == 1)
+    e = rel_err_elem(r["u"][1], r["u"][0], 1e-3)
+    print(f"  inner {r['k'][1].sum()} rel err u {rel_err(r['u'][1], r['u'][0]):.2e} elem {e:.2e}", flush=True)
+    assert e < 1e-10
+
+
+def test_strip_fp64_whole_schedule(oracle_mod):
+    """The swelling strip over its whole schedule: 100 diffusion steps, the
+    inner loop stopped by the density kinetic energy (1 to 1607 inner steps
+    per slow step).  Counts identical; u, c and p within 1e-10."""
+    print("[multirate] strip2d fp64 whole schedule (100 slow steps)", flush=True)
+    c = cases.strip2d()
+    assert c.run["n_slow"] == 100 and c.run["fixed_inner"] == 0
+    r = _run_pair(oracle_mod, c, B.SPH_F64)
+    assert r["rc"] == (0, 0)
+    assert np.array_equal(r["k"][0], r["k"][1]), np.nonzero(r["k"][0] != r["k"][1])
+    assert np.all(r["conv"][1] == 1) and r["k"][1].max() > 1000
+    for f in ("u", "c", "p"):
+        e = rel_err_elem(r[f][1], r[f][0], 1e-3)
+        print(f"  {f}: rel err {rel_err(r[f][1], r[f][0]):.2e} elem {e:.2e}", flush=True)
+        assert e < 1e-10, f
 
 
 def test_graph_equals_eager_bitwise(oracle_mod):
@@ -118,7 +164,14 @@ def test_neck_j2_load(oracle_mod, prec):
     tol = TOL[prec]
     assert rel_err(r["u"][1], r["u"][0]) < tol
     assert r["pl"][0][6].max() > 0, "must reach plasticity"
-    assert rel_err(r["pl"][1][6], r["pl"][0][6]) < (1e-8 if prec == B.SPH_F64 else 1e-2)
+    ea, ey = rel_err(r["pl"][1][6], r["pl"][0][6]), rel_err(r["pl"][1][:6], r["pl"][0][:6])
+    print(f"  rel err u {rel_err(r['u'][1], r['u'][0]):.2e} alpha {ea:.2e} Y {ey:.2e}", flush=True)
+    # the plastic strain alpha grows from zero where the trial stress first
+    # crosses the yield surface: its value there is the small difference of
+    # two nearly equal stresses, which takes the stress's rounding with a
+    # gain of |s| / (|s| - k); that gain bounds the tolerance
+    assert ea < (1e-9 if prec == B.SPH_F64 else 2e-3)
+    assert ey < (1e-9 if prec == B.SPH_F64 else 2e-3)
 
 
 def test_cap_warning(oracle_mod):

@@ -73,9 +73,14 @@ def test_solid_stage(oracle_mod, dim, model, prec):
     assert rel_err(host(st.acc), acco) < tol
     assert rel_err(host(st.v) - v, vo - v) < tol  # velocity increments
     if model == "J2":
-        assert rel_err(host(st.plastic)[6], pl[6]) < (1e-8 if prec == B.SPH_F64 else 2e-3)
+        ea, ey = rel_err(host(st.plastic)[6], pl[6]), rel_err(host(st.plastic)[:6], pl[:6])
+        print(f"  J2 state rel err alpha {ea:.2e} Y {ey:.2e}", flush=True)
+        # alpha starts where the trial stress first crosses the yield
+        # surface, as the small difference of two nearly equal stresses: it
+        # takes their rounding with the gain |s| / (|s| - k)
+        assert ea < (1e-9 if prec == B.SPH_F64 else 2e-3)
         assert pl[6].max() > 0, "the case must reach the plastic regime"
-        assert rel_err(host(st.plastic)[:6], pl[:6]) < tol * 10
+        assert ey < tol * 10
     rc, bits = B.sph_status(nb)
     assert rc == 0 and bits == 0
     nb.close()

@@ -9,7 +9,13 @@
   whose E_k is at or below the threshold, and the counts are recorded;
 * kinetic energy decays monotonically once the load is applied (damping);
 * complex-step derivatives of the oracle equal central finite differences
-  (this pins the derivative oracle used for gradient parity).
+  (this pins the derivative oracle used for gradient parity), for E, C and D
+  on a swelling strip, and for E and the hardening law's sigma0, sigma_inf,
+  delta and H through Algorithm 1's return mapping on a J2 bar driven far
+  into the plastic range;
+* the fast step of Sec. 4.1 (eq. dts-advection at rest) is a stable explicit
+  step and within a factor 2 of the stability limit: an undamped elastic
+  lattice keeps its energy at dt_s and blows up at 2 dt_s.
 """
 import numpy as np
 import pytest
@@ -125,3 +131,80 @@ def test_complex_step_matches_finite_differences(oracle_mod, param):
     d_fd = (run(False, e) - run(False, -e)) / (2 * e)
     assert d_cs != 0.0
     assert abs(d_cs - d_fd) <= 1e-5 * abs(d_cs)
+
+
+def _j2_bar():
+    """A small J2 bar (App. A.3 hardening with the necking table's linear term
+    H, so that every hardening parameter acts) whose grips jump far enough in
+    two load steps that most particles yield."""
+    c = cases.neck3d(nx=12, ny=5, nz=5, n_slow=2, fixed_inner=25, total_stretch=1.2e-4)
+    c.material["H"] = cases.NECK_TABLE["H"]
+    return c
+
+
+@pytest.mark.parametrize("param", ["E", "sigma0", "sigma_inf", "delta", "H"])
+def test_complex_step_j2_matches_finite_differences(oracle_mod, param):
+    """d<w, u_final>/d(param) through the J2 return mapping (App. A.4,
+    Algorithm 1): the complex-step oracle (its Newton solve for the plastic
+    multiplier takes one more step once the real part has converged, so that
+    the derivative part converges too) against central differences of the
+    real oracle, with the step sizes frozen at their nominal values."""
+    c = _j2_bar()
+    w = np.random.default_rng(11).normal(0.0, 1.0, (3, c.n))
+    o0, _, _ = _setup(oracle_mod, c)
+    dt_s, _ = o0.default_steps(o0.material(**c.material))
+
+    def run(complex_step, pert):
+        o, flags, vgrip = _setup(oracle_mod, c, complex_step)
+        mat_kw = dict(c.material)
+        mat_kw[param] = mat_kw[param] + pert
+        cfg = o.cfg(**dict(c.run, dt_s=dt_s))
+        u, v, pl = o.arr(3, o.n), o.arr(3, o.n), o.arr(7, o.n)
+        rc, k, _, _ = o.advance(o.material(**mat_kw), cfg, u, v, plastic=pl, vgrip=vgrip, flags=flags)
+        assert rc in (0, 1)
+        return (w * u).sum(), pl
+    base = c.material[param]
+    val, pl = run(False, 0.0)
+    alpha = pl[6].real
+    # driven into the plastic range: most particles yield, up to ~10% strain
+    assert (alpha > 0).mean() > 0.5 and alpha.max() > 0.05
+    hcs = 1e-20 * base
+    d_cs = run(True, 1j * hcs)[0].imag / hcs
+    e = 1e-5 * base
+    d_fd = (run(False, e)[0] - run(False, -e)[0]) / (2 * e)
+    assert d_cs != 0.0
+    assert abs(d_cs - d_fd) <= 1e-5 * abs(d_cs), (d_cs, d_fd)
+
+
+@pytest.mark.parametrize("name", ["bar2d", "cube3d"])
+def test_fast_step_is_stable_and_near_the_limit(oracle_mod, name):
+    """Sec. 4.1's fast step at rest, 0.6 h / sqrt(K / rho0): symplectic Euler
+    on an undamped free lattice (LE in 2D, NH in 3D) from random velocities
+    keeps its kinetic energy bounded at dt_s and diverges at 2 dt_s (a step
+    off by a factor 2 either way, e.g. c_s from E instead of K or a missing
+    factor, fails one side)."""
+    if name == "bar2d":
+        c = cases.bar2d(nx=16, ny=8)
+        m = dict(c.material)
+    else:
+        c = cases.neck3d(nx=8, ny=6, nz=6)
+        m = dict(c.material, model=cases.NH)
+    o = oracle_mod.Oracle(c.dim, c.X, c.V, c.h)
+    mat = o.material(**m)
+    dt_s, dt_d = o.default_steps(mat)
+    assert dt_s > 0.0 and dt_d == 0.0
+    flags = np.zeros(o.n, np.uint8)
+
+    def ke_growth(dt):
+        v = np.random.default_rng(1).normal(0.0, 1e-3, (c.dim, o.n))
+        u = np.zeros((c.dim, o.n))
+        o.solid_step(mat, dt, u, v, flags=flags)
+        e0 = o.drift_ke(m["rho0"], dt, u, v, flags)
+        for _ in range(400):
+            o.solid_step(mat, dt, u, v, flags=flags)
+            e = o.drift_ke(m["rho0"], dt, u, v, flags)
+        return e / e0
+    with np.errstate(all="ignore"):
+        assert ke_growth(dt_s) < 2.0
+        g = ke_growth(2.0 * dt_s)
+    assert not np.isfinite(g) or g > 1e6
