@@ -282,7 +282,7 @@ def test_batched_coupled_reverse_is_refused(oracle_mod):
     st.c.copy_(dev(bt.c_init[perm]))
     import torch
     grad = torch.zeros((2, B.SPH_NGRAD), dtype=torch.float64, device="cuda")
-    batch = B.SphBatch(bt.E, bt.D, bt.dt_s, bt.dt_slow, grad=grad)
+    batch = B.SphBatch(bt.E, bt.D, grad=grad)
     cfg = B.multirate_cfg(**dict(bt.run, slow_kind=cases.DIFFUSION_COUPLED), batch=batch)
     tape = B.SphTape(nb, B.SPH_F64, 1, 5, with_diffusion=True)
     adj = B.new_adjoint(nb, B.SPH_F64, with_diffusion=True)
