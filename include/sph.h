@@ -227,6 +227,21 @@ int sph_damping_sweep(const sph_nbr* nbr, const sph_material* mat, const sph_sta
 int sph_drift_ke(const sph_nbr* nbr, const sph_material* mat, const sph_state* st, double dt_s,
                  double* ke_out, void* stream);
 
+/* sph_drift_ke for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bitwise) as sph_drift_ke; the block
+ * partials of the kinetic-energy reduction live in a static device array of
+ * the library (512 KiB per GPU, kept until the process ends) instead of the
+ * handle's buffer, so the call allocates nothing, and it is never timed by
+ * sph_profile_enable.  Call it with the handle's device current.  Every
+ * partial is written before it is read, so calls need no clearing between
+ * them, but calls that overlap in time on one GPU race on that array.
+ * Errors: as sph_drift_ke, plus SPH_E_CAPACITY for more than 2^26
+ * particles (the array's limit) and SPH_E_ARG when the current device is
+ * not the handle's.  Asynchronous. */
+int sph_drift_ke_noalloc(const sph_nbr* nbr, const sph_material* mat, const sph_state* st,
+                         double dt_s, double* ke_out, void* stream);
+
 /* Loading slow step: u += dt_l * vgrip for SPH_FLAG_GRIP particles.  Async. */
 int sph_load_step(const sph_nbr* nbr, const sph_state* st, double dt_l, void* stream);
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "sph_diffusion_step_vjp", "sph_diffusion_step_coupled_vjp", "sph_advance_multirate_backward",
     "sph_constitutive",
     "sph_constitutive_vjp", "sph_build_neighbors_batched", "sph_advance_multirate_graph",
-    "sph_autotune", "sph_set_tuning", "sph_get_tuning", "sph_default_steps",
+    "sph_autotune", "sph_set_tuning", "sph_get_tuning", "sph_default_steps", "sph_drift_ke_noalloc",
 ]
 SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load",
                     "adj_stress", "adj_gather", "adj_damping"]
@@ -125,6 +125,7 @@ def lib():
     L.sph_solid_relax_step.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp]
     L.sph_damping_sweep.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, vp]
     L.sph_drift_ke.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp, vp]
+    L.sph_drift_ke_noalloc.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp, vp]
     L.sph_load_step.argtypes = [vp, C.POINTER(State), dbl, vp]
     L.sph_diffusion_step.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, dbl, vp]
     L.sph_diffusion_step_coupled.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, dbl,
@@ -360,6 +361,12 @@ def sph_drift_ke(nbr, mat, st, dt_s, ke_out=None, stream=None):
     cs = st.cstruct(nbr)
     _check(lib().sph_drift_ke(nbr.handle, C.byref(mat), C.byref(cs), float(dt_s), _dptr(ke_out),
                               _stream(stream)))
+
+
+def sph_drift_ke_noalloc(nbr, mat, st, dt_s, ke_out=None, stream=None):
+    cs = st.cstruct(nbr)
+    _check(lib().sph_drift_ke_noalloc(nbr.handle, C.byref(mat), C.byref(cs), float(dt_s),
+                                      _dptr(ke_out), _stream(stream)))
 
 
 def sph_load_step(nbr, st, dt_l, stream=None):

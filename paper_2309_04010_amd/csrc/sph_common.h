@@ -102,7 +102,8 @@ constexpr int kDiffPerBlock = kDiffBlock / kDiffLanes;
 
 constexpr int kKeThreads = 256;
 constexpr int kKeItems = 4;             // particles per thread in the drift kernel
-constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (16.7M particles)
+constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (67M particles)
+constexpr int kStaticKeBlocks = 1 << 16;  // sph_drift_ke_noalloc: 512 KiB of partials per GPU
 
 // A tile is a run of consecutive sorted particles inside one row of cells
 // (fixed y, z).  Its neighbours all lie in the "window": the 3^(d-1) rows
@@ -292,6 +293,9 @@ int damp_prepare(const sph_nbr* nb, const sph_material* m, const sph_state* st, 
                  double dt, hipStream_t s);
 int drift_ke(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
              double* ke_out, hipStream_t s, bool gated);
+// drift_ke with its partials in a static device array (no library-owned scratch)
+int drift_ke_static(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
+                    double* ke_out, hipStream_t s);
 int load_step(const sph_nbr* nb, const sph_state* st, double dt_l, hipStream_t s);
 int diffusion_step_coupled(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                            double D, double dt, double c_bc, int nonlinear, hipStream_t s);

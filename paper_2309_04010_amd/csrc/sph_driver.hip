@@ -235,6 +235,20 @@ extern "C" int sph_drift_ke(const sph_nbr* nb, const sph_material* mat, const sp
   return drift_ke(nb, mat, st, dt_s, ke_out, (hipStream_t)stream, false);
 }
 
+extern "C" int sph_drift_ke_noalloc(const sph_nbr* nb, const sph_material* mat,
+                                    const sph_state* st, double dt_s, double* ke_out,
+                                    void* stream) {
+  clear_error();
+  int rc = check_state(nb, st, true);
+  if (rc) return rc;
+  if (!mat) {
+    set_error("material is NULL");
+    return SPH_E_ARG;
+  }
+  if ((rc = check_mixture(mat, st))) return rc;
+  return drift_ke_static(nb, mat, st, dt_s, ke_out, (hipStream_t)stream);
+}
+
 extern "C" int sph_load_step(const sph_nbr* nb, const sph_state* st, double dt_l, void* stream) {
   clear_error();
   int rc = check_state(nb, st, false);

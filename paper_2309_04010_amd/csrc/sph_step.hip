@@ -12,6 +12,7 @@
 // radii), not by the rounding of the absolute coordinates.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "sph_device.h"
@@ -1179,35 +1180,94 @@ int damping_sweep_rev(const sph_nbr* nb, const sph_material* m, const sph_state*
 
 template <typename T, int D>
 static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
-                   double* ke_out, hipStream_t s, bool gated) {
+                   double* ke_out, hipStream_t s, bool gated, double* partial, int64_t max_blocks,
+                   bool timed) {
   const int64_t per = (int64_t)kKeThreads * kKeItems;
   const int64_t nb_ = std::max<int64_t>(1, (nb->n + per - 1) / per);
-  if (nb_ > kKeMaxBlocks) {
-    set_error("too many particles for the kinetic-energy partials");
+  if (nb_ > max_blocks) {
+    set_error("too many particles for the kinetic-energy partials (%lld > %lld)",
+              (long long)nb->n, (long long)(max_blocks * per));
     return SPH_E_CAPACITY;
   }
   {
-    hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_DRIFT_KE, s);
+    hipEvent_t pe_ = timed ? prof_begin(nb, SPH_KERNEL_DRIFT_KE, s) : nullptr;
     k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
                                                           nb->V, m->rho0, dt, nb->ctrl,
-                                                          nb->ke_partial, gated, nb->rec_u,
+                                                          partial, gated, nb->rec_u,
                                                           bat_view(nb), mix_view<T>(m, st).c,
                                                           m->rho_l0);
     SPH_LAUNCH_CHECK();
-    k_ke_reduce<<<1, 1024, 0, s>>>(nb->ke_partial, (int)nb_, nb->ctrl, ke_out, gated);
-    prof_end(nb, SPH_KERNEL_DRIFT_KE, pe_, s);
+    k_ke_reduce<<<1, 1024, 0, s>>>(partial, (int)nb_, nb->ctrl, ke_out, gated);
+    if (timed) prof_end(nb, SPH_KERNEL_DRIFT_KE, pe_, s);
   }
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
 
+static int drift_dispatch(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
+                          double* ke_out, hipStream_t s, bool gated, double* partial,
+                          int64_t max_blocks, bool timed) {
+  if (st->prec == SPH_F64)
+    return nb->dim == 2
+               ? drift_t<double, 2>(nb, m, st, dt, ke_out, s, gated, partial, max_blocks, timed)
+               : drift_t<double, 3>(nb, m, st, dt, ke_out, s, gated, partial, max_blocks, timed);
+  return nb->dim == 2
+             ? drift_t<float, 2>(nb, m, st, dt, ke_out, s, gated, partial, max_blocks, timed)
+             : drift_t<float, 3>(nb, m, st, dt, ke_out, s, gated, partial, max_blocks, timed);
+}
+
 int drift_ke(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
              double* ke_out, hipStream_t s, bool gated) {
-  if (st->prec == SPH_F64)
-    return nb->dim == 2 ? drift_t<double, 2>(nb, m, st, dt, ke_out, s, gated)
-                        : drift_t<double, 3>(nb, m, st, dt, ke_out, s, gated);
-  return nb->dim == 2 ? drift_t<float, 2>(nb, m, st, dt, ke_out, s, gated)
-                      : drift_t<float, 3>(nb, m, st, dt, ke_out, s, gated);
+  return drift_dispatch(nb, m, st, dt, ke_out, s, gated, nb->ke_partial, kKeMaxBlocks, true);
+}
+
+// ---- drift + kinetic energy with the partials in a static device array -------
+// The block partials of the kinetic-energy reduction sit in `scratch`, one
+// copy per GPU that loads the library (kept until the process ends).  In host
+// code `scratch` names a host-side stand-in, not the device copy: its device
+// address is taken once per device with hipGetSymbolAddress and only that
+// address reaches the kernels.  Every block writes its own partial and the
+// reducer reads exactly the blocks of the launch, so nothing needs clearing
+// between calls; two calls that overlap in time on one GPU race on it.
+static __device__ __align__(256) double scratch[kStaticKeBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+
+int scratch_address(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device ordinal %d out of range", device);
+    return SPH_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+      return SPH_E_DEVICE;
+    }
+    g_scratch_dev[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[device];
+  return SPH_OK;
+}
+}  // namespace
+
+int drift_ke_static(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
+                    double* ke_out, hipStream_t s) {
+  int device = -1;
+  SPH_HIP(hipGetDevice(&device));
+  if (device != nb->device) {
+    set_error("the current device (%d) is not the neighbourhood's (%d)", device, nb->device);
+    return SPH_E_ARG;
+  }
+  double* partial = nullptr;
+  const int rc = scratch_address(device, &partial);
+  if (rc) return rc;
+  return drift_dispatch(nb, m, st, dt, ke_out, s, false, partial, kStaticKeBlocks, false);
 }
 
 int reset_ctrl(const sph_nbr* nb, int64_t k_limit, double ke_tol, hipStream_t s) {
