@@ -78,8 +78,8 @@ def algorithmic_bytes(kernel, dim, prec_bytes, model_j2=False, n_colors=8):
     if kernel == "diff_div":
         return 8 * d + T + T * dd + T * d + 2 * T + 1 + T  # X, V, B0, q, c(rw), flags | p
     if kernel == "adj_stress":
-        # X, V, B0, u_k, w, flags, p | G_bar, p_bar(rw, f64)
-        b = 8 * d + T + T * dd + 8 * d + T * d + 1 + T + T * dd + 16
+        # X, V, B0, H_k (the forward's record), w, flags, p | G_bar, p_bar(rw, f64)
+        b = 8 * d + T + T * dd + T * dd + T * d + 1 + T + T * dd + 16
         if model_j2:
             b += 7 * T + 2 * 7 * T
         return b
@@ -99,8 +99,8 @@ def flops_per_pair(kernel, dim):
     if kernel == "momentum":
         return geo + d * d + 2 * d * d + 2 * d
     if kernel == "adj_stress":
-        # V_b, V_a scalings; du; w du; w_b a_a - w_a a_b; two outer-product sums
-        return geo + 2 + d + d + 3 * d + 2 * d * d + 2 * d * d
+        # e = w grad; V_b a_a - V_a a_b; its outer-product sum with e
+        return geo + d + 3 * d + 2 * d * d
     if kernel == "adj_gather":
         # V_b scaling; G_bar_b d; its weighted sum; sum_b V_b grad W
         return geo + 1 + 2 * d * d + 2 * d + 2 * d

@@ -276,27 +276,29 @@ int sph_diffusion_step_coupled(const sph_nbr* nbr, const sph_material* mat, cons
  * (sph_advance_multirate_backward).  All arrays are caller-owned DEVICE
  * memory except k_rec (host).  Slice l of a checkpoint array holds the state
  * at the start of slow step l (before its load or diffusion update); slice
- * n_slow holds the final state.  hist_u receives u before every inner step of
- * one slow step (the last one of the forward run, when it fits, and each slow
- * step again while the reverse pass recomputes it), hist_plastic the J2 state
- * likewise.  Sizes: ck_u [n_slow_cap+1][dim][n] f64, ck_v [n_slow_cap+1][dim][n],
- * ck_plastic [n_slow_cap+1][7][n] (J2 only, else NULL), ck_c [n_slow_cap+1][n]
- * (diffusion only, else NULL), hist_u [k_hist_cap][dim][n] f64,
- * hist_plastic [k_hist_cap][7][n] (J2 only, else NULL); prec-typed arrays
- * follow sph_state.prec. */
+ * n_slow holds the final state.  hist_H receives, for every inner step of one
+ * slow step (the last one of the forward run, when it fits, and each slow
+ * step again while the reverse pass recomputes it), the displacement gradient
+ * H = F - I the stress stage formed (row-major dim x dim), hist_plastic the
+ * J2 state before the step; the reverse pass differentiates the constitutive
+ * update at exactly these values.  Sizes: ck_u [n_slow_cap+1][dim][n] f64,
+ * ck_v [n_slow_cap+1][dim][n], ck_plastic [n_slow_cap+1][7][n] (J2 only, else
+ * NULL), ck_c [n_slow_cap+1][n] (diffusion only, else NULL),
+ * hist_H [k_hist_cap][dim*dim][n], hist_plastic [k_hist_cap][7][n] (J2 only,
+ * else NULL); prec-typed arrays follow sph_state.prec. */
 typedef struct {
   int32_t n_slow_cap;  /* slow steps that fit */
   int32_t pad_;
-  int64_t k_hist_cap;  /* inner steps of one slow step that fit in hist_u */
+  int64_t k_hist_cap;  /* inner steps of one slow step that fit in hist_H */
   double* ck_u;
   void* ck_v;
   void* ck_plastic;
   void* ck_c;
-  double* hist_u;
+  void* hist_H;
   void* hist_plastic;
   int64_t* k_rec;      /* host [n_slow_cap]: inner steps taken per slow step (out) */
   int32_t n_rec;       /* out: slow steps recorded */
-  int32_t hist_slow;   /* out: slow step whose inner states hist_u holds, -1 if none */
+  int32_t hist_slow;   /* out: slow step whose inner states hist_H holds, -1 if none */
   double dt_s;         /* out: inner step used (frozen for the reverse pass) */
   double dt_slow;      /* out: slow step used */
 } sph_tape;
@@ -393,7 +395,7 @@ int sph_diffusion_step_coupled_vjp(const sph_nbr* nbr, const sph_material* mat,
  * final state; on return they hold the adjoint of the initial state and
  * adj->grad has the parameter gradients added.  The pass re-runs each slow
  * step from its checkpoint (recording its inner states, k_rec[l] <=
- * k_hist_cap required) unless hist_u already holds it; st is used as working
+ * k_hist_cap required) unless hist_H already holds it; st is used as working
  * storage and restored to the final state on return.  adj->p must be zero on
  * entry.  Slow steps: loading, diffusion, and the two-way coupled diffusion
  * (one specimen; its u-dependence through F, J and F^-1 goes to adj->u).

@@ -83,7 +83,7 @@ class Batch(C.Structure):
 
 class Tape(C.Structure):
     _fields_ = [("n_slow_cap", i32), ("pad_", i32), ("k_hist_cap", i64), ("ck_u", vp), ("ck_v", vp),
-                ("ck_plastic", vp), ("ck_c", vp), ("hist_u", vp), ("hist_plastic", vp), ("k_rec", vp),
+                ("ck_plastic", vp), ("ck_c", vp), ("hist_H", vp), ("hist_plastic", vp), ("k_rec", vp),
                 ("n_rec", i32), ("hist_slow", i32), ("dt_s", dbl), ("dt_slow", dbl)]
 
 
@@ -496,11 +496,11 @@ class SphTape:
         self.ck_v = z(n_slow + 1, d, n)
         self.ck_plastic = z(n_slow + 1, 7, n) if with_plastic else None
         self.ck_c = z(n_slow + 1, n) if with_diffusion else None
-        self.hist_u = z(max(k_hist, 1), d, n, dt=torch.float64)
+        self.hist_H = z(max(k_hist, 1), d * d, n)
         self.hist_plastic = z(max(k_hist, 1), 7, n) if with_plastic else None
         self.k_rec = np.zeros(max(n_slow, 1), np.int64)
         self._c = Tape(self.n_slow_cap, 0, self.k_hist_cap, _dptr(self.ck_u), _dptr(self.ck_v),
-                       _dptr(self.ck_plastic), _dptr(self.ck_c), _dptr(self.hist_u),
+                       _dptr(self.ck_plastic), _dptr(self.ck_c), _dptr(self.hist_H),
                        _dptr(self.hist_plastic), self.k_rec.ctypes.data_as(vp), 0, -1, 0.0, 0.0)
 
     def cstruct(self, nbr, st):
@@ -515,7 +515,7 @@ class SphTape:
         self.dt_slow = self._c.dt_slow
 
     def forget_inner_states(self):
-        """Mark hist_u as holding no slow step's inner states (hist_slow = -1):
+        """Mark hist_H as holding no slow step's inner states (hist_slow = -1):
         the next reverse pass re-runs every slow step from its checkpoint, as
         a checkpointed run whose inner states were not kept does."""
         self._c.hist_slow = -1

@@ -433,50 +433,47 @@ __device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot
 }
 
 // reverse of the stress stage + momentum sum + kick, one tile per workgroup:
-// gathers the neighbours' u (for H) and a_bar = dt w (free particles) from the
-// LDS window; writes G_bar = H_bar B0^T, updates the J2 state adjoint,
-// accumulates p_bar and the parameter partials.  Both sums share the pair's
-// e = grad W and keep their per-pair differences, V_b (u_b - u_a) and
-// V_b a_a - V_a a_b: taking the own particle's terms out of the loop makes
-// them cancel across the pairs, which costs FP32 gradients an order of
-// magnitude on smooth fields.  The window holds the relative position, V_b,
-// u_b and a_b: ten values in 3D, two 16-byte and one 8-byte LDS read per pair
-// (eight in 2D, one of them padding).
+// gathers a_bar = dt w (free particles) from the LDS window; takes the step's
+// H = F - I from the forward run's record (Hin), writes G_bar = H_bar B0^T
+// (Gb may be Hin: a particle's H is read before its G_bar is written, by the
+// same thread), updates the J2 state adjoint, accumulates p_bar and the
+// parameter partials.  The momentum transpose keeps its per-pair difference
+// V_b a_a - V_a a_b: taking the own particle's term out of the loop makes the
+// terms cancel across the pairs, which costs FP32 gradients an order of
+// magnitude on smooth fields.  The window holds the relative position, V_b
+// and a_b: seven values and a pad in 3D (two 16-byte LDS reads per pair),
+// five and a pad in 2D.
 template <typename T, int D, int LPP, int MODEL>
 __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
-    TileGeo<T> g, MatP<T> m, const double* __restrict__ u, const T* __restrict__ w,
+    TileGeo<T> g, MatP<T> m, const T* Hin, const T* __restrict__ w,
     const uint8_t* __restrict__ flags, T dt, T inv_rho0, const T* __restrict__ plastic,
-    T* __restrict__ plb, const T* __restrict__ p, double* __restrict__ pbar, T* __restrict__ Gb,
+    T* __restrict__ plb, const T* __restrict__ p, double* __restrict__ pbar, T* Gb,
     double* __restrict__ gpart, Ctrl* ctrl, Bat bt) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
-  constexpr int OV = D, OU = D + 1, OA = 2 * D + 1;  // offsets of V, u, a
-  using PK = Pk<T, D == 3 ? 10 : 8>;                    // (position, V, u, a[, 0])
+  constexpr int OV = D, OA = D + 1;             // offsets of V and a
+  using PK = Pk<T, D == 3 ? 8 : 6>;              // (position, V, a[, 0])
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const TileDesc& td = g.tiles[tile];
   const uint32_t window = td.window;
   const int64_t n = g.n;
   const int64_t p0 = td.p0;
-  double xo[3] = {0, 0, 0}, uo[3] = {0, 0, 0};
+  double xo[3] = {0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    xo[k] = g.X[k * n + p0];
-    uo[k] = u[k * n + p0];
-  }
+  for (int k = 0; k < D; ++k) xo[k] = g.X[k * n + p0];
   const WinMap wm = win_map(td);
   for (uint32_t l = threadIdx.x; l < window; l += blockDim.x) {
     const int64_t gi = wm(l);
     const bool fixed = flags && (flags[gi] & SPH_FLAG_FIXED);
     const T kf = fixed ? T(0) : (bt.spec ? bt.get<T>(BT_DT, bt.spec[gi]) : dt);
-    T vv[D == 3 ? 10 : 8];
+    T vv[D == 3 ? 8 : 6];
     vv[OV] = g.V[gi];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       vv[k] = (T)(g.X[k * n + gi] - xo[k]);
-      vv[OU + k] = (T)(u[k * n + gi] - uo[k]);
       vv[OA + k] = kf * w[k * n + gi];
     }
-    if (D == 2) vv[7] = T(0);
+    vv[2 * D + 1] = T(0);
     PK::store(smem_raw, window, l, vv);
   }
   __syncthreads();
@@ -484,16 +481,16 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
   const bool active = (uint32_t)t < td.count;
   uint32_t la;
   const int64_t a_own = tile_own(td, active ? (uint32_t)t : 0u, la);
-  T va[D == 3 ? 10 : 8];
+  T va[D == 3 ? 8 : 6];
   PK::load(smem_raw, window, la, va);
-  T Gs[D][D], Qs[D][D];
+  T Qs[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int k = 0; k < D; ++k) Gs[i][k] = Qs[i][k] = T(0);
+    for (int k = 0; k < D; ++k) Qs[i][k] = T(0);
   if (active)
     ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
-      T vb[D == 3 ? 10 : 8];
+      T vb[D == 3 ? 8 : 6];
       PK::load(smem_raw, window, l, vb);
       T d[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -501,30 +498,20 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
       T r2 = d[0] * d[0] + d[1] * d[1];
       if (D == 3) r2 += d[2] * d[2];
       const T w0 = dw_over_r(r2, g.inv_h, g.c5);
-      T e[3], f[3];
+      T e[3];
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        e[k] = w0 * d[k];
-        f[k] = vb[OV] * e[k];
-      }
+      for (int k = 0; k < D; ++k) e[k] = w0 * d[k];
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        const T du = vb[OU + i] - va[OU + i];
         const T qa = vb[OV] * va[OA + i] - va[OV] * vb[OA + i];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          Gs[i][k] += du * f[k];
-          Qs[i][k] += qa * e[k];
-        }
+        for (int k = 0; k < D; ++k) Qs[i][k] += qa * e[k];
       }
     });
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      Gs[i][k] = lane_sum<LPP>(Gs[i][k]);
-      Qs[i][k] = lane_sum<LPP>(Qs[i][k]);
-    }
+    for (int k = 0; k < D; ++k) Qs[i][k] = lane_sum<LPP>(Qs[i][k]);
   double thd[kNTheta] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (active && h == 0) {
     const int64_t a = a_own;
@@ -540,13 +527,10 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        T hs = T(0), ps = T(0);
+        T ps = T(0);
 #pragma unroll
-        for (int l = 0; l < D; ++l) {
-          hs += Gs[i][l] * B[l][k];
-          ps += Qs[i][l] * B[k][l];
-        }
-        Hm[i * 3 + k] = hs;
+        for (int l = 0; l < D; ++l) ps += Qs[i][l] * B[k][l];
+        Hm[i * 3 + k] = Hin[(i * D + k) * n + a];
         Pb[i * 3 + k] = ps * inv_rho0;
       }
     T pl[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)}, pv[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -1169,7 +1153,7 @@ int grad_reduce(const sph_nbr* nb, double* grad, hipStream_t s) {
 }
 
 template <typename T, int D, int LS, int LG, int MODEL>
-static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u,
+static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const void* H,
                        const void* plastic, const sph_state* st, const sph_adjoint* adj,
                        double dt, double drift_dt, hipStream_t s) {
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
@@ -1182,14 +1166,14 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
     return SPH_E_CAPACITY;
   }
   const size_t wm = (size_t)nb->tiling[prec].window_max;
-  const size_t lds_s = wm * Pk<T, D == 3 ? 10 : 8>::bytes + 16;
+  const size_t lds_s = wm * Pk<T, D == 3 ? 8 : 6>::bytes + 16;
   const size_t lds_g = wm * Pk<T, D + D * D>::bytes + 16;
   int rc = SPH_OK;
   if constexpr (LS > 0) {
     if ((rc = lds_attr(k_adj_stress<T, D, LS, MODEL>, lds_s))) return rc;
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_ADJ_STRESS, s);
     k_adj_stress<T, D, LS, MODEL><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
-        g, mp, u, (const T*)adj->v, st->flags, (T)dt, (T)(1.0 / m->rho0), (const T*)plastic,
+        g, mp, (const T*)H, (const T*)adj->v, st->flags, (T)dt, (T)(1.0 / m->rho0), (const T*)plastic,
         (T*)adj->plastic, (const T*)st->p, adj->p, (T*)adj->work, nb->gpart, nb->ctrl,
         bat_view(nb));
     prof_end(nb, SPH_KERNEL_ADJ_STRESS, pe_, s);
@@ -1207,7 +1191,7 @@ static int adj_solid_l(const sph_nbr* nb, const sph_material* m, const double* u
 }
 
 template <typename T, int D>
-static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const double* u,
+static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const void* u,
                        const void* plastic, const sph_state* st, const sph_adjoint* adj,
                        double dt, double drift_dt, hipStream_t s) {
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
@@ -1261,7 +1245,7 @@ static int check_adj(const sph_nbr* nb, const sph_material* m, const sph_state* 
   return SPH_OK;
 }
 
-int adj_solid(const sph_nbr* nb, const sph_material* m, const double* u, const void* plastic,
+int adj_solid(const sph_nbr* nb, const sph_material* m, const void* u, const void* plastic,
               const sph_state* st, const sph_adjoint* adj, double dt, double drift_dt,
               hipStream_t s) {
   if (st->prec == SPH_F64)
@@ -1405,7 +1389,9 @@ extern "C" int sph_solid_relax_step_vjp(const sph_nbr* nb, const sph_material* m
   int rc = check_adj(nb, mat, st, adj);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  rc = adj_solid(nb, mat, st->u, st->plastic, st, adj, dt_s, 0.0, s);
+  // the step's H from u, into adj->work, where the reverse replaces it by G_bar
+  if ((rc = displacement_gradient(nb, st, adj->work, s))) return rc;
+  rc = adj_solid(nb, mat, adj->work, st->plastic, st, adj, dt_s, 0.0, s);
   if (rc) return rc;
   return grad_reduce(nb, adj->grad, s);
 }

@@ -199,7 +199,7 @@ struct sph_nbr {
   double* gpart = nullptr;           // device [gpart_slots][SPH_NGRAD] gradient partials
   int64_t gpart_slots = 0;
   // inner-step recording of a taped run (set by the driver while it runs)
-  mutable double* rec_u = nullptr;   // [k][dim][n]: u before inner step k
+  mutable void* rec_H = nullptr;     // [k][dim*dim][n]: H = F - I of inner step k
   mutable void* rec_pl = nullptr;    // [k][7][n]: J2 state before inner step k
   // cell-grid segments (one per specimen) and the segment of each cell
   std::vector<sph::GridSeg> segs;
@@ -304,8 +304,11 @@ int diffusion_step(const sph_nbr* nb, const sph_material* m, const sph_state* st
 int reset_ctrl(const sph_nbr* nb, int64_t k_limit, double ke_tol, hipStream_t s);
 int check_state(const sph_nbr* nb, const sph_state* st, bool need_v);
 int check_mixture(const sph_material* m, const sph_state* st);
-// reverse mode (sph_adjoint.hip)
-int adj_solid(const sph_nbr* nb, const sph_material* m, const double* u, const void* plastic,
+// H = F - I of st->u into H ([dim*dim][n], st->prec): the stress stage's gather
+int displacement_gradient(const sph_nbr* nb, const sph_state* st, void* H, hipStream_t s);
+// reverse mode (sph_adjoint.hip); H: the step's F - I ([dim*dim][n]), may
+// alias adj->work (each particle's entries are read before its own are written)
+int adj_solid(const sph_nbr* nb, const sph_material* m, const void* H, const void* plastic,
               const sph_state* st, const sph_adjoint* adj, double dt, double drift_dt,
               hipStream_t s);
 int adj_damping(const sph_nbr* nb, const sph_material* m, const sph_state* st,

@@ -171,7 +171,7 @@ int check_tape(const sph_nbr* nb, const sph_material* m, const sph_state* st,
 struct RecGuard {  // inner-state recording is switched off on every exit
   const sph_nbr* nb;
   ~RecGuard() {
-    nb->rec_u = nullptr;
+    nb->rec_H = nullptr;
     nb->rec_pl = nullptr;
   }
 };
@@ -408,11 +408,11 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     rc = reset_ctrl(nb, nk, adaptive ? cfg->ke_tol : -1.0, s);
     if (rc) break;
     // the last slow step's inner states go to the tape when they fit (eager launches only)
-    const bool rec = tape && l == cfg->n_slow - 1 && !graph && tape->hist_u &&
+    const bool rec = tape && l == cfg->n_slow - 1 && !graph && tape->hist_H &&
                      nk <= tape->k_hist_cap &&
                      (m->model != SPH_MODEL_J2 || tape->hist_plastic);
     if (rec) {
-      nb->rec_u = tape->hist_u;
+      nb->rec_H = tape->hist_H;
       nb->rec_pl = tape->hist_plastic;
       recorded = true;
     }
@@ -439,7 +439,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
       if (nb->prof) prof_resolve(nb);
       if (hc->done || launched >= nk) break;
     }
-    nb->rec_u = nullptr;
+    nb->rec_H = nullptr;
     nb->rec_pl = nullptr;
     if (rc) break;
     if (tape) tape->k_rec[l] = hc->k;
@@ -499,7 +499,7 @@ int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* 
   for (int l = L - 1; l >= 0; --l) {
     const int64_t kl = tape->k_rec[l];
     if (tape->hist_slow != l) {
-      if (kl > 0 && (kl > tape->k_hist_cap || !tape->hist_u ||
+      if (kl > 0 && (kl > tape->k_hist_cap || !tape->hist_H ||
                      (m->model == SPH_MODEL_J2 && !tape->hist_plastic))) {
         set_error("slow step %d has %lld inner steps; the tape records %lld", l, (long long)kl,
                   (long long)tape->k_hist_cap);
@@ -513,7 +513,7 @@ int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* 
       if (rc) return rc;
       if (kl > 0) {
         if ((rc = reset_ctrl(nb, kl, -1.0, s))) return rc;
-        nb->rec_u = tape->hist_u;
+        nb->rec_H = tape->hist_H;
         nb->rec_pl = tape->hist_plastic;
         tape->hist_slow = -1;
         for (int64_t done = 0; done < kl;) {
@@ -521,7 +521,7 @@ int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* 
           if ((rc = inner_steps(nb, m, st, dt, cfg->eta, c, s))) return rc;
           done += c;
         }
-        nb->rec_u = nullptr;
+        nb->rec_H = nullptr;
         nb->rec_pl = nullptr;
         tape->hist_slow = l;
       }
@@ -532,12 +532,12 @@ int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* 
         first = false;
       }
       if ((rc = adj_damping(nb, m, st, adj, cfg->eta, dt, s))) return rc;
-      const double* uk = tape->hist_u + (size_t)k * d * n;
+      const void* Hk = (const char*)tape->hist_H + (size_t)k * d * d * n * T;
       const void* plk = m->model == SPH_MODEL_J2
                             ? (const void*)((const char*)tape->hist_plastic + (size_t)k * 7 * n * T)
                             : nullptr;
       const bool has_prev = before[l] + k > 0;
-      if ((rc = adj_solid(nb, m, uk, plk, st, adj, dt, has_prev ? dt : 0.0, s))) return rc;
+      if ((rc = adj_solid(nb, m, Hk, plk, st, adj, dt, has_prev ? dt : 0.0, s))) return rc;
     }
     if (cfg->slow_kind == SPH_SLOW_DIFFUSION) {
       const void* c_before = (const char*)tape->ck_c + (size_t)l * n * T;
@@ -620,15 +620,15 @@ int forward_fixed_enqueue(const sph_nbr* nb, const sph_material* m, const sph_st
     if (tape) tape->k_rec[l] = nk;
     if (nk <= 0) continue;
     if ((rc = reset_ctrl(nb, nk, -1.0, s))) return rc;
-    const bool rec = tape && l == cfg->n_slow - 1 && tape->hist_u && nk <= tape->k_hist_cap &&
+    const bool rec = tape && l == cfg->n_slow - 1 && tape->hist_H && nk <= tape->k_hist_cap &&
                      (m->model != SPH_MODEL_J2 || tape->hist_plastic);
     if (rec) {
-      nb->rec_u = tape->hist_u;
+      nb->rec_H = tape->hist_H;
       nb->rec_pl = tape->hist_plastic;
       recorded = true;
     }
     if ((rc = inner_steps(nb, m, st, dt_s, cfg->eta, (int)nk, s))) return rc;
-    nb->rec_u = nullptr;
+    nb->rec_H = nullptr;
     nb->rec_pl = nullptr;
   }
   if (tape) {

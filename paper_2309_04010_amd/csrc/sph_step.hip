@@ -39,14 +39,17 @@ static Mix<T> mix_view(const sph_material* m, const sph_state* st) {
                 (T)m->rho_l0};
 }
 
-// stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0
-template <typename T, int D, int LPP, int MODEL>
+// stress stage: H = (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a; P(H); PB = P B0.
+// A recorded run (rec_H) keeps the H of every inner step, [k][D*D][n], for
+// the reverse pass; HONLY writes H to rec_H (no step index) and stops there.
+template <typename T, int D, int LPP, int MODEL, bool HONLY = false>
 __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
                                                              const double* __restrict__ u,
                                                              T* __restrict__ PB,
                                                              T* __restrict__ plastic,
                                                              const T* __restrict__ p, Ctrl* ctrl,
                                                              bool gated, T* __restrict__ rec_pl,
+                                                             T* __restrict__ rec_H,
                                                              Bat bt, Mix<T> mx) {
   if (gated && ctrl->done) return;
   const int64_t tile = xcd_tile(g.n_tiles);
@@ -135,6 +138,14 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
       for (int l = 0; l < D; ++l) acc += G[i][l] * B[l][k];
       Hm[i * 3 + k] = acc;
     }
+  if (rec_H) {
+    T* r = HONLY ? rec_H : rec_H + ctrl->k * D * D * n;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) r[(i * D + k) * n + a] = Hm[i * 3 + k];
+  }
+  if constexpr (HONLY) return;
   T pl[7];
   if (model_is<MODEL>(m, SPH_MODEL_J2)) {
 #pragma unroll
@@ -498,10 +509,9 @@ template <typename T, int D>
 __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     int64_t n, double* __restrict__ u, const T* __restrict__ v, const uint8_t* __restrict__ flags,
     const double* __restrict__ V, double rho0, double dt, Ctrl* ctrl, double* partial,
-    bool gated, double* __restrict__ rec_u, Bat bt, const T* __restrict__ cmix, double rho_l0) {
+    bool gated, Bat bt, const T* __restrict__ cmix, double rho_l0) {
   if (gated && ctrl->done) return;
   __shared__ double red[kKeThreads];
-  double* __restrict__ rec = rec_u ? rec_u + ctrl->k * D * n : nullptr;
   const int64_t a0 = blockIdx.x * (int64_t)(kKeThreads * kKeItems) + threadIdx.x;
   // every load of the thread's particles first, then the updates
   double uo[kKeItems][D], Va[kKeItems], dta[kKeItems], ra[kKeItems];
@@ -549,7 +559,6 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         const double vk = (double)vv[it][k];
-        if (rec) rec[k * n + a] = uo[it][k];
         if (!fixed) u[k * n + a] = uo[it][k] + dta[it] * vk;
         v2 += vk * vk;
       }
@@ -998,7 +1007,8 @@ static int solid_stage_l(const sph_nbr* nb, const sph_material* m, const sph_sta
     hipEvent_t pe_ = prof_begin(nb, SPH_KERNEL_STRESS, s);
     k_stress<T, D, LS, MODEL><<<grid, (unsigned)(g.tmax * LS), lds_s, s>>>(
         g, mp, st->u, (T*)st->PB, (T*)st->plastic, (const T*)st->p, nb->ctrl, gated,
-        m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr, bat_view(nb), mix_view<T>(m, st));
+        m->model == SPH_MODEL_J2 ? (T*)nb->rec_pl : nullptr, (T*)nb->rec_H, bat_view(nb),
+        mix_view<T>(m, st));
     prof_end(nb, SPH_KERNEL_STRESS, pe_, s);
     SPH_LAUNCH_CHECK();
   }
@@ -1041,6 +1051,33 @@ static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_sta
     case 8: return solid_stage_l<T, D, 0, 8, -1>(nb, m, st, dt, s, gated);
     default: return solid_stage_l<T, D, 0, 4, -1>(nb, m, st, dt, s, gated);
   }
+}
+
+// H = F - I of st->u into H [D*D][n] (the stress stage's gather alone)
+template <typename T, int D>
+static int displacement_gradient_t(const sph_nbr* nb, const sph_state* st, void* H, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  TileGeo<T> g = tile_geo<T>(nb, prec);
+  if (g.n_tiles == 0) return SPH_OK;
+  const unsigned grid = (unsigned)(8 * ((g.n_tiles + 7) / 8));
+  const size_t lds_s = (size_t)nb->tiling[prec].window_max * 2 * sizeof(vec4<T>);
+  constexpr int L = 2;
+  auto kern = k_stress<T, D, L, SPH_MODEL_LE, true>;
+  int rc = lds_attr(kern, lds_s);
+  if (rc) return rc;
+  kern<<<grid, (unsigned)(g.tmax * L), lds_s, s>>>(g, MatP<T>{}, st->u, nullptr, nullptr, nullptr,
+                                                   nb->ctrl, false, nullptr, (T*)H, bat_view(nb),
+                                                   Mix<T>{});
+  SPH_LAUNCH_CHECK();
+  return SPH_OK;
+}
+
+int displacement_gradient(const sph_nbr* nb, const sph_state* st, void* H, hipStream_t s) {
+  if (st->prec == SPH_F64)
+    return nb->dim == 2 ? displacement_gradient_t<double, 2>(nb, st, H, s)
+                        : displacement_gradient_t<double, 3>(nb, st, H, s);
+  return nb->dim == 2 ? displacement_gradient_t<float, 2>(nb, st, H, s)
+                      : displacement_gradient_t<float, 3>(nb, st, H, s);
 }
 
 int solid_stage(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
@@ -1193,7 +1230,7 @@ static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st
     hipEvent_t pe_ = timed ? prof_begin(nb, SPH_KERNEL_DRIFT_KE, s) : nullptr;
     k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
                                                           nb->V, m->rho0, dt, nb->ctrl,
-                                                          partial, gated, nb->rec_u,
+                                                          partial, gated,
                                                           bat_view(nb), mix_view<T>(m, st).c,
                                                           m->rho_l0);
     SPH_LAUNCH_CHECK();

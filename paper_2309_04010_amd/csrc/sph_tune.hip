@@ -173,7 +173,11 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
   if ((rc = pick(TUNE_MOMENTUM, {2, 4, 8}, solid, &ms))) return rc;
   res.ms_solid = ms;
   if (with_adjoint) {
-    auto adjr = [&]() { return adj_solid(nb, m, st->u, w.plastic, &w, &a, dt_s, dt_s, s); };
+    // the reverse takes the step's H, here that of st->u
+    void* Hs = nullptr;
+    if ((rc = sc.alloc(&Hs, d * d * n * T))) return rc;
+    if ((rc = displacement_gradient(nb, st, Hs, s))) return rc;
+    auto adjr = [&]() { return adj_solid(nb, m, Hs, w.plastic, &w, &a, dt_s, dt_s, s); };
     if ((rc = pick(TUNE_ADJ_STRESS, {1, 2, 4}, adjr, &ms))) return rc;
     if ((rc = pick(TUNE_ADJ_GATHER, {2, 4, 8}, adjr, &ms))) return rc;
     res.ms_adjoint = ms;
