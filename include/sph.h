@@ -472,7 +472,7 @@ int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, con
 
 /* ------------------------------------------------------------------------
  * Launch shapes.  The tiled gather kernels split each particle's neighbour
- * list over 1, 2, 4 or 8 lanes; the damping pass gives each anchor 8, 16, 32
+ * list over 1, 2 or 4 lanes; the damping pass gives each anchor 8, 16, 32
  * or 64 lanes.  The fastest choice depends on the particle set and precision.
  * sph_autotune times every candidate on this handle's data (HIP events, a
  * few launches each, on scratch copies of v, PB and the J2 state: st is not
@@ -484,9 +484,9 @@ int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, con
  * exceed the LDS). */
 typedef struct {
   int32_t lpp_stress;      /* 1, 2, 4 */
-  int32_t lpp_momentum;    /* 2, 4, 8 */
+  int32_t lpp_momentum;    /* 1, 2, 4 */
   int32_t lpp_adj_stress;  /* 1, 2, 4 */
-  int32_t lpp_adj_gather;  /* 2, 4, 8 */
+  int32_t lpp_adj_gather;  /* 1, 2, 4 */
   int32_t damp_lanes[8];   /* per colour: 0, 8, 16, 32, 64 */
   double ms_solid, ms_adjoint, ms_damping_sweep; /* out: best times of sph_autotune */
 } sph_tuning;

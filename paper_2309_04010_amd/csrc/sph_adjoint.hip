@@ -444,7 +444,7 @@ __device__ __forceinline__ void block_grad_add(double (&v)[NV], const int (&slot
 // and a_b: seven values and a pad in 3D (two 16-byte LDS reads per pair),
 // five and a pad in 2D.
 template <typename T, int D, int LPP, int MODEL>
-__global__ __launch_bounds__(128 * LPP) void k_adj_stress(
+__global__ __launch_bounds__(256 * LPP) void k_adj_stress(
     TileGeo<T> g, MatP<T> m, const T* Hin, const T* __restrict__ w,
     const uint8_t* __restrict__ flags, T dt, T inv_rho0, const T* __restrict__ plastic,
     T* __restrict__ plb, const T* __restrict__ p, double* __restrict__ pbar, T* Gb,
@@ -582,7 +582,7 @@ __global__ __launch_bounds__(128 * LPP) void k_adj_stress(
 // w_a -= drift_dt (...) (for a term added after that drift's transpose has
 // already taken the rest of u_bar)
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_adj_gather(
+__global__ __launch_bounds__(256 * LPP) void k_adj_gather(
     TileGeo<T> g, const T* __restrict__ Gb, double* __restrict__ ub, T* __restrict__ w,
     const uint8_t* __restrict__ flags, double drift_dt, Bat bt, int drift_incr = 0) {
   const int64_t tile = xcd_tile(g.n_tiles);
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(256) void k_acd_pre(int64_t n, const T* __restrict_
 
 // pass 2 (tiled gather over the saturation and div_bar)
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_acd_a(
+__global__ __launch_bounds__(256 * LPP) void k_acd_a(
     TileGeo<T> g, const T* __restrict__ sat, const T* __restrict__ divb, const T* __restrict__ Fi,
     T* __restrict__ Jb, T* __restrict__ sbar, T* __restrict__ Fib, T* __restrict__ cb,
     const T* __restrict__ cold, T Dc, int nonlinear, double* __restrict__ gpart) {
@@ -1023,7 +1023,7 @@ __global__ __launch_bounds__(128 * LPP) void k_acd_a(
 // pass 3 (tiled gather over s_bar): a_bar_a = -sum_b (V_a s_bar_b + V_b s_bar_a) . grad0 W;
 // c_bar += a_bar / J, J_bar -= a_bar c / J^2; F_bar and G_bar = F_bar B0^T (into Fib)
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_acd_b(TileGeo<T> g, const T* __restrict__ sbar,
+__global__ __launch_bounds__(256 * LPP) void k_acd_b(TileGeo<T> g, const T* __restrict__ sbar,
                                                      const T* __restrict__ Fi, T* __restrict__ Fib,
                                                      const T* __restrict__ Jb, T* __restrict__ cb,
                                                      const T* __restrict__ cold) {
@@ -1213,7 +1213,7 @@ static int adj_solid_t(const sph_nbr* nb, const sph_material* m, const void* u,
   if (rc) return rc;
   switch (nb->tune.lpp[TUNE_ADJ_GATHER][prec]) {
     case 2: return adj_solid_l<T, D, 0, 2, -1>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
-    case 8: return adj_solid_l<T, D, 0, 8, -1>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
+    case 1: return adj_solid_l<T, D, 0, 1, -1>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
     default: return adj_solid_l<T, D, 0, 4, -1>(nb, m, u, plastic, st, adj, dt, drift_dt, s);
   }
 }

@@ -254,7 +254,9 @@ __device__ __forceinline__ T dw_over_r(T r2, T inv_h, T c5) {
 // momentum sum and its transpose (relative position and a 3 x 3 tensor, twelve
 // values), in 2D the stress stages (two 4-vectors); the formula is
 // ceil((dim + dim^2) / 4) 4-vectors, which covers both.
-inline int tile_tmax(int prec) { return prec == SPH_F64 ? 64 : 128; }
+// Particles per tile: 256 in FP32 (a workgroup of 256 x lanes threads, the
+// window's staging shared by more particles), 64 in FP64.
+inline int tile_tmax(int prec) { return prec == SPH_F64 ? 64 : 256; }
 inline int64_t tile_lds_bytes_per_particle(int prec, int dim) {
   const int t = prec == SPH_F64 ? 8 : 4;
   return (int64_t)t * 4 * ((dim + dim * dim + 3) / 4);

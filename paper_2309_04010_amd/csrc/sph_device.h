@@ -251,10 +251,10 @@ __device__ int constitutive(const MatP<T>& m, const T* H, T* pl, T p, T* P) {
 template <typename T>
 using vec4 = T __attribute__((ext_vector_type(4)));
 
-// lanes per particle of the tile kernels: per-handle choices (Tune), set by
-// sph_autotune; the defaults are the fastest on the 1M-particle plate (the
-// stress kernels with 2, the momentum-shaped ones -- more LDS traffic per
-// pair -- with 4)
+// lanes per particle of the tile kernels (1, 2 or 4; a workgroup is
+// tile_tmax x lanes threads, at most 256 x 4): per-handle choices (Tune), set
+// by sph_autotune, else the defaults (2 for the stress kernels, 4 for the
+// momentum-shaped ones, which read more LDS per pair)
 
 template <typename T>
 struct TileGeo {
@@ -405,31 +405,42 @@ __device__ __forceinline__ WinMap win_map(const TileDesc& td) {
 }
 
 // Blocked-ELL walk: lane h of a particle takes the blocks of four neighbour
-// indices c = h, h + LPP, ...; two registers alternate so that the load of
-// block c + 2 LPP is in flight while block c + LPP is applied (a register
-// copy of a pending load would force the wait early).
+// indices c = h, h + LPP, ...; three registers rotate so that the loads of
+// the next three blocks are in flight while one is applied.  Every load is
+// unconditional (clamped to the particle's last block, which is always in its
+// row), so the wait before a block's use is an exact count of the loads
+// issued after it.
 template <int LPP, typename F>
 __device__ __forceinline__ void ell_walk(const uint16_t* ell, uint32_t ell_off, int tmax, int t,
                                          int h, uint32_t width, F&& f) {
   const uint2* e = reinterpret_cast<const uint2*>(ell + ell_off) + t;
   const int nb4 = (int)(width >> 2);
-  uint2 bA = make_uint2(0u, 0u), bB = make_uint2(0u, 0u);
-  if (h < nb4) bA = e[(int64_t)h * tmax];
-  if (h + LPP < nb4) bB = e[(int64_t)(h + LPP) * tmax];
-  for (int c = h; c < nb4; c += 2 * LPP) {
-    f(bA.x & 0xFFFFu);
-    f(bA.x >> 16);
-    f(bA.y & 0xFFFFu);
-    f(bA.y >> 16);
-    if (c + 2 * LPP < nb4) bA = e[(int64_t)(c + 2 * LPP) * tmax];
-    if (c + LPP < nb4) {
-      f(bB.x & 0xFFFFu);
-      f(bB.x >> 16);
-      f(bB.y & 0xFFFFu);
-      f(bB.y >> 16);
-      if (c + 3 * LPP < nb4) bB = e[(int64_t)(c + 3 * LPP) * tmax];
-    }
+  if (h >= nb4) return;
+  const int last = nb4 - 1;
+  auto ld = [&](int c) -> uint2 { return e[(int64_t)(c < last ? c : last) * tmax]; };
+  auto apply = [&](uint2 b) {
+    f(b.x & 0xFFFFu);
+    f(b.x >> 16);
+    f(b.y & 0xFFFFu);
+    f(b.y >> 16);
+  };
+  // the blocks this lane takes, in full rounds of three and a remainder; the
+  // remainder reads the registers the last round loaded, so the loads stay
+  // at the top of each round
+  const int cnt = (nb4 - h + LPP - 1) / LPP;
+  const int full = cnt / 3, rem = cnt - 3 * full;
+  uint2 b0 = ld(h), b1 = ld(h + LPP), b2 = ld(h + 2 * LPP);
+  int c = h;
+  for (int i = 0; i < full; ++i, c += 3 * LPP) {
+    apply(b0);
+    b0 = ld(c + 3 * LPP);
+    apply(b1);
+    b1 = ld(c + 4 * LPP);
+    apply(b2);
+    b2 = ld(c + 5 * LPP);
   }
+  if (rem >= 1) apply(b0);
+  if (rem >= 2) apply(b1);
 }
 
 template <typename T>

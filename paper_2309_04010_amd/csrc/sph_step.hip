@@ -43,7 +43,7 @@ static Mix<T> mix_view(const sph_material* m, const sph_state* st) {
 // A recorded run (rec_H) keeps the H of every inner step, [k][D*D][n], for
 // the reverse pass; HONLY writes H to rec_H (no step index) and stops there.
 template <typename T, int D, int LPP, int MODEL, bool HONLY = false>
-__global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
+__global__ __launch_bounds__(256 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
                                                              const double* __restrict__ u,
                                                              T* __restrict__ PB,
                                                              T* __restrict__ plastic,
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(128 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
 // the build: the window holds the relative position and V_b PB_b, twelve
 // values in 3D, and the pair loop needs no neighbour volume.
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
+__global__ __launch_bounds__(256 * LPP) void k_momentum(TileGeo<T> g,
                                                                  const T* __restrict__ PB,
                                                                  T* __restrict__ v,
                                                                  T* __restrict__ acc_out,
@@ -317,9 +317,11 @@ __global__ __launch_bounds__(128 * LPP) void k_momentum(TileGeo<T> g,
 // q = beta / (1 - beta (i_a + i_b)), precomputed per run with i_a, i_b.
 //
 // The anchor's 2^d-cell block lives in LDS as one 4-vector per particle
-// (velocity, inverse mass).  A row is a level of the schedule, or a chunk of
-// at most G of its pairs; its pairs share no particle and run on the group's
-// lanes in parallel, the rows in order.  Row words and (pair word, q) records
+// (velocity, inverse mass), and a spare zero slot after it.  A row is a level
+// of the schedule, or a chunk of at most G of its pairs; its pairs share no
+// particle and run on the group's lanes in parallel, the rows in order.  A
+// lane without a pair in a row updates the spare slot with q = 0 (no change),
+// so the row body has no branch, and only the velocity is written back.  Row words and (pair word, q) records
 // stream from memory through two register rings (the row word 2K steps
 // ahead, the record K steps ahead), so the serial row loop has one LDS round
 // trip per row and the LDS holds only the blocks: many wavefronts share a
@@ -353,7 +355,11 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
   constexpr int SB = 8;  // block particles per lane in flight while staging
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int grp = threadIdx.x / G, lg = threadIdx.x % G;
-  const size_t per = ((size_t)bmax * sizeof(vec4<T>) + 15) & ~(size_t)15;
+  const size_t per = (((size_t)bmax + 1) * sizeof(vec4<T>) + 15) & ~(size_t)15;
+  // a lane without a pair in a row updates the group's spare slot (index
+  // bmax, zero, with q = 0: no change), so the row body has no branch
+  constexpr uint32_t S4 = sizeof(vec4<T>);
+  const uint32_t idle_w = ((uint32_t)bmax * S4) | (((uint32_t)bmax * S4) << 16);
   unsigned char* svb = smem_raw + grp * per;  // [bmax] (v, inverse mass), by byte offset
   vec4<T>* sv = reinterpret_cast<vec4<T>*>(svb);
   const int64_t ai = a_begin + (int64_t)blockIdx.x * APW + grp;
@@ -416,15 +422,17 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
     for (int e = 0; e < SB; ++e)
       if (l0 + e * G < nblk) sv[l0 + e * G] = x[e];
   }
+  if (lg == 0) sv[bmax] = vec4<T>{T(0), T(0), T(0), T(0)};
   __syncthreads();
   for (int t0 = 0; __any(t0 < nrw); t0 += K) {
     const uint32_t* pi = REV ? rp - t0 : rp + t0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const PairQ<T> pq = ring[k];
-      if (pq.w != kNoPair) {
-        vec4<T>* pa = reinterpret_cast<vec4<T>*>(svb + (pq.w & 0xFFFFu));
-        vec4<T>* pb = reinterpret_cast<vec4<T>*>(svb + (pq.w >> 16));
+      const uint32_t w = pq.w == kNoPair ? idle_w : pq.w;
+      {
+        vec4<T>* pa = reinterpret_cast<vec4<T>*>(svb + (w & 0xFFFFu));
+        vec4<T>* pb = reinterpret_cast<vec4<T>*>(svb + (w >> 16));
         vec4<T> va = *pa, vb = *pb;
         const T ka = va.w * pq.q, kb = vb.w * pq.q;
         if constexpr (!REV) {
@@ -445,8 +453,10 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
           vb.y -= sy;
           vb.z -= sz;
         }
-        *pa = va;
-        *pb = vb;
+        // the inverse mass (w) stays as staged
+        struct V3 { T x, y, z; };
+        *reinterpret_cast<V3*>(pa) = V3{va.x, va.y, va.z};
+        *reinterpret_cast<V3*>(pb) = V3{vb.x, vb.y, vb.z};
       }
       // refill after the record's last use, into the same registers (a
       // copy would have to wait for the load); rwr[k] holds the row word of
@@ -667,7 +677,7 @@ __device__ __forceinline__ void inv_d(const T* A, T det, T* Ai) {
 // grad0 W, the flux is q = -D w g with w = a (nonlinear) or 1, and what is
 // stored is the reference (Piola) flux J F^-1 q.
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_diff_grad(TileGeo<T> g, const T* __restrict__ f,
+__global__ __launch_bounds__(256 * LPP) void k_diff_grad(TileGeo<T> g, const T* __restrict__ f,
                                                          const T* __restrict__ Fi,
                                                          T* __restrict__ q, T Dc, int nonlinear,
                                                          Bat bt) {
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(128 * LPP) void k_diff_grad(TileGeo<T> g, const T* 
 // displacement), kept as F^-1 in Fi [D*D][n], and the saturation c / det F
 // in sat [n]
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_diff_F(TileGeo<T> g, const double* __restrict__ u,
+__global__ __launch_bounds__(256 * LPP) void k_diff_F(TileGeo<T> g, const double* __restrict__ u,
                                                       const T* __restrict__ c, T* __restrict__ Fi,
                                                       T* __restrict__ sat) {
   const int64_t tile = xcd_tile(g.n_tiles);
@@ -867,7 +877,7 @@ __global__ __launch_bounds__(128 * LPP) void k_diff_F(TileGeo<T> g, const double
 // once per lane.  With Fi (coupled), c is the content per reference volume:
 // the Dirichlet value is c_bc J and p = C (c / J - c0).
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_diff_div(TileGeo<T> g, T* __restrict__ c,
+__global__ __launch_bounds__(256 * LPP) void k_diff_div(TileGeo<T> g, T* __restrict__ c,
                                                         const T* __restrict__ q, T* __restrict__ p,
                                                         const uint8_t* __restrict__ flags, T dt,
                                                         T c_bc, T Cs, T c0, Bat bt,
@@ -1048,7 +1058,7 @@ static int solid_stage_t(const sph_nbr* nb, const sph_material* m, const sph_sta
   if (rc) return rc;
   switch (lm) {
     case 2: return solid_stage_l<T, D, 0, 2, -1>(nb, m, st, dt, s, gated);
-    case 8: return solid_stage_l<T, D, 0, 8, -1>(nb, m, st, dt, s, gated);
+    case 1: return solid_stage_l<T, D, 0, 1, -1>(nb, m, st, dt, s, gated);
     default: return solid_stage_l<T, D, 0, 4, -1>(nb, m, st, dt, s, gated);
   }
 }
@@ -1105,7 +1115,7 @@ constexpr int damp_width_index() {
 template <typename T>
 static size_t damp_lds_per_anchor(const sph_nbr* nb, int col) {
   const size_t bmax = (size_t)std::max<int64_t>(nb->damp_bmax[col], 1);
-  return (bmax * sizeof(vec4<T>) + 15) & ~(size_t)15;
+  return ((bmax + 1) * sizeof(vec4<T>) + 15) & ~(size_t)15;  // + the idle lanes' slot
 }
 
 template <typename T, int D, int G, bool REV>
@@ -1132,7 +1142,7 @@ template <typename T>
 static int damp_prepare_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                           double eta, double dt, hipStream_t s) {
   // pair words hold LDS byte offsets (16 bits), records 32-bit byte offsets
-  if ((int64_t)nb->damp_block_max * (int64_t)sizeof(vec4<T>) > 65535 ||
+  if ((int64_t)(nb->damp_block_max + 1) * (int64_t)sizeof(vec4<T>) > 65535 ||
       (nb->n_upairs + 1) * (int64_t)sizeof(PairQ<T>) > (int64_t)0xFFFFFFFF) {
     set_error("damping sweep: anchor blocks of %lld particles or %lld pairs exceed its addressing",
               (long long)nb->damp_block_max, (long long)nb->n_upairs);
@@ -1418,7 +1428,7 @@ static int diffusion_coupled_t(const sph_nbr* nb, const sph_material* m, const s
 // evaluation would, where an exact g_a would leave a residual force of the
 // positions' rounding on every particle (visible in FP32 on thin bodies).
 template <typename T, int D, int LPP>
-__global__ __launch_bounds__(128 * LPP) void k_gsum(TileGeo<T> g, T* __restrict__ gs) {
+__global__ __launch_bounds__(256 * LPP) void k_gsum(TileGeo<T> g, T* __restrict__ gs) {
   const int64_t tile = xcd_tile(g.n_tiles);
   if (tile >= g.n_tiles) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -68,11 +68,11 @@ extern "C" int sph_set_tuning(sph_nbr* nb, int prec, const sph_tuning* t) {
     set_error("bad arguments");
     return SPH_E_ARG;
   }
-  auto ok_s = [](int v) { return v == 1 || v == 2 || v == 4; };
-  auto ok_m = [](int v) { return v == 2 || v == 4 || v == 8; };
-  if (!ok_s(t->lpp_stress) || !ok_m(t->lpp_momentum) || !ok_s(t->lpp_adj_stress) ||
-      !ok_m(t->lpp_adj_gather)) {
-    set_error("lanes per particle: stress kernels 1, 2 or 4; momentum-shaped kernels 2, 4 or 8");
+  // a tile's workgroup is tile_tmax x lanes threads, at most 1024
+  auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
+  if (!ok(t->lpp_stress) || !ok(t->lpp_momentum) || !ok(t->lpp_adj_stress) ||
+      !ok(t->lpp_adj_gather)) {
+    set_error("lanes per particle of the tiled kernels: 1, 2 or 4");
     return SPH_E_ARG;
   }
   for (int c = 0; c < 8; ++c)
@@ -170,7 +170,7 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
   double ms = 0.0;
   if ((rc = pick(TUNE_STRESS, {1, 2, 4}, solid, &ms))) return rc;
   res.ms_solid = ms;
-  if ((rc = pick(TUNE_MOMENTUM, {2, 4, 8}, solid, &ms))) return rc;
+  if ((rc = pick(TUNE_MOMENTUM, {1, 2, 4}, solid, &ms))) return rc;
   res.ms_solid = ms;
   if (with_adjoint) {
     // the reverse takes the step's H, here that of st->u
@@ -179,7 +179,7 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     if ((rc = displacement_gradient(nb, st, Hs, s))) return rc;
     auto adjr = [&]() { return adj_solid(nb, m, Hs, w.plastic, &w, &a, dt_s, dt_s, s); };
     if ((rc = pick(TUNE_ADJ_STRESS, {1, 2, 4}, adjr, &ms))) return rc;
-    if ((rc = pick(TUNE_ADJ_GATHER, {2, 4, 8}, adjr, &ms))) return rc;
+    if ((rc = pick(TUNE_ADJ_GATHER, {1, 2, 4}, adjr, &ms))) return rc;
     res.ms_adjoint = ms;
     if ((rc = grad_reduce(nb, a.grad, s))) return rc;  // clears the partials it accumulated
   }
