@@ -606,7 +606,18 @@ __global__ void k_sched_fill(const uint32_t* key, const uint32_t* cs, const int6
 }
 
 // ---------------------------------------------------------------------------
-// tiles: ELL of window-local neighbour indices
+// tiles: ELL of window-local neighbour indices.  The order of a particle's
+// neighbours is free (it only orders the terms of its sums), and is chosen
+// for the LDS banks: a window particle's staged values sit at a 16-byte (or
+// 48-byte) stride, so eight lanes that read eight windows slots distinct mod
+// 8 hit distinct groups of four banks.  Entry p of tile particle t takes, in
+// ascending order within the class, a neighbour whose slot is (t + p) mod 8
+// when one is left (else the next class that has one); the eight lanes of an
+// eighth of a wavefront -- eight particles at one entry with one lane per
+// particle, or four particles at entries p and p + 4 with two -- then read
+// distinct classes wherever the classes allow.
+constexpr int kEllSpread = 256;  // longer lists keep ascending order
+
 __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __restrict__ off,
                            const uint32_t* __restrict__ idx, int tmax, uint16_t* __restrict__ ell,
                            int32_t* err) {
@@ -623,6 +634,11 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
     } else {
       own = td.count0 > 0 ? td.own_base : td.own_base1;  // unused column: any valid index
     }
+    auto at = [&](uint32_t j) -> uint16_t* {
+      return ell + (int64_t)td.ell_off + (int64_t)(j >> 2) * 4 * tmax + 4 * t + (j & 3);
+    };
+    uint16_t L[kEllSpread];
+    const bool spread = deg <= kEllSpread;
     for (uint32_t j = 0; j < td.width; ++j) {  // width: multiple of 4
       uint32_t loc = own;
       if ((int64_t)j < deg) {
@@ -639,8 +655,21 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
           base += td.run_count[r];
         }
         if (!found) atomicOr(err, 4);
+        if (spread) L[j] = (uint16_t)loc;
       }
-      ell[(int64_t)td.ell_off + (int64_t)(j >> 2) * 4 * tmax + 4 * t + (j & 3)] = (uint16_t)loc;
+      *at(j) = (uint16_t)loc;
+    }
+    if (!spread) continue;
+    int cur[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // next candidate of each class (ascending)
+    for (int p = 0; p < (int)deg; ++p) {
+      const int d = (t + p) & 7;
+      int pick = -1;
+      for (int k = 0; k < 8 && pick < 0; ++k) {
+        const int r = (d + k) & 7;
+        while (cur[r] < (int)deg && (L[cur[r]] & 7) != r) ++cur[r];
+        if (cur[r] < (int)deg) pick = cur[r]++;
+      }
+      *at((uint32_t)p) = L[pick];
     }
   }
 }
@@ -726,60 +755,198 @@ __global__ void k_lev_fill(const int64_t* __restrict__ aoff, const uint32_t* __r
   dloff[b + prev + 1] = (uint16_t)(hi - lo);
 }
 
-// Rows of the damping sweep for one lane-group width G: the pairs of each
-// level in consecutive chunks of at most G (a level's pairs share no
-// particle, so splitting it keeps the result).  A row word is
-// first | end << 16, relative to the anchor's first pair; an empty row is 0.
-// Each anchor's list is padded with empty rows to the longest list of its
-// wavefront (64 / G consecutive anchors of its colour) and framed by
-// kDampRowPad empty rows on either side, so that the sweep reads rows ahead
-// in either direction without bounds tests.
-__global__ void k_rows_count(const uint32_t* __restrict__ anlev, const uint16_t* __restrict__ dloff,
-                             const uint32_t* __restrict__ dloff_base, int64_t n_anchors, int G,
-                             int64_t* __restrict__ cnt) {
-  const int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (ai >= n_anchors) return;
-  const uint16_t* lo = dloff + dloff_base[ai];
-  const int nl = (int)anlev[ai];
-  int64_t r = 0;
-  for (int L = 0; L < nl; ++L) r += ((int)lo[L + 1] - (int)lo[L] + G - 1) / G;
-  cnt[ai] = r;
-}
+// Joint rows of the damping sweep (setup, on the host).  A wavefront sweeps
+// APW = 64 / G anchors of one colour together: each of its G-lane groups
+// stages one anchor's block, and a row of the wavefront's schedule holds up
+// to 64 pairs from any of its anchors, one per lane.  In a row an anchor
+// contributes pairs of one level only (the pairs of a level share no
+// particle, nor do the blocks of one colour), and its levels come in order,
+// so the sweep is the canonical one; the lane order inside a row is free and
+// is chosen so that each eighth of the wavefront's LDS accesses spreads over
+// the banks.  Rows are filled by list scheduling:
+// the anchors with the most levels still to go take their next level first,
+// a level that does not fit the row's free lanes is split.  The anchors of a
+// colour are grouped into wavefronts by descending level count, so anchors
+// that need as many rows share one.  Per width G:
+//   drow       row words first | end << 16, relative to the wavefront's first
+//              record; each wavefront's list framed by kDampRowPad empty rows
+//   drow_base  [n_waves + 1] start of each framed list
+//   dwave      [n_waves][APW] anchors of each wavefront (0xFFFFFFFF: none)
+//   dwrec      [n_waves] first record of each wavefront, from its colour's
+//              first pair
+//   djinfo     [n_upairs] record position of each canonical pair | its
+//              anchor's group << 28
+// A wavefront's records must stay below 2^16 (the row words' range); a width
+// whose wavefronts exceed it is marked unusable.
+template <typename T>
+static int dalloc(T** p, int64_t count);
 
-struct ColourOffsets {
-  int64_t off[9];
-};
-
-// padded list length of every anchor: its wavefront's longest list + frames
-__global__ void k_rows_wave(const int64_t* __restrict__ cnt, ColourOffsets co, int64_t n_anchors,
-                            int apw, int64_t* __restrict__ padded) {
-  const int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (ai >= n_anchors) return;
-  int c = 0;
-  while (c < 7 && ai >= co.off[c + 1]) ++c;
-  const int64_t w0 = co.off[c] + (ai - co.off[c]) / apw * apw;
-  const int64_t w1 = w0 + apw < co.off[c + 1] ? w0 + apw : co.off[c + 1];
-  int64_t m = 0;
-  for (int64_t a = w0; a < w1; ++a) m = cnt[a] > m ? cnt[a] : m;
-  padded[ai] = m + 2 * kDampRowPad;
-}
-
-__global__ void k_rows_fill(const uint32_t* __restrict__ anlev, const uint16_t* __restrict__ dloff,
-                            const uint32_t* __restrict__ dloff_base, const int64_t* __restrict__ base,
-                            int64_t n_anchors, int G, uint32_t* __restrict__ rows) {
-  const int64_t ai = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (ai >= n_anchors) return;
-  const uint16_t* lo = dloff + dloff_base[ai];
-  const int nl = (int)anlev[ai];
-  const int64_t b = base[ai], e = base[ai + 1];
-  int64_t j = b;
-  for (int r = 0; r < kDampRowPad; ++r) rows[j++] = 0u;
-  for (int L = 0; L < nl; ++L)
-    for (uint32_t f = lo[L]; f < lo[L + 1]; f += (uint32_t)G) {
-      const uint32_t en = f + (uint32_t)G < lo[L + 1] ? f + (uint32_t)G : lo[L + 1];
-      rows[j++] = f | (en << 16);
+static int build_joint_rows(sph_nbr* nb, hipStream_t s) {
+  const int64_t na = nb->n_anchors, np = nb->n_upairs;
+  std::vector<uint32_t> anlev(na), dloff_base(na);
+  std::vector<int64_t> aoff(na + 1);
+  int64_t nloff = 0;
+  if (na > 0) {
+    SPH_HIP(hipMemcpyAsync(anlev.data(), nb->anlev, na * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(dloff_base.data(), nb->dloff_base, na * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipMemcpyAsync(aoff.data(), nb->aoff, (na + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+    nloff = (int64_t)dloff_base[na - 1] + anlev[na - 1] + 1;
+  } else {
+    aoff[0] = 0;
+  }
+  std::vector<uint16_t> dloff(std::max<int64_t>(nloff, 1));
+  if (nloff > 0) {
+    SPH_HIP(hipMemcpyAsync(dloff.data(), nb->dloff, nloff * sizeof(uint16_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<uint32_t> info(std::max<int64_t>(np, 1)), dpair(std::max<int64_t>(np, 1));
+  if (np > 0) {
+    SPH_HIP(hipMemcpyAsync(dpair.data(), nb->dpair, np * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+  }
+  struct RowPair {
+    int64_t i;        // canonical pair
+    uint32_t g;       // its anchor's group in the wavefront
+    uint32_t qa, qb;  // slot mod 8 of the two particles
+  };
+  std::vector<RowPair> rp;
+  for (int gi = 0; gi < kDampWidths; ++gi) {
+    const int apw = 64 / (8 << gi);
+    std::vector<uint32_t> rows, wave, wrec;
+    std::vector<int64_t> rbase;
+    bool ok = true;
+    int64_t nw = 0;
+    for (int c = 0; c < 8; ++c) {
+      nb->dwave_off[gi][c] = nw;
+      const int64_t a0 = nb->color_off[c], a1 = nb->color_off[c + 1];
+      std::vector<int64_t> order;
+      for (int64_t a = a0; a < a1; ++a) order.push_back(a);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int64_t x, int64_t y) { return anlev[x] > anlev[y]; });
+      const int64_t po = a0 < na ? aoff[a0] : np;
+      const uint32_t per = (uint32_t)std::max<int64_t>(nb->damp_bmax[c], 1) + 1;  // slots per block
+      int64_t rec_c = 0;  // records of the colour so far
+      for (size_t w0 = 0; w0 < order.size(); w0 += apw, ++nw) {
+        const int k = (int)std::min<size_t>(apw, order.size() - w0);
+        int64_t wa[8];
+        int lev[8], taken[8];
+        for (int g = 0; g < apw; ++g) {
+          wave.push_back(g < k ? (uint32_t)order[w0 + g] : 0xFFFFFFFFu);
+          if (g < k) {
+            wa[g] = order[w0 + g];
+            lev[g] = 0;
+            taken[g] = 0;
+          }
+        }
+        wrec.push_back((uint32_t)rec_c);
+        rbase.push_back((int64_t)rows.size());
+        for (int r = 0; r < kDampRowPad; ++r) rows.push_back(0u);
+        int64_t cur = 0;  // records of this wavefront so far
+        for (;;) {
+          int idx[8], m = 0;
+          for (int g = 0; g < k; ++g)
+            if (lev[g] < (int)anlev[wa[g]]) idx[m++] = g;
+          if (m == 0) break;
+          std::stable_sort(idx, idx + m, [&](int x, int y) {
+            return (int)anlev[wa[x]] - lev[x] > (int)anlev[wa[y]] - lev[y];
+          });
+          const int64_t first = cur;
+          int free = 64;
+          rp.clear();
+          for (int j = 0; j < m && free > 0; ++j) {
+            const int g = idx[j];
+            const uint16_t* lo = dloff.data() + dloff_base[wa[g]];
+            const int size = (int)lo[lev[g] + 1] - (int)lo[lev[g]];
+            const int take = std::min(free, size - taken[g]);
+            const int64_t p0 = aoff[wa[g]] + lo[lev[g]] + taken[g];
+            for (int t = 0; t < take; ++t) {
+              const uint32_t wd = dpair[p0 + t];
+              const uint32_t sa_ = (uint32_t)g * per + (wd & 0xFFFFu), sb_ = (uint32_t)g * per + (wd >> 16);
+              rp.push_back(RowPair{p0 + t, (uint32_t)g, sa_ & 7u, sb_ & 7u});
+            }
+            cur += take;
+            free -= take;
+            taken[g] += take;
+            if (taken[g] == size) {
+              ++lev[g];
+              taken[g] = 0;
+            }
+          }
+          // lanes in eighths of 8: within an eighth, pairs whose particles'
+          // 16-byte LDS slots fall on distinct groups of four banks (slot mod
+          // 8) first -- the pairs of a row are independent, so their lane
+          // order is free; on the 1M plate this takes a fifth of the sweep's
+          // LDS bank-conflict cycles away
+          {
+            std::vector<char> used(rp.size(), 0);
+            int64_t pos = first;
+            size_t left = rp.size();
+            while (left > 0) {
+              const int q = (int)std::min<size_t>(8, left);
+              uint32_t ma = 0, mb = 0;
+              int got = 0;
+              for (size_t j = 0; j < rp.size() && got < q; ++j)
+                if (!used[j] && !((ma >> rp[j].qa) & 1u) && !((mb >> rp[j].qb) & 1u)) {
+                  used[j] = 1;
+                  ma |= 1u << rp[j].qa;
+                  mb |= 1u << rp[j].qb;
+                  info[rp[j].i] = (uint32_t)(po + rec_c + pos++) | (rp[j].g << 28);
+                  ++got;
+                }
+              for (size_t j = 0; j < rp.size() && got < q; ++j)
+                if (!used[j] && !(((ma >> rp[j].qa) & 1u) && ((mb >> rp[j].qb) & 1u))) {
+                  used[j] = 1;
+                  ma |= 1u << rp[j].qa;
+                  mb |= 1u << rp[j].qb;
+                  info[rp[j].i] = (uint32_t)(po + rec_c + pos++) | (rp[j].g << 28);
+                  ++got;
+                }
+              for (size_t j = 0; j < rp.size() && got < q; ++j)
+                if (!used[j]) {
+                  used[j] = 1;
+                  info[rp[j].i] = (uint32_t)(po + rec_c + pos++) | (rp[j].g << 28);
+                  ++got;
+                }
+              left -= (size_t)q;
+            }
+          }
+          if (cur > 65535) ok = false;
+          rows.push_back((uint32_t)(first & 0xFFFF) | ((uint32_t)(cur & 0xFFFF) << 16));
+        }
+        for (int r = 0; r < kDampRowPad; ++r) rows.push_back(0u);
+        rec_c += cur;
+      }
     }
-  while (j < e) rows[j++] = 0u;
+    nb->dwave_off[gi][8] = nw;
+    rbase.push_back((int64_t)rows.size());
+    if (np + 1 >= (int64_t)(1u << 28)) ok = false;
+    nb->dwidth_ok[gi] = ok;
+    if (wave.empty()) wave.push_back(0xFFFFFFFFu);
+    if (wrec.empty()) wrec.push_back(0u);
+    if (rows.empty()) rows.push_back(0u);
+    int rc;
+    if ((rc = dalloc(&nb->drow[gi], (int64_t)rows.size())) ||
+        (rc = dalloc(&nb->drow_base[gi], (int64_t)rbase.size())) ||
+        (rc = dalloc(&nb->dwave[gi], (int64_t)wave.size())) ||
+        (rc = dalloc(&nb->dwrec[gi], (int64_t)wrec.size())) ||
+        (rc = dalloc(&nb->djinfo[gi], std::max<int64_t>(np, 1))))
+      return rc;
+    SPH_HIP(hipMemcpyAsync(nb->drow[gi], rows.data(), rows.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s));
+    SPH_HIP(hipMemcpyAsync(nb->drow_base[gi], rbase.data(), rbase.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    SPH_HIP(hipMemcpyAsync(nb->dwave[gi], wave.data(), wave.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s));
+    SPH_HIP(hipMemcpyAsync(nb->dwrec[gi], wrec.data(), wrec.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, s));
+    if (np > 0)
+      SPH_HIP(hipMemcpyAsync(nb->djinfo[gi], info.data(), np * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s));
+    SPH_HIP(hipStreamSynchronize(s));  // the host vectors are reused
+  }
+  return SPH_OK;
 }
 
 // host planning of row tiles (setup only)
@@ -940,10 +1107,10 @@ static void free_nbr(sph_nbr* h) {
                   (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg, h->dwq[0], h->dwq[1],
                   h->imass[0], h->imass[1]})
     if (p) hipFree(p);
-  for (int gi = 0; gi < kDampWidths; ++gi) {
-    if (h->drow[gi]) hipFree(h->drow[gi]);
-    if (h->drow_base[gi]) hipFree(h->drow_base[gi]);
-  }
+  for (int gi = 0; gi < kDampWidths; ++gi)
+    for (void* p : {(void*)h->drow[gi], (void*)h->drow_base[gi], (void*)h->dwave[gi],
+                    (void*)h->dwrec[gi], (void*)h->djinfo[gi]})
+      if (p) hipFree(p);
   free_graph_cache(h);
   if (h->ctrl_host) hipHostFree(h->ctrl_host);
   if (h->prof) {
@@ -1237,9 +1404,10 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
       nb->damp_block_max = std::max(nb->damp_block_max, nb->damp_bmax[c]);
       nb->damp_pairs_max = std::max(nb->damp_pairs_max, nb->damp_pmax[c]);
     }
-    // LDS of one anchor in the FP64 sweep: its block (v, inverse mass)
-    const int64_t need = nb->damp_block_max * (4 * 8);
-    if (need > kDampLdsBudget || nb->damp_pairs_max > 65535) {
+    // LDS of one anchor in the FP64 sweep: its block (v, inverse mass) and a
+    // spare slot, addressed by 16-bit byte offsets
+    const int64_t need = (nb->damp_block_max + 1) * (4 * 8);
+    if (need > std::min<int64_t>(kDampLdsBudget, 65536) || nb->damp_pairs_max > 65535) {
       set_error("an anchor block needs %lld B of LDS for the damping sweep (limit %lld): "
                 "neighbourhoods this dense are not supported", (long long)need,
                 (long long)kDampLdsBudget);
@@ -1265,45 +1433,7 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
                                                   nb->dloff_base);
       SPH_LAUNCH_CHECK();
     }
-    // rows of every lane-group width; after the last list, empty rows twice
-    // as many as the longest list holds (read, from its middle, by the unused
-    // lane groups of a colour's last wavefront)
-    ColourOffsets co;
-    for (int c = 0; c < 9; ++c) co.off[c] = nb->color_off[c];
-    int64_t* lpad = nullptr;
-    if ((rc_ = dalloc(&lpad, base + 1))) return rc_;
-    std::vector<int64_t> hpad(base);
-    for (int gi = 0; gi < kDampWidths; ++gi) {
-      const int G = 8 << gi;
-      if (base > 0) {
-        k_rows_count<<<nblocks(base, 256), 256, 0, s>>>(nb->anlev, nb->dloff, nb->dloff_base, base, G,
-                                                        lcnt);
-        SPH_LAUNCH_CHECK();
-        k_rows_wave<<<nblocks(base, 256), 256, 0, s>>>(lcnt, co, base, 64 / G, lpad);
-        SPH_LAUNCH_CHECK();
-      }
-      if ((rc_ = dalloc(&nb->drow_base[gi], base + 1))) return rc_;
-      if ((rc_ = scan_exclusive(lpad, nb->drow_base[gi], base, nb->drow_base[gi] + base, s)))
-        return rc_;
-      int64_t nrows = 0;
-      SPH_HIP(hipMemcpyAsync(&nrows, nb->drow_base[gi] + base, sizeof(int64_t), hipMemcpyDeviceToHost,
-                             s));
-      if (base > 0)
-        SPH_HIP(hipMemcpyAsync(hpad.data(), lpad, base * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-      SPH_HIP(hipStreamSynchronize(s));
-      int64_t longest = 2 * kDampRowPad;
-      for (int64_t a = 0; a < base; ++a) longest = std::max(longest, hpad[a]);
-      nb->drow_empty[gi] = nrows + longest;
-      if ((rc_ = dalloc(&nb->drow[gi], nrows + 2 * longest))) return rc_;
-      SPH_HIP(hipMemsetAsync(nb->drow[gi] + nrows, 0, 2 * longest * sizeof(uint32_t), s));
-      if (base > 0) {
-        k_rows_fill<<<nblocks(base, 64), 64, 0, s>>>(nb->anlev, nb->dloff, nb->dloff_base,
-                                                     nb->drow_base[gi], base, G, nb->drow[gi]);
-        SPH_LAUNCH_CHECK();
-      }
-    }
-    SPH_HIP(hipStreamSynchronize(s));
-    hipFree(lpad);
+    if ((rc_ = build_joint_rows(nb, s))) return rc_;
     // first pair of every colour
     for (int c = 0; c < 9; ++c) {
       const int64_t a = std::min<int64_t>(nb->color_off[c], base);

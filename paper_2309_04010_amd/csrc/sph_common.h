@@ -139,10 +139,11 @@ struct Tiling {
 
 // damping pair word: a_loc | b_loc << 16 (locals inside the anchor's
 // 2^d-cell block, in ascending sorted order); each anchor's level offsets sit
-// in dloff, its rows for lane-group width 8 << i in drow[i]
+// in dloff; the joint rows of the wavefronts for lane-group width 8 << i
+// (64 >> (3 + i) anchors per wavefront) in drow[i], dwave[i], ...
 constexpr int kDampLocBits = 16;
 constexpr int kDampWidths = 4;          // lane-group widths 8, 16, 32, 64
-constexpr int kDampRowPad = 24;         // empty rows framing each anchor's row list (3K)
+constexpr int kDampRowPad = 24;         // empty rows framing each wavefront's row list (3K)
 constexpr int kDampMaxLocal = 1 << kDampLocBits;
 constexpr int kDampMaxLevel = 255;      // levels of one anchor (offsets held in 4 registers)
 constexpr int64_t kDampLdsBudget = 159 * 1024;  // gfx950: 160 KB of LDS per workgroup
@@ -185,9 +186,15 @@ struct sph_nbr {
   int64_t damp_pairs_max = 0;        // largest pair count of one anchor
   int64_t damp_bmax[8] = {0};        // the same, per colour (sizes each pass's LDS)
   int64_t damp_pmax[8] = {0};
-  uint32_t* drow[sph::kDampWidths] = {};       // rows (first | end << 16) per lane-group width
-  int64_t* drow_base[sph::kDampWidths] = {};   // [n_anchors + 1] start of each anchor's framed list
-  int64_t drow_empty[sph::kDampWidths] = {};   // middle of the empty rows after the last list
+  // joint rows of the damping sweep per lane-group width (build_joint_rows)
+  uint32_t* drow[sph::kDampWidths] = {};       // row words first | end << 16, framed per wavefront
+  int64_t* drow_base[sph::kDampWidths] = {};   // [n_waves + 1] start of each wavefront's framed list
+  uint32_t* dwave[sph::kDampWidths] = {};      // [n_waves][64 / G] anchors of each wavefront
+  uint32_t* dwrec[sph::kDampWidths] = {};      // [n_waves] first record, from the colour's first pair
+  uint32_t* djinfo[sph::kDampWidths] = {};     // [n_upairs] record position | group << 28
+  int64_t dwave_off[sph::kDampWidths][9] = {}; // first wavefront of each colour
+  bool dwidth_ok[sph::kDampWidths] = {};       // every wavefront's records fit the row words
+  mutable int damp_g_used[2][8] = {};          // widths the per-run records were laid out for
   int64_t damp_pair_off[9] = {};               // first pair of each colour (canonical order)
   float* dgeo32 = nullptr;           // [n_upairs] 2 V_a V_b (dW/dr)/r per pair
   double* dgeo64 = nullptr;

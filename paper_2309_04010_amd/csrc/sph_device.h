@@ -277,10 +277,12 @@ static TileGeo<T> tile_geo(const sph_nbr* nb, int prec) {
   return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5, g.gsum};
 }
 
-// N values per window particle as N/4 whole 4-vectors ([window][N/4]) and a
-// remainder array ([window] of 1 or 2 values) after them, so that every LDS
-// read is aligned and no padding is read: 6 values are one 16-byte and one
-// 8-byte read, 9 values two 16-byte reads and one 4-byte read.
+// N values per window particle as N/4 arrays of 4-vectors ([N/4][window])
+// and a remainder array ([window] of 1 or 2 values) after them, so that every
+// LDS read is aligned, no padding is read, and every array has a 16-byte
+// stride (window slots distinct mod 8 fall on distinct banks): 6 values are
+// one 16-byte and one 8-byte read, 9 values two 16-byte reads and one 4-byte
+// read.
 template <typename T, int N>
 struct Pk {
   static constexpr int Q = N / 4, R = N % 4;
@@ -288,7 +290,7 @@ struct Pk {
   static constexpr size_t bytes = Q * sizeof(vec4<T>) + R * sizeof(T);  // per particle
   __device__ static __forceinline__ void store(unsigned char* lds, uint32_t window, uint32_t l,
                                                const T* v) {
-    vec4<T>* q = reinterpret_cast<vec4<T>*>(lds) + (size_t)l * Q;
+    vec4<T>* q = reinterpret_cast<vec4<T>*>(lds) + l;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       vec4<T> pv;
@@ -296,7 +298,7 @@ struct Pk {
       pv.y = v[4 * j + 1];
       pv.z = v[4 * j + 2];
       pv.w = v[4 * j + 3];
-      q[j] = pv;
+      q[(size_t)j * window] = pv;
     }
     unsigned char* rb = lds + (size_t)window * Q * sizeof(vec4<T>);
     if constexpr (R == 2) {
@@ -311,10 +313,10 @@ struct Pk {
   }
   __device__ static __forceinline__ void load(const unsigned char* lds, uint32_t window,
                                               uint32_t l, T* v) {
-    const vec4<T>* q = reinterpret_cast<const vec4<T>*>(lds) + (size_t)l * Q;
+    const vec4<T>* q = reinterpret_cast<const vec4<T>*>(lds) + l;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const vec4<T> pv = q[j];
+      const vec4<T> pv = q[(size_t)j * window];
       v[4 * j] = pv.x;
       v[4 * j + 1] = pv.y;
       v[4 * j + 2] = pv.z;

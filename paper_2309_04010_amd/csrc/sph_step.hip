@@ -308,29 +308,30 @@ __global__ __launch_bounds__(256 * LPP) void k_momentum(TileGeo<T> g,
   }
 }
 
-// damping: anchors of one colour, G lanes per anchor, 64 / G anchors per
-// wavefront (one workgroup).  The implicit update of one pair, with inverse
-// masses i_a, i_b (zero for a fixed particle, which then acts as infinite
-// mass) and beta = eta dt g_ab <= 0, g_ab = 2 V_a V_b (dW/dr)/r:
+// damping: anchors of one colour, 64 / G anchors per wavefront (one
+// workgroup), G lanes per anchor while staging.  The implicit update of one
+// pair, with inverse masses i_a, i_b (zero for a fixed particle, which then
+// acts as infinite mass) and beta = eta dt g_ab <= 0, g_ab = 2 V_a V_b (dW/dr)/r:
 //   v_ab' = v_ab / (1 - beta (i_a + i_b)),  v_a += beta i_a v_ab',  v_b -= beta i_b v_ab',
 // i.e. v_a += i_a q (v_a - v_b), v_b -= i_b q (v_a - v_b) with
 // q = beta / (1 - beta (i_a + i_b)), precomputed per run with i_a, i_b.
 //
-// The anchor's 2^d-cell block lives in LDS as one 4-vector per particle
-// (velocity, inverse mass), and a spare zero slot after it.  A row is a level
-// of the schedule, or a chunk of at most G of its pairs; its pairs share no
-// particle and run on the group's lanes in parallel, the rows in order.  A
-// lane without a pair in a row updates the spare slot with q = 0 (no change),
-// so the row body has no branch, and only the velocity is written back.  Row words and (pair word, q) records
-// stream from memory through two register rings (the row word 2K steps
-// ahead, the record K steps ahead), so the serial row loop has one LDS round
-// trip per row and the LDS holds only the blocks: many wavefronts share a
-// CU.  The row lists of one wavefront's anchors are padded to one length and
-// framed by empty rows, so the ring reads need no bounds tests; a record is
-// addressed by a 32-bit offset from the colour's first pair, and a pair word
-// holds the two particles' LDS byte offsets.  One wavefront: its LDS
-// accesses complete in issue order, so a row reads what the previous row
-// wrote without a barrier.  The block is written back at the end; anchors
+// Each anchor's 2^d-cell block lives in LDS as one 4-vector per particle
+// (velocity, inverse mass), and a spare zero slot after it.  The wavefront
+// runs the joint rows of its anchors (build_joint_rows): a row holds up to 64
+// pairs, from one level of each anchor at most, one pair per lane; its pairs
+// share no particle, the rows run in order.  A lane without a pair in a row
+// updates the first group's spare slot with q = 0 (no change), so the row
+// body has no branch, and only the velocity is written back.  Row words and
+// (pair word, q) records stream from memory through two register rings (the
+// row word 2K steps ahead, the record K steps ahead), so the serial row loop
+// has one LDS round trip per row and the LDS holds only the blocks: many
+// wavefronts share a CU.  Each wavefront's row list is framed by empty rows,
+// so the ring reads need no bounds tests; a record is addressed by a 32-bit
+// offset from the colour's first pair, and a pair word holds the two
+// particles' LDS byte offsets in the wavefront's blocks.  One wavefront: its
+// LDS accesses complete in issue order, so a row reads what the previous row
+// wrote without a barrier.  The blocks are written back at the end; anchors
 // of one colour touch disjoint blocks.
 //
 // REV: the transposed sweep used by the reverse pass: rows in reverse order
@@ -339,13 +340,13 @@ constexpr uint32_t kNoPair = 0xFFFFFFFFu;  // the record after the last pair hol
 
 template <typename T, int D, int G, bool REV>
 __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c, uint32_t sent,
-                                             int64_t pair_off_c, const T* __restrict__ imass,
+                                             const T* __restrict__ imass,
                                              const uint32_t* __restrict__ rows,
-                                             const int64_t* __restrict__ rbase, int64_t empty_mid,
-                                             const int64_t* __restrict__ aoff,
-                                             const uint32_t* __restrict__ ablk, int64_t a_begin,
-                                             int64_t a_end, int bmax, int64_t n, T* v, Ctrl* ctrl,
-                                             bool gated) {
+                                             const int64_t* __restrict__ rbase,
+                                             const uint32_t* __restrict__ wave_anchor,
+                                             const uint32_t* __restrict__ wave_rec, int64_t w0,
+                                             const uint32_t* __restrict__ ablk, int bmax,
+                                             int64_t n, T* v, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
   constexpr int APW = 64 / G;
   constexpr int K = 8;  // steps of records in flight (deeper rings measured slower)
@@ -353,22 +354,24 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
   // reads row words 2K steps ahead: every row read stays within the frames
   static_assert(3 * K <= kDampRowPad, "row frames too short for the ring");
   constexpr int SB = 8;  // block particles per lane in flight while staging
+  constexpr uint32_t S4 = sizeof(vec4<T>);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int grp = threadIdx.x / G, lg = threadIdx.x % G;
-  const size_t per = (((size_t)bmax + 1) * sizeof(vec4<T>) + 15) & ~(size_t)15;
-  // a lane without a pair in a row updates the group's spare slot (index
-  // bmax, zero, with q = 0: no change), so the row body has no branch
-  constexpr uint32_t S4 = sizeof(vec4<T>);
+  const uint32_t lane = threadIdx.x;
+  // group g's block at byte g * per; slot bmax of group 0 serves the idle lanes
+  const size_t per = ((size_t)bmax + 1) * S4;
   const uint32_t idle_w = ((uint32_t)bmax * S4) | (((uint32_t)bmax * S4) << 16);
-  unsigned char* svb = smem_raw + grp * per;  // [bmax] (v, inverse mass), by byte offset
-  vec4<T>* sv = reinterpret_cast<vec4<T>*>(svb);
-  const int64_t ai = a_begin + (int64_t)blockIdx.x * APW + grp;
-  const bool live = ai < a_end;
-  uint32_t b0 = 0, b2 = 0, b4 = 0, b6 = 0, e0 = 0, e1 = 0, e2 = 0, nblk = 0, lo_rel = 0;
-  const uint32_t* rp = rows + empty_mid;  // row of step 0; then forward, or backward in REV
-  int nrw = 0;
+  vec4<T>* sv = reinterpret_cast<vec4<T>*>(smem_raw + grp * per);
+  const int64_t wv = w0 + blockIdx.x;
+  const uint32_t ai = wave_anchor[wv * APW + grp];
+  const bool live = ai != 0xFFFFFFFFu;
+  const uint32_t lo_rel = wave_rec[wv];
+  const int64_t rb = rbase[wv];
+  const int nrw = (int)(rbase[wv + 1] - rb) - 2 * kDampRowPad;  // the same for all lanes
+  const uint32_t* rp = rows + rb + kDampRowPad + (REV ? nrw - 1 : 0);
+  uint32_t b0 = 0, b2 = 0, b4 = 0, b6 = 0, e0 = 0, e1 = 0, e2 = 0, nblk = 0;
   if (live) {
-    const uint32_t* bl = ablk + 8 * ai;
+    const uint32_t* bl = ablk + 8 * (int64_t)ai;
     b0 = bl[0];
     b2 = bl[2];
     b4 = bl[4];
@@ -377,16 +380,12 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
     e1 = e0 + bl[3];
     e2 = e1 + bl[5];
     nblk = e2 + bl[7];
-    lo_rel = (uint32_t)(aoff[ai] - pair_off_c);
-    const int64_t rb = rbase[ai];
-    nrw = (int)(rbase[ai + 1] - rb) - 2 * kDampRowPad;
-    rp = rows + rb + kDampRowPad + (REV ? nrw - 1 : 0);
   }
   auto row = [&](const uint32_t* p, int k) -> uint32_t { return REV ? p[-k] : p[k]; };
   // this lane's record in a row (the sentinel when the lane has no pair there)
   const unsigned char* dwqb = reinterpret_cast<const unsigned char*>(dwq_c);
   auto rec = [&](uint32_t rw) -> PairQ<T> {
-    const uint32_t i = (rw & 0xFFFFu) + (uint32_t)lg;
+    const uint32_t i = (rw & 0xFFFFu) + lane;
     const uint32_t idx = i < (rw >> 16) ? lo_rel + i : sent;
     return *reinterpret_cast<const PairQ<T>*>(dwqb + (size_t)(idx * (uint32_t)sizeof(PairQ<T>)));
   };
@@ -424,15 +423,15 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
   }
   if (lg == 0) sv[bmax] = vec4<T>{T(0), T(0), T(0), T(0)};
   __syncthreads();
-  for (int t0 = 0; __any(t0 < nrw); t0 += K) {
+  for (int t0 = 0; t0 < nrw; t0 += K) {
     const uint32_t* pi = REV ? rp - t0 : rp + t0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const PairQ<T> pq = ring[k];
       const uint32_t w = pq.w == kNoPair ? idle_w : pq.w;
       {
-        vec4<T>* pa = reinterpret_cast<vec4<T>*>(svb + (w & 0xFFFFu));
-        vec4<T>* pb = reinterpret_cast<vec4<T>*>(svb + (w >> 16));
+        vec4<T>* pa = reinterpret_cast<vec4<T>*>(smem_raw + (w & 0xFFFFu));
+        vec4<T>* pb = reinterpret_cast<vec4<T>*>(smem_raw + (w >> 16));
         vec4<T> va = *pa, vb = *pb;
         const T ka = va.w * pq.q, kb = vb.w * pq.q;
         if constexpr (!REV) {
@@ -475,16 +474,25 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
   }
 }
 
-// Per-run damping coefficients: q of every pair and the inverse mass of
-// every particle depend only on eta dt, rho0, the volumes and the flags,
-// which a multi-time-step run holds fixed, so they are computed once per run
-// (or per call of a lone sweep) and stored beside the pair words.
+// Per-run damping records: the pair word (the two particles' LDS byte
+// offsets in their wavefront's blocks) and q, at the pair's position in the
+// joint rows of its colour's lane-group width.  q and the inverse masses
+// depend only on eta dt, rho0, the volumes and the flags, which a
+// multi-time-step run holds fixed, so they are computed once per run (or per
+// call of a lone sweep).
+struct DampLayout {
+  int64_t pair_off[9];                // first pair of each colour
+  int32_t per[8];                     // LDS slots of one anchor: its colour's bmax + 1
+  const uint32_t* jinfo[8];           // the colour's width's record position | group << 28
+};
+
 template <typename T>
 __global__ void k_damp_prep(int64_t n_upairs, int64_t n, const uint32_t* __restrict__ sa,
                             const uint32_t* __restrict__ sb, const uint32_t* __restrict__ dpair,
                             const T* __restrict__ dgeo, const T* __restrict__ V,
                             const uint8_t* __restrict__ flags, T inv_rho0, T eta_dt, Bat bt,
-                            PairQ<T>* __restrict__ dwq, T* __restrict__ imass, Mix<T> mx) {
+                            DampLayout lay, PairQ<T>* __restrict__ dwq, T* __restrict__ imass,
+                            Mix<T> mx) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   auto im = [&](int64_t a) -> T {
     const bool fixed = flags && (flags[a] & SPH_FLAG_FIXED);
@@ -498,16 +506,19 @@ __global__ void k_damp_prep(int64_t n_upairs, int64_t n, const uint32_t* __restr
     dwq[i] = none;
   }
   if (i >= n_upairs) return;
+  int c = 0;
+  while (c < 7 && i >= lay.pair_off[c + 1]) ++c;
+  const uint32_t inf = lay.jinfo[c][i];
+  const uint32_t base = (inf >> 28) * (uint32_t)lay.per[c];
   const uint32_t a = sa[i], b = sb[i];
   const T edt = bt.spec ? bt.get<T>(BT_ETADT, bt.spec[a]) : eta_dt;
   const T beta = edt * dgeo[i];
-  // the pair word as the two particles' byte offsets in the sweep's LDS block
   constexpr uint32_t S = sizeof(vec4<T>);
   const uint32_t w = dpair[i];
   PairQ<T> pq{};
-  pq.w = ((w & 0xFFFFu) * S) | (((w >> 16) * S) << 16);
+  pq.w = ((base + (w & 0xFFFFu)) * S) | (((base + (w >> 16)) * S) << 16);
   pq.q = beta / (T(1) - beta * (im(a) + im(b)));
-  dwq[i] = pq;
+  dwq[inf & 0x0FFFFFFFu] = pq;
 }
 
 // drift + kinetic energy: every block writes its partial E_k (fixed-order
@@ -1115,25 +1126,43 @@ constexpr int damp_width_index() {
 template <typename T>
 static size_t damp_lds_per_anchor(const sph_nbr* nb, int col) {
   const size_t bmax = (size_t)std::max<int64_t>(nb->damp_bmax[col], 1);
-  return ((bmax + 1) * sizeof(vec4<T>) + 15) & ~(size_t)15;  // + the idle lanes' slot
+  return (bmax + 1) * sizeof(vec4<T>);  // the block and its spare slot
+}
+
+// Lane-group width of a colour pass: the tuned width (sph_autotune), else 16;
+// widened while the wavefront's blocks would exceed the LDS budget or the
+// 16-bit byte offsets of the pair words, or its joint rows are unusable.
+template <typename T>
+static int damp_width(const sph_nbr* nb, int col) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  int G = nb->tune.damp_g[prec][col];
+  if (G == 0) G = 16;
+  const size_t per = damp_lds_per_anchor<T>(nb, col);
+  auto fits = [&](int g) {
+    const int gi = g == 8 ? 0 : (g == 16 ? 1 : (g == 32 ? 2 : 3));
+    const size_t lds = (size_t)(64 / g) * per;
+    return nb->dwidth_ok[gi] && lds <= (size_t)kDampLdsBudget && lds <= 65536;
+  };
+  while (G < 64 && !fits(G)) G *= 2;
+  return G;
 }
 
 template <typename T, int D, int G, bool REV>
 static int damp_launch(const sph_nbr* nb, const sph_state* st, hipStream_t s, bool gated,
                        int col) {
   constexpr int APW = 64 / G, gi = damp_width_index<G>();
-  const int64_t a0 = nb->color_off[col], a1 = nb->color_off[col + 1];
+  const int64_t w0 = nb->dwave_off[gi][col], w1 = nb->dwave_off[gi][col + 1];
+  if (w1 <= w0) return SPH_OK;
   const int bmax = (int)std::max<int64_t>(nb->damp_bmax[col], 1);
   const size_t lds = APW * damp_lds_per_anchor<T>(nb, col);
   int rc = lds_attr(k_damp<T, D, G, REV>, lds);
   if (rc) return rc;
-  const unsigned grid = (unsigned)((a1 - a0 + APW - 1) / APW);
   const int p = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   const int64_t po = nb->damp_pair_off[col];
-  k_damp<T, D, G, REV><<<grid, 64, lds, s>>>(
-      (const PairQ<T>*)nb->dwq[p] + po, (uint32_t)(nb->n_upairs - po), po, (const T*)nb->imass[p],
-      nb->drow[gi], nb->drow_base[gi], nb->drow_empty[gi], nb->aoff, nb->ablk, a0, a1, bmax,
-      nb->n, (T*)st->v, nb->ctrl, gated);
+  k_damp<T, D, G, REV><<<(unsigned)(w1 - w0), 64, lds, s>>>(
+      (const PairQ<T>*)nb->dwq[p] + po, (uint32_t)(nb->n_upairs - po), (const T*)nb->imass[p],
+      nb->drow[gi], nb->drow_base[gi], nb->dwave[gi], nb->dwrec[gi], w0, nb->ablk, bmax, nb->n,
+      (T*)st->v, nb->ctrl, gated);
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
@@ -1141,35 +1170,50 @@ static int damp_launch(const sph_nbr* nb, const sph_state* st, hipStream_t s, bo
 template <typename T>
 static int damp_prepare_t(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                           double eta, double dt, hipStream_t s) {
-  // pair words hold LDS byte offsets (16 bits), records 32-bit byte offsets
-  if ((int64_t)(nb->damp_block_max + 1) * (int64_t)sizeof(vec4<T>) > 65535 ||
-      (nb->n_upairs + 1) * (int64_t)sizeof(PairQ<T>) > (int64_t)0xFFFFFFFF) {
-    set_error("damping sweep: anchor blocks of %lld particles or %lld pairs exceed its addressing",
-              (long long)nb->damp_block_max, (long long)nb->n_upairs);
+  // records hold 32-bit byte offsets from a colour's first pair
+  if ((nb->n_upairs + 1) * (int64_t)sizeof(PairQ<T>) > (int64_t)0xFFFFFFFF) {
+    set_error("damping sweep: %lld pairs exceed its addressing", (long long)nb->n_upairs);
     return SPH_E_CAPACITY;
+  }
+  const int p = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  DampLayout lay{};
+  for (int c = 0; c < 9; ++c) lay.pair_off[c] = nb->damp_pair_off[c];
+  for (int c = 0; c < 8; ++c) {
+    const int G = damp_width<T>(nb, c);
+    const int gi = G == 8 ? 0 : (G == 16 ? 1 : (G == 32 ? 2 : 3));
+    if (64 / G * damp_lds_per_anchor<T>(nb, c) > 65536) {
+      set_error("damping sweep: an anchor block of %lld particles exceeds its LDS addressing",
+                (long long)nb->damp_bmax[c]);
+      return SPH_E_CAPACITY;
+    }
+    lay.per[c] = (int32_t)std::max<int64_t>(nb->damp_bmax[c], 1) + 1;
+    lay.jinfo[c] = nb->djinfo[gi];
+    nb->damp_g_used[p][c] = G;
   }
   Geo<T> g = geo<T>(nb);
   const T* dgeo = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)nb->dgeo64
                                                            : (const void*)nb->dgeo32);
-  const int p = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
   const int64_t m_ = std::max<int64_t>(nb->n_upairs + 1, nb->n);
   k_damp_prep<T><<<nblk(std::max<int64_t>(m_, 1), 256), 256, 0, s>>>(
       nb->n_upairs, nb->n, nb->sa, nb->sb, nb->dpair, dgeo, g.V, st->flags, (T)(1.0 / m->rho0),
-      (T)(eta * dt), bat_view(nb), (PairQ<T>*)nb->dwq[p], (T*)nb->imass[p], mix_view<T>(m, st));
+      (T)(eta * dt), bat_view(nb), lay, (PairQ<T>*)nb->dwq[p], (T*)nb->imass[p],
+      mix_view<T>(m, st));
   SPH_LAUNCH_CHECK();
   return SPH_OK;
 }
 
-// Lanes per anchor of each colour pass: the tuned width (sph_autotune), else
-// 16; widened while the wavefront's LDS would exceed the budget.  Outside a
-// run (no per-run coefficients) the coefficients are computed first.
+// One sweep, colour after colour, each pass with its colour's width.  The
+// per-run records are laid out for the widths in force when they were made;
+// outside a run, or when a width has changed since, they are made first.
 template <typename T, int D, bool REV>
 static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
                      double dt, hipStream_t s, bool gated) {
   int rc;
-  if (!nb->damp_pre && (rc = damp_prepare_t<T>(nb, m, st, eta, dt, s))) return rc;
   const int ncol = 1 << D;
   const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  bool stale = !nb->damp_pre;
+  for (int c = 0; c < ncol && !stale; ++c) stale = nb->damp_g_used[prec][c] != damp_width<T>(nb, c);
+  if (stale && (rc = damp_prepare_t<T>(nb, m, st, eta, dt, s))) return rc;
   // timed per sweep: one event pair around its colour passes, which share
   // the sweep's time (an event pair per pass adds its queue time to each)
   const int kind = REV ? SPH_KERNEL_ADJ_DAMPING : SPH_KERNEL_DAMPING;
@@ -1178,12 +1222,7 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
   for (int c_ = 0; c_ < ncol; ++c_) {
     const int col = REV ? ncol - 1 - c_ : c_;
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
-    int want = nb->tune.damp_g[prec][col];
-    if (want == 0) want = 16;
-    while (want < 64 && (size_t)(64 / want) * damp_lds_per_anchor<T>(nb, col) >
-                            (size_t)kDampLdsBudget)
-      want *= 2;
-    switch (want) {
+    switch (nb->damp_g_used[prec][col]) {
       case 8: rc = damp_launch<T, D, 8, REV>(nb, st, s, gated, col); break;
       case 16: rc = damp_launch<T, D, 16, REV>(nb, st, s, gated, col); break;
       case 32: rc = damp_launch<T, D, 32, REV>(nb, st, s, gated, col); break;

@@ -192,6 +192,8 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     double bt = 1e300;
     for (int g : {8, 16, 32, 64}) {
       tn.damp_g[prec][col] = g;
+      // the records laid out for this width, outside the timing
+      if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) break;
       // time the whole sweep: only this colour's launch differs between candidates
       double t = 0.0;
       rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
