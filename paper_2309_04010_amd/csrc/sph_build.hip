@@ -771,7 +771,8 @@ __global__ void k_lev_fill(const int64_t* __restrict__ aoff, const uint32_t* __r
 //   drow       row words first | end << 16, relative to the wavefront's first
 //              record; each wavefront's list framed by kDampRowPad empty rows
 //   drow_base  [n_waves + 1] start of each framed list
-//   dwave      [n_waves][APW] anchors of each wavefront (0xFFFFFFFF: none)
+//   dwave      [n_waves][APW][8] block runs (begin, count) x 4 of each
+//              wavefront's anchors (all counts 0: no anchor)
 //   dwrec      [n_waves] first record of each wavefront, from its colour's
 //              first pair
 //   djinfo     [n_upairs] record position of each canonical pair | its
@@ -802,8 +803,13 @@ static int build_joint_rows(sph_nbr* nb, hipStream_t s) {
     SPH_HIP(hipStreamSynchronize(s));
   }
   std::vector<uint32_t> info(std::max<int64_t>(np, 1)), dpair(std::max<int64_t>(np, 1));
+  std::vector<uint32_t> ablk(8 * std::max<int64_t>(na, 1));
   if (np > 0) {
     SPH_HIP(hipMemcpyAsync(dpair.data(), nb->dpair, np * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SPH_HIP(hipStreamSynchronize(s));
+  }
+  if (na > 0) {
+    SPH_HIP(hipMemcpyAsync(ablk.data(), nb->ablk, 8 * na * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SPH_HIP(hipStreamSynchronize(s));
   }
   struct RowPair {
@@ -833,7 +839,7 @@ static int build_joint_rows(sph_nbr* nb, hipStream_t s) {
         int64_t wa[8];
         int lev[8], taken[8];
         for (int g = 0; g < apw; ++g) {
-          wave.push_back(g < k ? (uint32_t)order[w0 + g] : 0xFFFFFFFFu);
+          for (int e = 0; e < 8; ++e) wave.push_back(g < k ? ablk[8 * order[w0 + g] + e] : 0u);
           if (g < k) {
             wa[g] = order[w0 + g];
             lev[g] = 0;
@@ -923,7 +929,7 @@ static int build_joint_rows(sph_nbr* nb, hipStream_t s) {
     rbase.push_back((int64_t)rows.size());
     if (np + 1 >= (int64_t)(1u << 28)) ok = false;
     nb->dwidth_ok[gi] = ok;
-    if (wave.empty()) wave.push_back(0xFFFFFFFFu);
+    if (wave.empty()) wave.push_back(0u);
     if (wrec.empty()) wrec.push_back(0u);
     if (rows.empty()) rows.push_back(0u);
     int rc;

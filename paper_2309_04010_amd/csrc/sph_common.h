@@ -189,7 +189,7 @@ struct sph_nbr {
   // joint rows of the damping sweep per lane-group width (build_joint_rows)
   uint32_t* drow[sph::kDampWidths] = {};       // row words first | end << 16, framed per wavefront
   int64_t* drow_base[sph::kDampWidths] = {};   // [n_waves + 1] start of each wavefront's framed list
-  uint32_t* dwave[sph::kDampWidths] = {};      // [n_waves][64 / G] anchors of each wavefront
+  uint32_t* dwave[sph::kDampWidths] = {};      // [n_waves][64 / G][8] block runs of its anchors
   uint32_t* dwrec[sph::kDampWidths] = {};      // [n_waves] first record, from the colour's first pair
   uint32_t* djinfo[sph::kDampWidths] = {};     // [n_upairs] record position | group << 28
   int64_t dwave_off[sph::kDampWidths][9] = {}; // first wavefront of each colour

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
         xv[e].x = (T)(g.X[gi] - xo[0]);
         xv[e].y = (T)(g.X[n + gi] - xo[1]);
         xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
-        xv[e].w = g.V[gi];
+        xv[e].w = g.c5 * g.V[gi];
         uv[e].x = (T)(u[gi] - uo[0]);
         uv[e].y = (T)(u[n + gi] - uo[1]);
         uv[e].z = D == 3 ? (T)(u[2 * n + gi] - uo[2]) : T(0);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
     T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
+    const T w = dw_scaled(r2, g.mhih, xb.w);  // xb.w = c5 V_b
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const T wd = w * du[i];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256 * LPP) void k_momentum(TileGeo<T> g,
     for (int k = 0; k < D; ++k) d[k] = xa[k] - xb[k];
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w = dw_over_r(r2, g.inv_h, g.c5);
+    const T w = dw_scaled(r2, g.mhih, g.c5);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       T s = T(0);
@@ -343,10 +343,9 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
                                              const T* __restrict__ imass,
                                              const uint32_t* __restrict__ rows,
                                              const int64_t* __restrict__ rbase,
-                                             const uint32_t* __restrict__ wave_anchor,
+                                             const uint32_t* __restrict__ wave_blk,
                                              const uint32_t* __restrict__ wave_rec, int64_t w0,
-                                             const uint32_t* __restrict__ ablk, int bmax,
-                                             int64_t n, T* v, Ctrl* ctrl, bool gated) {
+                                             int bmax, int64_t n, T* v, Ctrl* ctrl, bool gated) {
   if (gated && ctrl->done) return;
   constexpr int APW = 64 / G;
   constexpr int K = 8;  // steps of records in flight (deeper rings measured slower)
@@ -363,24 +362,15 @@ __global__ __launch_bounds__(64) void k_damp(const PairQ<T>* __restrict__ dwq_c,
   const uint32_t idle_w = ((uint32_t)bmax * S4) | (((uint32_t)bmax * S4) << 16);
   vec4<T>* sv = reinterpret_cast<vec4<T>*>(smem_raw + grp * per);
   const int64_t wv = w0 + blockIdx.x;
-  const uint32_t ai = wave_anchor[wv * APW + grp];
-  const bool live = ai != 0xFFFFFFFFu;
   const uint32_t lo_rel = wave_rec[wv];
   const int64_t rb = rbase[wv];
   const int nrw = (int)(rbase[wv + 1] - rb) - 2 * kDampRowPad;  // the same for all lanes
   const uint32_t* rp = rows + rb + kDampRowPad + (REV ? nrw - 1 : 0);
-  uint32_t b0 = 0, b2 = 0, b4 = 0, b6 = 0, e0 = 0, e1 = 0, e2 = 0, nblk = 0;
-  if (live) {
-    const uint32_t* bl = ablk + 8 * (int64_t)ai;
-    b0 = bl[0];
-    b2 = bl[2];
-    b4 = bl[4];
-    b6 = bl[6];
-    e0 = bl[1];
-    e1 = e0 + bl[3];
-    e2 = e1 + bl[5];
-    nblk = e2 + bl[7];
-  }
+  // this group's anchor block: four runs (begin, count) of sorted particles
+  // (all counts zero when the wavefront has no anchor for the group)
+  const uint32_t* bl = wave_blk + (wv * APW + grp) * 8;
+  const uint32_t b0 = bl[0], b2 = bl[2], b4 = bl[4], b6 = bl[6];
+  const uint32_t e0 = bl[1], e1 = e0 + bl[3], e2 = e1 + bl[5], nblk = e2 + bl[7];
   auto row = [&](const uint32_t* p, int k) -> uint32_t { return REV ? p[-k] : p[k]; };
   // this lane's record in a row (the sentinel when the lane has no pair there)
   const unsigned char* dwqb = reinterpret_cast<const unsigned char*>(dwq_c);
@@ -1161,7 +1151,7 @@ static int damp_launch(const sph_nbr* nb, const sph_state* st, hipStream_t s, bo
   const int64_t po = nb->damp_pair_off[col];
   k_damp<T, D, G, REV><<<(unsigned)(w1 - w0), 64, lds, s>>>(
       (const PairQ<T>*)nb->dwq[p] + po, (uint32_t)(nb->n_upairs - po), (const T*)nb->imass[p],
-      nb->drow[gi], nb->drow_base[gi], nb->dwave[gi], nb->dwrec[gi], w0, nb->ablk, bmax, nb->n,
+      nb->drow[gi], nb->drow_base[gi], nb->dwave[gi], nb->dwrec[gi], w0, bmax, nb->n,
       (T*)st->v, nb->ctrl, gated);
   SPH_LAUNCH_CHECK();
   return SPH_OK;
@@ -1501,7 +1491,7 @@ __global__ __launch_bounds__(256 * LPP) void k_gsum(TileGeo<T> g, T* __restrict_
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
+    const T w = dw_scaled(r2, g.mhih, g.c5) * xb.w;  // the momentum sum's kernel arithmetic
 #pragma unroll
     for (int k = 0; k < D; ++k) m[k] += w * d[k];
   });
