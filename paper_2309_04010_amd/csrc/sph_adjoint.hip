@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256 * LPP) void k_adj_stress(
       for (int k = 0; k < D; ++k) d[k] = va[k] - vb[k];
       T r2 = d[0] * d[0] + d[1] * d[1];
       if (D == 3) r2 += d[2] * d[2];
-      const T w0 = dw_scaled(r2, g.mhih, g.c5);
+      const T w0 = dw_over_r(r2, g.inv_h, g.c5);
       T e[3];
 #pragma unroll
       for (int k = 0; k < D; ++k) e[k] = w0 * d[k];
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(256 * LPP) void k_adj_gather(
     for (int k = 0; k < D; ++k) d[k] = xa[k] - xb[k];
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w0 = dw_scaled(r2, g.mhih, g.c5);
+    const T w0 = dw_over_r(r2, g.inv_h, g.c5);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       T s = T(0);

@@ -268,24 +268,13 @@ struct TileGeo {
   int64_t n;
   T inv_h, c5;
   const T* gsum;  // [dim][n] sum_b V_b grad_a W_ab
-  T mhih;         // -inv_h / 2: (dW/dr)/r = c5 t^3, t = 1 + mhih r
 };
 
 template <typename T>
 static TileGeo<T> tile_geo(const sph_nbr* nb, int prec) {
   const Tiling& t = nb->tiling[prec];
   Geo<T> g = geo<T>(nb);
-  return TileGeo<T>{t.tiles, t.ell,  t.tmax, t.n_tiles, g.X,  g.V,
-                    g.B0,    g.n,    g.inv_h, g.c5,     g.gsum, (T)(-0.5 * nb->inv_h)};
-}
-
-// cv (dW/dr)/r / c5 = cv t^3 with t = 1 - r / (2h): one fused step for t, and
-// the factor cv (c5, or c5 times a neighbour's volume staged with it) taken
-// into the cube
-template <typename T>
-__device__ __forceinline__ T dw_scaled(T r2, T mhih, T cv) {
-  const T t = hw_sqrt(r2) * mhih + T(1);
-  return (t * t) * (t * cv);
+  return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5, g.gsum};
 }
 
 // N values per window particle as N/4 arrays of 4-vectors ([N/4][window])

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
         xv[e].x = (T)(g.X[gi] - xo[0]);
         xv[e].y = (T)(g.X[n + gi] - xo[1]);
         xv[e].z = D == 3 ? (T)(g.X[2 * n + gi] - xo[2]) : T(0);
-        xv[e].w = g.c5 * g.V[gi];
+        xv[e].w = g.V[gi];
         uv[e].x = (T)(u[gi] - uo[0]);
         uv[e].y = (T)(u[n + gi] - uo[1]);
         uv[e].z = D == 3 ? (T)(u[2 * n + gi] - uo[2]) : T(0);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
     T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w = dw_scaled(r2, g.mhih, xb.w);  // xb.w = c5 V_b
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const T wd = w * du[i];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256 * LPP) void k_momentum(TileGeo<T> g,
     for (int k = 0; k < D; ++k) d[k] = xa[k] - xb[k];
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w = dw_scaled(r2, g.mhih, g.c5);
+    const T w = dw_over_r(r2, g.inv_h, g.c5);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       T s = T(0);
@@ -1491,7 +1491,7 @@ __global__ __launch_bounds__(256 * LPP) void k_gsum(TileGeo<T> g, T* __restrict_
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T r2 = d[0] * d[0] + d[1] * d[1];
     if (D == 3) r2 += d[2] * d[2];
-    const T w = dw_scaled(r2, g.mhih, g.c5) * xb.w;  // the momentum sum's kernel arithmetic
+    const T w = dw_over_r(r2, g.inv_h, g.c5) * xb.w;
 #pragma unroll
     for (int k = 0; k < D; ++k) m[k] += w * d[k];
   });

@@ -33,23 +33,35 @@ def fp32_vs_fp64(nx, inner=1000):
         idx = pr.perm.argsort()[c.observable["J_index"]]
         w = torch.zeros((c.dim, c.n), dtype=torch.float64, device="cuda")
         w[c.observable["J_component"], torch.as_tensor(idx).cuda()] = 1.0 / len(idx)
-        u = host(pr.forward(pr.theta0())).copy()
+        ut = pr.forward(pr.theta0())
+        J = float((ut.double() * w).sum().item())
+        u = host(ut).copy()
         g = host(pr.backward(w))
-        out[prec] = (u, g)
+        out[prec] = (u, g, J)
         pr.close()
-    (u32, g32), (u64, g64) = out[B.SPH_F32], out[B.SPH_F64]
+    (u32, g32, J32), (u64, g64, J64) = out[B.SPH_F32], out[B.SPH_F64]
     ue = float(np.abs(u32 - u64).max() / np.abs(u64).max())
     ge = {nm: float(abs(g32[B.GRAD_NAMES.index(nm)] - g64[B.GRAD_NAMES.index(nm)]) /
                     abs(g64[B.GRAD_NAMES.index(nm)])) for nm in ("E", "D", "C_swell")}
+    ge["J"] = abs(J32 - J64) / abs(J64)
     return ue, ge
 
 
-# Bounds: the FP32 path holds the state within 2.0e-6 and the gradients within
+# Bounds: the FP32 path holds the state within 2.0e-6, the deflection within
+# 8.6e-7 and the gradients within
 # 2.3e-6 (E), 4.6e-7 (D) and 1.6e-8 (C) here.  The two gather mistakes named
 # above gave 4.2e-5 on the state and 2.1e-5 on E (own-term sum evaluated
 # exactly), and 1.6e-6 to 1.9e-6 on D and 4.1e-6 to 4.5e-5 on C (per-pair
 # differences taken apart).
-BOUNDS = dict(state=1.5e-5, E=1.0e-5, D=1.2e-6, C_swell=1.0e-6)
+BOUNDS = dict(state=1.5e-5, E=1.0e-5, D=1.2e-6, C_swell=1.0e-6, J=1.0e-5)
+
+# The full plate (500 x 500 x 4, the benchmark's): the state within 6.0e-6
+# and the deflection J within 4.3e-6 to 2.5e-5 of FP64.  Its bending response
+# is far softer than its in-plane one, so the FP32 deflection follows the last
+# bits of the kernel weights: four algebraically equal forms of (dW/dr)/r in
+# the momentum-shaped gathers gave J errors from 4.3e-6 to 1.6e-4 and state
+# errors from 6.0e-6 to 3.3e-5.  These bounds keep the form that holds them.
+BOUNDS_FULL = dict(state=1.5e-5, E=2.0e-5, D=3.0e-6, C_swell=1.0e-5, J=5.0e-5)
 
 
 def test_fp32_plate_state_and_gradient():
@@ -59,3 +71,12 @@ def test_fp32_plate_state_and_gradient():
     assert ue < BOUNDS["state"]
     for nm, err in ge.items():
         assert err < BOUNDS[nm], (nm, err)
+
+
+def test_fp32_full_plate_state_deflection_and_gradient():
+    print("[fp32 accuracy] plate 500x500x4, one slow step x 1000 inner steps", flush=True)
+    ue, ge = fp32_vs_fp64(500)
+    print(f"  state {ue:.3e}  gradient and J {ge}", flush=True)
+    assert ue < BOUNDS_FULL["state"]
+    for nm, err in ge.items():
+        assert err < BOUNDS_FULL[nm], (nm, err)
