@@ -8,7 +8,7 @@ step of that checkpointed adjoint: the diffusion update and 1000 inner steps
 of {deformation gradient + stress, pair momentum + kick, implicit pairwise
 damping sweep (4 colour passes on the plate), drift + kinetic energy}
 forward, then the reverse pass of that slow step, which first re-runs it
-from its checkpoint to record u before every inner step (a long run keeps
+from its checkpoint to record H = F - I of every inner step (a long run keeps
 only the checkpoints) and then runs the 1000 transposed inner steps and the
 transposed diffusion step, giving the gradient of the mean centre deflection
 with respect to E, D and C.  FP32 bulk arithmetic with FP64 displacements

@@ -91,7 +91,8 @@ struct Bat {
 // per precision and colour (0: the automatic rule)
 enum TuneKernel { TUNE_STRESS = 0, TUNE_MOMENTUM, TUNE_ADJ_STRESS, TUNE_ADJ_GATHER, TUNE_COUNT };
 struct Tune {
-  int lpp[TUNE_COUNT][2] = {{2, 2}, {4, 4}, {2, 2}, {4, 4}};
+  // [kernel][SPH_F32, SPH_F64]: the tuned choices on the 1M-particle plate
+  int lpp[TUNE_COUNT][2] = {{1, 2}, {2, 4}, {1, 2}, {2, 4}};
   int damp_g[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
 };
 

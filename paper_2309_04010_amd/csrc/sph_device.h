@@ -253,8 +253,8 @@ using vec4 = T __attribute__((ext_vector_type(4)));
 
 // lanes per particle of the tile kernels (1, 2 or 4; a workgroup is
 // tile_tmax x lanes threads, at most 256 x 4): per-handle choices (Tune), set
-// by sph_autotune, else the defaults (2 for the stress kernels, 4 for the
-// momentum-shaped ones, which read more LDS per pair)
+// by sph_autotune, else the defaults (in FP32 1 for the stress kernels, 2 for
+// the momentum-shaped ones, which read more LDS per pair; twice that in FP64)
 
 template <typename T>
 struct TileGeo {
