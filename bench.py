@@ -266,7 +266,14 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True, tap
     run = dict(case.run)
     run.update(n_slow=1, fixed_inner=inner)
     c = dataclasses.replace(case, run=run)
-    pr = A.MultirateProblem(c, prec, k_hist=inner, chunk=min(inner, 250))
+    # the recorded inner states of a slow step take (dim^2) values per
+    # particle per inner step: where they do not fit, the reverse pass goes
+    # in segments (two-level checkpointing)
+    torch.cuda.empty_cache()
+    pr = A.MultirateProblem(c, prec, k_hist=inner, chunk=min(inner, 250), tape_mem_frac=0.8)
+    segments = pr.tape.seg_cap + 1
+    if segments > 1:
+        taped_steps = 0
     th = pr.theta0()
     tuning = B.sph_autotune(pr.nb, pr._material(th), pr.st, run["eta"], pr.run["dt_s"],
                             with_adjoint=True).as_dict()
@@ -330,8 +337,10 @@ def run_adjoint(case, prec, steps, warmup, inner, torch, B, A, profile=True, tap
                 status=bits, grad=g.cpu().numpy(),
                 J=float((pr.st.u * w).sum().item()), u=u,
                 u_finite=bool(np.isfinite(u).all()), tuning=tuning, breakdown=breakdown,
-                dominant=dominant)
+                dominant=dominant, tape_k_hist=pr.tape.k_hist_cap, tape_segments=segments)
     pr.close()
+    del pr
+    torch.cuda.empty_cache()
     return info, prof
 
 
@@ -684,12 +693,15 @@ def main():
               for i in (B.SPH_GRAD_E, B.SPH_GRAD_D, B.SPH_GRAD_C)}
         accuracy = dict(reference="the same step on the FP64 GPU path (itself within 1e-10 of the "
                                   "FP64 oracle in the parity tests)",
-                        u_rel_err=ue, J_fp32=adj32["J"], J_fp64=adj64["J"], grad=gr)
+                        u_rel_err=ue, J_fp32=adj32["J"], J_fp64=adj64["J"], grad=gr,
+                        fp64_tape_segments=adj64["tape_segments"])
 
     # dominant kernel class (by total time in the profiled untimed step),
     # timed with HIP events around its launches in the timed region
     kern = adj32["dominant"]
     nper = adj32["n"]
+    seg_note = ("" if adj32["tape_segments"] == 1 else
+                f" in {adj32['tape_segments']} segments of {adj32['tape_k_hist']} inner steps")
     workload_key = f"plate3d-{args.nx}x{args.nx}x4-fp32"
     copy_bw = copy_bandwidth(torch)
     npass = adj32["damping_passes"]
@@ -822,13 +834,15 @@ def main():
             "workload": f"plate3d {args.nx}x{args.nx}x4 membrane ({adj32['n']} particles, {P} directed "
                         f"pairs), neo-Hookean + fluid pressure, checkpointed adjoint; per step one "
                         f"slow step of it: a diffusion slow step + {args.inner} inner steps forward, "
-                        f"then its reverse pass (the slow step re-run from its checkpoint with u "
-                        f"recorded, {args.inner} transposed inner steps, the transposed diffusion "
+                        f"then its reverse pass (the slow step re-run from its checkpoint with "
+                        f"H = F - I recorded{seg_note}, {args.inner} transposed inner steps, the "
+                        f"transposed diffusion "
                         f"step) for d(mean centre deflection)/d(E, D, C); FP32 bulk / FP64 "
                         f"displacement",
             "headline": "per slow step of the 50 x 1000 checkpointed adjoint, re-run included; "
                         "full_adjoint times the whole run",
             "adjoint": True,
+            "tape_segments": adj32["tape_segments"],
             "parallelism": "single GPU",
         },
         "roofline": roofline,

@@ -285,7 +285,18 @@ int sph_diffusion_step_coupled(const sph_nbr* nbr, const sph_material* mat, cons
  * ck_v [n_slow_cap+1][dim][n], ck_plastic [n_slow_cap+1][7][n] (J2 only, else
  * NULL), ck_c [n_slow_cap+1][n] (diffusion only, else NULL),
  * hist_H [k_hist_cap][dim*dim][n], hist_plastic [k_hist_cap][7][n] (J2 only,
- * else NULL); prec-typed arrays follow sph_state.prec. */
+ * else NULL); prec-typed arrays follow sph_state.prec.
+ * A slow step with more inner steps than k_hist_cap is reversed in segments
+ * of k_hist_cap inner steps, last segment first (two-level checkpointing):
+ * the reverse pass re-runs the slow step once to store the state at the
+ * start of every segment but the first in seg_u [seg_cap][dim][n] f64,
+ * seg_v [seg_cap][dim][n] and seg_plastic [seg_cap][7][n] (J2 only, else
+ * NULL), then re-runs each segment from there with its inner states
+ * recorded.  ceil(k / k_hist_cap) - 1 <= seg_cap is required (seg_cap = 0,
+ * NULL arrays: no segments, k <= k_hist_cap); the cost is one more forward
+ * run of the slow step, the memory (2 dim + 7) values per particle per
+ * segment instead of dim^2 + 7 per inner step.  The results equal those of
+ * an unsegmented reverse pass. */
 typedef struct {
   int32_t n_slow_cap;  /* slow steps that fit */
   int32_t pad_;
@@ -301,6 +312,10 @@ typedef struct {
   int32_t hist_slow;   /* out: slow step whose inner states hist_H holds, -1 if none */
   double dt_s;         /* out: inner step used (frozen for the reverse pass) */
   double dt_slow;      /* out: slow step used */
+  int64_t seg_cap;     /* inner checkpoints that fit in seg_u, seg_v, seg_plastic */
+  double* seg_u;
+  void* seg_v;
+  void* seg_plastic;
 } sph_tape;
 
 /* Multi-time-step driver (Sec. 4.2): for l = 1..n_slow, one slow step (load
@@ -394,8 +409,8 @@ int sph_diffusion_step_coupled_vjp(const sph_nbr* nbr, const sph_material* mat,
  * entry adj->u, adj->v (and adj->plastic, adj->c) hold the adjoint of the
  * final state; on return they hold the adjoint of the initial state and
  * adj->grad has the parameter gradients added.  The pass re-runs each slow
- * step from its checkpoint (recording its inner states, k_rec[l] <=
- * k_hist_cap required) unless hist_H already holds it; st is used as working
+ * step from its checkpoint (recording its inner states, in segments when
+ * k_rec[l] > k_hist_cap) unless hist_H already holds it; st is used as working
  * storage and restored to the final state on return.  adj->p must be zero on
  * entry.  Slow steps: loading, diffusion, and the two-way coupled diffusion
  * (one specimen; its u-dependence through F, J and F^-1 goes to adj->u).

@@ -24,7 +24,13 @@ PARAMS = B.GRAD_NAMES  # order of theta
 
 
 class MultirateProblem:
-    def __init__(self, case, prec, k_hist=None, chunk=64, use_graph=0):
+    def __init__(self, case, prec, k_hist=None, chunk=64, use_graph=0, seg_cap=0,
+                 tape_mem_frac=None):
+        """k_hist: inner steps whose states the tape holds at once (default:
+        the whole slow step); seg_cap: inner checkpoints for longer slow steps
+        (reversed in segments).  tape_mem_frac: instead, fit the tape for slow
+        steps of k_hist inner steps into this fraction of the device memory
+        left free (SphTape.plan)."""
         import torch
         self.case = case
         self.prec = prec
@@ -53,9 +59,13 @@ class MultirateProblem:
         n_slow = r["n_slow"]
         if k_hist is None:
             k_hist = r["fixed_inner"] if r.get("fixed_inner", 0) > 0 else r.get("k_max", 0)
-        self.tape = B.SphTape(self.nb, prec, n_slow, int(k_hist), with_plastic=self.j2,
-                              with_diffusion=self.diff)
         self.adj = B.new_adjoint(self.nb, prec, with_plastic=self.j2, with_diffusion=self.diff)
+        if tape_mem_frac is not None:
+            free = torch.cuda.mem_get_info()[0]
+            k_hist, seg_cap = B.SphTape.plan(self.nb.n, self.nb.dim, prec, k_hist,
+                                             tape_mem_frac * free, with_plastic=self.j2)
+        self.tape = B.SphTape(self.nb, prec, n_slow, int(k_hist), with_plastic=self.j2,
+                              with_diffusion=self.diff, seg_cap=seg_cap)
         self._fwd_id = 0
         self._tape_id = -1
         self.last = None

@@ -84,7 +84,8 @@ class Batch(C.Structure):
 class Tape(C.Structure):
     _fields_ = [("n_slow_cap", i32), ("pad_", i32), ("k_hist_cap", i64), ("ck_u", vp), ("ck_v", vp),
                 ("ck_plastic", vp), ("ck_c", vp), ("hist_H", vp), ("hist_plastic", vp), ("k_rec", vp),
-                ("n_rec", i32), ("hist_slow", i32), ("dt_s", dbl), ("dt_slow", dbl)]
+                ("n_rec", i32), ("hist_slow", i32), ("dt_s", dbl), ("dt_slow", dbl),
+                ("seg_cap", i64), ("seg_u", vp), ("seg_v", vp), ("seg_plastic", vp)]
 
 
 class Adjoint(C.Structure):
@@ -481,10 +482,13 @@ def sph_advance_multirate(nbr, mat, st, cfg, tape=None, stream=None):
 
 # --- reverse mode -------------------------------------------------------------
 class SphTape:
-    """Device checkpoints of a forward multi-time-step run (sph_tape)."""
+    """Device checkpoints of a forward multi-time-step run (sph_tape).
+    k_hist: inner steps whose states the tape holds at once; seg_cap: inner
+    checkpoints for slow steps longer than that (reversed in segments of
+    k_hist inner steps, up to (seg_cap + 1) * k_hist)."""
 
     def __init__(self, nbr, prec, n_slow, k_hist, with_plastic=False, with_diffusion=False,
-                 device="cuda"):
+                 device="cuda", seg_cap=0):
         import torch
         d, n = nbr.dim, nbr.n
         T = torch.float32 if prec == SPH_F32 else torch.float64
@@ -498,10 +502,30 @@ class SphTape:
         self.ck_c = z(n_slow + 1, n) if with_diffusion else None
         self.hist_H = z(max(k_hist, 1), d * d, n)
         self.hist_plastic = z(max(k_hist, 1), 7, n) if with_plastic else None
+        self.seg_cap = int(seg_cap)
+        self.seg_u = z(seg_cap, d, n, dt=torch.float64) if seg_cap > 0 else None
+        self.seg_v = z(seg_cap, d, n) if seg_cap > 0 else None
+        self.seg_plastic = z(seg_cap, 7, n) if seg_cap > 0 and with_plastic else None
         self.k_rec = np.zeros(max(n_slow, 1), np.int64)
         self._c = Tape(self.n_slow_cap, 0, self.k_hist_cap, _dptr(self.ck_u), _dptr(self.ck_v),
                        _dptr(self.ck_plastic), _dptr(self.ck_c), _dptr(self.hist_H),
-                       _dptr(self.hist_plastic), self.k_rec.ctypes.data_as(vp), 0, -1, 0.0, 0.0)
+                       _dptr(self.hist_plastic), self.k_rec.ctypes.data_as(vp), 0, -1, 0.0, 0.0,
+                       self.seg_cap, _dptr(self.seg_u), _dptr(self.seg_v), _dptr(self.seg_plastic))
+
+    @staticmethod
+    def plan(n, dim, prec, k_inner, budget_bytes, with_plastic=False):
+        """(k_hist, seg_cap) for slow steps of k_inner inner steps with the
+        recorded inner states within budget_bytes: the whole slow step when it
+        fits, else the fewest segments whose states and inner checkpoints do."""
+        T = 4 if prec == SPH_F32 else 8
+        per_step = (dim * dim + (7 if with_plastic else 0)) * n * T
+        per_seg = (dim * 8 + dim * T + (7 * T if with_plastic else 0)) * n
+        k_inner = max(int(k_inner), 1)
+        for ns in range(1, k_inner + 1):
+            k_hist = -(-k_inner // ns)
+            if k_hist * per_step + (ns - 1) * per_seg <= budget_bytes:
+                return k_hist, ns - 1
+        raise SphError(SPH_E_CAPACITY, "no segmentation of the tape fits the budget")
 
     def cstruct(self, nbr, st):
         if st.prec != self.prec:

@@ -154,6 +154,51 @@ int tape_copy(const sph_nbr* nb, const sph_material* m, const sph_state* st, con
   return rc;
 }
 
+// inner checkpoint j of the segmented reverse pass (the state at the start
+// of segment j + 1 of a slow step): u, v and the J2 state
+int seg_copy(const sph_nbr* nb, const sph_material* m, const sph_state* st, const sph_tape* tp,
+             int64_t j, bool to_tape, hipStream_t s) {
+  const size_t n = (size_t)nb->n, d = (size_t)nb->dim;
+  const size_t T = st->prec == SPH_F64 ? 8 : 4;
+  auto cp = [&](void* base, void* arr, size_t bytes) -> int {
+    char* t = (char*)base + (size_t)j * bytes;
+    SPH_HIP(hipMemcpyAsync(to_tape ? (void*)t : arr, to_tape ? arr : (void*)t, bytes,
+                           hipMemcpyDeviceToDevice, s));
+    return SPH_OK;
+  };
+  int rc = cp(tp->seg_u, st->u, d * n * 8);
+  if (!rc) rc = cp(tp->seg_v, st->v, d * n * T);
+  if (!rc && m->model == SPH_MODEL_J2) rc = cp(tp->seg_plastic, st->plastic, 7 * n * T);
+  return rc;
+}
+
+// segments of k_hist_cap inner steps the reverse pass splits a slow step of
+// kl inner steps into
+int64_t n_segments(const sph_tape* tp, int64_t kl) {
+  return kl <= 0 ? 0 : (kl + tp->k_hist_cap - 1) / tp->k_hist_cap;
+}
+
+// the tape can re-run and reverse slow steps of these inner counts
+int check_segments(const sph_material* m, const sph_tape* tp, const int64_t* counts, int L) {
+  const bool j2 = m->model == SPH_MODEL_J2;
+  for (int l = 0; l < L; ++l) {
+    const int64_t kl = counts[l];
+    if (kl <= 0) continue;
+    if (tp->k_hist_cap <= 0 || !tp->hist_H || (j2 && !tp->hist_plastic)) {
+      set_error("slow step %d has %lld inner steps; the tape records none", l, (long long)kl);
+      return SPH_E_CAPACITY;
+    }
+    const int64_t ns = n_segments(tp, kl);
+    if (ns > 1 && (ns - 1 > tp->seg_cap || !tp->seg_u || !tp->seg_v || (j2 && !tp->seg_plastic))) {
+      set_error("slow step %d has %lld inner steps: %lld segments of %lld need %lld inner "
+                "checkpoints, the tape holds %lld", l, (long long)kl, (long long)ns,
+                (long long)tp->k_hist_cap, (long long)(ns - 1), (long long)tp->seg_cap);
+      return SPH_E_CAPACITY;
+    }
+  }
+  return SPH_OK;
+}
+
 int check_tape(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                const sph_multirate_cfg* cfg, const sph_tape* tp) {
   if (cfg->n_slow > tp->n_slow_cap) {
@@ -482,7 +527,9 @@ namespace {
 
 // Reverse pass: slow steps last to first; each is re-run from its checkpoint
 // with its inner states recorded (unless the tape already holds them), then
-// its inner steps are reversed, then its slow update.  Enqueues only (no
+// its inner steps are reversed, then its slow update.  A slow step longer
+// than the tape's k_hist_cap goes in segments of that many inner steps, each
+// re-run from an inner checkpoint the pass lays first.  Enqueues only (no
 // host synchronisation), so that it can be captured in a graph.
 int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* st,
                      const sph_multirate_cfg* cfg, sph_tape* tape, const sph_adjoint* adj,
@@ -492,52 +539,85 @@ int backward_enqueue(const sph_nbr* nb, const sph_material* m, const sph_state* 
   const double dt = tape->dt_s, dt_slow = tape->dt_slow;
   const size_t n = (size_t)nb->n, d = (size_t)nb->dim;
   const size_t T = st->prec == SPH_F64 ? 8 : 4;
+  const int64_t K = tape->k_hist_cap;
   std::vector<int64_t> before(L + 1, 0);
   for (int l = 0; l < L; ++l) before[l + 1] = before[l] + tape->k_rec[l];
+  if ((rc = check_segments(m, tape, tape->k_rec, L))) return rc;
   RecGuard rec_guard{nb};
   bool first = true;  // the next reversed inner step is the run's last one
-  for (int l = L - 1; l >= 0; --l) {
-    const int64_t kl = tape->k_rec[l];
-    if (tape->hist_slow != l) {
-      if (kl > 0 && (kl > tape->k_hist_cap || !tape->hist_H ||
-                     (m->model == SPH_MODEL_J2 && !tape->hist_plastic))) {
-        set_error("slow step %d has %lld inner steps; the tape records %lld", l, (long long)kl,
-                  (long long)tape->k_hist_cap);
-        return SPH_E_CAPACITY;
-      }
-      if ((rc = tape_copy(nb, m, st, tape, l, false, s))) return rc;
-      rc = cfg->slow_kind == SPH_SLOW_LOAD ? load_step(nb, st, dt_slow, s)
+  // slow step l from its checkpoint: the state its inner steps start from
+  auto slow_update = [&](int l) -> int {
+    int r = tape_copy(nb, m, st, tape, l, false, s);
+    if (r) return r;
+    return cfg->slow_kind == SPH_SLOW_LOAD ? load_step(nb, st, dt_slow, s)
            : cfg->slow_kind == SPH_SLOW_DIFFUSION_COUPLED
                ? diffusion_step_coupled(nb, m, st, cfg->D, dt_slow, cfg->c_bc, cfg->diff_nonlinear, s)
                : diffusion_step(nb, m, st, cfg->D, dt_slow, cfg->c_bc, s);
-      if (rc) return rc;
-      if (kl > 0) {
-        if ((rc = reset_ctrl(nb, kl, -1.0, s))) return rc;
-        nb->rec_H = tape->hist_H;
-        nb->rec_pl = tape->hist_plastic;
-        tape->hist_slow = -1;
-        for (int64_t done = 0; done < kl;) {
-          const int c = (int)std::min<int64_t>(kl - done, 256);
-          if ((rc = inner_steps(nb, m, st, dt, cfg->eta, c, s))) return rc;
-          done += c;
-        }
-        nb->rec_H = nullptr;
-        nb->rec_pl = nullptr;
-        tape->hist_slow = l;
-      }
+  };
+  // `steps` inner steps from the current state; `record`: their H (and J2
+  // state) to hist_H [0, steps)
+  auto rerun = [&](int64_t steps, bool record) -> int {
+    int r = reset_ctrl(nb, steps, -1.0, s);
+    if (r) return r;
+    nb->rec_H = record ? tape->hist_H : nullptr;
+    nb->rec_pl = record ? tape->hist_plastic : nullptr;
+    for (int64_t done = 0; done < steps && !r;) {
+      const int c = (int)std::min<int64_t>(steps - done, 256);
+      r = inner_steps(nb, m, st, dt, cfg->eta, c, s);
+      done += c;
     }
-    for (int64_t k = kl - 1; k >= 0; --k) {
+    nb->rec_H = nullptr;
+    nb->rec_pl = nullptr;
+    return r;
+  };
+  // the transposed inner steps k1 - 1 .. k0 of slow step l, whose recorded
+  // states hist_H holds from index 0 = step k0
+  auto reverse = [&](int l, int64_t k0, int64_t k1) -> int {
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      int r;
       if (first) {
-        if ((rc = adj_drift(nb, st, adj, dt, s))) return rc;
+        if ((r = adj_drift(nb, st, adj, dt, s))) return r;
         first = false;
       }
-      if ((rc = adj_damping(nb, m, st, adj, cfg->eta, dt, s))) return rc;
-      const void* Hk = (const char*)tape->hist_H + (size_t)k * d * d * n * T;
+      if ((r = adj_damping(nb, m, st, adj, cfg->eta, dt, s))) return r;
+      const size_t i = (size_t)(k - k0);
+      const void* Hk = (const char*)tape->hist_H + i * d * d * n * T;
       const void* plk = m->model == SPH_MODEL_J2
-                            ? (const void*)((const char*)tape->hist_plastic + (size_t)k * 7 * n * T)
+                            ? (const void*)((const char*)tape->hist_plastic + i * 7 * n * T)
                             : nullptr;
       const bool has_prev = before[l] + k > 0;
-      if ((rc = adj_solid(nb, m, Hk, plk, st, adj, dt, has_prev ? dt : 0.0, s))) return rc;
+      if ((r = adj_solid(nb, m, Hk, plk, st, adj, dt, has_prev ? dt : 0.0, s))) return r;
+    }
+    return SPH_OK;
+  };
+  for (int l = L - 1; l >= 0; --l) {
+    const int64_t kl = tape->k_rec[l];
+    const int64_t ns = n_segments(tape, kl);
+    if (tape->hist_slow == l) {
+      if ((rc = reverse(l, 0, kl))) return rc;
+    } else if (ns <= 1) {
+      if ((rc = slow_update(l))) return rc;
+      if (kl > 0) {
+        tape->hist_slow = -1;
+        if ((rc = rerun(kl, true))) return rc;
+        tape->hist_slow = l;
+        if ((rc = reverse(l, 0, kl))) return rc;
+      }
+    } else {
+      // two-level checkpointing: store the start of segments 1 .. ns - 1,
+      // then re-run and reverse the segments last to first
+      tape->hist_slow = -1;
+      if ((rc = slow_update(l))) return rc;
+      for (int64_t j = 1; j < ns; ++j) {
+        if ((rc = rerun(K, false))) return rc;
+        if ((rc = seg_copy(nb, m, st, tape, j - 1, true, s))) return rc;
+      }
+      for (int64_t j = ns - 1; j >= 0; --j) {
+        const int64_t k0 = j * K, k1 = std::min(kl, k0 + K);
+        if (j < ns - 1)
+          rc = j == 0 ? slow_update(l) : seg_copy(nb, m, st, tape, j - 1, false, s);
+        if (rc || (rc = rerun(k1 - k0, true)) || (rc = reverse(l, k0, k1))) return rc;
+      }
     }
     if (cfg->slow_kind == SPH_SLOW_DIFFUSION) {
       const void* c_before = (const char*)tape->ck_c + (size_t)l * n * T;
@@ -677,6 +757,7 @@ extern "C" int sph_advance_multirate_backward(const sph_nbr* nb, const sph_mater
     set_error("the tape holds %d slow steps, cfg asks for %d", tape->n_rec, cfg->n_slow);
     return SPH_E_ARG;
   }
+  if ((rc = check_segments(m, tape, tape->k_rec, cfg->n_slow))) return rc;
   hipStream_t s = (hipStream_t)stream;
   BatGuard bat_guard{nb};
   if ((rc = batch_begin(nb, m, cfg, s))) return rc;
@@ -710,11 +791,7 @@ extern "C" int sph_advance_multirate_graph(const sph_nbr* nb, const sph_material
   std::vector<int64_t> counts(std::max(cfg->n_slow, 1));
   for (int l = 0; l < cfg->n_slow; ++l)
     counts[l] = cfg->k_sched ? cfg->k_sched[l] : cfg->fixed_inner;
-  if (adj && cfg->n_slow > 0 && counts[cfg->n_slow - 1] > tape->k_hist_cap) {
-    set_error("the tape must hold the inner states of one slow step (%lld > %lld)",
-              (long long)counts[cfg->n_slow - 1], (long long)tape->k_hist_cap);
-    return SPH_E_CAPACITY;
-  }
+  if (adj && (rc = check_segments(m, tape, counts.data(), cfg->n_slow))) return rc;
   double dt_rest = 0.0, dt_diff = 0.0;
   rest_steps(nb->h, m, cfg->D, &dt_rest, &dt_diff);
   const double dt_s = cfg->dt_s > 0.0 ? cfg->dt_s : dt_rest;

@@ -105,3 +105,23 @@ def test_default_steps_reject_bad_arguments(libsph):
     assert e.value.code == B.SPH_E_ARG
     with pytest.raises(B.SphError):
         B.sph_default_steps(0.0, B.material(0, E=1e9, nu=0.3, rho0=1000.0))
+
+
+def test_tape_plan_fits_the_budget():
+    """SphTape.plan: the whole slow step when its recorded states fit, else
+    the fewest segments whose states and inner checkpoints do (host logic)."""
+    n, d = 1000, 3
+    per_step = 9 * n * 8
+    per_seg = (3 * 8 + 3 * 8) * n
+    assert B.SphTape.plan(n, d, B.SPH_F64, 100, 100 * per_step) == (100, 0)
+    k, seg = B.SphTape.plan(n, d, B.SPH_F64, 100, 30 * per_step)
+    assert (k, seg) == (25, 3)
+    assert k * per_step + seg * per_seg <= 30 * per_step
+    assert (seg + 1) * k >= 100 and seg * k < 100
+    k32, seg32 = B.SphTape.plan(n, d, B.SPH_F32, 100, 30 * per_step)
+    assert (k32, seg32) == (50, 1)
+    assert B.SphTape.plan(n, d, B.SPH_F64, 100, 50 * per_step) == (34, 2)
+    assert B.SphTape.plan(n, d, B.SPH_F64, 100, 50 * per_step, with_plastic=True) == (25, 3)
+    with pytest.raises(B.SphError) as e:
+        B.SphTape.plan(n, d, B.SPH_F64, 100, per_seg)
+    assert e.value.code == B.SPH_E_CAPACITY

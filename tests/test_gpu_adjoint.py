@@ -387,6 +387,50 @@ def test_backward_is_deterministic_and_recomputes(oracle_mod):
     pr.close()
 
 
+@pytest.mark.parametrize("prec", PRECS, ids=PIDS)
+@pytest.mark.parametrize("name", ["strip2d", "neck3d", "bar2d"])
+def test_segmented_reverse_equals_whole(oracle_mod, name, prec):
+    """Slow steps reversed in segments of k_hist inner steps (two-level
+    checkpointing, a ragged last segment) give the gradient, the adjoint state
+    and the restored final state of the reverse pass over whole slow steps,
+    bitwise: the same kernels see the same recorded states.  One inner
+    checkpoint too few is refused before anything runs."""
+    print(f"[adjoint] segmented reverse {name} prec={prec}", flush=True)
+    c, _ = _run_case(name)
+    kh = c.run["fixed_inner"] if c.run["fixed_inner"] > 0 else 20000
+    pr = A.MultirateProblem(c, prec, k_hist=kh)
+    th = pr.theta0()
+    pr.forward(th)
+    pr.freeze()
+    kmax = int(pr.k_sched.max())
+    K = 7 if kmax <= 60 else kmax // 5 + 3
+    ns = -(-kmax // K)
+    assert ns >= 3 and kmax % K != 0, (kmax, K)
+    w = dev(np.random.default_rng(4).normal(0.0, 1.0, (c.dim, c.n)))
+    u_end = pr.forward(th).clone()
+    g_whole = pr.backward(w, recompute=True)
+    au, av = pr.adj.u.clone(), pr.adj.v.clone()
+    whole = pr.tape
+    pr.tape = B.SphTape(pr.nb, prec, c.run["n_slow"], K, with_plastic=pr.j2,
+                        with_diffusion=pr.diff, seg_cap=ns - 1)
+    pr.forward(th)
+    assert torch.equal(pr.st.u, u_end)
+    g_seg = pr.backward(w)
+    assert torch.equal(g_seg, g_whole)
+    assert torch.equal(pr.adj.u, au) and torch.equal(pr.adj.v, av)
+    assert torch.equal(pr.st.u, u_end)
+    assert pr.tape.hist_slow == -1
+    pr.tape = B.SphTape(pr.nb, prec, c.run["n_slow"], K, with_plastic=pr.j2,
+                        with_diffusion=pr.diff, seg_cap=ns - 2)
+    pr.forward(th)
+    with pytest.raises(B.SphError) as e:
+        pr.backward(w)
+    assert e.value.code == B.SPH_E_CAPACITY
+    assert torch.equal(pr.st.u, u_end)
+    pr.tape = whole
+    pr.close()
+
+
 def test_finite_differences_plate_subset(oracle_mod):
     """d(mean centre deflection)/d(E, D, C) on the 40 x 40 x 4 plate: the
     reverse pass against central differences of the GPU FP64 forward run with

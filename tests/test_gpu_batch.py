@@ -207,11 +207,13 @@ def test_whole_run_graph_equals_eager_bitwise(oracle_mod, prec):
     R.nb.close()
 
 
-def test_single_specimen_whole_run_graph(oracle_mod):
-    """Without a batch: one recorded forward + reverse equals the eager pair."""
+@pytest.mark.parametrize("k_hist,seg_cap", [(12, 0), (5, 2)], ids=["whole", "segments"])
+def test_single_specimen_whole_run_graph(oracle_mod, k_hist, seg_cap):
+    """Without a batch: one recorded forward + reverse equals the eager pair,
+    also with the slow steps reversed in segments (5 + 5 + 2 inner steps)."""
     from paper_2309_04010_amd import adjoint as A
     c = cases.strip2d(nx=20, ny=6, n_slow=3, fixed_inner=12, k_max=0)
-    pr = A.MultirateProblem(c, B.SPH_F64, k_hist=12)
+    pr = A.MultirateProblem(c, B.SPH_F64, k_hist=k_hist, seg_cap=seg_cap)
     th = pr.theta0()
     w = dev(np.random.default_rng(3).normal(0.0, 1.0, (2, c.n)))
     pr.forward(th)
