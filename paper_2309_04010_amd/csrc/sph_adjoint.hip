@@ -479,8 +479,8 @@ __global__ __launch_bounds__(256 * LPP) void k_adj_stress(
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   const bool active = (uint32_t)t < td.count;
-  uint32_t la;
-  const int64_t a_own = tile_own(td, active ? (uint32_t)t : 0u, la);
+  uint32_t la, nb4;
+  const int64_t a_own = tile_own(g.tslot, g.tmax, tile, td, active ? (uint32_t)t : 0u, la, nb4);
   T va[D == 3 ? 8 : 6];
   PK::load(smem_raw, window, la, va);
   T Qs[D][D];
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(256 * LPP) void k_adj_stress(
 #pragma unroll
     for (int k = 0; k < D; ++k) Qs[i][k] = T(0);
   if (active)
-    ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
       T vb[D == 3 ? 8 : 6];
       PK::load(smem_raw, window, l, vb);
       T d[3] = {T(0), T(0), T(0)};
@@ -609,13 +609,13 @@ __global__ __launch_bounds__(256 * LPP) void k_adj_gather(
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   T xa[D + D * D];
   PK::load(smem_raw, window, la, xa);
   const T* Ga = xa + D;
   T f[3] = {T(0), T(0), T(0)};
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     T xb[D + D * D];
     PK::load(smem_raw, window, l, xb);
     const T* Gbb = xb + D;
@@ -903,12 +903,12 @@ __global__ __launch_bounds__(256 * LPP) void k_acd_a(
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   const bool active = (uint32_t)t < td.count;
-  uint32_t la;
-  const int64_t a = tile_own(td, active ? (uint32_t)t : 0u, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, active ? (uint32_t)t : 0u, la, nb4);
   const vec4<T> xa = sx[la], fa = sf[la];
   T sv[3] = {T(0), T(0), T(0)}, m[3] = {T(0), T(0), T(0)}, e[3] = {T(0), T(0), T(0)};
   if (active)
-    ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+    ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
       const vec4<T> xb = sx[l], fb = sf[l];
       T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
       T r2 = d[0] * d[0] + d[1] * d[1];
@@ -1057,11 +1057,11 @@ __global__ __launch_bounds__(256 * LPP) void k_acd_b(TileGeo<T> g, const T* __re
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   const vec4<T> xa = sx[la], sa = ss[la];
   T t1 = T(0), m[3] = {T(0), T(0), T(0)};
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     const vec4<T> xb = sx[l], sb = ss[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T r2 = d[0] * d[0] + d[1] * d[1];

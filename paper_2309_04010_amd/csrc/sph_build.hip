@@ -608,27 +608,30 @@ __global__ void k_sched_fill(const uint32_t* key, const uint32_t* cs, const int6
 // ---------------------------------------------------------------------------
 // tiles: ELL of window-local neighbour indices.  The order of a particle's
 // neighbours is free (it only orders the terms of its sums), and is chosen
-// for the LDS banks: a window particle's staged values sit at a 16-byte (or
-// 48-byte) stride, so eight lanes that read eight windows slots distinct mod
-// 8 hit distinct groups of four banks.  Entry p of tile particle t takes, in
-// ascending order within the class, a neighbour whose slot is (t + p) mod 8
-// when one is left (else the next class that has one); the eight lanes of an
-// eighth of a wavefront -- eight particles at one entry with one lane per
-// particle, or four particles at entries p and p + 4 with two -- then read
-// distinct classes wherever the classes allow.
+// for the LDS banks: a window particle's staged values sit at 16-byte slots,
+// and a 128-bit LDS read serves sixteen lanes at a time, without a conflict
+// when their slots are distinct mod 16.  Entry p of tile particle t takes, in
+// ascending order within the class, a neighbour whose slot is
+//   t + (p mod 4) + 8 ((p / 4) mod 2) + 4 (p / 8)   (mod 16)
+// when one is left (else the next class that has one).  With one lane per
+// particle, sixteen particles at one entry then read distinct classes; with
+// two, eight particles at entries p and p + 4 (offsets 8 apart); with four,
+// four particles at p, p + 4, p + 8, p + 12 (offsets 0, 8, 4, 12).  Along one
+// particle's list every sixteen entries take every class once.
 constexpr int kEllSpread = 256;  // longer lists keep ascending order
 
-__global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __restrict__ off,
-                           const uint32_t* __restrict__ idx, int tmax, uint16_t* __restrict__ ell,
-                           int32_t* err) {
+__global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const uint32_t* __restrict__ tslot,
+                           const int64_t* __restrict__ off, const uint32_t* __restrict__ idx,
+                           int tmax, uint16_t* __restrict__ ell, int32_t* err) {
   const TileDesc& td = tiles[blockIdx.x];
   for (int t = threadIdx.x; t < tmax; t += blockDim.x) {
     uint32_t own = 0;
     int64_t j0 = 0, deg = 0;
     if ((uint32_t)t < td.count) {
-      const int64_t a = (uint32_t)t < td.count0 ? (int64_t)td.p0 + t
-                                                : (int64_t)td.p1 + (t - td.count0);
-      own = (uint32_t)t < td.count0 ? td.own_base + t : td.own_base1 + (t - td.count0);
+      // thread slot t holds own particle s (slots by descending degree)
+      const uint32_t sl = tslot[(int64_t)blockIdx.x * tmax + t] & 0xFFFFu;
+      const int64_t a = sl < td.count0 ? (int64_t)td.p0 + sl : (int64_t)td.p1 + (sl - td.count0);
+      own = sl < td.count0 ? td.own_base + sl : td.own_base1 + (sl - td.count0);
       j0 = off[a];
       deg = off[a + 1] - j0;
     } else {
@@ -660,13 +663,14 @@ __global__ void k_tile_ell(const TileDesc* __restrict__ tiles, const int64_t* __
       *at(j) = (uint16_t)loc;
     }
     if (!spread) continue;
-    int cur[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // next candidate of each class (ascending)
+    int cur[16];  // next candidate of each class (ascending)
+    for (int r = 0; r < 16; ++r) cur[r] = 0;
     for (int p = 0; p < (int)deg; ++p) {
-      const int d = (t + p) & 7;
+      const int d = (t + (p & 3) + 8 * ((p >> 2) & 1) + 4 * (p >> 3)) & 15;
       int pick = -1;
-      for (int k = 0; k < 8 && pick < 0; ++k) {
-        const int r = (d + k) & 7;
-        while (cur[r] < (int)deg && (L[cur[r]] & 7) != r) ++cur[r];
+      for (int k = 0; k < 16 && pick < 0; ++k) {
+        const int r = (d + k) & 15;
+        while (cur[r] < (int)deg && (L[cur[r]] & 15) != r) ++cur[r];
         if (cur[r] < (int)deg) pick = cur[r]++;
       }
       *at((uint32_t)p) = L[pick];
@@ -815,7 +819,7 @@ static int build_joint_rows(sph_nbr* nb, hipStream_t s) {
   struct RowPair {
     int64_t i;        // canonical pair
     uint32_t g;       // its anchor's group in the wavefront
-    uint32_t qa, qb;  // slot mod 8 of the two particles
+    uint32_t qa, qb;  // LDS slot mod 8 of the two particles
   };
   std::vector<RowPair> rp;
   for (int gi = 0; gi < kDampWidths; ++gi) {
@@ -881,10 +885,10 @@ static int build_joint_rows(sph_nbr* nb, hipStream_t s) {
             }
           }
           // lanes in eighths of 8: within an eighth, pairs whose particles'
-          // 16-byte LDS slots fall on distinct groups of four banks (slot mod
-          // 8) first -- the pairs of a row are independent, so their lane
-          // order is free; on the 1M plate this takes a fifth of the sweep's
-          // LDS bank-conflict cycles away
+          // 16-byte LDS slots are distinct mod 8 first -- the pairs of a row
+          // are independent, so their lane order is free.  (Groups of 16
+          // distinct mod 16, which a 128-bit read alone would want, measured
+          // slower: the row also writes 96 bits per particle.)
           {
             std::vector<char> used(rp.size(), 0);
             int64_t pos = first;
@@ -964,20 +968,31 @@ static int build_joint_rows(sph_nbr* nb, hipStream_t s) {
 // cell may exceed it up to `wmax_hard` (the whole LDS of a CU).
 static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
                       const std::vector<int64_t>& off, int tmax, int64_t wmax, int64_t wmax_hard,
-                      std::vector<TileDesc>& out, int64_t& window_max, int64_t& ell_len) {
+                      std::vector<TileDesc>& out, std::vector<uint32_t>& tslot,
+                      int64_t& window_max, int64_t& ell_len) {
   const int dim = nb->dim;
   out.clear();
+  tslot.clear();
   window_max = 0;
   ell_len = 0;
   auto own_index = [](const TileDesc& td, uint32_t t) -> int64_t {
     return t < td.count0 ? (int64_t)td.p0 + t : (int64_t)td.p1 + (t - td.count0);
   };
+  std::vector<uint32_t> ord;
   auto emit = [&](TileDesc& td) {
     uint32_t width = 0;
+    ord.resize(td.count);
     for (uint32_t t = 0; t < td.count; ++t) {
       const int64_t a = own_index(td, t);
       width = std::max<uint32_t>(width, (uint32_t)(off[a + 1] - off[a]));
+      ord[t] = t;
     }
+    auto deg = [&](uint32_t t) { return off[own_index(td, t) + 1] - off[own_index(td, t)]; };
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return deg(x) > deg(y); });
+    for (int t = 0; t < tmax; ++t)
+      tslot.push_back((uint32_t)t < td.count
+                          ? ord[t] | (uint32_t)((deg(ord[t]) + 3) / 4) << 16
+                          : 0u);
     td.width = (width + 3) & ~3u;
     td.ell_off = (uint32_t)ell_len;
     ell_len += (int64_t)td.width * tmax;
@@ -1106,7 +1121,8 @@ static void free_nbr(sph_nbr* h) {
                   h->B0,  h->Vf,   h->B0f,        h->gsum, h->gsumf, h->sa,      h->sb,      h->slev, h->akey,
                   h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk, h->gpart,
                   h->dgeo32, h->dgeo64, h->dloff, h->dloff_base,
-                  h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell};
+                  h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell,
+                  h->tiling[0].tslot, h->tiling[1].tslot};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (void* p : {(void*)h->spec, (void*)h->spec_off_dev, (void*)h->bt32, (void*)h->bt64,
@@ -1465,21 +1481,27 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
       Tiling& T = nb->tiling[prec];
       T.tmax = tile_tmax(prec);
       std::vector<TileDesc> tv;
+      std::vector<uint32_t> ts;
       rc_ = plan_tiles(nb, hcs, hoff, T.tmax, tile_wmax(prec, dim), tile_wmax_hard(prec, dim), tv,
-                       T.window_max, T.ell_len);
+                       ts, T.window_max, T.ell_len);
       if (rc_) {
         hipFree(terr);
         set_error("tile planning failed (a cell row window exceeds the LDS budget)");
         return rc_;
       }
       T.n_tiles = (int64_t)tv.size();
-      if ((rc_ = dalloc(&T.tiles, T.n_tiles)) || (rc_ = dalloc(&T.ell, T.ell_len))) return rc_;
+      if ((rc_ = dalloc(&T.tiles, T.n_tiles)) || (rc_ = dalloc(&T.ell, T.ell_len)) ||
+          (rc_ = dalloc(&T.tslot, std::max<int64_t>((int64_t)ts.size(), 1))))
+        return rc_;
       SPH_HIP(hipMemcpyAsync(T.tiles, tv.data(), T.n_tiles * sizeof(TileDesc),
                              hipMemcpyHostToDevice, s));
+      if (!ts.empty())
+        SPH_HIP(hipMemcpyAsync(T.tslot, ts.data(), ts.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, s));
       SPH_HIP(hipMemsetAsync(terr, 0, sizeof(int32_t), s));
       if (T.n_tiles > 0) {
-        k_tile_ell<<<(unsigned)T.n_tiles, 128, 0, s>>>(T.tiles, nb->nbr_off, nb->nbr_idx, T.tmax,
-                                                       T.ell, terr);
+        k_tile_ell<<<(unsigned)T.n_tiles, 128, 0, s>>>(T.tiles, T.tslot, nb->nbr_off, nb->nbr_idx,
+                                                       T.tmax, T.ell, terr);
         SPH_LAUNCH_CHECK();
       }
       int32_t he = 0;

@@ -117,10 +117,14 @@ constexpr int kStaticKeBlocks = 1 << 16;  // sph_drift_ke_noalloc: 512 KiB of pa
 // are contiguous; entries past a particle's degree hold its own index (a zero
 // contribution).  `width` is a multiple of 4.
 // A tile's own particles are one run of a row of cells, or two runs (the same
-// x-range of two stacked rows): thread t < count0 takes particle p0 + t at
-// window position own_base + t, the others p1 + (t - count0) at own_base1 +
-// (t - count0).  The window is the concatenation of nruns runs of sorted
+// x-range of two stacked rows): own particle s < count0 is p0 + s at window
+// position own_base + s, the others p1 + (s - count0) at own_base1 +
+// (s - count0).  The window is the concatenation of nruns runs of sorted
 // particles (the neighbouring rows' cells over the x-range widened by one).
+// Thread slots take the own particles by descending neighbour count (stable),
+// so that the lanes of a wavefront walk lists of about one length and stop
+// at their own: tslot[tile][t] = s | (blocks of four entries of s's list)
+// << 16 (0 for t >= count).
 struct TileDesc {
   uint32_t p0, count, ell_off, width;
   uint32_t nruns, window, own_base, count0;
@@ -136,6 +140,7 @@ struct Tiling {
   int64_t ell_len = 0;
   TileDesc* tiles = nullptr;  // device
   uint16_t* ell = nullptr;    // device
+  uint32_t* tslot = nullptr;  // device [n_tiles][tmax]
 };
 
 // damping pair word: a_loc | b_loc << 16 (locals inside the anchor's

@@ -260,6 +260,7 @@ template <typename T>
 struct TileGeo {
   const TileDesc* tiles;
   const uint16_t* ell;
+  const uint32_t* tslot;
   int tmax;
   int64_t n_tiles;
   const double* X;
@@ -274,7 +275,8 @@ template <typename T>
 static TileGeo<T> tile_geo(const sph_nbr* nb, int prec) {
   const Tiling& t = nb->tiling[prec];
   Geo<T> g = geo<T>(nb);
-  return TileGeo<T>{t.tiles, t.ell, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5, g.gsum};
+  return TileGeo<T>{t.tiles, t.ell, t.tslot, t.tmax, t.n_tiles, g.X, g.V, g.B0, g.n, g.inv_h, g.c5,
+                    g.gsum};
 }
 
 // N values per window particle as N/4 arrays of 4-vectors ([N/4][window])
@@ -335,13 +337,20 @@ struct Pk {
 };
 
 // own particle t of a tile: its sorted index and its window position
-__device__ __forceinline__ int64_t tile_own(const TileDesc& td, uint32_t t, uint32_t& la) {
-  if (t < td.count0) {
-    la = td.own_base + t;
-    return (int64_t)td.p0 + t;
+// the own particle of thread slot t of a tile, its window position la and
+// the blocks of four entries of its neighbour list
+__device__ __forceinline__ int64_t tile_own(const uint32_t* __restrict__ tslot, int tmax,
+                                            int64_t tile, const TileDesc& td, uint32_t t,
+                                            uint32_t& la, uint32_t& nb4) {
+  const uint32_t info = tslot[tile * tmax + t];
+  const uint32_t s = info & 0xFFFFu;
+  nb4 = info >> 16;
+  if (s < td.count0) {
+    la = td.own_base + s;
+    return (int64_t)td.p0 + s;
   }
-  la = td.own_base1 + (t - td.count0);
-  return (int64_t)td.p1 + (t - td.count0);
+  la = td.own_base1 + (s - td.count0);
+  return (int64_t)td.p1 + (s - td.count0);
 }
 
 __device__ __forceinline__ int64_t xcd_tile(int64_t n_tiles) {
@@ -414,9 +423,9 @@ __device__ __forceinline__ WinMap win_map(const TileDesc& td) {
 // issued after it.
 template <int LPP, typename F>
 __device__ __forceinline__ void ell_walk(const uint16_t* ell, uint32_t ell_off, int tmax, int t,
-                                         int h, uint32_t width, F&& f) {
+                                         int h, uint32_t blocks, F&& f) {
   const uint2* e = reinterpret_cast<const uint2*>(ell + ell_off) + t;
-  const int nb4 = (int)(width >> 2);
+  const int nb4 = (int)blocks;
   if (h >= nb4) return;
   const int last = nb4 - 1;
   auto ld = [&](int c) -> uint2 { return e[(int64_t)(c < last ? c : last) * tmax]; };

@@ -96,15 +96,15 @@ __global__ __launch_bounds__(256 * LPP) void k_stress(TileGeo<T> g, MatP<T> m,
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   const vec4<T> xa = sx[la], ua = su[la];
   T G[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) G[i][k] = T(0);
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     const vec4<T> xb = sx[l], ub = su[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
@@ -262,12 +262,12 @@ __global__ __launch_bounds__(256 * LPP) void k_momentum(TileGeo<T> g,
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   T xa[D + D * D];
   PK::load(smem_raw, window, la, xa);
   T f[3] = {T(0), T(0), T(0)};
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     T xb[D + D * D];
     PK::load(smem_raw, window, l, xb);
     const T* Pb = xb + D;
@@ -720,14 +720,14 @@ __global__ __launch_bounds__(256 * LPP) void k_diff_grad(TileGeo<T> g, const T* 
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   const vec4<T> xa = sx[la];
   const T fa = sf[la];
   T s[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) s[k] = T(0);
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     const vec4<T> xb = sx[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T r2 = d[0] * d[0] + d[1] * d[1];
@@ -828,15 +828,15 @@ __global__ __launch_bounds__(256 * LPP) void k_diff_F(TileGeo<T> g, const double
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   const vec4<T> xa = sx[la], ua = su[la];
   T G[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) G[i][k] = T(0);
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     const vec4<T> xb = sx[l], ub = su[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T du[3] = {ub.x - ua.x, ub.y - ua.y, ub.z - ua.z};
@@ -933,12 +933,12 @@ __global__ __launch_bounds__(256 * LPP) void k_diff_div(TileGeo<T> g, T* __restr
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   const vec4<T> xa = sx[la], ya = sy[la];
   T m[3] = {T(0), T(0), T(0)};
   T tb = T(0);
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     const vec4<T> xb = sx[l], yb = sy[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T r2 = d[0] * d[0] + d[1] * d[1];
@@ -1482,11 +1482,11 @@ __global__ __launch_bounds__(256 * LPP) void k_gsum(TileGeo<T> g, T* __restrict_
   __syncthreads();
   const int t = threadIdx.x / LPP, h = threadIdx.x % LPP;
   if ((uint32_t)t >= td.count) return;
-  uint32_t la;
-  const int64_t a = tile_own(td, (uint32_t)t, la);
+  uint32_t la, nb4;
+  const int64_t a = tile_own(g.tslot, g.tmax, tile, td, (uint32_t)t, la, nb4);
   const vec4<T> xa = sx[la];
   T m[3] = {T(0), T(0), T(0)};
-  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, td.width, [&](uint32_t l) {
+  ell_walk<LPP>(g.ell, td.ell_off, g.tmax, t, h, nb4, [&](uint32_t l) {
     const vec4<T> xb = sx[l];
     T d[3] = {xa.x - xb.x, xa.y - xb.y, xa.z - xb.z};
     T r2 = d[0] * d[0] + d[1] * d[1];
