@@ -8,6 +8,8 @@
 // the handle; later launches on that handle use them.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <vector>
 
 #include "sph_common.h"
@@ -145,25 +147,36 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
   }
   if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) return rc;
   sph_tuning res{};
-  const int reps = 3;
+  const int reps = 3, trials = 3;
   Tune& tn = nb->tune;
   // tiled kernels: vary one kernel's lanes at a time (the other launch of
-  // the pair is the same in every candidate, so the fastest sum picks it)
+  // the pair is the same in every candidate, so the fastest sum picks it);
+  // the candidates take turns over several trials and each keeps its best
+  // time, so that a slow moment of the device does not decide
   auto pick = [&](int k, std::initializer_list<int> cands, auto&& run, double* best_ms) -> int {
-    int best = tn.lpp[k][prec];
-    double bt = 1e300;
-    for (int c : cands) {
-      tn.lpp[k][prec] = c;
-      double ms = 0.0;
-      int r = time_ms(s, reps, run, &ms);
-      if (r) return r;
-      if (ms < bt) {
-        bt = ms;
-        best = c;
+    double bt[4] = {1e300, 1e300, 1e300, 1e300};
+    if (cands.size() > 4) return SPH_E_ARG;
+    for (int tr = 0; tr < trials; ++tr) {
+      int i = 0;
+      for (int c : cands) {
+        tn.lpp[k][prec] = c;
+        double ms = 0.0;
+        int r = time_ms(s, reps, run, &ms);
+        if (r) return r;
+        bt[i] = std::min(bt[i], ms);
+        ++i;
       }
     }
+    int i = 0, best = tn.lpp[k][prec];
+    *best_ms = 1e300;
+    for (int c : cands) {
+      if (bt[i] < *best_ms) {
+        *best_ms = bt[i];
+        best = c;
+      }
+      ++i;
+    }
     tn.lpp[k][prec] = best;
-    *best_ms = bt;
     return SPH_OK;
   };
   auto solid = [&]() { return solid_stage(nb, m, &w, dt_s, s, false); };
@@ -190,19 +203,20 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
     int best = 0;
     double bt = 1e300;
-    for (int g : {8, 16, 32, 64}) {
-      tn.damp_g[prec][col] = g;
-      // the records laid out for this width, outside the timing
-      if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) break;
-      // time the whole sweep: only this colour's launch differs between candidates
-      double t = 0.0;
-      rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
-      if (rc) break;
-      if (t < bt) {
-        bt = t;
-        best = g;
+    for (int tr = 0; tr < trials && rc == SPH_OK; ++tr)
+      for (int g : {8, 16, 32, 64}) {
+        tn.damp_g[prec][col] = g;
+        // the records laid out for this width, outside the timing
+        if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) break;
+        // time the whole sweep: only this colour's launch differs between candidates
+        double t = 0.0;
+        rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
+        if (rc) break;
+        if (t < bt) {
+          bt = t;
+          best = g;
+        }
       }
-    }
     if (rc) break;
     tn.damp_g[prec][col] = best;
     sweep = bt;
