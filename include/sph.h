@@ -195,6 +195,28 @@ int sph_build_neighbors(int dim, int64_t n, const double* X, const double* V, do
 int sph_nbr_destroy(sph_nbr* nbr);
 int sph_nbr_query(const sph_nbr* nbr, sph_nbr_info* info);
 
+/* Device scratch of the per-step calls (the boundary's workspace): the
+ * per-run damping records and inverse masses of both precisions (Sec. 4.3),
+ * the block partials of the kinetic-energy reduction (Sec. 4.2) and of the
+ * parameter gradients.  The handle allocates it when it is built; no
+ * per-step call allocates.  A caller that manages device memory itself (a
+ * pool, memory shared with other work) can hand its own in:
+ * sph_workspace_size writes the bytes needed to *bytes (fixed for the
+ * handle); sph_set_workspace makes the handle use [ws, ws + bytes) from then
+ * on and frees the handle's own block, or, with ws = NULL, allocates a block
+ * of its own again.  ws: device memory on the handle's device, 256-byte
+ * aligned, at least sph_workspace_size bytes, not used by anything else
+ * (another handle included) while this handle uses it, and kept until the
+ * handle is destroyed or given another workspace; its contents are the
+ * library's.  The call waits for `stream`, and for the device, so no call of
+ * the handle may still run; it zeroes the gradient partials, marks the
+ * damping records for re-computation (the next damping call lays them out)
+ * and drops the cached whole-run graph.  Synchronous.  Errors: SPH_E_ARG
+ * (NULL handle or bytes, ws misaligned or smaller than needed),
+ * SPH_E_DEVICE. */
+int sph_workspace_size(const sph_nbr* nbr, int64_t* bytes);
+int sph_set_workspace(sph_nbr* nbr, void* ws, int64_t bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * One solid stage of an inner step (Sec. 3.1): deformation gradient from u
  *   F_a = I + (sum_b V_b (u_b - u_a) (x) grad_a W_ab) B0_a

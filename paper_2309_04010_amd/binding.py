@@ -32,6 +32,7 @@ EXPORTED = [
     "sph_constitutive",
     "sph_constitutive_vjp", "sph_build_neighbors_batched", "sph_advance_multirate_graph",
     "sph_autotune", "sph_set_tuning", "sph_get_tuning", "sph_default_steps", "sph_drift_ke_noalloc",
+    "sph_workspace_size", "sph_set_workspace",
 ]
 SPH_KERNEL_NAMES = ["stress", "momentum", "damping", "drift_ke", "diff_grad", "diff_div", "load",
                     "adj_stress", "adj_gather", "adj_damping"]
@@ -123,6 +124,8 @@ def lib():
     L.sph_build_neighbors.argtypes = [C.c_int, i64, vp, vp, dbl, vp, C.POINTER(vp)]
     L.sph_nbr_destroy.argtypes = [vp]
     L.sph_nbr_query.argtypes = [vp, C.POINTER(NbrInfo)]
+    L.sph_workspace_size.argtypes = [vp, C.POINTER(i64)]
+    L.sph_set_workspace.argtypes = [vp, vp, i64, vp]
     L.sph_solid_relax_step.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp]
     L.sph_damping_sweep.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, dbl, vp]
     L.sph_drift_ke.argtypes = [vp, C.POINTER(Material), C.POINTER(State), dbl, vp, vp]
@@ -368,6 +371,29 @@ def sph_drift_ke_noalloc(nbr, mat, st, dt_s, ke_out=None, stream=None):
     cs = st.cstruct(nbr)
     _check(lib().sph_drift_ke_noalloc(nbr.handle, C.byref(mat), C.byref(cs), float(dt_s),
                                       _dptr(ke_out), _stream(stream)))
+
+
+def sph_workspace_size(nbr):
+    """Bytes of the per-step scratch of the handle (its workspace)."""
+    b = i64(0)
+    _check(lib().sph_workspace_size(nbr.handle, C.byref(b)))
+    return int(b.value)
+
+
+def sph_set_workspace(nbr, ws=None, stream=None):
+    """Make the handle use the device tensor `ws` (any dtype, contiguous,
+    256-byte aligned, at least sph_workspace_size bytes) as its per-step
+    scratch, or its own block again with ws=None.  The caller keeps `ws`
+    alive while the handle uses it."""
+    if ws is None:
+        _check(lib().sph_set_workspace(nbr.handle, None, 0, _stream(stream)))
+        nbr._ws = None
+        return
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise SphError(SPH_E_ARG, "ws must be a contiguous device tensor")
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().sph_set_workspace(nbr.handle, _dptr(ws), int(nbytes), _stream(stream)))
+    nbr._ws = ws
 
 
 def sph_load_step(nbr, st, dt_l, stream=None):

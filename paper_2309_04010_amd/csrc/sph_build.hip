@@ -1115,19 +1115,51 @@ static int plan_tiles(const sph_nbr* nb, const std::vector<uint32_t>& cs,
 }
 
 // ---------------------------------------------------------------------------
+// the per-step scratch: (pair word, q) damping records of both precisions
+// (8 B in FP32, 16 B (word, pad, q) in FP64, and a sentinel record after the
+// last pair), the inverse masses of both precisions, the kinetic-energy block
+// partials and the gradient partials, each at a 256-byte boundary
+constexpr int kWsParts = 6;
+static int64_t ws_layout(const sph_nbr* nb, int64_t off[kWsParts + 1]) {
+  const int64_t n1 = std::max<int64_t>(nb->n, 1);
+  const int64_t part[kWsParts] = {(nb->n_upairs + 1) * 8, (nb->n_upairs + 1) * 16,
+                                  n1 * (int64_t)sizeof(float), n1 * (int64_t)sizeof(double),
+                                  kKeMaxBlocks * (int64_t)sizeof(double),
+                                  nb->gpart_slots * SPH_NGRAD * (int64_t)sizeof(double)};
+  off[0] = 0;
+  for (int i = 0; i < kWsParts; ++i) off[i + 1] = (off[i] + part[i] + 255) & ~int64_t(255);
+  return off[kWsParts];
+}
+
+// point the handle's scratch into `base` and clear what must start at zero
+static int ws_attach(sph_nbr* nb, char* base, hipStream_t s) {
+  int64_t off[kWsParts + 1];
+  ws_layout(nb, off);
+  nb->dwq[SPH_F32] = base + off[0];
+  nb->dwq[SPH_F64] = base + off[1];
+  nb->imass[SPH_F32] = base + off[2];
+  nb->imass[SPH_F64] = base + off[3];
+  nb->ke_partial = reinterpret_cast<double*>(base + off[4]);
+  nb->gpart = reinterpret_cast<double*>(base + off[5]);
+  SPH_HIP(hipMemsetAsync(nb->gpart, 0, nb->gpart_slots * SPH_NGRAD * sizeof(double), s));
+  nb->damp_pre = false;
+  for (int p = 0; p < 2; ++p)
+    for (int c = 0; c < 8; ++c) nb->damp_g_used[p][c] = 0;
+  return SPH_OK;
+}
+
 static void free_nbr(sph_nbr* h) {
   if (!h) return;
   void* ptrs[] = {h->key, h->perm, h->cell_start, h->nbr_off, h->nbr_idx, h->X,   h->V,
                   h->B0,  h->Vf,   h->B0f,        h->gsum, h->gsumf, h->sa,      h->sb,      h->slev, h->akey,
-                  h->aoff, h->anlev, h->ctrl,     h->ke_partial, h->dpair, h->ablk, h->gpart,
+                  h->aoff, h->anlev, h->ctrl,     h->ws_own, h->dpair, h->ablk,
                   h->dgeo32, h->dgeo64, h->dloff, h->dloff_base,
                   h->tiling[0].tiles, h->tiling[0].ell, h->tiling[1].tiles, h->tiling[1].ell,
                   h->tiling[0].tslot, h->tiling[1].tslot};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (void* p : {(void*)h->spec, (void*)h->spec_off_dev, (void*)h->bt32, (void*)h->bt64,
-                  (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg, h->dwq[0], h->dwq[1],
-                  h->imass[0], h->imass[1]})
+                  (void*)h->gdiff, (void*)h->dsegs, (void*)h->cell_seg})
     if (p) hipFree(p);
   for (int gi = 0; gi < kDampWidths; ++gi)
     for (void* p : {(void*)h->drow[gi], (void*)h->drow_base[gi], (void*)h->dwave[gi],
@@ -1527,23 +1559,17 @@ static int build(int dim, int64_t n, const double* X, const double* V, double h,
   SPH_HIP(hipMalloc(&nb->ctrl, sizeof(Ctrl)));
   SPH_HIP(hipMemsetAsync(nb->ctrl, 0, sizeof(Ctrl), s));
   SPH_HIP(hipHostMalloc((void**)&nb->ctrl_host, sizeof(Ctrl), hipHostMallocDefault));
-  SPH_HIP(hipMalloc(&nb->ke_partial, kKeMaxBlocks * sizeof(double)));
-  // per-run damping coefficients
-  // (pair word, q) records, 8 B in FP32, 16 B (word, pad, q) in FP64, and a
-  // sentinel record after the last pair
-  SPH_HIP(hipMalloc(&nb->dwq[SPH_F32], (nb->n_upairs + 1) * 8));
-  SPH_HIP(hipMalloc(&nb->dwq[SPH_F64], (nb->n_upairs + 1) * 16));
-  SPH_HIP(hipMalloc(&nb->imass[SPH_F32], std::max<int64_t>(n, 1) * sizeof(float)));
-  SPH_HIP(hipMalloc(&nb->imass[SPH_F64], std::max<int64_t>(n, 1) * sizeof(double)));
   // per-workgroup partial sums of the parameter gradients (reverse mode)
   {
     int64_t slots = (n + kDiffPerBlock - 1) / kDiffPerBlock;
     for (int prec = 0; prec < 2; ++prec)
       slots = std::max<int64_t>(slots, 8 * ((nb->tiling[prec].n_tiles + 7) / 8));
     nb->gpart_slots = std::max<int64_t>(slots, 1);
-    SPH_HIP(hipMalloc(&nb->gpart, nb->gpart_slots * SPH_NGRAD * sizeof(double)));
-    SPH_HIP(hipMemsetAsync(nb->gpart, 0, nb->gpart_slots * SPH_NGRAD * sizeof(double), s));
   }
+  // the per-step scratch, in one block of the handle's own
+  int64_t off[kWsParts + 1];
+  SPH_HIP(hipMalloc(&nb->ws_own, ws_layout(nb, off)));
+  if ((rc_ = ws_attach(nb, static_cast<char*>(nb->ws_own), s))) return rc_;
   SPH_HIP(hipStreamSynchronize(s));
   return SPH_OK;
 }
@@ -1609,6 +1635,50 @@ extern "C" int sph_nbr_destroy(sph_nbr* nb) {
   if (!nb) return SPH_OK;
   hipDeviceSynchronize();
   free_nbr(nb);
+  return SPH_OK;
+}
+
+extern "C" int sph_workspace_size(const sph_nbr* nb, int64_t* bytes) {
+  clear_error();
+  if (!nb || !bytes) {
+    set_error("null argument");
+    return SPH_E_ARG;
+  }
+  int64_t off[kWsParts + 1];
+  *bytes = ws_layout(nb, off);
+  return SPH_OK;
+}
+
+extern "C" int sph_set_workspace(sph_nbr* nb, void* ws, int64_t bytes, void* stream) {
+  clear_error();
+  if (!nb) {
+    set_error("null handle");
+    return SPH_E_ARG;
+  }
+  int64_t off[kWsParts + 1];
+  const int64_t need = ws_layout(nb, off);
+  if (ws && (bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u))) {
+    set_error("workspace of %lld bytes at %p: need %lld bytes at a 256-byte boundary",
+              (long long)bytes, ws, (long long)need);
+    return SPH_E_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  SPH_HIP(hipStreamSynchronize(s));
+  SPH_HIP(hipDeviceSynchronize());
+  free_graph_cache(nb);  // its launches hold the old scratch addresses
+  char* base = static_cast<char*>(ws);
+  if (ws) {
+    if (nb->ws_own) {
+      SPH_HIP(hipFree(nb->ws_own));
+      nb->ws_own = nullptr;
+    }
+  } else {
+    if (!nb->ws_own) SPH_HIP(hipMalloc(&nb->ws_own, need));
+    base = static_cast<char*>(nb->ws_own);
+  }
+  int rc = ws_attach(nb, base, s);
+  if (rc) return rc;
+  SPH_HIP(hipStreamSynchronize(s));
   return SPH_OK;
 }
 
