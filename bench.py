@@ -34,7 +34,7 @@ strips.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner M] [--no-cpu]
                   [--no-fp64] [--no-sweep] [--no-coupled] [--necking none|sample|full]
                   [--necking-compare] [--nx N] [--copy-calibration] [--full-adjoint]
-                  [--no-full-adjoint]
+                  [--no-full-adjoint] [--no-small] [--neck3d-slow N]
 """
 from __future__ import annotations
 
@@ -634,6 +634,9 @@ def main():
                     help="necking runs: sample = the full 2D run and the first 1000 load increments "
                          "of the 3D one; full = both full runs")
     ap.add_argument("--no-neck3d", action="store_true", help="skip the neck3d, bar2d and strip2d runs")
+    ap.add_argument("--no-small", action="store_true", help="skip the bar2d and strip2d runs")
+    ap.add_argument("--neck3d-slow", type=int, default=100,
+                    help="loading slow steps of the neck3d runs (1000 inner steps each)")
     ap.add_argument("--full-adjoint", action="store_true",
                     help="run the whole checkpointed adjoint (50 slow x 1000 inner steps) in FP64 as "
                          "well as in FP32 (the FP32 run is in the default bench)")
@@ -792,7 +795,7 @@ def main():
         full_adjoint = run_full_adjoint(case, torch, B, A, inner=args.inner, with_fp64=args.full_adjoint)
         print("[bench] whole checkpointed adjoint done", flush=True)
 
-    small = None if args.no_neck3d else run_small_configs(torch, B)
+    small = None if (args.no_neck3d or args.no_small) else run_small_configs(torch, B)
     if small:
         print("[bench] bar2d / strip2d done", flush=True)
 
@@ -801,10 +804,10 @@ def main():
     neck = None
     if not args.no_neck3d:
         nc = cases.neck3d()
-        neck = {"workload": f"neck3d 100x20x20 ({nc.n} particles), J2, 100 loading slow steps x 1000 inner "
-                            f"steps, forward"}
+        neck = {"workload": f"neck3d 100x20x20 ({nc.n} particles), J2, {args.neck3d_slow} loading slow "
+                            f"steps x 1000 inner steps, forward"}
         for prec, tag in ((B.SPH_F32, "f32"), (B.SPH_F64, "f64")):
-            info, _ = run_gpu(nc, prec, 100, 1, 1000, torch, B, profile=False)
+            info, _ = run_gpu(nc, prec, args.neck3d_slow, 1, 1000, torch, B, profile=False)
             neck[tag] = dict(seconds=info["seconds"], inner_steps=info["total_inner"], pairs=info["pairs"],
                              interactions_per_s=info["pairs"] * info["total_inner"] / info["seconds"],
                              status=info["status"], u_finite=info["u_finite"])

@@ -232,6 +232,7 @@ struct sph_nbr {
   void* imass[2] = {nullptr, nullptr};  // [n] inverse mass (0 for fixed particles)
   mutable bool damp_pre = false;        // set by the driver while they are valid
   void* graph_cache = nullptr;       // instantiated whole-run graph (sph_advance_multirate_graph)
+  void* chunk_cache = nullptr;       // instantiated chunk of inner steps (sph_advance_multirate)
   // the per-step scratch (dwq, imass, ke_partial, gpart) is carved from one
   // block: the handle's own (ws_own) or the caller's (sph_set_workspace)
   void* ws_own = nullptr;

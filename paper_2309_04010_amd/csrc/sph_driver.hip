@@ -135,6 +135,20 @@ struct GraphChunk {
   }
 };
 
+// the instantiated chunk of inner steps of sph_advance_multirate, kept with
+// the arguments its launches were recorded with
+struct ChunkGraph {
+  std::vector<unsigned char> key;
+  GraphChunk gc;
+};
+
+template <typename S>
+void key_add(std::vector<unsigned char>& k, const S* p) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+  if (p) k.insert(k.end(), b, b + sizeof(S));
+  else k.push_back(0);
+}
+
 // checkpoint slice l of a tape <-> the state arrays
 int tape_copy(const sph_nbr* nb, const sph_material* m, const sph_state* st, const sph_tape* tp,
               int l, bool to_tape, hipStream_t s) {
@@ -397,37 +411,59 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     rep->k_max = k_max;
     rep->total_inner = 0;
   }
-  hipStream_t user = (hipStream_t)stream;
-  hipStream_t s = user;
-  hipStream_t own = nullptr;
-  hipEvent_t ev = nullptr;
-  GraphChunk gc;
+  hipStream_t s = (hipStream_t)stream;
+  hipGraphExec_t exec = nullptr;
   const bool graph = cfg->use_graph != 0;
   BatGuard bat_guard{nb};
-  if ((rc = batch_begin(nb, m, cfg, user))) return rc;
-  if ((rc = damp_prepare(nb, m, st, cfg->eta, dt_s, user))) return rc;
+  if ((rc = batch_begin(nb, m, cfg, s))) return rc;
+  if ((rc = damp_prepare(nb, m, st, cfg->eta, dt_s, s))) return rc;
   if (graph) {
-    // capture needs a non-null stream: run on a private one ordered after `user`
-    SPH_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
-    SPH_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    SPH_HIP(hipEventRecord(ev, user));
-    SPH_HIP(hipStreamWaitEvent(own, ev, 0));
-    s = own;
-    if (nb->prof) nb->prof->suspend = true;
-    SPH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    rc = inner_steps(nb, m, st, dt_s, cfg->eta, chunk, s);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &g);
-    if (nb->prof) nb->prof->suspend = false;
-    gc.graph = g;
-    if (rc == SPH_OK && e != hipSuccess) {
-      set_error("graph capture failed: %s", hipGetErrorString(e));
-      rc = SPH_E_DEVICE;
+    // one chunk of inner steps as a graph, kept on the handle for later
+    // calls with the same arguments
+    std::vector<unsigned char> key;
+    key_add(key, m);
+    key_add(key, st);
+    key_add(key, &dt_s);
+    key_add(key, &cfg->eta);
+    key_add(key, &chunk);
+    key_add(key, &nb->tune);
+    const Bat bv = bat_view(nb);
+    key_add(key, &bv);
+    ChunkGraph* cg = reinterpret_cast<ChunkGraph*>(nb->chunk_cache);
+    if (!cg || cg->key != key) {
+      delete cg;
+      cg = new ChunkGraph();
+      const_cast<sph_nbr*>(nb)->chunk_cache = cg;
+      // capture needs a non-null stream: a private one, which runs nothing
+      hipStream_t cap = nullptr;
+      SPH_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      if (nb->prof) nb->prof->suspend = true;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        rc = inner_steps(nb, m, st, dt_s, cfg->eta, chunk, cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cap, &g);
+        cg->gc.graph = g;
+      }
+      if (nb->prof) nb->prof->suspend = false;
+      hipStreamDestroy(cap);
+      if (rc == SPH_OK && e != hipSuccess) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        rc = SPH_E_DEVICE;
+      }
+      if (rc == SPH_OK &&
+          hipGraphInstantiate(&cg->gc.exec, cg->gc.graph, nullptr, nullptr, 0) != hipSuccess) {
+        set_error("graph instantiation failed");
+        rc = SPH_E_DEVICE;
+      }
+      if (rc) {
+        delete cg;
+        const_cast<sph_nbr*>(nb)->chunk_cache = nullptr;
+        return rc;
+      }
+      cg->key = key;
     }
-    if (rc == SPH_OK && hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0) != hipSuccess) {
-      set_error("graph instantiation failed");
-      rc = SPH_E_DEVICE;
-    }
+    exec = cg->gc.exec;
   }
   int warn = 0;
   for (int32_t l = 0; l < cfg->n_slow && rc == SPH_OK; ++l) {
@@ -465,7 +501,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     for (;;) {
       int64_t mcount = graph ? chunk : std::min<int64_t>(chunk, nk - launched);
       if (graph) {
-        if (hipGraphLaunch(gc.exec, s) != hipSuccess) {
+        if (hipGraphLaunch(exec, s) != hipSuccess) {
           set_error("graph launch failed");
           rc = SPH_E_DEVICE;
           break;
@@ -500,25 +536,14 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
       break;
     }
   }
-  if (graph) {
-    hipEvent_t ev2 = nullptr;
-    if (hipEventCreateWithFlags(&ev2, hipEventDisableTiming) == hipSuccess) {
-      hipEventRecord(ev2, s);
-      hipStreamWaitEvent(user, ev2, 0);
-      hipStreamSynchronize(s);
-      hipEventDestroy(ev2);
-    }
-    hipEventDestroy(ev);
-    hipStreamDestroy(own);
-  }
   if (rc) return rc;
   if (tape) {
-    if ((rc = tape_copy(nb, m, st, tape, cfg->n_slow, true, user))) return rc;
+    if ((rc = tape_copy(nb, m, st, tape, cfg->n_slow, true, s))) return rc;
     tape->n_rec = cfg->n_slow;
     tape->hist_slow = recorded ? cfg->n_slow - 1 : -1;
     tape->dt_s = dt_s;
     tape->dt_slow = dt_slow;
-    SPH_HIP(hipStreamSynchronize(user));
+    SPH_HIP(hipStreamSynchronize(s));
   }
   return warn ? SPH_W_NOT_CONVERGED : SPH_OK;
 }
@@ -732,18 +757,13 @@ struct WholeGraph {
   }
 };
 
-template <typename S>
-void key_add(std::vector<unsigned char>& k, const S* p) {
-  const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
-  if (p) k.insert(k.end(), b, b + sizeof(S));
-  else k.push_back(0);
-}
-
 }  // namespace
 
 void sph::free_graph_cache(sph_nbr* nb) {
   delete reinterpret_cast<WholeGraph*>(nb->graph_cache);
   nb->graph_cache = nullptr;
+  delete reinterpret_cast<ChunkGraph*>(nb->chunk_cache);
+  nb->chunk_cache = nullptr;
 }
 
 extern "C" int sph_advance_multirate_backward(const sph_nbr* nb, const sph_material* m,

@@ -15,6 +15,7 @@ Eager launches and hipGraph chunk replays give bitwise-identical results.
 """
 import numpy as np
 import pytest
+import torch
 
 from paper_2309_04010_amd import binding as B
 from paper_2309_04010_amd import cases
@@ -125,6 +126,26 @@ def test_graph_equals_eager_bitwise(oracle_mod):
     assert np.array_equal(a["k"][1], b["k"][1])
     assert np.array_equal(a["u"][1], b["u"][1])
     assert np.array_equal(a["v"][1], b["v"][1])
+
+
+def test_graph_chunk_reused_and_recaptured(oracle_mod):
+    """The chunk graph of sph_advance_multirate stays on the handle: a call
+    with the same arguments replays it, a call with another material records
+    it again; every run equals the eager one bitwise, counts included."""
+    from paper_2309_04010_amd import adjoint as A
+    c = cases.bar2d(n_slow=2)
+    pe = A.MultirateProblem(c, B.SPH_F64, chunk=50)
+    pg = A.MultirateProblem(c, B.SPH_F64, chunk=50, use_graph=1)
+    th = pe.theta0()
+    th2 = th.copy()
+    th2[0] *= 1.1
+    for t in (th, th, th2, th):
+        ue = pe.forward(t, record=False).clone()
+        ug = pg.forward(t, record=False).clone()
+        assert np.array_equal(pe.last["k"], pg.last["k"])
+        assert torch.equal(ue, ug)
+    pe.close()
+    pg.close()
 
 
 def test_bar_fp32_frozen_schedule(oracle_mod):
