@@ -518,13 +518,18 @@ int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, con
  * runs to come.  Synchronous; allocates scratch for its own duration.
  * sph_set_tuning / sph_get_tuning write and read the choices directly
  * (damp_lanes 0 = automatic: 16, widened while a wavefront's anchors would
- * exceed the LDS). */
+ * exceed the LDS).  damp_idle chooses what the lanes of a damping row
+ * without a pair do: 1 = update a spare slot with a zero coefficient (no
+ * branch: shorter rows, for passes of few wavefronts), 2 = skip the row's LDS
+ * work (a branch: less LDS traffic, for passes of many wavefronts), 0 =
+ * automatic (2 from 512 wavefronts a pass up); the results are the same. */
 typedef struct {
   int32_t lpp_stress;      /* 1, 2, 4 */
   int32_t lpp_momentum;    /* 1, 2, 4 */
   int32_t lpp_adj_stress;  /* 1, 2, 4 */
   int32_t lpp_adj_gather;  /* 1, 2, 4 */
   int32_t damp_lanes[8];   /* per colour: 0, 8, 16, 32, 64 */
+  int32_t damp_idle[8];    /* per colour: 0, 1, 2 */
   double ms_solid, ms_adjoint, ms_damping_sweep; /* out: best times of sph_autotune */
 } sph_tuning;
 int sph_autotune(sph_nbr* nbr, const sph_material* mat, const sph_state* st, double eta,

@@ -96,12 +96,14 @@ class Adjoint(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("lpp_stress", i32), ("lpp_momentum", i32), ("lpp_adj_stress", i32), ("lpp_adj_gather", i32),
-                ("damp_lanes", i32 * 8), ("ms_solid", dbl), ("ms_adjoint", dbl), ("ms_damping_sweep", dbl)]
+                ("damp_lanes", i32 * 8), ("damp_idle", i32 * 8), ("ms_solid", dbl), ("ms_adjoint", dbl),
+                ("ms_damping_sweep", dbl)]
 
     def as_dict(self):
         return dict(lpp_stress=self.lpp_stress, lpp_momentum=self.lpp_momentum,
                     lpp_adj_stress=self.lpp_adj_stress, lpp_adj_gather=self.lpp_adj_gather,
-                    damp_lanes=list(self.damp_lanes), ms_solid=self.ms_solid, ms_adjoint=self.ms_adjoint,
+                    damp_lanes=list(self.damp_lanes), damp_idle=list(self.damp_idle),
+                    ms_solid=self.ms_solid, ms_adjoint=self.ms_adjoint,
                     ms_damping_sweep=self.ms_damping_sweep)
 
 
@@ -712,8 +714,9 @@ def sph_autotune(nbr, mat, st, eta, dt_s, with_adjoint=True, stream=None):
 
 
 def sph_set_tuning(nbr, prec, lpp_stress=2, lpp_momentum=4, lpp_adj_stress=2, lpp_adj_gather=4,
-                   damp_lanes=(0,) * 8):
-    t = Tuning(lpp_stress, lpp_momentum, lpp_adj_stress, lpp_adj_gather, (i32 * 8)(*damp_lanes), 0.0, 0.0, 0.0)
+                   damp_lanes=(0,) * 8, damp_idle=(0,) * 8):
+    t = Tuning(lpp_stress, lpp_momentum, lpp_adj_stress, lpp_adj_gather, (i32 * 8)(*damp_lanes),
+               (i32 * 8)(*damp_idle), 0.0, 0.0, 0.0)
     _check(lib().sph_set_tuning(nbr.handle, int(prec), C.byref(t)))
 
 

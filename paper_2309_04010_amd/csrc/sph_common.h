@@ -94,6 +94,8 @@ struct Tune {
   // [kernel][SPH_F32, SPH_F64]: the tuned choices on the 1M-particle plate
   int lpp[TUNE_COUNT][2] = {{1, 2}, {2, 4}, {1, 2}, {2, 4}};
   int damp_g[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
+  // idle lanes of a damping row: 0 automatic, 1 spare slot, 2 skip
+  int damp_idle[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
 };
 
 // reverse diffusion gathers (CSR lists): lanes per particle, threads per block

@@ -77,17 +77,23 @@ extern "C" int sph_set_tuning(sph_nbr* nb, int prec, const sph_tuning* t) {
     set_error("lanes per particle of the tiled kernels: 1, 2 or 4");
     return SPH_E_ARG;
   }
-  for (int c = 0; c < 8; ++c)
+  for (int c = 0; c < 8; ++c) {
     if (t->damp_lanes[c] != 0 && t->damp_lanes[c] != 8 && t->damp_lanes[c] != 16 &&
         t->damp_lanes[c] != 32 && t->damp_lanes[c] != 64) {
       set_error("damping lanes per anchor: 0 (automatic), 8, 16, 32 or 64");
       return SPH_E_ARG;
     }
+    if (t->damp_idle[c] < 0 || t->damp_idle[c] > 2) {
+      set_error("damping idle lanes: 0 (automatic), 1 (spare slot) or 2 (skip)");
+      return SPH_E_ARG;
+    }
+  }
   nb->tune.lpp[TUNE_STRESS][prec] = t->lpp_stress;
   nb->tune.lpp[TUNE_MOMENTUM][prec] = t->lpp_momentum;
   nb->tune.lpp[TUNE_ADJ_STRESS][prec] = t->lpp_adj_stress;
   nb->tune.lpp[TUNE_ADJ_GATHER][prec] = t->lpp_adj_gather;
   for (int c = 0; c < 8; ++c) nb->tune.damp_g[prec][c] = t->damp_lanes[c];
+  for (int c = 0; c < 8; ++c) nb->tune.damp_idle[prec][c] = t->damp_idle[c];
   return SPH_OK;
 }
 
@@ -103,6 +109,7 @@ extern "C" int sph_get_tuning(const sph_nbr* nb, int prec, sph_tuning* t) {
   t->lpp_adj_stress = nb->tune.lpp[TUNE_ADJ_STRESS][prec];
   t->lpp_adj_gather = nb->tune.lpp[TUNE_ADJ_GATHER][prec];
   for (int c = 0; c < 8; ++c) t->damp_lanes[c] = nb->tune.damp_g[prec][c];
+  for (int c = 0; c < 8; ++c) t->damp_idle[c] = nb->tune.damp_idle[prec][c];
   return SPH_OK;
 }
 
@@ -201,24 +208,30 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
   double sweep = 0.0;
   for (int col = 0; col < ncol; ++col) {
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
-    int best = 0;
+    int best = 0, best_idle = 0;
     double bt = 1e300;
     for (int tr = 0; tr < trials && rc == SPH_OK; ++tr)
       for (int g : {8, 16, 32, 64}) {
         tn.damp_g[prec][col] = g;
         // the records laid out for this width, outside the timing
         if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) break;
-        // time the whole sweep: only this colour's launch differs between candidates
-        double t = 0.0;
-        rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
-        if (rc) break;
-        if (t < bt) {
-          bt = t;
-          best = g;
+        for (int idle : {1, 2}) {
+          tn.damp_idle[prec][col] = idle;
+          // time the whole sweep: only this colour's launch differs between candidates
+          double t = 0.0;
+          rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
+          if (rc) break;
+          if (t < bt) {
+            bt = t;
+            best = g;
+            best_idle = idle;
+          }
         }
+        if (rc) break;
       }
     if (rc) break;
     tn.damp_g[prec][col] = best;
+    tn.damp_idle[prec][col] = best_idle;
     sweep = bt;
   }
   nb->damp_pre = false;
@@ -230,6 +243,7 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
   res.lpp_adj_stress = tn.lpp[TUNE_ADJ_STRESS][prec];
   res.lpp_adj_gather = tn.lpp[TUNE_ADJ_GATHER][prec];
   for (int c = 0; c < 8; ++c) res.damp_lanes[c] = tn.damp_g[prec][c];
+  for (int c = 0; c < 8; ++c) res.damp_idle[c] = tn.damp_idle[prec][c];
   if (out) *out = res;
   return SPH_OK;
 }

@@ -12,6 +12,7 @@ import itertools
 
 import numpy as np
 import pytest
+import torch
 
 from paper_2309_04010_amd import binding as B
 from paper_2309_04010_amd import cases
@@ -72,17 +73,23 @@ def test_every_forward_launch_shape_matches_oracle(oracle_mod, dim, prec):
     Sdv = dv.copy()
     o.damping_sweep(NH["rho0"], eta, dt, Sdv, flags)
     rhs = (wbar * Sdv).sum()
+    ref = None
     for g in (8, 16, 32, 64):
-        print(f"[tune] dim={dim} prec={prec} damping lanes {g}", flush=True)
-        B.sph_set_tuning(nb, prec, damp_lanes=(g,) * 8)
-        st.v.copy_(dev(v, T))
-        B.sph_damping_sweep(nb, mg, st, eta, dt)
-        assert rel_err(host(st.v), w) < TOL[prec], g
-        adj = B.new_adjoint(nb, prec)
-        adj.v.copy_(dev(wbar, T))
-        B.sph_damping_sweep_vjp(nb, mg, st, adj, eta, dt)
-        lhs = (host(adj.v) * dv).sum()
-        assert abs(lhs - rhs) <= (1e-12 if prec == B.SPH_F64 else 1e-5) * abs(rhs), g
+        for idle in (1, 2):
+            print(f"[tune] dim={dim} prec={prec} damping lanes {g} idle mode {idle}", flush=True)
+            B.sph_set_tuning(nb, prec, damp_lanes=(g,) * 8, damp_idle=(idle,) * 8)
+            st.v.copy_(dev(v, T))
+            B.sph_damping_sweep(nb, mg, st, eta, dt)
+            assert rel_err(host(st.v), w) < TOL[prec], g
+            # every width and idle mode runs the same canonical order: same bits
+            if ref is None:
+                ref = st.v.clone()
+            assert torch.equal(st.v, ref), (g, idle)
+            adj = B.new_adjoint(nb, prec)
+            adj.v.copy_(dev(wbar, T))
+            B.sph_damping_sweep_vjp(nb, mg, st, adj, eta, dt)
+            lhs = (host(adj.v) * dv).sum()
+            assert abs(lhs - rhs) <= (1e-12 if prec == B.SPH_F64 else 1e-5) * abs(rhs), g
     nb.close()
 
 
@@ -130,9 +137,11 @@ def test_autotune_leaves_state_and_keeps_parity(oracle_mod):
     assert t.lpp_stress in (1, 2, 4) and t.lpp_momentum in (1, 2, 4)
     assert t.lpp_adj_stress in (1, 2, 4) and t.lpp_adj_gather in (1, 2, 4)
     assert all(g in (8, 16, 32, 64) for g in list(t.damp_lanes)[:4])
+    assert all(i in (1, 2) for i in list(t.damp_idle)[:4])
     assert t.ms_solid > 0 and t.ms_damping_sweep > 0
     got = B.sph_get_tuning(nb, B.SPH_F64)
     assert got.lpp_stress == t.lpp_stress and list(got.damp_lanes) == list(t.damp_lanes)
+    assert list(got.damp_idle) == list(t.damp_idle)
     # a run with the tuned shapes against the oracle
     st.v.zero_()
     flags = np.ascontiguousarray(c.flags[perm])
