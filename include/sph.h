@@ -522,7 +522,9 @@ int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, con
  * without a pair do: 1 = update a spare slot with a zero coefficient (no
  * branch: shorter rows, for passes of few wavefronts), 2 = skip the row's LDS
  * work (a branch: less LDS traffic, for passes of many wavefronts), 0 =
- * automatic (2 from 512 wavefronts a pass up); the results are the same. */
+ * automatic (2 from 512 wavefronts a pass up); the results are the same.
+ * sph_autotune sets it to automatic: its repeated sweeps over the same data
+ * keep the records in the last-level cache, where the two forms time alike. */
 typedef struct {
   int32_t lpp_stress;      /* 1, 2, 4 */
   int32_t lpp_momentum;    /* 1, 2, 4 */

@@ -208,32 +208,30 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
   double sweep = 0.0;
   for (int col = 0; col < ncol; ++col) {
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
-    int best = 0, best_idle = 0;
+    int best = 0;
     double bt = 1e300;
     for (int tr = 0; tr < trials && rc == SPH_OK; ++tr)
       for (int g : {8, 16, 32, 64}) {
         tn.damp_g[prec][col] = g;
         // the records laid out for this width, outside the timing
         if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) break;
-        for (int idle : {1, 2}) {
-          tn.damp_idle[prec][col] = idle;
-          // time the whole sweep: only this colour's launch differs between candidates
-          double t = 0.0;
-          rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
-          if (rc) break;
-          if (t < bt) {
-            bt = t;
-            best = g;
-            best_idle = idle;
-          }
-        }
+        // time the whole sweep: only this colour's launch differs between candidates
+        double t = 0.0;
+        rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
         if (rc) break;
+        if (t < bt) {
+          bt = t;
+          best = g;
+        }
       }
     if (rc) break;
     tn.damp_g[prec][col] = best;
-    tn.damp_idle[prec][col] = best_idle;
     sweep = bt;
   }
+  // the idle lanes of a row follow the automatic rule: timed here, on the
+  // same data sweep after sweep, the records stay in the last-level cache
+  // and both forms time alike, while inside a run they do not
+  for (int c = 0; c < 8; ++c) tn.damp_idle[prec][c] = 0;
   nb->damp_pre = false;
   if (rc) return rc;
   SPH_HIP(hipStreamSynchronize(s));
