@@ -568,8 +568,15 @@ __global__ __launch_bounds__(256 * LPP) void k_adj_stress(
 #pragma unroll
     for (int i = 0; i < kNTheta; ++i) thd[i] = (double)th[i];
   }
-  const int slots[kNTheta] = {SPH_GRAD_E, SPH_GRAD_S0, SPH_GRAD_SINF, SPH_GRAD_DELTA, SPH_GRAD_H};
-  block_grad_add<kNTheta>(thd, slots, gpart);
+  if constexpr (MODEL == SPH_MODEL_LE || MODEL == SPH_MODEL_NH) {
+    // the hardening parameters' partials are zero for these models: reduce E's only
+    double the[1] = {thd[0]};
+    const int slot1[1] = {SPH_GRAD_E};
+    block_grad_add<1>(the, slot1, gpart);
+  } else {
+    const int slots[kNTheta] = {SPH_GRAD_E, SPH_GRAD_S0, SPH_GRAD_SINF, SPH_GRAD_DELTA, SPH_GRAD_H};
+    block_grad_add<kNTheta>(thd, slots, gpart);
+  }
 }
 
 // reverse of the displacement-gradient sum:
