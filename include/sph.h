@@ -179,10 +179,13 @@ typedef struct {
  *      cell index floor((X - origin) / 2h) clamped to [0, nc-1].  Particles
  *      are stably sorted by cell key (x fastest); lists are in ascending
  *      sorted position.
- *   Damping schedule: each unordered pair is anchored at the componentwise
- *   minimum of its two cells, except along an axis only two cells deep, where
- *   the anchor takes the first cell (the block then spans that axis, and the
- *   colours odd along it stay empty); the pair is coloured by the parity of
+ *   Damping schedule: each unordered pair {a < b} is anchored at a cell A
+ *   whose block A .. A+1 holds both particles: per axis, the lower of the two
+ *   cells where they differ; where both sit in cell c, c - 1 if c >= 1 and
+ *   bit k (the axis index) of a + b is set, else c (a, b counted from the
+ *   specimen's first sorted position); along an axis only two cells deep,
+ *   the first cell (the block then spans that axis, and the colours odd
+ *   along it stay empty).  The pair is coloured by the parity of
  *   its anchor (2^dim colours, so anchors of one colour touch disjoint
  *   2^dim-cell blocks); within an anchor, pairs in ascending (a, b) take the
  *   smallest level not used by an earlier pair sharing a particle.

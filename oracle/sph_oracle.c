@@ -324,12 +324,16 @@ orc_sys* orc_create(int dim, int64_t n, const double* X_id, const double* V_id, 
   }
 
   /* --- damping schedule (Sec. 4.3).  Every unordered pair {a<b} is
-   *     anchored at the componentwise minimum of the two particles' cells,
-   *     except along an axis only two cells deep, where the anchor takes
-   *     the first cell: the block then spans that axis, and the two colours
-   *     along it would touch the same cells anyway.  The colour is the
-   *     parity vector of the anchor.  Within an anchor, pairs are taken in
-   *     ascending (a, b) and given the smallest level not used by an
+   *     anchored at a cell A whose block of 2^dim cells A .. A+1 holds both
+   *     particles.  Along an axis where the two cells differ A takes the
+   *     lower one; along an axis where both particles sit in cell c it takes
+   *     c - 1 when c >= 1 and bit k (k = the axis) of a + b is set, else c,
+   *     so that the pairs of one particle spread over the colours instead of
+   *     piling onto its own cell's anchor; along an axis only two cells deep
+   *     it takes the first cell (the block then spans that axis, and the two
+   *     colours along it would touch the same cells anyway).  The colour is
+   *     the parity vector of the anchor.  Within an anchor, pairs are taken
+   *     in ascending (a, b) and given the smallest level not used by an
    *     earlier pair of the same anchor that shares a particle (first fit).
    *     Canonical order: colour, anchor key, level, a, b. --- */
   int64_t np = s->n_pairs / 2;
@@ -345,7 +349,14 @@ orc_sys* orc_create(int dim, int64_t n, const double* X_id, const double* V_id, 
       int64_t ca[3], cb[3], an[3];
       cell_coords(s, s->key[a], ca);
       cell_coords(s, s->key[b], cb);
-      for (int k = 0; k < 3; ++k) an[k] = s->nc[k] == 2 ? 0 : (ca[k] < cb[k] ? ca[k] : cb[k]);
+      for (int k = 0; k < 3; ++k) {
+        if (s->nc[k] == 2)
+          an[k] = 0;
+        else if (ca[k] != cb[k])
+          an[k] = ca[k] < cb[k] ? ca[k] : cb[k];
+        else
+          an[k] = (ca[k] >= 1 && (((a + b) >> k) & 1)) ? ca[k] - 1 : ca[k];
+      }
       ua[m] = (uint32_t)a;
       ub[m] = (uint32_t)b;
       uk[m] = (uint32_t)(an[0] + s->nc[0] * (an[1] + s->nc[1] * an[2]));

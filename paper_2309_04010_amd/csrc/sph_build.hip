@@ -477,19 +477,33 @@ __device__ __forceinline__ Block anchor_block(uint32_t akey, const Grid& g, cons
   return blk;
 }
 
-// a pair's anchor: the componentwise minimum of its two cells, except along
-// an axis of exactly two cells (of its specimen's grid segment), where it is
-// the first cell, so that the block spans the axis and one colour pass covers
-// what the two parities along it would (same-colour blocks stay disjoint)
-__device__ __forceinline__ bool anchored_at(uint32_t ks, uint32_t kt, const int64_t A[3],
-                                            const Grid& g) {
+// a pair's anchor: a cell A whose block A .. A+1 holds both particles.
+// Along an axis where the two cells differ it is the lower one; along an axis
+// where both sit in cell c it is c - 1 when c >= 1 and bit k (the axis) of
+// s + t is set, with s, t the pair's positions in its specimen's sorted
+// range, else c (a particle's pairs spread over the colours instead of all
+// landing on its own cell's anchor); along an axis of exactly two cells (of
+// its specimen's grid segment) it is the first cell, so that the block spans
+// the axis and one colour pass covers what the two parities along it would
+// (same-colour blocks stay disjoint)
+__device__ __forceinline__ bool anchored_at(int64_t s, int64_t t, uint32_t ks, uint32_t kt,
+                                            const int64_t A[3], const Grid& g,
+                                            const uint32_t* cs) {
   const GridSeg sg = seg_of_cell(g, ks);  // neighbours never cross specimens
   int64_t cs_[3], ct[3];
   key_coords_s(ks, sg, cs_);
   key_coords_s(kt, sg, ct);
   const int64_t nc[3] = {sg.nc0, sg.nc1, sg.nc2};
+  const int64_t p0 = cs[sg.koff];  // the specimen's first sorted particle
+  const int64_t sum = (s - p0) + (t - p0);
   for (int k = 0; k < 3; ++k) {
-    const int64_t m = nc[k] == 2 ? 0 : (cs_[k] < ct[k] ? cs_[k] : ct[k]);
+    int64_t m;
+    if (nc[k] == 2)
+      m = 0;
+    else if (cs_[k] != ct[k])
+      m = cs_[k] < ct[k] ? cs_[k] : ct[k];
+    else
+      m = (cs_[k] >= 1 && ((sum >> k) & 1)) ? cs_[k] - 1 : cs_[k];
     if (m != A[k]) return false;
   }
   return true;
@@ -511,7 +525,7 @@ __global__ void k_sched_count(const uint32_t* key, const uint32_t* cs, const int
       for (int64_t j = off[s]; j < off[s + 1]; ++j) {
         uint32_t t = idx[j];
         if ((int64_t)t <= s) continue;
-        if (anchored_at(key[s], key[t], A, g)) ++m;
+        if (anchored_at(s, t, key[s], key[t], A, g, cs)) ++m;
       }
   }
   cnt[c] = m;
@@ -567,7 +581,7 @@ __global__ void k_sched_fill(const uint32_t* key, const uint32_t* cs, const int6
       for (int64_t j = off[s]; j < off[s + 1]; ++j) {
         uint32_t t = idx[j];
         if ((int64_t)t <= s) continue;
-        if (!anchored_at(key[s], key[t], A, g)) continue;
+        if (!anchored_at(s, (int64_t)t, key[s], key[t], A, g, cs)) continue;
         int64_t ls = lbase[r] + (s - blk.beg[r]);
         int64_t lt = -1;
         for (int q = 0; q < blk.nr; ++q)

@@ -140,8 +140,19 @@ def test_schedule_invariants(oracle_mod, name, dim, gen):
             prev = -1
             for i in range(lo, hi):
                 ca, cb = coords(int(o.key[a[i]])), coords(int(o.key[b[i]]))
-                want = np.where(np.array(nc) == 2, 0, np.minimum(ca, cb))
-                assert np.array_equal(want, A), "anchor = componentwise min cell (first cell on a 2-cell axis)"
+                # the anchor's block A .. A+1 holds both particles
+                assert np.all(A <= np.minimum(ca, cb)) and np.all(np.maximum(ca, cb) <= A + 1)
+                # and the choice is the reading's: the lower cell where they
+                # differ; where they share cell c, c - 1 (c >= 1) when bit k
+                # of a + b is set; the first cell along a 2-cell axis
+                for k in range(3):
+                    if nc[k] == 2:
+                        want = 0
+                    elif ca[k] != cb[k]:
+                        want = min(ca[k], cb[k])
+                    else:
+                        want = ca[k] - 1 if ca[k] >= 1 and ((a[i] + b[i]) >> k) & 1 else ca[k]
+                    assert A[k] == want, "anchor rule"
                 assert lev[i] >= prev
                 prev = lev[i]
                 for p in (a[i], b[i]):
