@@ -306,6 +306,9 @@ int prof_resolve(const sph_nbr* nb);
 // ---- host entry points implemented per translation unit ----------------------
 int solid_stage(const sph_nbr* nb, const sph_material* m, const sph_state* st, double dt,
                 hipStream_t s, bool gated);
+// one colour pass of the forward sweep with the records already laid out
+// (the tuner times passes one by one)
+int damping_pass(const sph_nbr* nb, const sph_state* st, int col, hipStream_t s);
 int damping_sweep(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
                   double dt, hipStream_t s, bool gated);
 int damping_sweep_rev(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,

@@ -1240,6 +1240,25 @@ static int damping_t(const sph_nbr* nb, const sph_material* m, const sph_state* 
   return SPH_OK;
 }
 
+template <typename T, int D>
+static int damping_pass_t(const sph_nbr* nb, const sph_state* st, int col, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? SPH_F64 : SPH_F32;
+  switch (nb->damp_g_used[prec][col]) {
+    case 8: return damp_launch<T, D, 8, false>(nb, st, s, false, col);
+    case 16: return damp_launch<T, D, 16, false>(nb, st, s, false, col);
+    case 32: return damp_launch<T, D, 32, false>(nb, st, s, false, col);
+    default: return damp_launch<T, D, 64, false>(nb, st, s, false, col);
+  }
+}
+
+int damping_pass(const sph_nbr* nb, const sph_state* st, int col, hipStream_t s) {
+  if (st->prec == SPH_F64)
+    return nb->dim == 2 ? damping_pass_t<double, 2>(nb, st, col, s)
+                        : damping_pass_t<double, 3>(nb, st, col, s);
+  return nb->dim == 2 ? damping_pass_t<float, 2>(nb, st, col, s)
+                      : damping_pass_t<float, 3>(nb, st, col, s);
+}
+
 int damping_sweep(const sph_nbr* nb, const sph_material* m, const sph_state* st, double eta,
                   double dt, hipStream_t s, bool gated) {
   if (st->prec == SPH_F64)

@@ -203,7 +203,11 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     res.ms_adjoint = ms;
     if ((rc = grad_reduce(nb, a.grad, s))) return rc;  // clears the partials it accumulated
   }
-  // damping: each colour pass separately
+  // damping: each colour pass separately.  The idle lanes of a row follow
+  // the automatic rule: timed here, on the same data pass after pass, the
+  // records stay in the last-level cache and both forms time alike, while
+  // inside a run they do not
+  for (int c = 0; c < 8; ++c) tn.damp_idle[prec][c] = 0;
   const int ncol = 1 << nb->dim;
   double sweep = 0.0;
   for (int col = 0; col < ncol; ++col) {
@@ -215,9 +219,10 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
         tn.damp_g[prec][col] = g;
         // the records laid out for this width, outside the timing
         if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) break;
-        // time the whole sweep: only this colour's launch differs between candidates
+        // time this colour's pass alone (within a whole sweep the widths of
+        // one colour differ by less than the sweep's noise)
         double t = 0.0;
-        rc = time_ms(s, reps, [&]() { return damping_sweep(nb, m, &w, eta, dt_s, s, false); }, &t);
+        rc = time_ms(s, reps, [&]() { return damping_pass(nb, &w, col, s); }, &t);
         if (rc) break;
         if (t < bt) {
           bt = t;
@@ -226,12 +231,8 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
       }
     if (rc) break;
     tn.damp_g[prec][col] = best;
-    sweep = bt;
+    sweep += bt;
   }
-  // the idle lanes of a row follow the automatic rule: timed here, on the
-  // same data sweep after sweep, the records stay in the last-level cache
-  // and both forms time alike, while inside a run they do not
-  for (int c = 0; c < 8; ++c) tn.damp_idle[prec][c] = 0;
   nb->damp_pre = false;
   if (rc) return rc;
   SPH_HIP(hipStreamSynchronize(s));

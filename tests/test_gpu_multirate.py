@@ -2,7 +2,7 @@
 
 FP64: the inner-step counts chosen by the kinetic-energy early exit are
 identical to the oracle's and the fields agree to 1e-10, over the whole
-schedules of the 2D bar (100 loading steps, 49,900 inner steps) and of the
+schedules of the 2D bar (100 loading steps, 43,900 inner steps) and of the
 swelling strip (100 diffusion steps, 3,225 inner steps).  FP32 bulk with FP64
 displacement: fields within 1e-4 of the FP64 oracle on runs with a frozen
 schedule.  On an adaptive schedule the FP32 run may cross the kinetic-energy
@@ -88,7 +88,7 @@ def test_bar_fp64_adaptive_counts_identical(oracle_mod, use_graph):
 
 def test_bar_fp64_whole_schedule(oracle_mod):
     """The 2D bar over its whole schedule: 100 loading steps, each relaxed
-    until E_k <= 1e-8 E_ref (479-519 inner steps each).  Every count equals
+    until E_k <= 1e-8 E_ref (439 inner steps each).  Every count equals
     the oracle's and the final fields agree to 1e-10, element by element."""
     print("[multirate] bar2d fp64 whole schedule (100 slow steps)", flush=True)
     c = cases.bar2d()
