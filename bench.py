@@ -534,22 +534,31 @@ def run_small_configs(torch, B):
             ("strip2d_f64", cases.strip2d(), B.SPH_F64))
     u_end = {}
     for tag, c, prec in runs:
-        nb, st = setup(c, prec, torch, B)
-        cfg = B.multirate_cfg(**c.run, chunk=250)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, k, ke, conv, rep = B.sph_advance_multirate(nb, B.material(**c.material), st, cfg)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        u_end[tag] = st.u.double().cpu().numpy()
-        out[tag] = dict(particles=nb.info.n, pairs=nb.info.n_pairs, N_S=int(len(k)), N_s=int(k.sum()),
+        res = {}
+        for g in (0, 1):
+            nb, st = setup(c, prec, torch, B)
+            cfg = B.multirate_cfg(**c.run, chunk=250, use_graph=g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, k, ke, conv, rep = B.sph_advance_multirate(nb, B.material(**c.material), st, cfg)
+            torch.cuda.synchronize()
+            res[g] = (time.perf_counter() - t0, k, conv, st.u.double().cpu().numpy())
+            n, pairs = nb.info.n, nb.info.n_pairs
+            nb.close()
+        sec, k, conv, u_end[tag] = res[0]
+        gsec = res[1][0]
+        out[tag] = dict(particles=n, pairs=pairs, N_S=int(len(k)), N_s=int(k.sum()),
                         k_min=int(k.min()), k_max=int(k.max()), converged=int(conv.sum()), seconds=sec,
-                        interactions_per_s=nb.info.n_pairs * float(k.sum()) / sec)
-        nb.close()
+                        interactions_per_s=pairs * float(k.sum()) / sec, seconds_graph=gsec,
+                        interactions_per_s_graph=pairs * float(k.sum()) / gsec,
+                        graph_equals_eager=bool(np.array_equal(res[1][1], k) and
+                                                np.array_equal(res[1][3], u_end[tag])))
     out["strip2d_f32_u_rel_err"] = float(np.abs(u_end["strip2d_f32"] - u_end["strip2d_f64"]).max() /
                                          np.abs(u_end["strip2d_f64"]).max())
     out["note"] = ("bar2d: 40x8, LE, 100 loading slow steps; strip2d: 200x10, NH + swelling, 100 diffusion "
-                   "slow steps; inner counts by the kinetic-energy stop test (N_s inner steps in all)")
+                   "slow steps; inner counts by the kinetic-energy stop test (N_s inner steps in all); "
+                   "seconds: eager launches, seconds_graph: the inner steps replayed as a hipGraph (its "
+                   "capture included)")
     return out
 
 
@@ -813,6 +822,11 @@ def main():
                              status=info["status"], u_finite=info["u_finite"])
             print(f"[bench] neck3d {tag} done: {info['seconds']:.1f} s", flush=True)
         neck["f32_over_f64"] = neck["f32"]["interactions_per_s"] / neck["f64"]["interactions_per_s"]
+        info, _ = run_gpu(nc, B.SPH_F32, args.neck3d_slow, 1, 1000, torch, B, profile=False, use_graph=1)
+        neck["f32_graph"] = dict(seconds=info["seconds"], inner_steps=info["total_inner"],
+                                 interactions_per_s=info["pairs"] * info["total_inner"] / info["seconds"],
+                                 status=info["status"], u_finite=info["u_finite"])
+        print(f"[bench] neck3d f32 graph done: {info['seconds']:.1f} s", flush=True)
 
     sweep = None
     if not args.no_sweep:

@@ -150,8 +150,14 @@ typedef struct {
   double ke_tol;       /* absolute kinetic-energy threshold of the early exit */
   double D;            /* diffusion coefficient */
   double c_bc;         /* Dirichlet saturation */
-  int32_t chunk;       /* inner steps launched between host polls (<= 0: 64) */
-  int32_t use_graph;   /* 1: replay each chunk as a captured hipGraph */
+  int32_t chunk;       /* most inner steps launched between host polls (<= 0: 64);
+                          an adaptive run polls first after min(chunk, 16) steps and
+                          doubles the interval after each poll, up to chunk */
+  int32_t use_graph;   /* 1: replay the inner steps as a captured hipGraph of one
+                          chunk, or in an adaptive run of min(chunk, 16) steps
+                          launched as often as each interval needs; the graph
+                          stays on the handle for later calls with the same
+                          arguments */
   const int64_t* k_sched; /* host, optional [n_slow]: frozen inner counts */
   const struct sph_batch* batch; /* optional: per-specimen parameters (see sph_build_neighbors_batched) */
   int32_t diff_nonlinear; /* SPH_SLOW_DIFFUSION_COUPLED: flux -D a grad a (1) or -D grad a (0) */

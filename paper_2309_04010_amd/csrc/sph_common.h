@@ -103,6 +103,7 @@ constexpr int kDiffLanes = 8;
 constexpr int kDiffBlock = 1024;
 constexpr int kDiffPerBlock = kDiffBlock / kDiffLanes;
 
+constexpr int kPollFirst = 16;          // inner steps before an adaptive run's first poll
 constexpr int kKeThreads = 256;
 constexpr int kKeItems = 4;             // particles per thread in the drift kernel
 constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (67M particles)

@@ -4,7 +4,10 @@
 // energy falls to the threshold.  The stop test runs on the device (the
 // drift/E_k kernel sets a flag that every later inner kernel checks), so the
 // host only polls once per chunk of inner steps; a chunk can be replayed as a
-// captured hipGraph to remove per-kernel launch cost on small problems.
+// captured hipGraph to remove per-kernel launch cost on small problems.  In
+// an adaptive run the first poll comes after a short chunk and each later one
+// after twice as many steps, up to the configured chunk, so that a slow step
+// that relaxes in a few inner steps does not launch a whole chunk after it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -402,6 +405,9 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
   const int64_t k_max = cfg->k_max > 0 ? cfg->k_max : (int64_t)std::floor(dt_slow / dt_s) + 1;
   const bool adaptive = cfg->k_sched == nullptr && cfg->fixed_inner <= 0;
   const int chunk = cfg->chunk > 0 ? cfg->chunk : 64;
+  // inner steps of the first poll interval of an adaptive run, and of the
+  // captured graph there (replayed to fill each interval)
+  const int first = adaptive ? std::min(chunk, kPollFirst) : chunk;
   if (tape && (rc = check_tape(nb, m, st, cfg, tape))) return rc;
   RecGuard rec_guard{nb};
   bool recorded = false;
@@ -425,7 +431,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
     key_add(key, st);
     key_add(key, &dt_s);
     key_add(key, &cfg->eta);
-    key_add(key, &chunk);
+    key_add(key, &first);
     key_add(key, &nb->tune);
     const Bat bv = bat_view(nb);
     key_add(key, &bv);
@@ -440,7 +446,7 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
       if (nb->prof) nb->prof->suspend = true;
       hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        rc = inner_steps(nb, m, st, dt_s, cfg->eta, chunk, cap);
+        rc = inner_steps(nb, m, st, dt_s, cfg->eta, first, cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cap, &g);
         cg->gc.graph = g;
@@ -498,14 +504,21 @@ extern "C" int sph_advance_multirate(const sph_nbr* nb, const sph_material* m,
       recorded = true;
     }
     int64_t launched = 0;
+    int64_t interval = first;
     for (;;) {
-      int64_t mcount = graph ? chunk : std::min<int64_t>(chunk, nk - launched);
+      int64_t mcount = std::min<int64_t>(interval, nk - launched);
+      interval = std::min<int64_t>(2 * interval, chunk);
       if (graph) {
-        if (hipGraphLaunch(exec, s) != hipSuccess) {
-          set_error("graph launch failed");
-          rc = SPH_E_DEVICE;
-          break;
+        // whole graphs: the steps past nk return at once on the device
+        const int64_t reps = (mcount + first - 1) / first;
+        for (int64_t r = 0; r < reps && rc == SPH_OK; ++r) {
+          if (hipGraphLaunch(exec, s) != hipSuccess) {
+            set_error("graph launch failed");
+            rc = SPH_E_DEVICE;
+          }
         }
+        if (rc) break;
+        mcount = reps * first;
       } else {
         rc = inner_steps(nb, m, st, dt_s, cfg->eta, (int)mcount, s);
         if (rc) break;

@@ -128,6 +128,29 @@ def test_graph_equals_eager_bitwise(oracle_mod):
     assert np.array_equal(a["v"][1], b["v"][1])
 
 
+def test_strip_adaptive_graph_equals_eager(oracle_mod):
+    """The strip's whole adaptive schedule (1 to 1607 inner steps per slow
+    step): the short graph replayed over growing poll intervals takes the
+    same counts and fields as eager launches, bit for bit."""
+    print("[multirate] strip2d adaptive graph vs eager (100 slow steps)", flush=True)
+    c = cases.strip2d()
+    out = []
+    for g in (0, 1):
+        o, nb = build_pair(oracle_mod, c.dim, c.X, c.V, c.h)
+        st = B.new_state(nb, B.SPH_F64, with_diffusion=True)
+        st.flags = dev(np.ascontiguousarray(c.flags[o.perm]))
+        st.c.copy_(dev(np.ascontiguousarray(c.c_init[o.perm]), torch_dtype(B.SPH_F64)))
+        cfg = B.multirate_cfg(**c.run, chunk=250, use_graph=g)
+        rc, k, ke, conv, rep = B.sph_advance_multirate(nb, B.material(**c.material), st, cfg)
+        assert rc == 0 and np.all(conv == 1)
+        out.append((k, host(st.u), host(st.c)))
+        nb.close()
+    assert out[0][0].min() == 1 and out[0][0].max() > 1000
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+
+
 def test_graph_chunk_reused_and_recaptured(oracle_mod):
     """The chunk graph of sph_advance_multirate stays on the handle: a call
     with the same arguments replays it, a call with another material records
