@@ -106,6 +106,7 @@ constexpr int kDiffPerBlock = kDiffBlock / kDiffLanes;
 constexpr int kPollFirst = 16;          // inner steps before an adaptive run's first poll
 constexpr int kKeThreads = 256;
 constexpr int kKeItems = 4;             // particles per thread in the drift kernel
+constexpr int kKeFinishBlocks = 64;     // drift grids this small reduce E_k in their last block
 constexpr int kKeMaxBlocks = 1 << 16;   // partial sums (67M particles)
 constexpr int kStaticKeBlocks = 1 << 16;  // sph_drift_ke_noalloc: 512 KiB of partials per GPU
 

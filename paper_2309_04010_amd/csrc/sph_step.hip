@@ -515,16 +515,44 @@ __global__ void k_damp_prep(int64_t n_upairs, int64_t n, const uint32_t* __restr
   dwq[inf & 0x0FFFFFFFu] = pq;
 }
 
+// The stop state after an inner step's kinetic energy ke: the step count, the
+// early exit, the cap and the non-finite status (one thread).
+__device__ __forceinline__ void ke_finish(Ctrl* ctrl, double ke, double* ke_out, bool gated) {
+  if (ke_out) *ke_out = ke;
+  if (gated) {
+    ctrl->ke = ke;
+    const int64_t k = ctrl->k + 1;
+    ctrl->k = k;
+    if (!isfinite(ke)) {
+      ctrl->status |= SPH_STATUS_NONFINITE;
+      ctrl->done = 1;
+    } else if (ke <= ctrl->ke_tol) {
+      ctrl->stopped_by_ke = 1;
+      ctrl->done = 1;
+    } else if (k >= ctrl->k_limit) {
+      ctrl->done = 1;
+    }
+  } else if (!isfinite(ke)) {
+    ctrl->status |= SPH_STATUS_NONFINITE;
+  }
+}
+
 // drift + kinetic energy: every block writes its partial E_k (fixed-order
-// tree), then one block reduces the partials in a fixed order, records E_k
-// and updates the stop state (deterministic: no floating-point atomics).
-// (Electing the last block with a ticket instead costs a device-scope release
-// fence per block, an L2 write-back, which is slower than the extra launch.)
-template <typename T, int D>
+// tree), then the partials are reduced in a fixed order, E_k recorded and the
+// stop state updated (deterministic: no floating-point atomics).  On a large
+// grid a second kernel (k_ke_reduce) reduces them.  On a grid of at most
+// kKeFinishBlocks blocks (FIN) the last block to finish, elected with a
+// ticket, reduces them itself and saves that launch; its sum takes the same
+// order as k_ke_reduce's, so E_k is the same bit for bit.  (On large grids
+// the device-scope release fence every block then needs, an L2 write-back
+// per block, costs more than the launch.)
+template <typename T, int D, bool FIN>
 __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     int64_t n, double* __restrict__ u, const T* __restrict__ v, const uint8_t* __restrict__ flags,
     const double* __restrict__ V, double rho0, double dt, Ctrl* ctrl, double* partial,
-    bool gated, Bat bt, const T* __restrict__ cmix, double rho_l0) {
+    bool gated, Bat bt, const T* __restrict__ cmix, double rho_l0, double* ke_out) {
+  // a FIN grid: every block reads done before it takes its ticket, and the
+  // last block, which may set it, takes the last ticket
   if (gated && ctrl->done) return;
   __shared__ double red[kKeThreads];
   const int64_t a0 = blockIdx.x * (int64_t)(kKeThreads * kKeItems) + threadIdx.x;
@@ -586,7 +614,36 @@ __global__ __launch_bounds__(kKeThreads) void k_drift_ke(
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if constexpr (!FIN) {
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  } else {
+    static_assert(kKeFinishBlocks <= kKeThreads, "one partial per thread of the last block");
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&partial[blockIdx.x], red[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t t = __hip_atomic_fetch_add(&ctrl->ticket, 1u, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+      last = t == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    // the partials in k_ke_reduce's order: its 1024-slot tree over at most
+    // kKeFinishBlocks values adds zeros until the slots below 64 remain
+    const int nblk = (int)gridDim.x;
+    red[threadIdx.x] = (int)threadIdx.x < nblk
+                           ? __hip_atomic_load(&partial[threadIdx.x], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                           : 0.0;
+    __syncthreads();
+    for (int w = kKeThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      ctrl->ticket = 0u;
+      ke_finish(ctrl, red[0], ke_out, gated);
+    }
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_ke_reduce(const double* __restrict__ partial,
@@ -602,26 +659,7 @@ __global__ __launch_bounds__(1024) void k_ke_reduce(const double* __restrict__ p
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double ke = red[0];
-    if (ke_out) *ke_out = ke;
-    if (gated) {
-      ctrl->ke = ke;
-      const int64_t k = ctrl->k + 1;
-      ctrl->k = k;
-      if (!isfinite(ke)) {
-        ctrl->status |= SPH_STATUS_NONFINITE;
-        ctrl->done = 1;
-      } else if (ke <= ctrl->ke_tol) {
-        ctrl->stopped_by_ke = 1;
-        ctrl->done = 1;
-      } else if (k >= ctrl->k_limit) {
-        ctrl->done = 1;
-      }
-    } else if (!isfinite(ke)) {
-      ctrl->status |= SPH_STATUS_NONFINITE;
-    }
-  }
+  if (threadIdx.x == 0) ke_finish(ctrl, red[0], ke_out, gated);
 }
 
 __global__ void k_reset_ctrl(Ctrl* c, int64_t k_limit, double ke_tol) {
@@ -1298,13 +1336,17 @@ static int drift_t(const sph_nbr* nb, const sph_material* m, const sph_state* st
   }
   {
     hipEvent_t pe_ = timed ? prof_begin(nb, SPH_KERNEL_DRIFT_KE, s) : nullptr;
-    k_drift_ke<T, D><<<(unsigned)nb_, kKeThreads, 0, s>>>(nb->n, st->u, (const T*)st->v, st->flags,
-                                                          nb->V, m->rho0, dt, nb->ctrl,
-                                                          partial, gated,
-                                                          bat_view(nb), mix_view<T>(m, st).c,
-                                                          m->rho_l0);
-    SPH_LAUNCH_CHECK();
-    k_ke_reduce<<<1, 1024, 0, s>>>(partial, (int)nb_, nb->ctrl, ke_out, gated);
+    if (nb_ <= kKeFinishBlocks) {
+      k_drift_ke<T, D, true><<<(unsigned)nb_, kKeThreads, 0, s>>>(
+          nb->n, st->u, (const T*)st->v, st->flags, nb->V, m->rho0, dt, nb->ctrl, partial, gated,
+          bat_view(nb), mix_view<T>(m, st).c, m->rho_l0, ke_out);
+    } else {
+      k_drift_ke<T, D, false><<<(unsigned)nb_, kKeThreads, 0, s>>>(
+          nb->n, st->u, (const T*)st->v, st->flags, nb->V, m->rho0, dt, nb->ctrl, partial, gated,
+          bat_view(nb), mix_view<T>(m, st).c, m->rho_l0, nullptr);
+      SPH_LAUNCH_CHECK();
+      k_ke_reduce<<<1, 1024, 0, s>>>(partial, (int)nb_, nb->ctrl, ke_out, gated);
+    }
     if (timed) prof_end(nb, SPH_KERNEL_DRIFT_KE, pe_, s);
   }
   SPH_LAUNCH_CHECK();
