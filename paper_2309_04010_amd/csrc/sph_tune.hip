@@ -203,13 +203,43 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     res.ms_adjoint = ms;
     if ((rc = grad_reduce(nb, a.grad, s))) return rc;  // clears the partials it accumulated
   }
-  // damping: each colour pass separately.  The idle lanes of a row follow
-  // the automatic rule: timed here, on the same data pass after pass, the
-  // records stay in the last-level cache and both forms time alike, while
-  // inside a run they do not
+  // damping: each colour's width by the time of its own pass (within a whole
+  // sweep the widths of one colour differ by less than the sweep's noise),
+  // timed inside whole sweeps: the other colours' passes run between its
+  // timings as in a run, so its records are not left in the last-level
+  // cache (a pass timed back to back on a large body then favours widths
+  // that are slower in a run).  The idle lanes of a row follow the automatic
+  // rule, for the same reason.
   for (int c = 0; c < 8; ++c) tn.damp_idle[prec][c] = 0;
   const int ncol = 1 << nb->dim;
   double sweep = 0.0;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  SPH_HIP(hipEventCreate(&ea));
+  if (hipEventCreate(&eb) != hipSuccess) {
+    hipEventDestroy(ea);
+    set_error("event creation failed");
+    return SPH_E_DEVICE;
+  }
+  auto pass_in_sweep = [&](int col, double* ms) -> int {
+    double tot = 0.0;
+    for (int r = -1; r < reps; ++r) {  // r = -1: untimed
+      for (int c = 0; c < ncol; ++c) {
+        if (c == col) hipEventRecord(ea, s);
+        int e = damping_pass(nb, &w, c, s);
+        if (e) return e;
+        if (c == col) hipEventRecord(eb, s);
+      }
+      if (hipEventSynchronize(eb) != hipSuccess) {
+        set_error("timing the damping pass failed");
+        return SPH_E_DEVICE;
+      }
+      float t = 0.f;
+      hipEventElapsedTime(&t, ea, eb);
+      if (r >= 0) tot += t;
+    }
+    *ms = tot / reps;
+    return SPH_OK;
+  };
   for (int col = 0; col < ncol; ++col) {
     if (nb->color_off[col + 1] <= nb->color_off[col]) continue;
     int best = 0;
@@ -219,11 +249,8 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
         tn.damp_g[prec][col] = g;
         // the records laid out for this width, outside the timing
         if ((rc = damp_prepare(nb, m, &w, eta, dt_s, s))) break;
-        // time this colour's pass alone (within a whole sweep the widths of
-        // one colour differ by less than the sweep's noise)
         double t = 0.0;
-        rc = time_ms(s, reps, [&]() { return damping_pass(nb, &w, col, s); }, &t);
-        if (rc) break;
+        if ((rc = pass_in_sweep(col, &t))) break;
         if (t < bt) {
           bt = t;
           best = g;
@@ -233,6 +260,8 @@ extern "C" int sph_autotune(sph_nbr* nb, const sph_material* m, const sph_state*
     tn.damp_g[prec][col] = best;
     sweep += bt;
   }
+  hipEventDestroy(ea);
+  hipEventDestroy(eb);
   nb->damp_pre = false;
   if (rc) return rc;
   SPH_HIP(hipStreamSynchronize(s));
