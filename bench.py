@@ -28,8 +28,10 @@ the HBM and FP32 roofs, the per-kernel breakdown, the CPU oracle timed on a
 bounded sample (one thread, and all host cores), and, outside the timed
 region: the slow-step variants (one-way and two-way coupled diffusion), the
 cost of the mixture momentum, the necking runs of Sec. 5.1/5.2 with their
-iteration counts (N_S, N_s, N_d) and curves, and the batched sweep of 64
-strips.
+iteration counts (N_S, N_s, N_d) and curves, the batched sweep of 64
+strips, the 3D J2 bar (100 loading slow steps x 1000 inner steps; FP32 with
+eager launches and as a hipGraph, and FP64), and the 2D bar and the swelling
+strip over their whole adaptive schedules (eager and as a hipGraph).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--inner M] [--no-cpu]
                   [--no-fp64] [--no-sweep] [--no-coupled] [--necking none|sample|full]
