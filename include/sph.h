@@ -523,6 +523,9 @@ int sph_advance_multirate_graph(const sph_nbr* nbr, const sph_material* mat, con
  * sph_autotune times every candidate on this handle's data (HIP events, a
  * few launches each, on scratch copies of v, PB and the J2 state: st is not
  * modified) and keeps the fastest for st->prec; later launches use them.
+ * A damping width is timed on its own colour's pass, with events around that
+ * pass inside whole sweeps, so that the other colours' records pass through
+ * the caches between its timings as in a run.
  * with_adjoint also tunes the reverse kernels.  eta and dt_s are those of the
  * runs to come.  Synchronous; allocates scratch for its own duration.
  * sph_set_tuning / sph_get_tuning write and read the choices directly
@@ -541,7 +544,8 @@ typedef struct {
   int32_t lpp_adj_gather;  /* 1, 2, 4 */
   int32_t damp_lanes[8];   /* per colour: 0, 8, 16, 32, 64 */
   int32_t damp_idle[8];    /* per colour: 0, 1, 2 */
-  double ms_solid, ms_adjoint, ms_damping_sweep; /* out: best times of sph_autotune */
+  double ms_solid, ms_adjoint, ms_damping_sweep; /* out: best times of sph_autotune
+                                                    (the sweep's: the sum of its passes') */
 } sph_tuning;
 int sph_autotune(sph_nbr* nbr, const sph_material* mat, const sph_state* st, double eta,
                  double dt_s, int with_adjoint, sph_tuning* out, void* stream);
