@@ -254,7 +254,11 @@ int sph_damping_sweep(const sph_nbr* nbr, const sph_material* mat, const sph_sta
 
 /* Drift and kinetic energy (Sec. 4.2): u += dt_s v for free particles, then
  * E_k = sum 1/2 rho0 V |v|^2 reduced in a fixed order (deterministic) into
- * the device double *ke_out (may be NULL).  Asynchronous. */
+ * the device double *ke_out (may be NULL).  On sets of at most 65,536
+ * particles the last block of the drift kernel reduces E_k (elected through
+ * a counter in the handle's control block), else a second kernel does; the
+ * order of the sum, and so E_k, is the same either way.  Calls on one handle
+ * must not overlap.  Asynchronous. */
 int sph_drift_ke(const sph_nbr* nbr, const sph_material* mat, const sph_state* st, double dt_s,
                  double* ke_out, void* stream);
 
@@ -266,7 +270,8 @@ int sph_drift_ke(const sph_nbr* nbr, const sph_material* mat, const sph_state* s
  * handle's buffer, so the call allocates nothing, and it is never timed by
  * sph_profile_enable.  Call it with the handle's device current.  Every
  * partial is written before it is read, so calls need no clearing between
- * them, but calls that overlap in time on one GPU race on that array.
+ * them, but calls that overlap in time on one GPU race on that array (and,
+ * on one handle, on its control block, as sph_drift_ke's do).
  * Errors: as sph_drift_ke, plus SPH_E_CAPACITY for more than 2^26
  * particles (the array's limit) and SPH_E_ARG when the current device is
  * not the handle's.  Asynchronous. */
