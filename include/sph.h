@@ -220,7 +220,9 @@ int sph_nbr_query(const sph_nbr* nbr, sph_nbr_info* info);
  * library's.  The call waits for `stream`, and for the device, so no call of
  * the handle may still run; it zeroes the gradient partials, marks the
  * damping records for re-computation (the next damping call lays them out)
- * and drops the cached whole-run graph.  Synchronous.  Errors: SPH_E_ARG
+ * and drops the cached graphs (the whole-run graph and the chunk graph of
+ * sph_advance_multirate), which point into the old block.  Synchronous.
+ * Errors: SPH_E_ARG
  * (NULL handle or bytes, ws misaligned or smaller than needed),
  * SPH_E_DEVICE. */
 int sph_workspace_size(const sph_nbr* nbr, int64_t* bytes);
